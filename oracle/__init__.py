@@ -1,0 +1,233 @@
+"""Plain FP64 CPU oracle for the loss-free embedding lift.
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the product path never does.  It
+shares no code with the GPU library (the two only read the same synthetic
+scenes).
+
+Split of work:
+  * ``slag_oracle.c`` -- per view: projection, per-pixel depth-sorted walk,
+    masking and the per-(Gaussian, segment) weight sums W_v (FP64), plus an
+    FP32 evaluation of the integer decisions (depth order, culling, box).
+  * this module -- the aggregation equation of the Method section:
+    E_k = sum_i sum_j W_i[k, j] E_ij / sum_i sum_j W_i[k, j], computed as one
+    sparse-times-dense product in FP64 (a library matmul), with E_k = 0 where
+    the denominator is 0.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+from typing import List, Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "slag_oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the C half of the oracle with gcc (FP64, OpenMP, no contraction)."""
+    if force or not os.path.exists(_SO):
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-shared",
+               "-fPIC", "-o", _SO + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class _Counts(ctypes.Structure):
+    _fields_ = [("n_contrib", ctypes.c_int64), ("n_tests", ctypes.c_int64),
+                ("n_visible", ctypes.c_int64), ("n_uncertain", ctypes.c_int64)]
+
+
+_lib_handle = None
+
+
+def _lib():
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        L = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        L.orc_lift_view.restype = P
+        L.orc_lift_view.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32,
+                                    P, P, ctypes.POINTER(_Counts), ctypes.POINTER(ctypes.c_int64)]
+        L.orc_view_fetch.argtypes = [P, P, P, P, P]
+        L.orc_view_free.argtypes = [P]
+        L.orc_mirror_view.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, P, P]
+        L.orc_project64_view.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, P, P]
+        L.orc_max_threads.restype = ctypes.c_int
+        _lib_handle = L
+    return _lib_handle
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def max_threads() -> int:
+    return int(_lib().orc_max_threads())
+
+
+@dataclasses.dataclass
+class ViewResult:
+    g: np.ndarray          # int32 Gaussian index
+    s: np.ndarray          # int32 view-local segment id
+    w: np.ndarray          # float64 W_v[g, s]
+    u: np.ndarray          # float64 decision-margin mass for the triple
+    n_contrib: int         # accepted blends (all pixels)
+    n_tests: int           # box-candidate evaluations before termination
+    n_visible: int
+    n_uncertain: int
+    T: Optional[np.ndarray] = None      # [H, W] final transmittance
+    wsum: Optional[np.ndarray] = None   # [H, W] sum of blend weights
+
+
+def lift_view(scene, v: int, mode: str = "box", pixels: bool = False,
+              nthreads: int = 0) -> ViewResult:
+    """W_v for one view (paper: rasterize, mask, sum over the view's pixels)."""
+    L = _lib()
+    cam = np.ascontiguousarray(scene.cams[v:v + 1])
+    ids = _c(scene.ids[v], np.int32)
+    H, W = ids.shape
+    T = np.empty((H, W), np.float64) if pixels else None
+    ws = np.empty((H, W), np.float64) if pixels else None
+    cnt = _Counts()
+    nt = ctypes.c_int64(0)
+    means, scales = _c(scene.means, np.float32), _c(scene.scales, np.float32)
+    quats, opac = _c(scene.quats, np.float32), _c(scene.opacity, np.float32)
+    h = L.orc_lift_view(scene.n, _p(means), _p(scales), _p(quats), _p(opac), _p(cam), _p(ids),
+                        0 if mode == "brute" else 1, int(nthreads), _p(T), _p(ws),
+                        ctypes.byref(cnt), ctypes.byref(nt))
+    if not h:
+        raise MemoryError("oracle view lift failed")
+    k = nt.value
+    g = np.empty(k, np.int32)
+    s = np.empty(k, np.int32)
+    w = np.empty(k, np.float64)
+    u = np.empty(k, np.float64)
+    L.orc_view_fetch(h, _p(g), _p(s), _p(w), _p(u))
+    L.orc_view_free(h)
+    return ViewResult(g, s, w, u, cnt.n_contrib, cnt.n_tests, cnt.n_visible, cnt.n_uncertain, T, ws)
+
+
+@dataclasses.dataclass
+class LiftResult:
+    num: np.ndarray        # [N, D] float64
+    den: np.ndarray        # [N] float64
+    E: np.ndarray          # [N, D] float64, 0 where den == 0
+    U: np.ndarray          # [N] float64 decision-margin mass per Gaussian
+    views: List[ViewResult]
+    n_contrib: int
+    n_tests: int
+
+
+def weight_matrix(scene, views: List[int], results: List[ViewResult], with_u: bool = False):
+    """Stack the per-view triples into one sparse [N, S_total] matrix."""
+    off = scene.seg_offsets
+    rows, cols, vals = [], [], []
+    for v, r in zip(views, results):
+        rows.append(r.g.astype(np.int64))
+        cols.append(off[v] + r.s.astype(np.int64))
+        vals.append(r.u if with_u else r.w)
+    if rows:
+        rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    else:
+        rows = cols = np.zeros(0, np.int64)
+        vals = np.zeros(0, np.float64)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(scene.n, int(off[-1])))
+
+
+def lift(scene, views: Optional[List[int]] = None, mode: str = "box",
+         nthreads: int = 0, pixels: bool = False) -> LiftResult:
+    """The lifted embeddings of the aggregation equation, in FP64."""
+    views = list(range(scene.n_views)) if views is None else [int(v) for v in views]
+    res = [lift_view(scene, v, mode=mode, nthreads=nthreads, pixels=pixels) for v in views]
+    Wm = weight_matrix(scene, views, res)
+    Um = weight_matrix(scene, views, res, with_u=True)
+    F = scene.feats_f64()
+    num = np.asarray(Wm @ F)
+    den = np.asarray(Wm.sum(axis=1)).ravel()
+    E = np.zeros_like(num)
+    nz = den > 0
+    E[nz] = num[nz] / den[nz, None]
+    U = np.asarray(Um.sum(axis=1)).ravel()
+    return LiftResult(num, den, E, U, res, sum(r.n_contrib for r in res),
+                      sum(r.n_tests for r in res))
+
+
+# ----------------------------------------------------------------------------
+# FP32 decisions: visibility, depth keys, tile membership
+
+@dataclasses.dataclass
+class MirrorView:
+    vis: np.ndarray     # uint8: 1 visible, 2 in front but off-screen, 0 culled
+    z32: np.ndarray     # float32 camera depth
+    box: np.ndarray     # int32 [N, 4] pixel box x0, x1, y0, y1 (valid where vis == 1)
+    mu: np.ndarray      # float32 [N, 2]
+    cov: np.ndarray     # float32 [N, 3]
+
+
+def mirror_view(scene, v: int) -> MirrorView:
+    L = _lib()
+    n = scene.n
+    cam = np.ascontiguousarray(scene.cams[v:v + 1])
+    vis = np.zeros(n, np.uint8)
+    z = np.zeros(n, np.float32)
+    box = np.zeros((n, 4), np.int32)
+    mu = np.zeros((n, 2), np.float32)
+    cov = np.zeros((n, 3), np.float32)
+    L.orc_mirror_view(n, _p(_c(scene.means, np.float32)), _p(_c(scene.scales, np.float32)),
+                      _p(_c(scene.quats, np.float32)), _p(cam), _p(vis), _p(z), _p(box),
+                      _p(mu), _p(cov))
+    return MirrorView(vis, z, box, mu, cov)
+
+
+def project64_view(scene, v: int):
+    """FP64 screen mean, covariance (with dilation), conic and camera depth."""
+    L = _lib()
+    n = scene.n
+    cam = np.ascontiguousarray(scene.cams[v:v + 1])
+    mu = np.zeros((n, 2))
+    cov = np.zeros((n, 3))
+    con = np.zeros((n, 3))
+    zc = np.zeros(n)
+    L.orc_project64_view(n, _p(_c(scene.means, np.float32)), _p(_c(scene.scales, np.float32)),
+                         _p(_c(scene.quats, np.float32)), _p(_c(scene.opacity, np.float32)),
+                         _p(cam), _p(mu), _p(cov), _p(con), _p(zc))
+    return mu, cov, con, zc
+
+
+def sorted_keys(scene, v: int, tile_w: int, tile_h: int, mv: Optional[MirrorView] = None):
+    """Reference tile lists of one view: (tile, depth bits, Gaussian) rows in
+    the order a front-to-back tile rasterizer must visit them -- ascending tile
+    (row-major tile index), then ascending FP32 depth, then Gaussian index."""
+    mv = mirror_view(scene, v) if mv is None else mv
+    W = int(scene.cams[v]["width"])
+    ntx = (W + tile_w - 1) // tile_w
+    g = np.flatnonzero(mv.vis == 1)
+    b = mv.box[g]
+    tx0, tx1 = b[:, 0] // tile_w, b[:, 1] // tile_w
+    ty0, ty1 = b[:, 2] // tile_h, b[:, 3] // tile_h
+    cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1)
+    tot = int(cnt.sum())
+    gi = np.repeat(g, cnt)
+    start = np.repeat(np.cumsum(cnt) - cnt, cnt)
+    k = np.arange(tot) - start
+    w = np.repeat(tx1 - tx0 + 1, cnt)
+    tx = np.repeat(tx0, cnt) + k % w
+    ty = np.repeat(ty0, cnt) + k // w
+    tile = (ty * ntx + tx).astype(np.int64)
+    zb = mv.z32[gi].view(np.uint32).astype(np.int64)
+    order = np.lexsort((gi, zb, tile))
+    return tile[order], zb[order].astype(np.uint32), gi[order].astype(np.int32)

@@ -1,0 +1,664 @@
+/*
+ * slag_oracle.c -- plain FP64 CPU oracle for the loss-free embedding lift.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test-suite, the smoke check and the benchmark's
+ * CPU-baseline leg use it.  It shares no code with the GPU library.
+ *
+ * What it computes (paper, Method section, "Semantic Embedding"):
+ *   - each Gaussian is projected to a screen mean and a 2D covariance
+ *     (the rasterizer call with K_i, R_i, t_i), here by EWA splatting;
+ *   - at every pixel p the Gaussians are visited front to back and each gets
+ *     the blend weight w_kp = alpha_kp * T_kp (the rasterizer's contribution
+ *     weight, our reading of the weight the modified rasterizer captures);
+ *   - the weight is masked by the segment that owns the pixel (parameter
+ *     masking, w'_kp = w_kp * M_j(p)) and summed per (Gaussian, segment)
+ *     (the aggregation equation's numerator and denominator sums over p).
+ * The view sums are returned as sparse (Gaussian, segment, W) triples; the
+ * contraction with the feature table and the normalisation are done by the
+ * Python half of the oracle.
+ *
+ * Conventions the paper leaves open (taken from 3D Gaussian splatting):
+ *   alpha = min(0.99, o * exp(-q/2)), q = d^T Sigma2^{-1} d, d = p - mu2,
+ *   p = pixel centre (u+0.5, v+0.5); contributions with alpha < 1/255 are
+ *   skipped; the walk stops *before* a Gaussian whose blend would take the
+ *   transmittance below 1e-4; Sigma2 gets +0.3 px^2 on its diagonal; the
+ *   Jacobian is evaluated at x/z, y/z clamped to 1.3 x the half-FOV tangent;
+ *   Gaussians with camera z <= 0.01 are culled.  q is clamped at 0 (a
+ *   positive-definite conic never gives q < 0; only rounding could).
+ *
+ * Depth order and culling are integer decisions taken from floating point,
+ * so they are taken in the kernel's precision: this file carries its own
+ * FP32 evaluation of camera depth and of the conservative pixel box, written
+ * op by op from the normative sequence documented with the library (fmaf
+ * where a fused multiply-add is specified, correctly rounded / and sqrt, no
+ * other contraction; build with -ffp-contract=off).  Everything that weighs a
+ * contribution is FP64.
+ *
+ * Decision margins.  An FP32 evaluation can flip a threshold decision that
+ * lies within rounding of its threshold.  For every such decision this file
+ * records an uncertainty mass U[g,s] that bounds how much W[g,s] could move
+ * because of it (see composite_pixel).  With U = 0 a triple must match
+ * exactly in membership.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    int32_t width, height;
+} orc_camera;
+
+typedef struct {
+    int64_t n_contrib;          /* accepted blends, all pixels (background included) */
+    int64_t n_tests;            /* box candidates evaluated before termination */
+    int64_t n_visible;          /* Gaussians with z > near, det > 0, non-empty box */
+    int64_t n_uncertain;        /* near-threshold decisions met */
+} orc_counts;
+
+/* ---- FP32 decision constants (float literals, exact bit patterns) ---- */
+#define F_NEAR  0.01f
+#define F_DIL   0.3f
+#define F_CLAMP 1.3f
+#define F_RHO2  0x1.62a41p+3f       /* float nearest to 2 ln 255 */
+
+/* ---- FP64 weighting constants ---- */
+#define D_AMIN (1.0 / 255.0)
+#define D_AMAX 0.99
+#define D_TMIN 1e-4
+#define D_DIL 0.3
+#define D_CLAMP 1.3
+/* relative half-widths of the bands in which an FP32 decision may differ */
+#define EPS_ALPHA 1e-3
+#define EPS_T 1e-3
+
+/* ========================================================================
+ * FP32 mirror: camera depth, culling and the conservative pixel box.
+ * ====================================================================== */
+typedef struct {
+    int vis_depth;      /* z32 > near and det32 > 0 */
+    int vis;            /* vis_depth and the box is non-empty */
+    float z32;
+    int32_t x0, x1, y0, y1;
+    float u, v, c00, c01, c11;
+} mirror_out;
+
+static void mirror_project(const float* m, const float* s, const float* q,
+                           const orc_camera* c, mirror_out* o)
+{
+    const float* R = c->R;
+    memset(o, 0, sizeof(*o));
+    float X = fmaf(R[0], m[0], fmaf(R[1], m[1], fmaf(R[2], m[2], c->t[0])));
+    float Y = fmaf(R[3], m[0], fmaf(R[4], m[1], fmaf(R[5], m[2], c->t[1])));
+    float Z = fmaf(R[6], m[0], fmaf(R[7], m[1], fmaf(R[8], m[2], c->t[2])));
+    o->z32 = Z;
+    if (!(Z > F_NEAR)) return;
+
+    float nq = fmaf(q[0], q[0], fmaf(q[1], q[1], fmaf(q[2], q[2], q[3] * q[3])));
+    float rn = 1.0f / sqrtf(nq);
+    float w = q[0] * rn, x = q[1] * rn, y = q[2] * rn, z = q[3] * rn;
+    float r[9];
+    r[0] = 1.0f - 2.0f * fmaf(y, y, z * z);
+    r[1] = 2.0f * fmaf(x, y, -(w * z));
+    r[2] = 2.0f * fmaf(x, z, (w * y));
+    r[3] = 2.0f * fmaf(x, y, (w * z));
+    r[4] = 1.0f - 2.0f * fmaf(x, x, z * z);
+    r[5] = 2.0f * fmaf(y, z, -(w * x));
+    r[6] = 2.0f * fmaf(x, z, -(w * y));
+    r[7] = 2.0f * fmaf(y, z, (w * x));
+    r[8] = 1.0f - 2.0f * fmaf(x, x, y * y);
+    float M[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) M[3 * i + j] = r[3 * i + j] * s[j];
+    float S[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = i; j < 3; j++) {
+            float v = fmaf(M[3 * i + 0], M[3 * j + 0],
+                           fmaf(M[3 * i + 1], M[3 * j + 1], M[3 * i + 2] * M[3 * j + 2]));
+            S[3 * i + j] = v;
+            S[3 * j + i] = v;
+        }
+
+    float iz = 1.0f / Z;
+    float txr = X * iz, tyr = Y * iz;
+    float limx = F_CLAMP * ((0.5f * (float)c->width) / c->fx);
+    float limy = F_CLAMP * ((0.5f * (float)c->height) / c->fy);
+    float tx = fminf(limx, fmaxf(-limx, txr));
+    float ty = fminf(limy, fmaxf(-limy, tyr));
+    float j00 = c->fx * iz, j02 = -(j00 * tx);
+    float j11 = c->fy * iz, j12 = -(j11 * ty);
+    float A[6];
+    for (int k = 0; k < 3; k++) {
+        A[k] = fmaf(j00, R[k], j02 * R[6 + k]);
+        A[3 + k] = fmaf(j11, R[3 + k], j12 * R[6 + k]);
+    }
+    float B[6];
+    for (int i = 0; i < 2; i++)
+        for (int k = 0; k < 3; k++)
+            B[3 * i + k] = fmaf(A[3 * i + 0], S[0 + k],
+                                fmaf(A[3 * i + 1], S[3 + k], A[3 * i + 2] * S[6 + k]));
+    float c00 = fmaf(B[0], A[0], fmaf(B[1], A[1], B[2] * A[2])) + F_DIL;
+    float c01 = fmaf(B[0], A[3], fmaf(B[1], A[4], B[2] * A[5]));
+    float c11 = fmaf(B[3], A[3], fmaf(B[4], A[4], B[5] * A[5])) + F_DIL;
+    float det = fmaf(c00, c11, -(c01 * c01));
+    if (!(det > 0.0f)) return;
+    o->vis_depth = 1;
+
+    float u = fmaf(c->fx, txr, c->cx);
+    float v = fmaf(c->fy, tyr, c->cy);
+    float ex = sqrtf(F_RHO2 * c00);
+    float ey = sqrtf(F_RHO2 * c11);
+    float x0 = ceilf(u - (ex + 1.5f)), x1 = floorf(u + (ex + 0.5f));
+    float y0 = ceilf(v - (ey + 1.5f)), y1 = floorf(v + (ey + 0.5f));
+    float wm1 = (float)(c->width - 1), hm1 = (float)(c->height - 1);
+    o->u = u; o->v = v; o->c00 = c00; o->c01 = c01; o->c11 = c11;
+    if (!(x0 <= wm1 && x1 >= 0.0f && y0 <= hm1 && y1 >= 0.0f)) return;
+    x0 = fmaxf(x0, 0.0f); x1 = fminf(x1, wm1);
+    y0 = fmaxf(y0, 0.0f); y1 = fminf(y1, hm1);
+    o->x0 = (int32_t)x0; o->x1 = (int32_t)x1;
+    o->y0 = (int32_t)y0; o->y1 = (int32_t)y1;
+    o->vis = 1;
+}
+
+/* ========================================================================
+ * FP64 EWA projection (the rasterizer's projection step).
+ * ====================================================================== */
+typedef struct {
+    double mu[2];
+    double cov[3];      /* Sigma2 (with dilation): xx, xy, yy */
+    double conic[3];    /* Sigma2^{-1}: xx, xy, yy */
+    double zc;          /* camera-space depth */
+    double o;
+} proj64;
+
+static void project64(const float* mf, const float* sf, const float* qf, float opac,
+                      const orc_camera* c, proj64* p)
+{
+    double R[9], t[3], m[3];
+    for (int i = 0; i < 9; i++) R[i] = c->R[i];
+    for (int i = 0; i < 3; i++) { t[i] = c->t[i]; m[i] = mf[i]; }
+    /* camera-space mean: m_c = R mu + t */
+    double X = R[0] * m[0] + R[1] * m[1] + R[2] * m[2] + t[0];
+    double Y = R[3] * m[0] + R[4] * m[1] + R[5] * m[2] + t[1];
+    double Z = R[6] * m[0] + R[7] * m[1] + R[8] * m[2] + t[2];
+    /* rotation of the Gaussian from its unit quaternion (w, x, y, z) */
+    double qn = sqrt((double)qf[0] * qf[0] + (double)qf[1] * qf[1] +
+                     (double)qf[2] * qf[2] + (double)qf[3] * qf[3]);
+    double w = qf[0] / qn, x = qf[1] / qn, y = qf[2] / qn, z = qf[3] / qn;
+    double Rq[9] = {
+        1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+        2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+        2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+    /* world covariance Sigma3 = Rq diag(s^2) Rq^T */
+    double S[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double acc = 0;
+            for (int k = 0; k < 3; k++)
+                acc += Rq[3 * i + k] * ((double)sf[k] * sf[k]) * Rq[3 * j + k];
+            S[3 * i + j] = acc;
+        }
+    /* camera covariance C = R Sigma3 R^T */
+    double RS[9], C[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double acc = 0;
+            for (int k = 0; k < 3; k++) acc += R[3 * i + k] * S[3 * k + j];
+            RS[3 * i + j] = acc;
+        }
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double acc = 0;
+            for (int k = 0; k < 3; k++) acc += RS[3 * i + k] * R[3 * j + k];
+            C[3 * i + j] = acc;
+        }
+    /* Jacobian of (fx X/Z + cx, fy Y/Z + cy) at the guard-clamped point */
+    double limx = D_CLAMP * (0.5 * c->width / (double)c->fx);
+    double limy = D_CLAMP * (0.5 * c->height / (double)c->fy);
+    double txz = X / Z, tyz = Y / Z;
+    double cx_ = fmin(limx, fmax(-limx, txz)), cy_ = fmin(limy, fmax(-limy, tyz));
+    double J[6] = {c->fx / Z, 0.0, -c->fx * cx_ / Z, 0.0, c->fy / Z, -c->fy * cy_ / Z};
+    /* Sigma2 = J C J^T + 0.3 I */
+    double JC[6];
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 3; j++) {
+            double acc = 0;
+            for (int k = 0; k < 3; k++) acc += J[3 * i + k] * C[3 * k + j];
+            JC[3 * i + j] = acc;
+        }
+    double s2[4];
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++) {
+            double acc = 0;
+            for (int k = 0; k < 3; k++) acc += JC[3 * i + k] * J[3 * j + k];
+            s2[2 * i + j] = acc;
+        }
+    double a = s2[0] + D_DIL, b = 0.5 * (s2[1] + s2[2]), d = s2[3] + D_DIL;
+    double det = a * d - b * b;
+    p->cov[0] = a; p->cov[1] = b; p->cov[2] = d;
+    p->conic[0] = d / det; p->conic[1] = -b / det; p->conic[2] = a / det;
+    p->mu[0] = c->fx * txz + c->cx;
+    p->mu[1] = c->fy * tyz + c->cy;
+    p->zc = Z;
+    p->o = opac;
+}
+
+/* ========================================================================
+ * growable arrays and a (g,s) -> (W,U) hash map
+ * ====================================================================== */
+typedef struct { int32_t g, s; double w, u; } contrib;
+typedef struct { contrib* a; int64_t n, cap; } cbuf;
+
+static int cbuf_push(cbuf* b, int32_t g, int32_t s, double w, double u)
+{
+    if (b->n == b->cap) {
+        int64_t nc = b->cap ? 2 * b->cap : 256;
+        contrib* na = (contrib*)realloc(b->a, (size_t)nc * sizeof(contrib));
+        if (!na) return -1;
+        b->a = na; b->cap = nc;
+    }
+    b->a[b->n].g = g; b->a[b->n].s = s; b->a[b->n].w = w; b->a[b->n].u = u;
+    b->n++;
+    return 0;
+}
+
+typedef struct { uint64_t* key; double* w; double* u; int64_t cap, n; } hmap;
+#define HEMPTY 0xFFFFFFFFFFFFFFFFull
+
+static int hmap_init(hmap* h, int64_t cap)
+{
+    int64_t c = 1024;
+    while (c < 2 * cap) c <<= 1;
+    h->key = (uint64_t*)malloc((size_t)c * 8);
+    h->w = (double*)calloc((size_t)c, 8);
+    h->u = (double*)calloc((size_t)c, 8);
+    if (!h->key || !h->w || !h->u) return -1;
+    memset(h->key, 0xFF, (size_t)c * 8);
+    h->cap = c; h->n = 0;
+    return 0;
+}
+
+static void hmap_free(hmap* h) { free(h->key); free(h->w); free(h->u); }
+
+static int64_t hslot(const hmap* h, uint64_t k)
+{
+    uint64_t x = k * 0x9E3779B97F4A7C15ull;
+    int64_t i = (int64_t)(x >> 17) & (h->cap - 1);
+    while (h->key[i] != HEMPTY && h->key[i] != k) i = (i + 1) & (h->cap - 1);
+    return i;
+}
+
+static int hmap_add(hmap* h, uint64_t k, double w, double u)
+{
+    if (2 * (h->n + 1) > h->cap) {
+        hmap nh;
+        if (hmap_init(&nh, h->cap)) return -1;
+        for (int64_t i = 0; i < h->cap; i++)
+            if (h->key[i] != HEMPTY) {
+                int64_t j = hslot(&nh, h->key[i]);
+                nh.key[j] = h->key[i]; nh.w[j] = h->w[i]; nh.u[j] = h->u[i]; nh.n++;
+            }
+        hmap_free(h);
+        *h = nh;
+    }
+    int64_t i = hslot(h, k);
+    if (h->key[i] == HEMPTY) { h->key[i] = k; h->n++; }
+    h->w[i] += w;
+    h->u[i] += u;
+    return 0;
+}
+
+/* ========================================================================
+ * per-pixel front-to-back walk
+ * ====================================================================== */
+typedef struct {
+    const proj64* P;
+    const mirror_out* Mi;
+} view_ctx;
+
+static inline double alpha_at(const proj64* p, double px, double py)
+{
+    double dx = px - p->mu[0], dy = py - p->mu[1];
+    double q = p->conic[0] * dx * dx + 2.0 * p->conic[1] * dx * dy + p->conic[2] * dy * dy;
+    if (q < 0.0) q = 0.0;
+    double a = p->o * exp(-0.5 * q);
+    return a < D_AMAX ? a : D_AMAX;
+}
+
+/*
+ * Walk the depth-ordered candidates of one pixel.  Emits (g, s, w, u) for
+ * accepted blends when the pixel has a segment (s >= 0).
+ *
+ * u bounds how far an FP32 walk could move this contribution:
+ *  - a blend with alpha within EPS_ALPHA of 1/255 may be skipped (u = w),
+ *    and one just below may be taken (a zero-weight entry with u = alpha T);
+ *    either flip scales the transmittance seen by everything behind it by
+ *    about (1 - alpha), so later blends get u += w * delta, delta += alpha;
+ *  - a stop decision with T' within (EPS_T + delta) of 1e-4 may go the
+ *    other way: if the walk continues here, this and every later blend may
+ *    vanish (u = w, delta = 1); if it stops here, this Gaussian and the next
+ *    acceptable one may still be blended (entries with u = their weights).
+ */
+static int composite_pixel(const view_ctx* vc, const int32_t* cand, int64_t nc,
+                           int ix, int iy, int32_t seg, cbuf* out,
+                           double* T_out, double* wsum_out, int64_t* n_c, int64_t* n_q,
+                           int64_t* n_unc, int count_box_only)
+{
+    const double px = ix + 0.5, py = iy + 0.5;
+    double T = 1.0, delta = 0.0, sumw = 0.0;
+    for (int64_t k = 0; k < nc; k++) {
+        const int32_t g = cand[k];
+        const proj64* p = &vc->P[g];
+        const mirror_out* mo = &vc->Mi[g];
+        if (!count_box_only || (mo->vis && ix >= mo->x0 && ix <= mo->x1 && iy >= mo->y0 && iy <= mo->y1))
+            (*n_q)++;
+        double alpha = alpha_at(p, px, py);
+        if (alpha < D_AMIN) {
+            if (alpha >= D_AMIN * (1.0 - EPS_ALPHA)) {
+                (*n_unc)++;
+                if (seg >= 0 && cbuf_push(out, g, seg, 0.0, alpha * T)) return -1;
+                delta += alpha;
+            }
+            continue;
+        }
+        int near_a = alpha < D_AMIN * (1.0 + EPS_ALPHA);
+        double Tn = T * (1.0 - alpha);
+        double band = (EPS_T + delta) * D_TMIN;
+        int near_t = fabs(Tn - D_TMIN) <= band;
+        if (near_a || near_t) (*n_unc)++;
+        if (Tn < D_TMIN) {
+            if (near_t && seg >= 0) {
+                if (cbuf_push(out, g, seg, 0.0, alpha * T)) return -1;
+                for (int64_t h = k + 1; h < nc; h++) {
+                    double ah = alpha_at(&vc->P[cand[h]], px, py);
+                    if (ah >= D_AMIN * (1.0 - EPS_ALPHA)) {
+                        if (cbuf_push(out, cand[h], seg, 0.0, ah * Tn)) return -1;
+                        break;
+                    }
+                }
+            }
+            break;
+        }
+        double w = alpha * T;
+        double u = w * (delta < 1.0 ? delta : 1.0);
+        if (near_a) u = w;
+        if (near_t) { u = w; delta = 1.0; }
+        (*n_c)++;
+        sumw += w;
+        if (seg >= 0 && cbuf_push(out, g, seg, w, u)) return -1;
+        if (near_a) delta += alpha;
+        T = Tn;
+    }
+    *T_out = T;
+    *wsum_out = sumw;
+    return 0;
+}
+
+/* depth order: ascending FP32 camera z, ties to the lower Gaussian index */
+static const float* g_sort_z;
+static int cmp_depth(const void* a, const void* b)
+{
+    int32_t ga = *(const int32_t*)a, gb = *(const int32_t*)b;
+    float za = g_sort_z[ga], zb = g_sort_z[gb];
+    if (za < zb) return -1;
+    if (za > zb) return 1;
+    return (ga > gb) - (ga < gb);
+}
+
+typedef struct { const float* z; int32_t* a; } sort_job;
+
+/* insertion/merge sort on a small array with the same order as cmp_depth;
+ * thread-safe (no global state) */
+static void sort_depth(int32_t* a, int64_t n, const float* z, int32_t* tmp)
+{
+    if (n < 24) {
+        for (int64_t i = 1; i < n; i++) {
+            int32_t v = a[i];
+            int64_t j = i - 1;
+            while (j >= 0 && (z[a[j]] > z[v] || (z[a[j]] == z[v] && a[j] > v))) {
+                a[j + 1] = a[j];
+                j--;
+            }
+            a[j + 1] = v;
+        }
+        return;
+    }
+    int64_t h = n / 2;
+    sort_depth(a, h, z, tmp);
+    sort_depth(a + h, n - h, z, tmp);
+    int64_t i = 0, j = h, k = 0;
+    while (i < h && j < n) {
+        int32_t x = a[i], y = a[j];
+        int take_y = (z[y] < z[x]) || (z[y] == z[x] && y < x);
+        tmp[k++] = take_y ? a[j++] : a[i++];
+    }
+    while (i < h) tmp[k++] = a[i++];
+    while (j < n) tmp[k++] = a[j++];
+    memcpy(a, tmp, (size_t)n * sizeof(int32_t));
+}
+
+typedef struct {
+    int64_t n_triples;
+    int32_t* g;
+    int32_t* s;
+    double* w;
+    double* u;
+} view_result;
+
+static int cmp_u64(const void* a, const void* b)
+{
+    uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return (x > y) - (x < y);
+}
+
+/*
+ * Lift one view.  mode 0 = brute (every Gaussian in front of the camera is a
+ * candidate of every pixel), mode 1 = box (only Gaussians whose conservative
+ * pixel box contains the pixel).  Both walk candidates in the same depth
+ * order, so the two must agree bit for bit.
+ */
+void* orc_lift_view(int64_t n, const float* means, const float* scales, const float* quats,
+                    const float* opacity, const orc_camera* cam, const int32_t* ids,
+                    int32_t mode, int32_t nthreads, double* pix_T, double* pix_wsum,
+                    orc_counts* counts, int64_t* n_triples)
+{
+    const int W = cam->width, H = cam->height;
+    proj64* P = (proj64*)malloc((size_t)(n ? n : 1) * sizeof(proj64));
+    mirror_out* Mi = (mirror_out*)malloc((size_t)(n ? n : 1) * sizeof(mirror_out));
+    float* z = (float*)malloc((size_t)(n ? n : 1) * sizeof(float));
+    if (!P || !Mi || !z) return NULL;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int64_t nvis = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nvis)
+    for (int64_t g = 0; g < n; g++) {
+        mirror_project(means + 3 * g, scales + 3 * g, quats + 4 * g, cam, &Mi[g]);
+        z[g] = Mi[g].z32;
+        if (Mi[g].vis_depth) project64(means + 3 * g, scales + 3 * g, quats + 4 * g, opacity[g], cam, &P[g]);
+        nvis += Mi[g].vis;
+    }
+
+    /* candidate lists */
+    const int64_t npix = (int64_t)W * H;
+    int64_t* start = (int64_t*)calloc((size_t)npix + 1, sizeof(int64_t));
+    int32_t* cand = NULL;
+    int32_t* all = NULL;
+    int64_t nall = 0;
+    if (!start) return NULL;
+    if (mode == 0) {
+        all = (int32_t*)malloc((size_t)(n ? n : 1) * sizeof(int32_t));
+        if (!all) return NULL;
+        for (int64_t g = 0; g < n; g++)
+            if (Mi[g].vis_depth) all[nall++] = (int32_t)g;
+        g_sort_z = z;
+        qsort(all, (size_t)nall, sizeof(int32_t), cmp_depth);
+    } else {
+        for (int64_t g = 0; g < n; g++) {
+            const mirror_out* m = &Mi[g];
+            if (!m->vis) continue;
+            for (int y = m->y0; y <= m->y1; y++)
+                for (int x = m->x0; x <= m->x1; x++) start[(int64_t)y * W + x + 1]++;
+        }
+        for (int64_t i = 0; i < npix; i++) start[i + 1] += start[i];
+        cand = (int32_t*)malloc((size_t)(start[npix] ? start[npix] : 1) * sizeof(int32_t));
+        int64_t* fill = (int64_t*)malloc((size_t)(npix ? npix : 1) * sizeof(int64_t));
+        if (!cand || !fill) return NULL;
+        memcpy(fill, start, (size_t)npix * sizeof(int64_t));
+        for (int64_t g = 0; g < n; g++) {
+            const mirror_out* m = &Mi[g];
+            if (!m->vis) continue;
+            for (int y = m->y0; y <= m->y1; y++)
+                for (int x = m->x0; x <= m->x1; x++) cand[fill[(int64_t)y * W + x]++] = (int32_t)g;
+        }
+        free(fill);
+    }
+
+    /* walk every pixel; rows in parallel, contributions kept per row */
+    view_ctx vc = {P, Mi};
+    cbuf* rows = (cbuf*)calloc((size_t)(H ? H : 1), sizeof(cbuf));
+    int64_t nc_tot = 0, nq_tot = 0, nu_tot = 0;
+    int failed = 0;
+    int64_t maxc = 0;
+    if (mode == 1)
+        for (int64_t i = 0; i < npix; i++)
+            if (start[i + 1] - start[i] > maxc) maxc = start[i + 1] - start[i];
+#pragma omp parallel reduction(+ : nc_tot, nq_tot, nu_tot)
+    {
+        int32_t* tmp = (int32_t*)malloc((size_t)(maxc + 1) * sizeof(int32_t));
+#pragma omp for schedule(dynamic, 1)
+        for (int y = 0; y < H; y++) {
+            for (int x = 0; x < W; x++) {
+                const int64_t pi = (int64_t)y * W + x;
+                const int32_t seg = ids[pi];
+                const int32_t* c;
+                int64_t ncand;
+                if (mode == 0) {
+                    c = all;
+                    ncand = nall;
+                } else {
+                    ncand = start[pi + 1] - start[pi];
+                    sort_depth(cand + start[pi], ncand, z, tmp);
+                    c = cand + start[pi];
+                }
+                double Tf = 1.0, ws = 0.0;
+                if (composite_pixel(&vc, c, ncand, x, y, seg, &rows[y], &Tf, &ws,
+                                    &nc_tot, &nq_tot, &nu_tot, mode == 0))
+                    failed = 1;
+                if (pix_T) pix_T[pi] = Tf;
+                if (pix_wsum) pix_wsum[pi] = ws;
+            }
+        }
+        free(tmp);
+    }
+
+    /* accumulate in pixel order (row-major, then depth order) */
+    int64_t tot = 0;
+    for (int y = 0; y < H; y++) tot += rows[y].n;
+    hmap hm;
+    if (failed || hmap_init(&hm, tot / 4 + 16)) return NULL;
+    for (int y = 0; y < H; y++) {
+        for (int64_t i = 0; i < rows[y].n; i++) {
+            const contrib* e = &rows[y].a[i];
+            if (hmap_add(&hm, ((uint64_t)(uint32_t)e->g << 32) | (uint32_t)e->s, e->w, e->u)) return NULL;
+        }
+        free(rows[y].a);
+    }
+    free(rows);
+
+    view_result* vr = (view_result*)calloc(1, sizeof(view_result));
+    uint64_t* keys = (uint64_t*)malloc((size_t)(hm.n ? hm.n : 1) * 8);
+    int64_t k = 0;
+    for (int64_t i = 0; i < hm.cap; i++)
+        if (hm.key[i] != HEMPTY) keys[k++] = hm.key[i];
+    qsort(keys, (size_t)k, 8, cmp_u64);
+    vr->n_triples = k;
+    vr->g = (int32_t*)malloc((size_t)(k ? k : 1) * 4);
+    vr->s = (int32_t*)malloc((size_t)(k ? k : 1) * 4);
+    vr->w = (double*)malloc((size_t)(k ? k : 1) * 8);
+    vr->u = (double*)malloc((size_t)(k ? k : 1) * 8);
+    for (int64_t i = 0; i < k; i++) {
+        int64_t sl = hslot(&hm, keys[i]);
+        vr->g[i] = (int32_t)(keys[i] >> 32);
+        vr->s[i] = (int32_t)(keys[i] & 0xFFFFFFFFu);
+        vr->w[i] = hm.w[sl];
+        vr->u[i] = hm.u[sl];
+    }
+    free(keys);
+    hmap_free(&hm);
+    free(start); free(cand); free(all); free(P); free(Mi); free(z);
+    if (counts) {
+        counts->n_contrib = nc_tot;
+        counts->n_tests = nq_tot;
+        counts->n_visible = nvis;
+        counts->n_uncertain = nu_tot;
+    }
+    if (n_triples) *n_triples = k;
+    return vr;
+}
+
+void orc_view_fetch(void* h, int32_t* g, int32_t* s, double* w, double* u)
+{
+    view_result* vr = (view_result*)h;
+    size_t k = (size_t)vr->n_triples;
+    if (g) memcpy(g, vr->g, k * 4);
+    if (s) memcpy(s, vr->s, k * 4);
+    if (w) memcpy(w, vr->w, k * 8);
+    if (u) memcpy(u, vr->u, k * 8);
+}
+
+void orc_view_free(void* h)
+{
+    view_result* vr = (view_result*)h;
+    if (!vr) return;
+    free(vr->g); free(vr->s); free(vr->w); free(vr->u);
+    free(vr);
+}
+
+/* FP32 mirror for every Gaussian of one view: visibility, depth and box. */
+void orc_mirror_view(int64_t n, const float* means, const float* scales, const float* quats,
+                     const orc_camera* cam, uint8_t* vis, float* z32, int32_t* box,
+                     float* mu, float* cov)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t g = 0; g < n; g++) {
+        mirror_out m;
+        mirror_project(means + 3 * g, scales + 3 * g, quats + 4 * g, cam, &m);
+        if (vis) vis[g] = (uint8_t)(m.vis ? 1 : (m.vis_depth ? 2 : 0));
+        if (z32) z32[g] = m.z32;
+        if (box) { box[4 * g] = m.x0; box[4 * g + 1] = m.x1; box[4 * g + 2] = m.y0; box[4 * g + 3] = m.y1; }
+        if (mu) { mu[2 * g] = m.u; mu[2 * g + 1] = m.v; }
+        if (cov) { cov[3 * g] = m.c00; cov[3 * g + 1] = m.c01; cov[3 * g + 2] = m.c11; }
+    }
+}
+
+/* FP64 projection of every Gaussian for one view (for closed-form checks). */
+void orc_project64_view(int64_t n, const float* means, const float* scales, const float* quats,
+                        const float* opacity, const orc_camera* cam, double* mu, double* cov,
+                        double* conic, double* zc)
+{
+    for (int64_t g = 0; g < n; g++) {
+        proj64 p;
+        project64(means + 3 * g, scales + 3 * g, quats + 4 * g, opacity[g], cam, &p);
+        if (mu) { mu[2 * g] = p.mu[0]; mu[2 * g + 1] = p.mu[1]; }
+        if (cov) for (int i = 0; i < 3; i++) cov[3 * g + i] = p.cov[i];
+        if (conic) for (int i = 0; i < 3; i++) conic[3 * g + i] = p.conic[i];
+        if (zc) zc[g] = p.zc;
+    }
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
