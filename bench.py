@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput of the segment-embedding lift on one MI355X.
+
+One step = one full lift (tile segment tables, projection, depth sort,
+binning, tile sort, compositing with masking, merge, contraction and
+normalisation) of the 200k-Gaussian / 100-view / D=512 BF16 synthetic scene,
+with every input resident in HBM before the timed region.
+
+Prints one JSON line: views/s (value), Gaussian-pixel contributions/s, the
+dominant kernel's achieved rate against its roofline (from HIP events on the
+library's stream), and the FP64 CPU oracle's rate on a bounded sample of the
+same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "plain_bf16_200k"
+WORKLOAD_DESC = ("200k Gaussians in 20 anisotropic clusters, 100 spiral views 512x384, "
+                 "40-80 Voronoi segments/view + ~10% background, D=512 BF16 features")
+METRIC = "lift views/s + Gaussian-pixel contribs/s at 1 GPU"
+
+# Peaks of one MI355X (vendor figures; 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz)
+HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12      # lane-operations per second (non-packed)
+# Minimal VALU issue slots per (pixel, Gaussian) support test of the blend
+# arithmetic: 2 sub, 5 mul/fma for the exponent, 1 clamp, exp2 (4 slots,
+# quarter rate), 1 mul + 1 min for alpha, 1 compare, 1 fma for T', 1 compare,
+# 1 mul for w, 1 select.
+OPS_PER_TEST = 19
+
+
+def _log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_2505_08124_amd", "csrc", "k_raster.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per composite launch from the committed PMC summary, if it was
+    taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "composite_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash() or d.get("workload") != WORKLOAD:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(scene, budget_s: float):
+    import oracle
+    views = []
+    t0 = time.perf_counter()
+    for v in range(scene.n_views):
+        views.append(v)
+        oracle.lift_view(scene, v)
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=len(views) / dt, unit="views/s", cores=oracle.max_threads(), kind="oracle",
+                sample=f"first {len(views)} of {scene.n_views} views of the same scene "
+                       f"(per-view W_v lift, FP64, box candidates), {dt:.1f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of oracle work for the CPU baseline (0 = skip)")
+    ap.add_argument("--no-count", action="store_true", help="skip the counting lift")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the lift is not sharded "
+              "across GPUs in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    import paper_2505_08124_amd as slag
+    from synthetic import make_scene
+
+    _log("generating scene", WORKLOAD)
+    scene = make_scene(WORKLOAD)
+    V = scene.n_views
+
+    # contributions and in-box tests (a separate counting lift, not timed)
+    n_contrib = n_tests = None
+    if not args.no_count:
+        with slag.Lifter(0, flags=slag.SLAG_FLAG_COUNT) as Lc:
+            Lc.set_scene(scene, device_tensors=True)
+            Lc.lift()
+            st = Lc.stats()
+            n_contrib, n_tests = st["n_contrib"], st["n_tests"]
+            n_tile_tests = st["n_tile_tests"]
+        _log(f"contributions {n_contrib}, in-box tests {n_tests}, tile tests {n_tile_tests}")
+
+    L = slag.Lifter(0, flags=slag.SLAG_FLAG_PROFILE)
+    L.set_scene(scene, device_tensors=True)
+    for _ in range(args.warmup):
+        L.lift()
+    L.embeddings()
+    torch.cuda.synchronize()
+    stage_ms = {}
+    ev_total = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        L.lift()
+        st = L.stats()          # synchronises; HIP-event stage times of this lift
+        ev_total += st["ms_total"]
+        for k, v in st["ms_stage"].items():
+            stage_ms[k] = stage_ms.get(k, 0.0) + v
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    stage_ms = {k: v / args.steps for k, v in stage_ms.items()}
+    _log("stage ms:", json.dumps({k: round(v, 4) for k, v in stage_ms.items()}))
+    _log(f"step {ms_step:.3f} ms wall, {ev_total / args.steps:.3f} ms HIP events")
+    E, den = L.embeddings()
+    assert np.isfinite(E).all()
+    info = L.stats()
+    L.close()
+
+    dom = max(stage_ms, key=stage_ms.get)
+    comp_ms = stage_ms.get("composite", 0.0)
+    roof = None
+    if n_tests is not None and comp_ms > 0:
+        ach = n_tests * OPS_PER_TEST / (comp_ms * 1e-3) / 1e12
+        roof = dict(kernel="k_composite", bound="alu", achieved=round(ach, 4),
+                    peak=round(VALU_PEAK_TOPS, 3), unit="Tops/s",
+                    frac=round(ach / VALU_PEAK_TOPS, 4), traffic=measured_traffic(),
+                    ops_per_test=OPS_PER_TEST, tests_per_launch=n_tests,
+                    avg_launch_ms=round(comp_ms, 4), dominant_stage=dom)
+
+    cpu = None
+    if args.cpu_budget > 0:
+        _log("timing the CPU oracle")
+        cpu = cpu_baseline(scene, args.cpu_budget)
+
+    out = {
+        "metric": METRIC,
+        "value": round(V / (ms_step * 1e-3), 2),
+        "unit": "views/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "desc": WORKLOAD_DESC, "n_gaussians": scene.n,
+                   "n_views": V, "resolution": [512, 384], "feature_dim": scene.dim,
+                   "feature_dtype": "bf16", "parallelism": "single GPU"},
+        "contribs_per_s": (round(n_contrib / (ms_step * 1e-3), 1) if n_contrib else None),
+        "n_contrib": n_contrib,
+        "n_visible_pairs": info["n_visible_pairs"],
+        "n_intersections": info["n_intersections"],
+        "ms_per_step_hip_events": round(ev_total / args.steps, 4),
+        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

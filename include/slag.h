@@ -1,0 +1,156 @@
+/*
+ * slag.h -- C interface of the MI355X (gfx950) lift of per-view segment
+ * embeddings into per-Gaussian embeddings.
+ *
+ * The operation (paper, Method section, "Semantic Embedding"):
+ *   1. every Gaussian G_k of the scene is rasterized with each training
+ *      camera (K_i, R_i, t_i); the rasterizer yields, for every pixel p, the
+ *      weights w_kp of the Gaussians contributing to p (the rasterizer
+ *      equation); here w_kp = alpha_kp * T_kp, the front-to-back blend weight;
+ *   2. the weights are masked by the segment that owns the pixel (parameter
+ *      masking, w'_kp = w_kp * M_j(p));
+ *   3. each Gaussian's embedding is the weight-normalised sum of the segment
+ *      features over all views, segments and pixels (the aggregation
+ *      equation): E_k = sum w'_kp E_ij / sum w'_kp, and E_k = 0 when the sum
+ *      of weights is 0.
+ *
+ * Conventions the paper does not fix (3D Gaussian splatting's):
+ *   alpha = min(0.99, o exp(-q/2)) with q = d^T Sigma2^{-1} d, d = pixel
+ *   centre (u+0.5, v+0.5) minus the projected mean; blends with alpha < 1/255
+ *   are skipped; a pixel stops before the Gaussian that would take its
+ *   transmittance below 1e-4; Sigma2 is the EWA projection with the Jacobian
+ *   at x/z, y/z clamped to 1.3 x the half-FOV tangent, plus 0.3 px^2 on the
+ *   diagonal; Gaussians with camera depth <= 0.01 are culled.  Per pixel the
+ *   Gaussians are visited by ascending FP32 camera depth, ties by ascending
+ *   Gaussian index.  Depth, culling and the conservative pixel box are
+ *   evaluated by a fixed FP32 operation sequence (see the library's
+ *   projection source), so they are reproducible bit for bit on the CPU.
+ *
+ * Threading: a context is used by one host thread at a time.  All calls are
+ * ordered on the context's HIP stream.  No call aborts or throws; every call
+ * returns a slag_status and, on failure, slag_last_error() describes it.
+ */
+#ifndef SLAG_H
+#define SLAG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SLAG_OK = 0,
+    SLAG_E_INVALID_ARG = 1,     /* bad pointer, size, id or parameter value */
+    SLAG_E_OUT_OF_MEMORY = 2,   /* device allocation failed */
+    SLAG_E_DEVICE = 3,          /* HIP runtime error; destroy the context */
+    SLAG_E_STATE = 4,           /* call out of order (e.g. lift before inputs) */
+    SLAG_E_CAPACITY = 5,        /* a size limit of the implementation was hit */
+    SLAG_E_NOT_SUPPORTED = 6
+} slag_status;
+
+typedef enum { SLAG_HOST = 0, SLAG_DEVICE = 1 } slag_mem;
+typedef enum { SLAG_F32 = 0, SLAG_BF16 = 1 } slag_dtype;
+
+/* One pinhole camera (OpenCV axes: x right, y down, z forward).
+ * Intrinsics K = [[fx,0,cx],[0,fy,cy],[0,0,1]]; R (row-major) and t map
+ * world points to camera space: X_cam = R X_world + t.  72 bytes. */
+typedef struct {
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    int32_t width, height;
+} slag_camera;
+
+enum {
+    SLAG_FLAG_PROFILE = 1,      /* record per-stage HIP events (slag_get_stats) */
+    SLAG_FLAG_COUNT = 2,        /* count blends and tests (slag_get_stats) */
+    SLAG_FLAG_KEEP_DEBUG = 4    /* keep the last view batch's tile lists and W rows */
+};
+
+typedef struct {
+    int32_t max_views_per_launch;   /* 0 = as many as fit (all views if possible) */
+    int32_t flags;                  /* SLAG_FLAG_* */
+    int64_t reserved[6];
+} slag_options;
+
+typedef struct {
+    int64_t n_views, n_batches;
+    int64_t n_visible_pairs;        /* (view, Gaussian) pairs with a non-empty box */
+    int64_t n_intersections;        /* (pair, 16x16 tile) entries */
+    int64_t n_part_slots;           /* per-(intersection, tile segment) partial sums */
+    int64_t n_weights;              /* non-zero (pair, tile, segment) weights */
+    int64_t n_contrib;              /* accepted blends, all pixels (SLAG_FLAG_COUNT) */
+    int64_t n_tests;                /* in-box tests before termination (SLAG_FLAG_COUNT) */
+    int64_t n_tile_tests;           /* tile-list tests executed (SLAG_FLAG_COUNT) */
+    double ms_total;                /* last lift, HIP events (SLAG_FLAG_PROFILE) */
+    double ms_stage[16];            /* per stage, see slag_stage_name() */
+    int32_t n_stages;
+    int32_t reserved;
+} slag_stats;
+
+typedef struct slag_ctx slag_ctx;
+
+/* Create a context on HIP device `device`.  `hip_stream` (a hipStream_t) is
+ * borrowed and must outlive the context; NULL makes the context create and
+ * own a stream.  `opt` may be NULL (defaults). */
+slag_status slag_create(int32_t device, void* hip_stream, const slag_options* opt,
+                        slag_ctx** out);
+void slag_destroy(slag_ctx* ctx);
+/* Context-owned message of the last failed call; valid until the next call. */
+const char* slag_last_error(const slag_ctx* ctx);
+
+/* The Gaussian set G = {G_1..G_N} (paper: the rasterizer's first argument).
+ * means_xyz[N][3], scales_xyz[N][3] (linear standard deviations, > 0),
+ * quats_wxyz[N][4] (rotation, any non-zero norm), opacity[N] in (0, 1].
+ * All FP32.  Pointers are `where`-resident and are copied before return.
+ * n = 0 is valid.  Non-finite values make the next lift fail with
+ * SLAG_E_INVALID_ARG. */
+slag_status slag_set_gaussians(slag_ctx* ctx, int64_t n, const float* means_xyz,
+                               const float* scales_xyz, const float* quats_wxyz,
+                               const float* opacity, slag_mem where);
+
+/* The training cameras (K_i, R_i, t_i) and image sizes; host memory, copied.
+ * Setting cameras discards previously set segment maps. */
+slag_status slag_set_cameras(slag_ctx* ctx, int32_t n_views, const slag_camera* cams);
+
+/* The masks M_j of view `view` as one segment id per pixel: ids[H][W]
+ * row-major int32, -1 = pixel in no mask, else 0 <= id < n_seg.  Copied.
+ * Ids out of range make the next lift fail with SLAG_E_INVALID_ARG. */
+slag_status slag_set_segments(slag_ctx* ctx, int32_t view, const int32_t* ids, int32_t n_seg,
+                              slag_mem where);
+
+/* The segment embeddings E_ij: table[sum_v n_seg_v][d], view-major (all
+ * segments of view 0, then view 1, ...), FP32 or BF16.  Copied. */
+slag_status slag_set_features(slag_ctx* ctx, int32_t d, slag_dtype dtype, const void* table,
+                              slag_mem where);
+
+/* Run the lift over every view.  Stream-ordered; returns once the work is
+ * enqueued (and after any host synchronisation needed for sizing). */
+slag_status slag_lift(slag_ctx* ctx);
+
+/* E_GAUSSIAN[N][d] (FP32) in input Gaussian order and, if `den` is not NULL,
+ * the weight sums den[N] (FP32).  Synchronises the stream.  Reports device-
+ * side validation failures of the last lift. */
+slag_status slag_get_embeddings(slag_ctx* ctx, float* out, float* den, slag_mem where);
+
+slag_status slag_get_stats(slag_ctx* ctx, slag_stats* stats);
+const char* slag_stage_name(int32_t stage);
+
+/* Debug exports for the last view batch (needs SLAG_FLAG_KEEP_DEBUG).
+ * Tile lists of view `view`: entries ordered by (tile, depth, Gaussian) with
+ * tile = ty * ceil(W/16) + tx; three host arrays of capacity `cap`.  *len
+ * receives the count (also when it exceeds cap, then nothing is written). */
+slag_status slag_debug_tile_lists(slag_ctx* ctx, int32_t view, uint32_t* tile,
+                                  uint32_t* depth_bits, uint32_t* gauss, int64_t cap,
+                                  int64_t* len);
+/* Masked weight sums of view `view` as (Gaussian, view-local segment, weight)
+ * entries, one per (Gaussian, tile, segment) with non-zero weight (a segment
+ * may repeat across the tiles of one Gaussian).  Host arrays. */
+slag_status slag_debug_weights(slag_ctx* ctx, int32_t view, uint32_t* gauss, uint32_t* seg,
+                               float* w, int64_t cap, int64_t* len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLAG_H */

@@ -1,0 +1,266 @@
+"""MI355X (gfx950) lift of per-view segment embeddings into per-Gaussian embeddings.
+
+Thin ctypes binding of ``include/slag.h``: the functions below carry the C
+names and only marshal arguments; every step of the lift runs in the HIP
+library ``lib/libslag.so``.  There is no fallback: if the library is missing
+or no GPU is present, calls raise.
+
+Arrays may be NumPy arrays (host memory) or torch tensors on a GPU (device
+memory, passed by pointer); PyTorch only provides device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libslag.so")
+
+SLAG_OK, SLAG_E_INVALID_ARG, SLAG_E_OUT_OF_MEMORY, SLAG_E_DEVICE, SLAG_E_STATE, \
+    SLAG_E_CAPACITY, SLAG_E_NOT_SUPPORTED = range(7)
+SLAG_HOST, SLAG_DEVICE = 0, 1
+SLAG_F32, SLAG_BF16 = 0, 1
+SLAG_FLAG_PROFILE, SLAG_FLAG_COUNT, SLAG_FLAG_KEEP_DEBUG = 1, 2, 4
+
+STATUS_NAMES = {0: "SLAG_OK", 1: "SLAG_E_INVALID_ARG", 2: "SLAG_E_OUT_OF_MEMORY",
+                3: "SLAG_E_DEVICE", 4: "SLAG_E_STATE", 5: "SLAG_E_CAPACITY",
+                6: "SLAG_E_NOT_SUPPORTED"}
+
+
+class slag_camera(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float),
+                ("cy", ctypes.c_float), ("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class slag_options(ctypes.Structure):
+    _fields_ = [("max_views_per_launch", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int64 * 6)]
+
+
+class slag_stats(ctypes.Structure):
+    _fields_ = [("n_views", ctypes.c_int64), ("n_batches", ctypes.c_int64),
+                ("n_visible_pairs", ctypes.c_int64), ("n_intersections", ctypes.c_int64),
+                ("n_part_slots", ctypes.c_int64), ("n_weights", ctypes.c_int64),
+                ("n_contrib", ctypes.c_int64), ("n_tests", ctypes.c_int64),
+                ("n_tile_tests", ctypes.c_int64), ("ms_total", ctypes.c_double),
+                ("ms_stage", ctypes.c_double * 16), ("n_stages", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+EXPORTS = ["slag_create", "slag_destroy", "slag_last_error", "slag_set_gaussians",
+           "slag_set_cameras", "slag_set_segments", "slag_set_features", "slag_lift",
+           "slag_get_embeddings", "slag_get_stats", "slag_stage_name", "slag_debug_tile_lists",
+           "slag_debug_weights"]
+
+_lib_handle = None
+
+
+def lib():
+    """Load libslag.so (raises if it has not been built)."""
+    global _lib_handle
+    if _lib_handle is not None:
+        return _lib_handle
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2505_08124_amd.build "
+                           "(there is no non-HIP fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.slag_create.argtypes = [I32, P, ctypes.POINTER(slag_options), ctypes.POINTER(P)]
+    L.slag_destroy.argtypes = [P]
+    L.slag_destroy.restype = None
+    L.slag_last_error.argtypes = [P]
+    L.slag_last_error.restype = ctypes.c_char_p
+    L.slag_set_gaussians.argtypes = [P, I64, P, P, P, P, I32]
+    L.slag_set_cameras.argtypes = [P, I32, P]
+    L.slag_set_segments.argtypes = [P, I32, P, I32, I32]
+    L.slag_set_features.argtypes = [P, I32, I32, P, I32]
+    L.slag_lift.argtypes = [P]
+    L.slag_get_embeddings.argtypes = [P, P, P, I32]
+    L.slag_get_stats.argtypes = [P, ctypes.POINTER(slag_stats)]
+    L.slag_stage_name.argtypes = [I32]
+    L.slag_stage_name.restype = ctypes.c_char_p
+    L.slag_debug_tile_lists.argtypes = [P, I32, P, P, P, I64, ctypes.POINTER(I64)]
+    L.slag_debug_weights.argtypes = [P, I32, P, P, P, I64, ctypes.POINTER(I64)]
+    for f in EXPORTS:
+        if f not in ("slag_destroy", "slag_last_error", "slag_stage_name"):
+            getattr(L, f).restype = I32
+    _lib_handle = L
+    return L
+
+
+class SlagError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(ctx, st):
+    if st != SLAG_OK:
+        m = lib().slag_last_error(ctx)
+        raise SlagError(st, m.decode() if m else "")
+
+
+def _ptr(a):
+    """(pointer, where) of a NumPy array or a GPU torch tensor; keeps no copy."""
+    if a is None:
+        return None, SLAG_HOST
+    if hasattr(a, "data_ptr") and hasattr(a, "is_cuda"):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(a.data_ptr()), (SLAG_DEVICE if a.is_cuda else SLAG_HOST)
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("array must be C-contiguous")
+    return a.ctypes.data_as(ctypes.c_void_p), SLAG_HOST
+
+
+# ---------------------------------------------------------------- C names
+
+def slag_create(device: int = 0, stream=None, max_views_per_launch: int = 0, flags: int = 0):
+    o = slag_options(max_views_per_launch, flags)
+    h = ctypes.c_void_p()
+    st = lib().slag_create(device, ctypes.c_void_p(stream) if stream else None, ctypes.byref(o),
+                           ctypes.byref(h))
+    if st != SLAG_OK:
+        raise SlagError(st, "slag_create failed")
+    return h
+
+
+def slag_destroy(ctx):
+    lib().slag_destroy(ctx)
+
+
+def slag_set_gaussians(ctx, means, scales, quats, opacity):
+    n = int(means.shape[0])
+    pm, w = _ptr(means)
+    ps, _ = _ptr(scales)
+    pq, _ = _ptr(quats)
+    po, _ = _ptr(opacity)
+    _check(ctx, lib().slag_set_gaussians(ctx, n, pm, ps, pq, po, w))
+
+
+def slag_set_cameras(ctx, cams: np.ndarray):
+    cams = np.ascontiguousarray(cams)
+    assert cams.dtype.itemsize == ctypes.sizeof(slag_camera)
+    _check(ctx, lib().slag_set_cameras(ctx, int(cams.shape[0]), cams.ctypes.data_as(ctypes.c_void_p)))
+
+
+def slag_set_segments(ctx, view: int, ids, n_seg: int):
+    p, w = _ptr(ids)
+    _check(ctx, lib().slag_set_segments(ctx, int(view), p, int(n_seg), w))
+
+
+def slag_set_features(ctx, table, dtype: int):
+    p, w = _ptr(table)
+    _check(ctx, lib().slag_set_features(ctx, int(table.shape[1]), int(dtype), p, w))
+
+
+def slag_lift(ctx):
+    _check(ctx, lib().slag_lift(ctx))
+
+
+def slag_get_embeddings(ctx, out, den=None):
+    p, w = _ptr(out)
+    pd, _ = _ptr(den)
+    _check(ctx, lib().slag_get_embeddings(ctx, p, pd, w))
+
+
+def slag_get_stats(ctx) -> dict:
+    s = slag_stats()
+    _check(ctx, lib().slag_get_stats(ctx, ctypes.byref(s)))
+    d = {f: getattr(s, f) for f, _ in slag_stats._fields_ if f not in ("ms_stage", "reserved")}
+    d["ms_stage"] = {lib().slag_stage_name(i).decode(): s.ms_stage[i] for i in range(s.n_stages)}
+    return d
+
+
+def slag_debug_tile_lists(ctx, view: int):
+    n = ctypes.c_int64(0)
+    _check(ctx, lib().slag_debug_tile_lists(ctx, view, None, None, None, 0, ctypes.byref(n)))
+    t = np.empty(n.value, np.uint32)
+    z = np.empty(n.value, np.uint32)
+    g = np.empty(n.value, np.uint32)
+    _check(ctx, lib().slag_debug_tile_lists(ctx, view, _ptr(t)[0], _ptr(z)[0], _ptr(g)[0], n.value,
+                                            ctypes.byref(n)))
+    return t, z, g
+
+
+def slag_debug_weights(ctx, view: int):
+    n = ctypes.c_int64(0)
+    _check(ctx, lib().slag_debug_weights(ctx, view, None, None, None, 0, ctypes.byref(n)))
+    g = np.empty(n.value, np.uint32)
+    s = np.empty(n.value, np.uint32)
+    w = np.empty(n.value, np.float32)
+    _check(ctx, lib().slag_debug_weights(ctx, view, _ptr(g)[0], _ptr(s)[0], _ptr(w)[0], n.value,
+                                         ctypes.byref(n)))
+    return g, s, w
+
+
+# ---------------------------------------------------------------- convenience
+
+class Lifter:
+    """One context on one device: upload a scene, lift, fetch."""
+
+    def __init__(self, device: int = 0, stream=None, max_views_per_launch: int = 0,
+                 flags: int = 0):
+        self.ctx = slag_create(device, stream, max_views_per_launch, flags)
+        self.n = 0
+        self.d = 0
+
+    def close(self):
+        if self.ctx:
+            slag_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_scene(self, scene, device_tensors: bool = False):
+        """Upload a synthetic.Scene (host arrays, or torch GPU tensors if asked)."""
+        if device_tensors:
+            import torch
+            dev = torch.device("cuda")
+            tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+            means, scales, quats, opac = (tt(scene.means), tt(scene.scales), tt(scene.quats),
+                                          tt(scene.opacity))
+            # the library copies on its own stream: make torch's copies land first
+            torch.cuda.synchronize()
+        else:
+            means, scales, quats, opac = scene.means, scene.scales, scene.quats, scene.opacity
+        slag_set_gaussians(self.ctx, means, scales, quats, opac)
+        slag_set_cameras(self.ctx, scene.cams)
+        for v, ids in enumerate(scene.ids):
+            slag_set_segments(self.ctx, v, np.ascontiguousarray(ids, np.int32), int(scene.nseg[v]))
+        dt = SLAG_BF16 if scene.feat_dtype == "bf16" else SLAG_F32
+        slag_set_features(self.ctx, np.ascontiguousarray(scene.feats), dt)
+        self.n = scene.n
+        self.d = scene.dim
+
+    def lift(self):
+        slag_lift(self.ctx)
+
+    def embeddings(self):
+        E = np.empty((self.n, self.d), np.float32)
+        den = np.empty(self.n, np.float32)
+        slag_get_embeddings(self.ctx, E, den)
+        return E, den
+
+    def stats(self) -> dict:
+        return slag_get_stats(self.ctx)
+
+    def tile_lists(self, view: int):
+        return slag_debug_tile_lists(self.ctx, view)
+
+    def weights(self, view: int):
+        return slag_debug_weights(self.ctx, view)

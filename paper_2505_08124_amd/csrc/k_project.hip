@@ -1,0 +1,340 @@
+// EWA projection of (view, Gaussian) pairs, culling, compaction of visible
+// pairs and their records (paper, Method: the rasterizer's projection of each
+// Gaussian to a screen mean mu'_k and covariance Sigma_k with K_i, R_i, t_i).
+//
+// Every value that feeds an integer decision (camera depth for culling and
+// ordering, the conservative pixel box for tile membership) follows one fixed
+// FP32 operation sequence: fmaf exactly where written, correctly rounded / and
+// sqrt, no other contraction (this file is built with -ffp-contract=off).
+// The same sequence written independently on the CPU reproduces the depth
+// keys and tile lists bit for bit.
+#include "slag_internal.h"
+
+namespace slag {
+
+namespace {
+
+constexpr float NEAR = 0.01f;
+constexpr float DIL = 0.3f;              // screen-space dilation (px^2)
+constexpr float RHO2 = 0x1.62a41p+3f;    // float nearest to 2 ln 255: q bound of alpha >= 1/255
+constexpr int PER_THREAD = 8;
+constexpr int CPB = 256 * PER_THREAD;    // Gaussians per block and view
+
+struct Proj {
+    float u, v, ca, cb, cc, z;
+    int x0, x1, y0, y1;
+};
+
+// World covariance Sigma3 = M M^T, M = Rq diag(s), from the normalised quaternion.
+__device__ __forceinline__ void world_cov(const float* s, const float* q, float* S)
+{
+    float nq = fmaf(q[0], q[0], fmaf(q[1], q[1], fmaf(q[2], q[2], q[3] * q[3])));
+    float rn = 1.0f / sqrtf(nq);
+    float w = q[0] * rn, x = q[1] * rn, y = q[2] * rn, z = q[3] * rn;
+    float r00 = 1.0f - 2.0f * fmaf(y, y, z * z);
+    float r01 = 2.0f * fmaf(x, y, -(w * z));
+    float r02 = 2.0f * fmaf(x, z, (w * y));
+    float r10 = 2.0f * fmaf(x, y, (w * z));
+    float r11 = 1.0f - 2.0f * fmaf(x, x, z * z);
+    float r12 = 2.0f * fmaf(y, z, -(w * x));
+    float r20 = 2.0f * fmaf(x, z, -(w * y));
+    float r21 = 2.0f * fmaf(y, z, (w * x));
+    float r22 = 1.0f - 2.0f * fmaf(x, x, y * y);
+    float m00 = r00 * s[0], m01 = r01 * s[1], m02 = r02 * s[2];
+    float m10 = r10 * s[0], m11 = r11 * s[1], m12 = r12 * s[2];
+    float m20 = r20 * s[0], m21 = r21 * s[1], m22 = r22 * s[2];
+    S[0] = fmaf(m00, m00, fmaf(m01, m01, m02 * m02));   // xx
+    S[1] = fmaf(m00, m10, fmaf(m01, m11, m02 * m12));   // xy
+    S[2] = fmaf(m00, m20, fmaf(m01, m21, m02 * m22));   // xz
+    S[3] = fmaf(m10, m10, fmaf(m11, m11, m12 * m12));   // yy
+    S[4] = fmaf(m10, m20, fmaf(m11, m21, m12 * m22));   // yz
+    S[5] = fmaf(m20, m20, fmaf(m21, m21, m22 * m22));   // zz
+}
+
+// Projection of one Gaussian into one view.  Returns false when culled (depth
+// at or in front of the near plane, degenerate covariance, empty pixel box).
+__device__ __forceinline__ bool project(const ViewDev& V, float mx, float my, float mz,
+                                        const float* S, Proj& P)
+{
+    const float* R = V.R;
+    float X = fmaf(R[0], mx, fmaf(R[1], my, fmaf(R[2], mz, V.t[0])));
+    float Y = fmaf(R[3], mx, fmaf(R[4], my, fmaf(R[5], mz, V.t[1])));
+    float Z = fmaf(R[6], mx, fmaf(R[7], my, fmaf(R[8], mz, V.t[2])));
+    P.z = Z;
+    if (!(Z > NEAR)) return false;
+    float iz = 1.0f / Z;
+    float txr = X * iz, tyr = Y * iz;
+    float tx = fminf(V.limx, fmaxf(-V.limx, txr));
+    float ty = fminf(V.limy, fmaxf(-V.limy, tyr));
+    float j00 = V.fx * iz, j02 = -(j00 * tx);
+    float j11 = V.fy * iz, j12 = -(j11 * ty);
+    // A = J R (2x3), Sigma2 = A Sigma3 A^T
+    float a0 = fmaf(j00, R[0], j02 * R[6]), a1 = fmaf(j00, R[1], j02 * R[7]),
+          a2 = fmaf(j00, R[2], j02 * R[8]);
+    float a3 = fmaf(j11, R[3], j12 * R[6]), a4 = fmaf(j11, R[4], j12 * R[7]),
+          a5 = fmaf(j11, R[5], j12 * R[8]);
+    const float sxx = S[0], sxy = S[1], sxz = S[2], syy = S[3], syz = S[4], szz = S[5];
+    float b0 = fmaf(a0, sxx, fmaf(a1, sxy, a2 * sxz));
+    float b1 = fmaf(a0, sxy, fmaf(a1, syy, a2 * syz));
+    float b2 = fmaf(a0, sxz, fmaf(a1, syz, a2 * szz));
+    float b3 = fmaf(a3, sxx, fmaf(a4, sxy, a5 * sxz));
+    float b4 = fmaf(a3, sxy, fmaf(a4, syy, a5 * syz));
+    float b5 = fmaf(a3, sxz, fmaf(a4, syz, a5 * szz));
+    float c00 = fmaf(b0, a0, fmaf(b1, a1, b2 * a2)) + DIL;
+    float c01 = fmaf(b0, a3, fmaf(b1, a4, b2 * a5));
+    float c11 = fmaf(b3, a3, fmaf(b4, a4, b5 * a5)) + DIL;
+    float det = fmaf(c00, c11, -(c01 * c01));
+    if (!(det > 0.0f)) return false;
+    float idet = 1.0f / det;
+    P.ca = c11 * idet;
+    P.cb = -(c01 * idet);
+    P.cc = c00 * idet;
+    float u = fmaf(V.fx, txr, V.cx);
+    float v = fmaf(V.fy, tyr, V.cy);
+    P.u = u;
+    P.v = v;
+    float ex = sqrtf(RHO2 * c00);
+    float ey = sqrtf(RHO2 * c11);
+    float x0 = ceilf(u - (ex + 1.5f)), x1 = floorf(u + (ex + 0.5f));
+    float y0 = ceilf(v - (ey + 1.5f)), y1 = floorf(v + (ey + 0.5f));
+    float wm1 = (float)(V.W - 1), hm1 = (float)(V.H - 1);
+    if (!(x0 <= wm1 && x1 >= 0.0f && y0 <= hm1 && y1 >= 0.0f)) return false;
+    P.x0 = (int)fmaxf(x0, 0.0f);
+    P.x1 = (int)fminf(x1, wm1);
+    P.y0 = (int)fmaxf(y0, 0.0f);
+    P.y1 = (int)fminf(y1, hm1);
+    return true;
+}
+
+__device__ __forceinline__ uint32_t tiles_of(const Proj& P)
+{
+    return (uint32_t)((P.x1 / TILE - P.x0 / TILE + 1) * (P.y1 / TILE - P.y0 / TILE + 1));
+}
+
+__device__ __forceinline__ void load_cov(const float* cov3, int64_t n, int64_t g, float* S)
+{
+#pragma unroll
+    for (int k = 0; k < 6; k++) S[k] = cov3[k * n + g];
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.
+__device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* lds, uint32_t& total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) lds[w] = x;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int i = 0; i < w; i++) off += lds[i];
+    total = lds[0] + lds[1] + lds[2] + lds[3];
+    __syncthreads();
+    return off + x - v;
+}
+
+__global__ __launch_bounds__(256) void k_prep_gauss(int64_t n, const float* __restrict__ means,
+                                                    const float* __restrict__ scales,
+                                                    const float* __restrict__ quats,
+                                                    const float* __restrict__ opac,
+                                                    float* __restrict__ cov3, uint32_t* err)
+{
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    float s[3] = {scales[3 * g], scales[3 * g + 1], scales[3 * g + 2]};
+    float q[4] = {quats[4 * g], quats[4 * g + 1], quats[4 * g + 2], quats[4 * g + 3]};
+    float o = opac[g];
+    bool ok = isfinite(means[3 * g]) && isfinite(means[3 * g + 1]) && isfinite(means[3 * g + 2]);
+    ok = ok && s[0] > 0.0f && s[1] > 0.0f && s[2] > 0.0f && isfinite(s[0]) && isfinite(s[1]) &&
+         isfinite(s[2]);
+    float nq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    ok = ok && nq > 0.0f && isfinite(nq) && o > 0.0f && o <= 1.0f;
+    if (!ok) {
+        atomicOr(err, 1u);
+        for (int k = 0; k < 6; k++) cov3[k * n + g] = 0.0f;
+        return;
+    }
+    float S[6];
+    world_cov(s, q, S);
+#pragma unroll
+    for (int k = 0; k < 6; k++) cov3[k * n + g] = S[k];
+}
+
+__global__ __launch_bounds__(256) void k_validate_ids(int64_t npix, const int32_t* __restrict__ ids,
+                                                      int32_t nseg, uint32_t* err)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    for (; i < npix; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t s = ids[i];
+        bad |= (s < -1) || (s >= nseg);
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(err, 2u);
+}
+
+// Pass 1: tile count of every (view, Gaussian) pair (0 = not visible), the
+// number of visible pairs per block, and the range of visible depth keys.
+__global__ __launch_bounds__(256) void k_count(int64_t n, const ViewDev* __restrict__ views,
+                                               const float* __restrict__ means,
+                                               const float* __restrict__ cov3,
+                                               uint32_t* __restrict__ tcnt,
+                                               uint32_t* __restrict__ blk_vis,
+                                               uint32_t* __restrict__ zrange)
+{
+    __shared__ uint32_t lds[4];
+    const int vl = blockIdx.y;
+    const ViewDev V = views[vl];
+    const int64_t g0 = (int64_t)blockIdx.x * CPB + (int64_t)threadIdx.x * PER_THREAD;
+    uint32_t nvis = 0, zmin = 0xFFFFFFFFu, zmax = 0;
+    uint32_t tc[PER_THREAD];
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; i++) {
+        const int64_t g = g0 + i;
+        tc[i] = 0;
+        if (g < n) {
+            float S[6];
+            load_cov(cov3, n, g, S);
+            Proj P;
+            if (project(V, means[3 * g], means[3 * g + 1], means[3 * g + 2], S, P)) {
+                tc[i] = tiles_of(P);
+                nvis++;
+                uint32_t zb = __float_as_uint(P.z);
+                zmin = min(zmin, zb);
+                zmax = max(zmax, zb);
+            }
+        }
+    }
+    uint32_t* out = tcnt + (int64_t)vl * n;
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; i++)
+        if (g0 + i < n) out[g0 + i] = tc[i];
+    uint32_t total;
+    block_exscan(nvis, lds, total);
+    // wave-level min/max then one atomic per wave
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        zmin = min(zmin, (uint32_t)__shfl_xor((int)zmin, d, 64));
+        zmax = max(zmax, (uint32_t)__shfl_xor((int)zmax, d, 64));
+    }
+    if ((threadIdx.x & 63) == 0 && zmax >= zmin) {
+        atomicMin(&zrange[0], zmin);
+        atomicMax(&zrange[1], zmax);
+    }
+    if (threadIdx.x == 0) blk_vis[(int64_t)vl * gridDim.x + blockIdx.x] = total;
+}
+
+// Pass 2: compact visible pairs in (view, Gaussian) order and write their
+// records, depth-sort keys, part sizes; tcnt is overwritten by the pair index
+// (NONE where not visible).
+__global__ __launch_bounds__(256) void k_emit_pairs(
+    int64_t n, const ViewDev* __restrict__ views, const float* __restrict__ means,
+    const float* __restrict__ cov3, const float* __restrict__ opac, uint32_t* __restrict__ tcnt,
+    const uint32_t* __restrict__ blk_off, float4* __restrict__ rec, uint32_t* __restrict__ pgauss,
+    uint16_t* __restrict__ pview, uint64_t* __restrict__ dkey, uint32_t* __restrict__ dval,
+    uint32_t* __restrict__ psz, uint32_t* __restrict__ pz, const uint32_t* __restrict__ sat,
+    uint32_t zmin, int zbits, unsigned long long* __restrict__ totals)
+{
+    __shared__ uint32_t lds[4];
+    const int vl = blockIdx.y;
+    const ViewDev V = views[vl];
+    const int64_t g0 = (int64_t)blockIdx.x * CPB + (int64_t)threadIdx.x * PER_THREAD;
+    uint32_t* io = tcnt + (int64_t)vl * n;
+    uint32_t vis = 0;
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; i++)
+        if (g0 + i < n && io[g0 + i] != 0) vis |= 1u << i;
+    const uint32_t nv = __popc(vis);
+    uint32_t total;
+    uint32_t pidx = blk_off[(int64_t)vl * gridDim.x + blockIdx.x] + block_exscan(nv, lds, total);
+    const int sw = V.ntx + 1;
+    const uint32_t* S = sat + V.sat_off;
+    unsigned long long n_isect = 0, n_part = 0;
+#pragma unroll 1
+    for (int i = 0; i < PER_THREAD; i++) {
+        const int64_t g = g0 + i;
+        if (g >= n) break;
+        if (!((vis >> i) & 1u)) {
+            io[g] = NONE;
+            continue;
+        }
+        float C[6];
+        load_cov(cov3, n, g, C);
+        Proj P;
+        project(V, means[3 * g], means[3 * g + 1], means[3 * g + 2], C, P);
+        rec[2 * (size_t)pidx] = make_float4(P.u, P.v, P.ca, P.cb);
+        rec[2 * (size_t)pidx + 1] =
+            make_float4(P.cc, opac[g], __uint_as_float((uint32_t)P.x0 | ((uint32_t)P.y0 << 16)),
+                        __uint_as_float((uint32_t)P.x1 | ((uint32_t)P.y1 << 16)));
+        pgauss[pidx] = (uint32_t)g;
+        pview[pidx] = (uint16_t)vl;
+        dkey[pidx] = ((uint64_t)vl << zbits) | (uint64_t)(__float_as_uint(P.z) - zmin);
+        dval[pidx] = pidx;
+        pz[pidx] = __float_as_uint(P.z);
+        // part slots of this pair: sum of the tile segment counts over its tile rect
+        const int tx0 = P.x0 / TILE, tx1 = P.x1 / TILE, ty0 = P.y0 / TILE, ty1 = P.y1 / TILE;
+        const uint32_t ps = S[(ty1 + 1) * sw + tx1 + 1] - S[ty0 * sw + tx1 + 1] -
+                            S[(ty1 + 1) * sw + tx0] + S[ty0 * sw + tx0];
+        psz[pidx] = ps;
+        n_isect += (unsigned long long)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+        n_part += ps;
+        io[g] = pidx;
+        pidx++;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        n_isect += __shfl_xor(n_isect, d, 64);
+        n_part += __shfl_xor(n_part, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && (n_isect | n_part)) {
+        atomicAdd(&totals[0], n_isect);
+        atomicAdd(&totals[1], n_part);
+    }
+}
+
+}  // namespace
+
+int count_blocks_per_view(int64_t n) { return (int)((n + CPB - 1) / CPB); }
+
+void launch_prep_gauss(int64_t n, const float* means, const float* scales, const float* quats,
+                       const float* opac, float* cov3, uint32_t* err, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_prep_gauss, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, means,
+                       scales, quats, opac, cov3, err);
+}
+
+void launch_validate_ids(int64_t npix, const int32_t* ids, int32_t nseg, uint32_t* err,
+                         hipStream_t st)
+{
+    if (npix <= 0) return;
+    int64_t blocks = (npix + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_validate_ids, dim3((unsigned)blocks), dim3(256), 0, st, npix, ids, nseg,
+                       err);
+}
+
+void launch_count(int nb, int64_t n, const ViewDev* views, const float* means, const float* cov3,
+                  uint32_t* tcnt, uint32_t* blk_vis, uint32_t* zrange, hipStream_t st)
+{
+    if (n <= 0 || nb <= 0) return;
+    hipLaunchKernelGGL(k_count, dim3((unsigned)count_blocks_per_view(n), (unsigned)nb), dim3(256),
+                       0, st, n, views, means, cov3, tcnt, blk_vis, zrange);
+}
+
+void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* means,
+                       const float* cov3, const float* opac, uint32_t* tcnt_pairof,
+                       const uint32_t* blk_off, float4* rec, uint32_t* pgauss, uint16_t* pview,
+                       uint64_t* dkey, uint32_t* dval, uint32_t* psz, uint32_t* pz,
+                       const uint32_t* sat, uint32_t zmin, int zbits,
+                       unsigned long long* totals, hipStream_t st)
+{
+    if (n <= 0 || nb <= 0) return;
+    hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)count_blocks_per_view(n), (unsigned)nb),
+                       dim3(256), 0, st, n, views, means, cov3, opac, tcnt_pairof, blk_off, rec,
+                       pgauss, pview, dkey, dval, psz, pz, sat, zmin, zbits, totals);
+}
+
+}  // namespace slag

@@ -1,0 +1,781 @@
+// Host side of the C interface: input upload and validation, the per-launch
+// view plan, workspace management, and the stream-ordered lift pipeline.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/slag.h"
+#include "slag_internal.h"
+
+using namespace slag;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    template <typename T>
+    T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+enum Stage {
+    ST_TILES = 0, ST_PROJECT, ST_DEPTH_SORT, ST_BIN, ST_TILE_SORT, ST_PART_PREP, ST_COMPOSITE,
+    ST_MERGE, ST_CONTRACT, ST_COUNT_
+};
+const char* kStageNames[ST_COUNT_] = {"tile_segments", "project", "depth_sort", "bin",
+                                      "tile_sort", "part_prep", "composite", "merge",
+                                      "contract"};
+
+struct Batch {
+    int v0 = 0, nb = 0;
+    uint32_t nbuckets = 0, nsat = 0;
+    DevBuf views, bucket_view;
+};
+
+struct TimedEvent {
+    int stage;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct slag_ctx {
+    int device = 0;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    slag_options opt{};
+    std::string err;
+
+    int64_t n = -1;
+    DevBuf means, scales, quats, opac, cov3;
+
+    int nviews = -1;
+    std::vector<slag_camera> cams;
+    std::vector<uint64_t> pix_off;
+    std::vector<int32_t> nseg;
+    std::vector<char> seg_set;
+    DevBuf ids;
+
+    int d = 0;
+    slag_dtype fdt = SLAG_F32;
+    DevBuf feats;
+    bool feats_set = false;
+    uint64_t feat_rows = 0;
+
+    DevBuf num, den;
+    bool have_out = false;
+
+    std::vector<Batch> plan;
+    int plan_views = -1;
+
+    // workspace
+    DevBuf ns_tile, segl, sat, tcnt, blk_vis, small, scan_ws, hist;
+    DevBuf rec, pgauss, pview, dkey, dkey_alt, dval, dval_alt, psz, pz, tcr, wlen;
+    DevBuf ikey, ikey_alt, ival, ival_alt, bstart, bend, part, wrow;
+    uint64_t* host_small = nullptr;   // pinned read-back area
+
+    // results of the last lift
+    slag_stats stats{};
+    std::vector<TimedEvent> events;
+    std::vector<hipEvent_t> free_events;
+    // last batch (debug exports)
+    int last_v0 = -1, last_nb = 0;
+    uint64_t last_npairs = 0, last_ni = 0;
+    const uint32_t* last_ikey = nullptr;
+    const uint32_t* last_ival = nullptr;
+};
+
+// small device area layout (uint64 words)
+enum { SM_TOT = 0, SM_ZRANGE = 2, SM_TOTALS = 4, SM_COUNTERS = 8, SM_NNZ = 12, SM_ERR = 14,
+       SM_WORDS = 16 };
+
+#define FAIL(ctx, code, msg)                 \
+    do {                                     \
+        (ctx)->err = (msg);                  \
+        return (code);                       \
+    } while (0)
+
+#define HC(ctx, expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);              \
+            return SLAG_E_DEVICE;                                                        \
+        }                                                                                \
+    } while (0)
+
+#define CK(expr)                          \
+    do {                                  \
+        slag_status s_ = (expr);          \
+        if (s_ != SLAG_OK) return s_;     \
+    } while (0)
+
+static slag_status ensure(slag_ctx* c, DevBuf& b, size_t bytes)
+{
+    if (bytes <= b.cap && b.p) return SLAG_OK;
+    if (b.p) {
+        hipStreamSynchronize(c->st);
+        hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t want = bytes + bytes / 8 + 256;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        c->err = "device allocation of " + std::to_string(want) + " bytes failed";
+        return SLAG_E_OUT_OF_MEMORY;
+    }
+    b.cap = want;
+    return SLAG_OK;
+}
+
+static void release(DevBuf& b)
+{
+    if (b.p) hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+static slag_status copy_in(slag_ctx* c, DevBuf& dst, const void* src, size_t bytes, slag_mem where)
+{
+    CK(ensure(c, dst, bytes));
+    if (bytes == 0) return SLAG_OK;
+    HC(c, hipMemcpyAsync(dst.p, src, bytes,
+                         where == SLAG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                         c->st));
+    return SLAG_OK;
+}
+
+static slag_status ensure_scan(slag_ctx* c, uint64_t len)
+{
+    return ensure(c, c->scan_ws, scan_workspace_bytes(std::max<uint64_t>(len, 1)));
+}
+
+static int bit_length(uint64_t x)
+{
+    int b = 0;
+    while (x) { b++; x >>= 1; }
+    return b;
+}
+
+// stage timing
+static slag_status stage_begin(slag_ctx* c, int stage, hipEvent_t* a)
+{
+    *a = nullptr;
+    if (!(c->opt.flags & SLAG_FLAG_PROFILE)) return SLAG_OK;
+    hipEvent_t e;
+    if (!c->free_events.empty()) { e = c->free_events.back(); c->free_events.pop_back(); }
+    else HC(c, hipEventCreate(&e));
+    HC(c, hipEventRecord(e, c->st));
+    *a = e;
+    (void)stage;
+    return SLAG_OK;
+}
+
+static slag_status stage_end(slag_ctx* c, int stage, hipEvent_t a)
+{
+    if (!a) return SLAG_OK;
+    hipEvent_t e;
+    if (!c->free_events.empty()) { e = c->free_events.back(); c->free_events.pop_back(); }
+    else HC(c, hipEventCreate(&e));
+    HC(c, hipEventRecord(e, c->st));
+    c->events.push_back({stage, a, e});
+    return SLAG_OK;
+}
+
+// ---------------------------------------------------------------- view plan
+
+static slag_status build_plan(slag_ctx* c)
+{
+    for (auto& b : c->plan) { release(b.views); release(b.bucket_view); }
+    c->plan.clear();
+    const int V = c->nviews;
+    int maxv = c->opt.max_views_per_launch > 0 ? c->opt.max_views_per_launch : V;
+    maxv = std::min(maxv, 65535);
+    // keep (view, Gaussian) indices and tile-list positions in 32 bits
+    const int64_t n = std::max<int64_t>(c->n, 1);
+    const int64_t cap_pairs = (int64_t)1 << 31;
+    maxv = (int)std::max<int64_t>(1, std::min<int64_t>(maxv, cap_pairs / n));
+    std::vector<uint64_t> seg_off(V + 1, 0);
+    for (int v = 0; v < V; v++) seg_off[v + 1] = seg_off[v] + (uint64_t)c->nseg[v];
+    for (int v0 = 0; v0 < V; v0 += maxv) {
+        Batch b;
+        b.v0 = v0;
+        b.nb = std::min(maxv, V - v0);
+        std::vector<ViewDev> vd(b.nb);
+        std::vector<uint32_t> bv;
+        uint32_t tb = 0, so = 0;
+        for (int i = 0; i < b.nb; i++) {
+            const slag_camera& cam = c->cams[v0 + i];
+            ViewDev& x = vd[i];
+            x.fx = cam.fx; x.fy = cam.fy; x.cx = cam.cx; x.cy = cam.cy;
+            std::memcpy(x.R, cam.R, sizeof(x.R));
+            std::memcpy(x.t, cam.t, sizeof(x.t));
+            x.W = cam.width; x.H = cam.height;
+            // guard clamp, same FP32 operations as the CPU decision path
+            volatile float hw = 0.5f * (float)cam.width, hh = 0.5f * (float)cam.height;
+            volatile float tanx = hw / cam.fx, tany = hh / cam.fy;
+            x.limx = 1.3f * tanx;
+            x.limy = 1.3f * tany;
+            x.ntx = (cam.width + TILE - 1) / TILE;
+            x.nty = (cam.height + TILE - 1) / TILE;
+            x.tile_base = tb;
+            x.sat_off = so;
+            x.pix_off = c->pix_off[v0 + i];
+            x.seg_off = (uint32_t)seg_off[v0 + i];
+            x.view = (uint32_t)(v0 + i);
+            const uint32_t nt = (uint32_t)(x.ntx * x.nty);
+            bv.insert(bv.end(), nt, (uint32_t)i);
+            tb += nt;
+            so += (uint32_t)((x.ntx + 1) * (x.nty + 1));
+        }
+        b.nbuckets = tb;
+        b.nsat = so;
+        CK(ensure(c, b.views, vd.size() * sizeof(ViewDev)));
+        CK(ensure(c, b.bucket_view, bv.size() * sizeof(uint32_t)));
+        HC(c, hipMemcpy(b.views.p, vd.data(), vd.size() * sizeof(ViewDev), hipMemcpyHostToDevice));
+        if (!bv.empty())
+            HC(c, hipMemcpy(b.bucket_view.p, bv.data(), bv.size() * sizeof(uint32_t),
+                            hipMemcpyHostToDevice));
+        c->plan.push_back(b);
+    }
+    c->plan_views = V;
+    return SLAG_OK;
+}
+
+// ------------------------------------------------------------------ the lift
+
+static slag_status read_small(slag_ctx* c, int off, int words)
+{
+    HC(c, hipMemcpyAsync(c->host_small + off, c->small.as<uint64_t>() + off, words * 8,
+                         hipMemcpyDeviceToHost, c->st));
+    HC(c, hipStreamSynchronize(c->st));
+    return SLAG_OK;
+}
+
+static slag_status lift_batch(slag_ctx* c, const Batch& B, bool first, bool last)
+{
+    hipStream_t st = c->st;
+    const int64_t n = c->n;
+    const int nb = B.nb;
+    const ViewDev* views = B.views.as<ViewDev>();
+    uint64_t* small = c->small.as<uint64_t>();
+    const bool count = (c->opt.flags & SLAG_FLAG_COUNT) != 0;
+    hipEvent_t ev;
+
+    // tile segment tables and their summed-area tables
+    CK(stage_begin(c, ST_TILES, &ev));
+    CK(ensure(c, c->ns_tile, (size_t)B.nbuckets * 4));
+    CK(ensure(c, c->segl, (size_t)B.nbuckets * TILE_PIX * 2));
+    CK(ensure(c, c->sat, (size_t)B.nsat * 4));
+    launch_tile_segs(B.nbuckets, B.bucket_view.as<uint32_t>(), views, c->ids.as<int32_t>(),
+                     c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(), st);
+    launch_sat(nb, views, c->ns_tile.as<uint32_t>(), c->sat.as<uint32_t>(), st);
+    CK(stage_end(c, ST_TILES, ev));
+
+    // projection: count, compact, records
+    CK(stage_begin(c, ST_PROJECT, &ev));
+    const uint64_t npq = (uint64_t)nb * (uint64_t)n;
+    const int cbv = count_blocks_per_view(n);
+    const uint64_t nblk = (uint64_t)cbv * nb;
+    CK(ensure(c, c->tcnt, npq * 4));
+    CK(ensure(c, c->blk_vis, nblk * 4 + 16));
+    CK(ensure_scan(c, nblk));
+    uint32_t* zr = reinterpret_cast<uint32_t*>(small + SM_ZRANGE);
+    launch_fill_u32(zr, 1, 0xFFFFFFFFu, st);
+    launch_fill_u32(zr + 1, 1, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(small + SM_TOTALS), 4, 0u, st);
+    launch_count(nb, n, views, c->means.as<float>(), c->cov3.as<float>(), c->tcnt.as<uint32_t>(),
+                 c->blk_vis.as<uint32_t>(), zr, st);
+    scan_u32(c->blk_vis.as<uint32_t>(), nblk, small + SM_TOT, c->scan_ws.p, st);
+    CK(read_small(c, 0, 4));
+    const uint64_t npairs = c->host_small[SM_TOT];
+    const uint32_t zmin = (uint32_t)(c->host_small[SM_ZRANGE] & 0xFFFFFFFFu);
+    const uint32_t zmax = (uint32_t)(c->host_small[SM_ZRANGE] >> 32);
+    if (npairs > 0xFFFFFFF0ull) FAIL(c, SLAG_E_CAPACITY, "too many visible pairs in one launch");
+    const int zbits = npairs ? bit_length((uint64_t)(zmax - zmin)) : 0;
+    const int vbits = bit_length((uint64_t)(nb > 0 ? nb - 1 : 0));
+    const uint64_t np = std::max<uint64_t>(npairs, 1);
+    CK(ensure(c, c->rec, np * 32));
+    CK(ensure(c, c->pgauss, np * 4));
+    CK(ensure(c, c->pview, np * 2));
+    CK(ensure(c, c->dkey, np * 8));
+    CK(ensure(c, c->dkey_alt, np * 8));
+    CK(ensure(c, c->dval, np * 4));
+    CK(ensure(c, c->dval_alt, np * 4));
+    CK(ensure(c, c->psz, np * 4 + 16));
+    CK(ensure(c, c->pz, np * 4));
+    CK(ensure(c, c->tcr, np * 4 + 16));
+    CK(ensure(c, c->wlen, np * 4));
+    launch_emit_pairs(nb, n, views, c->means.as<float>(), c->cov3.as<float>(), c->opac.as<float>(),
+                      c->tcnt.as<uint32_t>(), c->blk_vis.as<uint32_t>(), c->rec.as<float4>(),
+                      c->pgauss.as<uint32_t>(), c->pview.as<uint16_t>(), c->dkey.as<uint64_t>(),
+                      c->dval.as<uint32_t>(), c->psz.as<uint32_t>(), c->pz.as<uint32_t>(),
+                      c->sat.as<uint32_t>(), zmin, zbits,
+                      reinterpret_cast<unsigned long long*>(small + SM_TOTALS), st);
+    CK(stage_end(c, ST_PROJECT, ev));
+
+    uint64_t ni = 0, nparts = 0;
+    if (npairs) {
+        CK(read_small(c, SM_TOTALS, 2));
+        ni = c->host_small[SM_TOTALS];
+        nparts = c->host_small[SM_TOTALS + 1];
+        if (ni > 0xFFFFFFF0ull || nparts > 0xFFFFFFF0ull)
+            FAIL(c, SLAG_E_CAPACITY, "too many tile intersections in one launch; lower "
+                                     "max_views_per_launch");
+    }
+    c->stats.n_visible_pairs += (int64_t)npairs;
+    c->stats.n_intersections += (int64_t)ni;
+    c->stats.n_part_slots += (int64_t)nparts;
+
+    const uint32_t* order = nullptr;
+    const uint32_t* skey = nullptr;
+    const uint32_t* sval = nullptr;
+    if (npairs) {
+        // depth order of pairs within each view
+        CK(stage_begin(c, ST_DEPTH_SORT, &ev));
+        CK(ensure(c, c->hist, std::max(radix_hist_bytes(npairs), radix_hist_bytes(ni))));
+        CK(ensure_scan(c, std::max<uint64_t>(npairs, ni / 16 + 4096)));
+        bool alt = radix_sort_u64(c->dkey.as<uint64_t>(), c->dval.as<uint32_t>(),
+                                  c->dkey_alt.as<uint64_t>(), c->dval_alt.as<uint32_t>(), npairs,
+                                  zbits + vbits, c->hist.as<uint32_t>(), c->scan_ws.p, nullptr, st);
+        order = alt ? c->dval_alt.as<uint32_t>() : c->dval.as<uint32_t>();
+        CK(stage_end(c, ST_DEPTH_SORT, ev));
+
+        // (tile, pair) entries in depth order
+        CK(stage_begin(c, ST_BIN, &ev));
+        CK(ensure(c, c->ikey, ni * 4));
+        CK(ensure(c, c->ikey_alt, ni * 4));
+        CK(ensure(c, c->ival, ni * 4));
+        CK(ensure(c, c->ival_alt, ni * 4));
+        launch_rank_tiles(npairs, order, c->rec.as<float4>(), c->tcr.as<uint32_t>(), st);
+        scan_u32(c->tcr.as<uint32_t>(), npairs, nullptr, c->scan_ws.p, st);
+        launch_emit_isect(npairs, order, c->rec.as<float4>(), c->pview.as<uint16_t>(), views,
+                          c->tcr.as<uint32_t>(), c->ikey.as<uint32_t>(), c->ival.as<uint32_t>(),
+                          st);
+        CK(stage_end(c, ST_BIN, ev));
+
+        // stable sort by tile -> per-tile lists in (depth, Gaussian) order
+        CK(stage_begin(c, ST_TILE_SORT, &ev));
+        bool alt2 = radix_sort_u32(c->ikey.as<uint32_t>(), c->ival.as<uint32_t>(),
+                                   c->ikey_alt.as<uint32_t>(), c->ival_alt.as<uint32_t>(), ni,
+                                   bit_length(B.nbuckets > 0 ? B.nbuckets - 1 : 0),
+                                   c->hist.as<uint32_t>(), c->scan_ws.p, nullptr, st);
+        skey = alt2 ? c->ikey_alt.as<uint32_t>() : c->ikey.as<uint32_t>();
+        sval = alt2 ? c->ival_alt.as<uint32_t>() : c->ival.as<uint32_t>();
+        CK(ensure(c, c->bstart, (size_t)B.nbuckets * 4 + 4));
+        CK(ensure(c, c->bend, (size_t)B.nbuckets * 4 + 4));
+        launch_fill_u32(c->bstart.as<uint32_t>(), B.nbuckets, 0u, st);
+        launch_fill_u32(c->bend.as<uint32_t>(), B.nbuckets, 0u, st);
+        launch_bucket_ranges(ni, skey, c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(), st);
+        CK(stage_end(c, ST_TILE_SORT, ev));
+
+        // part slots: pair-major offsets, zeroed
+        CK(stage_begin(c, ST_PART_PREP, &ev));
+        scan_u32(c->psz.as<uint32_t>(), npairs, nullptr, c->scan_ws.p, st);
+        CK(ensure(c, c->part, std::max<uint64_t>(nparts, 1) * 4));
+        CK(ensure(c, c->wrow, std::max<uint64_t>(nparts, 1) * 8));
+        launch_fill_u32(c->part.as<uint32_t>(), nparts, 0u, st);
+        CK(stage_end(c, ST_PART_PREP, ev));
+
+        CK(stage_begin(c, ST_COMPOSITE, &ev));
+        launch_composite(count, B.nbuckets, B.bucket_view.as<uint32_t>(), views,
+                         c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(), sval,
+                         c->rec.as<float4>(), c->psz.as<uint32_t>(), c->sat.as<uint32_t>(),
+                         c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(), c->ids.as<int32_t>(),
+                         c->part.as<float>(),
+                         reinterpret_cast<unsigned long long*>(small + SM_COUNTERS), st);
+        CK(stage_end(c, ST_COMPOSITE, ev));
+
+        CK(stage_begin(c, ST_MERGE, &ev));
+        launch_merge(npairs, c->rec.as<float4>(), c->pview.as<uint16_t>(), views,
+                     c->psz.as<uint32_t>(), c->part.as<float>(), c->ns_tile.as<uint32_t>(),
+                     c->segl.as<uint16_t>(), c->wrow.as<uint2>(), c->wlen.as<uint32_t>(),
+                     reinterpret_cast<unsigned long long*>(small + SM_NNZ), st);
+        CK(stage_end(c, ST_MERGE, ev));
+    }
+
+    CK(stage_begin(c, ST_CONTRACT, &ev));
+    launch_contract(n, nb, c->d, c->fdt == SLAG_BF16, c->tcnt.as<uint32_t>(),
+                    c->wlen.as<uint32_t>(), c->psz.as<uint32_t>(), c->wrow.as<uint2>(),
+                    c->feats.p, c->num.as<float>(), c->den.as<float>(), first, last, st);
+    CK(stage_end(c, ST_CONTRACT, ev));
+
+    c->last_v0 = B.v0;
+    c->last_nb = nb;
+    c->last_npairs = npairs;
+    c->last_ni = ni;
+    c->last_ikey = skey;
+    c->last_ival = sval;
+    return SLAG_OK;
+}
+
+// ------------------------------------------------------------------ C API
+
+extern "C" {
+
+slag_status slag_create(int32_t device, void* hip_stream, const slag_options* opt, slag_ctx** out)
+{
+    if (!out) return SLAG_E_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return SLAG_E_INVALID_ARG;
+    if (hipSetDevice(device) != hipSuccess) return SLAG_E_DEVICE;
+    slag_ctx* c = new (std::nothrow) slag_ctx();
+    if (!c) return SLAG_E_OUT_OF_MEMORY;
+    c->device = device;
+    if (opt) c->opt = *opt;
+    if (hip_stream) {
+        c->st = reinterpret_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return SLAG_E_DEVICE;
+        }
+        c->own_stream = true;
+    }
+    if (ensure(c, c->small, SM_WORDS * 8) != SLAG_OK ||
+        hipHostMalloc((void**)&c->host_small, SM_WORDS * 8, hipHostMallocDefault) != hipSuccess) {
+        slag_destroy(c);
+        return SLAG_E_OUT_OF_MEMORY;
+    }
+    std::memset(c->host_small, 0, SM_WORDS * 8);
+    if (hipMemset(c->small.p, 0, SM_WORDS * 8) != hipSuccess) {
+        slag_destroy(c);
+        return SLAG_E_DEVICE;
+    }
+    *out = c;
+    return SLAG_OK;
+}
+
+void slag_destroy(slag_ctx* c)
+{
+    if (!c) return;
+    hipSetDevice(c->device);
+    if (c->st) hipStreamSynchronize(c->st);
+    DevBuf* bufs[] = {&c->means, &c->scales, &c->quats, &c->opac, &c->cov3, &c->ids, &c->feats,
+                      &c->num, &c->den, &c->ns_tile, &c->segl, &c->sat, &c->tcnt, &c->blk_vis,
+                      &c->small, &c->scan_ws, &c->hist, &c->rec, &c->pgauss, &c->pview, &c->dkey,
+                      &c->dkey_alt, &c->dval, &c->dval_alt, &c->psz, &c->pz, &c->tcr, &c->wlen,
+                      &c->ikey, &c->ikey_alt, &c->ival, &c->ival_alt, &c->bstart, &c->bend,
+                      &c->part, &c->wrow};
+    for (DevBuf* b : bufs) release(*b);
+    for (auto& b : c->plan) { release(b.views); release(b.bucket_view); }
+    for (auto& e : c->events) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
+    for (auto e : c->free_events) hipEventDestroy(e);
+    if (c->host_small) hipHostFree(c->host_small);
+    if (c->own_stream && c->st) hipStreamDestroy(c->st);
+    delete c;
+}
+
+const char* slag_last_error(const slag_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+const char* slag_stage_name(int32_t s)
+{
+    return (s >= 0 && s < ST_COUNT_) ? kStageNames[s] : "";
+}
+
+slag_status slag_set_gaussians(slag_ctx* c, int64_t n, const float* means, const float* scales,
+                               const float* quats, const float* opacity, slag_mem where)
+{
+    if (!c) return SLAG_E_INVALID_ARG;
+    c->err.clear();
+    if (n < 0 || (n > 0 && (!means || !scales || !quats || !opacity)))
+        FAIL(c, SLAG_E_INVALID_ARG, "null pointer or negative Gaussian count");
+    if (n >= ((int64_t)1 << 31)) FAIL(c, SLAG_E_CAPACITY, "at most 2^31 - 1 Gaussians");
+    if (where != SLAG_HOST && where != SLAG_DEVICE) FAIL(c, SLAG_E_INVALID_ARG, "bad memory kind");
+    HC(c, hipSetDevice(c->device));
+    CK(copy_in(c, c->means, means, (size_t)n * 12, where));
+    CK(copy_in(c, c->scales, scales, (size_t)n * 12, where));
+    CK(copy_in(c, c->quats, quats, (size_t)n * 16, where));
+    CK(copy_in(c, c->opac, opacity, (size_t)n * 4, where));
+    CK(ensure(c, c->cov3, (size_t)std::max<int64_t>(n, 1) * 24));
+    uint32_t* err = reinterpret_cast<uint32_t*>(c->small.as<uint64_t>() + SM_ERR);
+    launch_fill_u32(err, 1, 0u, c->st);
+    launch_prep_gauss(n, c->means.as<float>(), c->scales.as<float>(), c->quats.as<float>(),
+                      c->opac.as<float>(), c->cov3.as<float>(), err, c->st);
+    CK(read_small(c, SM_ERR, 1));
+    c->n = -1;
+    c->have_out = false;
+    if (c->host_small[SM_ERR] & 1)
+        FAIL(c, SLAG_E_INVALID_ARG, "Gaussian parameters must be finite, scales > 0, quaternions "
+                                    "non-zero and opacity in (0, 1]");
+    c->n = n;
+    c->plan_views = -1;   // launch sizes depend on n
+    return SLAG_OK;
+}
+
+slag_status slag_set_cameras(slag_ctx* c, int32_t n_views, const slag_camera* cams)
+{
+    if (!c) return SLAG_E_INVALID_ARG;
+    c->err.clear();
+    if (n_views < 0 || (n_views > 0 && !cams)) FAIL(c, SLAG_E_INVALID_ARG, "bad camera array");
+    uint64_t tot = 0;
+    std::vector<uint64_t> off(n_views + 1, 0);
+    for (int v = 0; v < n_views; v++) {
+        const slag_camera& k = cams[v];
+        if (k.width <= 0 || k.height <= 0 || k.width > 65535 || k.height > 65535)
+            FAIL(c, SLAG_E_INVALID_ARG, "camera " + std::to_string(v) + ": image size out of range");
+        bool fin = std::isfinite(k.fx) && std::isfinite(k.fy) && std::isfinite(k.cx) &&
+                   std::isfinite(k.cy) && k.fx > 0 && k.fy > 0;
+        for (int i = 0; i < 9; i++) fin = fin && std::isfinite(k.R[i]);
+        for (int i = 0; i < 3; i++) fin = fin && std::isfinite(k.t[i]);
+        if (!fin) FAIL(c, SLAG_E_INVALID_ARG, "camera " + std::to_string(v) + ": non-finite or "
+                                              "non-positive intrinsics/extrinsics");
+        off[v] = tot;
+        tot += (uint64_t)k.width * (uint64_t)k.height;
+    }
+    off[n_views] = tot;
+    HC(c, hipSetDevice(c->device));
+    CK(ensure(c, c->ids, std::max<uint64_t>(tot, 1) * 4));
+    c->cams.assign(cams, cams + n_views);
+    c->pix_off = off;
+    c->nviews = n_views;
+    c->nseg.assign(n_views, 0);
+    c->seg_set.assign(n_views, 0);
+    c->feats_set = false;
+    c->have_out = false;
+    c->plan_views = -1;
+    return SLAG_OK;
+}
+
+slag_status slag_set_segments(slag_ctx* c, int32_t view, const int32_t* ids, int32_t n_seg,
+                              slag_mem where)
+{
+    if (!c) return SLAG_E_INVALID_ARG;
+    c->err.clear();
+    if (c->nviews < 0) FAIL(c, SLAG_E_STATE, "set cameras before segments");
+    if (view < 0 || view >= c->nviews) FAIL(c, SLAG_E_INVALID_ARG, "view index out of range");
+    if (!ids || n_seg < 0) FAIL(c, SLAG_E_INVALID_ARG, "null ids or negative segment count");
+    if (n_seg > 65535) FAIL(c, SLAG_E_NOT_SUPPORTED, "at most 65535 segments per view");
+    HC(c, hipSetDevice(c->device));
+    const uint64_t npix = c->pix_off[view + 1] - c->pix_off[view];
+    int32_t* dst = c->ids.as<int32_t>() + c->pix_off[view];
+    HC(c, hipMemcpyAsync(dst, ids, npix * 4,
+                         where == SLAG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                         c->st));
+    uint32_t* err = reinterpret_cast<uint32_t*>(c->small.as<uint64_t>() + SM_ERR);
+    launch_fill_u32(err, 1, 0u, c->st);
+    launch_validate_ids((int64_t)npix, dst, n_seg, err, c->st);
+    CK(read_small(c, SM_ERR, 1));
+    if (c->host_small[SM_ERR] & 2) {
+        c->seg_set[view] = 0;
+        FAIL(c, SLAG_E_INVALID_ARG, "segment id out of range [-1, n_seg) in view " +
+                                        std::to_string(view));
+    }
+    if (c->nseg[view] != n_seg) c->feats_set = false;
+    c->nseg[view] = n_seg;
+    c->seg_set[view] = 1;
+    c->have_out = false;
+    c->plan_views = -1;
+    return SLAG_OK;
+}
+
+slag_status slag_set_features(slag_ctx* c, int32_t d, slag_dtype dtype, const void* table,
+                              slag_mem where)
+{
+    if (!c) return SLAG_E_INVALID_ARG;
+    c->err.clear();
+    if (c->nviews < 0) FAIL(c, SLAG_E_STATE, "set cameras and segments before features");
+    for (int v = 0; v < c->nviews; v++)
+        if (!c->seg_set[v]) FAIL(c, SLAG_E_STATE, "segments of view " + std::to_string(v) + " not set");
+    if (d <= 0 || (dtype != SLAG_F32 && dtype != SLAG_BF16))
+        FAIL(c, SLAG_E_INVALID_ARG, "bad feature dimension or dtype");
+    if (!contract_supported(d))
+        FAIL(c, SLAG_E_NOT_SUPPORTED, "feature dimension must be 64, 128, 256, 512, 768 or 1024");
+    uint64_t rows = 0;
+    for (int v = 0; v < c->nviews; v++) rows += (uint64_t)c->nseg[v];
+    if (rows > 0 && !table) FAIL(c, SLAG_E_INVALID_ARG, "null feature table");
+    HC(c, hipSetDevice(c->device));
+    const size_t es = dtype == SLAG_BF16 ? 2 : 4;
+    CK(copy_in(c, c->feats, table, rows * (size_t)d * es, where));
+    CK(ensure(c, c->feats, std::max<size_t>(rows * (size_t)d * es, 16)));
+    c->d = d;
+    c->fdt = dtype;
+    c->feat_rows = rows;
+    c->feats_set = true;
+    c->have_out = false;
+    return SLAG_OK;
+}
+
+slag_status slag_lift(slag_ctx* c)
+{
+    if (!c) return SLAG_E_INVALID_ARG;
+    c->err.clear();
+    if (c->n < 0) FAIL(c, SLAG_E_STATE, "Gaussians not set");
+    if (c->nviews < 0) FAIL(c, SLAG_E_STATE, "cameras not set");
+    for (int v = 0; v < c->nviews; v++)
+        if (!c->seg_set[v]) FAIL(c, SLAG_E_STATE, "segments of view " + std::to_string(v) + " not set");
+    if (!c->feats_set) FAIL(c, SLAG_E_STATE, "features not set (or segment counts changed)");
+    HC(c, hipSetDevice(c->device));
+    c->have_out = false;
+    for (auto& e : c->events) { c->free_events.push_back(e.a); c->free_events.push_back(e.b); }
+    c->events.clear();
+    std::memset(&c->stats, 0, sizeof(c->stats));
+    c->last_v0 = -1;
+    const int64_t n = c->n;
+    CK(ensure(c, c->num, (size_t)std::max<int64_t>(n, 1) * c->d * 4));
+    CK(ensure(c, c->den, (size_t)std::max<int64_t>(n, 1) * 4));
+    if (c->plan_views != c->nviews) CK(build_plan(c));
+    uint64_t* small = c->small.as<uint64_t>();
+    launch_fill_u32(reinterpret_cast<uint32_t*>(small + SM_COUNTERS), 12, 0u, c->st);
+    if (n == 0) {
+        c->have_out = true;
+        return SLAG_OK;
+    }
+    if (c->plan.empty()) {
+        launch_fill_u32(c->num.as<uint32_t>(), (uint64_t)n * c->d, 0u, c->st);
+        launch_fill_u32(c->den.as<uint32_t>(), (uint64_t)n, 0u, c->st);
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->opt.flags & SLAG_FLAG_PROFILE) {
+        CK(stage_begin(c, -1, &e0));
+    }
+    for (size_t i = 0; i < c->plan.size(); i++)
+        CK(lift_batch(c, c->plan[i], i == 0, i + 1 == c->plan.size()));
+    if (e0) {
+        if (!c->free_events.empty()) { e1 = c->free_events.back(); c->free_events.pop_back(); }
+        else HC(c, hipEventCreate(&e1));
+        HC(c, hipEventRecord(e1, c->st));
+        c->events.push_back({-1, e0, e1});
+    }
+    c->stats.n_views = c->nviews;
+    c->stats.n_batches = (int64_t)c->plan.size();
+    c->have_out = true;
+    return SLAG_OK;
+}
+
+slag_status slag_get_embeddings(slag_ctx* c, float* out, float* den, slag_mem where)
+{
+    if (!c) return SLAG_E_INVALID_ARG;
+    c->err.clear();
+    if (!c->have_out) FAIL(c, SLAG_E_STATE, "no lift result");
+    HC(c, hipSetDevice(c->device));
+    const hipMemcpyKind k = where == SLAG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const size_t n = (size_t)c->n;
+    if (out && n) HC(c, hipMemcpyAsync(out, c->num.p, n * c->d * 4, k, c->st));
+    if (den && n) HC(c, hipMemcpyAsync(den, c->den.p, n * 4, k, c->st));
+    HC(c, hipStreamSynchronize(c->st));
+    return SLAG_OK;
+}
+
+slag_status slag_get_stats(slag_ctx* c, slag_stats* s)
+{
+    if (!c || !s) return SLAG_E_INVALID_ARG;
+    c->err.clear();
+    HC(c, hipSetDevice(c->device));
+    HC(c, hipStreamSynchronize(c->st));
+    CK(read_small(c, SM_COUNTERS, 6));
+    c->stats.n_contrib = (int64_t)c->host_small[SM_COUNTERS];
+    c->stats.n_tests = (int64_t)c->host_small[SM_COUNTERS + 1];
+    c->stats.n_tile_tests = (int64_t)c->host_small[SM_COUNTERS + 2];
+    c->stats.n_weights = (int64_t)c->host_small[SM_NNZ];
+    for (int i = 0; i < 16; i++) c->stats.ms_stage[i] = 0.0;
+    c->stats.ms_total = 0.0;
+    for (auto& e : c->events) {
+        float ms = 0.0f;
+        HC(c, hipEventElapsedTime(&ms, e.a, e.b));
+        if (e.stage < 0) c->stats.ms_total += ms;
+        else c->stats.ms_stage[e.stage] += ms;
+    }
+    c->stats.n_stages = ST_COUNT_;
+    *s = c->stats;
+    return SLAG_OK;
+}
+
+slag_status slag_debug_tile_lists(slag_ctx* c, int32_t view, uint32_t* tile, uint32_t* depth_bits,
+                                  uint32_t* gauss, int64_t cap, int64_t* len)
+{
+    if (!c || !len) return SLAG_E_INVALID_ARG;
+    c->err.clear();
+    if (!(c->opt.flags & SLAG_FLAG_KEEP_DEBUG) || c->last_v0 < 0)
+        FAIL(c, SLAG_E_STATE, "debug exports need SLAG_FLAG_KEEP_DEBUG and a lift");
+    if (view < c->last_v0 || view >= c->last_v0 + c->last_nb)
+        FAIL(c, SLAG_E_STATE, "view not in the last launch");
+    HC(c, hipSetDevice(c->device));
+    HC(c, hipStreamSynchronize(c->st));
+    const uint64_t ni = c->last_ni, np = c->last_npairs;
+    *len = 0;
+    if (!ni) return SLAG_OK;
+    std::vector<uint32_t> k(ni), v(ni), pg(np), pz(np);
+    HC(c, hipMemcpy(k.data(), c->last_ikey, ni * 4, hipMemcpyDeviceToHost));
+    HC(c, hipMemcpy(v.data(), c->last_ival, ni * 4, hipMemcpyDeviceToHost));
+    HC(c, hipMemcpy(pg.data(), c->pgauss.p, np * 4, hipMemcpyDeviceToHost));
+    HC(c, hipMemcpy(pz.data(), c->pz.p, np * 4, hipMemcpyDeviceToHost));
+    const Batch* B = nullptr;
+    for (auto& b : c->plan)
+        if (b.v0 == c->last_v0) B = &b;
+    if (!B) FAIL(c, SLAG_E_STATE, "launch plan changed since the lift");
+    // tile base of the view within the launch
+    uint32_t tb = 0;
+    for (int i = c->last_v0; i < view; i++)
+        tb += (uint32_t)(((c->cams[i].width + TILE - 1) / TILE) * ((c->cams[i].height + TILE - 1) / TILE));
+    const uint32_t nt = (uint32_t)(((c->cams[view].width + TILE - 1) / TILE) *
+                                   ((c->cams[view].height + TILE - 1) / TILE));
+    int64_t m = 0;
+    for (uint64_t i = 0; i < ni; i++)
+        if (k[i] >= tb && k[i] < tb + nt) m++;
+    *len = m;
+    if (m > cap) return SLAG_OK;
+    int64_t o = 0;
+    for (uint64_t i = 0; i < ni; i++)
+        if (k[i] >= tb && k[i] < tb + nt) {
+            if (tile) tile[o] = k[i] - tb;
+            if (depth_bits) depth_bits[o] = pz[v[i]];
+            if (gauss) gauss[o] = pg[v[i]];
+            o++;
+        }
+    return SLAG_OK;
+}
+
+slag_status slag_debug_weights(slag_ctx* c, int32_t view, uint32_t* gauss, uint32_t* seg, float* w,
+                               int64_t cap, int64_t* len)
+{
+    if (!c || !len) return SLAG_E_INVALID_ARG;
+    c->err.clear();
+    if (!(c->opt.flags & SLAG_FLAG_KEEP_DEBUG) || c->last_v0 < 0)
+        FAIL(c, SLAG_E_STATE, "debug exports need SLAG_FLAG_KEEP_DEBUG and a lift");
+    if (view < c->last_v0 || view >= c->last_v0 + c->last_nb)
+        FAIL(c, SLAG_E_STATE, "view not in the last launch");
+    HC(c, hipSetDevice(c->device));
+    HC(c, hipStreamSynchronize(c->st));
+    const uint64_t np = c->last_npairs;
+    *len = 0;
+    if (!np) return SLAG_OK;
+    std::vector<uint32_t> pg(np), wl(np), pb(np);
+    std::vector<uint16_t> pv(np);
+    HC(c, hipMemcpy(pg.data(), c->pgauss.p, np * 4, hipMemcpyDeviceToHost));
+    HC(c, hipMemcpy(wl.data(), c->wlen.p, np * 4, hipMemcpyDeviceToHost));
+    HC(c, hipMemcpy(pb.data(), c->psz.p, np * 4, hipMemcpyDeviceToHost));
+    HC(c, hipMemcpy(pv.data(), c->pview.p, np * 2, hipMemcpyDeviceToHost));
+    const uint16_t vl = (uint16_t)(view - c->last_v0);
+    uint64_t seg_off = 0;
+    for (int i = 0; i < view; i++) seg_off += (uint64_t)c->nseg[i];
+    int64_t m = 0;
+    for (uint64_t p = 0; p < np; p++)
+        if (pv[p] == vl) m += wl[p];
+    *len = m;
+    if (m > cap) return SLAG_OK;
+    int64_t o = 0;
+    std::vector<uint2> row;
+    for (uint64_t p = 0; p < np; p++) {
+        if (pv[p] != vl || !wl[p]) continue;
+        row.resize(wl[p]);
+        HC(c, hipMemcpy(row.data(), c->wrow.as<uint2>() + pb[p], wl[p] * 8, hipMemcpyDeviceToHost));
+        for (uint32_t i = 0; i < wl[p]; i++) {
+            if (gauss) gauss[o] = pg[p];
+            if (seg) seg[o] = (uint32_t)(row[i].x - seg_off);
+            if (w) { float f; std::memcpy(&f, &row[i].y, 4); w[o] = f; }
+            o++;
+        }
+    }
+    return SLAG_OK;
+}
+
+}  // extern "C"

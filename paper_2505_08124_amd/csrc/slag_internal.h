@@ -1,0 +1,92 @@
+// Internal declarations shared by the host library and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace slag {
+
+constexpr int TILE = 16;                 // tile edge in pixels (16 x 16 = 4 waves of 8 x 8)
+constexpr int TILE_PIX = TILE * TILE;
+constexpr int NS_CAP = 8;                // tile segments accumulated per compositing pass
+constexpr int BATCH = 64;                // tile-list entries staged in LDS per step
+constexpr uint32_t NONE = 0xFFFFFFFFu;
+
+// One view of the current launch, with everything its kernels need.
+struct ViewDev {
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    int32_t W, H;
+    float limx, limy;        // guard clamp of x/z, y/z (1.3 x half-FOV tangent, FP32)
+    int32_t ntx, nty;        // tiles per row / column
+    uint32_t tile_base;      // first bucket (tile) of this view in the launch
+    uint32_t sat_off;        // first entry of this view's summed-area table
+    uint64_t pix_off;        // first pixel of this view in the id array
+    uint32_t seg_off;        // first feature row of this view
+    uint32_t view;           // global view index
+};
+
+// Pair record (one visible (view, Gaussian) pair), two float4:
+//   r0 = (u, v, conic_xx, conic_xy)   screen mean and inverse covariance
+//   r1 = (conic_yy, opacity, x0 | y0 << 16, x1 | y1 << 16)  pixel box (inclusive)
+
+// ---- launchers (each enqueues on `st`) ----
+void launch_prep_gauss(int64_t n, const float* means, const float* scales, const float* quats,
+                       const float* opac, float* cov3, uint32_t* err, hipStream_t st);
+void launch_validate_ids(int64_t npix, const int32_t* ids, int32_t nseg, uint32_t* err,
+                         hipStream_t st);
+void launch_count(int nb, int64_t n, const ViewDev* views, const float* means, const float* cov3,
+                  uint32_t* tcnt, uint32_t* blk_vis, uint32_t* zrange, hipStream_t st);
+int count_blocks_per_view(int64_t n);
+void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* means,
+                       const float* cov3, const float* opac, uint32_t* tcnt_pairof,
+                       const uint32_t* blk_off, float4* rec, uint32_t* pgauss, uint16_t* pview,
+                       uint64_t* dkey, uint32_t* dval, uint32_t* psz, uint32_t* pz,
+                       const uint32_t* sat, uint32_t zmin, int zbits,
+                       unsigned long long* totals, hipStream_t st);
+
+// scans: exclusive prefix sum in place; the 64-bit total goes to *total_dev
+size_t scan_workspace_bytes(uint64_t n);
+void scan_u32(uint32_t* data, uint64_t n, uint64_t* total_dev, void* ws, hipStream_t st);
+
+// stable LSD radix sort of (key, value) by bits [0, nbits); returns true when
+// the result ended in the *_alt buffers
+size_t radix_hist_bytes(uint64_t n);
+bool radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                    uint64_t n, int nbits, uint32_t* hist, void* scan_ws, uint64_t* tot,
+                    hipStream_t st);
+bool radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                    uint64_t n, int nbits, uint32_t* hist, void* scan_ws, uint64_t* tot,
+                    hipStream_t st);
+
+void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const float4* rec, uint32_t* tcr,
+                       hipStream_t st);
+void launch_emit_isect(uint64_t npairs, const uint32_t* order, const float4* rec,
+                       const uint16_t* pview, const ViewDev* views, const uint32_t* ioff,
+                       uint32_t* ikey, uint32_t* ival, hipStream_t st);
+void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
+void launch_bucket_ranges(uint64_t ni, const uint32_t* ikey, uint32_t* bstart, uint32_t* bend,
+                          hipStream_t st);
+
+void launch_tile_segs(uint32_t nbuckets, const uint32_t* bucket_view, const ViewDev* views,
+                      const int32_t* ids, uint32_t* ns_tile, uint16_t* segl, hipStream_t st);
+void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t* sat,
+                hipStream_t st);
+void launch_composite(bool count, uint32_t nbuckets, const uint32_t* bucket_view,
+                      const ViewDev* views, const uint32_t* bstart, const uint32_t* bend,
+                      const uint32_t* ival, const float4* rec, const uint32_t* part_base,
+                      const uint32_t* sat, const uint32_t* ns_tile, const uint16_t* segl,
+                      const int32_t* ids, float* part, unsigned long long* counters,
+                      hipStream_t st);
+void launch_merge(uint64_t npairs, const float4* rec, const uint16_t* pview, const ViewDev* views,
+                  const uint32_t* part_base, const float* part, const uint32_t* ns_tile,
+                  const uint16_t* segl, uint2* wrow, uint32_t* wlen,
+                  unsigned long long* nnz, hipStream_t st);
+
+bool contract_supported(int d);
+void launch_contract(int64_t n, int nb, int d, bool bf16, const uint32_t* pair_of,
+                     const uint32_t* wlen, const uint32_t* part_base, const uint2* wrow,
+                     const void* feats, float* num, float* den, bool first, bool last,
+                     hipStream_t st);
+
+}  // namespace slag

@@ -1,0 +1,48 @@
+"""The C-ABI library loads and exports every entry point its header declares
+(no GPU needed); argument errors are reported without a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "slag.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(slag_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2505_08124_amd as slag
+    L = slag.lib()
+    names = _declared()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(slag.EXPORTS)
+
+
+def test_null_arguments_are_rejected():
+    import paper_2505_08124_amd as slag
+    L = slag.lib()
+    assert L.slag_create(0, None, None, None) == slag.SLAG_E_INVALID_ARG
+    assert L.slag_lift(None) == slag.SLAG_E_INVALID_ARG
+    assert L.slag_get_stats(None, None) == slag.SLAG_E_INVALID_ARG
+    assert L.slag_stage_name(6) == b"composite"
+    assert L.slag_stage_name(99) == b""
+
+
+def test_oracle_library_loads():
+    import oracle
+    assert oracle.max_threads() >= 1
+
+
+def test_camera_layout_matches_generator():
+    import paper_2505_08124_amd as slag
+    from synthetic import camera_dtype
+    assert ctypes.sizeof(slag.slag_camera) == camera_dtype.itemsize == 72
+    for name, _ in slag.slag_camera._fields_:
+        assert getattr(slag.slag_camera, name).offset == camera_dtype.fields[name][1]

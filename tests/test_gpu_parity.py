@@ -1,0 +1,231 @@
+"""GPU parity: the HIP lift (through the C ABI) against the FP64 CPU oracle.
+
+Bars (see the oracle's header for the decision-margin mass U):
+  * tile lists (tile, FP32 depth bits, Gaussian) bit-exact with the oracle's
+    FP32 decision path;
+  * per-view weights W_v[g, s]: |W_gpu - W_orc| <= 2e-4 W_orc + U + 1e-9, and
+    exact membership of every (view, Gaussian, segment) triple with U = 0;
+  * embeddings: cosine >= 0.9999 for every Gaussian with non-zero weight
+    (Gaussians whose weight is more than 0.5% decision-margin mass are
+    reported, not compared), zero rows exactly where the oracle's are zero.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import make_scene
+
+pytestmark = pytest.mark.gpu
+
+RTOL_W = 2e-4
+COS_MIN = 0.9999
+
+
+def _say(*a):
+    print("[gpu-parity]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _lifter(scene, flags=0, max_views=0):
+    import paper_2505_08124_amd as slag
+    L = slag.Lifter(0, None, max_views, flags | slag.SLAG_FLAG_KEEP_DEBUG)
+    L.set_scene(scene)
+    return L
+
+
+def _gpu_triples(L, v):
+    g, s, w = L.weights(v)
+    key = g.astype(np.int64) * (1 << 32) + s.astype(np.int64)
+    uk, inv = np.unique(key, return_inverse=True)
+    ws = np.zeros(uk.size)
+    np.add.at(ws, inv, w.astype(np.float64))
+    return uk, ws
+
+
+def check_view_weights(L, scene, v, ores):
+    """Compare one view's W with the oracle's triples."""
+    gk, gw = _gpu_triples(L, v)
+    ok = ores.g.astype(np.int64) * (1 << 32) + ores.s.astype(np.int64)
+    allk = np.union1d(gk, ok)
+    Wg = np.zeros(allk.size)
+    Wo = np.zeros(allk.size)
+    U = np.zeros(allk.size)
+    Wg[np.searchsorted(allk, gk)] = gw
+    io = np.searchsorted(allk, ok)
+    Wo[io] = ores.w
+    U[io] = ores.u
+    err = np.abs(Wg - Wo)
+    bad = err > RTOL_W * Wo + U + 1e-9
+    assert not bad.any(), (
+        f"view {v}: {bad.sum()} weight mismatches, e.g. key {allk[bad][:5]} gpu {Wg[bad][:5]} "
+        f"oracle {Wo[bad][:5]} U {U[bad][:5]}")
+    strict = U == 0
+    assert np.array_equal(Wg[strict] > 0, Wo[strict] > 0)
+    return int(((Wg > 0) != (Wo > 0)).sum()), int((U > 0).sum())
+
+
+def check_embeddings(E, den, ref):
+    nz = ref.den > 0
+    assert np.array_equal(den > 0, nz) or np.all(ref.U[(den > 0) != nz] > 0)
+    # the denominator is a sum of W entries: same bar as the weights
+    err = np.abs(den[nz].astype(np.float64) - ref.den[nz])
+    assert np.all(err <= RTOL_W * ref.den[nz] + ref.U[nz] + 1e-9), (err / ref.den[nz]).max()
+    margin = ref.U[nz] / ref.den[nz]
+    Eg = E[nz].astype(np.float64)
+    Eo = ref.E[nz]
+    cos = np.sum(Eg * Eo, 1) / (np.linalg.norm(Eg, axis=1) * np.linalg.norm(Eo, axis=1) + 1e-300)
+    comp = margin <= 5e-3
+    assert cos[comp].min() >= COS_MIN, (cos[comp].min(), np.argmin(cos[comp]))
+    assert np.all(E[~nz] == 0)
+    return float(cos[comp].min()), float(np.abs(Eg - Eo).max())
+
+
+def check_tile_lists(L, scene, v):
+    t, z, g = L.tile_lists(v)
+    rt, rz, rg = oracle.sorted_keys(scene, v, 16, 16)
+    assert t.size == rt.size, (t.size, rt.size)
+    assert np.array_equal(t.astype(np.int64), rt)
+    assert np.array_equal(z, rz)
+    assert np.array_equal(g.astype(np.int64), rg.astype(np.int64))
+
+
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def lift_2k(scene_2k):
+    import paper_2505_08124_amd as slag
+    _say("plain_fp32_2k: lift (count mode)")
+    L = _lifter(scene_2k, flags=slag.SLAG_FLAG_COUNT)
+    L.lift()
+    E, den = L.embeddings()
+    return L, E, den
+
+
+def test_tile_lists_bit_exact_2k(scene_2k, lift_2k):
+    L, _, _ = lift_2k
+    for v in range(scene_2k.n_views):
+        _say("tile lists view", v)
+        check_tile_lists(L, scene_2k, v)
+
+
+def test_weights_match_oracle_2k(scene_2k, oracle_2k, lift_2k):
+    L, _, _ = lift_2k
+    for v in range(scene_2k.n_views):
+        _say("weights view", v)
+        flips, nunc = check_view_weights(L, scene_2k, v, oracle_2k.views[v])
+        _say(f"  membership flips {flips}, triples with margin mass {nunc}")
+
+
+def test_embeddings_match_oracle_2k(oracle_2k, lift_2k):
+    _, E, den = lift_2k
+    cmin, emax = check_embeddings(E, den, oracle_2k)
+    _say(f"min cosine {cmin:.9f}, max abs err {emax:.3g}")
+
+
+def test_counts_match_oracle_2k(oracle_2k, lift_2k):
+    L, _, _ = lift_2k
+    st = L.stats()
+    unc = sum(r.n_uncertain for r in oracle_2k.views)
+    assert abs(st["n_contrib"] - oracle_2k.n_contrib) <= unc
+    assert abs(st["n_tests"] - oracle_2k.n_tests) <= unc + st["n_contrib"] // 1000
+    assert st["n_tile_tests"] >= st["n_tests"]
+
+
+def test_repeat_and_batching_bitwise(scene_2k, lift_2k):
+    """Two lifts are bitwise equal (no float atomics); one view per launch
+    gives the same bits (views are summed in the same order)."""
+    L, E, den = lift_2k
+    L.lift()
+    E2, den2 = L.embeddings()
+    assert np.array_equal(E, E2) and np.array_equal(den, den2)
+    _say("one view per launch")
+    L1 = _lifter(scene_2k, max_views=1)
+    L1.lift()
+    E3, den3 = L1.embeddings()
+    assert np.array_equal(E, E3) and np.array_equal(den, den3)
+
+
+def test_permutation_equivariance_gpu(scene_2k, lift_2k):
+    _, E, den = lift_2k
+    perm = np.random.default_rng(1).permutation(scene_2k.n)
+    sc = dataclasses.replace(scene_2k, means=scene_2k.means[perm], scales=scene_2k.scales[perm],
+                             quats=scene_2k.quats[perm], opacity=scene_2k.opacity[perm])
+    L = _lifter(sc)
+    L.lift()
+    Ep, denp = L.embeddings()
+    inv = np.argsort(perm)
+    assert np.array_equal(Ep[inv], E) and np.array_equal(denp[inv], den)
+
+
+def _ragged_scene():
+    """Ragged image sizes (partial tiles), background, a view with per-pixel
+    noise ids (many segments per tile: several compositing passes)."""
+    sc = make_scene("uneven_1m", n=6000,
+                    views=dict(n=3, res_list=[(100, 75), (61, 47), (130, 90)]),
+                    segments=dict(lo=5, hi=30))
+    ids = [i.copy() for i in sc.ids]
+    rng = np.random.default_rng(4)
+    ids[0][rng.random(ids[0].shape) < 0.15] = -1
+    k = int(sc.nseg[1])
+    ids[1] = rng.integers(-1, k, size=ids[1].shape).astype(np.int32)
+    return dataclasses.replace(sc, ids=ids)
+
+
+def test_ragged_views_and_many_segments():
+    sc = _ragged_scene()
+    _say("ragged: oracle")
+    ref = oracle.lift(sc)
+    _say("ragged: gpu")
+    L = _lifter(sc)
+    L.lift()
+    E, den = L.embeddings()
+    for v in range(sc.n_views):
+        check_tile_lists(L, sc, v)
+        check_view_weights(L, sc, v, ref.views[v])
+    check_embeddings(E, den, ref)
+
+
+def test_uneven_resolutions_one_launch():
+    sc = make_scene("uneven_1m", n=40000, views=dict(n=6))
+    _say("uneven: oracle")
+    ref = oracle.lift(sc)
+    _say("uneven: gpu")
+    L = _lifter(sc)
+    L.lift()
+    E, den = L.embeddings()
+    for v in range(sc.n_views):
+        check_tile_lists(L, sc, v)
+        check_view_weights(L, sc, v, ref.views[v])
+    check_embeddings(E, den, ref)
+
+
+def test_empty_and_degenerate():
+    import paper_2505_08124_amd as slag
+    sc = make_scene("plain_fp32_2k", n=50)
+    # no Gaussians
+    e = dataclasses.replace(sc, means=sc.means[:0], scales=sc.scales[:0], quats=sc.quats[:0],
+                            opacity=sc.opacity[:0])
+    L = _lifter(e)
+    L.lift()
+    E, den = L.embeddings()
+    assert E.shape == (0, sc.dim)
+    # every pixel background: all weights zero, E = 0
+    bg = dataclasses.replace(sc, ids=[np.full_like(i, -1) for i in sc.ids])
+    L = _lifter(bg)
+    L.lift()
+    E, den = L.embeddings()
+    assert np.all(E == 0) and np.all(den == 0)
+    # everything behind the cameras
+    far = dataclasses.replace(sc, means=(sc.means * 0 + np.float32([0, 0, 100])).astype(np.float32))
+    L = _lifter(far)
+    L.lift()
+    E, den = L.embeddings()
+    ref = oracle.lift(far)
+    assert np.array_equal(den > 0, ref.den > 0)
+    # invalid input is rejected at upload
+    with pytest.raises(slag.SlagError):
+        L2 = slag.Lifter(0)
+        L2.set_scene(dataclasses.replace(sc, ids=[i + 100 for i in sc.ids]))
