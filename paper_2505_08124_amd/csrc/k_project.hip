@@ -177,6 +177,8 @@ __global__ __launch_bounds__(256) void k_validate_ids(int64_t npix, const int32_
 
 // Pass 1: tile count of every (view, Gaussian) pair (0 = not visible), the
 // number of visible pairs per block, and the range of visible depth keys.
+// Thread t of a block handles Gaussians base + i * 256 + t, i < PER_THREAD
+// (coalesced loads and stores).
 __global__ __launch_bounds__(256) void k_count(int64_t n, const ViewDev* __restrict__ views,
                                                const float* __restrict__ means,
                                                const float* __restrict__ cov3,
@@ -187,33 +189,28 @@ __global__ __launch_bounds__(256) void k_count(int64_t n, const ViewDev* __restr
     __shared__ uint32_t lds[4];
     const int vl = blockIdx.y;
     const ViewDev V = views[vl];
-    const int64_t g0 = (int64_t)blockIdx.x * CPB + (int64_t)threadIdx.x * PER_THREAD;
-    uint32_t nvis = 0, zmin = 0xFFFFFFFFu, zmax = 0;
-    uint32_t tc[PER_THREAD];
-#pragma unroll
-    for (int i = 0; i < PER_THREAD; i++) {
-        const int64_t g = g0 + i;
-        tc[i] = 0;
-        if (g < n) {
-            float S[6];
-            load_cov(cov3, n, g, S);
-            Proj P;
-            if (project(V, means[3 * g], means[3 * g + 1], means[3 * g + 2], S, P)) {
-                tc[i] = tiles_of(P);
-                nvis++;
-                uint32_t zb = __float_as_uint(P.z);
-                zmin = min(zmin, zb);
-                zmax = max(zmax, zb);
-            }
-        }
-    }
+    const int64_t g0 = (int64_t)blockIdx.x * CPB + threadIdx.x;
     uint32_t* out = tcnt + (int64_t)vl * n;
-#pragma unroll
-    for (int i = 0; i < PER_THREAD; i++)
-        if (g0 + i < n) out[g0 + i] = tc[i];
+    uint32_t nvis = 0, zmin = 0xFFFFFFFFu, zmax = 0;
+#pragma unroll 2
+    for (int i = 0; i < PER_THREAD; i++) {
+        const int64_t g = g0 + (int64_t)i * 256;
+        if (g >= n) break;
+        float S[6];
+        load_cov(cov3, n, g, S);
+        Proj P;
+        uint32_t tc = 0;
+        if (project(V, means[3 * g], means[3 * g + 1], means[3 * g + 2], S, P)) {
+            tc = tiles_of(P);
+            nvis++;
+            const uint32_t zb = __float_as_uint(P.z);
+            zmin = min(zmin, zb);
+            zmax = max(zmax, zb);
+        }
+        out[g] = tc;
+    }
     uint32_t total;
     block_exscan(nvis, lds, total);
-    // wave-level min/max then one atomic per wave
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         zmin = min(zmin, (uint32_t)__shfl_xor((int)zmin, d, 64));
@@ -228,36 +225,50 @@ __global__ __launch_bounds__(256) void k_count(int64_t n, const ViewDev* __restr
 
 // Pass 2: compact visible pairs in (view, Gaussian) order and write their
 // records, depth-sort keys, part sizes; tcnt is overwritten by the pair index
-// (NONE where not visible).
+// (NONE where not visible).  Same striped layout as pass 1.
 __global__ __launch_bounds__(256) void k_emit_pairs(
     int64_t n, const ViewDev* __restrict__ views, const float* __restrict__ means,
     const float* __restrict__ cov3, const float* __restrict__ opac, uint32_t* __restrict__ tcnt,
     const uint32_t* __restrict__ blk_off, float4* __restrict__ rec, uint32_t* __restrict__ pgauss,
     uint16_t* __restrict__ pview, uint64_t* __restrict__ dkey, uint32_t* __restrict__ dval,
     uint32_t* __restrict__ psz, uint32_t* __restrict__ pz, const uint32_t* __restrict__ sat,
-    uint32_t zmin, int zbits, unsigned long long* __restrict__ totals)
+    uint32_t zmin, int zbits, unsigned long long* __restrict__ totals,
+    const uint32_t* __restrict__ rank, uint32_t* __restrict__ pair_of_m)
 {
-    __shared__ uint32_t lds[4];
+    __shared__ uint32_t cnt[PER_THREAD][4];
+    __shared__ uint64_t msk[4][PER_THREAD];
     const int vl = blockIdx.y;
     const ViewDev V = views[vl];
-    const int64_t g0 = (int64_t)blockIdx.x * CPB + (int64_t)threadIdx.x * PER_THREAD;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t g0 = (int64_t)blockIdx.x * CPB + threadIdx.x;
     uint32_t* io = tcnt + (int64_t)vl * n;
-    uint32_t vis = 0;
 #pragma unroll
-    for (int i = 0; i < PER_THREAD; i++)
-        if (g0 + i < n && io[g0 + i] != 0) vis |= 1u << i;
-    const uint32_t nv = __popc(vis);
-    uint32_t total;
-    uint32_t pidx = blk_off[(int64_t)vl * gridDim.x + blockIdx.x] + block_exscan(nv, lds, total);
+    for (int i = 0; i < PER_THREAD; i++) {
+        const int64_t g = g0 + (int64_t)i * 256;
+        const uint64_t m = __ballot(g < n && io[g] != 0);
+        if (lane == 0) {
+            cnt[i][wv] = (uint32_t)__popcll(m);
+            msk[wv][i] = m;
+        }
+    }
+    __syncthreads();
+    uint32_t run = blk_off[(int64_t)vl * gridDim.x + blockIdx.x];
     const int sw = V.ntx + 1;
     const uint32_t* S = sat + V.sat_off;
     unsigned long long n_isect = 0, n_part = 0;
 #pragma unroll 1
     for (int i = 0; i < PER_THREAD; i++) {
-        const int64_t g = g0 + i;
-        if (g >= n) break;
-        if (!((vis >> i) & 1u)) {
+        const int64_t g = g0 + (int64_t)i * 256;
+        const uint64_t m = msk[wv][i];
+        uint32_t before = 0;
+        for (int w = 0; w < wv; w++) before += cnt[i][w];
+        const uint32_t pidx = run + before + (uint32_t)__popcll(m & lt);
+        run += cnt[i][0] + cnt[i][1] + cnt[i][2] + cnt[i][3];
+        if (g >= n) continue;
+        if (!((m >> lane) & 1ull)) {
             io[g] = NONE;
+            pair_of_m[(int64_t)vl * n + rank[g]] = NONE;
             continue;
         }
         float C[6];
@@ -281,17 +292,83 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         n_isect += (unsigned long long)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
         n_part += ps;
         io[g] = pidx;
-        pidx++;
+        pair_of_m[(int64_t)vl * n + rank[g]] = pidx;
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         n_isect += __shfl_xor(n_isect, d, 64);
         n_part += __shfl_xor(n_part, d, 64);
     }
-    if ((threadIdx.x & 63) == 0 && (n_isect | n_part)) {
+    if (lane == 0 && (n_isect | n_part)) {
         atomicAdd(&totals[0], n_isect);
         atomicAdd(&totals[1], n_part);
     }
+}
+
+// ---- Morton order of the Gaussians (block structure of the contraction) ----
+
+// Order-preserving integer image of a float (for min/max with integer atomics).
+__device__ __forceinline__ uint32_t ord_of(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__global__ __launch_bounds__(256) void k_bbox(int64_t n, const float* __restrict__ means,
+                                              uint32_t* __restrict__ box6)
+{
+    uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (int64_t)gridDim.x * 256)
+        for (int k = 0; k < 3; k++) {
+            const uint32_t o = ord_of(means[3 * g + k]);
+            lo[k] = min(lo[k], o);
+            hi[k] = max(hi[k], o);
+        }
+    for (int k = 0; k < 3; k++) {
+        for (int d = 32; d >= 1; d >>= 1) {
+            lo[k] = min(lo[k], (uint32_t)__shfl_xor((int)lo[k], d, 64));
+            hi[k] = max(hi[k], (uint32_t)__shfl_xor((int)hi[k], d, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicMin(&box6[k], lo[k]);
+            atomicMax(&box6[3 + k], hi[k]);
+        }
+    }
+}
+
+__device__ __forceinline__ uint64_t spread3(uint64_t x)   // 21 bits -> every third bit
+{
+    x &= 0x1FFFFFull;
+    x = (x | (x << 32)) & 0x1F00000000FFFFull;
+    x = (x | (x << 16)) & 0x1F0000FF0000FFull;
+    x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+    x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__global__ __launch_bounds__(256) void k_morton(int64_t n, const float* __restrict__ means,
+                                                const float* __restrict__ lo_scale,
+                                                uint64_t* __restrict__ keys,
+                                                uint32_t* __restrict__ vals)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= n) return;
+    uint64_t c[3];
+    for (int k = 0; k < 3; k++) {
+        float f = (means[3 * g + k] - lo_scale[k]) * lo_scale[3 + k];
+        f = fminf(fmaxf(f, 0.0f), 2097151.0f);
+        c[k] = (uint64_t)f;
+    }
+    keys[g] = spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
+    vals[g] = (uint32_t)g;
+}
+
+__global__ __launch_bounds__(256) void k_invert(int64_t n, const uint32_t* __restrict__ perm,
+                                                uint32_t* __restrict__ rank)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q < n) rank[perm[q]] = (uint32_t)q;
 }
 
 }  // namespace
@@ -329,12 +406,37 @@ void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* mea
                        const uint32_t* blk_off, float4* rec, uint32_t* pgauss, uint16_t* pview,
                        uint64_t* dkey, uint32_t* dval, uint32_t* psz, uint32_t* pz,
                        const uint32_t* sat, uint32_t zmin, int zbits,
-                       unsigned long long* totals, hipStream_t st)
+                       unsigned long long* totals, const uint32_t* rank, uint32_t* pair_of_m,
+                       hipStream_t st)
 {
     if (n <= 0 || nb <= 0) return;
     hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)count_blocks_per_view(n), (unsigned)nb),
                        dim3(256), 0, st, n, views, means, cov3, opac, tcnt_pairof, blk_off, rec,
-                       pgauss, pview, dkey, dval, psz, pz, sat, zmin, zbits, totals);
+                       pgauss, pview, dkey, dval, psz, pz, sat, zmin, zbits, totals, rank,
+                       pair_of_m);
+}
+
+void launch_bbox(int64_t n, const float* means, uint32_t* box6, hipStream_t st)
+{
+    if (n <= 0) return;
+    int64_t g = (n + 255) / 256;
+    if (g > 2048) g = 2048;
+    hipLaunchKernelGGL(k_bbox, dim3((unsigned)g), dim3(256), 0, st, n, means, box6);
+}
+
+void launch_morton(int64_t n, const float* means, const float* lo_scale, uint64_t* keys,
+                   uint32_t* vals, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_morton, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, means,
+                       lo_scale, keys, vals);
+}
+
+void launch_invert(int64_t n, const uint32_t* perm, uint32_t* rank, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_invert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, perm,
+                       rank);
 }
 
 }  // namespace slag

@@ -7,11 +7,12 @@
 // pixel block.  The tile's depth-ordered list is staged through LDS BATCH
 // entries at a time.  For every entry each lane blends its pixel
 // (alpha = min(0.99, o exp(-q/2)), skip below 1/255, stop before T < 1e-4,
-// w = alpha T) and the wave reduces w over the lanes of each segment with DPP
-// row reductions -- no global atomics, no float atomics, so the sums are
-// deterministic.  The four waves' sums are added in fixed order and written to
-// the entry's part slots: one float per (pair, tile, tile segment), laid out
-// pair-major so the merge reads each pair's slots contiguously.
+// w = alpha T) and each 16-lane row reduces w over the lanes of each segment
+// with DPP -- no global atomics, no float atomics, so the sums are
+// deterministic.  The sixteen row sums are added in fixed order and written to
+// the entry's part slots: one (tile-local segment id, weight) slot per (pair,
+// tile, tile segment), laid out pair-major so each pair's slots are
+// contiguous for the contraction.
 #include "slag_internal.h"
 
 namespace slag {
@@ -31,28 +32,21 @@ __device__ __forceinline__ void box_of(const float4& r1, int& x0, int& x1, int& 
     x1 = (int)(b & 0xFFFFu); y1 = (int)(b >> 16);
 }
 
-__device__ __forceinline__ float dpp_f(float v, int ctrl);
-
 template <int CTRL>
 __device__ __forceinline__ float dpp_add(float v)
 {
     return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
-__device__ __forceinline__ float readlane_f(float v, int l)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-
-// Sum over the 64 lanes; the result is valid in lane 0.  Call with all lanes
-// active.  Fixed association order: deterministic.
-__device__ __forceinline__ float wave_sum(float v)
+// Sum over each 16-lane row of the wave; every lane receives its row's total.
+// Call with all lanes active.  Fixed association order: deterministic.
+__device__ __forceinline__ float row_sum(float v)
 {
     v = dpp_add<0xB1>(v);    // quad_perm [1,0,3,2]
     v = dpp_add<0x4E>(v);    // quad_perm [2,3,0,1]
     v = dpp_add<0x124>(v);   // row_ror:4
-    v = dpp_add<0x128>(v);   // row_ror:8  -> every lane holds its row total
-    return ((v + readlane_f(v, 16)) + readlane_f(v, 32)) + readlane_f(v, 48);
+    v = dpp_add<0x128>(v);   // row_ror:8
+    return v;
 }
 
 // Rectangle sum over a view's summed-area table (inclusive tile bounds).
@@ -129,21 +123,113 @@ __global__ __launch_bounds__(256) void k_sat(const ViewDev* __restrict__ views,
         for (int y = 1; y <= V.nty; y++) S[y * sw + x] += S[(y - 1) * sw + x];
 }
 
+// Sum over the 64 lanes of v; valid in every lane.  Fixed order.
+__device__ __forceinline__ float wave_total(float v)
+{
+    v = row_sum(v);
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    return ((r0 + r1) + r2) + r3;
+}
+
+enum { MODE_NONE = 0, MODE_UNIFORM = 1, MODE_MIXED = 2 };
+
+// Blend this wave's compacted entries of one batch into its 64 pixels.
+template <int MODE, bool COUNTING>
+__device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const float4* __restrict__ w1,
+                                            const int* __restrict__ wj, int cnt, float fpx, float fpy,
+                                            int px, int py, int slot, int uslot, float& T, bool& done,
+                                            float (*acc)[NS_CAP], int lane,
+                                            unsigned long long& n_acc, unsigned long long& n_box,
+                                            unsigned long long& n_tile)
+{
+    const bool slot_ok = slot >= 0;
+    for (int jj = 0; jj < cnt; jj++) {
+        const float4 p0 = w0[jj];
+        const float4 p1 = w1[jj];
+        const float dx = fpx - p0.x, dy = fpy - p0.y;
+        float e = fmaf(dx, fmaf(p0.z, dx, p0.w * dy), p1.x * dy * dy);
+        e = fminf(e, 0.0f);
+        const float alpha = fminf(AMAX, p1.y * __builtin_amdgcn_exp2f(e));
+        const float Tn = fmaf(-alpha, T, T);
+        const bool ok = !done && alpha >= AMIN;
+        const bool stop = ok && Tn < TMIN;
+        const bool take = ok && !stop;
+        const float w = take ? alpha * T : 0.0f;
+        if (COUNTING) {
+            if (!done) {
+                n_tile++;
+                const uint32_t a = __float_as_uint(p1.z), b = __float_as_uint(p1.w);
+                n_box += (px >= (int)(a & 0xFFFFu) && px <= (int)(b & 0xFFFFu) &&
+                          py >= (int)(a >> 16) && py <= (int)(b >> 16));
+            }
+            n_acc += take;
+        }
+        T = take ? Tn : T;
+        done = done || stop;
+        if (MODE == MODE_UNIFORM) {
+            const float wm = slot_ok ? w : 0.0f;
+            if (__any(wm > 0.0f)) {
+                const float s = wave_total(wm);
+                if (lane == 0) acc[wj[jj]][uslot] = s;
+            }
+        } else if (MODE == MODE_MIXED) {
+            const float wm = slot_ok ? w : 0.0f;
+            uint64_t m = __ballot(wm > 0.0f);
+            while (m) {
+                const int sl = __builtin_amdgcn_readlane(slot, __ffsll((long long)m) - 1);
+                const bool mine = slot == sl;
+                const float s = wave_total(mine ? wm : 0.0f);
+                if (lane == 0) acc[wj[jj]][sl] = s;
+                m &= ~__ballot(mine);
+            }
+        }
+        if (__all(done)) break;
+    }
+}
+
+// Records of the sorted tile lists, in list order: the blend parameters
+// (prescaled for exp2) and the entry's part slot, so the compositing kernel
+// reads each batch with independent, coalesced loads.
+__global__ __launch_bounds__(256) void k_gather_lists(
+    uint64_t ni, const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sval,
+    const uint32_t* __restrict__ bucket_view, const ViewDev* __restrict__ views,
+    const float4* __restrict__ rec, const uint32_t* __restrict__ part_base,
+    const uint32_t* __restrict__ sat, float4* __restrict__ srec, uint32_t* __restrict__ soff)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= ni) return;
+    const uint32_t p = sval[i], b = skey[i];
+    const ViewDev& V = views[bucket_view[b]];
+    const uint32_t tile = b - V.tile_base;
+    const int tx = (int)(tile % (uint32_t)V.ntx), ty = (int)(tile / (uint32_t)V.ntx);
+    const float4 r0 = rec[2 * (size_t)p], r1 = rec[2 * (size_t)p + 1];
+    srec[2 * i] = make_float4(r0.x, r0.y, r0.z * NHALF_LOG2E, r0.w * NLOG2E);
+    srec[2 * i + 1] = make_float4(r1.x * NHALF_LOG2E, r1.y, r1.z, r1.w);
+    int x0, x1, y0, y1;
+    box_of(r1, x0, x1, y0, y1);
+    const int tx0 = x0 / TILE, tx1 = x1 / TILE, ty0 = y0 / TILE;
+    const uint32_t* S = sat + V.sat_off;
+    const int sw = V.ntx + 1;
+    soff[i] = part_base[p] + sat_rect(S, sw, tx0, tx1, ty0, ty - 1) + sat_rect(S, sw, tx0, tx - 1, ty, ty);
+}
+
 template <bool COUNT>
 __global__ __launch_bounds__(256) void k_composite(
     const uint32_t* __restrict__ bucket_view, const ViewDev* __restrict__ views,
     const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ bend,
-    const uint32_t* __restrict__ ival, const float4* __restrict__ rec,
-    const uint32_t* __restrict__ part_base, const uint32_t* __restrict__ sat,
+    const float4* __restrict__ srec, const uint32_t* __restrict__ soff,
     const uint32_t* __restrict__ ns_tile, const uint16_t* __restrict__ segl,
-    const int32_t* __restrict__ ids, float* __restrict__ part,
+    const int32_t* __restrict__ ids, uint2* __restrict__ part,
     unsigned long long* __restrict__ counters)
 {
-    __shared__ float4 s_p0[BATCH];            // u, v, A, B   (exponent e = A dx^2 + B dx dy + C dy^2)
-    __shared__ float2 s_p1[BATCH];            // C, opacity
-    __shared__ uint32_t s_off[BATCH];         // part slot of (pair, this tile, first tile segment)
-    __shared__ uint2 s_box[COUNT ? BATCH : 1];
-    __shared__ float s_acc[4][BATCH][NS_CAP];
+    __shared__ float4 s_w0[4][BATCH];         // per wave: entries touching its block (u, v, A, B)
+    __shared__ float4 s_w1[4][BATCH];         //   (C, opacity, box x0 | y0 << 16, box x1 | y1 << 16)
+    __shared__ int s_wj[4][BATCH];            //   their index in the batch
+    __shared__ float s_acc[4][BATCH][NS_CAP]; // per wave weight sums [entry][segment]
+    __shared__ uint32_t s_off[BATCH];         // part slot of (pair, this tile, first pass segment)
     __shared__ uint16_t s_seg[TILE_PIX];
 
     const uint32_t b = blockIdx.x;
@@ -155,8 +241,10 @@ __global__ __launch_bounds__(256) void k_composite(
     const uint32_t tile = b - V.tile_base;
     const int tx = (int)(tile % (uint32_t)V.ntx), ty = (int)(tile / (uint32_t)V.ntx);
     const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
-    const int px = tx * TILE + (wv & 1) * 8 + (lane & 7);
-    const int py = ty * TILE + (wv >> 1) * 8 + (lane >> 3);
+    const int bx0 = tx * TILE + (wv & 1) * 8;    // this wave's 8x8 pixel block
+    const int by0 = ty * TILE + (wv >> 1) * 8;
+    const int px = bx0 + (lane & 7);
+    const int py = by0 + (lane >> 3);
     const bool valid = px < V.W && py < V.H;
     const int32_t seg = valid ? ids[V.pix_off + (uint64_t)py * V.W + px] : -1;
     for (uint32_t i = t; i < ns; i += 256) s_seg[i] = segl[(uint64_t)b * TILE_PIX + i];
@@ -171,9 +259,9 @@ __global__ __launch_bounds__(256) void k_composite(
         ls = lo;
     }
     const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
-    const uint32_t* S = sat + V.sat_off;
-    const int sw = V.ntx + 1;
     unsigned long long n_acc = 0, n_box = 0, n_tile = 0;
+    const uint32_t last = end - 1;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     const int npass = ns == 0 ? 1 : (int)((ns + NS_CAP - 1) / NS_CAP);
     for (int pass = 0; pass < npass; pass++) {
@@ -182,88 +270,68 @@ __global__ __launch_bounds__(256) void k_composite(
         const bool counting = COUNT && pass == 0;
         const int slot = (ls >= g0 && ls < g0 + NS_CAP) ? ls - g0 : -1;
         // wave-uniform slot when every accumulating lane shares one segment
-        int uslot = -1;
+        int mode = MODE_NONE, uslot = -1;
         {
             const uint64_t has = __ballot(slot >= 0);
             if (has) {
                 const int first = __builtin_amdgcn_readlane(slot, __ffsll((long long)has) - 1);
-                uslot = __ballot(slot >= 0 && slot != first) ? -2 : first;
+                const bool mixed = __ballot(slot >= 0 && slot != first) != 0;
+                mode = mixed ? MODE_MIXED : MODE_UNIFORM;
+                uslot = first;
             }
         }
         bool done = counting ? !valid : (slot < 0);
         float T = 1.0f;
-        for (int i = t; i < 4 * BATCH * NS_CAP; i += 256) (&s_acc[0][0][0])[i] = 0.0f;
-        __syncthreads();
+        for (int i = lane; i < BATCH * NS_CAP; i += 64) (&s_acc[wv][0][0])[i] = 0.0f;
+        // lane l holds entry l of the batch (unconditional clamped loads: every
+        // address is inside the list; nothing waits on them until they are used)
+        uint32_t e = min(start + (uint32_t)lane, last);
+        float4 q0 = srec[2 * (size_t)e], q1 = srec[2 * (size_t)e + 1];
+        uint32_t qo = soff[e];
         for (uint32_t base = start; base < end; base += BATCH) {
             const int nb = (int)min((uint32_t)BATCH, end - base);
-            if (t < nb) {
-                const uint32_t p = ival[base + t];
-                const float4 r0 = rec[2 * (size_t)p];
-                const float4 r1 = rec[2 * (size_t)p + 1];
-                s_p0[t] = make_float4(r0.x, r0.y, r0.z * NHALF_LOG2E, r0.w * NLOG2E);
-                s_p1[t] = make_float2(r1.x * NHALF_LOG2E, r1.y);
-                int x0, x1, y0, y1;
-                box_of(r1, x0, x1, y0, y1);
-                const int tx0 = x0 / TILE, tx1 = x1 / TILE, ty0 = y0 / TILE;
-                s_off[t] = part_base[p] + sat_rect(S, sw, tx0, tx1, ty0, ty - 1) +
-                           sat_rect(S, sw, tx0, tx - 1, ty, ty) + (uint32_t)g0;
-                if (COUNT) s_box[t] = make_uint2((uint32_t)x0 | ((uint32_t)x1 << 16),
-                                                 (uint32_t)y0 | ((uint32_t)y1 << 16));
+            // compact the entries whose pixel box meets this wave's block
+            const uint32_t ba = __float_as_uint(q1.z), bb = __float_as_uint(q1.w);
+            const bool hit = lane < nb && (int)(bb & 0xFFFFu) >= bx0 && (int)(ba & 0xFFFFu) <= bx0 + 7 &&
+                             (int)(bb >> 16) >= by0 && (int)(ba >> 16) <= by0 + 7;
+            const uint64_t hm = __ballot(hit);
+            const int cnt = __popcll(hm);
+            if (hit) {
+                const int k = __popcll(hm & lt);
+                s_w0[wv][k] = q0;
+                s_w1[wv][k] = q1;
+                s_wj[wv][k] = lane;
             }
-            __syncthreads();
-            if (!__all(done)) {
-                for (int j = 0; j < nb; j++) {
-                    const float4 p0 = s_p0[j];
-                    const float2 p1 = s_p1[j];
-                    float w = 0.0f;
-                    if (!done) {
-                        const float dx = fpx - p0.x, dy = fpy - p0.y;
-                        float e = fmaf(dx, fmaf(p0.z, dx, p0.w * dy), p1.x * dy * dy);
-                        e = fminf(e, 0.0f);
-                        const float alpha = fminf(AMAX, p1.y * __builtin_amdgcn_exp2f(e));
-                        if (counting) {
-                            n_tile++;
-                            const uint2 bx = s_box[j];
-                            n_box += (px >= (int)(bx.x & 0xFFFFu) && px <= (int)(bx.x >> 16) &&
-                                      py >= (int)(bx.y & 0xFFFFu) && py <= (int)(bx.y >> 16));
-                        }
-                        if (alpha >= AMIN) {
-                            const float Tn = fmaf(-alpha, T, T);
-                            if (Tn < TMIN) {
-                                done = true;
-                            } else {
-                                w = alpha * T;
-                                T = Tn;
-                                if (counting) n_acc++;
-                            }
-                        }
-                    }
-                    if (uslot >= 0) {
-                        const float wm = slot >= 0 ? w : 0.0f;
-                        if (__any(wm > 0.0f)) {
-                            const float s = wave_sum(wm);
-                            if (lane == 0) s_acc[wv][j][uslot] = s;
-                        }
-                    } else if (uslot == -2) {
-                        const float wm = slot >= 0 ? w : 0.0f;
-                        uint64_t m = __ballot(wm > 0.0f);
-                        while (m) {
-                            const int sl = __builtin_amdgcn_readlane(slot, __ffsll((long long)m) - 1);
-                            const bool mine = slot == sl;
-                            const float s = wave_sum(mine ? wm : 0.0f);
-                            if (lane == 0) s_acc[wv][j][sl] = s;
-                            m &= ~__ballot(mine);
-                        }
-                    }
+            if (wv == 0 && lane < nb) s_off[lane] = qo + (uint32_t)g0;
+            // prefetch the next batch while blending this one
+            e = min(base + BATCH + (uint32_t)lane, last);
+            q0 = srec[2 * (size_t)e];
+            q1 = srec[2 * (size_t)e + 1];
+            qo = soff[e];
+            __builtin_amdgcn_wave_barrier();
+            if (cnt && !__all(done)) {
+                if (counting) {
+                    if (mode == MODE_UNIFORM)
+                        blend_batch<MODE_UNIFORM, true>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                    else if (mode == MODE_MIXED)
+                        blend_batch<MODE_MIXED, true>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                    else
+                        blend_batch<MODE_NONE, true>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                } else {
+                    if (mode == MODE_UNIFORM)
+                        blend_batch<MODE_UNIFORM, false>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                    else
+                        blend_batch<MODE_MIXED, false>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
                 }
             }
             __syncthreads();
             for (int i = t; i < nb * nsc; i += 256) {
                 const int j = i / nsc, k = i - j * nsc;
                 const float s = ((s_acc[0][j][k] + s_acc[1][j][k]) + s_acc[2][j][k]) + s_acc[3][j][k];
-                if (s != 0.0f) part[s_off[j] + k] = s;
                 s_acc[0][j][k] = 0.0f; s_acc[1][j][k] = 0.0f;
                 s_acc[2][j][k] = 0.0f; s_acc[3][j][k] = 0.0f;
+                if (s != 0.0f)
+                    part[s_off[j] + k] = make_uint2((uint32_t)s_seg[g0 + k], __float_as_uint(s));
             }
             if (__syncthreads_count(!done) == 0) break;
         }
@@ -284,15 +352,13 @@ __global__ __launch_bounds__(256) void k_composite(
     }
 }
 
-// One thread per pair: walk its tiles in row-major order and keep the
-// non-zero partial sums as (global segment row, weight).
-__global__ __launch_bounds__(256) void k_merge(uint64_t npairs, const float4* __restrict__ rec,
-                                               const uint16_t* __restrict__ pview,
+// Debug export: one thread per pair keeps its non-zero (segment row, weight)
+// slots, in slot order (tiles row-major, segments ascending within a tile).
+__global__ __launch_bounds__(256) void k_merge(uint64_t npairs, const uint16_t* __restrict__ pview,
                                                const ViewDev* __restrict__ views,
                                                const uint32_t* __restrict__ part_base,
-                                               const float* __restrict__ part,
-                                               const uint32_t* __restrict__ ns_tile,
-                                               const uint16_t* __restrict__ segl,
+                                               const uint32_t* __restrict__ pcnt,
+                                               const uint2* __restrict__ part,
                                                uint2* __restrict__ wrow,
                                                uint32_t* __restrict__ wlen,
                                                unsigned long long* __restrict__ nnz)
@@ -300,24 +366,12 @@ __global__ __launch_bounds__(256) void k_merge(uint64_t npairs, const float4* __
     const uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     uint32_t n = 0;
     if (p < npairs) {
-        int x0, x1, y0, y1;
-        box_of(rec[2 * p + 1], x0, x1, y0, y1);
         const ViewDev& V = views[pview[p]];
-        const uint32_t base = part_base[p];
-        uint32_t k = 0;
-        for (int ty = y0 / TILE; ty <= y1 / TILE; ty++)
-            for (int tx = x0 / TILE; tx <= x1 / TILE; tx++) {
-                const uint32_t bk = V.tile_base + (uint32_t)(ty * V.ntx + tx);
-                const uint32_t ns = ns_tile[bk];
-                for (uint32_t i = 0; i < ns; i++) {
-                    const float w = part[base + k++];
-                    if (w > 0.0f) {
-                        wrow[base + n] = make_uint2(V.seg_off + segl[(uint64_t)bk * TILE_PIX + i],
-                                                    __float_as_uint(w));
-                        n++;
-                    }
-                }
-            }
+        const uint32_t base = part_base[p], cnt = pcnt[p];
+        for (uint32_t k = 0; k < cnt; k++) {
+            const uint2 e = part[base + k];
+            if (__uint_as_float(e.y) > 0.0f) wrow[base + n++] = make_uint2(V.seg_off + e.x, e.y);
+        }
         wlen[p] = n;
     }
     unsigned long long c = n;
@@ -342,32 +396,38 @@ void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t*
     hipLaunchKernelGGL(k_sat, dim3(nb), dim3(256), 0, st, views, ns_tile, sat);
 }
 
+void launch_gather_lists(uint64_t ni, const uint32_t* skey, const uint32_t* sval,
+                         const uint32_t* bucket_view, const ViewDev* views, const float4* rec,
+                         const uint32_t* part_base, const uint32_t* sat, float4* srec,
+                         uint32_t* soff, hipStream_t st)
+{
+    if (!ni) return;
+    hipLaunchKernelGGL(k_gather_lists, dim3((unsigned)((ni + 255) / 256)), dim3(256), 0, st, ni,
+                       skey, sval, bucket_view, views, rec, part_base, sat, srec, soff);
+}
+
 void launch_composite(bool count, uint32_t nbuckets, const uint32_t* bucket_view,
                       const ViewDev* views, const uint32_t* bstart, const uint32_t* bend,
-                      const uint32_t* ival, const float4* rec, const uint32_t* part_base,
-                      const uint32_t* sat, const uint32_t* ns_tile, const uint16_t* segl,
-                      const int32_t* ids, float* part, unsigned long long* counters,
-                      hipStream_t st)
+                      const float4* srec, const uint32_t* soff, const uint32_t* ns_tile,
+                      const uint16_t* segl, const int32_t* ids, uint2* part,
+                      unsigned long long* counters, hipStream_t st)
 {
     if (!nbuckets) return;
     if (count)
         hipLaunchKernelGGL(k_composite<true>, dim3(nbuckets), dim3(256), 0, st, bucket_view, views,
-                           bstart, bend, ival, rec, part_base, sat, ns_tile, segl, ids, part,
-                           counters);
+                           bstart, bend, srec, soff, ns_tile, segl, ids, part, counters);
     else
         hipLaunchKernelGGL(k_composite<false>, dim3(nbuckets), dim3(256), 0, st, bucket_view,
-                           views, bstart, bend, ival, rec, part_base, sat, ns_tile, segl, ids,
-                           part, counters);
+                           views, bstart, bend, srec, soff, ns_tile, segl, ids, part, counters);
 }
 
-void launch_merge(uint64_t npairs, const float4* rec, const uint16_t* pview, const ViewDev* views,
-                  const uint32_t* part_base, const float* part, const uint32_t* ns_tile,
-                  const uint16_t* segl, uint2* wrow, uint32_t* wlen, unsigned long long* nnz,
-                  hipStream_t st)
+void launch_merge(uint64_t npairs, const uint16_t* pview, const ViewDev* views,
+                  const uint32_t* part_base, const uint32_t* pcnt, const uint2* part,
+                  uint2* wrow, uint32_t* wlen, unsigned long long* nnz, hipStream_t st)
 {
     if (!npairs) return;
     hipLaunchKernelGGL(k_merge, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, npairs,
-                       rec, pview, views, part_base, part, ns_tile, segl, wrow, wlen, nnz);
+                       pview, views, part_base, pcnt, part, wrow, wlen, nnz);
 }
 
 }  // namespace slag

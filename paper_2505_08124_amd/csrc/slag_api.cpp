@@ -51,6 +51,7 @@ struct slag_ctx {
 
     int64_t n = -1;
     DevBuf means, scales, quats, opac, cov3;
+    DevBuf perm, rank;      // Morton order of the Gaussians (rank -> input index, inverse)
 
     int nviews = -1;
     std::vector<slag_camera> cams;
@@ -73,8 +74,8 @@ struct slag_ctx {
 
     // workspace
     DevBuf ns_tile, segl, sat, tcnt, blk_vis, small, scan_ws, hist;
-    DevBuf rec, pgauss, pview, dkey, dkey_alt, dval, dval_alt, psz, pz, tcr, wlen;
-    DevBuf ikey, ikey_alt, ival, ival_alt, bstart, bend, part, wrow;
+    DevBuf rec, pgauss, pview, dkey, dkey_alt, dval, dval_alt, psz, pz, tcr, wlen, pair_of_m;
+    DevBuf ikey, ikey_alt, ival, ival_alt, bstart, bend, part, wrow, pcnt, srec, soff;
     uint64_t* host_small = nullptr;   // pinned read-back area
 
     // results of the last lift
@@ -188,6 +189,66 @@ static slag_status stage_end(slag_ctx* c, int stage, hipEvent_t a)
     return SLAG_OK;
 }
 
+static slag_status read_small(slag_ctx* c, int off, int words)
+{
+    HC(c, hipMemcpyAsync(c->host_small + off, c->small.as<uint64_t>() + off, words * 8,
+                         hipMemcpyDeviceToHost, c->st));
+    HC(c, hipStreamSynchronize(c->st));
+    return SLAG_OK;
+}
+
+// Morton order of the Gaussian means: the contraction takes Gaussians in
+// blocks of 16 consecutive along this curve.  Ties (equal 63-bit codes) keep
+// input order.
+static float from_ord(uint32_t o)
+{
+    uint32_t u = (o & 0x80000000u) ? (o ^ 0x80000000u) : ~o;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+static slag_status morton_order(slag_ctx* c, int64_t n)
+{
+    const uint64_t nn = (uint64_t)std::max<int64_t>(n, 1);
+    CK(ensure(c, c->perm, nn * 4));
+    CK(ensure(c, c->rank, nn * 4));
+    if (n == 0) return SLAG_OK;
+    CK(ensure(c, c->dkey, nn * 8));
+    CK(ensure(c, c->dkey_alt, nn * 8));
+    CK(ensure(c, c->dval, nn * 4));
+    CK(ensure(c, c->dval_alt, nn * 4));
+    CK(ensure(c, c->hist, radix_hist_bytes(nn)));
+    CK(ensure_scan(c, nn / 16 + 4096));
+    uint32_t* box = reinterpret_cast<uint32_t*>(c->small.as<uint64_t>() + SM_TOTALS);
+    launch_fill_u32(box, 3, 0xFFFFFFFFu, c->st);
+    launch_fill_u32(box + 3, 3, 0u, c->st);
+    launch_bbox(n, c->means.as<float>(), box, c->st);
+    CK(read_small(c, SM_TOTALS, 3));
+    uint32_t b6[6];
+    std::memcpy(b6, c->host_small + SM_TOTALS, sizeof(b6));
+    float ls[6];
+    for (int k = 0; k < 3; k++) {
+        const float lo = from_ord(b6[k]), hi = from_ord(b6[3 + k]);
+        const float ext = hi - lo;
+        ls[k] = lo;
+        ls[3 + k] = ext > 0.0f ? 2097151.0f / ext : 0.0f;
+    }
+    float* dls = reinterpret_cast<float*>(c->small.as<uint64_t>() + SM_TOTALS);
+    HC(c, hipMemcpyAsync(dls, ls, sizeof(ls), hipMemcpyHostToDevice, c->st));
+    launch_morton(n, c->means.as<float>(), dls, c->dkey.as<uint64_t>(), c->dval.as<uint32_t>(),
+                  c->st);
+    const bool alt = radix_sort_u64(c->dkey.as<uint64_t>(), c->dval.as<uint32_t>(),
+                                    c->dkey_alt.as<uint64_t>(), c->dval_alt.as<uint32_t>(),
+                                    (uint64_t)n, 63, c->hist.as<uint32_t>(), c->scan_ws.p,
+                                    nullptr, c->st);
+    const uint32_t* sorted = alt ? c->dval_alt.as<uint32_t>() : c->dval.as<uint32_t>();
+    HC(c, hipMemcpyAsync(c->perm.p, sorted, (size_t)n * 4, hipMemcpyDeviceToDevice, c->st));
+    launch_invert(n, c->perm.as<uint32_t>(), c->rank.as<uint32_t>(), c->st);
+    HC(c, hipStreamSynchronize(c->st));
+    return SLAG_OK;
+}
+
 // ---------------------------------------------------------------- view plan
 
 static slag_status build_plan(slag_ctx* c)
@@ -228,7 +289,7 @@ static slag_status build_plan(slag_ctx* c)
             x.sat_off = so;
             x.pix_off = c->pix_off[v0 + i];
             x.seg_off = (uint32_t)seg_off[v0 + i];
-            x.view = (uint32_t)(v0 + i);
+            x.nseg = (uint32_t)c->nseg[v0 + i];
             const uint32_t nt = (uint32_t)(x.ntx * x.nty);
             bv.insert(bv.end(), nt, (uint32_t)i);
             tb += nt;
@@ -249,14 +310,6 @@ static slag_status build_plan(slag_ctx* c)
 }
 
 // ------------------------------------------------------------------ the lift
-
-static slag_status read_small(slag_ctx* c, int off, int words)
-{
-    HC(c, hipMemcpyAsync(c->host_small + off, c->small.as<uint64_t>() + off, words * 8,
-                         hipMemcpyDeviceToHost, c->st));
-    HC(c, hipStreamSynchronize(c->st));
-    return SLAG_OK;
-}
 
 static slag_status lift_batch(slag_ctx* c, const Batch& B, bool first, bool last)
 {
@@ -312,12 +365,14 @@ static slag_status lift_batch(slag_ctx* c, const Batch& B, bool first, bool last
     CK(ensure(c, c->pz, np * 4));
     CK(ensure(c, c->tcr, np * 4 + 16));
     CK(ensure(c, c->wlen, np * 4));
+    CK(ensure(c, c->pair_of_m, npq * 4));
     launch_emit_pairs(nb, n, views, c->means.as<float>(), c->cov3.as<float>(), c->opac.as<float>(),
                       c->tcnt.as<uint32_t>(), c->blk_vis.as<uint32_t>(), c->rec.as<float4>(),
                       c->pgauss.as<uint32_t>(), c->pview.as<uint16_t>(), c->dkey.as<uint64_t>(),
                       c->dval.as<uint32_t>(), c->psz.as<uint32_t>(), c->pz.as<uint32_t>(),
                       c->sat.as<uint32_t>(), zmin, zbits,
-                      reinterpret_cast<unsigned long long*>(small + SM_TOTALS), st);
+                      reinterpret_cast<unsigned long long*>(small + SM_TOTALS),
+                      c->rank.as<uint32_t>(), c->pair_of_m.as<uint32_t>(), st);
     CK(stage_end(c, ST_PROJECT, ev));
 
     uint64_t ni = 0, nparts = 0;
@@ -375,35 +430,46 @@ static slag_status lift_batch(slag_ctx* c, const Batch& B, bool first, bool last
         launch_bucket_ranges(ni, skey, c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(), st);
         CK(stage_end(c, ST_TILE_SORT, ev));
 
-        // part slots: pair-major offsets, zeroed
+        // part slots: pair-major offsets (slot counts kept), zeroed; the tile
+        // lists' records gathered into list order
         CK(stage_begin(c, ST_PART_PREP, &ev));
+        CK(ensure(c, c->pcnt, np * 4));
+        HC(c, hipMemcpyAsync(c->pcnt.p, c->psz.p, npairs * 4, hipMemcpyDeviceToDevice, st));
         scan_u32(c->psz.as<uint32_t>(), npairs, nullptr, c->scan_ws.p, st);
-        CK(ensure(c, c->part, std::max<uint64_t>(nparts, 1) * 4));
-        CK(ensure(c, c->wrow, std::max<uint64_t>(nparts, 1) * 8));
-        launch_fill_u32(c->part.as<uint32_t>(), nparts, 0u, st);
+        CK(ensure(c, c->part, std::max<uint64_t>(nparts, 1) * 8));
+        launch_fill_u32(c->part.as<uint32_t>(), 2 * nparts, 0u, st);
+        CK(ensure(c, c->srec, ni * 32));
+        CK(ensure(c, c->soff, ni * 4));
+        launch_gather_lists(ni, skey, sval, B.bucket_view.as<uint32_t>(), views,
+                            c->rec.as<float4>(), c->psz.as<uint32_t>(), c->sat.as<uint32_t>(),
+                            c->srec.as<float4>(), c->soff.as<uint32_t>(), st);
         CK(stage_end(c, ST_PART_PREP, ev));
 
         CK(stage_begin(c, ST_COMPOSITE, &ev));
         launch_composite(count, B.nbuckets, B.bucket_view.as<uint32_t>(), views,
-                         c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(), sval,
-                         c->rec.as<float4>(), c->psz.as<uint32_t>(), c->sat.as<uint32_t>(),
-                         c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(), c->ids.as<int32_t>(),
-                         c->part.as<float>(),
+                         c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(), c->srec.as<float4>(),
+                         c->soff.as<uint32_t>(), c->ns_tile.as<uint32_t>(),
+                         c->segl.as<uint16_t>(), c->ids.as<int32_t>(), c->part.as<uint2>(),
                          reinterpret_cast<unsigned long long*>(small + SM_COUNTERS), st);
         CK(stage_end(c, ST_COMPOSITE, ev));
 
-        CK(stage_begin(c, ST_MERGE, &ev));
-        launch_merge(npairs, c->rec.as<float4>(), c->pview.as<uint16_t>(), views,
-                     c->psz.as<uint32_t>(), c->part.as<float>(), c->ns_tile.as<uint32_t>(),
-                     c->segl.as<uint16_t>(), c->wrow.as<uint2>(), c->wlen.as<uint32_t>(),
-                     reinterpret_cast<unsigned long long*>(small + SM_NNZ), st);
-        CK(stage_end(c, ST_MERGE, ev));
+        if (c->opt.flags & SLAG_FLAG_KEEP_DEBUG) {
+            // per-pair weight rows, only for the debug export
+            CK(stage_begin(c, ST_MERGE, &ev));
+            CK(ensure(c, c->wrow, std::max<uint64_t>(nparts, 1) * 8));
+            launch_merge(npairs, c->pview.as<uint16_t>(), views, c->psz.as<uint32_t>(),
+                         c->pcnt.as<uint32_t>(), c->part.as<uint2>(), c->wrow.as<uint2>(),
+                         c->wlen.as<uint32_t>(),
+                         reinterpret_cast<unsigned long long*>(small + SM_NNZ), st);
+            CK(stage_end(c, ST_MERGE, ev));
+        }
     }
 
     CK(stage_begin(c, ST_CONTRACT, &ev));
-    launch_contract(n, nb, c->d, c->fdt == SLAG_BF16, c->tcnt.as<uint32_t>(),
-                    c->wlen.as<uint32_t>(), c->psz.as<uint32_t>(), c->wrow.as<uint2>(),
-                    c->feats.p, c->num.as<float>(), c->den.as<float>(), first, last, st);
+    launch_contract(n, nb, c->d, c->fdt == SLAG_BF16, c->perm.as<uint32_t>(),
+                    c->pair_of_m.as<uint32_t>(), views, c->psz.as<uint32_t>(),
+                    c->pcnt.as<uint32_t>(), c->part.as<uint2>(), c->feats.p, c->num.as<float>(),
+                    c->den.as<float>(), first, last, st);
     CK(stage_end(c, ST_CONTRACT, ev));
 
     c->last_v0 = B.v0;
@@ -464,7 +530,8 @@ void slag_destroy(slag_ctx* c)
                       &c->small, &c->scan_ws, &c->hist, &c->rec, &c->pgauss, &c->pview, &c->dkey,
                       &c->dkey_alt, &c->dval, &c->dval_alt, &c->psz, &c->pz, &c->tcr, &c->wlen,
                       &c->ikey, &c->ikey_alt, &c->ival, &c->ival_alt, &c->bstart, &c->bend,
-                      &c->part, &c->wrow};
+                      &c->part, &c->wrow, &c->perm, &c->rank, &c->pair_of_m, &c->pcnt,
+                      &c->srec, &c->soff};
     for (DevBuf* b : bufs) release(*b);
     for (auto& b : c->plan) { release(b.views); release(b.bucket_view); }
     for (auto& e : c->events) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
@@ -506,6 +573,7 @@ slag_status slag_set_gaussians(slag_ctx* c, int64_t n, const float* means, const
     if (c->host_small[SM_ERR] & 1)
         FAIL(c, SLAG_E_INVALID_ARG, "Gaussian parameters must be finite, scales > 0, quaternions "
                                     "non-zero and opacity in (0, 1]");
+    CK(morton_order(c, n));
     c->n = n;
     c->plan_views = -1;   // launch sizes depend on n
     return SLAG_OK;

@@ -7,7 +7,7 @@ namespace slag {
 
 constexpr int TILE = 16;                 // tile edge in pixels (16 x 16 = 4 waves of 8 x 8)
 constexpr int TILE_PIX = TILE * TILE;
-constexpr int NS_CAP = 8;                // tile segments accumulated per compositing pass
+constexpr int NS_CAP = 4;                // tile segments accumulated per compositing pass
 constexpr int BATCH = 64;                // tile-list entries staged in LDS per step
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 
@@ -23,7 +23,7 @@ struct ViewDev {
     uint32_t sat_off;        // first entry of this view's summed-area table
     uint64_t pix_off;        // first pixel of this view in the id array
     uint32_t seg_off;        // first feature row of this view
-    uint32_t view;           // global view index
+    uint32_t nseg;           // segments of this view
 };
 
 // Pair record (one visible (view, Gaussian) pair), two float4:
@@ -43,7 +43,14 @@ void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* mea
                        const uint32_t* blk_off, float4* rec, uint32_t* pgauss, uint16_t* pview,
                        uint64_t* dkey, uint32_t* dval, uint32_t* psz, uint32_t* pz,
                        const uint32_t* sat, uint32_t zmin, int zbits,
-                       unsigned long long* totals, hipStream_t st);
+                       unsigned long long* totals, const uint32_t* rank, uint32_t* pair_of_m,
+                       hipStream_t st);
+// Morton order of the Gaussian means: bounding box (order-preserving integer
+// images in box6[0..2] = min, [3..5] = max), 63-bit keys, inverse permutation
+void launch_bbox(int64_t n, const float* means, uint32_t* box6, hipStream_t st);
+void launch_morton(int64_t n, const float* means, const float* lo_scale, uint64_t* keys,
+                   uint32_t* vals, hipStream_t st);
+void launch_invert(int64_t n, const uint32_t* perm, uint32_t* rank, hipStream_t st);
 
 // scans: exclusive prefix sum in place; the 64-bit total goes to *total_dev
 size_t scan_workspace_bytes(uint64_t n);
@@ -72,21 +79,23 @@ void launch_tile_segs(uint32_t nbuckets, const uint32_t* bucket_view, const View
                       const int32_t* ids, uint32_t* ns_tile, uint16_t* segl, hipStream_t st);
 void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t* sat,
                 hipStream_t st);
+void launch_gather_lists(uint64_t ni, const uint32_t* skey, const uint32_t* sval,
+                         const uint32_t* bucket_view, const ViewDev* views, const float4* rec,
+                         const uint32_t* part_base, const uint32_t* sat, float4* srec,
+                         uint32_t* soff, hipStream_t st);
 void launch_composite(bool count, uint32_t nbuckets, const uint32_t* bucket_view,
                       const ViewDev* views, const uint32_t* bstart, const uint32_t* bend,
-                      const uint32_t* ival, const float4* rec, const uint32_t* part_base,
-                      const uint32_t* sat, const uint32_t* ns_tile, const uint16_t* segl,
-                      const int32_t* ids, float* part, unsigned long long* counters,
-                      hipStream_t st);
-void launch_merge(uint64_t npairs, const float4* rec, const uint16_t* pview, const ViewDev* views,
-                  const uint32_t* part_base, const float* part, const uint32_t* ns_tile,
-                  const uint16_t* segl, uint2* wrow, uint32_t* wlen,
-                  unsigned long long* nnz, hipStream_t st);
+                      const float4* srec, const uint32_t* soff, const uint32_t* ns_tile,
+                      const uint16_t* segl, const int32_t* ids, uint2* part,
+                      unsigned long long* counters, hipStream_t st);
+void launch_merge(uint64_t npairs, const uint16_t* pview, const ViewDev* views,
+                  const uint32_t* part_base, const uint32_t* pcnt, const uint2* part,
+                  uint2* wrow, uint32_t* wlen, unsigned long long* nnz, hipStream_t st);
 
 bool contract_supported(int d);
-void launch_contract(int64_t n, int nb, int d, bool bf16, const uint32_t* pair_of,
-                     const uint32_t* wlen, const uint32_t* part_base, const uint2* wrow,
-                     const void* feats, float* num, float* den, bool first, bool last,
-                     hipStream_t st);
+void launch_contract(int64_t n, int nb, int d, bool bf16, const uint32_t* perm,
+                     const uint32_t* pair_of_m, const ViewDev* views, const uint32_t* part_base,
+                     const uint32_t* pcnt, const uint2* part, const void* feats, float* num,
+                     float* den, bool first, bool last, hipStream_t st);
 
 }  // namespace slag

@@ -134,9 +134,10 @@ def test_counts_match_oracle_2k(oracle_2k, lift_2k):
     assert st["n_tile_tests"] >= st["n_tests"]
 
 
-def test_repeat_and_batching_bitwise(scene_2k, lift_2k):
-    """Two lifts are bitwise equal (no float atomics); one view per launch
-    gives the same bits (views are summed in the same order)."""
+def test_repeat_bitwise_and_batching(scene_2k, lift_2k):
+    """Two lifts are bitwise equal (no float atomics).  One view per launch
+    gives bitwise-equal weight sums (same order) and embeddings equal to FP32
+    rounding (the matrix-core chunks group the products differently)."""
     L, E, den = lift_2k
     L.lift()
     E2, den2 = L.embeddings()
@@ -145,7 +146,8 @@ def test_repeat_and_batching_bitwise(scene_2k, lift_2k):
     L1 = _lifter(scene_2k, max_views=1)
     L1.lift()
     E3, den3 = L1.embeddings()
-    assert np.array_equal(E, E3) and np.array_equal(den, den3)
+    assert np.array_equal(den, den3)
+    np.testing.assert_allclose(E3, E, rtol=1e-5, atol=1e-6)
 
 
 def test_permutation_equivariance_gpu(scene_2k, lift_2k):
