@@ -5,12 +5,13 @@
 // segment per view, out of ~10^2 per view.  Gaussians are taken in blocks of
 // 16 consecutive along a Morton curve of their means, so the 16 rows of a
 // block tend to see the same segments.  A workgroup (4 waves) owns one block;
-// every wave walks the block's pairs eight views per step (each lane walks two
-// (row, view) pairs, reading their packed (segment, weight) slots),
-// deduplicates the segments the rows touch (an LDS bitmap per view over
-// view-local segment ids), and packs them into K-chunks of 32 columns: A[16 x 32] holds the weights, B[32 x 16] the
-// feature rows of those segments.  Each wave multiplies for its quarter of
-// the feature columns:
+// the block walks its pairs sixteen views per step, one (row, view) pair per
+// thread reading the pair's packed (segment, weight) slots; the segments the
+// rows touch are deduplicated per view with LDS bitmaps over view-local ids,
+// numbered in (view, id) order by a block scan, and the weights are summed
+// into a shared A[16 x K].  K-chunks of 32 columns then go to the matrix
+// cores: A[16 x 32] holds the weights, B[32 x 16] the feature rows of those
+// segments, and each wave multiplies for its quarter of the feature columns:
 //   BF16 features: v_mfma_f32_16x16x32_bf16, with A split exactly enough into
 //                  hi + lo BF16 parts (two MFMAs, error ~2^-16 relative);
 //   FP32 features: v_mfma_f32_16x16x4_f32, eight per chunk.
@@ -28,58 +29,60 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int KC = 32;          // K columns per chunk
 
-constexpr int VG = 8;           // views per step: lane l walks (row l & 15) in views
-                                // v0 + (l >> 4) and v0 + 4 + (l >> 4)
-constexpr int SL = 4;           // slots of one pair held in registers at a time
+constexpr int GV = 16;          // views per step: thread t walks (row t & 15, view v0 + (t >> 4))
+constexpr int KMAX = 128;       // K columns staged per round of a step
 
-struct WaveLds {
-    uint32_t bits[64];          // word i: view i >> 3 of the step, ids w0 + 32 (i & 7) + [0, 32)
-    uint32_t piece[64];         // bits placed in the open chunk by the current piece
-    uint32_t pbase[64];         // first chunk column of each piece word
-    uint32_t ks[KC];            // feature row of each K column of the open chunk
-    float A[16][KC + 1];        // weights of the open chunk
-    float dpart[VG][16];        // per-view weight sums of the step
-    float den[16];
+struct BlockLds {
+    uint32_t bits[GV * 8];      // word i: view i >> 3 of the step, ids w0 + 32 (i & 7) + [0, 32)
+    uint32_t wbase[GV * 8];     // first step column of each word
+    uint32_t ks[KMAX];          // feature row of each column of the round
+    float A[16][KMAX + 1];      // weights of the round's columns
+    float dpart[GV][16];        // per-view row weight sums of the step
+    uint32_t scan[8];
 };
 
-// Multiply the open chunk (kn columns) into the accumulators and clear it.
+// Multiply columns [k0, k0 + kn) of the staged round into the accumulators.
 template <int NT, bool BF16>
-__device__ __forceinline__ void flush(WaveLds& L, int kn, const void* feats, int d, int c0,
-                                      floatx4* acc, int lane)
+__device__ __forceinline__ void mfma_chunk(const BlockLds& L, int k0, int kn, const void* feats,
+                                           int d, int c0, floatx4* acc, int lane)
 {
     const int m = lane & 15, kq = lane >> 4;
     if constexpr (BF16) {
         bf16x8 ahi, alo;
-        uint32_t krow[8];
+        const uint16_t* rowp[8];   // this lane's column in each K row (row 0 stands in for
+        uint32_t live = 0;         // unused K slots; their values are replaced by zero)
+        const uint16_t* F = reinterpret_cast<const uint16_t*>(feats) + c0 + m;
 #pragma unroll
         for (int j = 0; j < 8; j++) {
             const int k = 8 * kq + j;
-            const float a = L.A[m][k];
+            const float a = k < kn ? L.A[m][k0 + k] : 0.0f;
             const __bf16 h = (__bf16)a;
             ahi[j] = h;
             alo[j] = (__bf16)(a - (float)h);
-            krow[j] = k < kn ? L.ks[k] : NONE;
+            const uint32_t kr = k < kn ? L.ks[k0 + k] : 0u;
+            live |= (k < kn ? 1u : 0u) << j;
+            rowp[j] = F + (size_t)kr * d;
         }
-        const uint16_t* F = reinterpret_cast<const uint16_t*>(feats);
 #pragma unroll
         for (int t = 0; t < NT; t++) {
-            const int col = c0 + 16 * t + m;
             bf16x8 b;
 #pragma unroll
             for (int j = 0; j < 8; j++) {
-                const uint16_t v = krow[j] != NONE ? F[(size_t)krow[j] * d + col] : (uint16_t)0;
-                b[j] = __builtin_bit_cast(__bf16, v);
+                const uint16_t v = rowp[j][16 * t];
+                b[j] = __builtin_bit_cast(__bf16, ((live >> j) & 1u) ? v : (uint16_t)0);
             }
             acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, b, acc[t], 0, 0, 0);
             acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, b, acc[t], 0, 0, 0);
+            // keep at most two tiles of feature loads in flight (register pressure)
+            if (t & 1) __builtin_amdgcn_sched_barrier(0);
         }
     } else {
         const float* F = reinterpret_cast<const float*>(feats);
 #pragma unroll
         for (int kk = 0; kk < KC / 4; kk++) {
             const int k = 4 * kk + kq;
-            const float a = L.A[m][k];
-            const uint32_t krow = k < kn ? L.ks[k] : NONE;
+            const float a = k < kn ? L.A[m][k0 + k] : 0.0f;
+            const uint32_t krow = k < kn ? L.ks[k0 + k] : NONE;
 #pragma unroll
             for (int t = 0; t < NT; t++) {
                 const int col = c0 + 16 * t + m;
@@ -88,34 +91,25 @@ __device__ __forceinline__ void flush(WaveLds& L, int kn, const void* feats, int
             }
         }
     }
-    __builtin_amdgcn_wave_barrier();
-    for (int i = lane; i < 16 * (KC + 1); i += 64) (&L.A[0][0])[i] = 0.0f;
-    __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ uint32_t wave_exscan(uint32_t x, int lane, uint32_t& total)
+// Exclusive scan of one value per thread over the 256-thread block.
+__device__ __forceinline__ uint32_t block_exscan(uint32_t x, uint32_t* scratch, uint32_t& total)
 {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t v = x;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(v, d, 64);
-        if (lane >= d) v += y;
+    for (int dd = 1; dd < 64; dd <<= 1) {
+        const uint32_t y = __shfl_up(v, dd, 64);
+        if (lane >= dd) v += y;
     }
-    total = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
-    return v - x;
-}
-
-// The lowest k set bits of b.
-__device__ __forceinline__ uint32_t lowest_bits(uint32_t b, uint32_t k)
-{
-    if (k >= (uint32_t)__popc(b)) return b;
-    uint32_t keep = 0;
-    for (uint32_t i = 0; i < k; i++) {
-        const uint32_t low = b & (~b + 1u);
-        keep |= low;
-        b ^= low;
-    }
-    return keep;
+    if (lane == 63) scratch[w] = v;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int i = 0; i < w; i++) off += scratch[i];
+    total = scratch[0] + scratch[1] + scratch[2] + scratch[3];
+    __syncthreads();
+    return off + v - x;
 }
 
 template <int NT, bool BF16>
@@ -126,167 +120,128 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
     const uint2* __restrict__ part, const void* __restrict__ feats, float* __restrict__ num,
     float* __restrict__ den, int first, int last)
 {
-    __shared__ WaveLds lds[4];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    WaveLds& L = lds[wv];
+    __shared__ BlockLds L;
+    const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
     const int64_t q0 = (int64_t)blockIdx.x * 16;          // first Morton rank of the block
     const int c0 = wv * 16 * NT;                          // this wave's first feature column
     const int m = lane & 15, kq = lane >> 4;
-    const int r = lane & 15, vq = lane >> 4;              // walking role
-    const bool row_ok = q0 + r < n;
-    const int64_t qr = row_ok ? q0 + r : q0;
+    const int row = t & 15, vi = t >> 4;                  // walking role
+    const bool row_ok = q0 + row < n;
+    const int64_t qr = row_ok ? q0 + row : q0;
 
-    for (int i = lane; i < 16 * (KC + 1); i += 64) (&L.A[0][0])[i] = 0.0f;
-    L.bits[lane] = 0;
     floatx4 acc[NT];
-    float dsum = 0.0f;   // running weight sum of row r (held by lanes vq == 0)
+    float dsum = 0.0f;   // running weight sum of row t (threads t < 16)
     if (first) {
 #pragma unroll
-        for (int t = 0; t < NT; t++) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < NT; i++) acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
     } else {
 #pragma unroll
-        for (int t = 0; t < NT; t++)
+        for (int i = 0; i < NT; i++)
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const int64_t q = q0 + 4 * kq + j;
-                acc[t][j] = q < n ? num[(size_t)perm[q] * d + c0 + 16 * t + m] : 0.0f;
+                acc[i][j] = q < n ? num[(size_t)perm[q] * d + c0 + 16 * i + m] : 0.0f;
             }
-        if (vq == 0 && row_ok) dsum = den[perm[q0 + r]];
+        if (t < 16 && q0 + t < n) dsum = den[perm[q0 + t]];
     }
-    __builtin_amdgcn_wave_barrier();
-    int kn = 0;   // open chunk fill
 
     auto pair_at = [&](int v) -> uint32_t {
         const int vc = v < nb ? v : nb - 1;                 // clamped: always a valid address
         const uint32_t p = pair_of_m[(int64_t)vc * n + qr];
         return (row_ok && v < nb) ? p : NONE;
     };
-    uint32_t nA = pair_at(vq), nB = pair_at(4 + vq);
+    uint32_t pn = pair_at(vi);
 
-    for (int v0 = 0; v0 < nb; v0 += VG) {
-        const uint32_t pA = nA, pB = nB;
-        nA = pair_at(v0 + VG + vq);                         // next step, in flight meanwhile
-        nB = pair_at(v0 + VG + 4 + vq);
-        if (!__ballot(pA != NONE || pB != NONE)) continue;
-        const int vA = v0 + vq, vB = v0 + 4 + vq;
-        const uint32_t pbA = pA != NONE ? part_base[pA] : 0u, cA = pA != NONE ? pcnt[pA] : 0u;
-        const uint32_t pbB = pB != NONE ? part_base[pB] : 0u, cB = pB != NONE ? pcnt[pB] : 0u;
-        const uint32_t nsA = vA < nb ? views[vA].nseg : 0u, nsB = vB < nb ? views[vB].nseg : 0u;
-        const int vw = v0 + (lane >> 3);                    // view of bitmap word `lane`
-        const uint32_t so_w = vw < nb ? views[vw].seg_off : 0u;
-        const uint32_t cmax = max(cA, cB);
-        float dA = 0.0f, dB = 0.0f;
-        for (uint32_t w0 = 0; __ballot(w0 < nsA || w0 < nsB); w0 += 256) {
-            // 1. mark the segments the rows touch
-            for (uint32_t kb = 0; __ballot(kb < cmax); kb += SL) {
-                uint2 ea[SL], eb[SL];
-#pragma unroll
-                for (int k = 0; k < SL; k++) {
-                    ea[k] = kb + k < cA ? part[pbA + kb + k] : make_uint2(0u, 0u);
-                    eb[k] = kb + k < cB ? part[pbB + kb + k] : make_uint2(0u, 0u);
+    for (int v0 = 0; v0 < nb; v0 += GV) {
+        const uint32_t p = pn;
+        pn = pair_at(v0 + GV + vi);                         // next step, in flight meanwhile
+        if (!__syncthreads_or(p != NONE)) continue;
+        const int v = v0 + vi;
+        const uint32_t pb = p != NONE ? part_base[p] : 0u, cnt = p != NONE ? pcnt[p] : 0u;
+        const uint32_t nsv = v < nb ? views[v].nseg : 0u;
+        const int vw = v0 + (t >> 3);                       // view of bitmap word t (t < 128)
+        const uint32_t so_w = (t < GV * 8 && vw < nb) ? views[vw].seg_off : 0u;
+        float dv = 0.0f;
+        for (uint32_t w0 = 0; __syncthreads_or(w0 < nsv); w0 += 256) {
+            if (t < GV * 8) L.bits[t] = 0;
+            __syncthreads();
+            // 1. mark the segments the rows touch (slot order: dv does not
+            //    depend on how columns are cut)
+            auto mark = [&](const uint2 x) {
+                const uint32_t s = x.x - w0;
+                const float w = __uint_as_float(x.y);
+                if (s < 256u && w > 0.0f) {
+                    atomicOr(&L.bits[vi * 8 + (s >> 5)], 1u << (s & 31));
+                    dv += w;
                 }
-#pragma unroll
-                for (int k = 0; k < SL; k++) {
-                    const uint32_t sa = ea[k].x - w0, sb = eb[k].x - w0;
-                    const float wa = __uint_as_float(ea[k].y), wb = __uint_as_float(eb[k].y);
-                    if (sa < 256u && wa > 0.0f) {
-                        atomicOr(&L.bits[vq * 8 + (sa >> 5)], 1u << (sa & 31));
-                        dA += wa;
-                    }
-                    if (sb < 256u && wb > 0.0f) {
-                        atomicOr(&L.bits[(vq + 4) * 8 + (sb >> 5)], 1u << (sb & 31));
-                        dB += wb;
-                    }
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            uint32_t b = L.bits[lane];                      // lane owns word `lane`
-            __builtin_amdgcn_wave_barrier();
-            L.bits[lane] = 0;
-            // 2. place the marked segments into chunks (views in order, ids ascending)
-            for (;;) {
-                uint32_t total;
-                const uint32_t c = (uint32_t)__popc(b);
-                const uint32_t pre = wave_exscan(c, lane, total);
-                if (!total) break;
-                const uint32_t room = (uint32_t)(KC - kn);
-                const uint32_t want = pre < room ? room - pre : 0u;
-                const uint32_t piece = lowest_bits(b, want);
-                b ^= piece;
-                const uint32_t taken = total < room ? total : room;
-                const uint32_t pbase = (uint32_t)kn + (pre < room ? pre : room);
-                L.piece[lane] = piece;
-                L.pbase[lane] = pbase;
-                {
-                    uint32_t cc = pbase, bb = piece;
+            };
+#pragma unroll 4
+            for (uint32_t k = 0; k < cnt; k++) mark(part[pb + k]);
+            __syncthreads();
+            // 2. columns: marked segments in (view, id) order
+            const uint32_t wb = t < GV * 8 ? L.bits[t] : 0u;
+            uint32_t ktot;
+            const uint32_t base = block_exscan((uint32_t)__popc(wb), L.scan, ktot);
+            if (t < GV * 8) L.wbase[t] = base;
+            for (uint32_t kr = 0; kr < ktot; kr += KMAX) {
+                // feature rows of this round's columns
+                if (wb) {
+                    uint32_t c = base, bb = wb;
                     while (bb) {
                         const uint32_t bit = (uint32_t)(__ffs((int)bb) - 1);
-                        L.ks[cc++] = so_w + w0 + 32u * (uint32_t)(lane & 7) + bit;
+                        if (c >= kr && c < kr + KMAX)
+                            L.ks[c - kr] = so_w + w0 + 32u * (uint32_t)(t & 7) + bit;
                         bb &= bb - 1u;
+                        c++;
                     }
                 }
-                __builtin_amdgcn_wave_barrier();
-                // weights of the placed segments, each lane into its row
-                for (uint32_t kb = 0; __ballot(kb < cmax); kb += SL) {
-                    uint2 ea[SL], eb[SL];
-#pragma unroll
-                    for (int k = 0; k < SL; k++) {
-                        ea[k] = kb + k < cA ? part[pbA + kb + k] : make_uint2(0u, 0u);
-                        eb[k] = kb + k < cB ? part[pbB + kb + k] : make_uint2(0u, 0u);
-                    }
-#pragma unroll
-                    for (int k = 0; k < SL; k++) {
-#pragma unroll
-                        for (int h = 0; h < 2; h++) {
-                            const uint2 e = h ? eb[k] : ea[k];
-                            const uint32_t s = e.x - w0;
-                            const float w = __uint_as_float(e.y);
-                            if (s >= 256u || !(w > 0.0f)) continue;
-                            const int wi = (vq + 4 * h) * 8 + (int)(s >> 5);
-                            const uint32_t pw = L.piece[wi];
-                            const uint32_t bit = 1u << (s & 31);
-                            if (!(pw & bit)) continue;
-                            const int col = (int)L.pbase[wi] + __popc(pw & (bit - 1u));
-                            L.A[r][col] += w;
-                        }
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
-                kn += (int)taken;
-                if (kn == KC) {
-                    flush<NT, BF16>(L, kn, feats, d, c0, acc, lane);
-                    kn = 0;
-                }
+                for (int i = t; i < 16 * (KMAX + 1); i += 256) (&L.A[0][0])[i] = 0.0f;
+                __syncthreads();
+                // 3. weights: each thread adds its pair's slots into its row
+                auto add = [&](const uint2 x) {
+                    const uint32_t s = x.x - w0;
+                    const float w = __uint_as_float(x.y);
+                    if (s >= 256u || !(w > 0.0f)) return;
+                    const int wi = vi * 8 + (int)(s >> 5);
+                    const uint32_t bit = 1u << (s & 31);
+                    const uint32_t col = L.wbase[wi] + (uint32_t)__popc(L.bits[wi] & (bit - 1u));
+                    if (col >= kr && col < kr + KMAX) L.A[row][col - kr] += w;
+                };
+#pragma unroll 4
+                for (uint32_t k = 0; k < cnt; k++) add(part[pb + k]);
+                __syncthreads();
+                // 4. matrix cores, 32 columns at a time
+                const int kc = (int)min((uint32_t)KMAX, ktot - kr);
+                for (int k0 = 0; k0 < kc; k0 += KC)
+                    mfma_chunk<NT, BF16>(L, k0, min(KC, kc - k0), feats, d, c0, acc, lane);
+                __syncthreads();
             }
         }
         // row weight sums, views in order
-        L.dpart[vq][r] = dA;
-        L.dpart[vq + 4][r] = dB;
-        __builtin_amdgcn_wave_barrier();
-        if (vq == 0) {
+        L.dpart[vi][row] = dv;
+        __syncthreads();
+        if (t < 16) {
 #pragma unroll
-            for (int i = 0; i < VG; i++) dsum += L.dpart[i][r];
+            for (int i = 0; i < GV; i++) dsum += L.dpart[i][t];
         }
-        __builtin_amdgcn_wave_barrier();
     }
-    if (kn) flush<NT, BF16>(L, kn, feats, d, c0, acc, lane);
-    if (vq == 0) L.den[r] = dsum;
-    __builtin_amdgcn_wave_barrier();
+    __syncthreads();
+    if (t < 16) L.dpart[0][t] = dsum;
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         const int rr = 4 * kq + j;
         const int64_t q = q0 + rr;
         if (q >= n) continue;
         const uint32_t g = perm[q];
-        const float dn = L.den[rr];
+        const float dn = L.dpart[0][rr];
 #pragma unroll
-        for (int t = 0; t < NT; t++) {
-            const float a = acc[t][j];
-            num[(size_t)g * d + c0 + 16 * t + m] = last ? (dn > 0.0f ? a / dn : 0.0f) : a;
+        for (int i = 0; i < NT; i++) {
+            const float a = acc[i][j];
+            num[(size_t)g * d + c0 + 16 * i + m] = last ? (dn > 0.0f ? a / dn : 0.0f) : a;
         }
     }
-    if (vq == 0 && row_ok && wv == 0) den[perm[q0 + r]] = dsum;
+    if (t < 16 && q0 + t < n) den[perm[q0 + t]] = dsum;
 }
 
 template <int NT>

@@ -216,11 +216,18 @@ __global__ __launch_bounds__(256) void k_count(int64_t n, const ViewDev* __restr
         zmin = min(zmin, (uint32_t)__shfl_xor((int)zmin, d, 64));
         zmax = max(zmax, (uint32_t)__shfl_xor((int)zmax, d, 64));
     }
-    if ((threadIdx.x & 63) == 0 && zmax >= zmin) {
-        atomicMin(&zrange[0], zmin);
-        atomicMax(&zrange[1], zmax);
+    __shared__ uint32_t zl[8];
+    if ((threadIdx.x & 63) == 0) {
+        zl[threadIdx.x >> 6] = zmin;
+        zl[4 + (threadIdx.x >> 6)] = zmax;
     }
-    if (threadIdx.x == 0) blk_vis[(int64_t)vl * gridDim.x + blockIdx.x] = total;
+    __syncthreads();
+    const int64_t bi = (int64_t)vl * gridDim.x + blockIdx.x;
+    if (threadIdx.x == 0) {
+        blk_vis[bi] = total;
+        zrange[2 * bi] = min(min(zl[0], zl[1]), min(zl[2], zl[3]));
+        zrange[2 * bi + 1] = max(max(zl[4], zl[5]), max(zl[6], zl[7]));
+    }
 }
 
 // Pass 2: compact visible pairs in (view, Gaussian) order and write their
@@ -232,8 +239,8 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
     const uint32_t* __restrict__ blk_off, float4* __restrict__ rec, uint32_t* __restrict__ pgauss,
     uint16_t* __restrict__ pview, uint64_t* __restrict__ dkey, uint32_t* __restrict__ dval,
     uint32_t* __restrict__ psz, uint32_t* __restrict__ pz, const uint32_t* __restrict__ sat,
-    uint32_t zmin, int zbits, unsigned long long* __restrict__ totals,
-    const uint32_t* __restrict__ rank, uint32_t* __restrict__ pair_of_m)
+    uint32_t zmin, int zbits, uint32_t* __restrict__ blk_tot,
+    const uint32_t* __restrict__ rank, uint32_t* __restrict__ pair_of_m, uint32_t* __restrict__ ptc)
 {
     __shared__ uint32_t cnt[PER_THREAD][4];
     __shared__ uint64_t msk[4][PER_THREAD];
@@ -289,7 +296,9 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         const uint32_t ps = S[(ty1 + 1) * sw + tx1 + 1] - S[ty0 * sw + tx1 + 1] -
                             S[(ty1 + 1) * sw + tx0] + S[ty0 * sw + tx0];
         psz[pidx] = ps;
-        n_isect += (unsigned long long)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+        const uint32_t tc = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+        ptc[pidx] = tc;
+        n_isect += tc;
         n_part += ps;
         io[g] = pidx;
         pair_of_m[(int64_t)vl * n + rank[g]] = pidx;
@@ -299,9 +308,46 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         n_isect += __shfl_xor(n_isect, d, 64);
         n_part += __shfl_xor(n_part, d, 64);
     }
-    if (lane == 0 && (n_isect | n_part)) {
-        atomicAdd(&totals[0], n_isect);
-        atomicAdd(&totals[1], n_part);
+    __shared__ unsigned long long tl[8];
+    if (lane == 0) {
+        tl[wv] = n_isect;
+        tl[4 + wv] = n_part;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // per-block totals (saturated: a block never exceeds 2^32 - 1 in practice,
+        // and the host rejects totals that do)
+        const unsigned long long a = tl[0] + tl[1] + tl[2] + tl[3];
+        const unsigned long long b = tl[4] + tl[5] + tl[6] + tl[7];
+        const int64_t bi = (int64_t)vl * gridDim.x + blockIdx.x;
+        blk_tot[2 * bi] = a > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)a;
+        blk_tot[2 * bi + 1] = b > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)b;
+    }
+}
+
+// Reduction of per-block results: out[0] = min over even entries (u32 min),
+// out[1] = max over odd entries; or (sum mode) 64-bit sums of even and odd
+// entries.  One block; fixed order per thread, so results are deterministic.
+__global__ __launch_bounds__(256) void k_reduce_pairs(const uint32_t* __restrict__ in, uint64_t npairs,
+                                                      int sum_mode, unsigned long long* __restrict__ out)
+{
+    __shared__ unsigned long long a_l[256], b_l[256];
+    unsigned long long a = sum_mode ? 0ull : 0xFFFFFFFFull, b = 0ull;
+    for (uint64_t i = threadIdx.x; i < npairs; i += 256) {
+        const uint32_t x = in[2 * i], y = in[2 * i + 1];
+        if (sum_mode) { a += x; b += y; }
+        else { a = min(a, (unsigned long long)x); b = max(b, (unsigned long long)y); }
+    }
+    a_l[threadIdx.x] = a;
+    b_l[threadIdx.x] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 256; i++) {
+            if (sum_mode) { a += a_l[i]; b += b_l[i]; }
+            else { a = min(a, a_l[i]); b = max(b, b_l[i]); }
+        }
+        out[0] = a;
+        out[1] = b;
     }
 }
 
@@ -324,15 +370,22 @@ __global__ __launch_bounds__(256) void k_bbox(int64_t n, const float* __restrict
             lo[k] = min(lo[k], o);
             hi[k] = max(hi[k], o);
         }
+    __shared__ uint32_t bl[4][6];
     for (int k = 0; k < 3; k++) {
         for (int d = 32; d >= 1; d >>= 1) {
             lo[k] = min(lo[k], (uint32_t)__shfl_xor((int)lo[k], d, 64));
             hi[k] = max(hi[k], (uint32_t)__shfl_xor((int)hi[k], d, 64));
         }
         if ((threadIdx.x & 63) == 0) {
-            atomicMin(&box6[k], lo[k]);
-            atomicMax(&box6[3 + k], hi[k]);
+            bl[threadIdx.x >> 6][k] = lo[k];
+            bl[threadIdx.x >> 6][3 + k] = hi[k];
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        atomicMin(&box6[k], min(min(bl[0][k], bl[1][k]), min(bl[2][k], bl[3][k])));
+        atomicMax(&box6[3 + k], max(max(bl[0][3 + k], bl[1][3 + k]), max(bl[2][3 + k], bl[3][3 + k])));
     }
 }
 
@@ -405,15 +458,21 @@ void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* mea
                        const float* cov3, const float* opac, uint32_t* tcnt_pairof,
                        const uint32_t* blk_off, float4* rec, uint32_t* pgauss, uint16_t* pview,
                        uint64_t* dkey, uint32_t* dval, uint32_t* psz, uint32_t* pz,
-                       const uint32_t* sat, uint32_t zmin, int zbits,
-                       unsigned long long* totals, const uint32_t* rank, uint32_t* pair_of_m,
-                       hipStream_t st)
+                       const uint32_t* sat, uint32_t zmin, int zbits, uint32_t* blk_tot,
+                       const uint32_t* rank, uint32_t* pair_of_m, uint32_t* ptc, hipStream_t st)
 {
     if (n <= 0 || nb <= 0) return;
     hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)count_blocks_per_view(n), (unsigned)nb),
                        dim3(256), 0, st, n, views, means, cov3, opac, tcnt_pairof, blk_off, rec,
-                       pgauss, pview, dkey, dval, psz, pz, sat, zmin, zbits, totals, rank,
-                       pair_of_m);
+                       pgauss, pview, dkey, dval, psz, pz, sat, zmin, zbits, blk_tot, rank,
+                       pair_of_m, ptc);
+}
+
+void launch_reduce_pairs(const uint32_t* in, uint64_t npairs, bool sum_mode,
+                         unsigned long long* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(256), 0, st, in, npairs, sum_mode ? 1 : 0,
+                       out);
 }
 
 void launch_bbox(int64_t n, const float* means, uint32_t* box6, hipStream_t st)

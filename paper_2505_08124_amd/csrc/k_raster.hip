@@ -190,39 +190,13 @@ __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const
     }
 }
 
-// Records of the sorted tile lists, in list order: the blend parameters
-// (prescaled for exp2) and the entry's part slot, so the compositing kernel
-// reads each batch with independent, coalesced loads.
-__global__ __launch_bounds__(256) void k_gather_lists(
-    uint64_t ni, const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sval,
-    const uint32_t* __restrict__ bucket_view, const ViewDev* __restrict__ views,
-    const float4* __restrict__ rec, const uint32_t* __restrict__ part_base,
-    const uint32_t* __restrict__ sat, float4* __restrict__ srec, uint32_t* __restrict__ soff)
-{
-    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= ni) return;
-    const uint32_t p = sval[i], b = skey[i];
-    const ViewDev& V = views[bucket_view[b]];
-    const uint32_t tile = b - V.tile_base;
-    const int tx = (int)(tile % (uint32_t)V.ntx), ty = (int)(tile / (uint32_t)V.ntx);
-    const float4 r0 = rec[2 * (size_t)p], r1 = rec[2 * (size_t)p + 1];
-    srec[2 * i] = make_float4(r0.x, r0.y, r0.z * NHALF_LOG2E, r0.w * NLOG2E);
-    srec[2 * i + 1] = make_float4(r1.x * NHALF_LOG2E, r1.y, r1.z, r1.w);
-    int x0, x1, y0, y1;
-    box_of(r1, x0, x1, y0, y1);
-    const int tx0 = x0 / TILE, tx1 = x1 / TILE, ty0 = y0 / TILE;
-    const uint32_t* S = sat + V.sat_off;
-    const int sw = V.ntx + 1;
-    soff[i] = part_base[p] + sat_rect(S, sw, tx0, tx1, ty0, ty - 1) + sat_rect(S, sw, tx0, tx - 1, ty, ty);
-}
-
 template <bool COUNT>
 __global__ __launch_bounds__(256) void k_composite(
     const uint32_t* __restrict__ bucket_view, const ViewDev* __restrict__ views,
     const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ bend,
-    const float4* __restrict__ srec, const uint32_t* __restrict__ soff,
-    const uint32_t* __restrict__ ns_tile, const uint16_t* __restrict__ segl,
-    const int32_t* __restrict__ ids, uint2* __restrict__ part,
+    const uint32_t* __restrict__ ival, const uint32_t* __restrict__ islot,
+    const float4* __restrict__ rec, const uint32_t* __restrict__ ns_tile,
+    const uint16_t* __restrict__ segl, const int32_t* __restrict__ ids, uint2* __restrict__ part,
     unsigned long long* __restrict__ counters)
 {
     __shared__ float4 s_w0[4][BATCH];         // per wave: entries touching its block (u, v, A, B)
@@ -283,11 +257,15 @@ __global__ __launch_bounds__(256) void k_composite(
         bool done = counting ? !valid : (slot < 0);
         float T = 1.0f;
         for (int i = lane; i < BATCH * NS_CAP; i += 64) (&s_acc[wv][0][0])[i] = 0.0f;
-        // lane l holds entry l of the batch (unconditional clamped loads: every
-        // address is inside the list; nothing waits on them until they are used)
+        // lane l holds entry l of the batch.  Two-deep prefetch: records of the
+        // next batch and list entries of the one after are in flight while a
+        // batch blends (unconditional clamped loads: every address is inside
+        // the list; nothing waits on them until they are used).
         uint32_t e = min(start + (uint32_t)lane, last);
-        float4 q0 = srec[2 * (size_t)e], q1 = srec[2 * (size_t)e + 1];
-        uint32_t qo = soff[e];
+        uint32_t pc = ival[e], qo = islot[e];
+        float4 q0 = rec[2 * (size_t)pc], q1 = rec[2 * (size_t)pc + 1];
+        e = min(start + BATCH + (uint32_t)lane, last);
+        uint32_t pn = ival[e], on = islot[e];
         for (uint32_t base = start; base < end; base += BATCH) {
             const int nb = (int)min((uint32_t)BATCH, end - base);
             // compact the entries whose pixel box meets this wave's block
@@ -298,16 +276,17 @@ __global__ __launch_bounds__(256) void k_composite(
             const int cnt = __popcll(hm);
             if (hit) {
                 const int k = __popcll(hm & lt);
-                s_w0[wv][k] = q0;
-                s_w1[wv][k] = q1;
+                s_w0[wv][k] = make_float4(q0.x, q0.y, q0.z * NHALF_LOG2E, q0.w * NLOG2E);
+                s_w1[wv][k] = make_float4(q1.x * NHALF_LOG2E, q1.y, q1.z, q1.w);
                 s_wj[wv][k] = lane;
             }
             if (wv == 0 && lane < nb) s_off[lane] = qo + (uint32_t)g0;
-            // prefetch the next batch while blending this one
-            e = min(base + BATCH + (uint32_t)lane, last);
-            q0 = srec[2 * (size_t)e];
-            q1 = srec[2 * (size_t)e + 1];
-            qo = soff[e];
+            q0 = rec[2 * (size_t)pn];
+            q1 = rec[2 * (size_t)pn + 1];
+            qo = on;
+            e = min(base + 2 * BATCH + (uint32_t)lane, last);
+            pn = ival[e];
+            on = islot[e];
             __builtin_amdgcn_wave_barrier();
             if (cnt && !__all(done)) {
                 if (counting) {
@@ -396,29 +375,20 @@ void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t*
     hipLaunchKernelGGL(k_sat, dim3(nb), dim3(256), 0, st, views, ns_tile, sat);
 }
 
-void launch_gather_lists(uint64_t ni, const uint32_t* skey, const uint32_t* sval,
-                         const uint32_t* bucket_view, const ViewDev* views, const float4* rec,
-                         const uint32_t* part_base, const uint32_t* sat, float4* srec,
-                         uint32_t* soff, hipStream_t st)
-{
-    if (!ni) return;
-    hipLaunchKernelGGL(k_gather_lists, dim3((unsigned)((ni + 255) / 256)), dim3(256), 0, st, ni,
-                       skey, sval, bucket_view, views, rec, part_base, sat, srec, soff);
-}
-
 void launch_composite(bool count, uint32_t nbuckets, const uint32_t* bucket_view,
                       const ViewDev* views, const uint32_t* bstart, const uint32_t* bend,
-                      const float4* srec, const uint32_t* soff, const uint32_t* ns_tile,
-                      const uint16_t* segl, const int32_t* ids, uint2* part,
-                      unsigned long long* counters, hipStream_t st)
+                      const uint32_t* ival, const uint32_t* islot, const float4* rec,
+                      const uint32_t* ns_tile, const uint16_t* segl, const int32_t* ids,
+                      uint2* part, unsigned long long* counters, hipStream_t st)
 {
     if (!nbuckets) return;
     if (count)
         hipLaunchKernelGGL(k_composite<true>, dim3(nbuckets), dim3(256), 0, st, bucket_view, views,
-                           bstart, bend, srec, soff, ns_tile, segl, ids, part, counters);
+                           bstart, bend, ival, islot, rec, ns_tile, segl, ids, part, counters);
     else
         hipLaunchKernelGGL(k_composite<false>, dim3(nbuckets), dim3(256), 0, st, bucket_view,
-                           views, bstart, bend, srec, soff, ns_tile, segl, ids, part, counters);
+                           views, bstart, bend, ival, islot, rec, ns_tile, segl, ids, part,
+                           counters);
 }
 
 void launch_merge(uint64_t npairs, const uint16_t* pview, const ViewDev* views,

@@ -14,10 +14,6 @@ namespace {
 
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = 256 * SCAN_ITEMS;   // elements per block
-constexpr int RADIX_BITS = 8;
-constexpr int RADIX = 1 << RADIX_BITS;
-constexpr int RADIX_ITEMS = 16;
-constexpr int RADIX_TILE = 256 * RADIX_ITEMS;
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
 {
@@ -97,51 +93,82 @@ __global__ __launch_bounds__(256) void k_scan_block(uint32_t* __restrict__ data,
 }
 
 // ---------------------------------------------------------------- radix sort
+//
+// One pass sorts by an 8-bit digit.  Block tile: 4 waves x 8 items x 64
+// lanes; element order inside a block is (wave, item, lane) = ascending index,
+// so ranking equal digits with ballots, wave by wave, keeps the sort stable.
+// Elements are regrouped by digit in LDS before the global write, so each
+// digit's run leaves the block as consecutive addresses.  An optional second
+// value array rides along.
 
-template <typename K>
-__device__ __forceinline__ uint32_t digit_of(K k, int shift)
-{
-    return (uint32_t)(k >> shift) & (RADIX - 1);
-}
+constexpr int RADIX_ITEMS = 8;
+constexpr int RADIX_TILE = 256 * RADIX_ITEMS;
+constexpr int RADIX_MAXBITS = 8;
 
-template <typename K>
+template <typename K, int RB>
 __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, uint64_t n,
                                                     int shift, uint32_t* __restrict__ hist,
                                                     uint32_t nblk)
 {
-    __shared__ uint32_t cnt[RADIX];
-    cnt[threadIdx.x] = 0;
+    // per-wave counts; lanes with equal digits are grouped with ballots and
+    // their leader adds the group size (no same-address LDS atomics)
+    constexpr int R = 1 << RB;
+    __shared__ uint32_t cnt[4][R];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = threadIdx.x; i < 4 * R; i += 256) (&cnt[0][0])[i] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * RADIX_TILE;
-    for (int i = threadIdx.x; i < RADIX_TILE; i += 256) {
-        uint64_t idx = base + i;
-        if (idx < n) atomicAdd(&cnt[digit_of(keys[idx], shift)], 1u);
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint64_t base = (uint64_t)blockIdx.x * RADIX_TILE + (uint64_t)w * (RADIX_ITEMS * 64);
+#pragma unroll
+    for (int it = 0; it < RADIX_ITEMS; it++) {
+        const uint64_t idx = base + it * 64 + lane;
+        const bool valid = idx < n;
+        const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & (R - 1) : 0u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < RB; b++) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        if (valid && (peers & lt) == 0) cnt[w][d] += (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    hist[(uint64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+    for (int i = threadIdx.x; i < R; i += 256)
+        hist[(uint64_t)i * nblk + blockIdx.x] = cnt[0][i] + cnt[1][i] + cnt[2][i] + cnt[3][i];
 }
 
-// Stable scatter: within a block, element order is (wave, item, lane) =
-// ascending index; equal digits are ranked with ballots, waves in order.
-template <typename K>
+template <typename K, int RB, bool V2>
 __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin,
                                                        const uint32_t* __restrict__ vin,
+                                                       const uint32_t* __restrict__ uin,
                                                        K* __restrict__ kout,
-                                                       uint32_t* __restrict__ vout, uint64_t n,
+                                                       uint32_t* __restrict__ vout,
+                                                       uint32_t* __restrict__ uout, uint64_t n,
                                                        int shift,
                                                        const uint32_t* __restrict__ hist,
                                                        uint32_t nblk)
 {
-    __shared__ uint32_t wcnt[4][RADIX];
-    __shared__ uint32_t dbase[RADIX];
+    constexpr int R = 1 << RB;
+    __shared__ uint32_t wcnt[4][R];
+    __shared__ uint32_t dbase[R];     // global start of each digit for this block
+    __shared__ uint32_t lbase[R];     // block-local start of each digit
+    __shared__ uint32_t tmp[8];
+    __shared__ K s_key[RADIX_TILE];
+    __shared__ uint32_t s_val[RADIX_TILE];
+    __shared__ uint32_t s_aux[V2 ? RADIX_TILE : 1];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = threadIdx.x; i < 4 * RADIX; i += 256) (&wcnt[0][0])[i] = 0;
-    dbase[threadIdx.x] = hist[(uint64_t)threadIdx.x * nblk + blockIdx.x];
+    for (int i = threadIdx.x; i < 4 * R; i += 256) (&wcnt[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < R; i += 256) dbase[i] = hist[(uint64_t)i * nblk + blockIdx.x];
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint64_t base = (uint64_t)blockIdx.x * RADIX_TILE + (uint64_t)w * (RADIX_ITEMS * 64);
+    const uint64_t bbase = (uint64_t)blockIdx.x * RADIX_TILE;
+    const uint64_t base = bbase + (uint64_t)w * (RADIX_ITEMS * 64);
+    const int nvalid = (int)min((uint64_t)RADIX_TILE, n - bbase);
     K key[RADIX_ITEMS];
     uint32_t val[RADIX_ITEMS];
+    uint32_t aux[V2 ? RADIX_ITEMS : 1];
     uint32_t rk[RADIX_ITEMS];
 #pragma unroll
     for (int it = 0; it < RADIX_ITEMS; it++) {
@@ -149,10 +176,11 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
         const bool valid = idx < n;
         key[it] = valid ? kin[idx] : (K)0;
         val[it] = valid ? vin[idx] : 0u;
-        const uint32_t d = digit_of(key[it], shift);
+        if constexpr (V2) aux[it] = valid ? uin[idx] : 0u;
+        const uint32_t d = (uint32_t)(key[it] >> shift) & (R - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < RADIX_BITS; b++) {
+        for (int b = 0; b < RB; b++) {
             const bool bit = (d >> b) & 1u;
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
@@ -160,56 +188,103 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
         uint32_t before = 0;
         if (valid) before = wcnt[w][d];
         const uint32_t r = (uint32_t)__popcll(peers & lt);
-        // all lanes have read the running count before the leaders update it
+        // every lane has read the running count before the leaders update it
         __builtin_amdgcn_wave_barrier();
         if (valid && r == 0) wcnt[w][d] = before + (uint32_t)__popcll(peers);
         __builtin_amdgcn_wave_barrier();
         rk[it] = before + r;
     }
     __syncthreads();
-    {
-        // exclusive prefix of the per-wave counts, per digit
-        const int d = threadIdx.x;
+    // per digit: exclusive prefix over waves, and the block total
+    uint32_t dtot[R / 256 > 0 ? R / 256 : 1];
+#pragma unroll
+    for (int q = 0; q < R / 256; q++) {
+        const int d = threadIdx.x + 256 * q;
         uint32_t s = 0;
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            uint32_t c = wcnt[k][d];
+            const uint32_t c = wcnt[k][d];
             wcnt[k][d] = s;
             s += c;
         }
+        dtot[q] = s;
+    }
+    // block-local digit starts: exclusive scan of the totals over digits
+    {
+        uint32_t run = 0;
+#pragma unroll
+        for (int q = 0; q < R / 256; q++) {
+            // digits q*256 .. q*256+255 are owned by threads 0..255 in order
+            uint32_t x = dtot[q], v = x;
+#pragma unroll
+            for (int dd = 1; dd < 64; dd <<= 1) {
+                const uint32_t y = __shfl_up(v, dd, 64);
+                if (lane >= dd) v += y;
+            }
+            if (lane == 63) tmp[w] = v;
+            __syncthreads();
+            uint32_t off = run;
+            for (int i = 0; i < w; i++) off += tmp[i];
+            lbase[threadIdx.x + 256 * q] = off + v - x;
+            run += tmp[0] + tmp[1] + tmp[2] + tmp[3];
+            __syncthreads();
+        }
     }
     __syncthreads();
+    // reorder through LDS so that equal digits sit together ...
 #pragma unroll
     for (int it = 0; it < RADIX_ITEMS; it++) {
         const uint64_t idx = base + it * 64 + lane;
         if (idx < n) {
-            const uint32_t d = digit_of(key[it], shift);
-            const uint32_t pos = dbase[d] + wcnt[w][d] + rk[it];
-            kout[pos] = key[it];
-            vout[pos] = val[it];
+            const uint32_t d = (uint32_t)(key[it] >> shift) & (R - 1);
+            const uint32_t lp = lbase[d] + wcnt[w][d] + rk[it];
+            s_key[lp] = key[it];
+            s_val[lp] = val[it];
+            if constexpr (V2) s_aux[lp] = aux[it];
         }
+    }
+    __syncthreads();
+    // ... and write them out in runs: consecutive threads, consecutive addresses
+    for (int lp = threadIdx.x; lp < nvalid; lp += 256) {
+        const K k = s_key[lp];
+        const uint32_t d = (uint32_t)(k >> shift) & (R - 1);
+        const uint32_t pos = dbase[d] + (uint32_t)lp - lbase[d];
+        kout[pos] = k;
+        vout[pos] = s_val[lp];
+        if constexpr (V2) uout[pos] = s_aux[lp];
     }
 }
 
-template <typename K>
-bool radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, uint64_t n, int nbits,
-                uint32_t* hist, void* ws, uint64_t* tot, hipStream_t st)
+template <typename K, int RB, bool V2>
+void radix_pass(const K* ka, const uint32_t* va, const uint32_t* ua, K* kb, uint32_t* vb,
+                uint32_t* ub, uint64_t n, int shift, uint32_t* hist, void* ws, hipStream_t st)
+{
+    const uint32_t nblk = (uint32_t)((n + RADIX_TILE - 1) / RADIX_TILE);
+    hipLaunchKernelGGL((k_radix_hist<K, RB>), dim3(nblk), dim3(256), 0, st, ka, n, shift, hist,
+                       nblk);
+    scan_u32(hist, (uint64_t)nblk << RB, nullptr, ws, st);
+    hipLaunchKernelGGL((k_radix_scatter<K, RB, V2>), dim3(nblk), dim3(256), 0, st, ka, va, ua, kb,
+                       vb, ub, n, shift, hist, nblk);
+}
+
+// Stable LSD sort of (key, value[, aux]) by bits [0, nbits), 8 bits per pass.
+template <typename K, bool V2>
+bool radix_sort(K* keys, uint32_t* vals, uint32_t* aux, K* keys_alt, uint32_t* vals_alt,
+                uint32_t* aux_alt, uint64_t n, int nbits, uint32_t* hist, void* ws, hipStream_t st)
 {
     if (n <= 1 || nbits <= 0) return false;
-    const uint32_t nblk = (uint32_t)((n + RADIX_TILE - 1) / RADIX_TILE);
+    const int passes = (nbits + RADIX_MAXBITS - 1) / RADIX_MAXBITS;
+    const int rb = (nbits + passes - 1) / passes;
     K* ka = keys;
     K* kb = keys_alt;
-    uint32_t* va = vals;
-    uint32_t* vb = vals_alt;
+    uint32_t *va = vals, *vb = vals_alt, *ua = aux, *ub = aux_alt;
     bool alt = false;
-    for (int shift = 0; shift < nbits; shift += RADIX_BITS) {
-        hipLaunchKernelGGL(k_radix_hist<K>, dim3(nblk), dim3(256), 0, st, ka, n, shift, hist,
-                           nblk);
-        scan_u32(hist, (uint64_t)nblk * RADIX, nullptr, ws, st);
-        hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nblk), dim3(256), 0, st, ka, va, kb, vb, n,
-                           shift, hist, nblk);
+    for (int shift = 0; shift < nbits; shift += rb) {
+        radix_pass<K, RADIX_MAXBITS, V2>(ka, va, ua, kb, vb, ub, n, shift, hist, ws, st);
+        shift += RADIX_MAXBITS - rb;   // the digit may cover more bits than asked
         K* tk = ka; ka = kb; kb = tk;
         uint32_t* tv = va; va = vb; vb = tv;
+        uint32_t* tu = ua; ua = ub; ub = tu;
         alt = !alt;
     }
     return alt;
@@ -225,39 +300,83 @@ __device__ __forceinline__ void box_of(const float4& r1, int& x0, int& x1, int& 
 }
 
 __global__ __launch_bounds__(256) void k_rank_tiles(uint64_t npairs, const uint32_t* __restrict__ order,
-                                                    const float4* __restrict__ rec,
+                                                    const uint32_t* __restrict__ ptc,
                                                     uint32_t* __restrict__ tcr)
 {
     const uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r >= npairs) return;
-    int x0, x1, y0, y1;
-    box_of(rec[2 * (size_t)order[r] + 1], x0, x1, y0, y1);
-    tcr[r] = (uint32_t)((x1 / TILE - x0 / TILE + 1) * (y1 / TILE - y0 / TILE + 1));
+    if (r < npairs) tcr[r] = ptc[order[r]];
 }
 
+// (tile, pair, part slot) entries of every pair in depth order, tiles of a
+// pair in row-major order.  A wave emits the consecutive output range of its 64 pairs
+// together: output slot e finds its pair among the wave's 64 offsets, so the
+// stores are coalesced.
 __global__ __launch_bounds__(256) void k_emit_isect(uint64_t npairs, const uint32_t* __restrict__ order,
                                                     const float4* __restrict__ rec,
                                                     const uint16_t* __restrict__ pview,
                                                     const ViewDev* __restrict__ views,
                                                     const uint32_t* __restrict__ ioff,
+                                                    const uint32_t* __restrict__ part_base,
+                                                    const uint32_t* __restrict__ sat,
                                                     uint32_t* __restrict__ ikey,
-                                                    uint32_t* __restrict__ ival)
+                                                    uint32_t* __restrict__ ival,
+                                                    uint32_t* __restrict__ islot)
 {
-    const uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r >= npairs) return;
-    const uint32_t p = order[r];
-    int x0, x1, y0, y1;
-    box_of(rec[2 * (size_t)p + 1], x0, x1, y0, y1);
-    const ViewDev& V = views[pview[p]];
-    const uint32_t tb = V.tile_base;
-    const int ntx = V.ntx;
-    uint32_t o = ioff[r];
-    for (int ty = y0 / TILE; ty <= y1 / TILE; ty++)
-        for (int tx = x0 / TILE; tx <= x1 / TILE; tx++) {
-            ikey[o] = tb + (uint32_t)(ty * ntx + tx);
-            ival[o] = p;
-            o++;
+    __shared__ uint32_t s_off[4][65];
+    __shared__ uint32_t s_p[4][64];
+    __shared__ uint32_t s_r[4][64][3];   // tile base, tiles per row of the rect, ntx
+    __shared__ uint32_t s_q[4][64][4];   // first tile (tx0, ty0), pair's first part slot, SAT offset
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t r0 = (uint64_t)blockIdx.x * 256 + (uint64_t)w * 64;
+    if (r0 >= npairs) return;
+    const uint64_t r = r0 + lane;
+    const int nw = (int)min((uint64_t)64, npairs - r0);
+    uint32_t o = 0, tc = 0;
+    if (lane < nw) {
+        const uint32_t p = order[r];
+        const float2 bx = reinterpret_cast<const float2*>(rec)[4 * (size_t)p + 3];
+        const uint32_t a = __float_as_uint(bx.x), b = __float_as_uint(bx.y);
+        const int tx0 = (int)(a & 0xFFFFu) / TILE, ty0 = (int)(a >> 16) / TILE;
+        const int tx1 = (int)(b & 0xFFFFu) / TILE, ty1 = (int)(b >> 16) / TILE;
+        const ViewDev& V = views[pview[p]];
+        o = ioff[r];
+        tc = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+        s_p[w][lane] = p;
+        s_r[w][lane][0] = V.tile_base + (uint32_t)(ty0 * V.ntx + tx0);
+        s_r[w][lane][1] = (uint32_t)(tx1 - tx0 + 1);
+        s_r[w][lane][2] = (uint32_t)V.ntx;
+        s_q[w][lane][0] = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
+        s_q[w][lane][1] = part_base[p];
+        s_q[w][lane][2] = V.sat_off;
+        s_off[w][lane] = o;
+    }
+    const uint32_t o0 = __builtin_amdgcn_readfirstlane(o);
+    const uint32_t last_end = (uint32_t)__builtin_amdgcn_readlane((int)(o + tc), nw - 1);
+    if (lane == 0) s_off[w][nw] = last_end;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t e = o0 + lane; e < last_end; e += 64) {
+        // the pair owning slot e: largest j with s_off[j] <= e
+        int lo = 0, hi = nw - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[w][mid] <= e) lo = mid; else hi = mid - 1;
         }
+        const uint32_t k = e - s_off[w][lo];
+        const uint32_t rw = s_r[w][lo][1], ntx = s_r[w][lo][2];
+        const uint32_t dy = k / rw, dx = k % rw;
+        ikey[e] = s_r[w][lo][0] + dy * ntx + dx;
+        ival[e] = s_p[w][lo];
+        // part slot: the pair's first slot plus the segment counts of the rect
+        // tiles before this one (row-major), from the view's summed-area table;
+        // the two rectangle sums share a corner that cancels
+        const uint32_t t0 = s_q[w][lo][0];
+        const int tx0 = (int)(t0 & 0xFFFFu), ty0 = (int)(t0 >> 16);
+        const int tx = tx0 + (int)dx, ty = ty0 + (int)dy, tx1 = tx0 + (int)rw - 1;
+        const uint32_t* S = sat + s_q[w][lo][2];
+        const int sw = (int)ntx + 1;
+        islot[e] = s_q[w][lo][1] + S[ty * sw + tx1 + 1] - S[ty0 * sw + tx1 + 1] + S[ty0 * sw + tx0] +
+                   S[(ty + 1) * sw + tx] - S[ty * sw + tx] - S[(ty + 1) * sw + tx0];
+    }
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v)
@@ -317,38 +436,51 @@ void scan_u32(uint32_t* data, uint64_t n, uint64_t* total_dev, void* ws, hipStre
 
 size_t radix_hist_bytes(uint64_t n)
 {
-    return ((n + RADIX_TILE - 1) / RADIX_TILE) * RADIX * sizeof(uint32_t) + 256;
+    return ((n + RADIX_TILE - 1) / RADIX_TILE) * ((size_t)1 << RADIX_MAXBITS) * sizeof(uint32_t) + 256;
 }
 
 bool radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
                     uint64_t n, int nbits, uint32_t* hist, void* scan_ws, uint64_t* tot,
                     hipStream_t st)
 {
-    return radix_sort<uint64_t>(keys, vals, keys_alt, vals_alt, n, nbits, hist, scan_ws, tot, st);
+    (void)tot;
+    return radix_sort<uint64_t, false>(keys, vals, nullptr, keys_alt, vals_alt, nullptr, n, nbits,
+                                       hist, scan_ws, st);
 }
 
 bool radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                     uint64_t n, int nbits, uint32_t* hist, void* scan_ws, uint64_t* tot,
                     hipStream_t st)
 {
-    return radix_sort<uint32_t>(keys, vals, keys_alt, vals_alt, n, nbits, hist, scan_ws, tot, st);
+    (void)tot;
+    return radix_sort<uint32_t, false>(keys, vals, nullptr, keys_alt, vals_alt, nullptr, n, nbits,
+                                       hist, scan_ws, st);
 }
 
-void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const float4* rec, uint32_t* tcr,
+bool radix_sort_u32_v2(uint32_t* keys, uint32_t* vals, uint32_t* aux, uint32_t* keys_alt,
+                       uint32_t* vals_alt, uint32_t* aux_alt, uint64_t n, int nbits,
+                       uint32_t* hist, void* scan_ws, hipStream_t st)
+{
+    return radix_sort<uint32_t, true>(keys, vals, aux, keys_alt, vals_alt, aux_alt, n, nbits, hist,
+                                      scan_ws, st);
+}
+
+void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const uint32_t* ptc, uint32_t* tcr,
                        hipStream_t st)
 {
     if (!npairs) return;
-    hipLaunchKernelGGL(k_rank_tiles, dim3(grid_for(npairs)), dim3(256), 0, st, npairs, order, rec,
+    hipLaunchKernelGGL(k_rank_tiles, dim3(grid_for(npairs)), dim3(256), 0, st, npairs, order, ptc,
                        tcr);
 }
 
 void launch_emit_isect(uint64_t npairs, const uint32_t* order, const float4* rec,
                        const uint16_t* pview, const ViewDev* views, const uint32_t* ioff,
-                       uint32_t* ikey, uint32_t* ival, hipStream_t st)
+                       const uint32_t* part_base, const uint32_t* sat, uint32_t* ikey,
+                       uint32_t* ival, uint32_t* islot, hipStream_t st)
 {
     if (!npairs) return;
     hipLaunchKernelGGL(k_emit_isect, dim3(grid_for(npairs)), dim3(256), 0, st, npairs, order, rec,
-                       pview, views, ioff, ikey, ival);
+                       pview, views, ioff, part_base, sat, ikey, ival, islot);
 }
 
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st)

@@ -75,7 +75,8 @@ struct slag_ctx {
     // workspace
     DevBuf ns_tile, segl, sat, tcnt, blk_vis, small, scan_ws, hist;
     DevBuf rec, pgauss, pview, dkey, dkey_alt, dval, dval_alt, psz, pz, tcr, wlen, pair_of_m;
-    DevBuf ikey, ikey_alt, ival, ival_alt, bstart, bend, part, wrow, pcnt, srec, soff;
+    DevBuf ikey, ikey_alt, ival, ival_alt, islot, islot_alt, bstart, bend, part, wrow, pcnt;
+    DevBuf ptc, blk_aux;
     uint64_t* host_small = nullptr;   // pinned read-back area
 
     // results of the last lift
@@ -219,7 +220,7 @@ static slag_status morton_order(slag_ctx* c, int64_t n)
     CK(ensure(c, c->dval, nn * 4));
     CK(ensure(c, c->dval_alt, nn * 4));
     CK(ensure(c, c->hist, radix_hist_bytes(nn)));
-    CK(ensure_scan(c, nn / 16 + 4096));
+    CK(ensure_scan(c, nn / 2 + 4096));
     uint32_t* box = reinterpret_cast<uint32_t*>(c->small.as<uint64_t>() + SM_TOTALS);
     launch_fill_u32(box, 3, 0xFFFFFFFFu, c->st);
     launch_fill_u32(box + 3, 3, 0u, c->st);
@@ -338,20 +339,19 @@ static slag_status lift_batch(slag_ctx* c, const Batch& B, bool first, bool last
     const uint64_t nblk = (uint64_t)cbv * nb;
     CK(ensure(c, c->tcnt, npq * 4));
     CK(ensure(c, c->blk_vis, nblk * 4 + 16));
+    CK(ensure(c, c->blk_aux, nblk * 8 + 16));
     CK(ensure_scan(c, nblk));
-    uint32_t* zr = reinterpret_cast<uint32_t*>(small + SM_ZRANGE);
-    launch_fill_u32(zr, 1, 0xFFFFFFFFu, st);
-    launch_fill_u32(zr + 1, 1, 0u, st);
-    launch_fill_u32(reinterpret_cast<uint32_t*>(small + SM_TOTALS), 4, 0u, st);
     launch_count(nb, n, views, c->means.as<float>(), c->cov3.as<float>(), c->tcnt.as<uint32_t>(),
-                 c->blk_vis.as<uint32_t>(), zr, st);
+                 c->blk_vis.as<uint32_t>(), c->blk_aux.as<uint32_t>(), st);
+    launch_reduce_pairs(c->blk_aux.as<uint32_t>(), nblk, false,
+                        reinterpret_cast<unsigned long long*>(small + SM_ZRANGE), st);
     scan_u32(c->blk_vis.as<uint32_t>(), nblk, small + SM_TOT, c->scan_ws.p, st);
     CK(read_small(c, 0, 4));
     const uint64_t npairs = c->host_small[SM_TOT];
-    const uint32_t zmin = (uint32_t)(c->host_small[SM_ZRANGE] & 0xFFFFFFFFu);
-    const uint32_t zmax = (uint32_t)(c->host_small[SM_ZRANGE] >> 32);
+    const uint32_t zmin = (uint32_t)c->host_small[SM_ZRANGE];
+    const uint32_t zmax = (uint32_t)c->host_small[SM_ZRANGE + 1];
     if (npairs > 0xFFFFFFF0ull) FAIL(c, SLAG_E_CAPACITY, "too many visible pairs in one launch");
-    const int zbits = npairs ? bit_length((uint64_t)(zmax - zmin)) : 0;
+    const int zbits = (npairs && zmax >= zmin) ? bit_length((uint64_t)(zmax - zmin)) : 0;
     const int vbits = bit_length((uint64_t)(nb > 0 ? nb - 1 : 0));
     const uint64_t np = std::max<uint64_t>(npairs, 1);
     CK(ensure(c, c->rec, np * 32));
@@ -363,16 +363,20 @@ static slag_status lift_batch(slag_ctx* c, const Batch& B, bool first, bool last
     CK(ensure(c, c->dval_alt, np * 4));
     CK(ensure(c, c->psz, np * 4 + 16));
     CK(ensure(c, c->pz, np * 4));
+    CK(ensure(c, c->ptc, np * 4));
     CK(ensure(c, c->tcr, np * 4 + 16));
     CK(ensure(c, c->wlen, np * 4));
+    CK(ensure(c, c->pcnt, np * 4));
     CK(ensure(c, c->pair_of_m, npq * 4));
     launch_emit_pairs(nb, n, views, c->means.as<float>(), c->cov3.as<float>(), c->opac.as<float>(),
                       c->tcnt.as<uint32_t>(), c->blk_vis.as<uint32_t>(), c->rec.as<float4>(),
                       c->pgauss.as<uint32_t>(), c->pview.as<uint16_t>(), c->dkey.as<uint64_t>(),
                       c->dval.as<uint32_t>(), c->psz.as<uint32_t>(), c->pz.as<uint32_t>(),
-                      c->sat.as<uint32_t>(), zmin, zbits,
-                      reinterpret_cast<unsigned long long*>(small + SM_TOTALS),
-                      c->rank.as<uint32_t>(), c->pair_of_m.as<uint32_t>(), st);
+                      c->sat.as<uint32_t>(), zmin, zbits, c->blk_aux.as<uint32_t>(),
+                      c->rank.as<uint32_t>(), c->pair_of_m.as<uint32_t>(), c->ptc.as<uint32_t>(),
+                      st);
+    launch_reduce_pairs(c->blk_aux.as<uint32_t>(), nblk, true,
+                        reinterpret_cast<unsigned long long*>(small + SM_TOTALS), st);
     CK(stage_end(c, ST_PROJECT, ev));
 
     uint64_t ni = 0, nparts = 0;
@@ -388,41 +392,48 @@ static slag_status lift_batch(slag_ctx* c, const Batch& B, bool first, bool last
     c->stats.n_intersections += (int64_t)ni;
     c->stats.n_part_slots += (int64_t)nparts;
 
-    const uint32_t* order = nullptr;
     const uint32_t* skey = nullptr;
     const uint32_t* sval = nullptr;
     if (npairs) {
         // depth order of pairs within each view
         CK(stage_begin(c, ST_DEPTH_SORT, &ev));
         CK(ensure(c, c->hist, std::max(radix_hist_bytes(npairs), radix_hist_bytes(ni))));
-        CK(ensure_scan(c, std::max<uint64_t>(npairs, ni / 16 + 4096)));
-        bool alt = radix_sort_u64(c->dkey.as<uint64_t>(), c->dval.as<uint32_t>(),
-                                  c->dkey_alt.as<uint64_t>(), c->dval_alt.as<uint32_t>(), npairs,
-                                  zbits + vbits, c->hist.as<uint32_t>(), c->scan_ws.p, nullptr, st);
-        order = alt ? c->dval_alt.as<uint32_t>() : c->dval.as<uint32_t>();
+        CK(ensure_scan(c, std::max<uint64_t>(npairs, ni / 2 + 4096)));
+        const bool alt = radix_sort_u64(c->dkey.as<uint64_t>(), c->dval.as<uint32_t>(),
+                                        c->dkey_alt.as<uint64_t>(), c->dval_alt.as<uint32_t>(),
+                                        npairs, zbits + vbits, c->hist.as<uint32_t>(),
+                                        c->scan_ws.p, nullptr, st);
+        const uint32_t* order = alt ? c->dval_alt.as<uint32_t>() : c->dval.as<uint32_t>();
         CK(stage_end(c, ST_DEPTH_SORT, ev));
 
-        // (tile, pair) entries in depth order
+        // (tile, pair, part slot) entries in depth order; part slots pair-major
         CK(stage_begin(c, ST_BIN, &ev));
+        HC(c, hipMemcpyAsync(c->pcnt.p, c->psz.p, npairs * 4, hipMemcpyDeviceToDevice, st));
+        scan_u32(c->psz.as<uint32_t>(), npairs, nullptr, c->scan_ws.p, st);
         CK(ensure(c, c->ikey, ni * 4));
         CK(ensure(c, c->ikey_alt, ni * 4));
         CK(ensure(c, c->ival, ni * 4));
         CK(ensure(c, c->ival_alt, ni * 4));
-        launch_rank_tiles(npairs, order, c->rec.as<float4>(), c->tcr.as<uint32_t>(), st);
+        CK(ensure(c, c->islot, ni * 4));
+        CK(ensure(c, c->islot_alt, ni * 4));
+        launch_rank_tiles(npairs, order, c->ptc.as<uint32_t>(), c->tcr.as<uint32_t>(), st);
         scan_u32(c->tcr.as<uint32_t>(), npairs, nullptr, c->scan_ws.p, st);
         launch_emit_isect(npairs, order, c->rec.as<float4>(), c->pview.as<uint16_t>(), views,
-                          c->tcr.as<uint32_t>(), c->ikey.as<uint32_t>(), c->ival.as<uint32_t>(),
+                          c->tcr.as<uint32_t>(), c->psz.as<uint32_t>(), c->sat.as<uint32_t>(),
+                          c->ikey.as<uint32_t>(), c->ival.as<uint32_t>(), c->islot.as<uint32_t>(),
                           st);
         CK(stage_end(c, ST_BIN, ev));
 
         // stable sort by tile -> per-tile lists in (depth, Gaussian) order
         CK(stage_begin(c, ST_TILE_SORT, &ev));
-        bool alt2 = radix_sort_u32(c->ikey.as<uint32_t>(), c->ival.as<uint32_t>(),
-                                   c->ikey_alt.as<uint32_t>(), c->ival_alt.as<uint32_t>(), ni,
-                                   bit_length(B.nbuckets > 0 ? B.nbuckets - 1 : 0),
-                                   c->hist.as<uint32_t>(), c->scan_ws.p, nullptr, st);
+        const bool alt2 = radix_sort_u32_v2(
+            c->ikey.as<uint32_t>(), c->ival.as<uint32_t>(), c->islot.as<uint32_t>(),
+            c->ikey_alt.as<uint32_t>(), c->ival_alt.as<uint32_t>(), c->islot_alt.as<uint32_t>(), ni,
+            bit_length(B.nbuckets > 0 ? B.nbuckets - 1 : 0), c->hist.as<uint32_t>(), c->scan_ws.p,
+            st);
         skey = alt2 ? c->ikey_alt.as<uint32_t>() : c->ikey.as<uint32_t>();
         sval = alt2 ? c->ival_alt.as<uint32_t>() : c->ival.as<uint32_t>();
+        const uint32_t* sslot = alt2 ? c->islot_alt.as<uint32_t>() : c->islot.as<uint32_t>();
         CK(ensure(c, c->bstart, (size_t)B.nbuckets * 4 + 4));
         CK(ensure(c, c->bend, (size_t)B.nbuckets * 4 + 4));
         launch_fill_u32(c->bstart.as<uint32_t>(), B.nbuckets, 0u, st);
@@ -430,26 +441,17 @@ static slag_status lift_batch(slag_ctx* c, const Batch& B, bool first, bool last
         launch_bucket_ranges(ni, skey, c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(), st);
         CK(stage_end(c, ST_TILE_SORT, ev));
 
-        // part slots: pair-major offsets (slot counts kept), zeroed; the tile
-        // lists' records gathered into list order
+        // part slots, zeroed
         CK(stage_begin(c, ST_PART_PREP, &ev));
-        CK(ensure(c, c->pcnt, np * 4));
-        HC(c, hipMemcpyAsync(c->pcnt.p, c->psz.p, npairs * 4, hipMemcpyDeviceToDevice, st));
-        scan_u32(c->psz.as<uint32_t>(), npairs, nullptr, c->scan_ws.p, st);
         CK(ensure(c, c->part, std::max<uint64_t>(nparts, 1) * 8));
         launch_fill_u32(c->part.as<uint32_t>(), 2 * nparts, 0u, st);
-        CK(ensure(c, c->srec, ni * 32));
-        CK(ensure(c, c->soff, ni * 4));
-        launch_gather_lists(ni, skey, sval, B.bucket_view.as<uint32_t>(), views,
-                            c->rec.as<float4>(), c->psz.as<uint32_t>(), c->sat.as<uint32_t>(),
-                            c->srec.as<float4>(), c->soff.as<uint32_t>(), st);
         CK(stage_end(c, ST_PART_PREP, ev));
 
         CK(stage_begin(c, ST_COMPOSITE, &ev));
         launch_composite(count, B.nbuckets, B.bucket_view.as<uint32_t>(), views,
-                         c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(), c->srec.as<float4>(),
-                         c->soff.as<uint32_t>(), c->ns_tile.as<uint32_t>(),
-                         c->segl.as<uint16_t>(), c->ids.as<int32_t>(), c->part.as<uint2>(),
+                         c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(), sval, sslot,
+                         c->rec.as<float4>(), c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
+                         c->ids.as<int32_t>(), c->part.as<uint2>(),
                          reinterpret_cast<unsigned long long*>(small + SM_COUNTERS), st);
         CK(stage_end(c, ST_COMPOSITE, ev));
 
@@ -531,7 +533,7 @@ void slag_destroy(slag_ctx* c)
                       &c->dkey_alt, &c->dval, &c->dval_alt, &c->psz, &c->pz, &c->tcr, &c->wlen,
                       &c->ikey, &c->ikey_alt, &c->ival, &c->ival_alt, &c->bstart, &c->bend,
                       &c->part, &c->wrow, &c->perm, &c->rank, &c->pair_of_m, &c->pcnt,
-                      &c->srec, &c->soff};
+                      &c->islot, &c->islot_alt, &c->ptc, &c->blk_aux};
     for (DevBuf* b : bufs) release(*b);
     for (auto& b : c->plan) { release(b.views); release(b.bucket_view); }
     for (auto& e : c->events) { hipEventDestroy(e.a); hipEventDestroy(e.b); }

@@ -42,9 +42,12 @@ void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* mea
                        const float* cov3, const float* opac, uint32_t* tcnt_pairof,
                        const uint32_t* blk_off, float4* rec, uint32_t* pgauss, uint16_t* pview,
                        uint64_t* dkey, uint32_t* dval, uint32_t* psz, uint32_t* pz,
-                       const uint32_t* sat, uint32_t zmin, int zbits,
-                       unsigned long long* totals, const uint32_t* rank, uint32_t* pair_of_m,
-                       hipStream_t st);
+                       const uint32_t* sat, uint32_t zmin, int zbits, uint32_t* blk_tot,
+                       const uint32_t* rank, uint32_t* pair_of_m, uint32_t* ptc, hipStream_t st);
+// out[0..1] = (min of even, max of odd) entries of in[2 * npairs], or their
+// 64-bit sums in sum mode; one block
+void launch_reduce_pairs(const uint32_t* in, uint64_t npairs, bool sum_mode,
+                         unsigned long long* out, hipStream_t st);
 // Morton order of the Gaussian means: bounding box (order-preserving integer
 // images in box6[0..2] = min, [3..5] = max), 63-bit keys, inverse permutation
 void launch_bbox(int64_t n, const float* means, uint32_t* box6, hipStream_t st);
@@ -66,11 +69,16 @@ bool radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t
                     uint64_t n, int nbits, uint32_t* hist, void* scan_ws, uint64_t* tot,
                     hipStream_t st);
 
-void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const float4* rec, uint32_t* tcr,
+bool radix_sort_u32_v2(uint32_t* keys, uint32_t* vals, uint32_t* aux, uint32_t* keys_alt,
+                       uint32_t* vals_alt, uint32_t* aux_alt, uint64_t n, int nbits,
+                       uint32_t* hist, void* scan_ws, hipStream_t st);
+
+void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const uint32_t* ptc, uint32_t* tcr,
                        hipStream_t st);
 void launch_emit_isect(uint64_t npairs, const uint32_t* order, const float4* rec,
                        const uint16_t* pview, const ViewDev* views, const uint32_t* ioff,
-                       uint32_t* ikey, uint32_t* ival, hipStream_t st);
+                       const uint32_t* part_base, const uint32_t* sat, uint32_t* ikey,
+                       uint32_t* ival, uint32_t* islot, hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
 void launch_bucket_ranges(uint64_t ni, const uint32_t* ikey, uint32_t* bstart, uint32_t* bend,
                           hipStream_t st);
@@ -79,15 +87,11 @@ void launch_tile_segs(uint32_t nbuckets, const uint32_t* bucket_view, const View
                       const int32_t* ids, uint32_t* ns_tile, uint16_t* segl, hipStream_t st);
 void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t* sat,
                 hipStream_t st);
-void launch_gather_lists(uint64_t ni, const uint32_t* skey, const uint32_t* sval,
-                         const uint32_t* bucket_view, const ViewDev* views, const float4* rec,
-                         const uint32_t* part_base, const uint32_t* sat, float4* srec,
-                         uint32_t* soff, hipStream_t st);
 void launch_composite(bool count, uint32_t nbuckets, const uint32_t* bucket_view,
                       const ViewDev* views, const uint32_t* bstart, const uint32_t* bend,
-                      const float4* srec, const uint32_t* soff, const uint32_t* ns_tile,
-                      const uint16_t* segl, const int32_t* ids, uint2* part,
-                      unsigned long long* counters, hipStream_t st);
+                      const uint32_t* ival, const uint32_t* islot, const float4* rec,
+                      const uint32_t* ns_tile, const uint16_t* segl, const int32_t* ids,
+                      uint2* part, unsigned long long* counters, hipStream_t st);
 void launch_merge(uint64_t npairs, const uint16_t* pview, const ViewDev* views,
                   const uint32_t* part_base, const uint32_t* pcnt, const uint2* part,
                   uint2* wrow, uint32_t* wlen, unsigned long long* nnz, hipStream_t st);
