@@ -360,10 +360,14 @@ static int composite_pixel(const view_ctx* vc, const int32_t* cand, int64_t nc,
         if (!count_box_only || (mo->vis && ix >= mo->x0 && ix <= mo->x1 && iy >= mo->y0 && iy <= mo->y1))
             (*n_q)++;
         double alpha = alpha_at(p, px, py);
+        /* upstream flips change T here by a relative amount of at most delta
+         * (to first order), so a flipped decision here moves at most
+         * alpha T (1 + delta) */
+        const double grow = 1.0 + (delta < 1.0 ? delta : 1.0);
         if (alpha < D_AMIN) {
             if (alpha >= D_AMIN * (1.0 - EPS_ALPHA)) {
                 (*n_unc)++;
-                if (seg >= 0 && cbuf_push(out, g, seg, 0.0, alpha * T)) return -1;
+                if (seg >= 0 && cbuf_push(out, g, seg, 0.0, alpha * T * grow)) return -1;
                 delta += alpha;
             }
             continue;
@@ -375,11 +379,11 @@ static int composite_pixel(const view_ctx* vc, const int32_t* cand, int64_t nc,
         if (near_a || near_t) (*n_unc)++;
         if (Tn < D_TMIN) {
             if (near_t && seg >= 0) {
-                if (cbuf_push(out, g, seg, 0.0, alpha * T)) return -1;
+                if (cbuf_push(out, g, seg, 0.0, alpha * T * grow)) return -1;
                 for (int64_t h = k + 1; h < nc; h++) {
                     double ah = alpha_at(&vc->P[cand[h]], px, py);
                     if (ah >= D_AMIN * (1.0 - EPS_ALPHA)) {
-                        if (cbuf_push(out, cand[h], seg, 0.0, ah * Tn)) return -1;
+                        if (cbuf_push(out, cand[h], seg, 0.0, ah * Tn * grow)) return -1;
                         break;
                     }
                 }
@@ -388,8 +392,8 @@ static int composite_pixel(const view_ctx* vc, const int32_t* cand, int64_t nc,
         }
         double w = alpha * T;
         double u = w * (delta < 1.0 ? delta : 1.0);
-        if (near_a) u = w;
-        if (near_t) { u = w; delta = 1.0; }
+        if (near_a) u = w * grow;
+        if (near_t) { u = w * grow; delta = 1.0; }
         (*n_c)++;
         sumw += w;
         if (seg >= 0 && cbuf_push(out, g, seg, w, u)) return -1;
