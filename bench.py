@@ -87,6 +87,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0 = skip)")
     ap.add_argument("--no-count", action="store_true", help="skip the counting lift")
+    ap.add_argument("--eager", action="store_true", help="time eager lifts instead of graph replays")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
+                    help="also run one plain device copy of BYTES (read) + BYTES (write), "
+                         "to scale hardware traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the lift is not sharded "
@@ -113,31 +117,53 @@ def main():
             n_tile_tests = st["n_tile_tests"]
         _log(f"contributions {n_contrib}, in-box tests {n_tests}, tile tests {n_tile_tests}")
 
-    L = slag.Lifter(0, flags=slag.SLAG_FLAG_PROFILE)
+    if args.copy_calib > 0:
+        # elementwise kernel reading and writing exactly copy_calib bytes
+        x = torch.ones(args.copy_calib // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        _log(f"copy calibration: {args.copy_calib} bytes read and written")
+        del x, y
+
+    # timed region: graph replays of the whole lift (the first lift runs
+    # eagerly and captures the launch sequence; warm-up covers it)
+    flags = slag.SLAG_FLAG_PROFILE | (0 if args.eager else slag.SLAG_FLAG_GRAPH)
+    L = slag.Lifter(0, flags=flags)
     L.set_scene(scene, device_tensors=True)
-    for _ in range(args.warmup):
+    for _ in range(max(args.warmup, 1)):
         L.lift()
     L.embeddings()
     torch.cuda.synchronize()
-    stage_ms = {}
     ev_total = 0.0
     t0 = time.perf_counter()
     for _ in range(args.steps):
         L.lift()
-        st = L.stats()          # synchronises; HIP-event stage times of this lift
-        ev_total += st["ms_total"]
-        for k, v in st["ms_stage"].items():
-            stage_ms[k] = stage_ms.get(k, 0.0) + v
+        ev_total += L.stats()["ms_total"]   # synchronises; HIP events around the lift
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
-    stage_ms = {k: v / args.steps for k, v in stage_ms.items()}
-    _log("stage ms:", json.dumps({k: round(v, 4) for k, v in stage_ms.items()}))
-    _log(f"step {ms_step:.3f} ms wall, {ev_total / args.steps:.3f} ms HIP events")
+    _log(f"step {ms_step:.3f} ms wall, {ev_total / args.steps:.3f} ms HIP events "
+         f"({'eager' if args.eager else 'graph replay'})")
     E, den = L.embeddings()
     assert np.isfinite(E).all()
     info = L.stats()
     L.close()
+
+    # per-stage HIP events (same kernels, launched eagerly on the library's
+    # stream; a graph replay records no per-stage events)
+    stage_ms = {}
+    with slag.Lifter(0, flags=slag.SLAG_FLAG_PROFILE) as Lp:
+        Lp.set_scene(scene, device_tensors=True)
+        Lp.lift()
+        Lp.stats()
+        for _ in range(args.steps):
+            Lp.lift()
+            for k, v in Lp.stats()["ms_stage"].items():
+                stage_ms[k] = stage_ms.get(k, 0.0) + v
+    stage_ms = {k: v / args.steps for k, v in stage_ms.items()}
+    _log("stage ms:", json.dumps({k: round(v, 4) for k, v in stage_ms.items()}))
 
     dom = max(stage_ms, key=stage_ms.get)
     comp_ms = stage_ms.get("composite", 0.0)
@@ -176,6 +202,7 @@ def main():
         "n_visible_pairs": info["n_visible_pairs"],
         "n_intersections": info["n_intersections"],
         "ms_per_step_hip_events": round(ev_total / args.steps, 4),
+        "launch": "eager" if args.eager else "hip graph replay",
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -65,7 +65,12 @@ typedef struct {
 enum {
     SLAG_FLAG_PROFILE = 1,      /* record per-stage HIP events (slag_get_stats) */
     SLAG_FLAG_COUNT = 2,        /* count blends and tests (slag_get_stats) */
-    SLAG_FLAG_KEEP_DEBUG = 4    /* keep the last view batch's tile lists and W rows */
+    SLAG_FLAG_KEEP_DEBUG = 4,   /* keep the last view batch's tile lists and W rows */
+    SLAG_FLAG_GRAPH = 8         /* replay the lift as one HIP graph while the inputs are
+                                   unchanged: the first lift after an input change runs
+                                   eagerly (sizing every buffer) and captures its launch
+                                   sequence; later lifts launch the graph.  Replays record
+                                   ms_total but no per-stage times. */
 };
 
 typedef struct {
@@ -104,8 +109,8 @@ const char* slag_last_error(const slag_ctx* ctx);
  * means_xyz[N][3], scales_xyz[N][3] (linear standard deviations, > 0),
  * quats_wxyz[N][4] (rotation, any non-zero norm), opacity[N] in (0, 1].
  * All FP32.  Pointers are `where`-resident and are copied before return.
- * n = 0 is valid.  Non-finite values make the next lift fail with
- * SLAG_E_INVALID_ARG. */
+ * n = 0 is valid.  Non-finite or out-of-range values are rejected here
+ * with SLAG_E_INVALID_ARG (a validation kernel and one synchronisation). */
 slag_status slag_set_gaussians(slag_ctx* ctx, int64_t n, const float* means_xyz,
                                const float* scales_xyz, const float* quats_wxyz,
                                const float* opacity, slag_mem where);
@@ -116,7 +121,7 @@ slag_status slag_set_cameras(slag_ctx* ctx, int32_t n_views, const slag_camera* 
 
 /* The masks M_j of view `view` as one segment id per pixel: ids[H][W]
  * row-major int32, -1 = pixel in no mask, else 0 <= id < n_seg.  Copied.
- * Ids out of range make the next lift fail with SLAG_E_INVALID_ARG. */
+ * Ids out of range are rejected here with SLAG_E_INVALID_ARG. */
 slag_status slag_set_segments(slag_ctx* ctx, int32_t view, const int32_t* ids, int32_t n_seg,
                               slag_mem where);
 
@@ -126,12 +131,12 @@ slag_status slag_set_features(slag_ctx* ctx, int32_t d, slag_dtype dtype, const 
                               slag_mem where);
 
 /* Run the lift over every view.  Stream-ordered; returns once the work is
- * enqueued (and after any host synchronisation needed for sizing). */
+ * enqueued (and after any host synchronisation needed for sizing: two per
+ * view batch in an eager lift, none in a graph replay). */
 slag_status slag_lift(slag_ctx* ctx);
 
 /* E_GAUSSIAN[N][d] (FP32) in input Gaussian order and, if `den` is not NULL,
- * the weight sums den[N] (FP32).  Synchronises the stream.  Reports device-
- * side validation failures of the last lift. */
+ * the weight sums den[N] (FP32).  Synchronises the stream. */
 slag_status slag_get_embeddings(slag_ctx* ctx, float* out, float* den, slag_mem where);
 
 slag_status slag_get_stats(slag_ctx* ctx, slag_stats* stats);

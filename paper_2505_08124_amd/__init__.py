@@ -23,7 +23,7 @@ SLAG_OK, SLAG_E_INVALID_ARG, SLAG_E_OUT_OF_MEMORY, SLAG_E_DEVICE, SLAG_E_STATE, 
     SLAG_E_CAPACITY, SLAG_E_NOT_SUPPORTED = range(7)
 SLAG_HOST, SLAG_DEVICE = 0, 1
 SLAG_F32, SLAG_BF16 = 0, 1
-SLAG_FLAG_PROFILE, SLAG_FLAG_COUNT, SLAG_FLAG_KEEP_DEBUG = 1, 2, 4
+SLAG_FLAG_PROFILE, SLAG_FLAG_COUNT, SLAG_FLAG_KEEP_DEBUG, SLAG_FLAG_GRAPH = 1, 2, 4, 8
 
 STATUS_NAMES = {0: "SLAG_OK", 1: "SLAG_E_INVALID_ARG", 2: "SLAG_E_OUT_OF_MEMORY",
                 3: "SLAG_E_DEVICE", 4: "SLAG_E_STATE", 5: "SLAG_E_CAPACITY",
@@ -51,10 +51,20 @@ class slag_stats(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class slag_train_cfg(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("batch_rows", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("reserved", ctypes.c_int64 * 4)]
+
+
 EXPORTS = ["slag_create", "slag_destroy", "slag_last_error", "slag_set_gaussians",
            "slag_set_cameras", "slag_set_segments", "slag_set_features", "slag_lift",
            "slag_get_embeddings", "slag_get_stats", "slag_stage_name", "slag_debug_tile_lists",
-           "slag_debug_weights"]
+           "slag_debug_weights",
+           # include/slag_codec.h
+           "slag_codec_init", "slag_codec_get_params", "slag_codec_clear_pool",
+           "slag_codec_set_pool", "slag_codec_add_lift_rows", "slag_codec_pool_size",
+           "slag_codec_loss_grad", "slag_codec_train", "slag_lift_codec", "slag_get_codes"]
 
 _lib_handle = None
 
@@ -85,6 +95,17 @@ def lib():
     L.slag_stage_name.restype = ctypes.c_char_p
     L.slag_debug_tile_lists.argtypes = [P, I32, P, P, P, I64, ctypes.POINTER(I64)]
     L.slag_debug_weights.argtypes = [P, I32, P, P, P, I64, ctypes.POINTER(I64)]
+    L.slag_codec_init.argtypes = [P, I32, I32, I32, I32, P, I32]
+    L.slag_codec_get_params.argtypes = [P, P, I32]
+    L.slag_codec_clear_pool.argtypes = [P]
+    L.slag_codec_set_pool.argtypes = [P, I64, P, I64, P, P, P, P, I32]
+    L.slag_codec_add_lift_rows.argtypes = [P, I64, ctypes.c_uint64, ctypes.POINTER(I64)]
+    L.slag_codec_pool_size.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64),
+                                       ctypes.POINTER(I64)]
+    L.slag_codec_loss_grad.argtypes = [P, I64, I64, ctypes.POINTER(ctypes.c_float), P, I32]
+    L.slag_codec_train.argtypes = [P, ctypes.POINTER(slag_train_cfg), P]
+    L.slag_lift_codec.argtypes = [P]
+    L.slag_get_codes.argtypes = [P, P, I32]
     for f in EXPORTS:
         if f not in ("slag_destroy", "slag_last_error", "slag_stage_name"):
             getattr(L, f).restype = I32
@@ -198,6 +219,69 @@ def slag_debug_weights(ctx, view: int):
     return g, s, w
 
 
+# ---------------------------------------------------------------- codec (slag_codec.h)
+
+def codec_param_count(d: int, hidden: int, k: int) -> int:
+    return hidden * d + hidden + k * hidden + k + hidden * k + hidden + d * hidden + d
+
+
+def slag_codec_init(ctx, d: int, hidden: int, k: int, precision: int, params):
+    p, w = _ptr(params)
+    _check(ctx, lib().slag_codec_init(ctx, d, hidden, k, precision, p, w))
+
+
+def slag_codec_get_params(ctx, out):
+    p, w = _ptr(out)
+    _check(ctx, lib().slag_codec_get_params(ctx, p, w))
+
+
+def slag_codec_clear_pool(ctx):
+    _check(ctx, lib().slag_codec_clear_pool(ctx))
+
+
+def slag_codec_set_pool(ctx, feats, row_ptr, col, w, target):
+    pf, where = _ptr(feats)
+    _check(ctx, lib().slag_codec_set_pool(ctx, int(feats.shape[0]), pf, int(target.shape[0]),
+                                          _ptr(row_ptr)[0], _ptr(col)[0], _ptr(w)[0],
+                                          _ptr(target)[0], where))
+
+
+def slag_codec_add_lift_rows(ctx, max_rows: int, seed: int) -> int:
+    added = ctypes.c_int64(0)
+    _check(ctx, lib().slag_codec_add_lift_rows(ctx, int(max_rows), int(seed), ctypes.byref(added)))
+    return added.value
+
+
+def slag_codec_pool_size(ctx):
+    a, b, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(ctx, lib().slag_codec_pool_size(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def slag_codec_loss_grad(ctx, row0: int, n_rows: int, grad=None) -> float:
+    loss = ctypes.c_float(0.0)
+    pg, w = _ptr(grad)
+    _check(ctx, lib().slag_codec_loss_grad(ctx, int(row0), int(n_rows), ctypes.byref(loss), pg, w))
+    return loss.value
+
+
+def slag_codec_train(ctx, steps: int, batch_rows: int = 0, lr: float = 1e-3, beta1: float = 0.9,
+                     beta2: float = 0.999, eps: float = 1e-8) -> np.ndarray:
+    cfg = slag_train_cfg(int(steps), int(batch_rows), lr, beta1, beta2, eps)
+    hist = np.zeros(max(int(steps), 1), np.float32)
+    _check(ctx, lib().slag_codec_train(ctx, ctypes.byref(cfg), hist.ctypes.data_as(ctypes.c_void_p)))
+    return hist[:steps]
+
+
+def slag_lift_codec(ctx):
+    _check(ctx, lib().slag_lift_codec(ctx))
+
+
+def slag_get_codes(ctx, out):
+    p, w = _ptr(out)
+    _check(ctx, lib().slag_get_codes(ctx, p, w))
+
+
 # ---------------------------------------------------------------- convenience
 
 class Lifter:
@@ -258,6 +342,14 @@ class Lifter:
 
     def stats(self) -> dict:
         return slag_get_stats(self.ctx)
+
+    def lift_codec(self):
+        slag_lift_codec(self.ctx)
+
+    def codes(self, k: int):
+        C = np.empty((self.n, k), np.float32)
+        slag_get_codes(self.ctx, C)
+        return C
 
     def tile_lists(self, view: int):
         return slag_debug_tile_lists(self.ctx, view)

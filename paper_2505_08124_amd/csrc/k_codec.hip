@@ -1,0 +1,527 @@
+// Learned segment-feature codec: encoder D -> H -> k and decoder k -> H -> D
+// (tanh-form GELU), trained through the lift's mixing (each Gaussian's code
+// is the weight-normalised sum of its segments' codes; the loss is the mean
+// of 1 - cos(decoded code, plain-lift embedding)), and used by the codec lift.
+// This is an extension of the paper's lift, which aggregates the full
+// features; the aggregation of codes is the same weighted average.
+//
+// Products run on the matrix cores: v_mfma_f32_16x16x32_bf16 with operands
+// rounded to bf16 (FP32 master weights, FP32 accumulation), or
+// v_mfma_f32_16x16x4f32 in full FP32 (used to check gradients).
+#include "slag_internal.h"
+
+namespace slag {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int GT = 64;     // output tile edge per workgroup
+constexpr int GK = 32;     // K per staged chunk
+
+constexpr float kGeluC = 0.7978845608028654f;   // sqrt(2 / pi)
+constexpr float kGeluA = 0.044715f;
+
+__device__ __forceinline__ float gelu_f(float x)
+{
+    const float u = kGeluC * (x + kGeluA * x * x * x);
+    return 0.5f * x * (1.0f + tanhf(u));
+}
+
+__device__ __forceinline__ float gelu_grad_f(float x)
+{
+    const float u = kGeluC * (x + kGeluA * x * x * x);
+    const float th = tanhf(u);
+    return 0.5f * (1.0f + th) + 0.5f * x * (1.0f - th * th) * kGeluC * (1.0f + 3.0f * kGeluA * x * x);
+}
+
+__device__ __forceinline__ float load_elem(const float* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float load_elem(const uint16_t* p, int64_t i)
+{
+    return __uint_as_float((uint32_t)p[i] << 16);
+}
+
+__device__ __forceinline__ float epilogue(float v, int64_t row, int col, int64_t idx,
+                                          const GemmEpi& e)
+{
+    if (e.bias) v += e.bias[col];
+    if (e.zsave) e.zsave[idx] = v;
+    if (e.act == GEMM_GELU) v = gelu_f(v);
+    else if (e.act == GEMM_GELU_BWD) v *= gelu_grad_f(e.aux[idx]);
+    if (e.rowmask && !(e.rowmask[row] > 0.0f)) v = 0.0f;
+    return v;
+}
+
+// C[M][N] (row-major, leading dimension ldc) = op(A)[M][K] op(B)[K][N] with
+// the epilogue; A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn].
+// blockIdx.z selects a slice of K; with more than one slice the raw sums go
+// to out + z M N (row-major, leading dimension N) and k_gemm_reduce finishes.
+template <bool BF16, typename TA>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __restrict__ A,
+                                              int64_t sam, int64_t sak,
+                                              const float* __restrict__ B, int64_t sbk,
+                                              int64_t sbn, int kper, float* __restrict__ out,
+                                              int64_t ldc, GemmEpi epi)
+{
+    __shared__ float As[GT][GK + 1];
+    __shared__ float Bs[GK][GT + 1];
+    const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+    const int64_t m0 = (int64_t)blockIdx.y * GT;
+    const int n0 = blockIdx.x * GT;
+    const int kb = blockIdx.z * kper, ke = min(K, kb + kper);
+    const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+    const int li = lane & 15, lq = lane >> 4;
+    const bool a_kfast = sak == 1, b_nfast = sbn == 1;
+
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = kb; k0 < ke; k0 += GK) {
+#pragma unroll
+        for (int i = 0; i < GT * GK / 256; i++) {
+            const int e = t + 256 * i;
+            const int mm = a_kfast ? (e >> 5) : (e & 63);
+            const int kk = a_kfast ? (e & 31) : (e >> 6);
+            const int64_t gm = m0 + mm;
+            const int gk = k0 + kk;
+            As[mm][kk] = (gm < M && gk < ke) ? load_elem(A, gm * sam + (int64_t)gk * sak) : 0.0f;
+            const int nn = b_nfast ? (e & 63) : (e >> 5);
+            const int kb2 = b_nfast ? (e >> 6) : (e & 31);
+            const int gn = n0 + nn, gk2 = k0 + kb2;
+            Bs[kb2][nn] = (gn < N && gk2 < ke) ? B[(int64_t)gk2 * sbk + (int64_t)gn * sbn] : 0.0f;
+        }
+        __syncthreads();
+        if constexpr (BF16) {
+            bf16x8 a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    a[i][j] = (__bf16)As[wm + 16 * i + li][8 * lq + j];
+                    b[i][j] = (__bf16)Bs[8 * lq + j][wn + 16 * i + li];
+                }
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int j = 0; j < 2; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < GK / 4; kk++) {
+                float a[2], b[2];
+#pragma unroll
+                for (int i = 0; i < 2; i++) {
+                    a[i] = As[wm + 16 * i + li][4 * kk + lq];
+                    b[i] = Bs[4 * kk + lq][wn + 16 * i + li];
+                }
+#pragma unroll
+                for (int i = 0; i < 2; i++)
+#pragma unroll
+                    for (int j = 0; j < 2; j++)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+
+    const bool split = gridDim.z > 1;
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int64_t row = m0 + wm + 16 * i + 4 * lq + r;
+                const int col = n0 + wn + 16 * j + li;
+                if (row >= M || col >= N) continue;
+                if (split) {
+                    out[((int64_t)blockIdx.z * M + row) * N + col] = acc[i][j][r];
+                } else {
+                    const int64_t idx = row * ldc + col;
+                    out[idx] = epilogue(acc[i][j][r], row, col, idx, epi);
+                }
+            }
+}
+
+// Sum of the K slices in slice order, then the epilogue.
+__global__ __launch_bounds__(256) void k_gemm_reduce(int M, int N, int splits,
+                                                     const float* __restrict__ part,
+                                                     float* __restrict__ out, int64_t ldc,
+                                                     GemmEpi epi)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)M * N) return;
+    const int64_t row = i / N;
+    const int col = (int)(i - row * N);
+    float s = 0.0f;
+    for (int z = 0; z < splits; z++) s += part[(int64_t)z * M * N + i];
+    const int64_t idx = row * ldc + col;
+    out[idx] = epilogue(s, row, col, idx, epi);
+}
+
+// Column sums of X[R][N] over row slices (partials [slices][N]).
+__global__ __launch_bounds__(256) void k_colsum_part(int R, int N, const float* __restrict__ X,
+                                                     int rows_per, float* __restrict__ part)
+{
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    if (col >= N) return;
+    const int r0 = blockIdx.y * rows_per, r1 = min(R, r0 + rows_per);
+    float s = 0.0f;
+    for (int r = r0; r < r1; r++) s += X[(int64_t)r * N + col];
+    part[(int64_t)blockIdx.y * N + col] = s;
+}
+
+__global__ __launch_bounds__(256) void k_colsum_fin(int N, int slices, const float* __restrict__ part,
+                                                    float* __restrict__ out)
+{
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    if (col >= N) return;
+    float s = 0.0f;
+    for (int z = 0; z < slices; z++) s += part[(int64_t)z * N + col];
+    out[col] = s;
+}
+
+// code[r][c] = sum_j w[j] C[col[j]][c], j in [row_ptr[r], row_ptr[r + 1]).
+__global__ __launch_bounds__(256) void k_mix(int R, int k, const uint32_t* __restrict__ row_ptr,
+                                             const uint32_t* __restrict__ col,
+                                             const float* __restrict__ w,
+                                             const float* __restrict__ C, float* __restrict__ code)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)R * k) return;
+    const int r = (int)(i / k), c = (int)(i - (int64_t)r * k);
+    float s = 0.0f;
+    for (uint32_t j = row_ptr[r]; j < row_ptr[r + 1]; j++) s += w[j] * C[(int64_t)col[j] * k + c];
+    code[i] = s;
+}
+
+// dC[col[j]][c] += w[j] dcode[r][c] (training only; float atomics).
+__global__ __launch_bounds__(256) void k_mix_bwd(int R, int k, const uint32_t* __restrict__ row_ptr,
+                                                 const uint32_t* __restrict__ col,
+                                                 const float* __restrict__ w,
+                                                 const float* __restrict__ dcode,
+                                                 float* __restrict__ dC)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)R * k) return;
+    const int r = (int)(i / k), c = (int)(i - (int64_t)r * k);
+    const float g = dcode[i];
+    for (uint32_t j = row_ptr[r]; j < row_ptr[r + 1]; j++)
+        atomicAdd(&dC[(int64_t)col[j] * k + c], w[j] * g);
+}
+
+// Per row (one wave each): loss_r = 1 - cos(y_r, t_r) and
+// dy_r = -(t_r / (|y||t|) - cos y_r / |y|^2) / R.  Per-block loss sums.
+__global__ __launch_bounds__(256) void k_cos_loss(int R, int d, const float* __restrict__ y,
+                                                  const float* __restrict__ tg, float inv_r,
+                                                  float* __restrict__ dy,
+                                                  float* __restrict__ loss_part)
+{
+    __shared__ float s_l[4];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + wv;
+    float l = 0.0f;
+    if (r < R) {
+        const float* yr = y + r * d;
+        const float* tr = tg + r * d;
+        float yy = 0.f, tt = 0.f, yt = 0.f;
+        for (int c = lane; c < d; c += 64) {
+            const float a = yr[c], b = tr[c];
+            yy += a * a;
+            tt += b * b;
+            yt += a * b;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            yy += __shfl_xor(yy, o, 64);
+            tt += __shfl_xor(tt, o, 64);
+            yt += __shfl_xor(yt, o, 64);
+        }
+        const float ny = sqrtf(yy), nt = sqrtf(tt);
+        const bool ok = ny > 0.0f && nt > 0.0f;
+        const float cs = ok ? yt / (ny * nt) : 0.0f;
+        const float at = ok ? inv_r / (ny * nt) : 0.0f, ay = ok ? inv_r * cs / yy : 0.0f;
+        for (int c = lane; c < d; c += 64) dy[r * d + c] = -(at * tr[c] - ay * yr[c]);
+        l = 1.0f - cs;
+    }
+    if (lane == 0) s_l[wv] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = s_l[0] + s_l[1] + s_l[2] + s_l[3];
+}
+
+// Mean of the per-block loss sums (one block; fixed order).
+__global__ __launch_bounds__(256) void k_loss_fin(int nb, const float* __restrict__ part,
+                                                  float inv_r, float* __restrict__ out)
+{
+    __shared__ float s[256];
+    float a = 0.0f;
+    for (int i = threadIdx.x; i < nb; i += 256) a += part[i];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0] * inv_r;
+}
+
+// Adam with bias correction; step is 1-based.
+__global__ __launch_bounds__(256) void k_adam(int64_t n, float* __restrict__ p,
+                                              const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, float lr, float b1, float b2,
+                                              float eps, float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// BF16 (bits) or FP32 rows to FP32.
+__global__ __launch_bounds__(256) void k_to_f32(int64_t n, const void* __restrict__ src, int bf16,
+                                                float* __restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    dst[i] = bf16 ? __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(src)[i] << 16)
+                  : reinterpret_cast<const float*>(src)[i];
+}
+
+// ---- training rows from a plain lift ----
+
+// SplitMix64 (Steele, Lea, Flood 2014) of seed + index: the row sampler.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x)
+{
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// flag[g] = 1 for Gaussians with weight whose hash falls under the threshold.
+__global__ __launch_bounds__(256) void k_pick_rows(int64_t n, const float* __restrict__ den,
+                                                   uint64_t seed, uint32_t thresh,
+                                                   uint32_t* __restrict__ flag)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= n) return;
+    const uint32_t h = (uint32_t)(splitmix64(seed + (uint64_t)g) >> 32);
+    flag[g] = (den[g] > 0.0f && h < thresh) ? 1u : 0u;
+}
+
+// Row length of each picked Gaussian (rows beyond max_rows are dropped):
+// the merged weight-row lengths of its pairs over the launch's views.
+__global__ __launch_bounds__(256) void k_row_len(int64_t n, int nb, const uint32_t* __restrict__ flag,
+                                                 const uint32_t* __restrict__ ridx,
+                                                 uint32_t max_rows,
+                                                 const uint32_t* __restrict__ rank,
+                                                 const uint32_t* __restrict__ pair_of_m,
+                                                 const uint32_t* __restrict__ wlen,
+                                                 uint32_t* __restrict__ len, uint32_t* __restrict__ gid)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= n || !flag[g] || ridx[g] >= max_rows) return;
+    const uint32_t q = rank[g];
+    uint32_t l = 0;
+    for (int v = 0; v < nb; v++) {
+        const uint32_t p = pair_of_m[(int64_t)v * n + q];
+        if (p != NONE) l += wlen[p];
+    }
+    len[ridx[g]] = l;
+    gid[ridx[g]] = (uint32_t)g;
+}
+
+// Row r: entries (pool segment, w / den), row pointer, and target E[g].
+__global__ __launch_bounds__(256) void k_row_gather(int64_t n, int nb, uint32_t rows,
+                                                    const uint32_t* __restrict__ gid,
+                                                    const uint32_t* __restrict__ off,
+                                                    uint32_t nnz0, uint32_t seg0,
+                                                    const uint32_t* __restrict__ rank,
+                                                    const uint32_t* __restrict__ pair_of_m,
+                                                    const uint32_t* __restrict__ wlen,
+                                                    const uint32_t* __restrict__ part_base,
+                                                    const uint2* __restrict__ wrow,
+                                                    const float* __restrict__ den,
+                                                    uint32_t* __restrict__ row_ptr,
+                                                    uint32_t* __restrict__ col, float* __restrict__ w)
+{
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= rows) return;
+    const uint32_t g = gid[r], q = rank[g];
+    const float inv = 1.0f / den[g];
+    uint32_t o = nnz0 + off[r];
+    row_ptr[r] = o;
+    for (int v = 0; v < nb; v++) {
+        const uint32_t p = pair_of_m[(int64_t)v * n + q];
+        if (p == NONE) continue;
+        const uint32_t b = part_base[p];
+        for (uint32_t j = 0; j < wlen[p]; j++) {
+            const uint2 e = wrow[b + j];
+            col[o] = seg0 + e.x;
+            w[o] = __uint_as_float(e.y) * inv;
+            o++;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_copy_rows(uint32_t rows, int d, const uint32_t* __restrict__ gid,
+                                                   const float* __restrict__ src,
+                                                   float* __restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)rows * d) return;
+    const int64_t r = i / d;
+    const int c = (int)(i - r * d);
+    dst[i] = src[(int64_t)gid[r] * d + c];
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+void launch_pick_rows(int64_t n, const float* den, uint64_t seed, uint32_t thresh, uint32_t* flag,
+                      hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_pick_rows, dim3(blocks(n)), dim3(256), 0, st, n, den, seed, thresh, flag);
+}
+
+void launch_row_len(int64_t n, int nb, const uint32_t* flag, const uint32_t* ridx,
+                    uint32_t max_rows, const uint32_t* rank, const uint32_t* pair_of_m,
+                    const uint32_t* wlen, uint32_t* len, uint32_t* gid, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_row_len, dim3(blocks(n)), dim3(256), 0, st, n, nb, flag, ridx, max_rows,
+                       rank, pair_of_m, wlen, len, gid);
+}
+
+void launch_row_gather(int64_t n, int nb, uint32_t rows, const uint32_t* gid, const uint32_t* off,
+                       uint32_t nnz0, uint32_t seg0, const uint32_t* rank,
+                       const uint32_t* pair_of_m, const uint32_t* wlen, const uint32_t* part_base,
+                       const uint2* wrow, const float* den, uint32_t* row_ptr, uint32_t* col,
+                       float* w, hipStream_t st)
+{
+    if (!rows) return;
+    hipLaunchKernelGGL(k_row_gather, dim3(blocks(rows)), dim3(256), 0, st, n, nb, rows, gid, off,
+                       nnz0, seg0, rank, pair_of_m, wlen, part_base, wrow, den, row_ptr, col, w);
+}
+
+void launch_copy_rows(uint32_t rows, int d, const uint32_t* gid, const float* src, float* dst,
+                      hipStream_t st)
+{
+    if (!rows) return;
+    hipLaunchKernelGGL(k_copy_rows, dim3(blocks((int64_t)rows * d)), dim3(256), 0, st, rows, d,
+                       gid, src, dst);
+}
+
+int gemm_splits(int M, int N, int K, int* kper)
+{
+    const int64_t tiles = (int64_t)((M + GT - 1) / GT) * ((N + GT - 1) / GT);
+    int splits = 1;
+    if (tiles < 512 && K > 8 * GK) {
+        splits = (int)std::min<int64_t>((K + 8 * GK - 1) / (8 * GK), (1024 + tiles - 1) / tiles);
+        splits = std::max(splits, 1);
+    }
+    int kp = (K + splits - 1) / splits;
+    kp = (kp + GK - 1) / GK * GK;
+    if (kp <= 0) kp = GK;
+    *kper = kp;
+    return (K + kp - 1) / kp;
+}
+
+void launch_gemm(bool bf16, bool a_bf16, int M, int N, int K, const void* A, int64_t sam,
+                 int64_t sak, const float* B, int64_t sbk, int64_t sbn, float* C, int64_t ldc,
+                 const GemmEpi& epi, float* part, hipStream_t st)
+{
+    if (M <= 0 || N <= 0) return;
+    int kper = GK;
+    const int splits = K > 0 ? gemm_splits(M, N, K, &kper) : 1;
+    const dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT), (unsigned)splits);
+    float* out = splits > 1 ? part : C;
+#define SLAG_GEMM(BF, TA)                                                                          \
+    hipLaunchKernelGGL((k_gemm<BF, TA>), grid, dim3(256), 0, st, M, N, K,                          \
+                       reinterpret_cast<const TA*>(A), sam, sak, B, sbk, sbn, kper, out, ldc, epi)
+    if (bf16) {
+        if (a_bf16) SLAG_GEMM(true, uint16_t);
+        else SLAG_GEMM(true, float);
+    } else {
+        if (a_bf16) SLAG_GEMM(false, uint16_t);
+        else SLAG_GEMM(false, float);
+    }
+#undef SLAG_GEMM
+    if (splits > 1)
+        hipLaunchKernelGGL(k_gemm_reduce, dim3(blocks((int64_t)M * N)), dim3(256), 0, st, M, N,
+                           splits, part, C, ldc, epi);
+}
+
+size_t gemm_part_floats(int M, int N, int K)
+{
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    int kper;
+    const int splits = gemm_splits(M, N, K, &kper);
+    return splits > 1 ? (size_t)splits * M * N : 0;
+}
+
+void launch_colsum(int R, int N, const float* X, float* out, float* part, hipStream_t st)
+{
+    if (N <= 0) return;
+    const int rows_per = 512;
+    const int slices = std::max(1, (R + rows_per - 1) / rows_per);
+    hipLaunchKernelGGL(k_colsum_part, dim3(blocks(N), slices), dim3(256), 0, st, R, N, X, rows_per,
+                       part);
+    hipLaunchKernelGGL(k_colsum_fin, dim3(blocks(N)), dim3(256), 0, st, N, slices, part, out);
+}
+
+size_t colsum_part_floats(int R, int N) { return (size_t)std::max(1, (R + 511) / 512) * N; }
+
+void launch_mix(int R, int k, const uint32_t* row_ptr, const uint32_t* col, const float* w,
+                const float* C, float* code, hipStream_t st)
+{
+    if (R <= 0) return;
+    hipLaunchKernelGGL(k_mix, dim3(blocks((int64_t)R * k)), dim3(256), 0, st, R, k, row_ptr, col,
+                       w, C, code);
+}
+
+void launch_mix_bwd(int R, int k, const uint32_t* row_ptr, const uint32_t* col, const float* w,
+                    const float* dcode, float* dC, hipStream_t st)
+{
+    if (R <= 0) return;
+    hipLaunchKernelGGL(k_mix_bwd, dim3(blocks((int64_t)R * k)), dim3(256), 0, st, R, k, row_ptr,
+                       col, w, dcode, dC);
+}
+
+void launch_cos_loss(int R, int d, const float* y, const float* tg, float* dy, float* loss_part,
+                     float* loss, hipStream_t st)
+{
+    if (R <= 0) return;
+    const int nb = (R + 3) / 4;
+    const float inv_r = 1.0f / (float)R;
+    hipLaunchKernelGGL(k_cos_loss, dim3(nb), dim3(256), 0, st, R, d, y, tg, inv_r, dy, loss_part);
+    hipLaunchKernelGGL(k_loss_fin, dim3(1), dim3(256), 0, st, nb, loss_part, inv_r, loss);
+}
+
+void launch_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,
+                 float b2, float eps, int64_t step, hipStream_t st)
+{
+    if (n <= 0) return;
+    const float c1 = 1.0f - (float)std::pow((double)b1, (double)step);
+    const float c2 = 1.0f - (float)std::pow((double)b2, (double)step);
+    hipLaunchKernelGGL(k_adam, dim3(blocks(n)), dim3(256), 0, st, n, p, g, m, v, lr, b1, b2, eps,
+                       c1, c2);
+}
+
+void launch_to_f32(int64_t n, const void* src, bool bf16, float* dst, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_to_f32, dim3(blocks(n)), dim3(256), 0, st, n, src, (int)bf16, dst);
+}
+
+}  // namespace slag

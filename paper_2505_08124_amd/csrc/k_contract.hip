@@ -124,6 +124,7 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
     const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
     const int64_t q0 = (int64_t)blockIdx.x * 16;          // first Morton rank of the block
     const int c0 = wv * 16 * NT;                          // this wave's first feature column
+    const bool wact = c0 < d;                             // (d < 64: waves past d only walk)
     const int m = lane & 15, kq = lane >> 4;
     const int row = t & 15, vi = t >> 4;                  // walking role
     const bool row_ok = q0 + row < n;
@@ -140,7 +141,7 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const int64_t q = q0 + 4 * kq + j;
-                acc[i][j] = q < n ? num[(size_t)perm[q] * d + c0 + 16 * i + m] : 0.0f;
+                acc[i][j] = (wact && q < n) ? num[(size_t)perm[q] * d + c0 + 16 * i + m] : 0.0f;
             }
         if (t < 16 && q0 + t < n) dsum = den[perm[q0 + t]];
     }
@@ -212,8 +213,9 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
                 __syncthreads();
                 // 4. matrix cores, 32 columns at a time
                 const int kc = (int)min((uint32_t)KMAX, ktot - kr);
-                for (int k0 = 0; k0 < kc; k0 += KC)
-                    mfma_chunk<NT, BF16>(L, k0, min(KC, kc - k0), feats, d, c0, acc, lane);
+                if (wact)
+                    for (int k0 = 0; k0 < kc; k0 += KC)
+                        mfma_chunk<NT, BF16>(L, k0, min(KC, kc - k0), feats, d, c0, acc, lane);
                 __syncthreads();
             }
         }
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
     for (int j = 0; j < 4; j++) {
         const int rr = 4 * kq + j;
         const int64_t q = q0 + rr;
-        if (q >= n) continue;
+        if (q >= n || !wact) continue;
         const uint32_t g = perm[q];
         const float dn = L.dpart[0][rr];
 #pragma unroll
@@ -268,6 +270,8 @@ bool contract_supported(int d)
     return d == 64 || d == 128 || d == 256 || d == 512 || d == 768 || d == 1024;
 }
 
+bool contract_supported_codes(int d) { return d == 16 || d == 32 || d == 48 || contract_supported(d); }
+
 void launch_contract(int64_t n, int nb, int d, bool bf16, const uint32_t* perm,
                      const uint32_t* pair_of_m, const ViewDev* views, const uint32_t* part_base,
                      const uint32_t* pcnt, const uint2* part, const void* feats, float* num,
@@ -277,6 +281,9 @@ void launch_contract(int64_t n, int nb, int d, bool bf16, const uint32_t* perm,
 #define SLAG_NT(NTV) launch_nt<NTV>(n, nb, d, bf16, perm, pair_of_m, views, part_base, pcnt, part, \
                                     feats, num, den, first, last, st)
     switch (d) {
+    case 16:
+    case 32:
+    case 48:
     case 64: SLAG_NT(1); break;
     case 128: SLAG_NT(2); break;
     case 256: SLAG_NT(4); break;

@@ -192,6 +192,7 @@ __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const
 
 template <bool COUNT>
 __global__ __launch_bounds__(256) void k_composite(
+    const uint32_t* __restrict__ order,
     const uint32_t* __restrict__ bucket_view, const ViewDev* __restrict__ views,
     const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ bend,
     const uint32_t* __restrict__ ival, const uint32_t* __restrict__ islot,
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(256) void k_composite(
     __shared__ uint32_t s_off[BATCH];         // part slot of (pair, this tile, first pass segment)
     __shared__ uint16_t s_seg[TILE_PIX];
 
-    const uint32_t b = blockIdx.x;
+    const uint32_t b = order[blockIdx.x];     // tiles with the longest lists first
     const uint32_t start = bstart[b], end = bend[b];
     if (start >= end) return;
     const uint32_t ns = ns_tile[b];
@@ -375,20 +376,22 @@ void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t*
     hipLaunchKernelGGL(k_sat, dim3(nb), dim3(256), 0, st, views, ns_tile, sat);
 }
 
-void launch_composite(bool count, uint32_t nbuckets, const uint32_t* bucket_view,
-                      const ViewDev* views, const uint32_t* bstart, const uint32_t* bend,
-                      const uint32_t* ival, const uint32_t* islot, const float4* rec,
-                      const uint32_t* ns_tile, const uint16_t* segl, const int32_t* ids,
-                      uint2* part, unsigned long long* counters, hipStream_t st)
+void launch_composite(bool count, uint32_t nbuckets, const uint32_t* order,
+                      const uint32_t* bucket_view, const ViewDev* views, const uint32_t* bstart,
+                      const uint32_t* bend, const uint32_t* ival, const uint32_t* islot,
+                      const float4* rec, const uint32_t* ns_tile, const uint16_t* segl,
+                      const int32_t* ids, uint2* part, unsigned long long* counters,
+                      hipStream_t st)
 {
     if (!nbuckets) return;
     if (count)
-        hipLaunchKernelGGL(k_composite<true>, dim3(nbuckets), dim3(256), 0, st, bucket_view, views,
-                           bstart, bend, ival, islot, rec, ns_tile, segl, ids, part, counters);
-    else
-        hipLaunchKernelGGL(k_composite<false>, dim3(nbuckets), dim3(256), 0, st, bucket_view,
+        hipLaunchKernelGGL(k_composite<true>, dim3(nbuckets), dim3(256), 0, st, order, bucket_view,
                            views, bstart, bend, ival, islot, rec, ns_tile, segl, ids, part,
                            counters);
+    else
+        hipLaunchKernelGGL(k_composite<false>, dim3(nbuckets), dim3(256), 0, st, order,
+                           bucket_view, views, bstart, bend, ival, islot, rec, ns_tile, segl, ids,
+                           part, counters);
 }
 
 void launch_merge(uint64_t npairs, const uint16_t* pview, const ViewDev* views,

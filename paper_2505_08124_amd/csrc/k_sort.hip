@@ -397,6 +397,20 @@ __global__ __launch_bounds__(256) void k_bucket_ranges(uint64_t ni, const uint32
     if (i + 1 == ni || ikey[i + 1] != k) bend[k] = (uint32_t)(i + 1);
 }
 
+// Dispatch-order keys: longer tile lists first (key = 0xFFFF - min(len, 0xFFFF)
+// sorts ascending into descending length; equal keys keep tile order).
+__global__ __launch_bounds__(256) void k_bucket_keys(uint32_t nb, const uint32_t* __restrict__ bstart,
+                                                     const uint32_t* __restrict__ bend,
+                                                     uint32_t* __restrict__ key,
+                                                     uint32_t* __restrict__ val)
+{
+    const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= nb) return;
+    const uint32_t len = bend[b] - bstart[b];
+    key[b] = 0xFFFFu - min(len, 0xFFFFu);
+    val[b] = b;
+}
+
 inline unsigned grid_for(uint64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -497,6 +511,14 @@ void launch_bucket_ranges(uint64_t ni, const uint32_t* ikey, uint32_t* bstart, u
     if (!ni) return;
     hipLaunchKernelGGL(k_bucket_ranges, dim3(grid_for(ni)), dim3(256), 0, st, ni, ikey, bstart,
                        bend);
+}
+
+void launch_bucket_keys(uint32_t nb, const uint32_t* bstart, const uint32_t* bend, uint32_t* key,
+                        uint32_t* val, hipStream_t st)
+{
+    if (!nb) return;
+    hipLaunchKernelGGL(k_bucket_keys, dim3(grid_for(nb)), dim3(256), 0, st, nb, bstart, bend, key,
+                       val);
 }
 
 }  // namespace slag

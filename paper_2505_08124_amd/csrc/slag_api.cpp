@@ -7,115 +7,22 @@
 #include <string>
 #include <vector>
 
-#include "../../include/slag.h"
-#include "slag_internal.h"
+#include "slag_ctx.h"
 
 using namespace slag;
+using namespace slag_host;
 
 namespace {
 
-struct DevBuf {
-    void* p = nullptr;
-    size_t cap = 0;
-    template <typename T>
-    T* as() const { return reinterpret_cast<T*>(p); }
-};
-
-enum Stage {
-    ST_TILES = 0, ST_PROJECT, ST_DEPTH_SORT, ST_BIN, ST_TILE_SORT, ST_PART_PREP, ST_COMPOSITE,
-    ST_MERGE, ST_CONTRACT, ST_COUNT_
-};
 const char* kStageNames[ST_COUNT_] = {"tile_segments", "project", "depth_sort", "bin",
                                       "tile_sort", "part_prep", "composite", "merge",
-                                      "contract"};
-
-struct Batch {
-    int v0 = 0, nb = 0;
-    uint32_t nbuckets = 0, nsat = 0;
-    DevBuf views, bucket_view;
-};
-
-struct TimedEvent {
-    int stage;
-    hipEvent_t a, b;
-};
+                                      "contract", "encode", "decode"};
 
 }  // namespace
 
-struct slag_ctx {
-    int device = 0;
-    hipStream_t st = nullptr;
-    bool own_stream = false;
-    slag_options opt{};
-    std::string err;
+namespace slag_host {
 
-    int64_t n = -1;
-    DevBuf means, scales, quats, opac, cov3;
-    DevBuf perm, rank;      // Morton order of the Gaussians (rank -> input index, inverse)
-
-    int nviews = -1;
-    std::vector<slag_camera> cams;
-    std::vector<uint64_t> pix_off;
-    std::vector<int32_t> nseg;
-    std::vector<char> seg_set;
-    DevBuf ids;
-
-    int d = 0;
-    slag_dtype fdt = SLAG_F32;
-    DevBuf feats;
-    bool feats_set = false;
-    uint64_t feat_rows = 0;
-
-    DevBuf num, den;
-    bool have_out = false;
-
-    std::vector<Batch> plan;
-    int plan_views = -1;
-
-    // workspace
-    DevBuf ns_tile, segl, sat, tcnt, blk_vis, small, scan_ws, hist;
-    DevBuf rec, pgauss, pview, dkey, dkey_alt, dval, dval_alt, psz, pz, tcr, wlen, pair_of_m;
-    DevBuf ikey, ikey_alt, ival, ival_alt, islot, islot_alt, bstart, bend, part, wrow, pcnt;
-    DevBuf ptc, blk_aux;
-    uint64_t* host_small = nullptr;   // pinned read-back area
-
-    // results of the last lift
-    slag_stats stats{};
-    std::vector<TimedEvent> events;
-    std::vector<hipEvent_t> free_events;
-    // last batch (debug exports)
-    int last_v0 = -1, last_nb = 0;
-    uint64_t last_npairs = 0, last_ni = 0;
-    const uint32_t* last_ikey = nullptr;
-    const uint32_t* last_ival = nullptr;
-};
-
-// small device area layout (uint64 words)
-enum { SM_TOT = 0, SM_ZRANGE = 2, SM_TOTALS = 4, SM_COUNTERS = 8, SM_NNZ = 12, SM_ERR = 14,
-       SM_WORDS = 16 };
-
-#define FAIL(ctx, code, msg)                 \
-    do {                                     \
-        (ctx)->err = (msg);                  \
-        return (code);                       \
-    } while (0)
-
-#define HC(ctx, expr)                                                                    \
-    do {                                                                                 \
-        hipError_t e_ = (expr);                                                          \
-        if (e_ != hipSuccess) {                                                          \
-            (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);              \
-            return SLAG_E_DEVICE;                                                        \
-        }                                                                                \
-    } while (0)
-
-#define CK(expr)                          \
-    do {                                  \
-        slag_status s_ = (expr);          \
-        if (s_ != SLAG_OK) return s_;     \
-    } while (0)
-
-static slag_status ensure(slag_ctx* c, DevBuf& b, size_t bytes)
+slag_status ensure(slag_ctx* c, DevBuf& b, size_t bytes)
 {
     if (bytes <= b.cap && b.p) return SLAG_OK;
     if (b.p) {
@@ -136,14 +43,34 @@ static slag_status ensure(slag_ctx* c, DevBuf& b, size_t bytes)
     return SLAG_OK;
 }
 
-static void release(DevBuf& b)
+void release(DevBuf& b)
 {
     if (b.p) hipFree(b.p);
     b.p = nullptr;
     b.cap = 0;
 }
 
-static slag_status copy_in(slag_ctx* c, DevBuf& dst, const void* src, size_t bytes, slag_mem where)
+slag_status grow_keep(slag_ctx* c, DevBuf& b, size_t bytes, size_t keep)
+{
+    if (bytes <= b.cap && b.p) return SLAG_OK;
+    DevBuf nb;
+    CK(ensure(c, nb, bytes));
+    if (keep && b.p) {
+        const hipError_t e = hipMemcpyAsync(nb.p, b.p, std::min(keep, b.cap), hipMemcpyDeviceToDevice,
+                                            c->st);
+        if (e != hipSuccess) {
+            release(nb);
+            c->err = std::string("grow_keep copy: ") + hipGetErrorString(e);
+            return SLAG_E_DEVICE;
+        }
+        hipStreamSynchronize(c->st);
+    }
+    release(b);
+    b = nb;
+    return SLAG_OK;
+}
+
+slag_status copy_in(slag_ctx* c, DevBuf& dst, const void* src, size_t bytes, slag_mem where)
 {
     CK(ensure(c, dst, bytes));
     if (bytes == 0) return SLAG_OK;
@@ -153,12 +80,12 @@ static slag_status copy_in(slag_ctx* c, DevBuf& dst, const void* src, size_t byt
     return SLAG_OK;
 }
 
-static slag_status ensure_scan(slag_ctx* c, uint64_t len)
+slag_status ensure_scan(slag_ctx* c, uint64_t len)
 {
     return ensure(c, c->scan_ws, scan_workspace_bytes(std::max<uint64_t>(len, 1)));
 }
 
-static int bit_length(uint64_t x)
+int bit_length(uint64_t x)
 {
     int b = 0;
     while (x) { b++; x >>= 1; }
@@ -166,10 +93,10 @@ static int bit_length(uint64_t x)
 }
 
 // stage timing
-static slag_status stage_begin(slag_ctx* c, int stage, hipEvent_t* a)
+slag_status stage_begin(slag_ctx* c, int stage, hipEvent_t* a)
 {
     *a = nullptr;
-    if (!(c->opt.flags & SLAG_FLAG_PROFILE)) return SLAG_OK;
+    if (!(c->opt.flags & SLAG_FLAG_PROFILE) || c->capturing) return SLAG_OK;
     hipEvent_t e;
     if (!c->free_events.empty()) { e = c->free_events.back(); c->free_events.pop_back(); }
     else HC(c, hipEventCreate(&e));
@@ -179,7 +106,7 @@ static slag_status stage_begin(slag_ctx* c, int stage, hipEvent_t* a)
     return SLAG_OK;
 }
 
-static slag_status stage_end(slag_ctx* c, int stage, hipEvent_t a)
+slag_status stage_end(slag_ctx* c, int stage, hipEvent_t a)
 {
     if (!a) return SLAG_OK;
     hipEvent_t e;
@@ -190,13 +117,15 @@ static slag_status stage_end(slag_ctx* c, int stage, hipEvent_t a)
     return SLAG_OK;
 }
 
-static slag_status read_small(slag_ctx* c, int off, int words)
+slag_status read_small(slag_ctx* c, int off, int words)
 {
     HC(c, hipMemcpyAsync(c->host_small + off, c->small.as<uint64_t>() + off, words * 8,
                          hipMemcpyDeviceToHost, c->st));
     HC(c, hipStreamSynchronize(c->st));
     return SLAG_OK;
 }
+
+}  // namespace slag_host
 
 // Morton order of the Gaussian means: the contraction takes Gaussians in
 // blocks of 16 consecutive along this curve.  Ties (equal 63-bit codes) keep
@@ -312,7 +241,16 @@ static slag_status build_plan(slag_ctx* c)
 
 // ------------------------------------------------------------------ the lift
 
-static slag_status lift_batch(slag_ctx* c, const Batch& B, bool first, bool last)
+// What the contraction multiplies the weights with, and where it writes.
+struct ContractTarget {
+    const void* table;   // [rows][d] FP32 or BF16
+    int d;
+    bool bf16;
+    float* out;          // [N][d]
+};
+
+static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
+                              const ContractTarget& ct)
 {
     hipStream_t st = c->st;
     const int64_t n = c->n;
@@ -346,10 +284,14 @@ static slag_status lift_batch(slag_ctx* c, const Batch& B, bool first, bool last
     launch_reduce_pairs(c->blk_aux.as<uint32_t>(), nblk, false,
                         reinterpret_cast<unsigned long long*>(small + SM_ZRANGE), st);
     scan_u32(c->blk_vis.as<uint32_t>(), nblk, small + SM_TOT, c->scan_ws.p, st);
-    CK(read_small(c, 0, 4));
-    const uint64_t npairs = c->host_small[SM_TOT];
-    const uint32_t zmin = (uint32_t)c->host_small[SM_ZRANGE];
-    const uint32_t zmax = (uint32_t)c->host_small[SM_ZRANGE + 1];
+    if (!c->capturing) {
+        CK(read_small(c, 0, 4));
+        B.npairs = c->host_small[SM_TOT];
+        B.zmin = (uint32_t)c->host_small[SM_ZRANGE];
+        B.zmax = (uint32_t)c->host_small[SM_ZRANGE + 1];
+    }
+    const uint64_t npairs = B.npairs;
+    const uint32_t zmin = B.zmin, zmax = B.zmax;
     if (npairs > 0xFFFFFFF0ull) FAIL(c, SLAG_E_CAPACITY, "too many visible pairs in one launch");
     const int zbits = (npairs && zmax >= zmin) ? bit_length((uint64_t)(zmax - zmin)) : 0;
     const int vbits = bit_length((uint64_t)(nb > 0 ? nb - 1 : 0));
@@ -381,9 +323,13 @@ static slag_status lift_batch(slag_ctx* c, const Batch& B, bool first, bool last
 
     uint64_t ni = 0, nparts = 0;
     if (npairs) {
-        CK(read_small(c, SM_TOTALS, 2));
-        ni = c->host_small[SM_TOTALS];
-        nparts = c->host_small[SM_TOTALS + 1];
+        if (!c->capturing) {
+            CK(read_small(c, SM_TOTALS, 2));
+            B.ni = c->host_small[SM_TOTALS];
+            B.nparts = c->host_small[SM_TOTALS + 1];
+        }
+        ni = B.ni;
+        nparts = B.nparts;
         if (ni > 0xFFFFFFF0ull || nparts > 0xFFFFFFF0ull)
             FAIL(c, SLAG_E_CAPACITY, "too many tile intersections in one launch; lower "
                                      "max_views_per_launch");
@@ -439,6 +385,20 @@ static slag_status lift_batch(slag_ctx* c, const Batch& B, bool first, bool last
         launch_fill_u32(c->bstart.as<uint32_t>(), B.nbuckets, 0u, st);
         launch_fill_u32(c->bend.as<uint32_t>(), B.nbuckets, 0u, st);
         launch_bucket_ranges(ni, skey, c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(), st);
+        // dispatch order of the compositing workgroups: longest lists first
+        CK(ensure(c, c->bkey, (size_t)B.nbuckets * 4 + 4));
+        CK(ensure(c, c->bkey_alt, (size_t)B.nbuckets * 4 + 4));
+        CK(ensure(c, c->bord, (size_t)B.nbuckets * 4 + 4));
+        CK(ensure(c, c->bord_alt, (size_t)B.nbuckets * 4 + 4));
+        CK(ensure(c, c->hist, radix_hist_bytes(B.nbuckets)));
+        CK(ensure_scan(c, B.nbuckets));
+        launch_bucket_keys(B.nbuckets, c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(),
+                           c->bkey.as<uint32_t>(), c->bord.as<uint32_t>(), st);
+        const bool alt3 = radix_sort_u32(c->bkey.as<uint32_t>(), c->bord.as<uint32_t>(),
+                                         c->bkey_alt.as<uint32_t>(), c->bord_alt.as<uint32_t>(),
+                                         B.nbuckets, 16, c->hist.as<uint32_t>(), c->scan_ws.p,
+                                         nullptr, st);
+        const uint32_t* border = alt3 ? c->bord_alt.as<uint32_t>() : c->bord.as<uint32_t>();
         CK(stage_end(c, ST_TILE_SORT, ev));
 
         // part slots, zeroed
@@ -448,7 +408,7 @@ static slag_status lift_batch(slag_ctx* c, const Batch& B, bool first, bool last
         CK(stage_end(c, ST_PART_PREP, ev));
 
         CK(stage_begin(c, ST_COMPOSITE, &ev));
-        launch_composite(count, B.nbuckets, B.bucket_view.as<uint32_t>(), views,
+        launch_composite(count, B.nbuckets, border, B.bucket_view.as<uint32_t>(), views,
                          c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(), sval, sslot,
                          c->rec.as<float4>(), c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
                          c->ids.as<int32_t>(), c->part.as<uint2>(),
@@ -468,10 +428,9 @@ static slag_status lift_batch(slag_ctx* c, const Batch& B, bool first, bool last
     }
 
     CK(stage_begin(c, ST_CONTRACT, &ev));
-    launch_contract(n, nb, c->d, c->fdt == SLAG_BF16, c->perm.as<uint32_t>(),
-                    c->pair_of_m.as<uint32_t>(), views, c->psz.as<uint32_t>(),
-                    c->pcnt.as<uint32_t>(), c->part.as<uint2>(), c->feats.p, c->num.as<float>(),
-                    c->den.as<float>(), first, last, st);
+    launch_contract(n, nb, ct.d, ct.bf16, c->perm.as<uint32_t>(), c->pair_of_m.as<uint32_t>(),
+                    views, c->psz.as<uint32_t>(), c->pcnt.as<uint32_t>(), c->part.as<uint2>(),
+                    ct.table, ct.out, c->den.as<float>(), first, last, st);
     CK(stage_end(c, ST_CONTRACT, ev));
 
     c->last_v0 = B.v0;
@@ -533,8 +492,11 @@ void slag_destroy(slag_ctx* c)
                       &c->dkey_alt, &c->dval, &c->dval_alt, &c->psz, &c->pz, &c->tcr, &c->wlen,
                       &c->ikey, &c->ikey_alt, &c->ival, &c->ival_alt, &c->bstart, &c->bend,
                       &c->part, &c->wrow, &c->perm, &c->rank, &c->pair_of_m, &c->pcnt,
-                      &c->islot, &c->islot_alt, &c->ptc, &c->blk_aux};
+                      &c->islot, &c->islot_alt, &c->ptc, &c->blk_aux, &c->bkey,
+                      &c->bkey_alt, &c->bord, &c->bord_alt};
+    destroy_graph(c);
     for (DevBuf* b : bufs) release(*b);
+    codec_release(c);
     for (auto& b : c->plan) { release(b.views); release(b.bucket_view); }
     for (auto& e : c->events) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
     for (auto e : c->free_events) hipEventDestroy(e);
@@ -555,6 +517,7 @@ slag_status slag_set_gaussians(slag_ctx* c, int64_t n, const float* means, const
 {
     if (!c) return SLAG_E_INVALID_ARG;
     c->err.clear();
+    invalidate_graph(c);
     if (n < 0 || (n > 0 && (!means || !scales || !quats || !opacity)))
         FAIL(c, SLAG_E_INVALID_ARG, "null pointer or negative Gaussian count");
     if (n >= ((int64_t)1 << 31)) FAIL(c, SLAG_E_CAPACITY, "at most 2^31 - 1 Gaussians");
@@ -585,6 +548,7 @@ slag_status slag_set_cameras(slag_ctx* c, int32_t n_views, const slag_camera* ca
 {
     if (!c) return SLAG_E_INVALID_ARG;
     c->err.clear();
+    invalidate_graph(c);
     if (n_views < 0 || (n_views > 0 && !cams)) FAIL(c, SLAG_E_INVALID_ARG, "bad camera array");
     uint64_t tot = 0;
     std::vector<uint64_t> off(n_views + 1, 0);
@@ -620,6 +584,7 @@ slag_status slag_set_segments(slag_ctx* c, int32_t view, const int32_t* ids, int
 {
     if (!c) return SLAG_E_INVALID_ARG;
     c->err.clear();
+    invalidate_graph(c);
     if (c->nviews < 0) FAIL(c, SLAG_E_STATE, "set cameras before segments");
     if (view < 0 || view >= c->nviews) FAIL(c, SLAG_E_INVALID_ARG, "view index out of range");
     if (!ids || n_seg < 0) FAIL(c, SLAG_E_INVALID_ARG, "null ids or negative segment count");
@@ -652,6 +617,7 @@ slag_status slag_set_features(slag_ctx* c, int32_t d, slag_dtype dtype, const vo
 {
     if (!c) return SLAG_E_INVALID_ARG;
     c->err.clear();
+    invalidate_graph(c);
     if (c->nviews < 0) FAIL(c, SLAG_E_STATE, "set cameras and segments before features");
     for (int v = 0; v < c->nviews; v++)
         if (!c->seg_set[v]) FAIL(c, SLAG_E_STATE, "segments of view " + std::to_string(v) + " not set");
@@ -674,7 +640,84 @@ slag_status slag_set_features(slag_ctx* c, int32_t d, slag_dtype dtype, const vo
     return SLAG_OK;
 }
 
-slag_status slag_lift(slag_ctx* c)
+}  // extern "C"
+
+namespace slag_host {
+
+// The launch sequence of one lift (eager, or recorded into a graph while
+// c->capturing: then no host synchronisation, allocation or event).
+static slag_status lift_sequence(slag_ctx* c, bool codec)
+{
+    CodecState& K = c->codec;
+    const int64_t n = c->n;
+    uint64_t* small = c->small.as<uint64_t>();
+    launch_fill_u32(reinterpret_cast<uint32_t*>(small + SM_COUNTERS), 12, 0u, c->st);
+    if (n == 0) return SLAG_OK;
+    ContractTarget ct{c->feats.p, c->d, c->fdt == SLAG_BF16, c->num.as<float>()};
+    if (codec) {
+        hipEvent_t ev;
+        CK(stage_begin(c, ST_ENCODE, &ev));
+        CK(codec_encode_table(c));
+        CK(stage_end(c, ST_ENCODE, ev));
+        CK(ensure(c, K.codes, (size_t)n * K.k * 4));
+        ct = ContractTarget{K.C.p, K.k, false, K.codes.as<float>()};
+    }
+    if (c->plan.empty()) {
+        launch_fill_u32(reinterpret_cast<uint32_t*>(ct.out), (uint64_t)n * ct.d, 0u, c->st);
+        launch_fill_u32(c->den.as<uint32_t>(), (uint64_t)n, 0u, c->st);
+    }
+    for (size_t i = 0; i < c->plan.size(); i++)
+        CK(lift_batch(c, c->plan[i], i == 0, i + 1 == c->plan.size(), ct));
+    if (codec) {
+        hipEvent_t ev;
+        CK(stage_begin(c, ST_DECODE, &ev));
+        CK(codec_decode_codes(c));
+        CK(stage_end(c, ST_DECODE, ev));
+    }
+    return SLAG_OK;
+}
+
+static void drop_graph(slag_ctx* c)
+{
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->graph_mode = -1;
+}
+
+// Record the launch sequence of the lift just run eagerly into a graph.
+static slag_status capture_lift(slag_ctx* c, bool codec)
+{
+    drop_graph(c);
+    HC(c, hipStreamBeginCapture(c->st, hipStreamCaptureModeRelaxed));
+    c->capturing = true;
+    const slag_status s = lift_sequence(c, codec);
+    c->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->st, &g);
+    if (s != SLAG_OK) {
+        if (g) hipGraphDestroy(g);
+        return s;
+    }
+    if (e != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        c->err = std::string("graph capture: ") + hipGetErrorString(e);
+        return SLAG_E_DEVICE;
+    }
+    c->graph = g;
+    const hipError_t ei = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        drop_graph(c);
+        c->err = std::string("graph instantiate: ") + hipGetErrorString(ei);
+        return SLAG_E_DEVICE;
+    }
+    c->graph_gen = c->gen;
+    c->graph_mode = codec ? 1 : 0;
+    return SLAG_OK;
+}
+
+slag_status run_lift(slag_ctx* c, bool codec)
 {
     if (!c) return SLAG_E_INVALID_ARG;
     c->err.clear();
@@ -683,43 +726,62 @@ slag_status slag_lift(slag_ctx* c)
     for (int v = 0; v < c->nviews; v++)
         if (!c->seg_set[v]) FAIL(c, SLAG_E_STATE, "segments of view " + std::to_string(v) + " not set");
     if (!c->feats_set) FAIL(c, SLAG_E_STATE, "features not set (or segment counts changed)");
+    CodecState& K = c->codec;
+    if (codec && !K.ready) FAIL(c, SLAG_E_STATE, "codec not initialised");
+    if (codec && K.d != c->d) FAIL(c, SLAG_E_STATE, "codec dimension differs from the features'");
     HC(c, hipSetDevice(c->device));
     c->have_out = false;
+    c->out_is_codec = false;
+    K.have_codes = false;
     for (auto& e : c->events) { c->free_events.push_back(e.a); c->free_events.push_back(e.b); }
     c->events.clear();
-    std::memset(&c->stats, 0, sizeof(c->stats));
-    c->last_v0 = -1;
-    const int64_t n = c->n;
-    CK(ensure(c, c->num, (size_t)std::max<int64_t>(n, 1) * c->d * 4));
-    CK(ensure(c, c->den, (size_t)std::max<int64_t>(n, 1) * 4));
-    if (c->plan_views != c->nviews) CK(build_plan(c));
-    uint64_t* small = c->small.as<uint64_t>();
-    launch_fill_u32(reinterpret_cast<uint32_t*>(small + SM_COUNTERS), 12, 0u, c->st);
-    if (n == 0) {
-        c->have_out = true;
-        return SLAG_OK;
-    }
-    if (c->plan.empty()) {
-        launch_fill_u32(c->num.as<uint32_t>(), (uint64_t)n * c->d, 0u, c->st);
-        launch_fill_u32(c->den.as<uint32_t>(), (uint64_t)n, 0u, c->st);
-    }
+    const bool use_graph = (c->opt.flags & SLAG_FLAG_GRAPH) != 0;
+    const bool replay = use_graph && c->gexec && c->graph_gen == c->gen &&
+                        c->graph_mode == (codec ? 1 : 0) && c->plan_views == c->nviews;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->opt.flags & SLAG_FLAG_PROFILE) {
         CK(stage_begin(c, -1, &e0));
     }
-    for (size_t i = 0; i < c->plan.size(); i++)
-        CK(lift_batch(c, c->plan[i], i == 0, i + 1 == c->plan.size()));
+    if (replay) {
+        HC(c, hipGraphLaunch(c->gexec, c->st));
+        c->stats = c->graph_stats;
+    } else {
+        std::memset(&c->stats, 0, sizeof(c->stats));
+        c->last_v0 = -1;
+        const int64_t n = c->n;
+        CK(ensure(c, c->num, (size_t)std::max<int64_t>(n, 1) * c->d * 4));
+        CK(ensure(c, c->den, (size_t)std::max<int64_t>(n, 1) * 4));
+        if (c->plan_views != c->nviews) CK(build_plan(c));
+        CK(lift_sequence(c, codec));
+        c->stats.n_views = c->nviews;
+        c->stats.n_batches = (int64_t)c->plan.size();
+    }
     if (e0) {
         if (!c->free_events.empty()) { e1 = c->free_events.back(); c->free_events.pop_back(); }
         else HC(c, hipEventCreate(&e1));
         HC(c, hipEventRecord(e1, c->st));
         c->events.push_back({-1, e0, e1});
     }
-    c->stats.n_views = c->nviews;
-    c->stats.n_batches = (int64_t)c->plan.size();
+    if (use_graph && !replay && c->n > 0) {
+        c->graph_stats = c->stats;
+        for (int i = 0; i < 16; i++) c->graph_stats.ms_stage[i] = 0.0;
+        CK(capture_lift(c, codec));
+    }
     c->have_out = true;
+    c->out_is_codec = codec;
+    K.have_codes = codec;
     return SLAG_OK;
 }
+
+void invalidate_graph(slag_ctx* c) { c->gen++; }
+
+void destroy_graph(slag_ctx* c) { drop_graph(c); }
+
+}  // namespace slag_host
+
+extern "C" {
+
+slag_status slag_lift(slag_ctx* c) { return run_lift(c, false); }
 
 slag_status slag_get_embeddings(slag_ctx* c, float* out, float* den, slag_mem where)
 {

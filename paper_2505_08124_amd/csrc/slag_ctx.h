@@ -1,0 +1,179 @@
+// Host-side state of a lift context, shared by the lift and the codec
+// entry points (private to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/slag.h"
+#include "../../include/slag_codec.h"
+#include "slag_internal.h"
+
+namespace slag_host {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    template <typename T>
+    T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+enum Stage {
+    ST_TILES = 0, ST_PROJECT, ST_DEPTH_SORT, ST_BIN, ST_TILE_SORT, ST_PART_PREP, ST_COMPOSITE,
+    ST_MERGE, ST_CONTRACT, ST_ENCODE, ST_DECODE, ST_COUNT_
+};
+
+struct Batch {
+    int v0 = 0, nb = 0;
+    uint32_t nbuckets = 0, nsat = 0;
+    DevBuf views, bucket_view;
+    // sizes read back by the last eager lift (reused while capturing a graph)
+    uint64_t npairs = 0, ni = 0, nparts = 0;
+    uint32_t zmin = 0, zmax = 0;
+};
+
+struct TimedEvent {
+    int stage;
+    hipEvent_t a, b;
+};
+
+// The learned codec: parameters, Adam state, training pool and work arrays.
+struct CodecState {
+    int d = 0, h = 0, k = 0;
+    bool bf16 = true;
+    bool ready = false;
+    int64_t nparam = 0;
+    DevBuf params, grad, adam_m, adam_v;
+    int64_t step = 0;
+    // training pool: segment features (FP32), rows (Gaussians) as CSR over
+    // pool segments with normalised weights, and target embeddings
+    int64_t pool_seg = 0, pool_rows = 0, pool_nnz = 0;
+    DevBuf pF, prow, pcol, pw, ptgt;
+    // work arrays
+    DevBuf a1, h1, C, dC, code, dcode, a3, h2, y, dy, gpart, cpart, lpart, loss;
+    // training-row extraction
+    DevBuf rflag, ridx, rlen, roff, rgid;
+    // codec lift
+    DevBuf codes, hid;
+    bool have_codes = false;
+};
+
+}  // namespace slag_host
+
+struct slag_ctx {
+    int device = 0;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    slag_options opt{};
+    std::string err;
+
+    int64_t n = -1;
+    slag_host::DevBuf means, scales, quats, opac, cov3;
+    slag_host::DevBuf perm, rank;   // Morton order of the Gaussians (rank -> input index, inverse)
+
+    int nviews = -1;
+    std::vector<slag_camera> cams;
+    std::vector<uint64_t> pix_off;
+    std::vector<int32_t> nseg;
+    std::vector<char> seg_set;
+    slag_host::DevBuf ids;
+
+    int d = 0;
+    slag_dtype fdt = SLAG_F32;
+    slag_host::DevBuf feats;
+    bool feats_set = false;
+    uint64_t feat_rows = 0;
+
+    slag_host::DevBuf num, den;
+    bool have_out = false;
+    bool out_is_codec = false;
+
+    std::vector<slag_host::Batch> plan;
+    int plan_views = -1;
+
+    // workspace
+    slag_host::DevBuf ns_tile, segl, sat, tcnt, blk_vis, small, scan_ws, hist;
+    slag_host::DevBuf rec, pgauss, pview, dkey, dkey_alt, dval, dval_alt, psz, pz, tcr, wlen,
+        pair_of_m;
+    slag_host::DevBuf ikey, ikey_alt, ival, ival_alt, islot, islot_alt, bstart, bend, part, wrow,
+        pcnt;
+    slag_host::DevBuf ptc, blk_aux, bkey, bkey_alt, bord, bord_alt;
+    uint64_t* host_small = nullptr;   // pinned read-back area
+
+    slag_host::CodecState codec;
+
+    // graph replay of the lift (SLAG_FLAG_GRAPH)
+    uint64_t gen = 1;                 // bumped by every input change
+    uint64_t graph_gen = 0;           // generation the graph was captured for
+    int graph_mode = -1;              // 0 plain, 1 codec
+    bool capturing = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    slag_stats graph_stats{};
+
+    // results of the last lift
+    slag_stats stats{};
+    std::vector<slag_host::TimedEvent> events;
+    std::vector<hipEvent_t> free_events;
+    // last batch (debug exports, training rows)
+    int last_v0 = -1, last_nb = 0;
+    uint64_t last_npairs = 0, last_ni = 0;
+    const uint32_t* last_ikey = nullptr;
+    const uint32_t* last_ival = nullptr;
+};
+
+namespace slag_host {
+
+// small device area layout (uint64 words)
+enum { SM_TOT = 0, SM_ZRANGE = 2, SM_TOTALS = 4, SM_COUNTERS = 8, SM_NNZ = 12, SM_ERR = 14,
+       SM_WORDS = 16 };
+
+#define FAIL(ctx, code, msg)                 \
+    do {                                     \
+        (ctx)->err = (msg);                  \
+        return (code);                       \
+    } while (0)
+
+#define HC(ctx, expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);              \
+            return SLAG_E_DEVICE;                                                        \
+        }                                                                                \
+    } while (0)
+
+#define CK(expr)                          \
+    do {                                  \
+        slag_status s_ = (expr);          \
+        if (s_ != SLAG_OK) return s_;     \
+    } while (0)
+
+// Device buffer of at least `bytes` (contents not kept when it grows).
+slag_status ensure(slag_ctx* c, DevBuf& b, size_t bytes);
+// Device buffer of at least `bytes`, keeping the first `keep` bytes.
+slag_status grow_keep(slag_ctx* c, DevBuf& b, size_t bytes, size_t keep);
+void release(DevBuf& b);
+slag_status copy_in(slag_ctx* c, DevBuf& dst, const void* src, size_t bytes, slag_mem where);
+slag_status ensure_scan(slag_ctx* c, uint64_t len);
+// Copy `words` uint64 words of the small device area to host_small (synchronous).
+slag_status read_small(slag_ctx* c, int off, int words);
+slag_status stage_begin(slag_ctx* c, int stage, hipEvent_t* a);
+slag_status stage_end(slag_ctx* c, int stage, hipEvent_t a);
+int bit_length(uint64_t x);
+
+// The lift (plain or codec) on the context's inputs.
+slag_status run_lift(slag_ctx* c, bool codec);
+// Codec pieces used by the lift: codes of the context's feature table into
+// codec.C, and decoding of codec.codes into the context's output.
+slag_status codec_encode_table(slag_ctx* c);
+slag_status codec_decode_codes(slag_ctx* c);
+// Release the codec's device memory.
+void codec_release(slag_ctx* c);
+// Mark the captured lift graph stale (any input change), or destroy it.
+void invalidate_graph(slag_ctx* c);
+void destroy_graph(slag_ctx* c);
+
+}  // namespace slag_host

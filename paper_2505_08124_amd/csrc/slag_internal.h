@@ -80,6 +80,8 @@ void launch_emit_isect(uint64_t npairs, const uint32_t* order, const float4* rec
                        const uint32_t* part_base, const uint32_t* sat, uint32_t* ikey,
                        uint32_t* ival, uint32_t* islot, hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
+void launch_bucket_keys(uint32_t nb, const uint32_t* bstart, const uint32_t* bend, uint32_t* key,
+                        uint32_t* val, hipStream_t st);
 void launch_bucket_ranges(uint64_t ni, const uint32_t* ikey, uint32_t* bstart, uint32_t* bend,
                           hipStream_t st);
 
@@ -87,19 +89,63 @@ void launch_tile_segs(uint32_t nbuckets, const uint32_t* bucket_view, const View
                       const int32_t* ids, uint32_t* ns_tile, uint16_t* segl, hipStream_t st);
 void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t* sat,
                 hipStream_t st);
-void launch_composite(bool count, uint32_t nbuckets, const uint32_t* bucket_view,
-                      const ViewDev* views, const uint32_t* bstart, const uint32_t* bend,
-                      const uint32_t* ival, const uint32_t* islot, const float4* rec,
-                      const uint32_t* ns_tile, const uint16_t* segl, const int32_t* ids,
-                      uint2* part, unsigned long long* counters, hipStream_t st);
+void launch_composite(bool count, uint32_t nbuckets, const uint32_t* order,
+                      const uint32_t* bucket_view, const ViewDev* views, const uint32_t* bstart,
+                      const uint32_t* bend, const uint32_t* ival, const uint32_t* islot,
+                      const float4* rec, const uint32_t* ns_tile, const uint16_t* segl,
+                      const int32_t* ids, uint2* part, unsigned long long* counters,
+                      hipStream_t st);
 void launch_merge(uint64_t npairs, const uint16_t* pview, const ViewDev* views,
                   const uint32_t* part_base, const uint32_t* pcnt, const uint2* part,
                   uint2* wrow, uint32_t* wlen, unsigned long long* nnz, hipStream_t st);
 
 bool contract_supported(int d);
+// code tables of the codec: d in {16, 32, 48} besides the feature sizes
+bool contract_supported_codes(int d);
 void launch_contract(int64_t n, int nb, int d, bool bf16, const uint32_t* perm,
                      const uint32_t* pair_of_m, const ViewDev* views, const uint32_t* part_base,
                      const uint32_t* pcnt, const uint2* part, const void* feats, float* num,
                      float* den, bool first, bool last, hipStream_t st);
+
+// ---- codec ----
+enum { GEMM_NONE = 0, GEMM_GELU = 1, GEMM_GELU_BWD = 2 };
+// Epilogue of a product, per output element (row, col) at index idx:
+// v += bias[col]; zsave[idx] = v; v = gelu(v) (GEMM_GELU) or
+// v *= gelu'(aux[idx]) (GEMM_GELU_BWD); v = 0 where rowmask[row] <= 0.
+struct GemmEpi {
+    const float* bias = nullptr;
+    int act = GEMM_NONE;
+    float* zsave = nullptr;
+    const float* aux = nullptr;
+    const float* rowmask = nullptr;
+};
+int gemm_splits(int M, int N, int K, int* kper);
+size_t gemm_part_floats(int M, int N, int K);
+void launch_gemm(bool bf16, bool a_bf16, int M, int N, int K, const void* A, int64_t sam,
+                 int64_t sak, const float* B, int64_t sbk, int64_t sbn, float* C, int64_t ldc,
+                 const GemmEpi& epi, float* part, hipStream_t st);
+size_t colsum_part_floats(int R, int N);
+void launch_colsum(int R, int N, const float* X, float* out, float* part, hipStream_t st);
+void launch_mix(int R, int k, const uint32_t* row_ptr, const uint32_t* col, const float* w,
+                const float* C, float* code, hipStream_t st);
+void launch_mix_bwd(int R, int k, const uint32_t* row_ptr, const uint32_t* col, const float* w,
+                    const float* dcode, float* dC, hipStream_t st);
+void launch_cos_loss(int R, int d, const float* y, const float* tg, float* dy, float* loss_part,
+                     float* loss, hipStream_t st);
+void launch_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,
+                 float b2, float eps, int64_t step, hipStream_t st);
+void launch_to_f32(int64_t n, const void* src, bool bf16, float* dst, hipStream_t st);
+void launch_pick_rows(int64_t n, const float* den, uint64_t seed, uint32_t thresh, uint32_t* flag,
+                      hipStream_t st);
+void launch_row_len(int64_t n, int nb, const uint32_t* flag, const uint32_t* ridx,
+                    uint32_t max_rows, const uint32_t* rank, const uint32_t* pair_of_m,
+                    const uint32_t* wlen, uint32_t* len, uint32_t* gid, hipStream_t st);
+void launch_row_gather(int64_t n, int nb, uint32_t rows, const uint32_t* gid, const uint32_t* off,
+                       uint32_t nnz0, uint32_t seg0, const uint32_t* rank,
+                       const uint32_t* pair_of_m, const uint32_t* wlen, const uint32_t* part_base,
+                       const uint2* wrow, const float* den, uint32_t* row_ptr, uint32_t* col,
+                       float* w, hipStream_t st);
+void launch_copy_rows(uint32_t rows, int d, const uint32_t* gid, const float* src, float* dst,
+                      hipStream_t st);
 
 }  // namespace slag

@@ -10,16 +10,21 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "slag.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(slag_[a-z_]+)\s*\(", src)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(slag_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
     import paper_2505_08124_amd as slag
     L = slag.lib()
     names = _declared()
-    assert len(names) >= 13
+    assert len(names) >= 23
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(slag.EXPORTS)
@@ -31,7 +36,11 @@ def test_null_arguments_are_rejected():
     assert L.slag_create(0, None, None, None) == slag.SLAG_E_INVALID_ARG
     assert L.slag_lift(None) == slag.SLAG_E_INVALID_ARG
     assert L.slag_get_stats(None, None) == slag.SLAG_E_INVALID_ARG
+    assert L.slag_codec_clear_pool(None) == slag.SLAG_E_INVALID_ARG
+    assert L.slag_lift_codec(None) == slag.SLAG_E_INVALID_ARG
+    assert L.slag_codec_train(None, None, None) == slag.SLAG_E_INVALID_ARG
     assert L.slag_stage_name(6) == b"composite"
+    assert L.slag_stage_name(10) == b"decode"
     assert L.slag_stage_name(99) == b""
 
 

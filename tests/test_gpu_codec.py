@@ -1,0 +1,144 @@
+"""GPU tests of the learned codec through the C ABI.
+
+* loss and gradient of the training objective against the FP64 reference
+  (FP32 products: relative error <= 1e-4 per parameter block; BF16 products:
+  <= 3e-2);
+* the codec lift (encode, lift codes, decode) against the FP64 reference on
+  the 2k-Gaussian scene, with the same parameters;
+* training on the GPU lowers the loss, and what it gains: on a held-out
+  scene the trained codec beats the PCA-k codec fitted to the training
+  embeddings, which beats the untrained network (mean cosine to the plain
+  lift).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import codec as cd
+from synthetic import make_scene
+from synthetic.codec_inputs import init_params, random_pool
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-codec]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _blocks(g, dims):
+    out, o = {}, 0
+    for name, shp in dims.shapes():
+        n = int(np.prod(shp))
+        out[name] = g[o:o + n]
+        o += n
+    return out
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("bf16", 3e-2)])
+def test_gradients_match_oracle(prec, tol):
+    import paper_2505_08124_amd as slag
+    dims = cd.Dims(d=64, h=32, k=16)
+    F, rp, col, w, T = random_pool(seed=21, S=48, R=40, d=dims.d)
+    p = init_params(dims.d, dims.h, dims.k, seed=22, bias_sd=0.1)
+    ref_loss, ref_g, _ = cd.loss_and_grad(p.astype(np.float64), dims, F, rp, col, w, T)
+    P = slag.SLAG_F32 if prec == "f32" else slag.SLAG_BF16
+    with slag.Lifter(0) as L:
+        slag.slag_codec_init(L.ctx, dims.d, dims.h, dims.k, P, p)
+        slag.slag_codec_set_pool(L.ctx, F, rp, col, w, T)
+        g = np.zeros(p.size, np.float32)
+        loss = slag.slag_codec_loss_grad(L.ctx, 0, 40, g)
+        # a sub-range of rows is its own mean
+        loss2 = slag.slag_codec_loss_grad(L.ctx, 10, 20)
+    l2, _, _ = cd.loss_and_grad(p.astype(np.float64), dims, F, rp[10:31] - rp[10], col[rp[10]:rp[30]],
+                                w[rp[10]:rp[30]], T[10:30])
+    _say(f"{prec}: loss gpu {loss:.7f} oracle {ref_loss:.7f}; rows 10..30 {loss2:.7f} / {l2:.7f}")
+    assert abs(loss - ref_loss) <= tol * 0.2 and abs(loss2 - l2) <= tol * 0.2
+    G, R = _blocks(g.astype(np.float64), dims), _blocks(ref_g, dims)
+    for name in G:
+        rel = np.linalg.norm(G[name] - R[name]) / max(np.linalg.norm(R[name]), 1e-30)
+        _say(f"  {name}: relative error {rel:.2e}")
+        assert rel <= tol, (name, rel)
+
+
+@pytest.mark.parametrize("prec,cos_min", [("f32", 0.9999), ("bf16", 0.99)])
+def test_codec_lift_matches_oracle(scene_2k, oracle_2k, prec, cos_min):
+    import paper_2505_08124_amd as slag
+    sc = scene_2k
+    dims = cd.Dims(d=sc.dim, h=64, k=16)
+    p = init_params(dims.d, dims.h, dims.k, seed=23, bias_sd=0.1)
+    W = oracle.weight_matrix(sc, list(range(sc.n_views)), oracle_2k.views)
+    rs = np.asarray(W.sum(axis=1)).ravel()
+    inv = np.divide(1.0, rs, out=np.zeros_like(rs), where=rs > 0)
+    import scipy.sparse as sp
+    Wn = sp.diags(inv) @ W
+    E_ref, code_ref = cd.codec_lift(p.astype(np.float64), dims, Wn, sc.feats_f64())
+    P = slag.SLAG_F32 if prec == "f32" else slag.SLAG_BF16
+    with slag.Lifter(0) as L:
+        L.set_scene(sc)
+        slag.slag_codec_init(L.ctx, dims.d, dims.h, dims.k, P, p)
+        L.lift_codec()
+        E, den = L.embeddings()
+        C = L.codes(dims.k)
+    nz = oracle_2k.den > 0
+    assert np.array_equal(den > 0, nz)
+    assert np.all(E[~nz] == 0) and np.all(C[~nz] == 0)
+    comp = nz & (oracle_2k.U / np.maximum(oracle_2k.den, 1e-300) <= 5e-3)
+    cos_e = cd.cosine_rows(E[comp], E_ref[comp])
+    cos_c = cd.cosine_rows(C[comp], code_ref[comp])
+    _say(f"{prec}: min cosine embeddings {cos_e.min():.6f}, codes {cos_c.min():.6f}")
+    assert cos_e.min() >= cos_min and cos_c.min() >= cos_min
+
+
+def _train_scene(seed, n, views):
+    return make_scene("codec_train", seed=seed, n=n, views=dict(n=views))
+
+
+def test_training_lowers_loss_and_beats_baselines():
+    import paper_2505_08124_amd as slag
+    n, views, k, h = 150_000, 48, 16, 256
+    dims = cd.Dims(d=512, h=h, k=k)
+    p0 = init_params(dims.d, dims.h, dims.k, seed=1040)
+    L = slag.Lifter(0)
+    slag.slag_codec_init(L.ctx, dims.d, h, k, slag.SLAG_BF16, p0)
+    train_E = []
+    for s in (1041, 1042, 1043):
+        _say("training scene", s)
+        sc = _train_scene(s, n, views)
+        L.set_scene(sc)
+        L.lift()
+        E, den = L.embeddings()
+        train_E.append(E[den > 0])
+        added = slag.slag_codec_add_lift_rows(L.ctx, 40_000, s)
+        _say("  rows added", added)
+        assert added > 30_000
+    nseg, nrows, nnz = slag.slag_codec_pool_size(L.ctx)
+    _say(f"pool: {nseg} segments, {nrows} rows, {nnz} weights")
+    hist = slag.slag_codec_train(L.ctx, steps=1500, batch_rows=8192, lr=1e-3)
+    _say(f"loss: first {hist[:5].mean():.4f}, last {hist[-20:].mean():.4f}")
+    assert hist[-20:].mean() < 0.5 * hist[:5].mean()
+    p1 = np.zeros_like(p0)
+    slag.slag_codec_get_params(L.ctx, p1)
+
+    _say("held-out scene 1044")
+    sc = _train_scene(1044, n, views)
+    L.set_scene(sc)
+    L.lift()
+    E_plain, den = L.embeddings()
+    nz = den > 0
+    L.lift_codec()
+    E_tr, _ = L.embeddings()
+    slag.slag_codec_init(L.ctx, dims.d, h, k, slag.SLAG_BF16, p0)
+    L.lift_codec()
+    E_un, _ = L.embeddings()
+    L.close()
+    mu, V = cd.pca_fit(np.concatenate(train_E)[::4], k)
+    E_pca = mu + (E_plain[nz] - mu) @ V.T @ V
+    c_tr = cd.cosine_rows(E_tr[nz], E_plain[nz])
+    c_un = cd.cosine_rows(E_un[nz], E_plain[nz])
+    c_pca = cd.cosine_rows(E_pca, E_plain[nz])
+    _say(f"mean cosine to the plain lift: trained {c_tr.mean():.4f} (p1 {np.percentile(c_tr, 1):.4f}, "
+         f"min {c_tr.min():.4f}), PCA-{k} {c_pca.mean():.4f}, untrained {c_un.mean():.4f}")
+    assert c_tr.mean() > c_pca.mean() > c_un.mean()

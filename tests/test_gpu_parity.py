@@ -162,6 +162,45 @@ def test_permutation_equivariance_gpu(scene_2k, lift_2k):
     assert np.array_equal(Ep[inv], E) and np.array_equal(denp[inv], den)
 
 
+def _other_gpu_work():
+    import torch
+    x = torch.randn(1 << 20, device="cuda")
+    float((x * x).sum().item())
+    torch.cuda.synchronize()
+
+
+def test_graph_replay_matches_eager(scene_2k, lift_2k):
+    """With graph replay the first lift runs eagerly and captures; every
+    later replay (with unrelated GPU work and synchronisations in between)
+    gives the eager result bitwise; changing an input re-runs eagerly."""
+    import paper_2505_08124_amd as slag
+    _, E_ref, den_ref = lift_2k
+    L = _lifter(scene_2k, flags=slag.SLAG_FLAG_GRAPH | slag.SLAG_FLAG_PROFILE)
+    L.lift()
+    E0, den0 = L.embeddings()
+    assert np.array_equal(E0, E_ref) and np.array_equal(den0, den_ref)
+    for i in range(3):
+        _other_gpu_work()
+        L.lift()
+        E, den = L.embeddings()
+        _say("replay", i, "ms", round(L.stats()["ms_total"], 4))
+        assert np.array_equal(E, E0) and np.array_equal(den, den0)
+    check_tile_lists(L, scene_2k, 1)
+    # new features: the next lift is eager again and matches a fresh context
+    rng = np.random.default_rng(9)
+    F2 = rng.standard_normal(scene_2k.feats.shape).astype(np.float32)
+    slag.slag_set_features(L.ctx, F2, slag.SLAG_F32)
+    L.lift()
+    E1, _ = L.embeddings()
+    L.lift()
+    E2, _ = L.embeddings()
+    sc2 = dataclasses.replace(scene_2k, feats=F2)
+    L2 = _lifter(sc2)
+    L2.lift()
+    E3, _ = L2.embeddings()
+    assert np.array_equal(E1, E3) and np.array_equal(E2, E3)
+
+
 def _ragged_scene():
     """Ragged image sizes (partial tiles), background, a view with per-pixel
     noise ids (many segments per tile: several compositing passes)."""
@@ -177,13 +216,18 @@ def _ragged_scene():
 
 
 def test_ragged_views_and_many_segments():
+    import paper_2505_08124_amd as slag
     sc = _ragged_scene()
     _say("ragged: oracle")
     ref = oracle.lift(sc)
     _say("ragged: gpu")
-    L = _lifter(sc)
+    L = _lifter(sc, flags=slag.SLAG_FLAG_GRAPH)
     L.lift()
     E, den = L.embeddings()
+    _other_gpu_work()
+    L.lift()
+    Er, denr = L.embeddings()
+    assert np.array_equal(E, Er) and np.array_equal(den, denr)
     for v in range(sc.n_views):
         check_tile_lists(L, sc, v)
         check_view_weights(L, sc, v, ref.views[v])
@@ -231,3 +275,68 @@ def test_empty_and_degenerate():
     with pytest.raises(slag.SlagError):
         L2 = slag.Lifter(0)
         L2.set_scene(dataclasses.replace(sc, ids=[i + 100 for i in sc.ids]))
+
+
+# --------------------------------------------------------------- full sizes
+
+def test_full_size_plain_bf16_200k():
+    """The benchmark's scene at full size, all 100 views in one launch (the
+    benchmark's configuration): every view's tile lists and W_v for sampled
+    views against the oracle, and the embeddings of every Gaussian against
+    the full FP64 oracle lift."""
+    import paper_2505_08124_amd as slag
+    sc = make_scene("plain_bf16_200k")
+    _say("200k: gpu lift as timed (graph replay, no debug exports)")
+    with slag.Lifter(0, flags=slag.SLAG_FLAG_GRAPH) as L0:
+        L0.set_scene(sc, device_tensors=True)
+        L0.lift()
+        Ee, dene = L0.embeddings()
+        L0.lift()
+        E0, den0 = L0.embeddings()
+    assert np.array_equal(Ee, E0) and np.array_equal(dene, den0)
+    _say("200k: gpu lift with debug exports")
+    L = _lifter(sc)
+    L.lift()
+    E, den = L.embeddings()
+    assert np.array_equal(E, E0) and np.array_equal(den, den0)
+    _say("200k: oracle lift of all views")
+    ref = oracle.lift(sc)
+    for v in (0, 37, 99):
+        _say("200k: view", v)
+        check_tile_lists(L, sc, v)
+        check_view_weights(L, sc, v, ref.views[v])
+    cmin, emax = check_embeddings(E, den, ref)
+    _say(f"200k: min cosine {cmin:.9f}, max abs err {emax:.3g}")
+    L.close()
+
+
+def test_full_size_uneven_1m_sampled_views():
+    """1M Gaussians, 300 views of three resolutions in one launch: tile lists
+    and W_v of one sampled view per resolution against the oracle; splitting
+    the views over two launches leaves den bitwise unchanged."""
+    sc = make_scene("uneven_1m")
+    res = [(int(c["width"]), int(c["height"])) for c in sc.cams]
+    picks = [res.index(r) for r in [(320, 240), (640, 480), (1280, 960)]]
+    _say("1m: gpu lift, one launch")
+    L = _lifter(sc)
+    L.lift()
+    E, den = L.embeddings()
+    st = L.stats()
+    _say(f"1m: pairs {st['n_visible_pairs']}, intersections {st['n_intersections']}")
+    assert st["n_batches"] == 1
+    for v in picks:
+        _say("1m: view", v, res[v])
+        check_tile_lists(L, sc, v)
+        check_view_weights(L, sc, v, oracle.lift_view(sc, v))
+    L.close()
+    nz = den > 0
+    assert np.all(np.linalg.norm(E[nz], axis=1) <= 1 + 1e-5)
+    assert np.all(E[~nz] == 0)
+    _say("1m: two launches of 150 views")
+    L2 = _lifter(sc, max_views=150)
+    L2.lift()
+    E2, den2 = L2.embeddings()
+    assert L2.stats()["n_batches"] == 2
+    assert np.array_equal(den, den2)
+    np.testing.assert_allclose(E2, E, rtol=1e-5, atol=1e-6)
+    L2.close()
