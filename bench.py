@@ -50,18 +50,22 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic():
-    """HBM bytes per composite launch from the committed PMC summary, if it was
-    taken on the current kernel source; else None."""
-    p = os.path.join(ROOT, "profiles", "composite_traffic.json")
+    """HBM bytes per compositing launch from the committed counter summary, if
+    it was taken on the current kernel source and this workload; else None."""
+    p = os.path.join(ROOT, "profiles", f"composite_traffic_{WORKLOAD}.txt")
     if not os.path.exists(p):
         return None
+    kv = {}
+    for line in open(p):
+        if ":" in line and not line.startswith(("|", "#", " ", "`")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash() or kv.get("workload") != WORKLOAD:
+        return None
     try:
-        d = json.load(open(p))
-    except Exception:
+        return int(float(kv["bytes_per_launch"]))
+    except (KeyError, ValueError):
         return None
-    if d.get("kernel_source_sha256_16") != kernel_source_hash() or d.get("workload") != WORKLOAD:
-        return None
-    return d.get("bytes_per_launch")
 
 
 def cpu_baseline(scene, budget_s: float):
@@ -79,6 +83,74 @@ def cpu_baseline(scene, budget_s: float):
                        f"(per-view W_v lift, FP64, box candidates), {dt:.1f} s wall")
 
 
+def codec_section(args, slag, torch):
+    """The learned codec on the uneven 1M-Gaussian / 300-view workload: train
+    on the plain lifts of three seeded scenes of the same recipe (GPU
+    kernels), then time the plain and the codec lift of the workload scene
+    (graph replays) and compare the codec's embeddings with the plain ones."""
+    from synthetic import make_scene
+    from synthetic.codec_inputs import init_params
+    d, h, k = 512, 256, 16
+    t0 = time.perf_counter()
+    L = slag.Lifter(0, flags=slag.SLAG_FLAG_GRAPH | slag.SLAG_FLAG_PROFILE | slag.SLAG_FLAG_AUTOTUNE)
+    slag.slag_codec_init(L.ctx, d, h, k, slag.SLAG_BF16, init_params(d, h, k, seed=1040))
+    for s in (1041, 1042, 1043):
+        _log("codec: training scene", s)
+        sc = make_scene("codec_train", seed=s)
+        L.set_scene(sc, device_tensors=True)
+        L.lift()
+        slag.slag_codec_add_lift_rows(L.ctx, 100_000, s)
+        del sc
+    nseg, nrows, nnz = slag.slag_codec_pool_size(L.ctx)
+    t1 = time.perf_counter()
+    steps = args.codec_steps
+    hist = slag.slag_codec_train(L.ctx, steps=steps, batch_rows=8192, lr=1e-3)
+    t2 = time.perf_counter()
+    _log(f"codec: trained {steps} steps on {nrows} rows in {t2 - t1:.1f} s, "
+         f"loss {hist[:5].mean():.4f} -> {hist[-20:].mean():.4f}")
+    sc = make_scene("uneven_1m")
+    L.set_scene(sc, device_tensors=True)
+    V = sc.n_views
+
+    def timed(fn, reps):
+        fn()
+        fn()
+        torch.cuda.synchronize()
+        ms = 0.0
+        for _ in range(reps):
+            fn()
+            ms += L.stats()["ms_total"]
+        return ms / reps
+
+    ms_plain = timed(L.lift, args.codec_reps)
+    tuning = slag.slag_get_tuning(L.ctx)
+    E_plain, den = L.embeddings()
+    ms_codec = timed(L.lift_codec, args.codec_reps)
+    E_codec, _ = L.embeddings()
+    L.close()
+    nz = den > 0
+    a, b = E_plain[nz].astype(np.float64), E_codec[nz].astype(np.float64)
+    cos = np.sum(a * b, 1) / (np.linalg.norm(a, axis=1) * np.linalg.norm(b, axis=1) + 1e-300)
+    out = dict(workload="uneven_1m", desc="1M Gaussians, 300 views of 320x240/640x480/1280x960, "
+               "50-150 segments/view, D=512 BF16 object-vocabulary features",
+               k=k, hidden=h, precision="bf16",
+               plain_views_per_s=round(V / (ms_plain * 1e-3), 2),
+               codec_views_per_s=round(V / (ms_codec * 1e-3), 2),
+               plain_ms=round(ms_plain, 3), codec_ms=round(ms_codec, 3),
+               speedup=round(ms_plain / ms_codec, 4),
+               cos_mean=round(float(cos.mean()), 5), cos_p1=round(float(np.percentile(cos, 1)), 5),
+               cos_min=round(float(cos.min()), 5),
+               frac_cos_ge_099=round(float((cos >= 0.99).mean()), 5),
+               tuning=tuning,
+               train=dict(scenes=[1041, 1042, 1043], rows=nrows, segments=nseg, weights=nnz,
+                          steps=steps, batch_rows=8192, seconds=round(t2 - t1, 2),
+                          loss_first=round(float(hist[:5].mean()), 5),
+                          loss_last=round(float(hist[-20:].mean()), 5),
+                          setup_seconds=round(t1 - t0, 1)))
+    _log("codec:", json.dumps(out))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +160,9 @@ def main():
                     help="seconds of oracle work for the CPU baseline (0 = skip)")
     ap.add_argument("--no-count", action="store_true", help="skip the counting lift")
     ap.add_argument("--eager", action="store_true", help="time eager lifts instead of graph replays")
+    ap.add_argument("--no-codec", action="store_true", help="skip the codec section")
+    ap.add_argument("--codec-steps", type=int, default=2000)
+    ap.add_argument("--codec-reps", type=int, default=5)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="also run one plain device copy of BYTES (read) + BYTES (write), "
                          "to scale hardware traffic counters")
@@ -129,7 +204,8 @@ def main():
 
     # timed region: graph replays of the whole lift (the first lift runs
     # eagerly and captures the launch sequence; warm-up covers it)
-    flags = slag.SLAG_FLAG_PROFILE | (0 if args.eager else slag.SLAG_FLAG_GRAPH)
+    flags = slag.SLAG_FLAG_PROFILE | slag.SLAG_FLAG_AUTOTUNE | \
+        (0 if args.eager else slag.SLAG_FLAG_GRAPH)
     L = slag.Lifter(0, flags=flags)
     L.set_scene(scene, device_tensors=True)
     for _ in range(max(args.warmup, 1)):
@@ -149,12 +225,14 @@ def main():
     E, den = L.embeddings()
     assert np.isfinite(E).all()
     info = L.stats()
+    tuning = slag.slag_get_tuning(L.ctx)
+    _log("tuning:", json.dumps(tuning))
     L.close()
 
     # per-stage HIP events (same kernels, launched eagerly on the library's
     # stream; a graph replay records no per-stage events)
     stage_ms = {}
-    with slag.Lifter(0, flags=slag.SLAG_FLAG_PROFILE) as Lp:
+    with slag.Lifter(0, flags=slag.SLAG_FLAG_PROFILE | slag.SLAG_FLAG_AUTOTUNE) as Lp:
         Lp.set_scene(scene, device_tensors=True)
         Lp.lift()
         Lp.stats()
@@ -175,6 +253,10 @@ def main():
                     frac=round(ach / VALU_PEAK_TOPS, 4), traffic=measured_traffic(),
                     ops_per_test=OPS_PER_TEST, tests_per_launch=n_tests,
                     avg_launch_ms=round(comp_ms, 4), dominant_stage=dom)
+
+    codec = None
+    if not args.no_codec:
+        codec = codec_section(args, slag, torch)
 
     cpu = None
     if args.cpu_budget > 0:
@@ -203,8 +285,10 @@ def main():
         "n_intersections": info["n_intersections"],
         "ms_per_step_hip_events": round(ev_total / args.steps, 4),
         "launch": "eager" if args.eager else "hip graph replay",
+        "tuning": tuning,
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": roof,
+        "codec": codec,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

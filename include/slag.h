@@ -66,11 +66,14 @@ enum {
     SLAG_FLAG_PROFILE = 1,      /* record per-stage HIP events (slag_get_stats) */
     SLAG_FLAG_COUNT = 2,        /* count blends and tests (slag_get_stats) */
     SLAG_FLAG_KEEP_DEBUG = 4,   /* keep the last view batch's tile lists and W rows */
-    SLAG_FLAG_GRAPH = 8         /* replay the lift as one HIP graph while the inputs are
+    SLAG_FLAG_GRAPH = 8,        /* replay the lift as one HIP graph while the inputs are
                                    unchanged: the first lift after an input change runs
                                    eagerly (sizing every buffer) and captures its launch
                                    sequence; later lifts launch the graph.  Replays record
                                    ms_total but no per-stage times. */
+    SLAG_FLAG_AUTOTUNE = 16     /* eager lifts time every compositing variant once per image
+                                   size (all give bitwise-equal results) and keep the
+                                   fastest for later lifts of this context */
 };
 
 typedef struct {
@@ -141,6 +144,18 @@ slag_status slag_get_embeddings(slag_ctx* ctx, float* out, float* den, slag_mem 
 
 slag_status slag_get_stats(slag_ctx* ctx, slag_stats* stats);
 const char* slag_stage_name(int32_t stage);
+
+/* Compositing variant chosen per image size (SLAG_FLAG_AUTOTUNE), with the
+ * time of each variant on the lift that tuned it. */
+typedef struct {
+    int32_t width, height;
+    int32_t variant;                /* index of the fastest, see slag_variant_name() */
+    int32_t n_variants;
+    float ms[8];                    /* per variant, compositing of this image size */
+} slag_tuning;
+/* Copies up to `cap` entries to out; *n receives the number of tuned sizes. */
+slag_status slag_get_tuning(slag_ctx* ctx, slag_tuning* out, int32_t cap, int32_t* n);
+const char* slag_variant_name(int32_t variant);
 
 /* Debug exports for the last view batch (needs SLAG_FLAG_KEEP_DEBUG).
  * Tile lists of view `view`: entries ordered by (tile, depth, Gaussian) with

@@ -23,7 +23,8 @@ SLAG_OK, SLAG_E_INVALID_ARG, SLAG_E_OUT_OF_MEMORY, SLAG_E_DEVICE, SLAG_E_STATE, 
     SLAG_E_CAPACITY, SLAG_E_NOT_SUPPORTED = range(7)
 SLAG_HOST, SLAG_DEVICE = 0, 1
 SLAG_F32, SLAG_BF16 = 0, 1
-SLAG_FLAG_PROFILE, SLAG_FLAG_COUNT, SLAG_FLAG_KEEP_DEBUG, SLAG_FLAG_GRAPH = 1, 2, 4, 8
+SLAG_FLAG_PROFILE, SLAG_FLAG_COUNT, SLAG_FLAG_KEEP_DEBUG, SLAG_FLAG_GRAPH, SLAG_FLAG_AUTOTUNE = \
+    1, 2, 4, 8, 16
 
 STATUS_NAMES = {0: "SLAG_OK", 1: "SLAG_E_INVALID_ARG", 2: "SLAG_E_OUT_OF_MEMORY",
                 3: "SLAG_E_DEVICE", 4: "SLAG_E_STATE", 5: "SLAG_E_CAPACITY",
@@ -51,6 +52,11 @@ class slag_stats(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class slag_tuning(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("n_variants", ctypes.c_int32), ("ms", ctypes.c_float * 8)]
+
+
 class slag_train_cfg(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int32), ("batch_rows", ctypes.c_int32), ("lr", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
@@ -60,7 +66,7 @@ class slag_train_cfg(ctypes.Structure):
 EXPORTS = ["slag_create", "slag_destroy", "slag_last_error", "slag_set_gaussians",
            "slag_set_cameras", "slag_set_segments", "slag_set_features", "slag_lift",
            "slag_get_embeddings", "slag_get_stats", "slag_stage_name", "slag_debug_tile_lists",
-           "slag_debug_weights",
+           "slag_debug_weights", "slag_get_tuning", "slag_variant_name",
            # include/slag_codec.h
            "slag_codec_init", "slag_codec_get_params", "slag_codec_clear_pool",
            "slag_codec_set_pool", "slag_codec_add_lift_rows", "slag_codec_pool_size",
@@ -95,6 +101,9 @@ def lib():
     L.slag_stage_name.restype = ctypes.c_char_p
     L.slag_debug_tile_lists.argtypes = [P, I32, P, P, P, I64, ctypes.POINTER(I64)]
     L.slag_debug_weights.argtypes = [P, I32, P, P, P, I64, ctypes.POINTER(I64)]
+    L.slag_get_tuning.argtypes = [P, ctypes.POINTER(slag_tuning), I32, ctypes.POINTER(I32)]
+    L.slag_variant_name.argtypes = [I32]
+    L.slag_variant_name.restype = ctypes.c_char_p
     L.slag_codec_init.argtypes = [P, I32, I32, I32, I32, P, I32]
     L.slag_codec_get_params.argtypes = [P, P, I32]
     L.slag_codec_clear_pool.argtypes = [P]
@@ -107,7 +116,7 @@ def lib():
     L.slag_lift_codec.argtypes = [P]
     L.slag_get_codes.argtypes = [P, P, I32]
     for f in EXPORTS:
-        if f not in ("slag_destroy", "slag_last_error", "slag_stage_name"):
+        if f not in ("slag_destroy", "slag_last_error", "slag_stage_name", "slag_variant_name"):
             getattr(L, f).restype = I32
     _lib_handle = L
     return L
@@ -195,6 +204,19 @@ def slag_get_stats(ctx) -> dict:
     d = {f: getattr(s, f) for f, _ in slag_stats._fields_ if f not in ("ms_stage", "reserved")}
     d["ms_stage"] = {lib().slag_stage_name(i).decode(): s.ms_stage[i] for i in range(s.n_stages)}
     return d
+
+
+def slag_get_tuning(ctx) -> list:
+    n = ctypes.c_int32(0)
+    _check(ctx, lib().slag_get_tuning(ctx, None, 0, ctypes.byref(n)))
+    arr = (slag_tuning * max(n.value, 1))()
+    _check(ctx, lib().slag_get_tuning(ctx, arr, n.value, ctypes.byref(n)))
+    out = []
+    for t in arr[:n.value]:
+        out.append(dict(width=t.width, height=t.height, variant=t.variant,
+                        name=lib().slag_variant_name(t.variant).decode(),
+                        ms=[round(t.ms[i], 4) for i in range(t.n_variants)]))
+    return out
 
 
 def slag_debug_tile_lists(ctx, view: int):

@@ -136,63 +136,104 @@ __device__ __forceinline__ float wave_total(float v)
 
 enum { MODE_NONE = 0, MODE_UNIFORM = 1, MODE_MIXED = 2 };
 
-// Blend this wave's compacted entries of one batch into its 64 pixels.
-template <int MODE, bool COUNTING>
+// Wave sums of four per-lane values: on return every lane of row r (lanes
+// 16 r .. 16 r + 15) holds the sum of value r over all 64 lanes.  Two lane
+// swaps across the wave halves, one across rows, then a DPP row sum: about
+// ten instructions for four sums.
+__device__ __forceinline__ float wave_sum4(float v0, float v1, float v2, float v3)
+{
+    const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v0), __float_as_uint(v2),
+                                                    false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v1), __float_as_uint(v3),
+                                                    false, false);
+    const float x0 = __uint_as_float(a[0]) + __uint_as_float(a[1]);   // lanes 0-31: v0, 32-63: v2
+    const float x1 = __uint_as_float(b[0]) + __uint_as_float(b[1]);   // lanes 0-31: v1, 32-63: v3
+    const auto c = __builtin_amdgcn_permlane16_swap(__float_as_uint(x0), __float_as_uint(x1),
+                                                    false, false);
+    return row_sum(__uint_as_float(c[0]) + __uint_as_float(c[1]));    // row r: value r
+}
+
+// Blend this wave's compacted entries of one batch into its 64 pixels, four
+// entries at a time; the four entries' per-segment weight sums over the
+// wave's pixels go to acc[batch entry][segment slot].
+template <int MODE, bool COUNTING, bool PAD>
 __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const float4* __restrict__ w1,
                                             const int* __restrict__ wj, int cnt, float fpx, float fpy,
-                                            int px, int py, int slot, int uslot, float& T, bool& done,
-                                            float (*acc)[NS_CAP], int lane,
+                                            int px, int py, int slot, int uslot, uint32_t slot_mask,
+                                            float& T, bool& done, float (*acc)[NS_CAP], int lane,
                                             unsigned long long& n_acc, unsigned long long& n_box,
                                             unsigned long long& n_tile)
 {
     const bool slot_ok = slot >= 0;
-    for (int jj = 0; jj < cnt; jj++) {
-        const float4 p0 = w0[jj];
-        const float4 p1 = w1[jj];
-        const float dx = fpx - p0.x, dy = fpy - p0.y;
-        float e = fmaf(dx, fmaf(p0.z, dx, p0.w * dy), p1.x * dy * dy);
-        e = fminf(e, 0.0f);
-        const float alpha = fminf(AMAX, p1.y * __builtin_amdgcn_exp2f(e));
-        const float Tn = fmaf(-alpha, T, T);
-        const bool ok = !done && alpha >= AMIN;
-        const bool stop = ok && Tn < TMIN;
-        const bool take = ok && !stop;
-        const float w = take ? alpha * T : 0.0f;
-        if (COUNTING) {
-            if (!done) {
-                n_tile++;
-                const uint32_t a = __float_as_uint(p1.z), b = __float_as_uint(p1.w);
-                n_box += (px >= (int)(a & 0xFFFFu) && px <= (int)(b & 0xFFFFu) &&
-                          py >= (int)(a >> 16) && py <= (int)(b >> 16));
+    const int r = lane >> 4;
+    const bool writer = (lane & 15) == 0;
+    for (int g = 0; g < cnt; g += 4) {
+        float w[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            // PAD: entries past cnt (up to the next multiple of four) are null:
+            // opacity 0, so alpha = 0 and nothing changes; else skip them
+            const int jj = g + u;
+            if (!PAD) {
+                w[u] = 0.0f;
+                if (jj >= cnt) continue;                 // wave-uniform
             }
-            n_acc += take;
+            const float4 p0 = w0[jj];
+            const float4 p1 = w1[jj];
+            const float dx = fpx - p0.x, dy = fpy - p0.y;
+            float e = fmaf(dx, fmaf(p0.z, dx, p0.w * dy), p1.x * dy * dy);
+            e = fminf(e, 0.0f);
+            const float alpha = fminf(AMAX, p1.y * __builtin_amdgcn_exp2f(e));
+            const float Tn = fmaf(-alpha, T, T);
+            if (COUNTING) {
+                const bool ok = !done && alpha >= AMIN;
+                const bool stop = ok && Tn < TMIN;
+                const bool take = ok && !stop;
+                w[u] = (take && slot_ok) ? alpha * T : 0.0f;
+                if (!done && jj < cnt) {
+                    n_tile++;
+                    const uint32_t a = __float_as_uint(p1.z), b = __float_as_uint(p1.w);
+                    n_box += (px >= (int)(a & 0xFFFFu) && px <= (int)(b & 0xFFFFu) &&
+                              py >= (int)(a >> 16) && py <= (int)(b >> 16));
+                }
+                n_acc += take;
+                T = take ? Tn : T;
+                done = done || stop;
+            } else {
+                // T = 0 marks a finished pixel (stopped, or nothing to add in
+                // this pass): then Tn = 0 < TMIN and w = 0 from here on
+                const bool ok = alpha >= AMIN;
+                const bool keep = Tn >= TMIN;
+                w[u] = (ok && keep) ? alpha * T : 0.0f;
+                T = ok ? (keep ? Tn : 0.0f) : T;
+            }
         }
-        T = take ? Tn : T;
-        done = done || stop;
+        if (!COUNTING) done = T == 0.0f;
+        const int jr = g + r;
         if (MODE == MODE_UNIFORM) {
-            const float wm = slot_ok ? w : 0.0f;
-            if (__any(wm > 0.0f)) {
-                const float s = wave_total(wm);
-                if (lane == 0) acc[wj[jj]][uslot] = s;
-            }
+            const float s = wave_sum4(w[0], w[1], w[2], w[3]);
+            if (writer && jr < cnt) acc[wj[jr]][uslot] = s;
         } else if (MODE == MODE_MIXED) {
-            const float wm = slot_ok ? w : 0.0f;
-            uint64_t m = __ballot(wm > 0.0f);
-            while (m) {
-                const int sl = __builtin_amdgcn_readlane(slot, __ffsll((long long)m) - 1);
+            uint32_t sm = slot_mask;
+            while (sm) {
+                const int sl = __builtin_ctz(sm);
+                sm &= sm - 1u;
                 const bool mine = slot == sl;
-                const float s = wave_total(mine ? wm : 0.0f);
-                if (lane == 0) acc[wj[jj]][sl] = s;
-                m &= ~__ballot(mine);
+                const float s = wave_sum4(mine ? w[0] : 0.0f, mine ? w[1] : 0.0f,
+                                          mine ? w[2] : 0.0f, mine ? w[3] : 0.0f);
+                if (writer && jr < cnt) acc[wj[jr]][sl] = s;
             }
         }
         if (__all(done)) break;
     }
 }
 
-template <bool COUNT>
-__global__ __launch_bounds__(256) void k_composite(
-    const uint32_t* __restrict__ order,
+// Variants (same arithmetic, bitwise-equal results): MINW = waves per SIMD
+// the register budget must allow; PAD = four-entry groups padded with null
+// entries (loads of a group can be issued together) or cut at the end.
+template <bool COUNT, int MINW, bool PAD>
+__global__ __launch_bounds__(256, MINW) void k_composite(
+    const uint32_t* __restrict__ order, uint32_t obase,
     const uint32_t* __restrict__ bucket_view, const ViewDev* __restrict__ views,
     const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ bend,
     const uint32_t* __restrict__ ival, const uint32_t* __restrict__ islot,
@@ -207,7 +248,7 @@ __global__ __launch_bounds__(256) void k_composite(
     __shared__ uint32_t s_off[BATCH];         // part slot of (pair, this tile, first pass segment)
     __shared__ uint16_t s_seg[TILE_PIX];
 
-    const uint32_t b = order[blockIdx.x];     // tiles with the longest lists first
+    const uint32_t b = order[obase + blockIdx.x];   // tiles with the longest lists first
     const uint32_t start = bstart[b], end = bend[b];
     if (start >= end) return;
     const uint32_t ns = ns_tile[b];
@@ -244,8 +285,10 @@ __global__ __launch_bounds__(256) void k_composite(
         const int nsc = min(NS_CAP, (int)ns - g0);
         const bool counting = COUNT && pass == 0;
         const int slot = (ls >= g0 && ls < g0 + NS_CAP) ? ls - g0 : -1;
-        // wave-uniform slot when every accumulating lane shares one segment
+        // wave-uniform slot when every accumulating lane shares one segment;
+        // else the set of slots present in the wave
         int mode = MODE_NONE, uslot = -1;
+        uint32_t slot_mask = 0;
         {
             const uint64_t has = __ballot(slot >= 0);
             if (has) {
@@ -253,10 +296,12 @@ __global__ __launch_bounds__(256) void k_composite(
                 const bool mixed = __ballot(slot >= 0 && slot != first) != 0;
                 mode = mixed ? MODE_MIXED : MODE_UNIFORM;
                 uslot = first;
+                for (int k = 0; k < nsc; k++)
+                    if (__ballot(slot == k)) slot_mask |= 1u << k;
             }
         }
         bool done = counting ? !valid : (slot < 0);
-        float T = 1.0f;
+        float T = (counting || slot >= 0) ? 1.0f : 0.0f;
         for (int i = lane; i < BATCH * NS_CAP; i += 64) (&s_acc[wv][0][0])[i] = 0.0f;
         // lane l holds entry l of the batch.  Two-deep prefetch: records of the
         // next batch and list entries of the one after are in flight while a
@@ -281,6 +326,10 @@ __global__ __launch_bounds__(256) void k_composite(
                 s_w1[wv][k] = make_float4(q1.x * NHALF_LOG2E, q1.y, q1.z, q1.w);
                 s_wj[wv][k] = lane;
             }
+            if (PAD && lane >= cnt && lane < ((cnt + 3) & ~3)) {   // null entries up to a multiple of 4
+                s_w0[wv][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                s_w1[wv][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
             if (wv == 0 && lane < nb) s_off[lane] = qo + (uint32_t)g0;
             q0 = rec[2 * (size_t)pn];
             q1 = rec[2 * (size_t)pn + 1];
@@ -292,16 +341,16 @@ __global__ __launch_bounds__(256) void k_composite(
             if (cnt && !__all(done)) {
                 if (counting) {
                     if (mode == MODE_UNIFORM)
-                        blend_batch<MODE_UNIFORM, true>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                        blend_batch<MODE_UNIFORM, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
                     else if (mode == MODE_MIXED)
-                        blend_batch<MODE_MIXED, true>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                        blend_batch<MODE_MIXED, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
                     else
-                        blend_batch<MODE_NONE, true>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                        blend_batch<MODE_NONE, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
                 } else {
                     if (mode == MODE_UNIFORM)
-                        blend_batch<MODE_UNIFORM, false>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                        blend_batch<MODE_UNIFORM, false, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
                     else
-                        blend_batch<MODE_MIXED, false>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                        blend_batch<MODE_MIXED, false, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
                 }
             }
             __syncthreads();
@@ -376,22 +425,38 @@ void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t*
     hipLaunchKernelGGL(k_sat, dim3(nb), dim3(256), 0, st, views, ns_tile, sat);
 }
 
-void launch_composite(bool count, uint32_t nbuckets, const uint32_t* order,
-                      const uint32_t* bucket_view, const ViewDev* views, const uint32_t* bstart,
-                      const uint32_t* bend, const uint32_t* ival, const uint32_t* islot,
-                      const float4* rec, const uint32_t* ns_tile, const uint16_t* segl,
-                      const int32_t* ids, uint2* part, unsigned long long* counters,
-                      hipStream_t st)
+int composite_variants() { return 4; }
+
+const char* composite_variant_name(int v)
+{
+    static const char* names[4] = {"occupancy 8, padded groups", "occupancy 6, padded groups",
+                                   "occupancy 5, padded groups", "occupancy 8, cut groups"};
+    return (v >= 0 && v < 4) ? names[v] : "";
+}
+
+void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t* order,
+                      uint32_t obase, const uint32_t* bucket_view, const ViewDev* views,
+                      const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
+                      const uint32_t* islot, const float4* rec, const uint32_t* ns_tile,
+                      const uint16_t* segl, const int32_t* ids, uint2* part,
+                      unsigned long long* counters, hipStream_t st)
 {
     if (!nbuckets) return;
-    if (count)
-        hipLaunchKernelGGL(k_composite<true>, dim3(nbuckets), dim3(256), 0, st, order, bucket_view,
-                           views, bstart, bend, ival, islot, rec, ns_tile, segl, ids, part,
-                           counters);
-    else
-        hipLaunchKernelGGL(k_composite<false>, dim3(nbuckets), dim3(256), 0, st, order,
-                           bucket_view, views, bstart, bend, ival, islot, rec, ns_tile, segl, ids,
-                           part, counters);
+#define SLAG_COMP(C, W, P)                                                                         \
+    hipLaunchKernelGGL((k_composite<C, W, P>), dim3(nbuckets), dim3(256), 0, st, order, obase,     \
+                       bucket_view, views, bstart, bend, ival, islot, rec, ns_tile, segl, ids,    \
+                       part, counters)
+    if (count) {
+        SLAG_COMP(true, 8, false);
+        return;
+    }
+    switch (variant) {
+    case 1: SLAG_COMP(false, 6, true); break;
+    case 2: SLAG_COMP(false, 5, true); break;
+    case 3: SLAG_COMP(false, 8, false); break;
+    default: SLAG_COMP(false, 8, true); break;
+    }
+#undef SLAG_COMP
 }
 
 void launch_merge(uint64_t npairs, const uint16_t* pview, const ViewDev* views,

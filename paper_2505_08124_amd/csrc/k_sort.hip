@@ -308,7 +308,9 @@ __global__ __launch_bounds__(256) void k_rank_tiles(uint64_t npairs, const uint3
 }
 
 // (tile, pair, part slot) entries of every pair in depth order, tiles of a
-// pair in row-major order.  A wave emits the consecutive output range of its 64 pairs
+// pair in row-major order; the tile key is (view in launch << lbits) | tile in
+// view.  Pairs come view-major, so a stable sort on the low lbits alone
+// leaves each (view, tile) list contiguous and in depth order.  A wave emits the consecutive output range of its 64 pairs
 // together: output slot e finds its pair among the wave's 64 offsets, so the
 // stores are coalesced.
 __global__ __launch_bounds__(256) void k_emit_isect(uint64_t npairs, const uint32_t* __restrict__ order,
@@ -318,6 +320,7 @@ __global__ __launch_bounds__(256) void k_emit_isect(uint64_t npairs, const uint3
                                                     const uint32_t* __restrict__ ioff,
                                                     const uint32_t* __restrict__ part_base,
                                                     const uint32_t* __restrict__ sat,
+                                                    int lbits,
                                                     uint32_t* __restrict__ ikey,
                                                     uint32_t* __restrict__ ival,
                                                     uint32_t* __restrict__ islot)
@@ -342,7 +345,7 @@ __global__ __launch_bounds__(256) void k_emit_isect(uint64_t npairs, const uint3
         o = ioff[r];
         tc = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
         s_p[w][lane] = p;
-        s_r[w][lane][0] = V.tile_base + (uint32_t)(ty0 * V.ntx + tx0);
+        s_r[w][lane][0] = ((uint32_t)pview[p] << lbits) + (uint32_t)(ty0 * V.ntx + tx0);
         s_r[w][lane][1] = (uint32_t)(tx1 - tx0 + 1);
         s_r[w][lane][2] = (uint32_t)V.ntx;
         s_q[w][lane][0] = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
@@ -386,20 +389,29 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint64_t n, uint3
         p[i] = v;
 }
 
+// Keys are (view in launch << lbits) | tile in view; bucket = the view's tile
+// base + tile.
 __global__ __launch_bounds__(256) void k_bucket_ranges(uint64_t ni, const uint32_t* __restrict__ ikey,
+                                                       const ViewDev* __restrict__ views, int lbits,
                                                        uint32_t* __restrict__ bstart,
                                                        uint32_t* __restrict__ bend)
 {
     const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= ni) return;
     const uint32_t k = ikey[i];
-    if (i == 0 || ikey[i - 1] != k) bstart[k] = (uint32_t)i;
-    if (i + 1 == ni || ikey[i + 1] != k) bend[k] = (uint32_t)(i + 1);
+    const bool first = i == 0 || ikey[i - 1] != k, lastk = i + 1 == ni || ikey[i + 1] != k;
+    if (!first && !lastk) return;
+    const uint32_t b = views[k >> lbits].tile_base + (k & ((1u << lbits) - 1u));
+    if (first) bstart[b] = (uint32_t)i;
+    if (lastk) bend[b] = (uint32_t)(i + 1);
 }
 
 // Dispatch-order keys: longer tile lists first (key = 0xFFFF - min(len, 0xFFFF)
 // sorts ascending into descending length; equal keys keep tile order).
-__global__ __launch_bounds__(256) void k_bucket_keys(uint32_t nb, const uint32_t* __restrict__ bstart,
+__global__ __launch_bounds__(256) void k_bucket_keys(uint32_t nb,
+                                                     const uint32_t* __restrict__ bucket_view,
+                                                     const uint8_t* __restrict__ view_cls,
+                                                     const uint32_t* __restrict__ bstart,
                                                      const uint32_t* __restrict__ bend,
                                                      uint32_t* __restrict__ key,
                                                      uint32_t* __restrict__ val)
@@ -407,7 +419,7 @@ __global__ __launch_bounds__(256) void k_bucket_keys(uint32_t nb, const uint32_t
     const uint32_t b = blockIdx.x * 256 + threadIdx.x;
     if (b >= nb) return;
     const uint32_t len = bend[b] - bstart[b];
-    key[b] = 0xFFFFu - min(len, 0xFFFFu);
+    key[b] = ((uint32_t)view_cls[bucket_view[b]] << 16) | (0xFFFFu - min(len, 0xFFFFu));
     val[b] = b;
 }
 
@@ -489,12 +501,12 @@ void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const uint32_t* p
 
 void launch_emit_isect(uint64_t npairs, const uint32_t* order, const float4* rec,
                        const uint16_t* pview, const ViewDev* views, const uint32_t* ioff,
-                       const uint32_t* part_base, const uint32_t* sat, uint32_t* ikey,
+                       const uint32_t* part_base, const uint32_t* sat, int lbits, uint32_t* ikey,
                        uint32_t* ival, uint32_t* islot, hipStream_t st)
 {
     if (!npairs) return;
     hipLaunchKernelGGL(k_emit_isect, dim3(grid_for(npairs)), dim3(256), 0, st, npairs, order, rec,
-                       pview, views, ioff, part_base, sat, ikey, ival, islot);
+                       pview, views, ioff, part_base, sat, lbits, ikey, ival, islot);
 }
 
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st)
@@ -505,20 +517,21 @@ void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st)
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)g), dim3(256), 0, st, p, n, v);
 }
 
-void launch_bucket_ranges(uint64_t ni, const uint32_t* ikey, uint32_t* bstart, uint32_t* bend,
-                          hipStream_t st)
+void launch_bucket_ranges(uint64_t ni, const uint32_t* ikey, const ViewDev* views, int lbits,
+                          uint32_t* bstart, uint32_t* bend, hipStream_t st)
 {
     if (!ni) return;
-    hipLaunchKernelGGL(k_bucket_ranges, dim3(grid_for(ni)), dim3(256), 0, st, ni, ikey, bstart,
-                       bend);
+    hipLaunchKernelGGL(k_bucket_ranges, dim3(grid_for(ni)), dim3(256), 0, st, ni, ikey, views,
+                       lbits, bstart, bend);
 }
 
-void launch_bucket_keys(uint32_t nb, const uint32_t* bstart, const uint32_t* bend, uint32_t* key,
+void launch_bucket_keys(uint32_t nb, const uint32_t* bucket_view, const uint8_t* view_cls,
+                        const uint32_t* bstart, const uint32_t* bend, uint32_t* key,
                         uint32_t* val, hipStream_t st)
 {
     if (!nb) return;
-    hipLaunchKernelGGL(k_bucket_keys, dim3(grid_for(nb)), dim3(256), 0, st, nb, bstart, bend, key,
-                       val);
+    hipLaunchKernelGGL(k_bucket_keys, dim3(grid_for(nb)), dim3(256), 0, st, nb, bucket_view,
+                       view_cls, bstart, bend, key, val);
 }
 
 }  // namespace slag

@@ -183,7 +183,7 @@ static slag_status morton_order(slag_ctx* c, int64_t n)
 
 static slag_status build_plan(slag_ctx* c)
 {
-    for (auto& b : c->plan) { release(b.views); release(b.bucket_view); }
+    for (auto& b : c->plan) { release(b.views); release(b.bucket_view); release(b.view_cls); }
     c->plan.clear();
     const int V = c->nviews;
     int maxv = c->opt.max_views_per_launch > 0 ? c->opt.max_views_per_launch : V;
@@ -192,12 +192,23 @@ static slag_status build_plan(slag_ctx* c)
     const int64_t n = std::max<int64_t>(c->n, 1);
     const int64_t cap_pairs = (int64_t)1 << 31;
     maxv = (int)std::max<int64_t>(1, std::min<int64_t>(maxv, cap_pairs / n));
+    // tile-sort keys are (view in launch << lbits) | tile in view, 32 bits
+    int lbits = 0;
+    for (int v = 0; v < V; v++) {
+        const int64_t nt = (int64_t)((c->cams[v].width + TILE - 1) / TILE) *
+                           ((c->cams[v].height + TILE - 1) / TILE);
+        lbits = std::max(lbits, bit_length((uint64_t)std::max<int64_t>(nt - 1, 0)));
+    }
+    lbits = std::max(lbits, 1);
+    if (lbits > 31) FAIL(c, SLAG_E_CAPACITY, "image too large for 32-bit tile keys");
+    maxv = (int)std::min<int64_t>(maxv, (int64_t)1 << (32 - lbits));
     std::vector<uint64_t> seg_off(V + 1, 0);
     for (int v = 0; v < V; v++) seg_off[v + 1] = seg_off[v] + (uint64_t)c->nseg[v];
     for (int v0 = 0; v0 < V; v0 += maxv) {
         Batch b;
         b.v0 = v0;
         b.nb = std::min(maxv, V - v0);
+        b.lbits = lbits;
         std::vector<ViewDev> vd(b.nb);
         std::vector<uint32_t> bv;
         uint32_t tb = 0, so = 0;
@@ -227,6 +238,29 @@ static slag_status build_plan(slag_ctx* c)
         }
         b.nbuckets = tb;
         b.nsat = so;
+        // resolution classes
+        std::vector<uint8_t> vcls(b.nb);
+        for (int i = 0; i < b.nb; i++) {
+            const uint32_t W = (uint32_t)vd[i].W, H = (uint32_t)vd[i].H;
+            int k = 0;
+            while (k < b.ncls && !(b.cls_w[k] == W && b.cls_h[k] == H)) k++;
+            if (k == b.ncls) {
+                if (b.ncls < 256) {
+                    b.cls_w.push_back(W);
+                    b.cls_h.push_back(H);
+                    b.cls_nb.push_back(0);
+                    b.ncls++;
+                } else {
+                    k = 255;   // beyond 256 sizes: share the last class
+                }
+            }
+            vcls[i] = (uint8_t)k;
+            b.cls_nb[k] += (uint32_t)(vd[i].ntx * vd[i].nty);
+        }
+        b.cls_off.assign(b.ncls + 1, 0);
+        for (int k = 0; k < b.ncls; k++) b.cls_off[k + 1] = b.cls_off[k] + b.cls_nb[k];
+        CK(ensure(c, b.view_cls, vcls.size() + 16));
+        HC(c, hipMemcpy(b.view_cls.p, vcls.data(), vcls.size(), hipMemcpyHostToDevice));
         CK(ensure(c, b.views, vd.size() * sizeof(ViewDev)));
         CK(ensure(c, b.bucket_view, bv.size() * sizeof(uint32_t)));
         HC(c, hipMemcpy(b.views.p, vd.data(), vd.size() * sizeof(ViewDev), hipMemcpyHostToDevice));
@@ -240,6 +274,28 @@ static slag_status build_plan(slag_ctx* c)
 }
 
 // ------------------------------------------------------------------ the lift
+
+// Time every compositing variant on one resolution class (second of two
+// runs each, so caches are warm) and keep the fastest.
+template <typename F>
+static slag_status tune_class(slag_ctx* c, TuneEntry& te, F&& launch)
+{
+    for (int i = 0; i < 2; i++)
+        if (!c->tune_ev[i]) HC(c, hipEventCreate(&c->tune_ev[i]));
+    float best = 0.0f;
+    for (int v = 0; v < te.n_variants; v++) {
+        launch(v);
+        HC(c, hipEventRecord(c->tune_ev[0], c->st));
+        launch(v);
+        HC(c, hipEventRecord(c->tune_ev[1], c->st));
+        HC(c, hipEventSynchronize(c->tune_ev[1]));
+        float ms = 0.0f;
+        HC(c, hipEventElapsedTime(&ms, c->tune_ev[0], c->tune_ev[1]));
+        te.ms[v] = ms;
+        if (v == 0 || ms < best) { best = ms; te.variant = v; }
+    }
+    return SLAG_OK;
+}
 
 // What the contraction multiplies the weights with, and where it writes.
 struct ContractTarget {
@@ -366,8 +422,8 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         scan_u32(c->tcr.as<uint32_t>(), npairs, nullptr, c->scan_ws.p, st);
         launch_emit_isect(npairs, order, c->rec.as<float4>(), c->pview.as<uint16_t>(), views,
                           c->tcr.as<uint32_t>(), c->psz.as<uint32_t>(), c->sat.as<uint32_t>(),
-                          c->ikey.as<uint32_t>(), c->ival.as<uint32_t>(), c->islot.as<uint32_t>(),
-                          st);
+                          B.lbits, c->ikey.as<uint32_t>(), c->ival.as<uint32_t>(),
+                          c->islot.as<uint32_t>(), st);
         CK(stage_end(c, ST_BIN, ev));
 
         // stable sort by tile -> per-tile lists in (depth, Gaussian) order
@@ -375,7 +431,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         const bool alt2 = radix_sort_u32_v2(
             c->ikey.as<uint32_t>(), c->ival.as<uint32_t>(), c->islot.as<uint32_t>(),
             c->ikey_alt.as<uint32_t>(), c->ival_alt.as<uint32_t>(), c->islot_alt.as<uint32_t>(), ni,
-            bit_length(B.nbuckets > 0 ? B.nbuckets - 1 : 0), c->hist.as<uint32_t>(), c->scan_ws.p,
+            B.lbits, c->hist.as<uint32_t>(), c->scan_ws.p,
             st);
         skey = alt2 ? c->ikey_alt.as<uint32_t>() : c->ikey.as<uint32_t>();
         sval = alt2 ? c->ival_alt.as<uint32_t>() : c->ival.as<uint32_t>();
@@ -384,7 +440,8 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         CK(ensure(c, c->bend, (size_t)B.nbuckets * 4 + 4));
         launch_fill_u32(c->bstart.as<uint32_t>(), B.nbuckets, 0u, st);
         launch_fill_u32(c->bend.as<uint32_t>(), B.nbuckets, 0u, st);
-        launch_bucket_ranges(ni, skey, c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(), st);
+        launch_bucket_ranges(ni, skey, views, B.lbits, c->bstart.as<uint32_t>(),
+                             c->bend.as<uint32_t>(), st);
         // dispatch order of the compositing workgroups: longest lists first
         CK(ensure(c, c->bkey, (size_t)B.nbuckets * 4 + 4));
         CK(ensure(c, c->bkey_alt, (size_t)B.nbuckets * 4 + 4));
@@ -392,12 +449,13 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         CK(ensure(c, c->bord_alt, (size_t)B.nbuckets * 4 + 4));
         CK(ensure(c, c->hist, radix_hist_bytes(B.nbuckets)));
         CK(ensure_scan(c, B.nbuckets));
-        launch_bucket_keys(B.nbuckets, c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(),
+        launch_bucket_keys(B.nbuckets, B.bucket_view.as<uint32_t>(), B.view_cls.as<uint8_t>(),
+                           c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(),
                            c->bkey.as<uint32_t>(), c->bord.as<uint32_t>(), st);
         const bool alt3 = radix_sort_u32(c->bkey.as<uint32_t>(), c->bord.as<uint32_t>(),
                                          c->bkey_alt.as<uint32_t>(), c->bord_alt.as<uint32_t>(),
-                                         B.nbuckets, 16, c->hist.as<uint32_t>(), c->scan_ws.p,
-                                         nullptr, st);
+                                         B.nbuckets, 16 + bit_length((uint64_t)(B.ncls - 1)),
+                                         c->hist.as<uint32_t>(), c->scan_ws.p, nullptr, st);
         const uint32_t* border = alt3 ? c->bord_alt.as<uint32_t>() : c->bord.as<uint32_t>();
         CK(stage_end(c, ST_TILE_SORT, ev));
 
@@ -408,11 +466,30 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         CK(stage_end(c, ST_PART_PREP, ev));
 
         CK(stage_begin(c, ST_COMPOSITE, &ev));
-        launch_composite(count, B.nbuckets, border, B.bucket_view.as<uint32_t>(), views,
-                         c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(), sval, sslot,
-                         c->rec.as<float4>(), c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
-                         c->ids.as<int32_t>(), c->part.as<uint2>(),
-                         reinterpret_cast<unsigned long long*>(small + SM_COUNTERS), st);
+        for (int k = 0; k < B.ncls; k++) {
+            if (!B.cls_nb[k]) continue;
+            auto launch = [&](int var) {
+                launch_composite(count, var, B.cls_nb[k], border, B.cls_off[k],
+                                 B.bucket_view.as<uint32_t>(), views, c->bstart.as<uint32_t>(),
+                                 c->bend.as<uint32_t>(), sval, sslot, c->rec.as<float4>(),
+                                 c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
+                                 c->ids.as<int32_t>(), c->part.as<uint2>(),
+                                 reinterpret_cast<unsigned long long*>(small + SM_COUNTERS), st);
+            };
+            const uint64_t key = ((uint64_t)B.cls_w[k] << 32) | B.cls_h[k];
+            auto it = c->tune.find(key);
+            if (it == c->tune.end() && (c->opt.flags & SLAG_FLAG_AUTOTUNE) && !c->capturing &&
+                !count) {
+                // every variant writes the same part slots, so trying them all
+                // is itself a correct compositing of this class
+                TuneEntry te;
+                te.n_variants = std::min(composite_variants(), 8);
+                CK(tune_class(c, te, launch));
+                it = c->tune.emplace(key, te).first;
+                continue;
+            }
+            launch(it == c->tune.end() ? 0 : it->second.variant);
+        }
         CK(stage_end(c, ST_COMPOSITE, ev));
 
         if (c->opt.flags & SLAG_FLAG_KEEP_DEBUG) {
@@ -497,8 +574,10 @@ void slag_destroy(slag_ctx* c)
     destroy_graph(c);
     for (DevBuf* b : bufs) release(*b);
     codec_release(c);
-    for (auto& b : c->plan) { release(b.views); release(b.bucket_view); }
+    for (auto& b : c->plan) { release(b.views); release(b.bucket_view); release(b.view_cls); }
     for (auto& e : c->events) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
+    for (auto e : c->tune_ev)
+        if (e) hipEventDestroy(e);
     for (auto e : c->free_events) hipEventDestroy(e);
     if (c->host_small) hipHostFree(c->host_small);
     if (c->own_stream && c->st) hipStreamDestroy(c->st);
@@ -506,6 +585,26 @@ void slag_destroy(slag_ctx* c)
 }
 
 const char* slag_last_error(const slag_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+slag_status slag_get_tuning(slag_ctx* c, slag_tuning* out, int32_t cap, int32_t* n)
+{
+    if (!c || !n || cap < 0 || (cap > 0 && !out)) return SLAG_E_INVALID_ARG;
+    c->err.clear();
+    *n = (int32_t)c->tune.size();
+    int32_t i = 0;
+    for (const auto& kv : c->tune) {
+        if (i >= cap) break;
+        slag_tuning& t = out[i++];
+        t.width = (int32_t)(kv.first >> 32);
+        t.height = (int32_t)(kv.first & 0xFFFFFFFFu);
+        t.variant = kv.second.variant;
+        t.n_variants = kv.second.n_variants;
+        for (int v = 0; v < 8; v++) t.ms[v] = kv.second.ms[v];
+    }
+    return SLAG_OK;
+}
+
+const char* slag_variant_name(int32_t v) { return composite_variant_name(v); }
 
 const char* slag_stage_name(int32_t s)
 {
@@ -844,25 +943,25 @@ slag_status slag_debug_tile_lists(slag_ctx* c, int32_t view, uint32_t* tile, uin
     for (auto& b : c->plan)
         if (b.v0 == c->last_v0) B = &b;
     if (!B) FAIL(c, SLAG_E_STATE, "launch plan changed since the lift");
-    // tile base of the view within the launch
-    uint32_t tb = 0;
-    for (int i = c->last_v0; i < view; i++)
-        tb += (uint32_t)(((c->cams[i].width + TILE - 1) / TILE) * ((c->cams[i].height + TILE - 1) / TILE));
-    const uint32_t nt = (uint32_t)(((c->cams[view].width + TILE - 1) / TILE) *
-                                   ((c->cams[view].height + TILE - 1) / TILE));
-    int64_t m = 0;
+    // keys are (view in launch << lbits) | tile in view; lists come out
+    // tile-major within the key order, so sort this view's entries by tile
+    // (stable: depth order within a tile is kept)
+    const uint32_t vl = (uint32_t)(view - c->last_v0);
+    const uint32_t mask = (1u << B->lbits) - 1u;
+    std::vector<uint64_t> sel;
     for (uint64_t i = 0; i < ni; i++)
-        if (k[i] >= tb && k[i] < tb + nt) m++;
+        if ((k[i] >> B->lbits) == vl) sel.push_back(((uint64_t)(k[i] & mask) << 32) | (uint64_t)i);
+    std::stable_sort(sel.begin(), sel.end(),
+                     [](uint64_t a, uint64_t b) { return (a >> 32) < (b >> 32); });
+    const int64_t m = (int64_t)sel.size();
     *len = m;
     if (m > cap) return SLAG_OK;
-    int64_t o = 0;
-    for (uint64_t i = 0; i < ni; i++)
-        if (k[i] >= tb && k[i] < tb + nt) {
-            if (tile) tile[o] = k[i] - tb;
-            if (depth_bits) depth_bits[o] = pz[v[i]];
-            if (gauss) gauss[o] = pg[v[i]];
-            o++;
-        }
+    for (int64_t o = 0; o < m; o++) {
+        const uint64_t i = sel[o] & 0xFFFFFFFFull;
+        if (tile) tile[o] = (uint32_t)(sel[o] >> 32);
+        if (depth_bits) depth_bits[o] = pz[v[i]];
+        if (gauss) gauss[o] = pg[v[i]];
+    }
     return SLAG_OK;
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -32,6 +33,18 @@ struct Batch {
     // sizes read back by the last eager lift (reused while capturing a graph)
     uint64_t npairs = 0, ni = 0, nparts = 0;
     uint32_t zmin = 0, zmax = 0;
+    // resolution classes (distinct image sizes, first appearance order): the
+    // compositing runs one launch per class, with the class's tuned variant
+    int ncls = 0;
+    int lbits = 0;     // bits of the largest view's tile count (tile-sort key width)
+    std::vector<uint32_t> cls_w, cls_h, cls_nb, cls_off;
+    DevBuf view_cls;   // [nb] uint8 class of each view
+};
+
+struct TuneEntry {
+    int variant = 0;
+    int n_variants = 0;
+    float ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 struct TimedEvent {
@@ -103,6 +116,10 @@ struct slag_ctx {
     uint64_t* host_small = nullptr;   // pinned read-back area
 
     slag_host::CodecState codec;
+
+    // compositing variant per image size (SLAG_FLAG_AUTOTUNE), and the events that time them
+    std::map<uint64_t, slag_host::TuneEntry> tune;
+    hipEvent_t tune_ev[2] = {nullptr, nullptr};
 
     // graph replay of the lift (SLAG_FLAG_GRAPH)
     uint64_t gen = 1;                 // bumped by every input change

@@ -77,24 +77,29 @@ void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const uint32_t* p
                        hipStream_t st);
 void launch_emit_isect(uint64_t npairs, const uint32_t* order, const float4* rec,
                        const uint16_t* pview, const ViewDev* views, const uint32_t* ioff,
-                       const uint32_t* part_base, const uint32_t* sat, uint32_t* ikey,
+                       const uint32_t* part_base, const uint32_t* sat, int lbits, uint32_t* ikey,
                        uint32_t* ival, uint32_t* islot, hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
-void launch_bucket_keys(uint32_t nb, const uint32_t* bstart, const uint32_t* bend, uint32_t* key,
+// Dispatch keys: (resolution class << 16) | (0xFFFF - min(list length, 0xFFFF)).
+void launch_bucket_keys(uint32_t nb, const uint32_t* bucket_view, const uint8_t* view_cls,
+                        const uint32_t* bstart, const uint32_t* bend, uint32_t* key,
                         uint32_t* val, hipStream_t st);
-void launch_bucket_ranges(uint64_t ni, const uint32_t* ikey, uint32_t* bstart, uint32_t* bend,
-                          hipStream_t st);
+void launch_bucket_ranges(uint64_t ni, const uint32_t* ikey, const ViewDev* views, int lbits,
+                          uint32_t* bstart, uint32_t* bend, hipStream_t st);
 
 void launch_tile_segs(uint32_t nbuckets, const uint32_t* bucket_view, const ViewDev* views,
                       const int32_t* ids, uint32_t* ns_tile, uint16_t* segl, hipStream_t st);
 void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t* sat,
                 hipStream_t st);
-void launch_composite(bool count, uint32_t nbuckets, const uint32_t* order,
-                      const uint32_t* bucket_view, const ViewDev* views, const uint32_t* bstart,
-                      const uint32_t* bend, const uint32_t* ival, const uint32_t* islot,
-                      const float4* rec, const uint32_t* ns_tile, const uint16_t* segl,
-                      const int32_t* ids, uint2* part, unsigned long long* counters,
-                      hipStream_t st);
+// Compositing variants (bitwise-equal results, different register budgets).
+int composite_variants();
+const char* composite_variant_name(int v);
+void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t* order,
+                      uint32_t obase, const uint32_t* bucket_view, const ViewDev* views,
+                      const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
+                      const uint32_t* islot, const float4* rec, const uint32_t* ns_tile,
+                      const uint16_t* segl, const int32_t* ids, uint2* part,
+                      unsigned long long* counters, hipStream_t st);
 void launch_merge(uint64_t npairs, const uint16_t* pview, const ViewDev* views,
                   const uint32_t* part_base, const uint32_t* pcnt, const uint2* part,
                   uint2* wrow, uint32_t* wlen, unsigned long long* nnz, hipStream_t st);

@@ -24,7 +24,7 @@ def test_library_exports_every_declared_symbol():
     import paper_2505_08124_amd as slag
     L = slag.lib()
     names = _declared()
-    assert len(names) >= 23
+    assert len(names) >= 25
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(slag.EXPORTS)
@@ -41,6 +41,8 @@ def test_null_arguments_are_rejected():
     assert L.slag_codec_train(None, None, None) == slag.SLAG_E_INVALID_ARG
     assert L.slag_stage_name(6) == b"composite"
     assert L.slag_stage_name(10) == b"decode"
+    assert L.slag_get_tuning(None, None, 0, None) == slag.SLAG_E_INVALID_ARG
+    assert L.slag_variant_name(0).startswith(b"occupancy")
     assert L.slag_stage_name(99) == b""
 
 

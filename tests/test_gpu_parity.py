@@ -356,7 +356,10 @@ def test_full_size_uneven_1m_sampled_views():
         check_view_weights(L, sc, v, oracle.lift_view(sc, v))
     L.close()
     nz = den > 0
-    assert np.all(np.linalg.norm(E[nz], axis=1) <= 1 + 1e-5)
+    # convex combinations of the feature rows as uploaded (BF16 rows are unit
+    # norm only to within 2^-9)
+    fmax = np.linalg.norm(sc.feats_f64(), axis=1).max()
+    assert np.all(np.linalg.norm(E[nz], axis=1) <= fmax * (1 + 1e-5))
     assert np.all(E[~nz] == 0)
     _say("1m: two launches of 150 views")
     L2 = _lifter(sc, max_views=150)
