@@ -83,6 +83,14 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2505_08124_amd.build "
                            "(there is no non-HIP fallback)")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64.so.7 and
+    # the dynamic loader serves that soname from whichever copy loads first.
+    # Load PyTorch's first (when installed) so that tensors handed to the
+    # library and the library's own calls share it.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     L.slag_create.argtypes = [I32, P, ctypes.POINTER(slag_options), ctypes.POINTER(P)]

@@ -5,11 +5,13 @@
 // segment per view, out of ~10^2 per view.  Gaussians are taken in blocks of
 // G = 16 RT consecutive along a Morton curve of their means, so the rows of a
 // block tend to see the same segments.  A workgroup (4 waves) owns one block;
-// the block walks its pairs 256 / G views per step, one (row, view) pair per
-// thread reading the pair's packed (segment, weight) slots; the segments the
+// the block walks its pairs VPT 256 / G views per step, VPT (row, view) pairs
+// per thread, reading each pair's part list of (segment, weight) entries
+// (appended by the compositing in arbitrary order; the sums below are exact
+// fixed-point sums, so the order does not matter); the segments the
 // rows touch are deduplicated per view with LDS bitmaps over view-local ids,
 // numbered in (view, id) order by a block scan, and the weights are summed
-// into a shared A[G x K].  K-chunks of 32 columns then go to the matrix
+// into a shared fixed-point A[G x K].  K-chunks of 32 columns then go to the matrix
 // cores: each wave loads the feature rows B[32 x 16] of its column tiles
 // once and multiplies them with all RT row tiles of A (RT-fold reuse of every
 // feature load, the scarce resource: the same segment rows are fetched again
@@ -32,6 +34,15 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int KC = 32;          // K columns per chunk
 
 constexpr int KMAX = 128;       // K columns staged per round of a step
+
+// Weights are summed in 64-bit fixed point with 40 fraction bits: integer
+// addition is exact, so the sums do not depend on the order in which the
+// compositing appended a pair's entries (a (view, segment) sum is at most the
+// segment's pixel count, < 2^23, well inside the range).
+constexpr float kFx = 1099511627776.0f;          // 2^40
+constexpr float kFxInv = 1.0f / 1099511627776.0f;
+__device__ __forceinline__ int64_t to_fx(float w) { return (int64_t)(w * kFx); }
+__device__ __forceinline__ float from_fx(int64_t x) { return (float)x * kFxInv; }
 constexpr int kContractRT = 1;  // row tiles per block (G = 16 Gaussians; 2 and 4 measured slower)
 
 // G = 16 RT rows per block; thread t walks row t % G and views
@@ -43,7 +54,7 @@ struct BlockLds {
     uint32_t bits[GV * 8];      // word i: view i >> 3 of the step, ids w0 + 32 (i & 7) + [0, 32)
     uint32_t wbase[GV * 8];     // first step column of each word
     uint32_t ks[KMAX];          // feature row of each column of the round
-    float A[G][KMAX + 1];       // weights of the round's columns
+    int64_t A[G][KMAX + 1];     // weights of the round's columns, fixed point
     float dpart[GV][G];         // per-view row weight sums of the step
     uint32_t scan[8];
 };
@@ -65,7 +76,7 @@ __device__ __forceinline__ void mfma_chunk(const BlockLds<RT>& L, int k0, int kn
             const int k = 8 * kq + j;
 #pragma unroll
             for (int r = 0; r < RT; r++) {
-                const float a = k < kn ? L.A[16 * r + m][k0 + k] : 0.0f;
+                const float a = k < kn ? from_fx(L.A[16 * r + m][k0 + k]) : 0.0f;
                 const __bf16 h = (__bf16)a;
                 ahi[r][j] = h;
                 alo[r][j] = (__bf16)(a - (float)h);
@@ -97,7 +108,7 @@ __device__ __forceinline__ void mfma_chunk(const BlockLds<RT>& L, int k0, int kn
             const int k = 4 * kk + kq;
             float a[RT];
 #pragma unroll
-            for (int r = 0; r < RT; r++) a[r] = k < kn ? L.A[16 * r + m][k0 + k] : 0.0f;
+            for (int r = 0; r < RT; r++) a[r] = k < kn ? from_fx(L.A[16 * r + m][k0 + k]) : 0.0f;
             const uint32_t krow = k < kn ? L.ks[k0 + k] : NONE;
 #pragma unroll
             for (int t = 0; t < NT; t++) {
@@ -131,7 +142,7 @@ __device__ __forceinline__ uint32_t block_exscan(uint32_t x, uint32_t* scratch, 
 }
 
 template <int NT, bool BF16, int RT>
-__global__ __launch_bounds__(256) void k_contract_mfma(
+__global__ __launch_bounds__(256, 3) void k_contract_mfma(
     int64_t n, int nb, int d, const uint32_t* __restrict__ perm,
     const uint32_t* __restrict__ pair_of_m, const ViewDev* __restrict__ views,
     const uint32_t* __restrict__ part_base, const uint32_t* __restrict__ pcnt,
@@ -194,9 +205,9 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
         }
         if (!__syncthreads_or(any)) continue;
         // bitmap words: word i covers view v0 + (i >> 3), ids w0 + 32 (i & 7) + [0, 32)
-        float dv[VPT];
+        int64_t dv[VPT];
 #pragma unroll
-        for (int j = 0; j < VPT; j++) dv[j] = 0.0f;
+        for (int j = 0; j < VPT; j++) dv[j] = 0;
         for (uint32_t w0 = 0; __syncthreads_or(w0 < nsv); w0 += 256) {
             for (int i = t; i < GV * 8; i += 256) L.bits[i] = 0;
             __syncthreads();
@@ -207,11 +218,11 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
                 const int vw = (vt + GT * j) * 8;
                 for (uint32_t k = 0; k < cnt[j]; k++) {
                     const uint2 x = part[pb[j] + k];
-                    const uint32_t s = x.x - w0;
+                    const uint32_t s = (x.x & 0xFFFFu) - w0;
                     const float w = __uint_as_float(x.y);
                     if (s < 256u && w > 0.0f) {
                         atomicOr(&L.bits[vw + (s >> 5)], 1u << (s & 31));
-                        dv[j] += w;
+                        dv[j] += to_fx(w);
                     }
                 }
             }
@@ -252,7 +263,7 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
                         c++;
                     }
                 }
-                for (int i = t; i < G * (KMAX + 1); i += 256) (&L.A[0][0])[i] = 0.0f;
+                for (int i = t; i < G * (KMAX + 1); i += 256) (&L.A[0][0])[i] = 0;
                 __syncthreads();
                 // 3. weights: each thread adds its pairs' slots into its row
 #pragma unroll
@@ -260,13 +271,13 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
                     const int vw = (vt + GT * j) * 8;
                     for (uint32_t k = 0; k < cnt[j]; k++) {
                         const uint2 x = part[pb[j] + k];
-                        const uint32_t s = x.x - w0;
+                        const uint32_t s = (x.x & 0xFFFFu) - w0;
                         const float w = __uint_as_float(x.y);
                         if (s >= 256u || !(w > 0.0f)) continue;
                         const int wi = vw + (int)(s >> 5);
                         const uint32_t bit = 1u << (s & 31);
                         const uint32_t col = L.wbase[wi] + (uint32_t)__popc(L.bits[wi] & (bit - 1u));
-                        if (col >= kr && col < kr + KMAX) L.A[row][col - kr] += w;
+                        if (col >= kr && col < kr + KMAX) L.A[row][col - kr] += to_fx(w);
                     }
                 }
                 __syncthreads();
@@ -280,7 +291,7 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
         }
         // row weight sums, views in order
 #pragma unroll
-        for (int j = 0; j < VPT; j++) L.dpart[vt + GT * j][row] = dv[j];
+        for (int j = 0; j < VPT; j++) L.dpart[vt + GT * j][row] = from_fx(dv[j]);
         __syncthreads();
         if (t < G) {
             const int nv = min(GV, nb - v0);

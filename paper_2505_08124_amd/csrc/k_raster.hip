@@ -236,7 +236,8 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
     const uint32_t* __restrict__ order, uint32_t obase,
     const uint32_t* __restrict__ bucket_view, const ViewDev* __restrict__ views,
     const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ bend,
-    const uint32_t* __restrict__ ival, const uint32_t* __restrict__ islot,
+    const uint32_t* __restrict__ ival, const uint32_t* __restrict__ part_base,
+    const uint32_t* __restrict__ pcap, uint32_t* __restrict__ pfill,
     const float4* __restrict__ rec, const uint32_t* __restrict__ ns_tile,
     const uint16_t* __restrict__ segl, const int32_t* __restrict__ ids, uint2* __restrict__ part,
     unsigned long long* __restrict__ counters)
@@ -245,7 +246,8 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
     __shared__ float4 s_w1[4][BATCH];         //   (C, opacity, box x0 | y0 << 16, box x1 | y1 << 16)
     __shared__ int s_wj[4][BATCH];            //   their index in the batch
     __shared__ float s_acc[4][BATCH][NS_CAP]; // per wave weight sums [entry][segment]
-    __shared__ uint32_t s_off[BATCH];         // part slot of (pair, this tile, first pass segment)
+    __shared__ uint32_t s_pair[BATCH];        // pair of each batch entry
+    __shared__ uint32_t s_tir[BATCH];         // index of this tile in the pair's tile rectangle
     __shared__ uint16_t s_seg[TILE_PIX];
 
     const uint32_t b = order[obase + blockIdx.x];   // tiles with the longest lists first
@@ -308,10 +310,10 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
         // batch blends (unconditional clamped loads: every address is inside
         // the list; nothing waits on them until they are used).
         uint32_t e = min(start + (uint32_t)lane, last);
-        uint32_t pc = ival[e], qo = islot[e];
-        float4 q0 = rec[2 * (size_t)pc], q1 = rec[2 * (size_t)pc + 1];
+        uint32_t pcur = ival[e];
+        float4 q0 = rec[2 * (size_t)pcur], q1 = rec[2 * (size_t)pcur + 1];
         e = min(start + BATCH + (uint32_t)lane, last);
-        uint32_t pn = ival[e], on = islot[e];
+        uint32_t pn = ival[e];
         for (uint32_t base = start; base < end; base += BATCH) {
             const int nb = (int)min((uint32_t)BATCH, end - base);
             // compact the entries whose pixel box meets this wave's block
@@ -330,13 +332,17 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
                 s_w0[wv][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 s_w1[wv][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
-            if (wv == 0 && lane < nb) s_off[lane] = qo + (uint32_t)g0;
+            if (wv == 0 && lane < nb) {
+                const int rtx0 = (int)(ba & 0xFFFFu) / TILE, rty0 = (int)(ba >> 16) / TILE;
+                const int rw = (int)(bb & 0xFFFFu) / TILE - rtx0 + 1;
+                s_pair[lane] = pcur;
+                s_tir[lane] = (uint32_t)((ty - rty0) * rw + (tx - rtx0));
+            }
             q0 = rec[2 * (size_t)pn];
             q1 = rec[2 * (size_t)pn + 1];
-            qo = on;
+            pcur = pn;
             e = min(base + 2 * BATCH + (uint32_t)lane, last);
             pn = ival[e];
-            on = islot[e];
             __builtin_amdgcn_wave_barrier();
             if (cnt && !__all(done)) {
                 if (counting) {
@@ -354,13 +360,35 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
                 }
             }
             __syncthreads();
-            for (int i = t; i < nb * nsc; i += 256) {
-                const int j = i / nsc, k = i - j * nsc;
-                const float s = ((s_acc[0][j][k] + s_acc[1][j][k]) + s_acc[2][j][k]) + s_acc[3][j][k];
-                s_acc[0][j][k] = 0.0f; s_acc[1][j][k] = 0.0f;
-                s_acc[2][j][k] = 0.0f; s_acc[3][j][k] = 0.0f;
-                if (s != 0.0f)
-                    part[s_off[j] + k] = make_uint2((uint32_t)s_seg[g0 + k], __float_as_uint(s));
+            // one thread per batch entry: the four waves' sums per segment, in
+            // a fixed order; the non-zero ones are appended to the pair's part
+            // list (one atomic per (pair, tile) with output; the lists'
+            // order is arbitrary, so readers visit entries by key)
+            if (t < nb) {
+                float sv[NS_CAP];
+                int nz = 0;
+#pragma unroll
+                for (int k = 0; k < NS_CAP; k++) {
+                    sv[k] = 0.0f;
+                    if (k < nsc) {
+                        sv[k] = ((s_acc[0][t][k] + s_acc[1][t][k]) + s_acc[2][t][k]) + s_acc[3][t][k];
+                        s_acc[0][t][k] = 0.0f; s_acc[1][t][k] = 0.0f;
+                        s_acc[2][t][k] = 0.0f; s_acc[3][t][k] = 0.0f;
+                        nz += sv[k] != 0.0f;
+                    }
+                }
+                if (nz) {
+                    const uint32_t p = s_pair[t];
+                    const uint32_t o = atomicAdd(&pfill[p], (uint32_t)nz);
+                    if (o + (uint32_t)nz <= pcap[p]) {   // always, by construction of pcap
+                        uint2* dst = part + part_base[p] + o;
+                        const uint32_t tk = (s_tir[t] & 0xFFFFu) << 16;
+#pragma unroll
+                        for (int k = 0; k < NS_CAP; k++)
+                            if (sv[k] != 0.0f)
+                                *dst++ = make_uint2(tk | (uint32_t)s_seg[g0 + k], __float_as_uint(sv[k]));
+                    }
+                }
             }
             if (__syncthreads_count(!done) == 0) break;
         }
@@ -381,8 +409,8 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
     }
 }
 
-// Debug export: one thread per pair keeps its non-zero (segment row, weight)
-// slots, in slot order (tiles row-major, segments ascending within a tile).
+// Debug export and training rows: one thread per pair copies its part list
+// (pcnt = the filled length) as (global segment row, weight).
 __global__ __launch_bounds__(256) void k_merge(uint64_t npairs, const uint16_t* __restrict__ pview,
                                                const ViewDev* __restrict__ views,
                                                const uint32_t* __restrict__ part_base,
@@ -399,7 +427,8 @@ __global__ __launch_bounds__(256) void k_merge(uint64_t npairs, const uint16_t* 
         const uint32_t base = part_base[p], cnt = pcnt[p];
         for (uint32_t k = 0; k < cnt; k++) {
             const uint2 e = part[base + k];
-            if (__uint_as_float(e.y) > 0.0f) wrow[base + n++] = make_uint2(V.seg_off + e.x, e.y);
+            if (__uint_as_float(e.y) > 0.0f)
+                wrow[base + n++] = make_uint2(V.seg_off + (e.x & 0xFFFFu), e.y);
         }
         wlen[p] = n;
     }
@@ -437,14 +466,16 @@ const char* composite_variant_name(int v)
 void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t* order,
                       uint32_t obase, const uint32_t* bucket_view, const ViewDev* views,
                       const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
-                      const uint32_t* islot, const float4* rec, const uint32_t* ns_tile,
-                      const uint16_t* segl, const int32_t* ids, uint2* part,
-                      unsigned long long* counters, hipStream_t st)
+                      const uint32_t* part_base, const uint32_t* pcap, uint32_t* pfill,
+                      const float4* rec, const uint32_t* ns_tile, const uint16_t* segl,
+                      const int32_t* ids, uint2* part, unsigned long long* counters,
+                      hipStream_t st)
 {
     if (!nbuckets) return;
 #define SLAG_COMP(C, W, P)                                                                         \
     hipLaunchKernelGGL((k_composite<C, W, P>), dim3(nbuckets), dim3(256), 0, st, order, obase,     \
-                       bucket_view, views, bstart, bend, ival, islot, rec, ns_tile, segl, ids,    \
+                       bucket_view, views, bstart, bend, ival, part_base, pcap, pfill, rec,       \
+                       ns_tile, segl, ids,                                                         \
                        part, counters)
     if (count) {
         SLAG_COMP(true, 8, false);

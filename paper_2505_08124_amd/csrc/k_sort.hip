@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) void k_rank_tiles(uint64_t npairs, const uint3
     if (r < npairs) tcr[r] = ptc[order[r]];
 }
 
-// (tile, pair, part slot) entries of every pair in depth order, tiles of a
+// (tile, pair) entries of every pair in depth order, tiles of a
 // pair in row-major order; the tile key is (view in launch << lbits) | tile in
 // view.  Pairs come view-major, so a stable sort on the low lbits alone
 // leaves each (view, tile) list contiguous and in depth order.  A wave emits the consecutive output range of its 64 pairs
@@ -318,17 +318,13 @@ __global__ __launch_bounds__(256) void k_emit_isect(uint64_t npairs, const uint3
                                                     const uint16_t* __restrict__ pview,
                                                     const ViewDev* __restrict__ views,
                                                     const uint32_t* __restrict__ ioff,
-                                                    const uint32_t* __restrict__ part_base,
-                                                    const uint32_t* __restrict__ sat,
                                                     int lbits,
                                                     uint32_t* __restrict__ ikey,
-                                                    uint32_t* __restrict__ ival,
-                                                    uint32_t* __restrict__ islot)
+                                                    uint32_t* __restrict__ ival)
 {
     __shared__ uint32_t s_off[4][65];
     __shared__ uint32_t s_p[4][64];
-    __shared__ uint32_t s_r[4][64][3];   // tile base, tiles per row of the rect, ntx
-    __shared__ uint32_t s_q[4][64][4];   // first tile (tx0, ty0), pair's first part slot, SAT offset
+    __shared__ uint32_t s_r[4][64][3];   // tile key base, tiles per row of the rect, ntx
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t r0 = (uint64_t)blockIdx.x * 256 + (uint64_t)w * 64;
     if (r0 >= npairs) return;
@@ -348,9 +344,6 @@ __global__ __launch_bounds__(256) void k_emit_isect(uint64_t npairs, const uint3
         s_r[w][lane][0] = ((uint32_t)pview[p] << lbits) + (uint32_t)(ty0 * V.ntx + tx0);
         s_r[w][lane][1] = (uint32_t)(tx1 - tx0 + 1);
         s_r[w][lane][2] = (uint32_t)V.ntx;
-        s_q[w][lane][0] = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
-        s_q[w][lane][1] = part_base[p];
-        s_q[w][lane][2] = V.sat_off;
         s_off[w][lane] = o;
     }
     const uint32_t o0 = __builtin_amdgcn_readfirstlane(o);
@@ -369,16 +362,6 @@ __global__ __launch_bounds__(256) void k_emit_isect(uint64_t npairs, const uint3
         const uint32_t dy = k / rw, dx = k % rw;
         ikey[e] = s_r[w][lo][0] + dy * ntx + dx;
         ival[e] = s_p[w][lo];
-        // part slot: the pair's first slot plus the segment counts of the rect
-        // tiles before this one (row-major), from the view's summed-area table;
-        // the two rectangle sums share a corner that cancels
-        const uint32_t t0 = s_q[w][lo][0];
-        const int tx0 = (int)(t0 & 0xFFFFu), ty0 = (int)(t0 >> 16);
-        const int tx = tx0 + (int)dx, ty = ty0 + (int)dy, tx1 = tx0 + (int)rw - 1;
-        const uint32_t* S = sat + s_q[w][lo][2];
-        const int sw = (int)ntx + 1;
-        islot[e] = s_q[w][lo][1] + S[ty * sw + tx1 + 1] - S[ty0 * sw + tx1 + 1] + S[ty0 * sw + tx0] +
-                   S[(ty + 1) * sw + tx] - S[ty * sw + tx] - S[(ty + 1) * sw + tx0];
     }
 }
 
@@ -501,12 +484,11 @@ void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const uint32_t* p
 
 void launch_emit_isect(uint64_t npairs, const uint32_t* order, const float4* rec,
                        const uint16_t* pview, const ViewDev* views, const uint32_t* ioff,
-                       const uint32_t* part_base, const uint32_t* sat, int lbits, uint32_t* ikey,
-                       uint32_t* ival, uint32_t* islot, hipStream_t st)
+                       int lbits, uint32_t* ikey, uint32_t* ival, hipStream_t st)
 {
     if (!npairs) return;
     hipLaunchKernelGGL(k_emit_isect, dim3(grid_for(npairs)), dim3(256), 0, st, npairs, order, rec,
-                       pview, views, ioff, part_base, sat, lbits, ikey, ival, islot);
+                       pview, views, ioff, lbits, ikey, ival);
 }
 
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st)

@@ -416,26 +416,20 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         CK(ensure(c, c->ikey_alt, ni * 4));
         CK(ensure(c, c->ival, ni * 4));
         CK(ensure(c, c->ival_alt, ni * 4));
-        CK(ensure(c, c->islot, ni * 4));
-        CK(ensure(c, c->islot_alt, ni * 4));
         launch_rank_tiles(npairs, order, c->ptc.as<uint32_t>(), c->tcr.as<uint32_t>(), st);
         scan_u32(c->tcr.as<uint32_t>(), npairs, nullptr, c->scan_ws.p, st);
         launch_emit_isect(npairs, order, c->rec.as<float4>(), c->pview.as<uint16_t>(), views,
-                          c->tcr.as<uint32_t>(), c->psz.as<uint32_t>(), c->sat.as<uint32_t>(),
-                          B.lbits, c->ikey.as<uint32_t>(), c->ival.as<uint32_t>(),
-                          c->islot.as<uint32_t>(), st);
+                          c->tcr.as<uint32_t>(), B.lbits, c->ikey.as<uint32_t>(),
+                          c->ival.as<uint32_t>(), st);
         CK(stage_end(c, ST_BIN, ev));
 
         // stable sort by tile -> per-tile lists in (depth, Gaussian) order
         CK(stage_begin(c, ST_TILE_SORT, &ev));
-        const bool alt2 = radix_sort_u32_v2(
-            c->ikey.as<uint32_t>(), c->ival.as<uint32_t>(), c->islot.as<uint32_t>(),
-            c->ikey_alt.as<uint32_t>(), c->ival_alt.as<uint32_t>(), c->islot_alt.as<uint32_t>(), ni,
-            B.lbits, c->hist.as<uint32_t>(), c->scan_ws.p,
-            st);
+        const bool alt2 = radix_sort_u32(c->ikey.as<uint32_t>(), c->ival.as<uint32_t>(),
+                                         c->ikey_alt.as<uint32_t>(), c->ival_alt.as<uint32_t>(), ni,
+                                         B.lbits, c->hist.as<uint32_t>(), c->scan_ws.p, nullptr, st);
         skey = alt2 ? c->ikey_alt.as<uint32_t>() : c->ikey.as<uint32_t>();
         sval = alt2 ? c->ival_alt.as<uint32_t>() : c->ival.as<uint32_t>();
-        const uint32_t* sslot = alt2 ? c->islot_alt.as<uint32_t>() : c->islot.as<uint32_t>();
         CK(ensure(c, c->bstart, (size_t)B.nbuckets * 4 + 4));
         CK(ensure(c, c->bend, (size_t)B.nbuckets * 4 + 4));
         launch_fill_u32(c->bstart.as<uint32_t>(), B.nbuckets, 0u, st);
@@ -459,35 +453,53 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         const uint32_t* border = alt3 ? c->bord_alt.as<uint32_t>() : c->bord.as<uint32_t>();
         CK(stage_end(c, ST_TILE_SORT, ev));
 
-        // part slots, zeroed
+        // part lists: capacity pcnt[p] at psz[p] (scanned), fill counts zeroed
         CK(stage_begin(c, ST_PART_PREP, &ev));
         CK(ensure(c, c->part, std::max<uint64_t>(nparts, 1) * 8));
-        launch_fill_u32(c->part.as<uint32_t>(), 2 * nparts, 0u, st);
+        CK(ensure(c, c->pfill, np * 4));
+        launch_fill_u32(c->pfill.as<uint32_t>(), npairs, 0u, st);
         CK(stage_end(c, ST_PART_PREP, ev));
 
         CK(stage_begin(c, ST_COMPOSITE, &ev));
+        auto clear_lists = [&]() { launch_fill_u32(c->pfill.as<uint32_t>(), npairs, 0u, st); };
+        // tuning: time every variant of each untuned size (each run starts
+        // from empty part lists), then composite every size once for real
+        bool tuned_now = false;
+        for (int k = 0; k < B.ncls && (c->opt.flags & SLAG_FLAG_AUTOTUNE) && !c->capturing && !count;
+             k++) {
+            if (!B.cls_nb[k]) continue;
+            const uint64_t key = ((uint64_t)B.cls_w[k] << 32) | B.cls_h[k];
+            if (c->tune.count(key)) continue;
+            auto launch = [&](int var) {
+                clear_lists();
+                launch_composite(false, var, B.cls_nb[k], border, B.cls_off[k],
+                                 B.bucket_view.as<uint32_t>(), views, c->bstart.as<uint32_t>(),
+                                 c->bend.as<uint32_t>(), sval, c->psz.as<uint32_t>(),
+                                 c->pcnt.as<uint32_t>(), c->pfill.as<uint32_t>(), c->rec.as<float4>(),
+                                 c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
+                                 c->ids.as<int32_t>(), c->part.as<uint2>(),
+                                 reinterpret_cast<unsigned long long*>(small + SM_COUNTERS), st);
+            };
+            TuneEntry te;
+            te.n_variants = std::min(composite_variants(), 8);
+            CK(tune_class(c, te, launch));
+            c->tune.emplace(key, te);
+            tuned_now = true;
+        }
+        if (tuned_now) clear_lists();
         for (int k = 0; k < B.ncls; k++) {
             if (!B.cls_nb[k]) continue;
             auto launch = [&](int var) {
                 launch_composite(count, var, B.cls_nb[k], border, B.cls_off[k],
                                  B.bucket_view.as<uint32_t>(), views, c->bstart.as<uint32_t>(),
-                                 c->bend.as<uint32_t>(), sval, sslot, c->rec.as<float4>(),
+                                 c->bend.as<uint32_t>(), sval, c->psz.as<uint32_t>(),
+                                 c->pcnt.as<uint32_t>(), c->pfill.as<uint32_t>(), c->rec.as<float4>(),
                                  c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
                                  c->ids.as<int32_t>(), c->part.as<uint2>(),
                                  reinterpret_cast<unsigned long long*>(small + SM_COUNTERS), st);
             };
             const uint64_t key = ((uint64_t)B.cls_w[k] << 32) | B.cls_h[k];
             auto it = c->tune.find(key);
-            if (it == c->tune.end() && (c->opt.flags & SLAG_FLAG_AUTOTUNE) && !c->capturing &&
-                !count) {
-                // every variant writes the same part slots, so trying them all
-                // is itself a correct compositing of this class
-                TuneEntry te;
-                te.n_variants = std::min(composite_variants(), 8);
-                CK(tune_class(c, te, launch));
-                it = c->tune.emplace(key, te).first;
-                continue;
-            }
             launch(it == c->tune.end() ? 0 : it->second.variant);
         }
         CK(stage_end(c, ST_COMPOSITE, ev));
@@ -497,7 +509,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
             CK(stage_begin(c, ST_MERGE, &ev));
             CK(ensure(c, c->wrow, std::max<uint64_t>(nparts, 1) * 8));
             launch_merge(npairs, c->pview.as<uint16_t>(), views, c->psz.as<uint32_t>(),
-                         c->pcnt.as<uint32_t>(), c->part.as<uint2>(), c->wrow.as<uint2>(),
+                         c->pfill.as<uint32_t>(), c->part.as<uint2>(), c->wrow.as<uint2>(),
                          c->wlen.as<uint32_t>(),
                          reinterpret_cast<unsigned long long*>(small + SM_NNZ), st);
             CK(stage_end(c, ST_MERGE, ev));
@@ -506,7 +518,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
 
     CK(stage_begin(c, ST_CONTRACT, &ev));
     launch_contract(n, nb, ct.d, ct.bf16, c->perm.as<uint32_t>(), c->pair_of_m.as<uint32_t>(),
-                    views, c->psz.as<uint32_t>(), c->pcnt.as<uint32_t>(), c->part.as<uint2>(),
+                    views, c->psz.as<uint32_t>(), c->pfill.as<uint32_t>(), c->part.as<uint2>(),
                     ct.table, ct.out, c->den.as<float>(), first, last, st);
     CK(stage_end(c, ST_CONTRACT, ev));
 
@@ -569,7 +581,7 @@ void slag_destroy(slag_ctx* c)
                       &c->dkey_alt, &c->dval, &c->dval_alt, &c->psz, &c->pz, &c->tcr, &c->wlen,
                       &c->ikey, &c->ikey_alt, &c->ival, &c->ival_alt, &c->bstart, &c->bend,
                       &c->part, &c->wrow, &c->perm, &c->rank, &c->pair_of_m, &c->pcnt,
-                      &c->islot, &c->islot_alt, &c->ptc, &c->blk_aux, &c->bkey,
+                      &c->pfill, &c->ptc, &c->blk_aux, &c->bkey,
                       &c->bkey_alt, &c->bord, &c->bord_alt};
     destroy_graph(c);
     for (DevBuf* b : bufs) release(*b);

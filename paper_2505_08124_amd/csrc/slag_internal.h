@@ -77,8 +77,7 @@ void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const uint32_t* p
                        hipStream_t st);
 void launch_emit_isect(uint64_t npairs, const uint32_t* order, const float4* rec,
                        const uint16_t* pview, const ViewDev* views, const uint32_t* ioff,
-                       const uint32_t* part_base, const uint32_t* sat, int lbits, uint32_t* ikey,
-                       uint32_t* ival, uint32_t* islot, hipStream_t st);
+                       int lbits, uint32_t* ikey, uint32_t* ival, hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
 // Dispatch keys: (resolution class << 16) | (0xFFFF - min(list length, 0xFFFF)).
 void launch_bucket_keys(uint32_t nb, const uint32_t* bucket_view, const uint8_t* view_cls,
@@ -94,12 +93,16 @@ void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t*
 // Compositing variants (bitwise-equal results, different register budgets).
 int composite_variants();
 const char* composite_variant_name(int v);
+// Part lists: pair p owns part[part_base[p] .. + pcap[p]); compositing
+// appends (tile-in-rect << 16 | view-local segment, weight) entries for its
+// non-zero sums, counting them in pfill[p] (zeroed before).
 void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t* order,
                       uint32_t obase, const uint32_t* bucket_view, const ViewDev* views,
                       const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
-                      const uint32_t* islot, const float4* rec, const uint32_t* ns_tile,
-                      const uint16_t* segl, const int32_t* ids, uint2* part,
-                      unsigned long long* counters, hipStream_t st);
+                      const uint32_t* part_base, const uint32_t* pcap, uint32_t* pfill,
+                      const float4* rec, const uint32_t* ns_tile, const uint16_t* segl,
+                      const int32_t* ids, uint2* part, unsigned long long* counters,
+                      hipStream_t st);
 void launch_merge(uint64_t npairs, const uint16_t* pview, const ViewDev* views,
                   const uint32_t* part_base, const uint32_t* pcnt, const uint2* part,
                   uint2* wrow, uint32_t* wlen, unsigned long long* nnz, hipStream_t st);
