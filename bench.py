@@ -90,7 +90,7 @@ def codec_section(args, slag, torch):
     (graph replays) and compare the codec's embeddings with the plain ones."""
     from synthetic import make_scene
     from synthetic.codec_inputs import init_params
-    d, h, k = 512, 256, 16
+    d, h, k = 512, args.codec_hidden, args.codec_k
     t0 = time.perf_counter()
     L = slag.Lifter(0, flags=slag.SLAG_FLAG_GRAPH | slag.SLAG_FLAG_PROFILE | slag.SLAG_FLAG_AUTOTUNE)
     slag.slag_codec_init(L.ctx, d, h, k, slag.SLAG_BF16, init_params(d, h, k, seed=1040))
@@ -162,6 +162,8 @@ def main():
     ap.add_argument("--eager", action="store_true", help="time eager lifts instead of graph replays")
     ap.add_argument("--no-codec", action="store_true", help="skip the codec section")
     ap.add_argument("--codec-steps", type=int, default=2000)
+    ap.add_argument("--codec-k", type=int, default=16, help="code size (16, 32, 48 or 64)")
+    ap.add_argument("--codec-hidden", type=int, default=256)
     ap.add_argument("--codec-reps", type=int, default=5)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="also run one plain device copy of BYTES (read) + BYTES (write), "

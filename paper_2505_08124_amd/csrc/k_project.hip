@@ -239,7 +239,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
     const uint32_t* __restrict__ blk_off, float4* __restrict__ rec, uint32_t* __restrict__ pgauss,
     uint16_t* __restrict__ pview, uint64_t* __restrict__ dkey, uint32_t* __restrict__ dval,
     uint32_t* __restrict__ psz, uint32_t* __restrict__ pz, const uint32_t* __restrict__ sat,
-    uint32_t zmin, int zbits, uint32_t* __restrict__ blk_tot,
+    uint32_t zmin, int zbits, int pbits, uint32_t* __restrict__ blk_tot,
     const uint32_t* __restrict__ rank, uint32_t* __restrict__ pair_of_m, uint32_t* __restrict__ ptc)
 {
     __shared__ uint32_t cnt[PER_THREAD][4];
@@ -288,8 +288,13 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
                         __uint_as_float((uint32_t)P.x1 | ((uint32_t)P.y1 << 16)));
         pgauss[pidx] = (uint32_t)g;
         pview[pidx] = (uint16_t)vl;
-        dkey[pidx] = ((uint64_t)vl << zbits) | (uint64_t)(__float_as_uint(P.z) - zmin);
-        dval[pidx] = pidx;
+        const uint64_t dk = ((uint64_t)vl << zbits) | (uint64_t)(__float_as_uint(P.z) - zmin);
+        if (pbits) {
+            dkey[pidx] = (dk << pbits) | pidx;       // the pair index rides in the low bits
+        } else {
+            dkey[pidx] = dk;
+            dval[pidx] = pidx;
+        }
         pz[pidx] = __float_as_uint(P.z);
         // part slots of this pair: sum of the tile segment counts over its tile rect
         const int tx0 = P.x0 / TILE, tx1 = P.x1 / TILE, ty0 = P.y0 / TILE, ty1 = P.y1 / TILE;
@@ -458,13 +463,13 @@ void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* mea
                        const float* cov3, const float* opac, uint32_t* tcnt_pairof,
                        const uint32_t* blk_off, float4* rec, uint32_t* pgauss, uint16_t* pview,
                        uint64_t* dkey, uint32_t* dval, uint32_t* psz, uint32_t* pz,
-                       const uint32_t* sat, uint32_t zmin, int zbits, uint32_t* blk_tot,
+                       const uint32_t* sat, uint32_t zmin, int zbits, int pbits, uint32_t* blk_tot,
                        const uint32_t* rank, uint32_t* pair_of_m, uint32_t* ptc, hipStream_t st)
 {
     if (n <= 0 || nb <= 0) return;
     hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)count_blocks_per_view(n), (unsigned)nb),
                        dim3(256), 0, st, n, views, means, cov3, opac, tcnt_pairof, blk_off, rec,
-                       pgauss, pview, dkey, dval, psz, pz, sat, zmin, zbits, blk_tot, rank,
+                       pgauss, pview, dkey, dval, psz, pz, sat, zmin, zbits, pbits, blk_tot, rank,
                        pair_of_m, ptc);
 }
 

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
         hist[(uint64_t)i * nblk + blockIdx.x] = cnt[0][i] + cnt[1][i] + cnt[2][i] + cnt[3][i];
 }
 
-template <typename K, int RB, bool V2>
+template <typename K, int RB, int NV>
 __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin,
                                                        const uint32_t* __restrict__ vin,
                                                        const uint32_t* __restrict__ uin,
@@ -156,8 +156,8 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
     __shared__ uint32_t lbase[R];     // block-local start of each digit
     __shared__ uint32_t tmp[8];
     __shared__ K s_key[RADIX_TILE];
-    __shared__ uint32_t s_val[RADIX_TILE];
-    __shared__ uint32_t s_aux[V2 ? RADIX_TILE : 1];
+    __shared__ uint32_t s_val[NV >= 1 ? RADIX_TILE : 1];
+    __shared__ uint32_t s_aux[NV >= 2 ? RADIX_TILE : 1];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < 4 * R; i += 256) (&wcnt[0][0])[i] = 0;
     for (int i = threadIdx.x; i < R; i += 256) dbase[i] = hist[(uint64_t)i * nblk + blockIdx.x];
@@ -167,16 +167,16 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
     const uint64_t base = bbase + (uint64_t)w * (RADIX_ITEMS * 64);
     const int nvalid = (int)min((uint64_t)RADIX_TILE, n - bbase);
     K key[RADIX_ITEMS];
-    uint32_t val[RADIX_ITEMS];
-    uint32_t aux[V2 ? RADIX_ITEMS : 1];
+    uint32_t val[NV >= 1 ? RADIX_ITEMS : 1];
+    uint32_t aux[NV >= 2 ? RADIX_ITEMS : 1];
     uint32_t rk[RADIX_ITEMS];
 #pragma unroll
     for (int it = 0; it < RADIX_ITEMS; it++) {
         const uint64_t idx = base + it * 64 + lane;
         const bool valid = idx < n;
         key[it] = valid ? kin[idx] : (K)0;
-        val[it] = valid ? vin[idx] : 0u;
-        if constexpr (V2) aux[it] = valid ? uin[idx] : 0u;
+        if constexpr (NV >= 1) val[it] = valid ? vin[idx] : 0u;
+        if constexpr (NV >= 2) aux[it] = valid ? uin[idx] : 0u;
         const uint32_t d = (uint32_t)(key[it] >> shift) & (R - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -239,8 +239,8 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
             const uint32_t d = (uint32_t)(key[it] >> shift) & (R - 1);
             const uint32_t lp = lbase[d] + wcnt[w][d] + rk[it];
             s_key[lp] = key[it];
-            s_val[lp] = val[it];
-            if constexpr (V2) s_aux[lp] = aux[it];
+            if constexpr (NV >= 1) s_val[lp] = val[it];
+            if constexpr (NV >= 2) s_aux[lp] = aux[it];
         }
     }
     __syncthreads();
@@ -250,12 +250,12 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
         const uint32_t d = (uint32_t)(k >> shift) & (R - 1);
         const uint32_t pos = dbase[d] + (uint32_t)lp - lbase[d];
         kout[pos] = k;
-        vout[pos] = s_val[lp];
-        if constexpr (V2) uout[pos] = s_aux[lp];
+        if constexpr (NV >= 1) vout[pos] = s_val[lp];
+        if constexpr (NV >= 2) uout[pos] = s_aux[lp];
     }
 }
 
-template <typename K, int RB, bool V2>
+template <typename K, int RB, int NV>
 void radix_pass(const K* ka, const uint32_t* va, const uint32_t* ua, K* kb, uint32_t* vb,
                 uint32_t* ub, uint64_t n, int shift, uint32_t* hist, void* ws, hipStream_t st)
 {
@@ -263,14 +263,15 @@ void radix_pass(const K* ka, const uint32_t* va, const uint32_t* ua, K* kb, uint
     hipLaunchKernelGGL((k_radix_hist<K, RB>), dim3(nblk), dim3(256), 0, st, ka, n, shift, hist,
                        nblk);
     scan_u32(hist, (uint64_t)nblk << RB, nullptr, ws, st);
-    hipLaunchKernelGGL((k_radix_scatter<K, RB, V2>), dim3(nblk), dim3(256), 0, st, ka, va, ua, kb,
+    hipLaunchKernelGGL((k_radix_scatter<K, RB, NV>), dim3(nblk), dim3(256), 0, st, ka, va, ua, kb,
                        vb, ub, n, shift, hist, nblk);
 }
 
-// Stable LSD sort of (key, value[, aux]) by bits [0, nbits), 8 bits per pass.
-template <typename K, bool V2>
+// Stable LSD sort of (key[, value[, aux]]) by bits [bit0, bit0 + nbits), 8 bits per pass.
+template <typename K, int NV>
 bool radix_sort(K* keys, uint32_t* vals, uint32_t* aux, K* keys_alt, uint32_t* vals_alt,
-                uint32_t* aux_alt, uint64_t n, int nbits, uint32_t* hist, void* ws, hipStream_t st)
+                uint32_t* aux_alt, uint64_t n, int bit0, int nbits, uint32_t* hist, void* ws,
+                hipStream_t st)
 {
     if (n <= 1 || nbits <= 0) return false;
     const int passes = (nbits + RADIX_MAXBITS - 1) / RADIX_MAXBITS;
@@ -279,8 +280,8 @@ bool radix_sort(K* keys, uint32_t* vals, uint32_t* aux, K* keys_alt, uint32_t* v
     K* kb = keys_alt;
     uint32_t *va = vals, *vb = vals_alt, *ua = aux, *ub = aux_alt;
     bool alt = false;
-    for (int shift = 0; shift < nbits; shift += rb) {
-        radix_pass<K, RADIX_MAXBITS, V2>(ka, va, ua, kb, vb, ub, n, shift, hist, ws, st);
+    for (int shift = bit0; shift < bit0 + nbits; shift += rb) {
+        radix_pass<K, RADIX_MAXBITS, NV>(ka, va, ua, kb, vb, ub, n, shift, hist, ws, st);
         shift += RADIX_MAXBITS - rb;   // the digit may cover more bits than asked
         K* tk = ka; ka = kb; kb = tk;
         uint32_t* tv = va; va = vb; vb = tv;
@@ -299,12 +300,22 @@ __device__ __forceinline__ void box_of(const float4& r1, int& x0, int& x1, int& 
     x1 = (int)(b & 0xFFFFu); y1 = (int)(b >> 16);
 }
 
+// The depth order is either a pair-index array or, packed, the low bits of
+// the sorted 64-bit depth keys.
+__device__ __forceinline__ uint32_t pair_at_rank(const uint32_t* __restrict__ order,
+                                                 const uint64_t* __restrict__ okey, uint64_t pmask,
+                                                 uint64_t r)
+{
+    return okey ? (uint32_t)(okey[r] & pmask) : order[r];
+}
+
 __global__ __launch_bounds__(256) void k_rank_tiles(uint64_t npairs, const uint32_t* __restrict__ order,
+                                                    const uint64_t* __restrict__ okey, uint64_t pmask,
                                                     const uint32_t* __restrict__ ptc,
                                                     uint32_t* __restrict__ tcr)
 {
     const uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r < npairs) tcr[r] = ptc[order[r]];
+    if (r < npairs) tcr[r] = ptc[pair_at_rank(order, okey, pmask, r)];
 }
 
 // (tile, pair) entries of every pair in depth order, tiles of a
@@ -314,6 +325,7 @@ __global__ __launch_bounds__(256) void k_rank_tiles(uint64_t npairs, const uint3
 // together: output slot e finds its pair among the wave's 64 offsets, so the
 // stores are coalesced.
 __global__ __launch_bounds__(256) void k_emit_isect(uint64_t npairs, const uint32_t* __restrict__ order,
+                                                    const uint64_t* __restrict__ okey, uint64_t pmask,
                                                     const float4* __restrict__ rec,
                                                     const uint16_t* __restrict__ pview,
                                                     const ViewDev* __restrict__ views,
@@ -332,7 +344,7 @@ __global__ __launch_bounds__(256) void k_emit_isect(uint64_t npairs, const uint3
     const int nw = (int)min((uint64_t)64, npairs - r0);
     uint32_t o = 0, tc = 0;
     if (lane < nw) {
-        const uint32_t p = order[r];
+        const uint32_t p = pair_at_rank(order, okey, pmask, r);
         const float2 bx = reinterpret_cast<const float2*>(rec)[4 * (size_t)p + 3];
         const uint32_t a = __float_as_uint(bx.x), b = __float_as_uint(bx.y);
         const int tx0 = (int)(a & 0xFFFFu) / TILE, ty0 = (int)(a >> 16) / TILE;
@@ -453,8 +465,15 @@ bool radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t
                     hipStream_t st)
 {
     (void)tot;
-    return radix_sort<uint64_t, false>(keys, vals, nullptr, keys_alt, vals_alt, nullptr, n, nbits,
-                                       hist, scan_ws, st);
+    return radix_sort<uint64_t, 1>(keys, vals, nullptr, keys_alt, vals_alt, nullptr, n, 0, nbits,
+                                   hist, scan_ws, st);
+}
+
+bool radix_sort_u64_keys(uint64_t* keys, uint64_t* keys_alt, uint64_t n, int bit0, int nbits,
+                         uint32_t* hist, void* scan_ws, hipStream_t st)
+{
+    return radix_sort<uint64_t, 0>(keys, nullptr, nullptr, keys_alt, nullptr, nullptr, n, bit0,
+                                   nbits, hist, scan_ws, st);
 }
 
 bool radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
@@ -462,33 +481,26 @@ bool radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t
                     hipStream_t st)
 {
     (void)tot;
-    return radix_sort<uint32_t, false>(keys, vals, nullptr, keys_alt, vals_alt, nullptr, n, nbits,
-                                       hist, scan_ws, st);
+    return radix_sort<uint32_t, 1>(keys, vals, nullptr, keys_alt, vals_alt, nullptr, n, 0, nbits,
+                                   hist, scan_ws, st);
 }
 
-bool radix_sort_u32_v2(uint32_t* keys, uint32_t* vals, uint32_t* aux, uint32_t* keys_alt,
-                       uint32_t* vals_alt, uint32_t* aux_alt, uint64_t n, int nbits,
-                       uint32_t* hist, void* scan_ws, hipStream_t st)
-{
-    return radix_sort<uint32_t, true>(keys, vals, aux, keys_alt, vals_alt, aux_alt, n, nbits, hist,
-                                      scan_ws, st);
-}
-
-void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const uint32_t* ptc, uint32_t* tcr,
-                       hipStream_t st)
+void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const uint64_t* okey,
+                       uint64_t pmask, const uint32_t* ptc, uint32_t* tcr, hipStream_t st)
 {
     if (!npairs) return;
-    hipLaunchKernelGGL(k_rank_tiles, dim3(grid_for(npairs)), dim3(256), 0, st, npairs, order, ptc,
-                       tcr);
+    hipLaunchKernelGGL(k_rank_tiles, dim3(grid_for(npairs)), dim3(256), 0, st, npairs, order, okey,
+                       pmask, ptc, tcr);
 }
 
-void launch_emit_isect(uint64_t npairs, const uint32_t* order, const float4* rec,
-                       const uint16_t* pview, const ViewDev* views, const uint32_t* ioff,
-                       int lbits, uint32_t* ikey, uint32_t* ival, hipStream_t st)
+void launch_emit_isect(uint64_t npairs, const uint32_t* order, const uint64_t* okey,
+                       uint64_t pmask, const float4* rec, const uint16_t* pview,
+                       const ViewDev* views, const uint32_t* ioff, int lbits, uint32_t* ikey,
+                       uint32_t* ival, hipStream_t st)
 {
     if (!npairs) return;
-    hipLaunchKernelGGL(k_emit_isect, dim3(grid_for(npairs)), dim3(256), 0, st, npairs, order, rec,
-                       pview, views, ioff, lbits, ikey, ival);
+    hipLaunchKernelGGL(k_emit_isect, dim3(grid_for(npairs)), dim3(256), 0, st, npairs, order, okey,
+                       pmask, rec, pview, views, ioff, lbits, ikey, ival);
 }
 
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st)

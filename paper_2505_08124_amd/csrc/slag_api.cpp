@@ -351,6 +351,10 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
     if (npairs > 0xFFFFFFF0ull) FAIL(c, SLAG_E_CAPACITY, "too many visible pairs in one launch");
     const int zbits = (npairs && zmax >= zmin) ? bit_length((uint64_t)(zmax - zmin)) : 0;
     const int vbits = bit_length((uint64_t)(nb > 0 ? nb - 1 : 0));
+    // depth keys carry the pair index in their low bits when everything fits
+    // in 64 bits (one 8-byte array to sort instead of 8 + 4 bytes)
+    const int pneed = std::max(1, bit_length(npairs > 0 ? npairs - 1 : 0));
+    const int pbits = (vbits + zbits + pneed <= 64) ? pneed : 0;
     const uint64_t np = std::max<uint64_t>(npairs, 1);
     CK(ensure(c, c->rec, np * 32));
     CK(ensure(c, c->pgauss, np * 4));
@@ -370,7 +374,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
                       c->tcnt.as<uint32_t>(), c->blk_vis.as<uint32_t>(), c->rec.as<float4>(),
                       c->pgauss.as<uint32_t>(), c->pview.as<uint16_t>(), c->dkey.as<uint64_t>(),
                       c->dval.as<uint32_t>(), c->psz.as<uint32_t>(), c->pz.as<uint32_t>(),
-                      c->sat.as<uint32_t>(), zmin, zbits, c->blk_aux.as<uint32_t>(),
+                      c->sat.as<uint32_t>(), zmin, zbits, pbits, c->blk_aux.as<uint32_t>(),
                       c->rank.as<uint32_t>(), c->pair_of_m.as<uint32_t>(), c->ptc.as<uint32_t>(),
                       st);
     launch_reduce_pairs(c->blk_aux.as<uint32_t>(), nblk, true,
@@ -401,11 +405,21 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         CK(stage_begin(c, ST_DEPTH_SORT, &ev));
         CK(ensure(c, c->hist, std::max(radix_hist_bytes(npairs), radix_hist_bytes(ni))));
         CK(ensure_scan(c, std::max<uint64_t>(npairs, ni / 2 + 4096)));
-        const bool alt = radix_sort_u64(c->dkey.as<uint64_t>(), c->dval.as<uint32_t>(),
-                                        c->dkey_alt.as<uint64_t>(), c->dval_alt.as<uint32_t>(),
-                                        npairs, zbits + vbits, c->hist.as<uint32_t>(),
-                                        c->scan_ws.p, nullptr, st);
-        const uint32_t* order = alt ? c->dval_alt.as<uint32_t>() : c->dval.as<uint32_t>();
+        const uint32_t* order = nullptr;
+        const uint64_t* okey = nullptr;
+        const uint64_t pmask = pbits ? ((1ull << pbits) - 1ull) : 0ull;
+        if (pbits) {
+            const bool alt = radix_sort_u64_keys(c->dkey.as<uint64_t>(), c->dkey_alt.as<uint64_t>(),
+                                                 npairs, pbits, zbits + vbits,
+                                                 c->hist.as<uint32_t>(), c->scan_ws.p, st);
+            okey = alt ? c->dkey_alt.as<uint64_t>() : c->dkey.as<uint64_t>();
+        } else {
+            const bool alt = radix_sort_u64(c->dkey.as<uint64_t>(), c->dval.as<uint32_t>(),
+                                            c->dkey_alt.as<uint64_t>(), c->dval_alt.as<uint32_t>(),
+                                            npairs, zbits + vbits, c->hist.as<uint32_t>(),
+                                            c->scan_ws.p, nullptr, st);
+            order = alt ? c->dval_alt.as<uint32_t>() : c->dval.as<uint32_t>();
+        }
         CK(stage_end(c, ST_DEPTH_SORT, ev));
 
         // (tile, pair, part slot) entries in depth order; part slots pair-major
@@ -416,10 +430,11 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         CK(ensure(c, c->ikey_alt, ni * 4));
         CK(ensure(c, c->ival, ni * 4));
         CK(ensure(c, c->ival_alt, ni * 4));
-        launch_rank_tiles(npairs, order, c->ptc.as<uint32_t>(), c->tcr.as<uint32_t>(), st);
+        launch_rank_tiles(npairs, order, okey, pmask, c->ptc.as<uint32_t>(), c->tcr.as<uint32_t>(),
+                          st);
         scan_u32(c->tcr.as<uint32_t>(), npairs, nullptr, c->scan_ws.p, st);
-        launch_emit_isect(npairs, order, c->rec.as<float4>(), c->pview.as<uint16_t>(), views,
-                          c->tcr.as<uint32_t>(), B.lbits, c->ikey.as<uint32_t>(),
+        launch_emit_isect(npairs, order, okey, pmask, c->rec.as<float4>(), c->pview.as<uint16_t>(),
+                          views, c->tcr.as<uint32_t>(), B.lbits, c->ikey.as<uint32_t>(),
                           c->ival.as<uint32_t>(), st);
         CK(stage_end(c, ST_BIN, ev));
 
