@@ -231,8 +231,10 @@ __global__ __launch_bounds__(256) void k_count(int64_t n, const ViewDev* __restr
 }
 
 // Pass 2: compact visible pairs in (view, Gaussian) order and write their
-// records, depth-sort keys, part sizes; tcnt is overwritten by the pair index
-// (NONE where not visible).  Same striped layout as pass 1.
+// records, depth-sort keys, part-list capacities and the (view, Morton rank)
+// -> pair map (NONE where not visible); pgauss and pz (Gaussian index and
+// depth bits per pair) only when given, for the debug exports.  Same striped
+// layout as pass 1.
 __global__ __launch_bounds__(256) void k_emit_pairs(
     int64_t n, const ViewDev* __restrict__ views, const float* __restrict__ means,
     const float* __restrict__ cov3, const float* __restrict__ opac, uint32_t* __restrict__ tcnt,
@@ -249,7 +251,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t g0 = (int64_t)blockIdx.x * CPB + threadIdx.x;
-    uint32_t* io = tcnt + (int64_t)vl * n;
+    const uint32_t* io = tcnt + (int64_t)vl * n;
 #pragma unroll
     for (int i = 0; i < PER_THREAD; i++) {
         const int64_t g = g0 + (int64_t)i * 256;
@@ -274,7 +276,6 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         run += cnt[i][0] + cnt[i][1] + cnt[i][2] + cnt[i][3];
         if (g >= n) continue;
         if (!((m >> lane) & 1ull)) {
-            io[g] = NONE;
             pair_of_m[(int64_t)vl * n + rank[g]] = NONE;
             continue;
         }
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         rec[2 * (size_t)pidx + 1] =
             make_float4(P.cc, opac[g], __uint_as_float((uint32_t)P.x0 | ((uint32_t)P.y0 << 16)),
                         __uint_as_float((uint32_t)P.x1 | ((uint32_t)P.y1 << 16)));
-        pgauss[pidx] = (uint32_t)g;
+        if (pgauss) pgauss[pidx] = (uint32_t)g;      // debug exports only
         pview[pidx] = (uint16_t)vl;
         const uint64_t dk = ((uint64_t)vl << zbits) | (uint64_t)(__float_as_uint(P.z) - zmin);
         if (pbits) {
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
             dkey[pidx] = dk;
             dval[pidx] = pidx;
         }
-        pz[pidx] = __float_as_uint(P.z);
+        if (pz) pz[pidx] = __float_as_uint(P.z);      // debug exports only
         // part slots of this pair: sum of the tile segment counts over its tile rect
         const int tx0 = P.x0 / TILE, tx1 = P.x1 / TILE, ty0 = P.y0 / TILE, ty1 = P.y1 / TILE;
         const uint32_t ps = S[(ty1 + 1) * sw + tx1 + 1] - S[ty0 * sw + tx1 + 1] -
@@ -305,7 +306,6 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         ptc[pidx] = tc;
         n_isect += tc;
         n_part += ps;
-        io[g] = pidx;
         pair_of_m[(int64_t)vl * n + rank[g]] = pidx;
     }
 #pragma unroll

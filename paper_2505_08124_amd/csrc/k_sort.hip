@@ -110,8 +110,8 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
                                                     int shift, uint32_t* __restrict__ hist,
                                                     uint32_t nblk)
 {
-    // per-wave counts; lanes with equal digits are grouped with ballots and
-    // their leader adds the group size (no same-address LDS atomics)
+    // per-wave counts in LDS: one add when a wave's items share a digit
+    // (common for the high digits), else one LDS atomic per item
     constexpr int R = 1 << RB;
     __shared__ uint32_t cnt[4][R];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -124,14 +124,14 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
         const uint64_t idx = base + it * 64 + lane;
         const bool valid = idx < n;
         const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & (R - 1) : 0u;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < RB; b++) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
+        // all valid lanes on one digit: the first adds them; else LDS atomics
+        const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
+        const uint64_t vm = __ballot(valid);
+        if (__ballot(valid && d != d0) == 0) {
+            if (lane == 0 && vm) cnt[w][d0] += (uint32_t)__popcll(vm);
+        } else if (valid) {
+            atomicAdd(&cnt[w][d], 1u);
         }
-        if (valid && (peers & lt) == 0) cnt[w][d] += (uint32_t)__popcll(peers);
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();

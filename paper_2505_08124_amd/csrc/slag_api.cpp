@@ -314,6 +314,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
     const ViewDev* views = B.views.as<ViewDev>();
     uint64_t* small = c->small.as<uint64_t>();
     const bool count = (c->opt.flags & SLAG_FLAG_COUNT) != 0;
+    const bool debug = (c->opt.flags & SLAG_FLAG_KEEP_DEBUG) != 0;
     hipEvent_t ev;
 
     // tile segment tables and their summed-area tables
@@ -372,8 +373,9 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
     CK(ensure(c, c->pair_of_m, npq * 4));
     launch_emit_pairs(nb, n, views, c->means.as<float>(), c->cov3.as<float>(), c->opac.as<float>(),
                       c->tcnt.as<uint32_t>(), c->blk_vis.as<uint32_t>(), c->rec.as<float4>(),
-                      c->pgauss.as<uint32_t>(), c->pview.as<uint16_t>(), c->dkey.as<uint64_t>(),
-                      c->dval.as<uint32_t>(), c->psz.as<uint32_t>(), c->pz.as<uint32_t>(),
+                      debug ? c->pgauss.as<uint32_t>() : nullptr, c->pview.as<uint16_t>(),
+                      c->dkey.as<uint64_t>(), c->dval.as<uint32_t>(), c->psz.as<uint32_t>(),
+                      debug ? c->pz.as<uint32_t>() : nullptr,
                       c->sat.as<uint32_t>(), zmin, zbits, pbits, c->blk_aux.as<uint32_t>(),
                       c->rank.as<uint32_t>(), c->pair_of_m.as<uint32_t>(), c->ptc.as<uint32_t>(),
                       st);
