@@ -117,7 +117,6 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < 4 * R; i += 256) (&cnt[0][0])[i] = 0;
     __syncthreads();
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint64_t base = (uint64_t)blockIdx.x * RADIX_TILE + (uint64_t)w * (RADIX_ITEMS * 64);
 #pragma unroll
     for (int it = 0; it < RADIX_ITEMS; it++) {
