@@ -316,10 +316,25 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
         uint32_t pn = ival[e];
         for (uint32_t base = start; base < end; base += BATCH) {
             const int nb = (int)min((uint32_t)BATCH, end - base);
-            // compact the entries whose pixel box meets this wave's block
+            // the bounding box of this wave's pixels that can still take
+            // weight (lane = 8 y + x), from the active-lane mask
+            const uint64_t am = __ballot(!done);
+            int ax0 = 0, ax1 = -1, ay0 = 0, ay1 = -1;
+            if (am) {
+                uint64_t c = am | (am >> 32);
+                c |= c >> 16;
+                c |= c >> 8;
+                const uint32_t cols = (uint32_t)(c & 0xFFu);
+                ax0 = __builtin_ctz(cols);
+                ax1 = 31 - __builtin_clz(cols);
+                ay0 = __builtin_ctzll(am) >> 3;
+                ay1 = (63 - __builtin_clzll(am)) >> 3;
+            }
+            // compact the entries whose pixel box meets those pixels' box
             const uint32_t ba = __float_as_uint(q1.z), bb = __float_as_uint(q1.w);
-            const bool hit = lane < nb && (int)(bb & 0xFFFFu) >= bx0 && (int)(ba & 0xFFFFu) <= bx0 + 7 &&
-                             (int)(bb >> 16) >= by0 && (int)(ba >> 16) <= by0 + 7;
+            const bool hit = lane < nb && (int)(bb & 0xFFFFu) >= bx0 + ax0 &&
+                             (int)(ba & 0xFFFFu) <= bx0 + ax1 && (int)(bb >> 16) >= by0 + ay0 &&
+                             (int)(ba >> 16) <= by0 + ay1;
             const uint64_t hm = __ballot(hit);
             const int cnt = __popcll(hm);
             if (hit) {
