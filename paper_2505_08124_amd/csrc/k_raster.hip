@@ -156,9 +156,14 @@ __device__ __forceinline__ float wave_sum4(float v0, float v1, float v2, float v
 // Blend this wave's compacted entries of one batch into its 64 pixels, four
 // entries at a time; the four entries' per-segment weight sums over the
 // wave's pixels go to acc[batch entry][segment slot].
+// A lane's pixel inside its wave's 8x8 block (lx, ly in 0..7).
+struct LaneXY {
+    float lx, ly;
+};
+
 template <int MODE, bool COUNTING, bool PAD>
 __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const float4* __restrict__ w1,
-                                            const int* __restrict__ wj, int cnt, float fpx, float fpy,
+                                            const int* __restrict__ wj, int cnt, const LaneXY& Q,
                                             int px, int py, int slot, int uslot, uint32_t slot_mask,
                                             float& T, bool& done, float (*acc)[NS_CAP], int lane,
                                             unsigned long long& n_acc, unsigned long long& n_box,
@@ -178,12 +183,15 @@ __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const
                 w[u] = 0.0f;
                 if (jj >= cnt) continue;                 // wave-uniform
             }
+            // alpha = min(0.99, o exp(-q/2)) = min(0.99, 2^e) with
+            // e = log2(o) - q log2(e) / 2 a quadratic in the lane's block
+            // coordinates (coefficients from the compaction step)
             const float4 p0 = w0[jj];
             const float4 p1 = w1[jj];
-            const float dx = fpx - p0.x, dy = fpy - p0.y;
-            float e = fmaf(dx, fmaf(p0.z, dx, p0.w * dy), p1.x * dy * dy);
-            e = fminf(e, 0.0f);
-            const float alpha = fminf(AMAX, p1.y * __builtin_amdgcn_exp2f(e));
+            const float tx = fmaf(p1.x, Q.ly, fmaf(p0.w, Q.lx, p0.y));   // cx + cxx lx + cxy ly
+            const float ty = fmaf(p1.y, Q.ly, p0.z);                       // cy + cyy ly
+            const float e = fmaf(ty, Q.ly, fmaf(tx, Q.lx, p0.x));
+            const float alpha = fminf(AMAX, __builtin_amdgcn_exp2f(e));
             const float Tn = fmaf(-alpha, T, T);
             if (COUNTING) {
                 const bool ok = !done && alpha >= AMIN;
@@ -242,8 +250,8 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
     const uint16_t* __restrict__ segl, const int32_t* __restrict__ ids, uint2* __restrict__ part,
     unsigned long long* __restrict__ counters)
 {
-    __shared__ float4 s_w0[4][BATCH];         // per wave: entries touching its block (u, v, A, B)
-    __shared__ float4 s_w1[4][BATCH];         //   (C, opacity, box x0 | y0 << 16, box x1 | y1 << 16)
+    __shared__ float4 s_w0[4][BATCH];         // per wave: entries touching its block, exponent
+    __shared__ float4 s_w1[4][BATCH];         //   coefficients (c0, cx, cy, cxx), (cxy, cyy, box, box)
     __shared__ int s_wj[4][BATCH];            //   their index in the batch
     __shared__ float s_acc[4][BATCH][NS_CAP]; // per wave weight sums [entry][segment]
     __shared__ uint32_t s_pair[BATCH];        // pair of each batch entry
@@ -276,7 +284,9 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
         }
         ls = lo;
     }
-    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    LaneXY Q;
+    Q.lx = (float)(lane & 7);
+    Q.ly = (float)(lane >> 3);
     unsigned long long n_acc = 0, n_box = 0, n_tile = 0;
     const uint32_t last = end - 1;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -338,13 +348,22 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
             const uint64_t hm = __ballot(hit);
             const int cnt = __popcll(hm);
             if (hit) {
+                // exponent log2(o) + A dx^2 + B dx dy + C dy^2 with dx = lx - du,
+                // dy = ly - dv (pixel centre relative to the entry's mean),
+                // expanded in the block coordinates lx, ly: six coefficients
                 const int k = __popcll(hm & lt);
-                s_w0[wv][k] = make_float4(q0.x, q0.y, q0.z * NHALF_LOG2E, q0.w * NLOG2E);
-                s_w1[wv][k] = make_float4(q1.x * NHALF_LOG2E, q1.y, q1.z, q1.w);
+                const float A = q0.z * NHALF_LOG2E, B = q0.w * NLOG2E, C = q1.x * NHALF_LOG2E;
+                const float du = q0.x - ((float)bx0 + 0.5f), dv = q0.y - ((float)by0 + 0.5f);
+                const float cx = -fmaf(2.0f * A, du, B * dv);
+                const float cy = -fmaf(B, du, 2.0f * C * dv);
+                const float c0 = fmaf(A * du, du, fmaf(B * du, dv, C * dv * dv)) +
+                                 __builtin_amdgcn_logf(q1.y);
+                s_w0[wv][k] = make_float4(c0, cx, cy, A);
+                s_w1[wv][k] = make_float4(B, C, q1.z, q1.w);
                 s_wj[wv][k] = lane;
             }
             if (PAD && lane >= cnt && lane < ((cnt + 3) & ~3)) {   // null entries up to a multiple of 4
-                s_w0[wv][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                s_w0[wv][lane] = make_float4(-1e30f, 0.0f, 0.0f, 0.0f);   // 2^e = 0
                 s_w1[wv][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
             if (wv == 0 && lane < nb) {
@@ -362,16 +381,16 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
             if (cnt && !__all(done)) {
                 if (counting) {
                     if (mode == MODE_UNIFORM)
-                        blend_batch<MODE_UNIFORM, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                        blend_batch<MODE_UNIFORM, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
                     else if (mode == MODE_MIXED)
-                        blend_batch<MODE_MIXED, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                        blend_batch<MODE_MIXED, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
                     else
-                        blend_batch<MODE_NONE, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                        blend_batch<MODE_NONE, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
                 } else {
                     if (mode == MODE_UNIFORM)
-                        blend_batch<MODE_UNIFORM, false, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                        blend_batch<MODE_UNIFORM, false, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
                     else
-                        blend_batch<MODE_MIXED, false, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, fpx, fpy, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                        blend_batch<MODE_MIXED, false, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
                 }
             }
             __syncthreads();
