@@ -145,7 +145,7 @@ template <int NT, bool BF16, int RT>
 __global__ __launch_bounds__(256, 3) void k_contract_mfma(
     int64_t n, int nb, int d, const uint32_t* __restrict__ perm,
     const uint32_t* __restrict__ pair_of_m, const ViewDev* __restrict__ views,
-    const uint32_t* __restrict__ part_base, const uint32_t* __restrict__ pcnt,
+    const uint2* __restrict__ pinfo,
     const uint2* __restrict__ part, const void* __restrict__ feats, float* __restrict__ num,
     float* __restrict__ den, int first, int last)
 {
@@ -198,8 +198,10 @@ __global__ __launch_bounds__(256, 3) void k_contract_mfma(
             const uint32_t p = pn[j];
             pn[j] = pair_at(v0 + GV + vt + GT * j);
             any = any || p != NONE;
-            pb[j] = p != NONE ? part_base[p] : 0u;
-            cnt[j] = p != NONE ? pcnt[p] : 0u;
+            uint2 pi = make_uint2(0u, 0u);
+            if (p != NONE) pi = pinfo[p];                 // (base, fill): one load
+            pb[j] = pi.x;
+            cnt[j] = pi.y;
             const int v = v0 + vt + GT * j;
             nsv = max(nsv, v < nb ? views[v].nseg : 0u);
         }
@@ -322,7 +324,7 @@ __global__ __launch_bounds__(256, 3) void k_contract_mfma(
 
 template <int NT, int RT>
 void launch_nt(int64_t n, int nb, int d, bool bf16, const uint32_t* perm, const uint32_t* pair_of_m,
-               const ViewDev* views, const uint32_t* part_base, const uint32_t* pcnt,
+               const ViewDev* views, const uint2* pinfo,
                const uint2* part, const void* feats, float* num, float* den, bool first, bool last,
                hipStream_t st)
 {
@@ -330,11 +332,11 @@ void launch_nt(int64_t n, int nb, int d, bool bf16, const uint32_t* perm, const 
     const dim3 grid((unsigned)((n + G - 1) / G));
     if (bf16)
         hipLaunchKernelGGL((k_contract_mfma<NT, true, RT>), grid, dim3(256), 0, st, n, nb, d, perm,
-                           pair_of_m, views, part_base, pcnt, part, feats, num, den, (int)first,
+                           pair_of_m, views, pinfo, part, feats, num, den, (int)first,
                            (int)last);
     else
         hipLaunchKernelGGL((k_contract_mfma<NT, false, RT>), grid, dim3(256), 0, st, n, nb, d, perm,
-                           pair_of_m, views, part_base, pcnt, part, feats, num, den, (int)first,
+                           pair_of_m, views, pinfo, part, feats, num, den, (int)first,
                            (int)last);
 }
 
@@ -348,12 +350,12 @@ bool contract_supported(int d)
 bool contract_supported_codes(int d) { return d == 16 || d == 32 || d == 48 || contract_supported(d); }
 
 void launch_contract(int64_t n, int nb, int d, bool bf16, const uint32_t* perm,
-                     const uint32_t* pair_of_m, const ViewDev* views, const uint32_t* part_base,
-                     const uint32_t* pcnt, const uint2* part, const void* feats, float* num,
+                     const uint32_t* pair_of_m, const ViewDev* views, const uint2* pinfo,
+                     const uint2* part, const void* feats, float* num,
                      float* den, bool first, bool last, hipStream_t st)
 {
     if (n <= 0) return;
-#define SLAG_NT(NTV) launch_nt<NTV, kContractRT>(n, nb, d, bf16, perm, pair_of_m, views, part_base, pcnt, part, \
+#define SLAG_NT(NTV) launch_nt<NTV, kContractRT>(n, nb, d, bf16, perm, pair_of_m, views, pinfo, part, \
                                     feats, num, den, first, last, st)
     switch (d) {
     case 16:

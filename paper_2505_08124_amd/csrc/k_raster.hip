@@ -244,8 +244,7 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
     const uint32_t* __restrict__ order, uint32_t obase,
     const uint32_t* __restrict__ bucket_view, const ViewDev* __restrict__ views,
     const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ bend,
-    const uint32_t* __restrict__ ival, const uint32_t* __restrict__ part_base,
-    const uint32_t* __restrict__ pcap, uint32_t* __restrict__ pfill,
+    const uint32_t* __restrict__ ival, uint2* __restrict__ pinfo,
     const float4* __restrict__ rec, const uint32_t* __restrict__ ns_tile,
     const uint16_t* __restrict__ segl, const int32_t* __restrict__ ids, uint2* __restrict__ part,
     unsigned long long* __restrict__ counters)
@@ -413,9 +412,12 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
                 }
                 if (nz) {
                     const uint32_t p = s_pair[t];
-                    const uint32_t o = atomicAdd(&pfill[p], (uint32_t)nz);
-                    if (o + (uint32_t)nz <= pcap[p]) {   // always, by construction of pcap
-                        uint2* dst = part + part_base[p] + o;
+                    // pinfo[p] = (list base, fill count); the capacity is the
+                    // next list's base (neighbouring record, same line mostly)
+                    const uint32_t b0 = pinfo[p].x, b1 = pinfo[p + 1].x;
+                    const uint32_t o = atomicAdd(&pinfo[p].y, (uint32_t)nz);
+                    if (o + (uint32_t)nz <= b1 - b0) {   // always, by construction of the capacity
+                        uint2* dst = part + b0 + o;
                         const uint32_t tk = (s_tir[t] & 0xFFFFu) << 16;
 #pragma unroll
                         for (int k = 0; k < NS_CAP; k++)
@@ -443,12 +445,23 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
     }
 }
 
+// Part-list records: pinfo[p] = (base, 0) from the scanned capacities, and
+// the sentinel pinfo[npairs] = (total, 0), so a list's capacity is the next
+// record's base minus its own.
+__global__ __launch_bounds__(256) void k_init_pinfo(uint64_t npairs, const uint32_t* __restrict__ base,
+                                                    uint32_t total, uint2* __restrict__ pinfo)
+{
+    const uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < npairs) pinfo[p] = make_uint2(base[p], 0u);
+    else if (p == npairs) pinfo[p] = make_uint2(total, 0u);
+}
+
 // Debug export and training rows: one thread per pair copies its part list
-// (pcnt = the filled length) as (global segment row, weight).
+// (pinfo[p] = (base, filled length)) as (global segment row, weight), to
+// wrow at the list's base.
 __global__ __launch_bounds__(256) void k_merge(uint64_t npairs, const uint16_t* __restrict__ pview,
                                                const ViewDev* __restrict__ views,
-                                               const uint32_t* __restrict__ part_base,
-                                               const uint32_t* __restrict__ pcnt,
+                                               const uint2* __restrict__ pinfo,
                                                const uint2* __restrict__ part,
                                                uint2* __restrict__ wrow,
                                                uint32_t* __restrict__ wlen,
@@ -458,7 +471,7 @@ __global__ __launch_bounds__(256) void k_merge(uint64_t npairs, const uint16_t* 
     uint32_t n = 0;
     if (p < npairs) {
         const ViewDev& V = views[pview[p]];
-        const uint32_t base = part_base[p], cnt = pcnt[p];
+        const uint32_t base = pinfo[p].x, cnt = pinfo[p].y;
         for (uint32_t k = 0; k < cnt; k++) {
             const uint2 e = part[base + k];
             if (__uint_as_float(e.y) > 0.0f)
@@ -500,15 +513,14 @@ const char* composite_variant_name(int v)
 void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t* order,
                       uint32_t obase, const uint32_t* bucket_view, const ViewDev* views,
                       const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
-                      const uint32_t* part_base, const uint32_t* pcap, uint32_t* pfill,
-                      const float4* rec, const uint32_t* ns_tile, const uint16_t* segl,
-                      const int32_t* ids, uint2* part, unsigned long long* counters,
-                      hipStream_t st)
+                      uint2* pinfo, const float4* rec, const uint32_t* ns_tile,
+                      const uint16_t* segl, const int32_t* ids, uint2* part,
+                      unsigned long long* counters, hipStream_t st)
 {
     if (!nbuckets) return;
 #define SLAG_COMP(C, W, P)                                                                         \
     hipLaunchKernelGGL((k_composite<C, W, P>), dim3(nbuckets), dim3(256), 0, st, order, obase,     \
-                       bucket_view, views, bstart, bend, ival, part_base, pcap, pfill, rec,       \
+                       bucket_view, views, bstart, bend, ival, pinfo, rec,                        \
                        ns_tile, segl, ids,                                                         \
                        part, counters)
     if (count) {
@@ -524,13 +536,21 @@ void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t
 #undef SLAG_COMP
 }
 
-void launch_merge(uint64_t npairs, const uint16_t* pview, const ViewDev* views,
-                  const uint32_t* part_base, const uint32_t* pcnt, const uint2* part,
-                  uint2* wrow, uint32_t* wlen, unsigned long long* nnz, hipStream_t st)
+void launch_init_pinfo(uint64_t npairs, const uint32_t* base, uint32_t total, uint2* pinfo,
+                       hipStream_t st)
+{
+    if (!npairs) return;
+    hipLaunchKernelGGL(k_init_pinfo, dim3((unsigned)((npairs + 256) / 256)), dim3(256), 0, st,
+                       npairs, base, total, pinfo);
+}
+
+void launch_merge(uint64_t npairs, const uint16_t* pview, const ViewDev* views, const uint2* pinfo,
+                  const uint2* part, uint2* wrow, uint32_t* wlen, unsigned long long* nnz,
+                  hipStream_t st)
 {
     if (!npairs) return;
     hipLaunchKernelGGL(k_merge, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, npairs,
-                       pview, views, part_base, pcnt, part, wrow, wlen, nnz);
+                       pview, views, pinfo, part, wrow, wlen, nnz);
 }
 
 }  // namespace slag

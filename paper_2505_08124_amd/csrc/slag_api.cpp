@@ -470,15 +470,18 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         const uint32_t* border = alt3 ? c->bord_alt.as<uint32_t>() : c->bord.as<uint32_t>();
         CK(stage_end(c, ST_TILE_SORT, ev));
 
-        // part lists: capacity pcnt[p] at psz[p] (scanned), fill counts zeroed
+        // part lists: pinfo[p] = (base psz[p] (scanned), fill 0), sentinel (total, 0)
         CK(stage_begin(c, ST_PART_PREP, &ev));
         CK(ensure(c, c->part, std::max<uint64_t>(nparts, 1) * 8));
-        CK(ensure(c, c->pfill, np * 4));
-        launch_fill_u32(c->pfill.as<uint32_t>(), npairs, 0u, st);
+        CK(ensure(c, c->pinfo, (np + 1) * 8));
+        launch_init_pinfo(npairs, c->psz.as<uint32_t>(), (uint32_t)nparts, c->pinfo.as<uint2>(), st);
         CK(stage_end(c, ST_PART_PREP, ev));
 
         CK(stage_begin(c, ST_COMPOSITE, &ev));
-        auto clear_lists = [&]() { launch_fill_u32(c->pfill.as<uint32_t>(), npairs, 0u, st); };
+        auto clear_lists = [&]() {
+            launch_init_pinfo(npairs, c->psz.as<uint32_t>(), (uint32_t)nparts,
+                              c->pinfo.as<uint2>(), st);
+        };
         // tuning: time every variant of each untuned size (each run starts
         // from empty part lists), then composite every size once for real
         bool tuned_now = false;
@@ -491,8 +494,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
                 clear_lists();
                 launch_composite(false, var, B.cls_nb[k], border, B.cls_off[k],
                                  B.bucket_view.as<uint32_t>(), views, c->bstart.as<uint32_t>(),
-                                 c->bend.as<uint32_t>(), sval, c->psz.as<uint32_t>(),
-                                 c->pcnt.as<uint32_t>(), c->pfill.as<uint32_t>(), c->rec.as<float4>(),
+                                 c->bend.as<uint32_t>(), sval, c->pinfo.as<uint2>(), c->rec.as<float4>(),
                                  c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
                                  c->ids.as<int32_t>(), c->part.as<uint2>(),
                                  reinterpret_cast<unsigned long long*>(small + SM_COUNTERS), st);
@@ -509,8 +511,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
             auto launch = [&](int var) {
                 launch_composite(count, var, B.cls_nb[k], border, B.cls_off[k],
                                  B.bucket_view.as<uint32_t>(), views, c->bstart.as<uint32_t>(),
-                                 c->bend.as<uint32_t>(), sval, c->psz.as<uint32_t>(),
-                                 c->pcnt.as<uint32_t>(), c->pfill.as<uint32_t>(), c->rec.as<float4>(),
+                                 c->bend.as<uint32_t>(), sval, c->pinfo.as<uint2>(), c->rec.as<float4>(),
                                  c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
                                  c->ids.as<int32_t>(), c->part.as<uint2>(),
                                  reinterpret_cast<unsigned long long*>(small + SM_COUNTERS), st);
@@ -525,8 +526,8 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
             // per-pair weight rows, only for the debug export
             CK(stage_begin(c, ST_MERGE, &ev));
             CK(ensure(c, c->wrow, std::max<uint64_t>(nparts, 1) * 8));
-            launch_merge(npairs, c->pview.as<uint16_t>(), views, c->psz.as<uint32_t>(),
-                         c->pfill.as<uint32_t>(), c->part.as<uint2>(), c->wrow.as<uint2>(),
+            launch_merge(npairs, c->pview.as<uint16_t>(), views, c->pinfo.as<uint2>(),
+                         c->part.as<uint2>(), c->wrow.as<uint2>(),
                          c->wlen.as<uint32_t>(),
                          reinterpret_cast<unsigned long long*>(small + SM_NNZ), st);
             CK(stage_end(c, ST_MERGE, ev));
@@ -535,7 +536,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
 
     CK(stage_begin(c, ST_CONTRACT, &ev));
     launch_contract(n, nb, ct.d, ct.bf16, c->perm.as<uint32_t>(), c->pair_of_m.as<uint32_t>(),
-                    views, c->psz.as<uint32_t>(), c->pfill.as<uint32_t>(), c->part.as<uint2>(),
+                    views, c->pinfo.as<uint2>(), c->part.as<uint2>(),
                     ct.table, ct.out, c->den.as<float>(), first, last, st);
     CK(stage_end(c, ST_CONTRACT, ev));
 
@@ -598,7 +599,7 @@ void slag_destroy(slag_ctx* c)
                       &c->dkey_alt, &c->dval, &c->dval_alt, &c->psz, &c->pz, &c->tcr, &c->wlen,
                       &c->ikey, &c->ikey_alt, &c->ival, &c->ival_alt, &c->bstart, &c->bend,
                       &c->part, &c->wrow, &c->perm, &c->rank, &c->pair_of_m, &c->pcnt,
-                      &c->pfill, &c->ptc, &c->blk_aux, &c->bkey,
+                      &c->pinfo, &c->ptc, &c->blk_aux, &c->bkey,
                       &c->bkey_alt, &c->bord, &c->bord_alt};
     destroy_graph(c);
     for (DevBuf* b : bufs) release(*b);

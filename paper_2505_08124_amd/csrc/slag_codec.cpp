@@ -317,8 +317,8 @@ slag_status slag_codec_add_lift_rows(slag_ctx* c, int64_t max_rows, uint64_t see
     uint64_t* small = c->small.as<uint64_t>();
     // merged per-pair weight rows (global segment ids)
     CK(ensure(c, c->wrow, std::max<int64_t>(c->stats.n_part_slots, 1) * 8));
-    launch_merge(np, c->pview.as<uint16_t>(), B.views.as<ViewDev>(), c->psz.as<uint32_t>(),
-                 c->pfill.as<uint32_t>(), c->part.as<uint2>(), c->wrow.as<uint2>(),
+    launch_merge(np, c->pview.as<uint16_t>(), B.views.as<ViewDev>(), c->pinfo.as<uint2>(),
+                 c->part.as<uint2>(), c->wrow.as<uint2>(),
                  c->wlen.as<uint32_t>(), reinterpret_cast<unsigned long long*>(small + SM_NNZ), st);
     // sample Gaussians with weight
     const double frac = std::min(1.0, (double)max_rows / (double)n);

@@ -95,27 +95,29 @@ void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t*
 // Compositing variants (bitwise-equal results, different register budgets).
 int composite_variants();
 const char* composite_variant_name(int v);
-// Part lists: pair p owns part[part_base[p] .. + pcap[p]); compositing
-// appends (tile-in-rect << 16 | view-local segment, weight) entries for its
-// non-zero sums, counting them in pfill[p] (zeroed before).
+// Part lists: pinfo[p] = (base, fill), pinfo[npairs] = (total, 0); pair p
+// owns part[base .. next base); compositing appends (tile-in-rect << 16 |
+// view-local segment, weight) entries for its non-zero sums, counting them
+// in the fill field (zeroed by launch_init_pinfo).
+void launch_init_pinfo(uint64_t npairs, const uint32_t* base, uint32_t total, uint2* pinfo,
+                       hipStream_t st);
 void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t* order,
                       uint32_t obase, const uint32_t* bucket_view, const ViewDev* views,
                       const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
-                      const uint32_t* part_base, const uint32_t* pcap, uint32_t* pfill,
-                      const float4* rec, const uint32_t* ns_tile, const uint16_t* segl,
-                      const int32_t* ids, uint2* part, unsigned long long* counters,
-                      hipStream_t st);
-void launch_merge(uint64_t npairs, const uint16_t* pview, const ViewDev* views,
-                  const uint32_t* part_base, const uint32_t* pcnt, const uint2* part,
-                  uint2* wrow, uint32_t* wlen, unsigned long long* nnz, hipStream_t st);
+                      uint2* pinfo, const float4* rec, const uint32_t* ns_tile,
+                      const uint16_t* segl, const int32_t* ids, uint2* part,
+                      unsigned long long* counters, hipStream_t st);
+void launch_merge(uint64_t npairs, const uint16_t* pview, const ViewDev* views, const uint2* pinfo,
+                  const uint2* part, uint2* wrow, uint32_t* wlen, unsigned long long* nnz,
+                  hipStream_t st);
 
 bool contract_supported(int d);
 // code tables of the codec: d in {16, 32, 48} besides the feature sizes
 bool contract_supported_codes(int d);
 void launch_contract(int64_t n, int nb, int d, bool bf16, const uint32_t* perm,
-                     const uint32_t* pair_of_m, const ViewDev* views, const uint32_t* part_base,
-                     const uint32_t* pcnt, const uint2* part, const void* feats, float* num,
-                     float* den, bool first, bool last, hipStream_t st);
+                     const uint32_t* pair_of_m, const ViewDev* views, const uint2* pinfo,
+                     const uint2* part, const void* feats, float* num, float* den, bool first,
+                     bool last, hipStream_t st);
 
 // ---- codec ----
 enum { GEMM_NONE = 0, GEMM_GELU = 1, GEMM_GELU_BWD = 2 };
