@@ -242,7 +242,8 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
     uint16_t* __restrict__ pview, uint64_t* __restrict__ dkey, uint32_t* __restrict__ dval,
     uint32_t* __restrict__ psz, uint32_t* __restrict__ pz, const uint32_t* __restrict__ sat,
     uint32_t zmin, int zbits, int pbits, uint32_t* __restrict__ blk_tot,
-    const uint32_t* __restrict__ rank, uint32_t* __restrict__ pair_of_m, uint32_t* __restrict__ ptc)
+    const uint32_t* __restrict__ rank, uint32_t* __restrict__ pair_of_m, uint2* __restrict__ prect,
+    int lbits)
 {
     __shared__ uint32_t cnt[PER_THREAD][4];
     __shared__ uint64_t msk[4][PER_THREAD];
@@ -302,8 +303,11 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         const uint32_t ps = S[(ty1 + 1) * sw + tx1 + 1] - S[ty0 * sw + tx1 + 1] -
                             S[(ty1 + 1) * sw + tx0] + S[ty0 * sw + tx0];
         psz[pidx] = ps;
-        const uint32_t tc = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-        ptc[pidx] = tc;
+        const uint32_t rw = (uint32_t)(tx1 - tx0 + 1), rh = (uint32_t)(ty1 - ty0 + 1);
+        const uint32_t tc = rw * rh;
+        // tile rectangle: (entry key of its top-left tile, width | height << 16)
+        prect[pidx] = make_uint2(((uint32_t)vl << lbits) + (uint32_t)(ty0 * V.ntx + tx0),
+                                 rw | (rh << 16));
         n_isect += tc;
         n_part += ps;
         pair_of_m[(int64_t)vl * n + rank[g]] = pidx;
@@ -464,13 +468,14 @@ void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* mea
                        const uint32_t* blk_off, float4* rec, uint32_t* pgauss, uint16_t* pview,
                        uint64_t* dkey, uint32_t* dval, uint32_t* psz, uint32_t* pz,
                        const uint32_t* sat, uint32_t zmin, int zbits, int pbits, uint32_t* blk_tot,
-                       const uint32_t* rank, uint32_t* pair_of_m, uint32_t* ptc, hipStream_t st)
+                       const uint32_t* rank, uint32_t* pair_of_m, uint2* prect, int lbits,
+                       hipStream_t st)
 {
     if (n <= 0 || nb <= 0) return;
     hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)count_blocks_per_view(n), (unsigned)nb),
                        dim3(256), 0, st, n, views, means, cov3, opac, tcnt_pairof, blk_off, rec,
                        pgauss, pview, dkey, dval, psz, pz, sat, zmin, zbits, pbits, blk_tot, rank,
-                       pair_of_m, ptc);
+                       pair_of_m, prect, lbits);
 }
 
 void launch_reduce_pairs(const uint32_t* in, uint64_t npairs, bool sum_mode,

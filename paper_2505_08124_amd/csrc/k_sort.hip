@@ -195,16 +195,19 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
     }
     __syncthreads();
     // per digit: exclusive prefix over waves, and the block total
-    uint32_t dtot[R / 256 > 0 ? R / 256 : 1];
+    constexpr int NQ = (R + 255) / 256;
+    uint32_t dtot[NQ];
 #pragma unroll
-    for (int q = 0; q < R / 256; q++) {
+    for (int q = 0; q < NQ; q++) {
         const int d = threadIdx.x + 256 * q;
         uint32_t s = 0;
+        if (d < R) {
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const uint32_t c = wcnt[k][d];
-            wcnt[k][d] = s;
-            s += c;
+            for (int k = 0; k < 4; k++) {
+                const uint32_t c = wcnt[k][d];
+                wcnt[k][d] = s;
+                s += c;
+            }
         }
         dtot[q] = s;
     }
@@ -212,7 +215,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
     {
         uint32_t run = 0;
 #pragma unroll
-        for (int q = 0; q < R / 256; q++) {
+        for (int q = 0; q < NQ; q++) {
             // digits q*256 .. q*256+255 are owned by threads 0..255 in order
             uint32_t x = dtot[q], v = x;
 #pragma unroll
@@ -224,7 +227,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
             __syncthreads();
             uint32_t off = run;
             for (int i = 0; i < w; i++) off += tmp[i];
-            lbase[threadIdx.x + 256 * q] = off + v - x;
+            if (threadIdx.x + 256 * q < R) lbase[threadIdx.x + 256 * q] = off + v - x;
             run += tmp[0] + tmp[1] + tmp[2] + tmp[3];
             __syncthreads();
         }
@@ -266,7 +269,9 @@ void radix_pass(const K* ka, const uint32_t* va, const uint32_t* ua, K* kb, uint
                        vb, ub, n, shift, hist, nblk);
 }
 
-// Stable LSD sort of (key[, value[, aux]]) by bits [bit0, bit0 + nbits), 8 bits per pass.
+// Stable LSD sort of (key[, value[, aux]]) by bits [bit0, bit0 + nbits): the
+// fewest passes of at most 8 bits, the bits split evenly over them (fewer
+// digits per pass give longer runs of equal digits, so fuller write lines).
 template <typename K, int NV>
 bool radix_sort(K* keys, uint32_t* vals, uint32_t* aux, K* keys_alt, uint32_t* vals_alt,
                 uint32_t* aux_alt, uint64_t n, int bit0, int nbits, uint32_t* hist, void* ws,
@@ -280,8 +285,16 @@ bool radix_sort(K* keys, uint32_t* vals, uint32_t* aux, K* keys_alt, uint32_t* v
     uint32_t *va = vals, *vb = vals_alt, *ua = aux, *ub = aux_alt;
     bool alt = false;
     for (int shift = bit0; shift < bit0 + nbits; shift += rb) {
-        radix_pass<K, RADIX_MAXBITS, NV>(ka, va, ua, kb, vb, ub, n, shift, hist, ws, st);
-        shift += RADIX_MAXBITS - rb;   // the digit may cover more bits than asked
+        switch (rb) {
+        case 1: radix_pass<K, 1, NV>(ka, va, ua, kb, vb, ub, n, shift, hist, ws, st); break;
+        case 2: radix_pass<K, 2, NV>(ka, va, ua, kb, vb, ub, n, shift, hist, ws, st); break;
+        case 3: radix_pass<K, 3, NV>(ka, va, ua, kb, vb, ub, n, shift, hist, ws, st); break;
+        case 4: radix_pass<K, 4, NV>(ka, va, ua, kb, vb, ub, n, shift, hist, ws, st); break;
+        case 5: radix_pass<K, 5, NV>(ka, va, ua, kb, vb, ub, n, shift, hist, ws, st); break;
+        case 6: radix_pass<K, 6, NV>(ka, va, ua, kb, vb, ub, n, shift, hist, ws, st); break;
+        case 7: radix_pass<K, 7, NV>(ka, va, ua, kb, vb, ub, n, shift, hist, ws, st); break;
+        default: radix_pass<K, 8, NV>(ka, va, ua, kb, vb, ub, n, shift, hist, ws, st); break;
+        }
         K* tk = ka; ka = kb; kb = tk;
         uint32_t* tv = va; va = vb; vb = tv;
         uint32_t* tu = ua; ua = ub; ub = tu;
@@ -310,11 +323,14 @@ __device__ __forceinline__ uint32_t pair_at_rank(const uint32_t* __restrict__ or
 
 __global__ __launch_bounds__(256) void k_rank_tiles(uint64_t npairs, const uint32_t* __restrict__ order,
                                                     const uint64_t* __restrict__ okey, uint64_t pmask,
-                                                    const uint32_t* __restrict__ ptc,
+                                                    const uint2* __restrict__ prect,
                                                     uint32_t* __restrict__ tcr)
 {
     const uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r < npairs) tcr[r] = ptc[pair_at_rank(order, okey, pmask, r)];
+    if (r < npairs) {
+        const uint32_t q = prect[pair_at_rank(order, okey, pmask, r)].y;
+        tcr[r] = (q & 0xFFFFu) * (q >> 16);
+    }
 }
 
 // (tile, pair) entries of every pair in depth order, tiles of a
@@ -325,8 +341,7 @@ __global__ __launch_bounds__(256) void k_rank_tiles(uint64_t npairs, const uint3
 // stores are coalesced.
 __global__ __launch_bounds__(256) void k_emit_isect(uint64_t npairs, const uint32_t* __restrict__ order,
                                                     const uint64_t* __restrict__ okey, uint64_t pmask,
-                                                    const float4* __restrict__ rec,
-                                                    const uint16_t* __restrict__ pview,
+                                                    const uint2* __restrict__ prect,
                                                     const ViewDev* __restrict__ views,
                                                     const uint32_t* __restrict__ ioff,
                                                     int lbits,
@@ -344,17 +359,13 @@ __global__ __launch_bounds__(256) void k_emit_isect(uint64_t npairs, const uint3
     uint32_t o = 0, tc = 0;
     if (lane < nw) {
         const uint32_t p = pair_at_rank(order, okey, pmask, r);
-        const float2 bx = reinterpret_cast<const float2*>(rec)[4 * (size_t)p + 3];
-        const uint32_t a = __float_as_uint(bx.x), b = __float_as_uint(bx.y);
-        const int tx0 = (int)(a & 0xFFFFu) / TILE, ty0 = (int)(a >> 16) / TILE;
-        const int tx1 = (int)(b & 0xFFFFu) / TILE, ty1 = (int)(b >> 16) / TILE;
-        const ViewDev& V = views[pview[p]];
+        const uint2 q = prect[p];
         o = ioff[r];
-        tc = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+        tc = (q.y & 0xFFFFu) * (q.y >> 16);
         s_p[w][lane] = p;
-        s_r[w][lane][0] = ((uint32_t)pview[p] << lbits) + (uint32_t)(ty0 * V.ntx + tx0);
-        s_r[w][lane][1] = (uint32_t)(tx1 - tx0 + 1);
-        s_r[w][lane][2] = (uint32_t)V.ntx;
+        s_r[w][lane][0] = q.x;
+        s_r[w][lane][1] = q.y & 0xFFFFu;
+        s_r[w][lane][2] = (uint32_t)views[q.x >> lbits].ntx;
         s_off[w][lane] = o;
     }
     const uint32_t o0 = __builtin_amdgcn_readfirstlane(o);
@@ -485,21 +496,21 @@ bool radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t
 }
 
 void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const uint64_t* okey,
-                       uint64_t pmask, const uint32_t* ptc, uint32_t* tcr, hipStream_t st)
+                       uint64_t pmask, const uint2* prect, uint32_t* tcr, hipStream_t st)
 {
     if (!npairs) return;
     hipLaunchKernelGGL(k_rank_tiles, dim3(grid_for(npairs)), dim3(256), 0, st, npairs, order, okey,
-                       pmask, ptc, tcr);
+                       pmask, prect, tcr);
 }
 
 void launch_emit_isect(uint64_t npairs, const uint32_t* order, const uint64_t* okey,
-                       uint64_t pmask, const float4* rec, const uint16_t* pview,
-                       const ViewDev* views, const uint32_t* ioff, int lbits, uint32_t* ikey,
-                       uint32_t* ival, hipStream_t st)
+                       uint64_t pmask, const uint2* prect, const ViewDev* views,
+                       const uint32_t* ioff, int lbits, uint32_t* ikey, uint32_t* ival,
+                       hipStream_t st)
 {
     if (!npairs) return;
     hipLaunchKernelGGL(k_emit_isect, dim3(grid_for(npairs)), dim3(256), 0, st, npairs, order, okey,
-                       pmask, rec, pview, views, ioff, lbits, ikey, ival);
+                       pmask, prect, views, ioff, lbits, ikey, ival);
 }
 
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st)

@@ -366,10 +366,9 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
     CK(ensure(c, c->dval_alt, np * 4));
     CK(ensure(c, c->psz, np * 4 + 16));
     CK(ensure(c, c->pz, np * 4));
-    CK(ensure(c, c->ptc, np * 4));
+    CK(ensure(c, c->prect, np * 8));
     CK(ensure(c, c->tcr, np * 4 + 16));
     CK(ensure(c, c->wlen, np * 4));
-    CK(ensure(c, c->pcnt, np * 4));
     CK(ensure(c, c->pair_of_m, npq * 4));
     launch_emit_pairs(nb, n, views, c->means.as<float>(), c->cov3.as<float>(), c->opac.as<float>(),
                       c->tcnt.as<uint32_t>(), c->blk_vis.as<uint32_t>(), c->rec.as<float4>(),
@@ -377,7 +376,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
                       c->dkey.as<uint64_t>(), c->dval.as<uint32_t>(), c->psz.as<uint32_t>(),
                       debug ? c->pz.as<uint32_t>() : nullptr,
                       c->sat.as<uint32_t>(), zmin, zbits, pbits, c->blk_aux.as<uint32_t>(),
-                      c->rank.as<uint32_t>(), c->pair_of_m.as<uint32_t>(), c->ptc.as<uint32_t>(),
+                      c->rank.as<uint32_t>(), c->pair_of_m.as<uint32_t>(), c->prect.as<uint2>(), B.lbits,
                       st);
     launch_reduce_pairs(c->blk_aux.as<uint32_t>(), nblk, true,
                         reinterpret_cast<unsigned long long*>(small + SM_TOTALS), st);
@@ -424,19 +423,18 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         }
         CK(stage_end(c, ST_DEPTH_SORT, ev));
 
-        // (tile, pair, part slot) entries in depth order; part slots pair-major
+        // (tile, pair) entries in depth order; part-list bases (pair-major) by scan
         CK(stage_begin(c, ST_BIN, &ev));
-        HC(c, hipMemcpyAsync(c->pcnt.p, c->psz.p, npairs * 4, hipMemcpyDeviceToDevice, st));
         scan_u32(c->psz.as<uint32_t>(), npairs, nullptr, c->scan_ws.p, st);
         CK(ensure(c, c->ikey, ni * 4));
         CK(ensure(c, c->ikey_alt, ni * 4));
         CK(ensure(c, c->ival, ni * 4));
         CK(ensure(c, c->ival_alt, ni * 4));
-        launch_rank_tiles(npairs, order, okey, pmask, c->ptc.as<uint32_t>(), c->tcr.as<uint32_t>(),
+        launch_rank_tiles(npairs, order, okey, pmask, c->prect.as<uint2>(), c->tcr.as<uint32_t>(),
                           st);
         scan_u32(c->tcr.as<uint32_t>(), npairs, nullptr, c->scan_ws.p, st);
-        launch_emit_isect(npairs, order, okey, pmask, c->rec.as<float4>(), c->pview.as<uint16_t>(),
-                          views, c->tcr.as<uint32_t>(), B.lbits, c->ikey.as<uint32_t>(),
+        launch_emit_isect(npairs, order, okey, pmask, c->prect.as<uint2>(), views,
+                          c->tcr.as<uint32_t>(), B.lbits, c->ikey.as<uint32_t>(),
                           c->ival.as<uint32_t>(), st);
         CK(stage_end(c, ST_BIN, ev));
 
@@ -598,8 +596,8 @@ void slag_destroy(slag_ctx* c)
                       &c->small, &c->scan_ws, &c->hist, &c->rec, &c->pgauss, &c->pview, &c->dkey,
                       &c->dkey_alt, &c->dval, &c->dval_alt, &c->psz, &c->pz, &c->tcr, &c->wlen,
                       &c->ikey, &c->ikey_alt, &c->ival, &c->ival_alt, &c->bstart, &c->bend,
-                      &c->part, &c->wrow, &c->perm, &c->rank, &c->pair_of_m, &c->pcnt,
-                      &c->pinfo, &c->ptc, &c->blk_aux, &c->bkey,
+                      &c->part, &c->wrow, &c->perm, &c->rank, &c->pair_of_m,
+                      &c->pinfo, &c->prect, &c->blk_aux, &c->bkey,
                       &c->bkey_alt, &c->bord, &c->bord_alt};
     destroy_graph(c);
     for (DevBuf* b : bufs) release(*b);

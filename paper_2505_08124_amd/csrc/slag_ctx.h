@@ -110,8 +110,8 @@ struct slag_ctx {
     slag_host::DevBuf ns_tile, segl, sat, tcnt, blk_vis, small, scan_ws, hist;
     slag_host::DevBuf rec, pgauss, pview, dkey, dkey_alt, dval, dval_alt, psz, pz, tcr, wlen,
         pair_of_m;
-    slag_host::DevBuf ikey, ikey_alt, ival, ival_alt, bstart, bend, part, wrow, pcnt, pinfo;
-    slag_host::DevBuf ptc, blk_aux, bkey, bkey_alt, bord, bord_alt;
+    slag_host::DevBuf ikey, ikey_alt, ival, ival_alt, bstart, bend, part, wrow, pinfo;
+    slag_host::DevBuf prect, blk_aux, bkey, bkey_alt, bord, bord_alt;
     uint64_t* host_small = nullptr;   // pinned read-back area
 
     slag_host::CodecState codec;

@@ -43,7 +43,8 @@ void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* mea
                        const uint32_t* blk_off, float4* rec, uint32_t* pgauss, uint16_t* pview,
                        uint64_t* dkey, uint32_t* dval, uint32_t* psz, uint32_t* pz,
                        const uint32_t* sat, uint32_t zmin, int zbits, int pbits, uint32_t* blk_tot,
-                       const uint32_t* rank, uint32_t* pair_of_m, uint32_t* ptc, hipStream_t st);
+                       const uint32_t* rank, uint32_t* pair_of_m, uint2* prect, int lbits,
+                       hipStream_t st);
 // out[0..1] = (min of even, max of odd) entries of in[2 * npairs], or their
 // 64-bit sums in sum mode; one block
 void launch_reduce_pairs(const uint32_t* in, uint64_t npairs, bool sum_mode,
@@ -73,13 +74,14 @@ bool radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t
 bool radix_sort_u64_keys(uint64_t* keys, uint64_t* keys_alt, uint64_t n, int bit0, int nbits,
                          uint32_t* hist, void* scan_ws, hipStream_t st);
 
-// depth order: order[r], or (okey non-null) okey[r] & pmask
+// depth order: order[r], or (okey non-null) okey[r] & pmask; prect[p] = (entry
+// key of the pair's top-left tile, rectangle width | height << 16)
 void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const uint64_t* okey,
-                       uint64_t pmask, const uint32_t* ptc, uint32_t* tcr, hipStream_t st);
+                       uint64_t pmask, const uint2* prect, uint32_t* tcr, hipStream_t st);
 void launch_emit_isect(uint64_t npairs, const uint32_t* order, const uint64_t* okey,
-                       uint64_t pmask, const float4* rec, const uint16_t* pview,
-                       const ViewDev* views, const uint32_t* ioff, int lbits, uint32_t* ikey,
-                       uint32_t* ival, hipStream_t st);
+                       uint64_t pmask, const uint2* prect, const ViewDev* views,
+                       const uint32_t* ioff, int lbits, uint32_t* ikey, uint32_t* ival,
+                       hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
 // Dispatch keys: (resolution class << 16) | (0xFFFF - min(list length, 0xFFFF)).
 void launch_bucket_keys(uint32_t nb, const uint32_t* bucket_view, const uint8_t* view_cls,
