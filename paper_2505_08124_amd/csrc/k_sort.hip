@@ -94,18 +94,25 @@ __global__ __launch_bounds__(256) void k_scan_block(uint32_t* __restrict__ data,
 
 // ---------------------------------------------------------------- radix sort
 //
-// One pass sorts by an 8-bit digit.  Block tile: 4 waves x 8 items x 64
-// lanes; element order inside a block is (wave, item, lane) = ascending index,
+// One pass sorts by a digit of up to 8 bits.  Block tile: 4 waves x ITEMS
+// items x 64 lanes; element order inside a block is (wave, item, lane) = ascending index,
 // so ranking equal digits with ballots, wave by wave, keeps the sort stable.
 // Elements are regrouped by digit in LDS before the global write, so each
 // digit's run leaves the block as consecutive addresses.  An optional second
 // value array rides along.
 
-constexpr int RADIX_ITEMS = 8;
-constexpr int RADIX_TILE = 256 * RADIX_ITEMS;
+// Items per thread: 16 (4096-element blocks) for passes of 6 bits or more,
+// whose many digits need the longer blocks to keep runs of equal digits
+// long; 8 below that, where smaller blocks give more workgroups.
+constexpr int RADIX_ITEMS_MIN = 8;
+constexpr int RADIX_TILE_MIN = 256 * RADIX_ITEMS_MIN;
 constexpr int RADIX_MAXBITS = 8;
+template <int RB> constexpr int radix_items() { return RB >= 6 ? 16 : 8; }
 
-template <typename K, int RB>
+// One wave counts one sort block (256 * ITEMS keys, 4 * ITEMS coalesced
+// loads per lane, all in flight), so a workgroup covers four blocks and each
+// wave writes its own column of the (digit, block) matrix.
+template <typename K, int RB, int ITEMS>
 __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, uint64_t n,
                                                     int shift, uint32_t* __restrict__ hist,
                                                     uint32_t nblk)
@@ -113,32 +120,44 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
     // per-wave counts in LDS: one add when a wave's items share a digit
     // (common for the high digits), else one LDS atomic per item
     constexpr int R = 1 << RB;
+    constexpr int TILE_N = 256 * ITEMS;
+    constexpr int PER = TILE_N / 64;
     __shared__ uint32_t cnt[4][R];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < 4 * R; i += 256) (&cnt[0][0])[i] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * RADIX_TILE + (uint64_t)w * (RADIX_ITEMS * 64);
+    const uint64_t sb = (uint64_t)blockIdx.x * 4 + w;
+    if (sb < nblk) {
+        const uint64_t base = sb * TILE_N + lane;
+        K k[PER];
 #pragma unroll
-    for (int it = 0; it < RADIX_ITEMS; it++) {
-        const uint64_t idx = base + it * 64 + lane;
-        const bool valid = idx < n;
-        const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & (R - 1) : 0u;
-        // all valid lanes on one digit: the first adds them; else LDS atomics
-        const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
-        const uint64_t vm = __ballot(valid);
-        if (__ballot(valid && d != d0) == 0) {
-            if (lane == 0 && vm) cnt[w][d0] += (uint32_t)__popcll(vm);
-        } else if (valid) {
-            atomicAdd(&cnt[w][d], 1u);
+        for (int it = 0; it < PER; it++) {
+            const uint64_t idx = base + (uint64_t)it * 64;
+            k[it] = idx < n ? keys[idx] : (K)0;
         }
-        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int it = 0; it < PER; it++) {
+            const bool valid = base + (uint64_t)it * 64 < n;
+            const uint32_t d = (uint32_t)(k[it] >> shift) & (R - 1);
+            // all valid lanes on one digit: the first adds them; else LDS atomics
+            const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
+            const uint64_t vm = __ballot(valid);
+            if (__ballot(valid && d != d0) == 0) {
+                if (lane == 0 && vm) cnt[w][d0] += (uint32_t)__popcll(vm);
+            } else if (valid) {
+                atomicAdd(&cnt[w][d], 1u);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < R; i += 256)
-        hist[(uint64_t)i * nblk + blockIdx.x] = cnt[0][i] + cnt[1][i] + cnt[2][i] + cnt[3][i];
+    for (int i = threadIdx.x; i < 4 * R; i += 256) {
+        const uint64_t b = (uint64_t)blockIdx.x * 4 + i / R;
+        if (b < nblk) hist[(uint64_t)(i % R) * nblk + b] = cnt[i / R][i % R];
+    }
 }
 
-template <typename K, int RB, int NV>
+template <typename K, int RB, int NV, int ITEMS>
 __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin,
                                                        const uint32_t* __restrict__ vin,
                                                        const uint32_t* __restrict__ uin,
@@ -150,27 +169,28 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
                                                        uint32_t nblk)
 {
     constexpr int R = 1 << RB;
+    constexpr int TILE_N = 256 * ITEMS;
     __shared__ uint32_t wcnt[4][R];
     __shared__ uint32_t dbase[R];     // global start of each digit for this block
     __shared__ uint32_t lbase[R];     // block-local start of each digit
     __shared__ uint32_t tmp[8];
-    __shared__ K s_key[RADIX_TILE];
-    __shared__ uint32_t s_val[NV >= 1 ? RADIX_TILE : 1];
-    __shared__ uint32_t s_aux[NV >= 2 ? RADIX_TILE : 1];
+    __shared__ K s_key[TILE_N];
+    __shared__ uint32_t s_val[NV >= 1 ? TILE_N : 1];
+    __shared__ uint32_t s_aux[NV >= 2 ? TILE_N : 1];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < 4 * R; i += 256) (&wcnt[0][0])[i] = 0;
     for (int i = threadIdx.x; i < R; i += 256) dbase[i] = hist[(uint64_t)i * nblk + blockIdx.x];
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint64_t bbase = (uint64_t)blockIdx.x * RADIX_TILE;
-    const uint64_t base = bbase + (uint64_t)w * (RADIX_ITEMS * 64);
-    const int nvalid = (int)min((uint64_t)RADIX_TILE, n - bbase);
-    K key[RADIX_ITEMS];
-    uint32_t val[NV >= 1 ? RADIX_ITEMS : 1];
-    uint32_t aux[NV >= 2 ? RADIX_ITEMS : 1];
-    uint32_t rk[RADIX_ITEMS];
+    const uint64_t bbase = (uint64_t)blockIdx.x * TILE_N;
+    const uint64_t base = bbase + (uint64_t)w * (ITEMS * 64);
+    const int nvalid = (int)min((uint64_t)TILE_N, n - bbase);
+    K key[ITEMS];
+    uint32_t val[NV >= 1 ? ITEMS : 1];
+    uint32_t aux[NV >= 2 ? ITEMS : 1];
+    uint32_t rk[ITEMS];
 #pragma unroll
-    for (int it = 0; it < RADIX_ITEMS; it++) {
+    for (int it = 0; it < ITEMS; it++) {
         const uint64_t idx = base + it * 64 + lane;
         const bool valid = idx < n;
         key[it] = valid ? kin[idx] : (K)0;
@@ -235,7 +255,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
     __syncthreads();
     // reorder through LDS so that equal digits sit together ...
 #pragma unroll
-    for (int it = 0; it < RADIX_ITEMS; it++) {
+    for (int it = 0; it < ITEMS; it++) {
         const uint64_t idx = base + it * 64 + lane;
         if (idx < n) {
             const uint32_t d = (uint32_t)(key[it] >> shift) & (R - 1);
@@ -261,12 +281,14 @@ template <typename K, int RB, int NV>
 void radix_pass(const K* ka, const uint32_t* va, const uint32_t* ua, K* kb, uint32_t* vb,
                 uint32_t* ub, uint64_t n, int shift, uint32_t* hist, void* ws, hipStream_t st)
 {
-    const uint32_t nblk = (uint32_t)((n + RADIX_TILE - 1) / RADIX_TILE);
-    hipLaunchKernelGGL((k_radix_hist<K, RB>), dim3(nblk), dim3(256), 0, st, ka, n, shift, hist,
-                       nblk);
+    constexpr int ITEMS = radix_items<RB>();
+    constexpr int TILE_N = 256 * ITEMS;
+    const uint32_t nblk = (uint32_t)((n + TILE_N - 1) / TILE_N);
+    hipLaunchKernelGGL((k_radix_hist<K, RB, ITEMS>), dim3((nblk + 3) / 4), dim3(256), 0, st, ka, n,
+                       shift, hist, nblk);
     scan_u32(hist, (uint64_t)nblk << RB, nullptr, ws, st);
-    hipLaunchKernelGGL((k_radix_scatter<K, RB, NV>), dim3(nblk), dim3(256), 0, st, ka, va, ua, kb,
-                       vb, ub, n, shift, hist, nblk);
+    hipLaunchKernelGGL((k_radix_scatter<K, RB, NV, ITEMS>), dim3(nblk), dim3(256), 0, st, ka, va, ua,
+                       kb, vb, ub, n, shift, hist, nblk);
 }
 
 // Stable LSD sort of (key[, value[, aux]]) by bits [bit0, bit0 + nbits): the
@@ -467,7 +489,8 @@ void scan_u32(uint32_t* data, uint64_t n, uint64_t* total_dev, void* ws, hipStre
 
 size_t radix_hist_bytes(uint64_t n)
 {
-    return ((n + RADIX_TILE - 1) / RADIX_TILE) * ((size_t)1 << RADIX_MAXBITS) * sizeof(uint32_t) + 256;
+    return ((n + RADIX_TILE_MIN - 1) / RADIX_TILE_MIN) * ((size_t)1 << RADIX_MAXBITS) * sizeof(uint32_t) +
+           256;
 }
 
 bool radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
