@@ -24,6 +24,7 @@ constexpr float AMAX = 0.99f;
 constexpr float TMIN = 1e-4f;
 constexpr float NHALF_LOG2E = -0.72134752044448170368f;   // -log2(e) / 2
 constexpr float NLOG2E = -1.44269504088896340736f;        // -log2(e)
+constexpr float LOG2_AMIN = -7.99435343685885793770f;     // log2(1 / 255)
 
 __device__ __forceinline__ void box_of(const float4& r1, int& x0, int& x1, int& y0, int& y1)
 {
@@ -135,6 +136,35 @@ __device__ __forceinline__ float wave_total(float v)
 }
 
 enum { MODE_NONE = 0, MODE_UNIFORM = 1, MODE_MIXED = 2 };
+
+// max over t in [t0, t1] of P a^2 + Q a t + R t^2 (R < 0): the vertex
+// -Q a / (2 R), clamped to the interval (the reciprocal's rounding moves the
+// point, and so the value, by far less than the caller's margin)
+__device__ __forceinline__ float qmax_edge(float a, float t0, float t1, float P, float Q, float R)
+{
+    const float t = fminf(fmaxf(-0.5f * (Q * a) * __builtin_amdgcn_rcpf(R), t0), t1);
+    return fmaf(fmaf(R, t, Q * a), t, P * a * a);
+}
+
+// Can an entry reach alpha >= 1/255 at any pixel of the active rectangle
+// (offsets dx in [x0, x1], dy in [y0, y1] from its mean)?  The exponent
+// log2(o) + A dx^2 + B dx dy + C dy^2 is concave, so its maximum over the
+// rectangle is 0 + log2(o) when the mean lies inside, else the largest of the
+// four edge maxima.  An entry is dropped only when that maximum stays below
+// log2(1/255) by a margin (0.01, plus 1e-6 of the magnitude of the terms the
+// blend sums) beyond any rounding of the blend's own evaluation: then every
+// pixel gets alpha < 1/255 and is left unchanged, so dropping it is exact.
+__device__ __forceinline__ bool reaches_amin(float A, float B, float C, float lo2, float x0,
+                                             float x1, float y0, float y1)
+{
+    float m = 0.0f;
+    if (!(x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f))
+        m = fmaxf(fmaxf(qmax_edge(x0, y0, y1, A, B, C), qmax_edge(x1, y0, y1, A, B, C)),
+                  fmaxf(qmax_edge(y0, x0, x1, C, B, A), qmax_edge(y1, x0, x1, C, B, A)));
+    const float d = fmaxf(fmaxf(fabsf(x0), fabsf(x1)), fmaxf(fabsf(y0), fabsf(y1))) + 8.0f;
+    const float mag = 3.0f * (fabsf(A) + fabsf(B) + fabsf(C)) * d * d + fabsf(lo2);
+    return lo2 + m >= LOG2_AMIN - 0.01f - 1e-6f * mag;
+}
 
 // Wave sums of four per-lane values: on return every lane of row r (lanes
 // 16 r .. 16 r + 15) holds the sum of value r over all 64 lanes.  Two lane
@@ -339,24 +369,29 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
                 ay0 = __builtin_ctzll(am) >> 3;
                 ay1 = (63 - __builtin_clzll(am)) >> 3;
             }
-            // compact the entries whose pixel box meets those pixels' box
+            // compact the entries whose pixel box meets those pixels' box (and,
+            // outside the counting pass, that can reach alpha >= 1/255 there)
             const uint32_t ba = __float_as_uint(q1.z), bb = __float_as_uint(q1.w);
-            const bool hit = lane < nb && (int)(bb & 0xFFFFu) >= bx0 + ax0 &&
-                             (int)(ba & 0xFFFFu) <= bx0 + ax1 && (int)(bb >> 16) >= by0 + ay0 &&
-                             (int)(ba >> 16) <= by0 + ay1;
+            bool hit = lane < nb && (int)(bb & 0xFFFFu) >= bx0 + ax0 &&
+                       (int)(ba & 0xFFFFu) <= bx0 + ax1 && (int)(bb >> 16) >= by0 + ay0 &&
+                       (int)(ba >> 16) <= by0 + ay1;
+            // exponent log2(o) + A dx^2 + B dx dy + C dy^2 with dx = lx - du,
+            // dy = ly - dv (pixel centre relative to the entry's mean)
+            const float A = q0.z * NHALF_LOG2E, B = q0.w * NLOG2E, C = q1.x * NHALF_LOG2E;
+            const float du = q0.x - ((float)bx0 + 0.5f), dv = q0.y - ((float)by0 + 0.5f);
+            const float lo2 = __builtin_amdgcn_logf(q1.y);
+            if (!COUNT && hit)
+                hit = reaches_amin(A, B, C, lo2, (float)ax0 - du, (float)ax1 - du, (float)ay0 - dv,
+                                   (float)ay1 - dv);
             const uint64_t hm = __ballot(hit);
             const int cnt = __popcll(hm);
             if (hit) {
-                // exponent log2(o) + A dx^2 + B dx dy + C dy^2 with dx = lx - du,
-                // dy = ly - dv (pixel centre relative to the entry's mean),
-                // expanded in the block coordinates lx, ly: six coefficients
+                // the exponent expanded in the block coordinates lx, ly: six
+                // coefficients
                 const int k = __popcll(hm & lt);
-                const float A = q0.z * NHALF_LOG2E, B = q0.w * NLOG2E, C = q1.x * NHALF_LOG2E;
-                const float du = q0.x - ((float)bx0 + 0.5f), dv = q0.y - ((float)by0 + 0.5f);
                 const float cx = -fmaf(2.0f * A, du, B * dv);
                 const float cy = -fmaf(B, du, 2.0f * C * dv);
-                const float c0 = fmaf(A * du, du, fmaf(B * du, dv, C * dv * dv)) +
-                                 __builtin_amdgcn_logf(q1.y);
+                const float c0 = fmaf(A * du, du, fmaf(B * du, dv, C * dv * dv)) + lo2;
                 s_w0[wv][k] = make_float4(c0, cx, cy, A);
                 s_w1[wv][k] = make_float4(B, C, q1.z, q1.w);
                 s_wj[wv][k] = lane;
