@@ -48,6 +48,10 @@ constexpr int kContractRT = 1;  // row tiles per block (G = 16 Gaussians; 2 and 
 // G = 16 RT rows per block; thread t walks row t % G and views
 // v0 + t / G + (256 / G) j, j < VPT: GV = VPT 256 / G views per step.
 constexpr int VPT = 2;
+// Part-list entries of one step staged in LDS (a step with more reads them
+// from global memory in both passes); SU loads per thread in flight.
+constexpr int STAGE = 3072;
+constexpr int SU = 4;
 template <int RT>
 struct BlockLds {
     static constexpr int G = 16 * RT, GT = 256 / G, GV = VPT * GT;
@@ -57,6 +61,11 @@ struct BlockLds {
     int64_t A[G][KMAX + 1];     // weights of the round's columns, fixed point
     float dpart[GV][G];         // per-view row weight sums of the step
     uint32_t scan[8];
+    // the step's part-list entries, staged once (both passes read them)
+    uint2 stage[STAGE];
+    uint32_t soff[256];         // first staged entry of each thread
+    uint32_t spb[256][VPT];     // list base and length of each thread's pairs
+    uint32_t scnt[256][VPT];
 };
 
 // Multiply columns [k0, k0 + kn) of the staged round into the accumulators
@@ -206,6 +215,54 @@ __global__ __launch_bounds__(256, 3) void k_contract_mfma(
             nsv = max(nsv, v < nb ? views[v].nseg : 0u);
         }
         if (!__syncthreads_or(any)) continue;
+        // stage the step's entries: thread t's lists go to [soff[t], ...) in
+        // pair order; all threads load, SU clamped (always valid) loads each
+        // in flight, the owner of entry i found by binary search over soff
+        uint32_t sb[VPT];
+        bool staged;
+        {
+            uint32_t ct = 0;
+#pragma unroll
+            for (int j = 0; j < VPT; j++) {
+                sb[j] = ct;
+                ct += cnt[j];
+                L.spb[t][j] = pb[j];
+                L.scnt[t][j] = cnt[j];
+            }
+            uint32_t tot;
+            const uint32_t off = block_exscan(ct, L.scan, tot);
+#pragma unroll
+            for (int j = 0; j < VPT; j++) sb[j] += off;
+            L.soff[t] = off;
+            staged = tot <= (uint32_t)STAGE;
+            __syncthreads();
+            if (staged && tot) {
+                for (uint32_t i0 = 0; i0 < tot; i0 += 256 * SU) {
+                    uint2 xv[SU];
+#pragma unroll
+                    for (int u = 0; u < SU; u++) {
+                        const uint32_t i = min(i0 + (uint32_t)(u * 256 + t), tot - 1u);
+                        int lo = 0, hi = 255;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (L.soff[mid] <= i) lo = mid; else hi = mid - 1;
+                        }
+                        uint32_t k = i - L.soff[lo];
+                        int jj = 0;
+#pragma unroll
+                        for (int j = 0; j + 1 < VPT; j++)
+                            if (jj == j && k >= L.scnt[lo][j]) { k -= L.scnt[lo][j]; jj = j + 1; }
+                        xv[u] = part[L.spb[lo][jj] + k];
+                    }
+#pragma unroll
+                    for (int u = 0; u < SU; u++) {
+                        const uint32_t i = i0 + (uint32_t)(u * 256 + t);
+                        if (i < tot) L.stage[i] = xv[u];
+                    }
+                }
+                __syncthreads();
+            }
+        }
         // bitmap words: word i covers view v0 + (i >> 3), ids w0 + 32 (i & 7) + [0, 32)
         int64_t dv[VPT];
 #pragma unroll
@@ -219,7 +276,7 @@ __global__ __launch_bounds__(256, 3) void k_contract_mfma(
             for (int j = 0; j < VPT; j++) {
                 const int vw = (vt + GT * j) * 8;
                 for (uint32_t k = 0; k < cnt[j]; k++) {
-                    const uint2 x = part[pb[j] + k];
+                    const uint2 x = staged ? L.stage[sb[j] + k] : part[pb[j] + k];
                     const uint32_t s = (x.x & 0xFFFFu) - w0;
                     const float w = __uint_as_float(x.y);
                     if (s < 256u && w > 0.0f) {
@@ -272,7 +329,7 @@ __global__ __launch_bounds__(256, 3) void k_contract_mfma(
                 for (int j = 0; j < VPT; j++) {
                     const int vw = (vt + GT * j) * 8;
                     for (uint32_t k = 0; k < cnt[j]; k++) {
-                        const uint2 x = part[pb[j] + k];
+                        const uint2 x = staged ? L.stage[sb[j] + k] : part[pb[j] + k];
                         const uint32_t s = (x.x & 0xFFFFu) - w0;
                         const float w = __uint_as_float(x.y);
                         if (s >= 256u || !(w > 0.0f)) continue;
