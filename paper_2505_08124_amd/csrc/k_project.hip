@@ -230,11 +230,12 @@ __global__ __launch_bounds__(256) void k_count(int64_t n, const ViewDev* __restr
     }
 }
 
-// Pass 2: compact visible pairs in (view, Gaussian) order and write their
-// records, depth-sort keys, part-list capacities and the (view, Morton rank)
-// -> pair map (NONE where not visible); pgauss and pz (Gaussian index and
-// depth bits per pair) only when given, for the debug exports.  Same striped
-// layout as pass 1.
+// Pass 2: compact visible pairs in (view, Gaussian) order (Gaussians are
+// stored in Morton order) and write their records, depth-sort keys, part-list
+// capacities, the caller's index of each pair's Gaussian (pgauss: the depth
+// order breaks ties by it) and the (view, Morton rank) -> pair map (NONE
+// where not visible); pz (depth bits per pair) only when given, for the
+// debug exports.  Same striped layout as pass 1.
 __global__ __launch_bounds__(256) void k_emit_pairs(
     int64_t n, const ViewDev* __restrict__ views, const float* __restrict__ means,
     const float* __restrict__ cov3, const float* __restrict__ opac, uint32_t* __restrict__ tcnt,
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
     uint16_t* __restrict__ pview, uint64_t* __restrict__ dkey, uint32_t* __restrict__ dval,
     uint32_t* __restrict__ psz, uint32_t* __restrict__ pz, const uint32_t* __restrict__ sat,
     uint32_t zmin, int zbits, int pbits, uint32_t* __restrict__ blk_tot,
-    const uint32_t* __restrict__ rank, uint32_t* __restrict__ pair_of_m, uint2* __restrict__ prect,
+    const uint32_t* __restrict__ perm, uint32_t* __restrict__ pair_of_m, uint2* __restrict__ prect,
     int lbits)
 {
     __shared__ uint32_t cnt[PER_THREAD][4];
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         run += cnt[i][0] + cnt[i][1] + cnt[i][2] + cnt[i][3];
         if (g >= n) continue;
         if (!((m >> lane) & 1ull)) {
-            pair_of_m[(int64_t)vl * n + rank[g]] = NONE;
+            pair_of_m[(int64_t)vl * n + g] = NONE;
             continue;
         }
         float C[6];
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         rec[2 * (size_t)pidx + 1] =
             make_float4(P.cc, opac[g], __uint_as_float((uint32_t)P.x0 | ((uint32_t)P.y0 << 16)),
                         __uint_as_float((uint32_t)P.x1 | ((uint32_t)P.y1 << 16)));
-        if (pgauss) pgauss[pidx] = (uint32_t)g;      // debug exports only
+        pgauss[pidx] = perm[g];                      // the caller's index of the Gaussian
         pview[pidx] = (uint16_t)vl;
         const uint64_t dk = ((uint64_t)vl << zbits) | (uint64_t)(__float_as_uint(P.z) - zmin);
         if (pbits) {
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
                                  rw | (rh << 16));
         n_isect += tc;
         n_part += ps;
-        pair_of_m[(int64_t)vl * n + rank[g]] = pidx;
+        pair_of_m[(int64_t)vl * n + g] = pidx;
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
@@ -433,6 +434,26 @@ __global__ __launch_bounds__(256) void k_invert(int64_t n, const uint32_t* __res
     if (q < n) rank[perm[q]] = (uint32_t)q;
 }
 
+// Gaussian q of the Morton order from input Gaussian perm[q]: means [n][3],
+// covariances [6][n], opacities [n].
+__global__ __launch_bounds__(256) void k_gather_gauss(int64_t n, const uint32_t* __restrict__ perm,
+                                                      const float* __restrict__ means,
+                                                      const float* __restrict__ cov3,
+                                                      const float* __restrict__ opac,
+                                                      float* __restrict__ means_o,
+                                                      float* __restrict__ cov3_o,
+                                                      float* __restrict__ opac_o)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const int64_t g = perm[q];
+#pragma unroll
+    for (int k = 0; k < 3; k++) means_o[3 * q + k] = means[3 * g + k];
+#pragma unroll
+    for (int k = 0; k < 6; k++) cov3_o[k * n + q] = cov3[k * n + g];
+    opac_o[q] = opac[g];
+}
+
 }  // namespace
 
 int count_blocks_per_view(int64_t n) { return (int)((n + CPB - 1) / CPB); }
@@ -468,13 +489,13 @@ void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* mea
                        const uint32_t* blk_off, float4* rec, uint32_t* pgauss, uint16_t* pview,
                        uint64_t* dkey, uint32_t* dval, uint32_t* psz, uint32_t* pz,
                        const uint32_t* sat, uint32_t zmin, int zbits, int pbits, uint32_t* blk_tot,
-                       const uint32_t* rank, uint32_t* pair_of_m, uint2* prect, int lbits,
+                       const uint32_t* perm, uint32_t* pair_of_m, uint2* prect, int lbits,
                        hipStream_t st)
 {
     if (n <= 0 || nb <= 0) return;
     hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)count_blocks_per_view(n), (unsigned)nb),
                        dim3(256), 0, st, n, views, means, cov3, opac, tcnt_pairof, blk_off, rec,
-                       pgauss, pview, dkey, dval, psz, pz, sat, zmin, zbits, pbits, blk_tot, rank,
+                       pgauss, pview, dkey, dval, psz, pz, sat, zmin, zbits, pbits, blk_tot, perm,
                        pair_of_m, prect, lbits);
 }
 
@@ -506,6 +527,15 @@ void launch_invert(int64_t n, const uint32_t* perm, uint32_t* rank, hipStream_t 
     if (n <= 0) return;
     hipLaunchKernelGGL(k_invert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, perm,
                        rank);
+}
+
+void launch_gather_gauss(int64_t n, const uint32_t* perm, const float* means, const float* cov3,
+                         const float* opac, float* means_o, float* cov3_o, float* opac_o,
+                         hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gather_gauss, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, perm,
+                       means, cov3, opac, means_o, cov3_o, opac_o);
 }
 
 }  // namespace slag

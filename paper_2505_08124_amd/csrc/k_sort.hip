@@ -450,9 +450,207 @@ __global__ __launch_bounds__(256) void k_bucket_keys(uint32_t nb,
     val[b] = b;
 }
 
+// ----------------------------------------------------------- depth ties
+//
+// After the depth sort, pairs of one view with bitwise-equal depth keep the
+// order of their pair indices, i.e. of the Morton order the Gaussians are
+// stored in; the depth order breaks such ties by the caller's Gaussian index
+// instead.  Exact FP32 depth ties are frequent in large scenes (mostly
+// pairs and triples), and a run can be as long as a view (a plane facing the
+// camera).  Runs of up to TIE_SHORT pairs are sorted in registers by the
+// thread at their head; longer ones are compacted, sorted by (run, Gaussian
+// index) with the radix sort and written back into their positions.
+// hi(i) = keys[i] >> shift is the key without its pair field; only the pair
+// field (or order[]) is ever rewritten, so concurrent readers of hi see
+// unchanged values.
+
+constexpr int TIE_SHORT = 8;
+
+__device__ __forceinline__ uint64_t tie_hi(const uint64_t* __restrict__ keys, int shift, uint64_t i)
+{
+    return keys[i] >> shift;
+}
+
+// Is position i inside a run of more than TIE_SHORT equal keys?  (Some window
+// of TIE_SHORT + 1 consecutive positions around i has equal ends.)
+__device__ __forceinline__ bool in_long_run(const uint64_t* __restrict__ keys, int shift,
+                                            uint64_t n, uint64_t i)
+{
+    const uint64_t h = tie_hi(keys, shift, i);
+    const bool nb = (i > 0 && tie_hi(keys, shift, i - 1) == h) ||
+                    (i + 1 < n && tie_hi(keys, shift, i + 1) == h);
+    if (!nb) return false;
+    for (uint64_t a = 0; a <= (uint64_t)TIE_SHORT; a++) {
+        if (a > i || i - a + TIE_SHORT >= n) continue;
+        if (tie_hi(keys, shift, i - a) == h && tie_hi(keys, shift, i - a + TIE_SHORT) == h)
+            return true;
+    }
+    return false;
+}
+
+__device__ __forceinline__ uint32_t pair_of(const uint64_t* __restrict__ keys,
+                                            const uint32_t* __restrict__ order, uint64_t pmask,
+                                            uint64_t i)
+{
+    return order ? order[i] : (uint32_t)(keys[i] & pmask);
+}
+
+// Short runs sorted by their head thread; positions in long runs counted
+// into *nlong.
+__global__ __launch_bounds__(256) void k_tie_short(uint64_t n, uint64_t* __restrict__ keys, int shift,
+                                                   uint32_t* __restrict__ order, uint64_t pmask,
+                                                   const uint32_t* __restrict__ gidx,
+                                                   unsigned long long* __restrict__ nlong)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    bool lng = false;
+    if (i < n) {
+        lng = in_long_run(keys, shift, n, i);
+        const uint64_t h = tie_hi(keys, shift, i);
+        const bool head = (i == 0 || tie_hi(keys, shift, i - 1) != h) &&
+                          (i + 1 < n && tie_hi(keys, shift, i + 1) == h);
+        if (head && !lng) {
+            uint32_t pv[TIE_SHORT], gv[TIE_SHORT];
+            int len = 0;
+            while (len < TIE_SHORT && i + len < n && tie_hi(keys, shift, i + len) == h) {
+                pv[len] = pair_of(keys, order, pmask, i + len);
+                gv[len] = gidx[pv[len]];
+                len++;
+            }
+            // insertion sort by the caller's index (distinct within a view)
+            for (int a = 1; a < len; a++) {
+                const uint32_t pk = pv[a], gk = gv[a];
+                int b = a - 1;
+                while (b >= 0 && gv[b] > gk) {
+                    pv[b + 1] = pv[b];
+                    gv[b + 1] = gv[b];
+                    b--;
+                }
+                pv[b + 1] = pk;
+                gv[b + 1] = gk;
+            }
+            for (int a = 0; a < len; a++) {
+                if (order) order[i + a] = pv[a];
+                else keys[i + a] = (keys[i + a] & ~pmask) | pv[a];
+            }
+        }
+    }
+    const uint64_t bl = __ballot(lng);
+    __shared__ uint32_t wl[4];
+    if ((threadIdx.x & 63) == 0) wl[threadIdx.x >> 6] = (uint32_t)__popcll(bl);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t t = wl[0] + wl[1] + wl[2] + wl[3];
+        if (t) atomicAdd(nlong, (unsigned long long)t);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tie_flags(uint64_t n, const uint64_t* __restrict__ keys,
+                                                   int shift, uint32_t* __restrict__ flag)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) flag[i] = in_long_run(keys, shift, n, i) ? 1u : 0u;
+}
+
+// fpos: exclusive scan of the long-run flags; per long-run position j (in
+// position order): its position, pair index and caller's Gaussian index
+__global__ __launch_bounds__(256) void k_tie_gather(uint64_t n, const uint64_t* __restrict__ keys,
+                                                    int shift, const uint32_t* __restrict__ order,
+                                                    uint64_t pmask,
+                                                    const uint32_t* __restrict__ fpos,
+                                                    const uint32_t* __restrict__ gidx,
+                                                    uint32_t* __restrict__ tpos,
+                                                    uint32_t* __restrict__ tv,
+                                                    uint32_t* __restrict__ tg)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n || !in_long_run(keys, shift, n, i)) return;
+    const uint32_t j = fpos[i];
+    const uint32_t p = pair_of(keys, order, pmask, i);
+    tpos[j] = (uint32_t)i;
+    tv[j] = p;
+    tg[j] = gidx[p];
+}
+
+__device__ __forceinline__ uint32_t tie_head(const uint64_t* __restrict__ keys, int shift,
+                                             const uint32_t* __restrict__ tpos, uint32_t j)
+{
+    return (j == 0 || tie_hi(keys, shift, tpos[j - 1]) != tie_hi(keys, shift, tpos[j])) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_tie_heads(uint32_t m, const uint64_t* __restrict__ keys,
+                                                   int shift, const uint32_t* __restrict__ tpos,
+                                                   uint32_t* __restrict__ head)
+{
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j < m) head[j] = tie_head(keys, shift, tpos, j);
+}
+
+// hs: exclusive scan of the run heads; sort key (run ordinal, Gaussian index)
+__global__ __launch_bounds__(256) void k_tie_keys(uint32_t m, const uint64_t* __restrict__ keys,
+                                                  int shift, const uint32_t* __restrict__ tpos,
+                                                  const uint32_t* __restrict__ hs,
+                                                  const uint32_t* __restrict__ tg, int gbits,
+                                                  uint64_t* __restrict__ tk)
+{
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t run = hs[j] + tie_head(keys, shift, tpos, j) - 1u;
+    tk[j] = ((uint64_t)run << gbits) | tg[j];
+}
+
+// the j-th pair of the sorted runs goes to the j-th long-run position: runs
+// keep their positions, their pairs come in Gaussian-index order
+__global__ __launch_bounds__(256) void k_tie_scatter(uint32_t m, const uint32_t* __restrict__ tpos,
+                                                     const uint32_t* __restrict__ tv,
+                                                     uint64_t* __restrict__ keys,
+                                                     uint32_t* __restrict__ order, uint64_t pmask)
+{
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t i = tpos[j];
+    if (order) order[i] = tv[j];
+    else keys[i] = (keys[i] & ~pmask) | tv[j];
+}
+
 inline unsigned grid_for(uint64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
+
+void launch_tie_short(uint64_t n, uint64_t* keys, int shift, uint32_t* order, uint64_t pmask,
+                      const uint32_t* gidx, unsigned long long* nlong, hipStream_t st)
+{
+    if (!n) return;
+    hipLaunchKernelGGL(k_tie_short, dim3(grid_for(n)), dim3(256), 0, st, n, keys, shift, order,
+                       pmask, gidx, nlong);
+}
+
+void launch_tie_flags(uint64_t n, const uint64_t* keys, int shift, uint32_t* flag, hipStream_t st)
+{
+    if (!n) return;
+    hipLaunchKernelGGL(k_tie_flags, dim3(grid_for(n)), dim3(256), 0, st, n, keys, shift, flag);
+}
+
+void launch_tie_fix(uint64_t n, uint32_t m, uint64_t* keys, int shift, uint32_t* order,
+                    uint64_t pmask, const uint32_t* fpos, const uint32_t* gidx, int gbits,
+                    uint32_t* tpos, uint32_t* tv, uint32_t* tv_alt, uint32_t* tg, uint32_t* head,
+                    uint64_t* tk, uint64_t* tk_alt, uint32_t* hist, void* scan_ws, hipStream_t st)
+{
+    if (!n || !m) return;
+    hipLaunchKernelGGL(k_tie_gather, dim3(grid_for(n)), dim3(256), 0, st, n, keys, shift, order,
+                       pmask, fpos, gidx, tpos, tv, tg);
+    hipLaunchKernelGGL(k_tie_heads, dim3(grid_for(m)), dim3(256), 0, st, m, keys, shift, tpos, head);
+    scan_u32(head, m, nullptr, scan_ws, st);
+    hipLaunchKernelGGL(k_tie_keys, dim3(grid_for(m)), dim3(256), 0, st, m, keys, shift, tpos, head,
+                       tg, gbits, tk);
+    // runs <= m / 2 + 1: their ordinals fit in bit_length(m) bits
+    int rbits = 0;
+    while (rbits < 32 && ((uint64_t)1 << rbits) <= (uint64_t)m) rbits++;
+    const bool alt = radix_sort_u64(tk, tv, tk_alt, tv_alt, m, rbits + gbits, hist, scan_ws,
+                                    nullptr, st);
+    hipLaunchKernelGGL(k_tie_scatter, dim3(grid_for(m)), dim3(256), 0, st, m, tpos,
+                       alt ? tv_alt : tv, keys, order, pmask);
+}
 
 size_t scan_workspace_bytes(uint64_t n)
 {

@@ -127,9 +127,11 @@ slag_status read_small(slag_ctx* c, int off, int words)
 
 }  // namespace slag_host
 
-// Morton order of the Gaussian means: the contraction takes Gaussians in
-// blocks of 16 consecutive along this curve.  Ties (equal 63-bit codes) keep
-// input order.
+// Morton order of the Gaussian means: the Gaussians are stored in this
+// order (pairs of nearby Gaussians get nearby pair indices, and the
+// contraction takes Gaussians in blocks of 16 consecutive along the curve).
+// Ties (equal 63-bit codes) keep input order.  perm[q] = input index of the
+// q-th Gaussian, rank = its inverse.
 static float from_ord(uint32_t o)
 {
     uint32_t u = (o & 0x80000000u) ? (o ^ 0x80000000u) : ~o;
@@ -175,7 +177,19 @@ static slag_status morton_order(slag_ctx* c, int64_t n)
     const uint32_t* sorted = alt ? c->dval_alt.as<uint32_t>() : c->dval.as<uint32_t>();
     HC(c, hipMemcpyAsync(c->perm.p, sorted, (size_t)n * 4, hipMemcpyDeviceToDevice, c->st));
     launch_invert(n, c->perm.as<uint32_t>(), c->rank.as<uint32_t>(), c->st);
+    DevBuf m2, c2, o2;
+    CK(ensure(c, m2, nn * 12));
+    CK(ensure(c, c2, nn * 24));
+    CK(ensure(c, o2, nn * 4));
+    launch_gather_gauss(n, c->perm.as<uint32_t>(), c->means.as<float>(), c->cov3.as<float>(),
+                        c->opac.as<float>(), m2.as<float>(), c2.as<float>(), o2.as<float>(), c->st);
     HC(c, hipStreamSynchronize(c->st));
+    std::swap(c->means, m2);
+    std::swap(c->cov3, c2);
+    std::swap(c->opac, o2);
+    release(m2);
+    release(c2);
+    release(o2);
     return SLAG_OK;
 }
 
@@ -372,11 +386,11 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
     CK(ensure(c, c->pair_of_m, npq * 4));
     launch_emit_pairs(nb, n, views, c->means.as<float>(), c->cov3.as<float>(), c->opac.as<float>(),
                       c->tcnt.as<uint32_t>(), c->blk_vis.as<uint32_t>(), c->rec.as<float4>(),
-                      debug ? c->pgauss.as<uint32_t>() : nullptr, c->pview.as<uint16_t>(),
+                      c->pgauss.as<uint32_t>(), c->pview.as<uint16_t>(),
                       c->dkey.as<uint64_t>(), c->dval.as<uint32_t>(), c->psz.as<uint32_t>(),
                       debug ? c->pz.as<uint32_t>() : nullptr,
                       c->sat.as<uint32_t>(), zmin, zbits, pbits, c->blk_aux.as<uint32_t>(),
-                      c->rank.as<uint32_t>(), c->pair_of_m.as<uint32_t>(), c->prect.as<uint2>(), B.lbits,
+                      c->perm.as<uint32_t>(), c->pair_of_m.as<uint32_t>(), c->prect.as<uint2>(), B.lbits,
                       st);
     launch_reduce_pairs(c->blk_aux.as<uint32_t>(), nblk, true,
                         reinterpret_cast<unsigned long long*>(small + SM_TOTALS), st);
@@ -420,6 +434,42 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
                                             npairs, zbits + vbits, c->hist.as<uint32_t>(),
                                             c->scan_ws.p, nullptr, st);
             order = alt ? c->dval_alt.as<uint32_t>() : c->dval.as<uint32_t>();
+        }
+        // equal depths: the caller's Gaussian index decides (pairs follow the
+        // storage order, the Morton order, until here)
+        {
+            uint64_t* tkeys = const_cast<uint64_t*>(okey);
+            if (!tkeys) tkeys = order == c->dval_alt.as<uint32_t>() ? c->dkey_alt.as<uint64_t>()
+                                                                  : c->dkey.as<uint64_t>();
+            launch_fill_u32(reinterpret_cast<uint32_t*>(small + SM_TIES), 2, 0u, st);
+            launch_tie_short(npairs, tkeys, pbits, const_cast<uint32_t*>(order), pmask,
+                             c->pgauss.as<uint32_t>(),
+                             reinterpret_cast<unsigned long long*>(small + SM_TIES), st);
+            if (!c->capturing) {
+                CK(read_small(c, SM_TIES, 1));
+                B.ntie = c->host_small[SM_TIES];
+            }
+            const uint64_t m = B.ntie;   // positions in runs of more than 8 pairs
+            if (m) {
+                CK(ensure(c, c->tflag, np * 4));
+                launch_tie_flags(npairs, tkeys, pbits, c->tflag.as<uint32_t>(), st);
+                scan_u32(c->tflag.as<uint32_t>(), npairs, nullptr, c->scan_ws.p, st);
+                CK(ensure(c, c->tpos, m * 4));
+                CK(ensure(c, c->tv, m * 4));
+                CK(ensure(c, c->tv_alt, m * 4));
+                CK(ensure(c, c->tg, m * 4));
+                CK(ensure(c, c->thead, m * 4));
+                CK(ensure(c, c->tk, m * 8));
+                CK(ensure(c, c->tk_alt, m * 8));
+                launch_tie_fix(npairs, (uint32_t)m, tkeys, pbits, const_cast<uint32_t*>(order),
+                               pmask, c->tflag.as<uint32_t>(), c->pgauss.as<uint32_t>(),
+                               std::max(1, bit_length((uint64_t)std::max<int64_t>(n - 1, 0))),
+                               c->tpos.as<uint32_t>(), c->tv.as<uint32_t>(),
+                               c->tv_alt.as<uint32_t>(), c->tg.as<uint32_t>(),
+                               c->thead.as<uint32_t>(), c->tk.as<uint64_t>(),
+                               c->tk_alt.as<uint64_t>(), c->hist.as<uint32_t>(), c->scan_ws.p,
+                               st);
+            }
         }
         CK(stage_end(c, ST_DEPTH_SORT, ev));
 
@@ -598,7 +648,8 @@ void slag_destroy(slag_ctx* c)
                       &c->ikey, &c->ikey_alt, &c->ival, &c->ival_alt, &c->bstart, &c->bend,
                       &c->part, &c->wrow, &c->perm, &c->rank, &c->pair_of_m,
                       &c->pinfo, &c->prect, &c->blk_aux, &c->bkey,
-                      &c->bkey_alt, &c->bord, &c->bord_alt};
+                      &c->bkey_alt, &c->bord, &c->bord_alt, &c->tflag, &c->tpos, &c->tv,
+                      &c->tv_alt, &c->tg, &c->thead, &c->tk, &c->tk_alt};
     destroy_graph(c);
     for (DevBuf* b : bufs) release(*b);
     codec_release(c);

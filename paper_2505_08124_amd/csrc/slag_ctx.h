@@ -31,7 +31,7 @@ struct Batch {
     uint32_t nbuckets = 0, nsat = 0;
     DevBuf views, bucket_view;
     // sizes read back by the last eager lift (reused while capturing a graph)
-    uint64_t npairs = 0, ni = 0, nparts = 0;
+    uint64_t npairs = 0, ni = 0, nparts = 0, ntie = 0;
     uint32_t zmin = 0, zmax = 0;
     // resolution classes (distinct image sizes, first appearance order): the
     // compositing runs one launch per class, with the class's tuned variant
@@ -112,6 +112,7 @@ struct slag_ctx {
         pair_of_m;
     slag_host::DevBuf ikey, ikey_alt, ival, ival_alt, bstart, bend, part, wrow, pinfo;
     slag_host::DevBuf prect, blk_aux, bkey, bkey_alt, bord, bord_alt;
+    slag_host::DevBuf tflag, tpos, tv, tv_alt, tg, thead, tk, tk_alt;   // depth ties
     uint64_t* host_small = nullptr;   // pinned read-back area
 
     slag_host::CodecState codec;
@@ -144,7 +145,7 @@ namespace slag_host {
 
 // small device area layout (uint64 words)
 enum { SM_TOT = 0, SM_ZRANGE = 2, SM_TOTALS = 4, SM_COUNTERS = 8, SM_NNZ = 12, SM_ERR = 14,
-       SM_WORDS = 16 };
+       SM_TIES = 16, SM_WORDS = 18 };
 
 #define FAIL(ctx, code, msg)                 \
     do {                                     \

@@ -43,7 +43,7 @@ void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* mea
                        const uint32_t* blk_off, float4* rec, uint32_t* pgauss, uint16_t* pview,
                        uint64_t* dkey, uint32_t* dval, uint32_t* psz, uint32_t* pz,
                        const uint32_t* sat, uint32_t zmin, int zbits, int pbits, uint32_t* blk_tot,
-                       const uint32_t* rank, uint32_t* pair_of_m, uint2* prect, int lbits,
+                       const uint32_t* perm, uint32_t* pair_of_m, uint2* prect, int lbits,
                        hipStream_t st);
 // out[0..1] = (min of even, max of odd) entries of in[2 * npairs], or their
 // 64-bit sums in sum mode; one block
@@ -55,6 +55,11 @@ void launch_bbox(int64_t n, const float* means, uint32_t* box6, hipStream_t st);
 void launch_morton(int64_t n, const float* means, const float* lo_scale, uint64_t* keys,
                    uint32_t* vals, hipStream_t st);
 void launch_invert(int64_t n, const uint32_t* perm, uint32_t* rank, hipStream_t st);
+// Gaussians into Morton order: q-th output = input perm[q] (means [n][3],
+// covariances [6][n], opacities [n]).
+void launch_gather_gauss(int64_t n, const uint32_t* perm, const float* means, const float* cov3,
+                         const float* opac, float* means_o, float* cov3_o, float* opac_o,
+                         hipStream_t st);
 
 // scans: exclusive prefix sum in place; the 64-bit total goes to *total_dev
 size_t scan_workspace_bytes(uint64_t n);
@@ -73,6 +78,22 @@ bool radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t
 // keys only, by bits [bit0, bit0 + nbits) (stable)
 bool radix_sort_u64_keys(uint64_t* keys, uint64_t* keys_alt, uint64_t n, int bit0, int nbits,
                          uint32_t* hist, void* scan_ws, hipStream_t st);
+
+// Depth ties: runs of equal sorted keys (without their low `shift` bits) get
+// their pairs in the caller's Gaussian order gidx[pair]; pairs are order[i],
+// or the low bits of keys[i] (pmask) when order is null.  launch_tie_short
+// reorders the runs of at most 8 pairs and adds the number of positions in
+// longer runs to *nlong; for those, launch_tie_flags marks them (flag[i] = 1)
+// and launch_tie_fix, given fpos = exclusive scan of the flags and their
+// count m, sorts them (gbits: bits of the Gaussian index).  Work arrays: m
+// entries each (tk, tk_alt: 64-bit); hist and scan_ws sized for n.
+void launch_tie_short(uint64_t n, uint64_t* keys, int shift, uint32_t* order, uint64_t pmask,
+                      const uint32_t* gidx, unsigned long long* nlong, hipStream_t st);
+void launch_tie_flags(uint64_t n, const uint64_t* keys, int shift, uint32_t* flag, hipStream_t st);
+void launch_tie_fix(uint64_t n, uint32_t m, uint64_t* keys, int shift, uint32_t* order,
+                    uint64_t pmask, const uint32_t* fpos, const uint32_t* gidx, int gbits,
+                    uint32_t* tpos, uint32_t* tv, uint32_t* tv_alt, uint32_t* tg, uint32_t* head,
+                    uint64_t* tk, uint64_t* tk_alt, uint32_t* hist, void* scan_ws, hipStream_t st);
 
 // depth order: order[r], or (okey non-null) okey[r] & pmask; prect[p] = (entry
 // key of the pair's top-left tile, rectangle width | height << 16)

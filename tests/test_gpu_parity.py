@@ -303,6 +303,52 @@ def test_empty_and_degenerate():
         L2.set_scene(dataclasses.replace(sc, ids=[i + 100 for i in sc.ids]))
 
 
+def _tie_scene():
+    """Cameras looking along +z (camera depth = world z, exactly): half the
+    Gaussians on one plane (one long run of equal depth per view), a block on
+    three repeated depths, 100 pairs of equal depth (short runs), the rest
+    distinct; stored in a shuffled order."""
+    from conftest import make_custom_scene
+    rng = np.random.default_rng(77)
+    n = 3000
+    z = rng.uniform(3.0, 9.0, n).astype(np.float32)
+    z[: n // 2] = 4.0                                    # a plane facing the cameras
+    z[n // 2: n // 2 + 300] = rng.choice(np.float32([5.0, 5.5, 6.25]), 300)
+    short = rng.choice(np.arange(n // 2 + 300, n), 200, replace=False)
+    z[short[:100]] = z[short[100:]]                      # pairs of equal depth
+    xy = rng.uniform(-1.0, 1.0, (n, 2)).astype(np.float32) * z[:, None] * np.float32([0.6, 0.45])
+    means = np.concatenate([xy, z[:, None]], 1)
+    perm = rng.permutation(n)                            # the caller's order
+    means = means[perm]
+    scales = rng.uniform(0.01, 0.06, (n, 3)).astype(np.float32)
+    quats = rng.normal(size=(n, 4)).astype(np.float32)
+    opacity = rng.uniform(0.2, 0.95, n).astype(np.float32)
+    W, H = 160, 120
+    cams = [dict(fx=120.0, fy=120.0, cx=80.0, cy=60.0, t=[0.0, 0.0, 0.0], width=W, height=H),
+            dict(fx=120.0, fy=120.0, cx=80.0, cy=60.0, t=[0.25, 0.0, 0.5], width=W, height=H)]
+    yy, xx = np.mgrid[0:H, 0:W]
+    ids = [((xx // 40) + 4 * (yy // 60)).astype(np.int32), ((xx // 32) % 5).astype(np.int32)]
+    feats = rng.normal(size=(8 + 5, 64)).astype(np.float32)
+    sc = make_custom_scene(means, scales, quats, opacity, cams, ids, feats, name="depth_ties")
+    return sc
+
+
+def test_depth_ties_follow_gaussian_index():
+    """Exact depth ties, in runs of every length, are broken by the caller's
+    Gaussian index (the library stores Gaussians in Morton order, so its own
+    order differs).  Tile lists must equal the oracle's bit for bit."""
+    sc = _tie_scene()
+    L = _lifter(sc)
+    L.lift()
+    for v in range(2):
+        _say("depth ties: tile lists view", v)
+        check_tile_lists(L, sc, v)
+    E, den = L.embeddings()
+    ref = oracle.lift(sc)
+    cmin, _ = check_embeddings(E, den, ref)
+    _say(f"depth ties: min cosine {cmin:.9f}")
+
+
 # --------------------------------------------------------------- full sizes
 
 def test_full_size_plain_bf16_200k():
