@@ -495,43 +495,75 @@ __device__ __forceinline__ uint32_t pair_of(const uint64_t* __restrict__ keys,
     return order ? order[i] : (uint32_t)(keys[i] & pmask);
 }
 
+__device__ __forceinline__ void cmp_swap(uint32_t& ga, uint32_t& pa, uint32_t& gb, uint32_t& pb)
+{
+    const bool sw = ga > gb;
+    const uint32_t g0 = sw ? gb : ga, g1 = sw ? ga : gb;
+    const uint32_t p0 = sw ? pb : pa, p1 = sw ? pa : pb;
+    ga = g0; gb = g1; pa = p0; pb = p1;
+}
+
 // Short runs sorted by their head thread; positions in long runs counted
-// into *nlong.
+// into *nlong.  A tied position loads the 2 TIE_SHORT + 1 keys around it at
+// once (the window decides both the long-run test and the run's extent); a
+// head then loads its pairs' Gaussian indices at once and sorts them with a
+// fixed 19-comparator network (padding sorts last).
 __global__ __launch_bounds__(256) void k_tie_short(uint64_t n, uint64_t* __restrict__ keys, int shift,
                                                    uint32_t* __restrict__ order, uint64_t pmask,
                                                    const uint32_t* __restrict__ gidx,
                                                    unsigned long long* __restrict__ nlong)
 {
+    static_assert(TIE_SHORT == 8, "the sorting network is for 8 entries");
+    constexpr int WN = 2 * TIE_SHORT + 1;
     const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     bool lng = false;
     if (i < n) {
-        lng = in_long_run(keys, shift, n, i);
         const uint64_t h = tie_hi(keys, shift, i);
-        const bool head = (i == 0 || tie_hi(keys, shift, i - 1) != h) &&
-                          (i + 1 < n && tie_hi(keys, shift, i + 1) == h);
-        if (head && !lng) {
-            uint32_t pv[TIE_SHORT], gv[TIE_SHORT];
-            int len = 0;
-            while (len < TIE_SHORT && i + len < n && tie_hi(keys, shift, i + len) == h) {
-                pv[len] = pair_of(keys, order, pmask, i + len);
-                gv[len] = gidx[pv[len]];
-                len++;
+        const bool tp = i > 0 && tie_hi(keys, shift, i - 1) == h;
+        const bool tn = i + 1 < n && tie_hi(keys, shift, i + 1) == h;
+        if (tp || tn) {
+            // window w[a] = key at i - TIE_SHORT + a (clamped addresses)
+            uint64_t w[WN];
+            bool eq[WN];
+#pragma unroll
+            for (int a = 0; a < WN; a++) {
+                const int64_t x = (int64_t)i - TIE_SHORT + a;
+                const uint64_t xc = x < 0 ? 0 : ((uint64_t)x >= n ? n - 1 : (uint64_t)x);
+                w[a] = keys[xc];
+                eq[a] = x >= 0 && (uint64_t)x < n && (w[a] >> shift) == h;
             }
-            // insertion sort by the caller's index (distinct within a view)
-            for (int a = 1; a < len; a++) {
-                const uint32_t pk = pv[a], gk = gv[a];
-                int b = a - 1;
-                while (b >= 0 && gv[b] > gk) {
-                    pv[b + 1] = pv[b];
-                    gv[b + 1] = gv[b];
-                    b--;
+#pragma unroll
+            for (int a = 0; a <= TIE_SHORT; a++) lng = lng || (eq[TIE_SHORT - a] && eq[WN - 1 - a]);
+            if (!tp && !lng) {
+                // head of a short run: positions i .. i + len - 1, len <= 8
+                uint32_t pv[TIE_SHORT], gv[TIE_SHORT];
+#pragma unroll
+                for (int a = 0; a < TIE_SHORT; a++) {
+                    const bool in = eq[TIE_SHORT + a];
+                    const uint64_t xc = in ? i + a : i;
+                    pv[a] = order ? order[xc] : (uint32_t)(w[TIE_SHORT + a] & pmask);
                 }
-                pv[b + 1] = pk;
-                gv[b + 1] = gk;
-            }
-            for (int a = 0; a < len; a++) {
-                if (order) order[i + a] = pv[a];
-                else keys[i + a] = (keys[i + a] & ~pmask) | pv[a];
+#pragma unroll
+                for (int a = 0; a < TIE_SHORT; a++) {
+                    const uint32_t g = gidx[pv[a]];
+                    gv[a] = eq[TIE_SHORT + a] ? g : 0xFFFFFFFFu;
+                }
+                cmp_swap(gv[0], pv[0], gv[1], pv[1]); cmp_swap(gv[2], pv[2], gv[3], pv[3]);
+                cmp_swap(gv[4], pv[4], gv[5], pv[5]); cmp_swap(gv[6], pv[6], gv[7], pv[7]);
+                cmp_swap(gv[0], pv[0], gv[2], pv[2]); cmp_swap(gv[1], pv[1], gv[3], pv[3]);
+                cmp_swap(gv[4], pv[4], gv[6], pv[6]); cmp_swap(gv[5], pv[5], gv[7], pv[7]);
+                cmp_swap(gv[1], pv[1], gv[2], pv[2]); cmp_swap(gv[5], pv[5], gv[6], pv[6]);
+                cmp_swap(gv[0], pv[0], gv[4], pv[4]); cmp_swap(gv[1], pv[1], gv[5], pv[5]);
+                cmp_swap(gv[2], pv[2], gv[6], pv[6]); cmp_swap(gv[3], pv[3], gv[7], pv[7]);
+                cmp_swap(gv[2], pv[2], gv[4], pv[4]); cmp_swap(gv[3], pv[3], gv[5], pv[5]);
+                cmp_swap(gv[1], pv[1], gv[2], pv[2]); cmp_swap(gv[3], pv[3], gv[4], pv[4]);
+                cmp_swap(gv[5], pv[5], gv[6], pv[6]);
+#pragma unroll
+                for (int a = 0; a < TIE_SHORT; a++) {
+                    if (!eq[TIE_SHORT + a]) continue;
+                    if (order) order[i + a] = pv[a];
+                    else keys[i + a] = (w[TIE_SHORT + a] & ~pmask) | pv[a];
+                }
             }
         }
     }
