@@ -285,9 +285,11 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         load_cov(cov3, n, g, C);
         Proj P;
         project(V, means[3 * g], means[3 * g + 1], means[3 * g + 2], C, P);
-        rec[2 * (size_t)pidx] = make_float4(P.u, P.v, P.ca, P.cb);
+        // compositing form: prescaled conic, log2 of the opacity
+        rec[2 * (size_t)pidx] = make_float4(P.u, P.v, P.ca * NHALF_LOG2E, P.cb * NLOG2E);
         rec[2 * (size_t)pidx + 1] =
-            make_float4(P.cc, opac[g], __uint_as_float((uint32_t)P.x0 | ((uint32_t)P.y0 << 16)),
+            make_float4(P.cc * NHALF_LOG2E, __builtin_amdgcn_logf(opac[g]),
+                        __uint_as_float((uint32_t)P.x0 | ((uint32_t)P.y0 << 16)),
                         __uint_as_float((uint32_t)P.x1 | ((uint32_t)P.y1 << 16)));
         pgauss[pidx] = perm[g];                      // the caller's index of the Gaussian
         pview[pidx] = (uint16_t)vl;

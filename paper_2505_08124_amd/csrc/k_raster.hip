@@ -22,8 +22,6 @@ namespace {
 constexpr float AMIN = 1.0f / 255.0f;
 constexpr float AMAX = 0.99f;
 constexpr float TMIN = 1e-4f;
-constexpr float NHALF_LOG2E = -0.72134752044448170368f;   // -log2(e) / 2
-constexpr float NLOG2E = -1.44269504088896340736f;        // -log2(e)
 constexpr float LOG2_AMIN = -7.99435343685885793770f;     // log2(1 / 255)
 
 __device__ __forceinline__ void box_of(const float4& r1, int& x0, int& x1, int& y0, int& y1)
@@ -377,9 +375,9 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
                        (int)(ba >> 16) <= by0 + ay1;
             // exponent log2(o) + A dx^2 + B dx dy + C dy^2 with dx = lx - du,
             // dy = ly - dv (pixel centre relative to the entry's mean)
-            const float A = q0.z * NHALF_LOG2E, B = q0.w * NLOG2E, C = q1.x * NHALF_LOG2E;
+            const float A = q0.z, B = q0.w, C = q1.x;   // prescaled in the record
             const float du = q0.x - ((float)bx0 + 0.5f), dv = q0.y - ((float)by0 + 0.5f);
-            const float lo2 = __builtin_amdgcn_logf(q1.y);
+            const float lo2 = q1.y;                        // log2(o)
             if (!COUNT && hit)
                 hit = reaches_amin(A, B, C, lo2, (float)ax0 - du, (float)ax1 - du, (float)ay0 - dv,
                                    (float)ay1 - dv);

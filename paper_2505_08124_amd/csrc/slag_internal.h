@@ -26,9 +26,14 @@ struct ViewDev {
     uint32_t nseg;           // segments of this view
 };
 
-// Pair record (one visible (view, Gaussian) pair), two float4:
-//   r0 = (u, v, conic_xx, conic_xy)   screen mean and inverse covariance
-//   r1 = (conic_yy, opacity, x0 | y0 << 16, x1 | y1 << 16)  pixel box (inclusive)
+// Pair record (one visible (view, Gaussian) pair), two float4, with the
+// inverse covariance prescaled so that alpha = o exp(-q/2) = 2^(log2(o) +
+// A dx^2 + B dx dy + C dy^2):
+//   r0 = (u, v, A, B)   screen mean, A = -log2(e)/2 conic_xx, B = -log2(e) conic_xy
+//   r1 = (C, log2(o), x0 | y0 << 16, x1 | y1 << 16)   C = -log2(e)/2 conic_yy;
+//        pixel box (inclusive)
+constexpr float NHALF_LOG2E = -0.72134752044448170368f;   // -log2(e) / 2
+constexpr float NLOG2E = -1.44269504088896340736f;        // -log2(e)
 
 // ---- launchers (each enqueues on `st`) ----
 void launch_prep_gauss(int64_t n, const float* means, const float* scales, const float* quats,
