@@ -56,48 +56,72 @@ __device__ __forceinline__ uint32_t sat_rect(const uint32_t* S, int sw, int xa, 
     return S[(yb + 1) * sw + xb + 1] - S[ya * sw + xb + 1] - S[(yb + 1) * sw + xa] + S[ya * sw + xa];
 }
 
-// Distinct segment ids of each tile, ascending (sort + unique in LDS).
+// Distinct segment ids of each tile, ascending.  Each wave extracts the
+// distinct ids among its 64 pixels with a ballot loop (one iteration per
+// distinct id); the up to 4 x 64 candidates are then merged: a candidate is
+// kept if no earlier candidate has its id, and goes to the position given by
+// the number of kept candidates with a smaller id.  Tiles hold few segments,
+// so both loops are short; 256 distinct ids cost 2 x 256 LDS reads per thread.
 __global__ __launch_bounds__(256) void k_tile_segs(const uint32_t* __restrict__ bucket_view,
                                                    const ViewDev* __restrict__ views,
                                                    const int32_t* __restrict__ ids,
                                                    uint32_t* __restrict__ ns_tile,
                                                    uint16_t* __restrict__ segl)
 {
-    __shared__ uint32_t s[TILE_PIX];
-    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t cand[4][64];
+    __shared__ uint32_t keep[TILE_PIX];
+    __shared__ uint32_t wn[4];
     const uint32_t b = blockIdx.x;
     const ViewDev& V = views[bucket_view[b]];
     const uint32_t tile = b - V.tile_base;
     const int tx = (int)(tile % (uint32_t)V.ntx), ty = (int)(tile / (uint32_t)V.ntx);
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int px = tx * TILE + (t & (TILE - 1)), py = ty * TILE + t / TILE;
     int32_t id = -1;
     if (px < V.W && py < V.H) id = ids[V.pix_off + (uint64_t)py * V.W + px];
-    s[t] = id >= 0 ? (uint32_t)id : 0xFFFFFFFFu;
+    // 1. distinct ids of this wave's pixels
+    bool left = id >= 0;
+    uint32_t nc = 0;
+    for (;;) {
+        const uint64_t act = __ballot(left);
+        if (!act) break;
+        const int v = __builtin_amdgcn_readlane(id, __ffsll((long long)act) - 1);
+        if (lane == 0) cand[w][nc] = (uint32_t)v;
+        nc++;
+        left = left && id != v;
+    }
+    if (lane == 0) wn[w] = nc;
     __syncthreads();
-    for (int k = 2; k <= TILE_PIX; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const int o = t ^ j;
-            if (o > t) {
-                const uint32_t a = s[t], c = s[o];
-                const bool up = (t & k) == 0;
-                if ((a > c) == up) { s[t] = c; s[o] = a; }
-            }
-            __syncthreads();
+    // 2. merge: candidate i of the flat list (waves in order)
+    const uint32_t n0 = wn[0], n1 = wn[1], n2 = wn[2], n3 = wn[3];
+    const uint32_t C = n0 + n1 + n2 + n3;
+    uint32_t c = 0xFFFFFFFFu;
+    bool kept = false;
+    if ((uint32_t)t < C) {
+        const uint32_t i = (uint32_t)t;
+        const int cw = i < n0 ? 0 : i < n0 + n1 ? 1 : i < n0 + n1 + n2 ? 2 : 3;
+        const uint32_t ci = i - (cw > 0 ? n0 : 0) - (cw > 1 ? n1 : 0) - (cw > 2 ? n2 : 0);
+        c = cand[cw][ci];
+        // earlier waves' candidates with the same id (a wave's own are distinct)
+        kept = true;
+        for (int u = 0; u < cw && kept; u++) {
+            const uint32_t nu = u == 0 ? n0 : u == 1 ? n1 : n2;
+            for (uint32_t j = 0; j < nu; j++)
+                if (cand[u][j] == c) { kept = false; break; }
         }
     }
-    const uint32_t k = s[t];
-    const uint32_t flag = (k != 0xFFFFFFFFu) && (t == 0 || s[t - 1] != k);
-    // block exclusive scan of flags
-    const int lane = t & 63, w = t >> 6;
-    const uint64_t m = __ballot(flag);
-    const uint32_t below = (uint32_t)__popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-    if (lane == 0) wsum[w] = (uint32_t)__popcll(m);
+    keep[t] = kept ? c : 0xFFFFFFFFu;
     __syncthreads();
-    uint32_t off = 0;
-    for (int i = 0; i < w; i++) off += wsum[i];
-    if (flag) segl[(uint64_t)b * TILE_PIX + off + below] = (uint16_t)k;
-    if (t == 0) ns_tile[b] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (kept) {
+        uint32_t pos = 0;
+        for (uint32_t j = 0; j < C; j++) pos += keep[j] < c;
+        segl[(uint64_t)b * TILE_PIX + pos] = (uint16_t)c;
+    }
+    const uint64_t km = __ballot(kept);
+    __syncthreads();
+    if (lane == 0) wn[w] = (uint32_t)__popcll(km);
+    __syncthreads();
+    if (t == 0) ns_tile[b] = wn[0] + wn[1] + wn[2] + wn[3];
 }
 
 // Per-view summed-area table of the tile segment counts: (nty+1) x (ntx+1).

@@ -417,20 +417,36 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint64_t n, uint3
 }
 
 // Keys are (view in launch << lbits) | tile in view; bucket = the view's tile
-// base + tile.
+// base + tile.  Four consecutive keys per thread (one 16-byte load) and
+// their two outer neighbours; a run's first and last positions set its range.
 __global__ __launch_bounds__(256) void k_bucket_ranges(uint64_t ni, const uint32_t* __restrict__ ikey,
                                                        const ViewDev* __restrict__ views, int lbits,
                                                        uint32_t* __restrict__ bstart,
                                                        uint32_t* __restrict__ bend)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= ni) return;
-    const uint32_t k = ikey[i];
-    const bool first = i == 0 || ikey[i - 1] != k, lastk = i + 1 == ni || ikey[i + 1] != k;
-    if (!first && !lastk) return;
-    const uint32_t b = views[k >> lbits].tile_base + (k & ((1u << lbits) - 1u));
-    if (first) bstart[b] = (uint32_t)i;
-    if (lastk) bend[b] = (uint32_t)(i + 1);
+    const uint64_t i0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (i0 >= ni) return;
+    uint32_t k[4];
+    if (i0 + 4 <= ni) {
+        const uint4 q = reinterpret_cast<const uint4*>(ikey)[i0 >> 2];
+        k[0] = q.x; k[1] = q.y; k[2] = q.z; k[3] = q.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; j++) k[j] = i0 + j < ni ? ikey[i0 + j] : 0u;
+    }
+    const uint32_t prev = i0 > 0 ? ikey[i0 - 1] : 0u, next = i0 + 4 < ni ? ikey[i0 + 4] : 0u;
+    const uint32_t lmask = (1u << lbits) - 1u;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint64_t i = i0 + j;
+        if (i >= ni) break;
+        const bool first = i == 0 || (j == 0 ? prev : k[j - 1]) != k[j];
+        const bool lastk = i + 1 == ni || (j == 3 ? next : k[j + 1]) != k[j];
+        if (!first && !lastk) continue;
+        const uint32_t b = views[k[j] >> lbits].tile_base + (k[j] & lmask);
+        if (first) bstart[b] = (uint32_t)i;
+        if (lastk) bend[b] = (uint32_t)(i + 1);
+    }
 }
 
 // Dispatch-order keys: longer tile lists first (key = 0xFFFF - min(len, 0xFFFF)
@@ -778,7 +794,7 @@ void launch_bucket_ranges(uint64_t ni, const uint32_t* ikey, const ViewDev* view
                           uint32_t* bstart, uint32_t* bend, hipStream_t st)
 {
     if (!ni) return;
-    hipLaunchKernelGGL(k_bucket_ranges, dim3(grid_for(ni)), dim3(256), 0, st, ni, ikey, views,
+    hipLaunchKernelGGL(k_bucket_ranges, dim3(grid_for((ni + 3) / 4)), dim3(256), 0, st, ni, ikey, views,
                        lbits, bstart, bend);
 }
 
