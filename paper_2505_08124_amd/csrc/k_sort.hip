@@ -520,10 +520,12 @@ __device__ __forceinline__ void cmp_swap(uint32_t& ga, uint32_t& pa, uint32_t& g
 }
 
 // Short runs sorted by their head thread; positions in long runs counted
-// into *nlong.  A tied position loads the 2 TIE_SHORT + 1 keys around it at
-// once (the window decides both the long-run test and the run's extent); a
-// head then loads its pairs' Gaussian indices at once and sorts them with a
-// fixed 19-comparator network (padding sorts last).
+// into *nlong.  The block's 256 keys and TIE_SHORT on each side are staged in
+// LDS once (coalesced); a tied position reads its window of 2 TIE_SHORT + 1
+// keys there (the window decides both the long-run test and the run's
+// extent); a head then loads its pairs' Gaussian indices at once and sorts
+// them with a fixed 19-comparator network (padding sorts last).  Writes
+// change only pair fields, so other blocks' halo copies keep valid depths.
 __global__ __launch_bounds__(256) void k_tie_short(uint64_t n, uint64_t* __restrict__ keys, int shift,
                                                    uint32_t* __restrict__ order, uint64_t pmask,
                                                    const uint32_t* __restrict__ gidx,
@@ -531,22 +533,27 @@ __global__ __launch_bounds__(256) void k_tie_short(uint64_t n, uint64_t* __restr
 {
     static_assert(TIE_SHORT == 8, "the sorting network is for 8 entries");
     constexpr int WN = 2 * TIE_SHORT + 1;
-    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    constexpr int SN = 256 + 2 * TIE_SHORT;
+    __shared__ uint64_t sk[SN];          // keys b0 - TIE_SHORT .. b0 + 256 + TIE_SHORT
+    const uint64_t b0 = (uint64_t)blockIdx.x * 256;
+    for (int a = threadIdx.x; a < SN; a += 256) {
+        const int64_t x = (int64_t)b0 - TIE_SHORT + a;
+        sk[a] = (x >= 0 && (uint64_t)x < n) ? keys[x] : 0ull;
+    }
+    __syncthreads();
+    const uint64_t i = b0 + threadIdx.x;
+    const int li = threadIdx.x + TIE_SHORT;   // i's slot in sk
     bool lng = false;
     if (i < n) {
-        const uint64_t h = tie_hi(keys, shift, i);
-        const bool tp = i > 0 && tie_hi(keys, shift, i - 1) == h;
-        const bool tn = i + 1 < n && tie_hi(keys, shift, i + 1) == h;
+        const uint64_t h = sk[li] >> shift;
+        const bool tp = i > 0 && (sk[li - 1] >> shift) == h;
+        const bool tn = i + 1 < n && (sk[li + 1] >> shift) == h;
         if (tp || tn) {
-            // window w[a] = key at i - TIE_SHORT + a (clamped addresses)
-            uint64_t w[WN];
             bool eq[WN];
 #pragma unroll
             for (int a = 0; a < WN; a++) {
                 const int64_t x = (int64_t)i - TIE_SHORT + a;
-                const uint64_t xc = x < 0 ? 0 : ((uint64_t)x >= n ? n - 1 : (uint64_t)x);
-                w[a] = keys[xc];
-                eq[a] = x >= 0 && (uint64_t)x < n && (w[a] >> shift) == h;
+                eq[a] = x >= 0 && (uint64_t)x < n && (sk[li - TIE_SHORT + a] >> shift) == h;
             }
 #pragma unroll
             for (int a = 0; a <= TIE_SHORT; a++) lng = lng || (eq[TIE_SHORT - a] && eq[WN - 1 - a]);
@@ -556,8 +563,7 @@ __global__ __launch_bounds__(256) void k_tie_short(uint64_t n, uint64_t* __restr
 #pragma unroll
                 for (int a = 0; a < TIE_SHORT; a++) {
                     const bool in = eq[TIE_SHORT + a];
-                    const uint64_t xc = in ? i + a : i;
-                    pv[a] = order ? order[xc] : (uint32_t)(w[TIE_SHORT + a] & pmask);
+                    pv[a] = order ? order[in ? i + a : i] : (uint32_t)(sk[li + a] & pmask);
                 }
 #pragma unroll
                 for (int a = 0; a < TIE_SHORT; a++) {
@@ -578,7 +584,7 @@ __global__ __launch_bounds__(256) void k_tie_short(uint64_t n, uint64_t* __restr
                 for (int a = 0; a < TIE_SHORT; a++) {
                     if (!eq[TIE_SHORT + a]) continue;
                     if (order) order[i + a] = pv[a];
-                    else keys[i + a] = (w[TIE_SHORT + a] & ~pmask) | pv[a];
+                    else keys[i + a] = (sk[li + a] & ~pmask) | pv[a];
                 }
             }
         }
