@@ -346,12 +346,14 @@ __device__ __forceinline__ uint32_t pair_at_rank(const uint32_t* __restrict__ or
 __global__ __launch_bounds__(256) void k_rank_tiles(uint64_t npairs, const uint32_t* __restrict__ order,
                                                     const uint64_t* __restrict__ okey, uint64_t pmask,
                                                     const uint2* __restrict__ prect,
-                                                    uint32_t* __restrict__ tcr)
+                                                    uint32_t* __restrict__ tcr,
+                                                    uint2* __restrict__ prank)
 {
     const uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (r < npairs) {
-        const uint32_t q = prect[pair_at_rank(order, okey, pmask, r)].y;
-        tcr[r] = (q & 0xFFFFu) * (q >> 16);
+        const uint2 q = prect[pair_at_rank(order, okey, pmask, r)];
+        tcr[r] = (q.y & 0xFFFFu) * (q.y >> 16);
+        prank[r] = q;   // the rectangle in depth order, for the emission
     }
 }
 
@@ -363,7 +365,7 @@ __global__ __launch_bounds__(256) void k_rank_tiles(uint64_t npairs, const uint3
 // stores are coalesced.
 __global__ __launch_bounds__(256) void k_emit_isect(uint64_t npairs, const uint32_t* __restrict__ order,
                                                     const uint64_t* __restrict__ okey, uint64_t pmask,
-                                                    const uint2* __restrict__ prect,
+                                                    const uint2* __restrict__ prank,
                                                     const ViewDev* __restrict__ views,
                                                     const uint32_t* __restrict__ ioff,
                                                     int lbits,
@@ -381,7 +383,7 @@ __global__ __launch_bounds__(256) void k_emit_isect(uint64_t npairs, const uint3
     uint32_t o = 0, tc = 0;
     if (lane < nw) {
         const uint32_t p = pair_at_rank(order, okey, pmask, r);
-        const uint2 q = prect[p];
+        const uint2 q = prank[r];
         o = ioff[r];
         tc = (q.y & 0xFFFFu) * (q.y >> 16);
         s_p[w][lane] = p;
@@ -771,21 +773,22 @@ bool radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t
 }
 
 void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const uint64_t* okey,
-                       uint64_t pmask, const uint2* prect, uint32_t* tcr, hipStream_t st)
+                       uint64_t pmask, const uint2* prect, uint32_t* tcr, uint2* prank,
+                       hipStream_t st)
 {
     if (!npairs) return;
     hipLaunchKernelGGL(k_rank_tiles, dim3(grid_for(npairs)), dim3(256), 0, st, npairs, order, okey,
-                       pmask, prect, tcr);
+                       pmask, prect, tcr, prank);
 }
 
 void launch_emit_isect(uint64_t npairs, const uint32_t* order, const uint64_t* okey,
-                       uint64_t pmask, const uint2* prect, const ViewDev* views,
+                       uint64_t pmask, const uint2* prank, const ViewDev* views,
                        const uint32_t* ioff, int lbits, uint32_t* ikey, uint32_t* ival,
                        hipStream_t st)
 {
     if (!npairs) return;
     hipLaunchKernelGGL(k_emit_isect, dim3(grid_for(npairs)), dim3(256), 0, st, npairs, order, okey,
-                       pmask, prect, views, ioff, lbits, ikey, ival);
+                       pmask, prank, views, ioff, lbits, ikey, ival);
 }
 
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st)

@@ -480,10 +480,11 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         CK(ensure(c, c->ikey_alt, ni * 4));
         CK(ensure(c, c->ival, ni * 4));
         CK(ensure(c, c->ival_alt, ni * 4));
+        CK(ensure(c, c->prank, np * 8));
         launch_rank_tiles(npairs, order, okey, pmask, c->prect.as<uint2>(), c->tcr.as<uint32_t>(),
-                          st);
+                          c->prank.as<uint2>(), st);
         scan_u32(c->tcr.as<uint32_t>(), npairs, nullptr, c->scan_ws.p, st);
-        launch_emit_isect(npairs, order, okey, pmask, c->prect.as<uint2>(), views,
+        launch_emit_isect(npairs, order, okey, pmask, c->prank.as<uint2>(), views,
                           c->tcr.as<uint32_t>(), B.lbits, c->ikey.as<uint32_t>(),
                           c->ival.as<uint32_t>(), st);
         CK(stage_end(c, ST_BIN, ev));
@@ -647,7 +648,7 @@ void slag_destroy(slag_ctx* c)
                       &c->dkey_alt, &c->dval, &c->dval_alt, &c->psz, &c->pz, &c->tcr, &c->wlen,
                       &c->ikey, &c->ikey_alt, &c->ival, &c->ival_alt, &c->bstart, &c->bend,
                       &c->part, &c->wrow, &c->perm, &c->rank, &c->pair_of_m,
-                      &c->pinfo, &c->prect, &c->blk_aux, &c->bkey,
+                      &c->pinfo, &c->prect, &c->prank, &c->blk_aux, &c->bkey,
                       &c->bkey_alt, &c->bord, &c->bord_alt, &c->tflag, &c->tpos, &c->tv,
                       &c->tv_alt, &c->tg, &c->thead, &c->tk, &c->tk_alt};
     destroy_graph(c);

@@ -111,7 +111,7 @@ struct slag_ctx {
     slag_host::DevBuf rec, pgauss, pview, dkey, dkey_alt, dval, dval_alt, psz, pz, tcr, wlen,
         pair_of_m;
     slag_host::DevBuf ikey, ikey_alt, ival, ival_alt, bstart, bend, part, wrow, pinfo;
-    slag_host::DevBuf prect, blk_aux, bkey, bkey_alt, bord, bord_alt;
+    slag_host::DevBuf prect, prank, blk_aux, bkey, bkey_alt, bord, bord_alt;
     slag_host::DevBuf tflag, tpos, tv, tv_alt, tg, thead, tk, tk_alt;   // depth ties
     uint64_t* host_small = nullptr;   // pinned read-back area
 

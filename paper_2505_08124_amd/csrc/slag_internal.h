@@ -101,11 +101,14 @@ void launch_tie_fix(uint64_t n, uint32_t m, uint64_t* keys, int shift, uint32_t*
                     uint64_t* tk, uint64_t* tk_alt, uint32_t* hist, void* scan_ws, hipStream_t st);
 
 // depth order: order[r], or (okey non-null) okey[r] & pmask; prect[p] = (entry
-// key of the pair's top-left tile, rectangle width | height << 16)
+// key of the pair's top-left tile, rectangle width | height << 16).
+// launch_rank_tiles writes the tile count tcr[r] and the rectangle prank[r]
+// of the pair of depth rank r; launch_emit_isect reads prank.
 void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const uint64_t* okey,
-                       uint64_t pmask, const uint2* prect, uint32_t* tcr, hipStream_t st);
+                       uint64_t pmask, const uint2* prect, uint32_t* tcr, uint2* prank,
+                       hipStream_t st);
 void launch_emit_isect(uint64_t npairs, const uint32_t* order, const uint64_t* okey,
-                       uint64_t pmask, const uint2* prect, const ViewDev* views,
+                       uint64_t pmask, const uint2* prank, const ViewDev* views,
                        const uint32_t* ioff, int lbits, uint32_t* ikey, uint32_t* ival,
                        hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
