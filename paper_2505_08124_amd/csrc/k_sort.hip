@@ -26,33 +26,26 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
     return x;
 }
 
-// Loads SCAN_ITEMS consecutive elements of thread t (zero past n).
-__device__ __forceinline__ void load_items(const uint32_t* data, uint64_t base, uint64_t n,
-                                           uint32_t* v)
-{
-    if (base + SCAN_ITEMS <= n && (base & 3) == 0) {
-        const uint4* p = reinterpret_cast<const uint4*>(data + base);
-#pragma unroll
-        for (int i = 0; i < SCAN_ITEMS / 4; i++) {
-            uint4 q = p[i];
-            v[4 * i] = q.x; v[4 * i + 1] = q.y; v[4 * i + 2] = q.z; v[4 * i + 3] = q.w;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < SCAN_ITEMS; i++) v[i] = (base + i < n) ? data[base + i] : 0u;
-    }
-}
+// Scans move their tiles through LDS: global loads and stores are striped
+// (element t + 256 i of the tile for thread t: one coalesced row per
+// instruction), the scan itself runs over SCAN_ITEMS consecutive elements
+// per thread.  One pad word per 16 keeps both LDS access patterns free of
+// bank conflicts.
+__device__ __forceinline__ int spad(int f) { return f + (f >> 4); }
+constexpr int SCAN_LDS = SCAN_TILE + SCAN_TILE / 16;
 
 __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ data, uint64_t n,
                                                      uint32_t* __restrict__ bsum,
                                                      unsigned long long* total)
 {
     __shared__ uint32_t lds[4];
-    uint32_t v[SCAN_ITEMS];
-    load_items(data, (uint64_t)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS, n, v);
+    const uint64_t b0 = (uint64_t)blockIdx.x * SCAN_TILE;
     uint32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; i++) s += v[i];
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        const uint64_t x = b0 + threadIdx.x + 256 * i;
+        s += x < n ? data[x] : 0u;
+    }
     s = wave_incl_scan(s);
     if ((threadIdx.x & 63) == 63) lds[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -69,26 +62,41 @@ __global__ __launch_bounds__(256) void k_scan_block(uint32_t* __restrict__ data,
                                                     unsigned long long* total)
 {
     __shared__ uint32_t lds[4];
-    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    __shared__ uint32_t tile[SCAN_LDS];
+    const int t = threadIdx.x;
+    const uint64_t b0 = (uint64_t)blockIdx.x * SCAN_TILE;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        const uint64_t x = b0 + t + 256 * i;
+        tile[spad(t + 256 * i)] = x < n ? data[x] : 0u;
+    }
+    __syncthreads();
     uint32_t v[SCAN_ITEMS];
-    load_items(data, base, n, v);
     uint32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; i++) s += v[i];
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        v[i] = tile[spad(t * SCAN_ITEMS + i)];
+        s += v[i];
+    }
     uint32_t incl = wave_incl_scan(s);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 63) lds[w] = incl;
+    const int w = t >> 6;
+    if ((t & 63) == 63) lds[w] = incl;
     __syncthreads();
     uint32_t off = boff ? boff[blockIdx.x] : 0u;
     for (int i = 0; i < w; i++) off += lds[i];
-    if (total && threadIdx.x == 0)
+    if (total && t == 0)
         *total = (unsigned long long)lds[0] + lds[1] + lds[2] + lds[3];
     uint32_t run = off + incl - s;
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; i++) {
-        uint32_t x = v[i];
-        if (base + i < n) data[base + i] = run;
-        run += x;
+        tile[spad(t * SCAN_ITEMS + i)] = run;
+        run += v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        const uint64_t x = b0 + t + 256 * i;
+        if (x < n) data[x] = tile[spad(t + 256 * i)];
     }
 }
 
