@@ -112,8 +112,9 @@ const char* slag_last_error(const slag_ctx* ctx);
  * means_xyz[N][3], scales_xyz[N][3] (linear standard deviations, > 0),
  * quats_wxyz[N][4] (rotation, any non-zero norm), opacity[N] in (0, 1].
  * All FP32.  Pointers are `where`-resident and are copied before return.
- * n = 0 is valid.  Non-finite or out-of-range values are rejected here
- * with SLAG_E_INVALID_ARG (a validation kernel and one synchronisation). */
+ * n = 0 is valid; more than 65535 x 2048 Gaussians is SLAG_E_CAPACITY.
+ * Non-finite or out-of-range values are rejected here with
+ * SLAG_E_INVALID_ARG (a validation kernel and one synchronisation). */
 slag_status slag_set_gaussians(slag_ctx* ctx, int64_t n, const float* means_xyz,
                                const float* scales_xyz, const float* quats_wxyz,
                                const float* opacity, slag_mem where);

@@ -187,9 +187,12 @@ __global__ __launch_bounds__(256) void k_count(int64_t n, const ViewDev* __restr
                                                uint32_t* __restrict__ zrange)
 {
     __shared__ uint32_t lds[4];
-    const int vl = blockIdx.y;
+    // grid (view, Gaussian block): consecutive workgroups are the views of one
+    // Gaussian block, whose data they then share through the caches
+    const int vl = blockIdx.x;
+    const int blk = blockIdx.y, nblk = gridDim.y;
     const ViewDev V = views[vl];
-    const int64_t g0 = (int64_t)blockIdx.x * CPB + threadIdx.x;
+    const int64_t g0 = (int64_t)blk * CPB + threadIdx.x;
     uint32_t* out = tcnt + (int64_t)vl * n;
     uint32_t nvis = 0, zmin = 0xFFFFFFFFu, zmax = 0;
 #pragma unroll 2
@@ -222,7 +225,7 @@ __global__ __launch_bounds__(256) void k_count(int64_t n, const ViewDev* __restr
         zl[4 + (threadIdx.x >> 6)] = zmax;
     }
     __syncthreads();
-    const int64_t bi = (int64_t)vl * gridDim.x + blockIdx.x;
+    const int64_t bi = (int64_t)vl * nblk + blk;
     if (threadIdx.x == 0) {
         blk_vis[bi] = total;
         zrange[2 * bi] = min(min(zl[0], zl[1]), min(zl[2], zl[3]));
@@ -248,11 +251,12 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
 {
     __shared__ uint32_t cnt[PER_THREAD][4];
     __shared__ uint64_t msk[4][PER_THREAD];
-    const int vl = blockIdx.y;
+    const int vl = blockIdx.x;                       // grid (view, Gaussian block)
+    const int blk = blockIdx.y, nblk = gridDim.y;
     const ViewDev V = views[vl];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t g0 = (int64_t)blockIdx.x * CPB + threadIdx.x;
+    const int64_t g0 = (int64_t)blk * CPB + threadIdx.x;
     const uint32_t* io = tcnt + (int64_t)vl * n;
 #pragma unroll
     for (int i = 0; i < PER_THREAD; i++) {
@@ -264,7 +268,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         }
     }
     __syncthreads();
-    uint32_t run = blk_off[(int64_t)vl * gridDim.x + blockIdx.x];
+    uint32_t run = blk_off[(int64_t)vl * nblk + blk];
     const int sw = V.ntx + 1;
     const uint32_t* S = sat + V.sat_off;
     unsigned long long n_isect = 0, n_part = 0;
@@ -331,7 +335,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         // and the host rejects totals that do)
         const unsigned long long a = tl[0] + tl[1] + tl[2] + tl[3];
         const unsigned long long b = tl[4] + tl[5] + tl[6] + tl[7];
-        const int64_t bi = (int64_t)vl * gridDim.x + blockIdx.x;
+        const int64_t bi = (int64_t)vl * nblk + blk;
         blk_tot[2 * bi] = a > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)a;
         blk_tot[2 * bi + 1] = b > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)b;
     }
@@ -482,7 +486,7 @@ void launch_count(int nb, int64_t n, const ViewDev* views, const float* means, c
                   uint32_t* tcnt, uint32_t* blk_vis, uint32_t* zrange, hipStream_t st)
 {
     if (n <= 0 || nb <= 0) return;
-    hipLaunchKernelGGL(k_count, dim3((unsigned)count_blocks_per_view(n), (unsigned)nb), dim3(256),
+    hipLaunchKernelGGL(k_count, dim3((unsigned)nb, (unsigned)count_blocks_per_view(n)), dim3(256),
                        0, st, n, views, means, cov3, tcnt, blk_vis, zrange);
 }
 
@@ -495,7 +499,7 @@ void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* mea
                        hipStream_t st)
 {
     if (n <= 0 || nb <= 0) return;
-    hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)count_blocks_per_view(n), (unsigned)nb),
+    hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)nb, (unsigned)count_blocks_per_view(n)),
                        dim3(256), 0, st, n, views, means, cov3, opac, tcnt_pairof, blk_off, rec,
                        pgauss, pview, dkey, dval, psz, pz, sat, zmin, zbits, pbits, blk_tot, perm,
                        pair_of_m, prect, lbits);

@@ -699,7 +699,9 @@ slag_status slag_set_gaussians(slag_ctx* c, int64_t n, const float* means, const
     invalidate_graph(c);
     if (n < 0 || (n > 0 && (!means || !scales || !quats || !opacity)))
         FAIL(c, SLAG_E_INVALID_ARG, "null pointer or negative Gaussian count");
-    if (n >= ((int64_t)1 << 31)) FAIL(c, SLAG_E_CAPACITY, "at most 2^31 - 1 Gaussians");
+    // the projection grid holds one row of workgroups per 2048 Gaussians
+    if (n >= ((int64_t)1 << 31) || count_blocks_per_view(n) > 65535)
+        FAIL(c, SLAG_E_CAPACITY, "at most 65535 x 2048 Gaussians");
     if (where != SLAG_HOST && where != SLAG_DEVICE) FAIL(c, SLAG_E_INVALID_ARG, "bad memory kind");
     HC(c, hipSetDevice(c->device));
     CK(copy_in(c, c->means, means, (size_t)n * 12, where));
