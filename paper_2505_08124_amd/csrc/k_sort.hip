@@ -1,11 +1,12 @@
 // Prefix scans, stable LSD radix sort and the tile binning of visible pairs.
 //
 // Tile lists must visit Gaussians front to back with ties broken by the
-// Gaussian index.  Pairs are compacted in (view, Gaussian) order, sorted
-// stably by (view, depth) once, expanded into (tile, pair) entries in that
-// order, and sorted stably by tile: each tile list comes out in (depth,
-// Gaussian) order without ever sorting the much longer intersection array by
-// depth.
+// caller's Gaussian index.  Pairs are compacted in (view, Morton rank) order,
+// sorted stably by (view, depth) once, runs of equal depth are put in the
+// caller's index order (the tie pass below), the pairs are expanded into
+// (tile, pair) entries in that order, and the entries are sorted stably by
+// tile: each tile list comes out in (depth, Gaussian index) order without
+// ever sorting the much longer intersection array by depth.
 #include "slag_internal.h"
 
 namespace slag {
