@@ -347,6 +347,16 @@ def test_depth_ties_follow_gaussian_index():
     ref = oracle.lift(sc)
     cmin, _ = check_embeddings(E, den, ref)
     _say(f"depth ties: min cosine {cmin:.9f}")
+    # graph replay (the captured lift includes the long-run path) gives the
+    # eager result bitwise, with unrelated GPU work between replays
+    import paper_2505_08124_amd as slag
+    Lg = _lifter(sc, flags=slag.SLAG_FLAG_GRAPH)
+    for i in range(3):
+        Lg.lift()
+        Eg, deng = Lg.embeddings()
+        assert np.array_equal(Eg, E) and np.array_equal(deng, den), i
+        _other_gpu_work()
+    check_tile_lists(Lg, sc, 1)
 
 
 # --------------------------------------------------------------- full sizes
