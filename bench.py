@@ -170,8 +170,8 @@ def main():
                          "to scale hardware traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the lift is not sharded "
-              "across GPUs in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library lifts on a "
+              "single GPU and does not shard across GPUs", file=sys.stderr)
         sys.exit(2)
 
     import torch
