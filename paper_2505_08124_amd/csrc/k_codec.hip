@@ -147,6 +147,125 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __r
             }
 }
 
+// Fused decoder for BF16 products, 64 code rows per workgroup: the hidden
+// layer h = gelu(code W3^T + b3) is formed on the matrix cores and kept in
+// LDS as bf16 (the rounding the two-product path applies when it stages h),
+// then y = h W4^T + b4 is formed 128 output columns at a time (32 per wave)
+// and written once, zero on rows whose rowmask <= 0.  The hidden layer never
+// reaches HBM and each W4 row is read once per workgroup.  Codes are padded
+// to KP columns with zeros; needs H % 64 == 0, H <= 384 and D % 128 == 0.
+template <int KP>
+__global__ __launch_bounds__(256) void k_decode_bf16(int M, int k, int H, int D,
+                                                     const float* __restrict__ code,
+                                                     const float* __restrict__ W3,
+                                                     const float* __restrict__ b3,
+                                                     const float* __restrict__ W4,
+                                                     const float* __restrict__ b4,
+                                                     const float* __restrict__ rowmask,
+                                                     float* __restrict__ y)
+{
+    extern __shared__ __align__(16) unsigned char dsm[];
+    const int HS = H + 8, KS = KP + 8;            // padded row strides (bf16)
+    __bf16* hid = reinterpret_cast<__bf16*>(dsm);  // [64][HS]
+    __bf16* cds = hid + 64 * HS;                   // [64][KS]
+    const int t = threadIdx.x, wv = t >> 6, lane = t & 63, m = lane & 15, kq = lane >> 4;
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    for (int e = t; e < 64 * KP; e += 256) {
+        const int rr = e / KP, kk = e - rr * KP;
+        const int64_t gr = r0 + rr;
+        cds[rr * KS + kk] = (__bf16)((gr < M && kk < k) ? code[gr * k + kk] : 0.0f);
+    }
+    __syncthreads();
+    // hidden layer: wave wv takes the 64-column groups c0 = 64 wv + 256 i
+    for (int c0 = 64 * wv; c0 < H; c0 += 256) {
+        floatx4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < KP; kk += 32) {
+            bf16x8 a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+                a[i] = *reinterpret_cast<const bf16x8*>(&cds[(16 * i + m) * KS + kk + 8 * kq]);
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const float* wr = W3 + (int64_t)(c0 + 16 * j + m) * k;
+#pragma unroll
+                for (int e = 0; e < 8; e++) {
+                    const int kc = kk + 8 * kq + e;
+                    b[j][e] = (__bf16)(kc < k ? wr[kc] : 0.0f);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int col = c0 + 16 * j + m;
+                const float bias = b3[col];
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+                    hid[(16 * i + 4 * kq + r) * HS + col] = (__bf16)gelu_f(acc[i][j][r] + bias);
+            }
+    }
+    __syncthreads();
+    float keep[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int64_t row = r0 + 16 * i + 4 * kq + r;
+            keep[i][r] = (row < M && !(rowmask && !(rowmask[row] > 0.0f))) ? 1.0f : 0.0f;
+        }
+    // output: 128 columns per pass, wave wv takes columns n0 + 32 wv .. + 31
+    for (int n0 = 0; n0 < D; n0 += 128) {
+        const int cb = n0 + 32 * wv;
+        floatx4 acc[4][2];
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 2; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int kk = 0; kk < H; kk += 32) {
+            bf16x8 a[4], b[2];
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+                a[i] = *reinterpret_cast<const bf16x8*>(&hid[(16 * i + m) * HS + kk + 8 * kq]);
+#pragma unroll
+            for (int j = 0; j < 2; j++) {
+                const float4* wr = reinterpret_cast<const float4*>(
+                    W4 + (int64_t)(cb + 16 * j + m) * H + kk + 8 * kq);
+                const float4 u0 = wr[0], u1 = wr[1];
+                b[j][0] = (__bf16)u0.x; b[j][1] = (__bf16)u0.y; b[j][2] = (__bf16)u0.z; b[j][3] = (__bf16)u0.w;
+                b[j][4] = (__bf16)u1.x; b[j][5] = (__bf16)u1.y; b[j][6] = (__bf16)u1.z; b[j][7] = (__bf16)u1.w;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 2; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 2; j++) {
+                const int col = cb + 16 * j + m;
+                const float bias = b4[col];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int64_t row = r0 + 16 * i + 4 * kq + r;
+                    if (row < M) y[row * D + col] = keep[i][r] * (acc[i][j][r] + bias);
+                }
+            }
+    }
+}
+
 // Sum of the K slices in slice order, then the epilogue.
 __global__ __launch_bounds__(256) void k_gemm_reduce(int M, int N, int splits,
                                                      const float* __restrict__ part,
@@ -435,6 +554,28 @@ int gemm_splits(int M, int N, int K, int* kper)
     if (kp <= 0) kp = GK;
     *kper = kp;
     return (K + kp - 1) / kp;
+}
+
+bool decode_fused_supported(int k, int H, int D)
+{
+    // LDS 64 (H + 8 + KP + 8) bf16 stays within the default 64 KiB
+    return k >= 1 && k <= 64 && H % 64 == 0 && H <= 384 && D % 128 == 0;
+}
+
+void launch_decode_bf16(int M, int k, int H, int D, const float* code, const float* W3,
+                        const float* b3, const float* W4, const float* b4, const float* rowmask,
+                        float* y, hipStream_t st)
+{
+    if (M <= 0) return;
+    const int KP = k <= 32 ? 32 : 64;
+    const size_t lds = (size_t)64 * ((H + 8) + (KP + 8)) * 2;
+    const dim3 grid((unsigned)((M + 63) / 64));
+    if (KP == 32)
+        hipLaunchKernelGGL((k_decode_bf16<32>), grid, dim3(256), lds, st, M, k, H, D, code, W3, b3,
+                           W4, b4, rowmask, y);
+    else
+        hipLaunchKernelGGL((k_decode_bf16<64>), grid, dim3(256), lds, st, M, k, H, D, code, W3, b3,
+                           W4, b4, rowmask, y);
 }
 
 void launch_gemm(bool bf16, bool a_bf16, int M, int N, int K, const void* A, int64_t sam,

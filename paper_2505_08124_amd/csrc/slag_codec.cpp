@@ -187,6 +187,13 @@ slag_status codec_encode_table(slag_ctx* c)
 slag_status codec_decode_codes(slag_ctx* c)
 {
     CodecState& S = c->codec;
+    if (S.bf16 && decode_fused_supported(S.k, S.h, S.d)) {
+        const Offsets o = offsets(S.d, S.h, S.k);
+        const float* P = S.params.as<float>();
+        launch_decode_bf16((int)c->n, S.k, S.h, S.d, S.codes.as<float>(), P + o.W3, P + o.b3,
+                           P + o.W4, P + o.b4, c->den.as<float>(), c->num.as<float>(), c->st);
+        return SLAG_OK;
+    }
     CK(ensure(c, S.hid, (size_t)std::max<int64_t>(c->n, 1) * S.h * 4));
     return decode(c, (int)c->n, S.codes.as<float>(), nullptr, S.hid.as<float>(), c->num.as<float>(),
                   c->den.as<float>());

@@ -164,6 +164,13 @@ struct GemmEpi {
 };
 int gemm_splits(int M, int N, int K, int* kper);
 size_t gemm_part_floats(int M, int N, int K);
+// Decoder y = (gelu(code W3^T + b3)) W4^T + b4 with BF16 products in one
+// kernel (the hidden layer stays in LDS); y rows with rowmask <= 0 are zero.
+// W3 [H][k], W4 [D][H] FP32 (rounded to bf16 like the staged products).
+bool decode_fused_supported(int k, int H, int D);
+void launch_decode_bf16(int M, int k, int H, int D, const float* code, const float* W3,
+                        const float* b3, const float* W4, const float* b4, const float* rowmask,
+                        float* y, hipStream_t st);
 void launch_gemm(bool bf16, bool a_bf16, int M, int N, int K, const void* A, int64_t sam,
                  int64_t sak, const float* B, int64_t sbk, int64_t sbn, float* C, int64_t ldc,
                  const GemmEpi& epi, float* part, hipStream_t st);

@@ -92,6 +92,34 @@ def test_codec_lift_matches_oracle(scene_2k, oracle_2k, prec, cos_min):
     assert cos_e.min() >= cos_min and cos_c.min() >= cos_min
 
 
+@pytest.mark.parametrize("k", [16, 48])
+def test_fused_decoder_codec_lift_matches_oracle(k):
+    """BF16 codec lift through the one-kernel decoder (hidden layer kept in
+    LDS; taken when H % 64 == 0, H <= 384 and D % 128 == 0) against the FP64
+    reference, for both code paddings (k <= 32 and k <= 64)."""
+    import paper_2505_08124_amd as slag
+    import scipy.sparse as sp
+    sc = make_scene("plain_fp32_2k", features=dict(D=128, dtype="bf16"))
+    ref = oracle.lift(sc, mode="box", pixels=True)
+    dims = cd.Dims(d=128, h=64, k=k)
+    p = init_params(dims.d, dims.h, dims.k, seed=24, bias_sd=0.1)
+    W = oracle.weight_matrix(sc, list(range(sc.n_views)), ref.views)
+    rs = np.asarray(W.sum(axis=1)).ravel()
+    inv = np.divide(1.0, rs, out=np.zeros_like(rs), where=rs > 0)
+    E_ref, _ = cd.codec_lift(p.astype(np.float64), dims, sp.diags(inv) @ W, sc.feats_f64())
+    with slag.Lifter(0) as L:
+        L.set_scene(sc)
+        slag.slag_codec_init(L.ctx, dims.d, dims.h, dims.k, slag.SLAG_BF16, p)
+        L.lift_codec()
+        E, den = L.embeddings()
+    nz = ref.den > 0
+    assert np.array_equal(den > 0, nz) and np.all(E[~nz] == 0)
+    comp = nz & (ref.U / np.maximum(ref.den, 1e-300) <= 5e-3)
+    cos = cd.cosine_rows(E[comp], E_ref[comp])
+    _say(f"fused decoder k={k}: min cosine {cos.min():.6f}")
+    assert cos.min() >= 0.99
+
+
 def _train_scene(seed, n, views):
     return make_scene("codec_train", seed=seed, n=n, views=dict(n=views))
 
