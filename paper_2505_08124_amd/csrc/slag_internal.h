@@ -43,6 +43,12 @@ void launch_validate_ids(int64_t npix, const int32_t* ids, int32_t nseg, uint32_
 void launch_count(int nb, int64_t n, const ViewDev* views, const float* means, const float* cov3,
                   uint32_t* tcnt, uint32_t* blk_vis, uint32_t* zrange, hipStream_t st);
 int count_blocks_per_view(int64_t n);
+// Pass 2 over the same (view, Gaussian block) grid: visible pairs compacted
+// in (view, Morton rank) order with their records, depth keys (pair index in
+// the low pbits bits when pbits > 0, else in dval), part-list capacities
+// psz, packed tile rectangles prect (entry key base for lbits), the caller's
+// Gaussian index pgauss[pair] = perm[g], the view pview, and the (view, rank)
+// -> pair map pair_of_m (NONE where not visible); pz only when non-null.
 void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* means,
                        const float* cov3, const float* opac, uint32_t* tcnt_pairof,
                        const uint32_t* blk_off, float4* rec, uint32_t* pgauss, uint16_t* pview,
