@@ -258,10 +258,16 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t g0 = (int64_t)blk * CPB + threadIdx.x;
     const uint32_t* io = tcnt + (int64_t)vl * n;
+    uint32_t tc[PER_THREAD];   // all loads in flight before the first is used
 #pragma unroll
     for (int i = 0; i < PER_THREAD; i++) {
         const int64_t g = g0 + (int64_t)i * 256;
-        const uint64_t m = __ballot(g < n && io[g] != 0);
+        const uint32_t v = io[g < n ? g : n - 1];   // unconditional: no branch between loads
+        tc[i] = g < n ? v : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; i++) {
+        const uint64_t m = __ballot(tc[i] != 0);
         if (lane == 0) {
             cnt[i][wv] = (uint32_t)__popcll(m);
             msk[wv][i] = m;

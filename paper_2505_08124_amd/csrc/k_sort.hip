@@ -66,11 +66,14 @@ __global__ __launch_bounds__(256) void k_scan_block(uint32_t* __restrict__ data,
     __shared__ uint32_t tile[SCAN_LDS];
     const int t = threadIdx.x;
     const uint64_t b0 = (uint64_t)blockIdx.x * SCAN_TILE;
+    uint32_t ld[SCAN_ITEMS];   // all loads in flight before the first LDS store
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; i++) {
         const uint64_t x = b0 + t + 256 * i;
-        tile[spad(t + 256 * i)] = x < n ? data[x] : 0u;
+        ld[i] = x < n ? data[x] : 0u;
     }
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) tile[spad(t + 256 * i)] = ld[i];
     __syncthreads();
     uint32_t v[SCAN_ITEMS];
     uint32_t s = 0;
@@ -187,9 +190,6 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
     __shared__ uint32_t s_val[NV >= 1 ? TILE_N : 1];
     __shared__ uint32_t s_aux[NV >= 2 ? TILE_N : 1];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = threadIdx.x; i < 4 * R; i += 256) (&wcnt[0][0])[i] = 0;
-    for (int i = threadIdx.x; i < R; i += 256) dbase[i] = hist[(uint64_t)i * nblk + blockIdx.x];
-    __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint64_t bbase = (uint64_t)blockIdx.x * TILE_N;
     const uint64_t base = bbase + (uint64_t)w * (ITEMS * 64);
@@ -198,6 +198,8 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
     uint32_t val[NV >= 1 ? ITEMS : 1];
     uint32_t aux[NV >= 2 ? ITEMS : 1];
     uint32_t rk[ITEMS];
+    // every load of the block is issued before the first is used (the
+    // ranking below has wave barriers, which keep loads from moving past them)
 #pragma unroll
     for (int it = 0; it < ITEMS; it++) {
         const uint64_t idx = base + it * 64 + lane;
@@ -205,6 +207,14 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
         key[it] = valid ? kin[idx] : (K)0;
         if constexpr (NV >= 1) val[it] = valid ? vin[idx] : 0u;
         if constexpr (NV >= 2) aux[it] = valid ? uin[idx] : 0u;
+    }
+    for (int i = threadIdx.x; i < 4 * R; i += 256) (&wcnt[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < R; i += 256) dbase[i] = hist[(uint64_t)i * nblk + blockIdx.x];
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < ITEMS; it++) {
+        const uint64_t idx = base + it * 64 + lane;
+        const bool valid = idx < n;
         const uint32_t d = (uint32_t)(key[it] >> shift) & (R - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -531,12 +541,16 @@ __device__ __forceinline__ void cmp_swap(uint32_t& ga, uint32_t& pa, uint32_t& g
 }
 
 // Short runs sorted by their head thread; positions in long runs counted
-// into *nlong.  The block's 256 keys and TIE_SHORT on each side are staged in
-// LDS once (coalesced); a tied position reads its window of 2 TIE_SHORT + 1
-// keys there (the window decides both the long-run test and the run's
-// extent); a head then loads its pairs' Gaussian indices at once and sorts
-// them with a fixed 19-comparator network (padding sorts last).  Writes
-// change only pair fields, so other blocks' halo copies keep valid depths.
+// into *nlong.  A block covers TIE_BLOCK positions, four per thread (strided,
+// so global accesses stay coalesced); its keys and TIE_SHORT on each side are
+// staged in LDS once, all loads in flight together.  A tied position reads its
+// window of 2 TIE_SHORT + 1 keys there (the window decides both the long-run
+// test and the run's extent); a head then loads its pairs' Gaussian indices
+// at once and sorts them with a fixed 19-comparator network (padding sorts
+// last).  Writes change only pair fields, so other blocks' halo copies keep
+// valid depths, and a run has one head, so no two threads write one position.
+constexpr int TIE_BLOCK = 1024;
+
 __global__ __launch_bounds__(256) void k_tie_short(uint64_t n, uint64_t* __restrict__ keys, int shift,
                                                    uint32_t* __restrict__ order, uint64_t pmask,
                                                    const uint32_t* __restrict__ gidx,
@@ -544,65 +558,78 @@ __global__ __launch_bounds__(256) void k_tie_short(uint64_t n, uint64_t* __restr
 {
     static_assert(TIE_SHORT == 8, "the sorting network is for 8 entries");
     constexpr int WN = 2 * TIE_SHORT + 1;
-    constexpr int SN = 256 + 2 * TIE_SHORT;
-    __shared__ uint64_t sk[SN];          // keys b0 - TIE_SHORT .. b0 + 256 + TIE_SHORT
-    const uint64_t b0 = (uint64_t)blockIdx.x * 256;
-    for (int a = threadIdx.x; a < SN; a += 256) {
+    constexpr int SN = TIE_BLOCK + 2 * TIE_SHORT;
+    constexpr int NL = (SN + 255) / 256;
+    __shared__ uint64_t sk[SN];          // keys b0 - TIE_SHORT .. b0 + TIE_BLOCK + TIE_SHORT
+    __shared__ uint32_t wl[4];
+    const uint64_t b0 = (uint64_t)blockIdx.x * TIE_BLOCK;
+    uint64_t ld[NL];
+#pragma unroll
+    for (int j = 0; j < NL; j++) {
+        const int a = threadIdx.x + 256 * j;
         const int64_t x = (int64_t)b0 - TIE_SHORT + a;
-        sk[a] = (x >= 0 && (uint64_t)x < n) ? keys[x] : 0ull;
+        ld[j] = (a < SN && x >= 0 && (uint64_t)x < n) ? keys[x] : 0ull;
+    }
+#pragma unroll
+    for (int j = 0; j < NL; j++) {
+        const int a = threadIdx.x + 256 * j;
+        if (a < SN) sk[a] = ld[j];
     }
     __syncthreads();
-    const uint64_t i = b0 + threadIdx.x;
-    const int li = threadIdx.x + TIE_SHORT;   // i's slot in sk
-    bool lng = false;
-    if (i < n) {
+    uint32_t nlng = 0;
+#pragma unroll 1
+    for (int k = 0; k < TIE_BLOCK / 256; k++) {
+        const int lo = threadIdx.x + 256 * k;
+        const uint64_t i = b0 + lo;
+        const int li = lo + TIE_SHORT;   // i's slot in sk
+        if (i >= n) break;
         const uint64_t h = sk[li] >> shift;
         const bool tp = i > 0 && (sk[li - 1] >> shift) == h;
         const bool tn = i + 1 < n && (sk[li + 1] >> shift) == h;
-        if (tp || tn) {
-            bool eq[WN];
+        if (!(tp || tn)) continue;
+        bool eq[WN];
 #pragma unroll
-            for (int a = 0; a < WN; a++) {
-                const int64_t x = (int64_t)i - TIE_SHORT + a;
-                eq[a] = x >= 0 && (uint64_t)x < n && (sk[li - TIE_SHORT + a] >> shift) == h;
-            }
+        for (int a = 0; a < WN; a++) {
+            const int64_t x = (int64_t)i - TIE_SHORT + a;
+            eq[a] = x >= 0 && (uint64_t)x < n && (sk[li - TIE_SHORT + a] >> shift) == h;
+        }
+        bool lng = false;
 #pragma unroll
-            for (int a = 0; a <= TIE_SHORT; a++) lng = lng || (eq[TIE_SHORT - a] && eq[WN - 1 - a]);
-            if (!tp && !lng) {
-                // head of a short run: positions i .. i + len - 1, len <= 8
-                uint32_t pv[TIE_SHORT], gv[TIE_SHORT];
+        for (int a = 0; a <= TIE_SHORT; a++) lng = lng || (eq[TIE_SHORT - a] && eq[WN - 1 - a]);
+        nlng += lng;
+        if (tp || lng) continue;
+        // head of a short run: positions i .. i + len - 1, len <= 8
+        uint32_t pv[TIE_SHORT], gv[TIE_SHORT];
 #pragma unroll
-                for (int a = 0; a < TIE_SHORT; a++) {
-                    const bool in = eq[TIE_SHORT + a];
-                    pv[a] = order ? order[in ? i + a : i] : (uint32_t)(sk[li + a] & pmask);
-                }
+        for (int a = 0; a < TIE_SHORT; a++) {
+            const bool in = eq[TIE_SHORT + a];
+            pv[a] = order ? order[in ? i + a : i] : (uint32_t)(sk[li + a] & pmask);
+        }
 #pragma unroll
-                for (int a = 0; a < TIE_SHORT; a++) {
-                    const uint32_t g = gidx[pv[a]];
-                    gv[a] = eq[TIE_SHORT + a] ? g : 0xFFFFFFFFu;
-                }
-                cmp_swap(gv[0], pv[0], gv[1], pv[1]); cmp_swap(gv[2], pv[2], gv[3], pv[3]);
-                cmp_swap(gv[4], pv[4], gv[5], pv[5]); cmp_swap(gv[6], pv[6], gv[7], pv[7]);
-                cmp_swap(gv[0], pv[0], gv[2], pv[2]); cmp_swap(gv[1], pv[1], gv[3], pv[3]);
-                cmp_swap(gv[4], pv[4], gv[6], pv[6]); cmp_swap(gv[5], pv[5], gv[7], pv[7]);
-                cmp_swap(gv[1], pv[1], gv[2], pv[2]); cmp_swap(gv[5], pv[5], gv[6], pv[6]);
-                cmp_swap(gv[0], pv[0], gv[4], pv[4]); cmp_swap(gv[1], pv[1], gv[5], pv[5]);
-                cmp_swap(gv[2], pv[2], gv[6], pv[6]); cmp_swap(gv[3], pv[3], gv[7], pv[7]);
-                cmp_swap(gv[2], pv[2], gv[4], pv[4]); cmp_swap(gv[3], pv[3], gv[5], pv[5]);
-                cmp_swap(gv[1], pv[1], gv[2], pv[2]); cmp_swap(gv[3], pv[3], gv[4], pv[4]);
-                cmp_swap(gv[5], pv[5], gv[6], pv[6]);
+        for (int a = 0; a < TIE_SHORT; a++) {
+            const uint32_t g = gidx[pv[a]];
+            gv[a] = eq[TIE_SHORT + a] ? g : 0xFFFFFFFFu;
+        }
+        cmp_swap(gv[0], pv[0], gv[1], pv[1]); cmp_swap(gv[2], pv[2], gv[3], pv[3]);
+        cmp_swap(gv[4], pv[4], gv[5], pv[5]); cmp_swap(gv[6], pv[6], gv[7], pv[7]);
+        cmp_swap(gv[0], pv[0], gv[2], pv[2]); cmp_swap(gv[1], pv[1], gv[3], pv[3]);
+        cmp_swap(gv[4], pv[4], gv[6], pv[6]); cmp_swap(gv[5], pv[5], gv[7], pv[7]);
+        cmp_swap(gv[1], pv[1], gv[2], pv[2]); cmp_swap(gv[5], pv[5], gv[6], pv[6]);
+        cmp_swap(gv[0], pv[0], gv[4], pv[4]); cmp_swap(gv[1], pv[1], gv[5], pv[5]);
+        cmp_swap(gv[2], pv[2], gv[6], pv[6]); cmp_swap(gv[3], pv[3], gv[7], pv[7]);
+        cmp_swap(gv[2], pv[2], gv[4], pv[4]); cmp_swap(gv[3], pv[3], gv[5], pv[5]);
+        cmp_swap(gv[1], pv[1], gv[2], pv[2]); cmp_swap(gv[3], pv[3], gv[4], pv[4]);
+        cmp_swap(gv[5], pv[5], gv[6], pv[6]);
 #pragma unroll
-                for (int a = 0; a < TIE_SHORT; a++) {
-                    if (!eq[TIE_SHORT + a]) continue;
-                    if (order) order[i + a] = pv[a];
-                    else keys[i + a] = (sk[li + a] & ~pmask) | pv[a];
-                }
-            }
+        for (int a = 0; a < TIE_SHORT; a++) {
+            if (!eq[TIE_SHORT + a]) continue;
+            if (order) order[i + a] = pv[a];
+            else keys[i + a] = (sk[li + a] & ~pmask) | pv[a];
         }
     }
-    const uint64_t bl = __ballot(lng);
-    __shared__ uint32_t wl[4];
-    if ((threadIdx.x & 63) == 0) wl[threadIdx.x >> 6] = (uint32_t)__popcll(bl);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) nlng += (uint32_t)__shfl_xor((int)nlng, d, 64);
+    if ((threadIdx.x & 63) == 0) wl[threadIdx.x >> 6] = nlng;
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t t = wl[0] + wl[1] + wl[2] + wl[3];
@@ -686,8 +713,8 @@ void launch_tie_short(uint64_t n, uint64_t* keys, int shift, uint32_t* order, ui
                       const uint32_t* gidx, unsigned long long* nlong, hipStream_t st)
 {
     if (!n) return;
-    hipLaunchKernelGGL(k_tie_short, dim3(grid_for(n)), dim3(256), 0, st, n, keys, shift, order,
-                       pmask, gidx, nlong);
+    hipLaunchKernelGGL(k_tie_short, dim3((unsigned)((n + TIE_BLOCK - 1) / TIE_BLOCK)), dim3(256), 0,
+                       st, n, keys, shift, order, pmask, gidx, nlong);
 }
 
 void launch_tie_flags(uint64_t n, const uint64_t* keys, int shift, uint32_t* flag, hipStream_t st)
