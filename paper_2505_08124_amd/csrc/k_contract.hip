@@ -177,6 +177,15 @@ __global__ __launch_bounds__(256, 3) void k_contract_mfma(
 #pragma unroll
             for (int i = 0; i < NT; i++) acc[r][i] = floatx4{0.f, 0.f, 0.f, 0.f};
     } else {
+        // clamped (always valid) loads, all in flight before the first is used
+        uint32_t gq[RT][4];
+#pragma unroll
+        for (int r = 0; r < RT; r++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int64_t q = q0 + 16 * r + 4 * kq + j;
+                gq[r][j] = perm[q < n ? q : n - 1];
+            }
 #pragma unroll
         for (int r = 0; r < RT; r++)
 #pragma unroll
@@ -184,7 +193,8 @@ __global__ __launch_bounds__(256, 3) void k_contract_mfma(
 #pragma unroll
                 for (int j = 0; j < 4; j++) {
                     const int64_t q = q0 + 16 * r + 4 * kq + j;
-                    acc[r][i][j] = (wact && q < n) ? num[(size_t)perm[q] * d + c0 + 16 * i + m] : 0.0f;
+                    const float x = num[(size_t)gq[r][j] * d + (wact ? c0 + 16 * i + m : 0)];
+                    acc[r][i][j] = (wact && q < n) ? x : 0.0f;
                 }
         if (t < G && q0 + t < n) dsum = den[perm[q0 + t]];
     }
