@@ -113,17 +113,25 @@ __global__ __launch_bounds__(256) void k_scan_block(uint32_t* __restrict__ data,
 // digit's run leaves the block as consecutive addresses.  An optional second
 // value array rides along.
 
-// Items per thread: 16 (4096-element blocks) for passes of 6 bits or more,
-// whose many digits need the longer blocks to keep runs of equal digits
-// long; 8 below that, where smaller blocks give more workgroups.
-constexpr int RADIX_ITEMS_MIN = 8;
+// Items per thread: 32 (8192-element blocks) for passes of 6 bits or more,
+// whose many digits need long blocks to keep runs of equal digits long;
+// 16 below that.  Bare 64-bit keys take 32 only in long sorts (at least
+// RADIX_LONG keys): their blocks hold 64 KB of LDS, two per CU, and a
+// sort of a few thousand such blocks ran faster with the smaller ones
+// (measured at 2e7 keys; 3e8 keys gained from the larger).
+constexpr int RADIX_ITEMS_MIN = 16;
 constexpr int RADIX_TILE_MIN = 256 * RADIX_ITEMS_MIN;
 constexpr int RADIX_MAXBITS = 8;
-template <int RB> constexpr int radix_items() { return RB >= 6 ? 16 : 8; }
+constexpr uint64_t RADIX_LONG = 1ull << 25;
+template <typename K, int RB, int NV>
+constexpr int radix_items(bool long_sort)
+{
+    return (RB >= 6 && (long_sort || !(sizeof(K) == 8 && NV == 0))) ? 32 : 16;
+}
 
 // One wave counts one sort block (256 * ITEMS keys, 4 * ITEMS coalesced
-// loads per lane, all in flight), so a workgroup covers four blocks and each
-// wave writes its own column of the (digit, block) matrix.
+// loads per lane, in flight 32 or 64 at a time), so a workgroup covers four
+// blocks and each wave writes its own column of the (digit, block) matrix.
 template <typename K, int RB, int ITEMS>
 __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, uint64_t n,
                                                     int shift, uint32_t* __restrict__ hist,
@@ -140,15 +148,17 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
     __syncthreads();
     const uint64_t sb = (uint64_t)blockIdx.x * 4 + w;
     if (sb < nblk) {
-        const uint64_t base = sb * TILE_N + lane;
-        K k[PER];
+        constexpr int CH = PER > 64 ? 32 : PER;   // keys held in registers at once
+        for (int c0 = 0; c0 < PER; c0 += CH) {
+        const uint64_t base = sb * TILE_N + lane + (uint64_t)c0 * 64;
+        K k[CH];
 #pragma unroll
-        for (int it = 0; it < PER; it++) {
+        for (int it = 0; it < CH; it++) {
             const uint64_t idx = base + (uint64_t)it * 64;
             k[it] = idx < n ? keys[idx] : (K)0;
         }
 #pragma unroll
-        for (int it = 0; it < PER; it++) {
+        for (int it = 0; it < CH; it++) {
             const bool valid = base + (uint64_t)it * 64 < n;
             const uint32_t d = (uint32_t)(k[it] >> shift) & (R - 1);
             // all valid lanes on one digit: the first adds them; else LDS atomics
@@ -160,6 +170,7 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
                 atomicAdd(&cnt[w][d], 1u);
             }
             __builtin_amdgcn_wave_barrier();
+        }
         }
     }
     __syncthreads();
@@ -296,11 +307,10 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
     }
 }
 
-template <typename K, int RB, int NV>
-void radix_pass(const K* ka, const uint32_t* va, const uint32_t* ua, K* kb, uint32_t* vb,
-                uint32_t* ub, uint64_t n, int shift, uint32_t* hist, void* ws, hipStream_t st)
+template <typename K, int RB, int NV, int ITEMS>
+void radix_pass_items(const K* ka, const uint32_t* va, const uint32_t* ua, K* kb, uint32_t* vb,
+                      uint32_t* ub, uint64_t n, int shift, uint32_t* hist, void* ws, hipStream_t st)
 {
-    constexpr int ITEMS = radix_items<RB>();
     constexpr int TILE_N = 256 * ITEMS;
     const uint32_t nblk = (uint32_t)((n + TILE_N - 1) / TILE_N);
     hipLaunchKernelGGL((k_radix_hist<K, RB, ITEMS>), dim3((nblk + 3) / 4), dim3(256), 0, st, ka, n,
@@ -308,6 +318,17 @@ void radix_pass(const K* ka, const uint32_t* va, const uint32_t* ua, K* kb, uint
     scan_u32(hist, (uint64_t)nblk << RB, nullptr, ws, st);
     hipLaunchKernelGGL((k_radix_scatter<K, RB, NV, ITEMS>), dim3(nblk), dim3(256), 0, st, ka, va, ua,
                        kb, vb, ub, n, shift, hist, nblk);
+}
+
+template <typename K, int RB, int NV>
+void radix_pass(const K* ka, const uint32_t* va, const uint32_t* ua, K* kb, uint32_t* vb,
+                uint32_t* ub, uint64_t n, int shift, uint32_t* hist, void* ws, hipStream_t st)
+{
+    constexpr int IS = radix_items<K, RB, NV>(false), IL = radix_items<K, RB, NV>(true);
+    if (IL != IS && n >= RADIX_LONG)
+        radix_pass_items<K, RB, NV, IL>(ka, va, ua, kb, vb, ub, n, shift, hist, ws, st);
+    else
+        radix_pass_items<K, RB, NV, IS>(ka, va, ua, kb, vb, ub, n, shift, hist, ws, st);
 }
 
 // Stable LSD sort of (key[, value[, aux]]) by bits [bit0, bit0 + nbits): the
