@@ -383,17 +383,42 @@ __device__ __forceinline__ uint32_t pair_at_rank(const uint32_t* __restrict__ or
     return okey ? (uint32_t)(okey[r] & pmask) : order[r];
 }
 
+// Four ranks per thread (strided by 256, coalesced): the four depth-order
+// loads, then the four rectangle gathers, each group in flight together
+// (clamped indices, so no branch separates them).
+constexpr int RANK_ITEMS = 4;
+
 __global__ __launch_bounds__(256) void k_rank_tiles(uint64_t npairs, const uint32_t* __restrict__ order,
                                                     const uint64_t* __restrict__ okey, uint64_t pmask,
                                                     const uint2* __restrict__ prect,
                                                     uint32_t* __restrict__ tcr,
                                                     uint2* __restrict__ prank)
 {
-    const uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r < npairs) {
-        const uint2 q = prect[pair_at_rank(order, okey, pmask, r)];
-        tcr[r] = (q.y & 0xFFFFu) * (q.y >> 16);
-        prank[r] = q;   // the rectangle in depth order, for the emission
+    const uint64_t r0 = (uint64_t)blockIdx.x * (256 * RANK_ITEMS) + threadIdx.x;
+    uint32_t p[RANK_ITEMS];
+    if (okey) {
+#pragma unroll
+        for (int i = 0; i < RANK_ITEMS; i++) {
+            const uint64_t r = r0 + 256 * i;
+            p[i] = (uint32_t)(okey[r < npairs ? r : npairs - 1] & pmask);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < RANK_ITEMS; i++) {
+            const uint64_t r = r0 + 256 * i;
+            p[i] = order[r < npairs ? r : npairs - 1];
+        }
+    }
+    uint2 q[RANK_ITEMS];
+#pragma unroll
+    for (int i = 0; i < RANK_ITEMS; i++) q[i] = prect[p[i]];
+#pragma unroll
+    for (int i = 0; i < RANK_ITEMS; i++) {
+        const uint64_t r = r0 + 256 * i;
+        if (r < npairs) {
+            tcr[r] = (q[i].y & 0xFFFFu) * (q[i].y >> 16);
+            prank[r] = q[i];   // the rectangle in depth order, for the emission
+        }
     }
 }
 
@@ -421,10 +446,15 @@ __global__ __launch_bounds__(256) void k_emit_isect(uint64_t npairs, const uint3
     const uint64_t r = r0 + lane;
     const int nw = (int)min((uint64_t)64, npairs - r0);
     uint32_t o = 0, tc = 0;
+    // clamped loads, all three in flight together
+    const uint64_t rc = lane < nw ? r : r0;
+    const uint2 ql = prank[rc];
+    const uint32_t ol = ioff[rc];
+    const uint32_t pl = okey ? (uint32_t)(okey[rc] & pmask) : order[rc];
     if (lane < nw) {
-        const uint32_t p = pair_at_rank(order, okey, pmask, r);
-        const uint2 q = prank[r];
-        o = ioff[r];
+        const uint32_t p = pl;
+        const uint2 q = ql;
+        o = ol;
         tc = (q.y & 0xFFFFu) * (q.y >> 16);
         s_p[w][lane] = p;
         s_r[w][lane][0] = q.x;
@@ -834,8 +864,9 @@ void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const uint64_t* o
                        hipStream_t st)
 {
     if (!npairs) return;
-    hipLaunchKernelGGL(k_rank_tiles, dim3(grid_for(npairs)), dim3(256), 0, st, npairs, order, okey,
-                       pmask, prect, tcr, prank);
+    const uint64_t per = 256 * RANK_ITEMS;
+    hipLaunchKernelGGL(k_rank_tiles, dim3((unsigned)((npairs + per - 1) / per)), dim3(256), 0, st,
+                       npairs, order, okey, pmask, prect, tcr, prank);
 }
 
 void launch_emit_isect(uint64_t npairs, const uint32_t* order, const uint64_t* okey,
