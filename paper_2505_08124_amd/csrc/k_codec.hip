@@ -80,19 +80,33 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __r
 #pragma unroll
         for (int j = 0; j < 2; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+    constexpr int TE = GT * GK / 256;   // tile elements per thread
     for (int k0 = kb; k0 < ke; k0 += GK) {
+        // clamped (always valid) loads of both tiles, all in flight before
+        // the first LDS store
+        float av[TE], bv[TE];
 #pragma unroll
-        for (int i = 0; i < GT * GK / 256; i++) {
+        for (int i = 0; i < TE; i++) {
             const int e = t + 256 * i;
             const int mm = a_kfast ? (e >> 5) : (e & 63);
             const int kk = a_kfast ? (e & 31) : (e >> 6);
             const int64_t gm = m0 + mm;
             const int gk = k0 + kk;
-            As[mm][kk] = (gm < M && gk < ke) ? load_elem(A, gm * sam + (int64_t)gk * sak) : 0.0f;
+            const bool oka = gm < M && gk < ke;
+            const float xa = load_elem(A, oka ? gm * sam + (int64_t)gk * sak : 0);
+            av[i] = oka ? xa : 0.0f;
             const int nn = b_nfast ? (e & 63) : (e >> 5);
             const int kb2 = b_nfast ? (e >> 6) : (e & 31);
             const int gn = n0 + nn, gk2 = k0 + kb2;
-            Bs[kb2][nn] = (gn < N && gk2 < ke) ? B[(int64_t)gk2 * sbk + (int64_t)gn * sbn] : 0.0f;
+            const bool okb = gn < N && gk2 < ke;
+            const float xb = B[okb ? (int64_t)gk2 * sbk + (int64_t)gn * sbn : 0];
+            bv[i] = okb ? xb : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < TE; i++) {
+            const int e = t + 256 * i;
+            As[a_kfast ? (e >> 5) : (e & 63)][a_kfast ? (e & 31) : (e >> 6)] = av[i];
+            Bs[b_nfast ? (e >> 6) : (e & 31)][b_nfast ? (e & 63) : (e >> 5)] = bv[i];
         }
         __syncthreads();
         if constexpr (BF16) {
@@ -170,10 +184,23 @@ __global__ __launch_bounds__(256) void k_decode_bf16(int M, int k, int H, int D,
     __bf16* cds = hid + 64 * HS;                   // [64][KS]
     const int t = threadIdx.x, wv = t >> 6, lane = t & 63, m = lane & 15, kq = lane >> 4;
     const int64_t r0 = (int64_t)blockIdx.x * 64;
-    for (int e = t; e < 64 * KP; e += 256) {
+    // clamped (always valid) loads, all in flight before the first LDS store
+    constexpr int CE = 64 * KP / 256;
+    float cv[CE];
+#pragma unroll
+    for (int u = 0; u < CE; u++) {
+        const int e = t + 256 * u;
         const int rr = e / KP, kk = e - rr * KP;
         const int64_t gr = r0 + rr;
-        cds[rr * KS + kk] = (__bf16)((gr < M && kk < k) ? code[gr * k + kk] : 0.0f);
+        const bool ok = gr < M && kk < k;
+        const float x = code[(ok ? gr : 0) * k + (ok ? kk : 0)];
+        cv[u] = ok ? x : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < CE; u++) {
+        const int e = t + 256 * u;
+        const int rr = e / KP, kk = e - rr * KP;
+        cds[rr * KS + kk] = (__bf16)cv[u];
     }
     __syncthreads();
     // hidden layer: wave wv takes the 64-column groups c0 = 64 wv + 256 i
@@ -195,7 +222,8 @@ __global__ __launch_bounds__(256) void k_decode_bf16(int M, int k, int H, int D,
 #pragma unroll
                 for (int e = 0; e < 8; e++) {
                     const int kc = kk + 8 * kq + e;
-                    b[j][e] = (__bf16)(kc < k ? wr[kc] : 0.0f);
+                    const float x = wr[kc < k ? kc : k - 1];   // clamped: no branch between loads
+                    b[j][e] = (__bf16)(kc < k ? x : 0.0f);
                 }
             }
 #pragma unroll
@@ -204,26 +232,45 @@ __global__ __launch_bounds__(256) void k_decode_bf16(int M, int k, int H, int D,
                 for (int j = 0; j < 4; j++)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
+        float bias[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) bias[j] = b3[c0 + 16 * j + m];
 #pragma unroll
         for (int i = 0; i < 4; i++)
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const int col = c0 + 16 * j + m;
-                const float bias = b3[col];
 #pragma unroll
                 for (int r = 0; r < 4; r++)
-                    hid[(16 * i + 4 * kq + r) * HS + col] = (__bf16)gelu_f(acc[i][j][r] + bias);
+                    hid[(16 * i + 4 * kq + r) * HS + col] = (__bf16)gelu_f(acc[i][j][r] + bias[j]);
             }
     }
-    __syncthreads();
+    // rows kept: inside the matrix and (with a mask) of positive mask value;
+    // clamped mask loads, all in flight together
     float keep[4][4];
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
         for (int r = 0; r < 4; r++) {
             const int64_t row = r0 + 16 * i + 4 * kq + r;
-            keep[i][r] = (row < M && !(rowmask && !(rowmask[row] > 0.0f))) ? 1.0f : 0.0f;
+            keep[i][r] = row < M ? 1.0f : 0.0f;
         }
+    if (rowmask) {
+        float mk[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int64_t row = r0 + 16 * i + 4 * kq + r;
+                mk[i][r] = rowmask[row < M ? row : M - 1];
+            }
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                if (!(mk[i][r] > 0.0f)) keep[i][r] = 0.0f;
+    }
+    __syncthreads();
     // output: 128 columns per pass, wave wv takes columns n0 + 32 wv .. + 31
     for (int n0 = 0; n0 < D; n0 += 128) {
         const int cb = n0 + 32 * wv;
@@ -251,16 +298,16 @@ __global__ __launch_bounds__(256) void k_decode_bf16(int M, int k, int H, int D,
                 for (int j = 0; j < 2; j++)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
+        const float bias[2] = {b4[cb + m], b4[cb + 16 + m]};
 #pragma unroll
         for (int i = 0; i < 4; i++)
 #pragma unroll
             for (int j = 0; j < 2; j++) {
                 const int col = cb + 16 * j + m;
-                const float bias = b4[col];
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
                     const int64_t row = r0 + 16 * i + 4 * kq + r;
-                    if (row < M) y[row * D + col] = keep[i][r] * (acc[i][j][r] + bias);
+                    if (row < M) y[row * D + col] = keep[i][r] * (acc[i][j][r] + bias[j]);
                 }
             }
     }
