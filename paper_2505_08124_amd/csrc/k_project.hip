@@ -195,15 +195,30 @@ __global__ __launch_bounds__(256) void k_count(int64_t n, const ViewDev* __restr
     const int64_t g0 = (int64_t)blk * CPB + threadIdx.x;
     uint32_t* out = tcnt + (int64_t)vl * n;
     uint32_t nvis = 0, zmin = 0xFFFFFFFFu, zmax = 0;
-#pragma unroll 2
+    // the next Gaussian's inputs are loaded (clamped, unconditionally) while
+    // the current one is projected
+    float nc[6], nm[3];
+    auto load_in = [&](int i) {
+        const int64_t g = g0 + (int64_t)i * 256;
+        const int64_t gc = g < n ? g : n - 1;
+        load_cov(cov3, n, gc, nc);
+        nm[0] = means[3 * gc];
+        nm[1] = means[3 * gc + 1];
+        nm[2] = means[3 * gc + 2];
+    };
+    load_in(0);
+#pragma unroll 1
     for (int i = 0; i < PER_THREAD; i++) {
         const int64_t g = g0 + (int64_t)i * 256;
         if (g >= n) break;
         float S[6];
-        load_cov(cov3, n, g, S);
+#pragma unroll
+        for (int k = 0; k < 6; k++) S[k] = nc[k];
+        const float mx = nm[0], my = nm[1], mz = nm[2];
+        if (i + 1 < PER_THREAD) load_in(i + 1);
         Proj P;
         uint32_t tc = 0;
-        if (project(V, means[3 * g], means[3 * g + 1], means[3 * g + 2], S, P)) {
+        if (project(V, mx, my, mz, S, P)) {
             tc = tiles_of(P);
             nvis++;
             const uint32_t zb = __float_as_uint(P.z);
@@ -278,8 +293,28 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
     const int sw = V.ntx + 1;
     const uint32_t* S = sat + V.sat_off;
     unsigned long long n_isect = 0, n_part = 0;
+    // the next Gaussian's inputs are loaded (clamped, unconditionally) while
+    // the current one is projected and written
+    struct GIn {
+        float C[6], x, y, z, o;
+        uint32_t pg;
+    };
+    auto load_in = [&](int i, GIn& a) {
+        const int64_t g = g0 + (int64_t)i * 256;
+        const int64_t gc = g < n ? g : n - 1;
+        load_cov(cov3, n, gc, a.C);
+        a.x = means[3 * gc];
+        a.y = means[3 * gc + 1];
+        a.z = means[3 * gc + 2];
+        a.o = opac[gc];
+        a.pg = perm[gc];
+    };
+    GIn nx;
+    load_in(0, nx);
 #pragma unroll 1
     for (int i = 0; i < PER_THREAD; i++) {
+        const GIn cur = nx;
+        if (i + 1 < PER_THREAD) load_in(i + 1, nx);
         const int64_t g = g0 + (int64_t)i * 256;
         const uint64_t m = msk[wv][i];
         uint32_t before = 0;
@@ -291,17 +326,15 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
             pair_of_m[(int64_t)vl * n + g] = NONE;
             continue;
         }
-        float C[6];
-        load_cov(cov3, n, g, C);
         Proj P;
-        project(V, means[3 * g], means[3 * g + 1], means[3 * g + 2], C, P);
+        project(V, cur.x, cur.y, cur.z, cur.C, P);
         // compositing form: prescaled conic, log2 of the opacity
         rec[2 * (size_t)pidx] = make_float4(P.u, P.v, P.ca * NHALF_LOG2E, P.cb * NLOG2E);
         rec[2 * (size_t)pidx + 1] =
-            make_float4(P.cc * NHALF_LOG2E, __builtin_amdgcn_logf(opac[g]),
+            make_float4(P.cc * NHALF_LOG2E, __builtin_amdgcn_logf(cur.o),
                         __uint_as_float((uint32_t)P.x0 | ((uint32_t)P.y0 << 16)),
                         __uint_as_float((uint32_t)P.x1 | ((uint32_t)P.y1 << 16)));
-        pgauss[pidx] = perm[g];                      // the caller's index of the Gaussian
+        pgauss[pidx] = cur.pg;                       // the caller's index of the Gaussian
         pview[pidx] = (uint16_t)vl;
         const uint64_t dk = ((uint64_t)vl << zbits) | (uint64_t)(__float_as_uint(P.z) - zmin);
         if (pbits) {
