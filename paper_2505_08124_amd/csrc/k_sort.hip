@@ -385,8 +385,13 @@ __device__ __forceinline__ uint32_t pair_at_rank(const uint32_t* __restrict__ or
 
 // Four ranks per thread (strided by 256, coalesced): the four depth-order
 // loads, then the four rectangle gathers, each group in flight together
-// (clamped indices, so no branch separates them).
+// (clamped indices, so no branch separates them).  Workgroups go to the
+// eight XCDs round-robin; XCD x is given the x-th eighth of the ranks, in
+// order, so its gathers stay within about one view's records at a time
+// (a view's pairs are contiguous in depth order and their records fit its
+// L2), instead of every XCD touching every view.
 constexpr int RANK_ITEMS = 4;
+constexpr int NXCD = 8;
 
 __global__ __launch_bounds__(256) void k_rank_tiles(uint64_t npairs, const uint32_t* __restrict__ order,
                                                     const uint64_t* __restrict__ okey, uint64_t pmask,
@@ -394,7 +399,12 @@ __global__ __launch_bounds__(256) void k_rank_tiles(uint64_t npairs, const uint3
                                                     uint32_t* __restrict__ tcr,
                                                     uint2* __restrict__ prank)
 {
-    const uint64_t r0 = (uint64_t)blockIdx.x * (256 * RANK_ITEMS) + threadIdx.x;
+    // the grid is a multiple of NXCD blocks: b -> (b % NXCD) * per + b / NXCD
+    // is a permutation of [0, gridDim.x)
+    const uint32_t per = gridDim.x / NXCD;
+    const uint32_t lb = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+    const uint64_t r0 = (uint64_t)lb * (256 * RANK_ITEMS) + threadIdx.x;
+    if (r0 - threadIdx.x >= npairs) return;
     uint32_t p[RANK_ITEMS];
     if (okey) {
 #pragma unroll
@@ -865,8 +875,10 @@ void launch_rank_tiles(uint64_t npairs, const uint32_t* order, const uint64_t* o
 {
     if (!npairs) return;
     const uint64_t per = 256 * RANK_ITEMS;
-    hipLaunchKernelGGL(k_rank_tiles, dim3((unsigned)((npairs + per - 1) / per)), dim3(256), 0, st,
-                       npairs, order, okey, pmask, prect, tcr, prank);
+    const uint64_t nblk = (npairs + per - 1) / per;
+    const uint64_t grid = (nblk + NXCD - 1) / NXCD * NXCD;   // whole rounds over the XCDs
+    hipLaunchKernelGGL(k_rank_tiles, dim3((unsigned)grid), dim3(256), 0, st, npairs, order, okey,
+                       pmask, prect, tcr, prank);
 }
 
 void launch_emit_isect(uint64_t npairs, const uint32_t* order, const uint64_t* okey,
