@@ -123,6 +123,7 @@ constexpr int RADIX_ITEMS_MIN = 16;
 constexpr int RADIX_TILE_MIN = 256 * RADIX_ITEMS_MIN;
 constexpr int RADIX_MAXBITS = 8;
 constexpr uint64_t RADIX_LONG = 1ull << 25;
+constexpr int NXCD = 8;   // XCDs of the chip; workgroups are dealt to them round-robin
 template <typename K, int RB, int NV>
 constexpr int radix_items(bool long_sort)
 {
@@ -200,9 +201,16 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
     __shared__ K s_key[TILE_N];
     __shared__ uint32_t s_val[NV >= 1 ? TILE_N : 1];
     __shared__ uint32_t s_aux[NV >= 2 ? TILE_N : 1];
+    // XCD-aware block order: the grid is a multiple of NXCD blocks and XCD x
+    // (workgroups are dealt round-robin) takes logical blocks x * per ..
+    // (x + 1) * per - 1, so neighbouring blocks, whose digit runs meet in
+    // shared cache lines, write them through the same L2
+    const uint32_t per = gridDim.x / NXCD;
+    const uint32_t lb = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+    if (lb >= nblk) return;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint64_t bbase = (uint64_t)blockIdx.x * TILE_N;
+    const uint64_t bbase = (uint64_t)lb * TILE_N;
     const uint64_t base = bbase + (uint64_t)w * (ITEMS * 64);
     const int nvalid = (int)min((uint64_t)TILE_N, n - bbase);
     K key[ITEMS];
@@ -220,7 +228,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* __restrict__ kin
         if constexpr (NV >= 2) aux[it] = valid ? uin[idx] : 0u;
     }
     for (int i = threadIdx.x; i < 4 * R; i += 256) (&wcnt[0][0])[i] = 0;
-    for (int i = threadIdx.x; i < R; i += 256) dbase[i] = hist[(uint64_t)i * nblk + blockIdx.x];
+    for (int i = threadIdx.x; i < R; i += 256) dbase[i] = hist[(uint64_t)i * nblk + lb];
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < ITEMS; it++) {
@@ -316,7 +324,8 @@ void radix_pass_items(const K* ka, const uint32_t* va, const uint32_t* ua, K* kb
     hipLaunchKernelGGL((k_radix_hist<K, RB, ITEMS>), dim3((nblk + 3) / 4), dim3(256), 0, st, ka, n,
                        shift, hist, nblk);
     scan_u32(hist, (uint64_t)nblk << RB, nullptr, ws, st);
-    hipLaunchKernelGGL((k_radix_scatter<K, RB, NV, ITEMS>), dim3(nblk), dim3(256), 0, st, ka, va, ua,
+    const uint32_t grid = (nblk + NXCD - 1) / NXCD * NXCD;   // whole rounds over the XCDs
+    hipLaunchKernelGGL((k_radix_scatter<K, RB, NV, ITEMS>), dim3(grid), dim3(256), 0, st, ka, va, ua,
                        kb, vb, ub, n, shift, hist, nblk);
 }
 
@@ -391,7 +400,6 @@ __device__ __forceinline__ uint32_t pair_at_rank(const uint32_t* __restrict__ or
 // (a view's pairs are contiguous in depth order and their records fit its
 // L2), instead of every XCD touching every view.
 constexpr int RANK_ITEMS = 4;
-constexpr int NXCD = 8;
 
 __global__ __launch_bounds__(256) void k_rank_tiles(uint64_t npairs, const uint32_t* __restrict__ order,
                                                     const uint64_t* __restrict__ okey, uint64_t pmask,
