@@ -95,6 +95,8 @@ typedef struct {
     double ms_stage[16];            /* per stage, see slag_stage_name() */
     int32_t n_stages;
     int32_t reserved;
+    int64_t n_lost;                 /* part-list entries lost to a capacity error (0 by
+                                       construction; non-zero fails slag_get_embeddings) */
 } slag_stats;
 
 typedef struct slag_ctx slag_ctx;
@@ -139,9 +141,16 @@ slag_status slag_set_features(slag_ctx* ctx, int32_t d, slag_dtype dtype, const 
  * view batch in an eager lift, none in a graph replay). */
 slag_status slag_lift(slag_ctx* ctx);
 
-/* E_GAUSSIAN[N][d] (FP32) in input Gaussian order and, if `den` is not NULL,
- * the weight sums den[N] (FP32).  Synchronises the stream. */
-slag_status slag_get_embeddings(slag_ctx* ctx, float* out, float* den, slag_mem where);
+/* The lifted embeddings E_GAUSSIAN[N][d] (the aggregation equation's
+ * normalised sums, paper Method "Semantic Embedding"), in input Gaussian
+ * order: `out` (may be NULL) receives FP32 values (dtype SLAG_F32, 4 d bytes
+ * per row) or their bfloat16 roundings, nearest even (SLAG_BF16, 2 d bytes
+ * per row); `den` (may be NULL) receives the weight sums den[N] (FP32).  Rows
+ * with den = 0 are 0.  Both are `where`-resident and caller-owned.
+ * Synchronises the stream.  Fails with SLAG_E_CAPACITY (and the result must
+ * not be used) if the last lift lost weights to a capacity error. */
+slag_status slag_get_embeddings(slag_ctx* ctx, void* out, slag_dtype dtype, float* den,
+                                slag_mem where);
 
 slag_status slag_get_stats(slag_ctx* ctx, slag_stats* stats);
 const char* slag_stage_name(int32_t stage);
@@ -170,6 +179,38 @@ slag_status slag_debug_tile_lists(slag_ctx* ctx, int32_t view, uint32_t* tile,
  * may repeat across the tiles of one Gaussian).  Host arrays. */
 slag_status slag_debug_weights(slag_ctx* ctx, int32_t view, uint32_t* gauss, uint32_t* seg,
                                float* w, int64_t cap, int64_t* len);
+
+/* Debug exports of the last lift (SLAG_FLAG_KEEP_DEBUG; the view must be in
+ * the last view batch).  `out` is a host buffer of `cap` bytes; *len receives
+ * the byte size of the export (also when it exceeds cap: then nothing is
+ * written).  Layouts (little-endian, row-major):
+ *   SLAG_DEBUG_KEYS          uint32 [entries][3]: (tile, FP32 depth bits, caller's Gaussian
+ *                            index) of the view's tile lists, ordered by (tile, depth,
+ *                            Gaussian); tile = ty * ceil(W / 16) + tx
+ *   SLAG_DEBUG_TILE_RANGES   uint32 [tiles][2]: [start, end) of each tile's rows in KEYS
+ *   SLAG_DEBUG_W_VIEW        uint32 [entries][3]: (Gaussian, view-local segment, FP32 weight
+ *                            bits), one per (Gaussian, tile, segment) with non-zero masked
+ *                            weight (the per-view sums of the aggregation equation, by tile)
+ *   SLAG_DEBUG_PIXEL_T_FINAL float [H][W]: transmittance after each pixel's front-to-back walk
+ *   SLAG_DEBUG_PIXEL_WSUM    float [H][W]: sum of the pixel's accepted blend weights (all
+ *                            pixels, masked or not); front-to-back compositing telescopes, so
+ *                            WSUM = 1 - T_FINAL up to rounding
+ *   SLAG_DEBUG_PIXEL_COUNT   uint32 [H][W]: accepted blends of the pixel
+ *   SLAG_DEBUG_COUNTERS      int64 [4]: accepted blends, in-box tests, tile-list tests, lost
+ *                            part-list entries (view ignored)
+ * The PIXEL_* exports need a lift with SLAG_FLAG_COUNT as well (the counting pass walks every
+ * pixel, background included); else SLAG_E_STATE. */
+typedef enum {
+    SLAG_DEBUG_KEYS = 0,
+    SLAG_DEBUG_TILE_RANGES = 1,
+    SLAG_DEBUG_W_VIEW = 2,
+    SLAG_DEBUG_PIXEL_T_FINAL = 3,
+    SLAG_DEBUG_PIXEL_WSUM = 4,
+    SLAG_DEBUG_PIXEL_COUNT = 5,
+    SLAG_DEBUG_COUNTERS = 6
+} slag_debug;
+slag_status slag_get_debug(slag_ctx* ctx, slag_debug what, int32_t view, void* out, int64_t cap,
+                           int64_t* len);
 
 #ifdef __cplusplus
 }

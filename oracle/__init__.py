@@ -57,8 +57,8 @@ def _lib():
         P = ctypes.c_void_p
         L.orc_lift_view.restype = P
         L.orc_lift_view.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32,
-                                    P, P, ctypes.POINTER(_Counts), ctypes.POINTER(ctypes.c_int64)]
-        L.orc_view_fetch.argtypes = [P, P, P, P, P]
+                                    P, P, P, ctypes.POINTER(_Counts), ctypes.POINTER(ctypes.c_int64)]
+        L.orc_view_fetch.argtypes = [P, P, P, P, P, P]
         L.orc_view_free.argtypes = [P]
         L.orc_mirror_view.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, P, P]
         L.orc_project64_view.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, P, P]
@@ -84,31 +84,39 @@ class ViewResult:
     g: np.ndarray          # int32 Gaussian index
     s: np.ndarray          # int32 view-local segment id
     w: np.ndarray          # float64 W_v[g, s]
-    u: np.ndarray          # float64 decision-margin mass for the triple
+    u: np.ndarray          # float64 decision mass for the triple (flips within the error bound)
+    r: np.ndarray          # float64 rounding mass: bound on an FP32 walk's deviation from w
     n_contrib: int         # accepted blends (all pixels)
     n_tests: int           # box-candidate evaluations before termination
     n_visible: int
-    n_uncertain: int
+    n_uncertain: int       # decisions that lay inside their error band
     T: Optional[np.ndarray] = None      # [H, W] final transmittance
     wsum: Optional[np.ndarray] = None   # [H, W] sum of blend weights
+    rho: Optional[np.ndarray] = None    # [H, W] bound on T's relative FP32 error (-1: a decision
+                                        # of the pixel lay inside its band)
 
 
 def lift_view(scene, v: int, mode: str = "box", pixels: bool = False,
-              nthreads: int = 0) -> ViewResult:
-    """W_v for one view (paper: rasterize, mask, sum over the view's pixels)."""
+              nthreads: int = 0, fp32: bool = False) -> ViewResult:
+    """W_v for one view (paper: rasterize, mask, sum over the view's pixels).
+
+    fp32=True runs the FP32 re-walk of the same per-pixel lists (test
+    infrastructure for the error model; its r and u are zero)."""
     L = _lib()
     cam = np.ascontiguousarray(scene.cams[v:v + 1])
     ids = _c(scene.ids[v], np.int32)
     H, W = ids.shape
     T = np.empty((H, W), np.float64) if pixels else None
     ws = np.empty((H, W), np.float64) if pixels else None
+    rho = np.empty((H, W), np.float64) if pixels else None
     cnt = _Counts()
     nt = ctypes.c_int64(0)
     means, scales = _c(scene.means, np.float32), _c(scene.scales, np.float32)
     quats, opac = _c(scene.quats, np.float32), _c(scene.opacity, np.float32)
+    m = (0 if mode == "brute" else 1) | (2 if fp32 else 0)
     h = L.orc_lift_view(scene.n, _p(means), _p(scales), _p(quats), _p(opac), _p(cam), _p(ids),
-                        0 if mode == "brute" else 1, int(nthreads), _p(T), _p(ws),
-                        ctypes.byref(cnt), ctypes.byref(nt))
+                        m, int(nthreads), _p(T), _p(ws), _p(rho), ctypes.byref(cnt),
+                        ctypes.byref(nt))
     if not h:
         raise MemoryError("oracle view lift failed")
     k = nt.value
@@ -116,9 +124,11 @@ def lift_view(scene, v: int, mode: str = "box", pixels: bool = False,
     s = np.empty(k, np.int32)
     w = np.empty(k, np.float64)
     u = np.empty(k, np.float64)
-    L.orc_view_fetch(h, _p(g), _p(s), _p(w), _p(u))
+    r = np.empty(k, np.float64)
+    L.orc_view_fetch(h, _p(g), _p(s), _p(w), _p(u), _p(r))
     L.orc_view_free(h)
-    return ViewResult(g, s, w, u, cnt.n_contrib, cnt.n_tests, cnt.n_visible, cnt.n_uncertain, T, ws)
+    return ViewResult(g, s, w, u, r, cnt.n_contrib, cnt.n_tests, cnt.n_visible, cnt.n_uncertain,
+                      T, ws, rho)
 
 
 @dataclasses.dataclass
@@ -126,20 +136,23 @@ class LiftResult:
     num: np.ndarray        # [N, D] float64
     den: np.ndarray        # [N] float64
     E: np.ndarray          # [N, D] float64, 0 where den == 0
-    U: np.ndarray          # [N] float64 decision-margin mass per Gaussian
+    U: np.ndarray          # [N] float64 decision mass per Gaussian
+    R: np.ndarray          # [N] float64 rounding mass per Gaussian
+    B: np.ndarray          # [N] float64 bound on |W| deviations (rounding + decisions + sums)
+    nnz: np.ndarray        # [N] int64 (view, segment) terms per Gaussian
     views: List[ViewResult]
     n_contrib: int
     n_tests: int
 
 
-def weight_matrix(scene, views: List[int], results: List[ViewResult], with_u: bool = False):
+def weight_matrix(scene, views: List[int], results: List[ViewResult], field: str = "w"):
     """Stack the per-view triples into one sparse [N, S_total] matrix."""
     off = scene.seg_offsets
     rows, cols, vals = [], [], []
     for v, r in zip(views, results):
         rows.append(r.g.astype(np.int64))
         cols.append(off[v] + r.s.astype(np.int64))
-        vals.append(r.u if with_u else r.w)
+        vals.append(getattr(r, field) if field != "bound" else weight_bound(r.w, r.u, r.r))
     if rows:
         rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
     else:
@@ -148,22 +161,61 @@ def weight_matrix(scene, views: List[int], results: List[ViewResult], with_u: bo
     return sp.csr_matrix((vals, (rows, cols)), shape=(scene.n, int(off[-1])))
 
 
+# Summation in the GPU path: a (pair, tile, segment) sum adds up to 256 pixel
+# weights through a 6-level wave tree and 3 cross-wave adds in FP32 (at most
+# 9 roundings of the running sum), and is accumulated in fixed point with 2^-40
+# truncation per entry (at most 2^10 tile entries per triple).
+SUM_REL = 16 * 2.0 ** -24
+SUM_ABS = 2.0 ** -30
+
+
+def weight_bound(w, u, r):
+    """Bound on |W_fp32 - W_fp64| for one triple: rounding mass, decision mass
+    (with its own rounding) and the summation of the per-pixel weights."""
+    return r + u * (1.0 + 2.0 ** -20) + SUM_REL * w + SUM_ABS
+
+
 def lift(scene, views: Optional[List[int]] = None, mode: str = "box",
          nthreads: int = 0, pixels: bool = False) -> LiftResult:
     """The lifted embeddings of the aggregation equation, in FP64."""
     views = list(range(scene.n_views)) if views is None else [int(v) for v in views]
     res = [lift_view(scene, v, mode=mode, nthreads=nthreads, pixels=pixels) for v in views]
     Wm = weight_matrix(scene, views, res)
-    Um = weight_matrix(scene, views, res, with_u=True)
     F = scene.feats_f64()
     num = np.asarray(Wm @ F)
     den = np.asarray(Wm.sum(axis=1)).ravel()
     E = np.zeros_like(num)
     nz = den > 0
     E[nz] = num[nz] / den[nz, None]
-    U = np.asarray(Um.sum(axis=1)).ravel()
-    return LiftResult(num, den, E, U, res, sum(r.n_contrib for r in res),
+    U = np.asarray(weight_matrix(scene, views, res, "u").sum(axis=1)).ravel()
+    R = np.asarray(weight_matrix(scene, views, res, "r").sum(axis=1)).ravel()
+    Bm = weight_matrix(scene, views, res, "bound")
+    B = np.asarray(Bm.sum(axis=1)).ravel()
+    nnz = np.diff(Bm.indptr).astype(np.int64)
+    return LiftResult(num, den, E, U, R, B, nnz, res, sum(r.n_contrib for r in res),
                       sum(r.n_tests for r in res))
+
+
+def embedding_bound(ref: LiftResult, fmax: float, n_views: int, bf16_split: bool = True):
+    """Per-Gaussian bound on ||E_fp32 - E_fp64||_2 (0 where den = 0), and the
+    mask of Gaussians whose weight could vanish (den <= B).
+
+    With W perturbed by dW (|dW_s| <= b_s, sum b_s = B): E' - E =
+    sum_s dW_s (F_s - E) / (den + sum dW), so ||E' - E|| <= 2 fmax B / (den - B).
+    The contraction adds the hi/lo split of W (2^-18 relative), FP32
+    accumulation of the products (at most nnz + 64 roundings of partial sums
+    bounded by fmax den) and the per-view FP32 sums of den (n_views
+    roundings); the division adds one rounding."""
+    u = 2.0 ** -24
+    den, B = ref.den, ref.B
+    ok = den > B
+    out = np.zeros_like(den)
+    split = 2.0 ** -18 if bf16_split else 0.0
+    d = np.where(ok, den - B, 1.0)
+    e_w = 2.0 * fmax * B / d
+    e_c = fmax * (split + (ref.nnz + 64 + n_views) * u) * den / d
+    out[ok] = (e_w + e_c)[ok] + u * np.linalg.norm(ref.E[ok], axis=1)
+    return out, ~ok & (den > 0)
 
 
 # ----------------------------------------------------------------------------

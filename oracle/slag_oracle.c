@@ -35,11 +35,26 @@
  * other contraction; build with -ffp-contract=off).  Everything that weighs a
  * contribution is FP64.
  *
- * Decision margins.  An FP32 evaluation can flip a threshold decision that
- * lies within rounding of its threshold.  For every such decision this file
- * records an uncertainty mass U[g,s] that bounds how much W[g,s] could move
- * because of it (see composite_pixel).  With U = 0 a triple must match
- * exactly in membership.
+ * Error model and decision margins.  The weights are exact (FP64) here; an
+ * FP32 evaluation of the same walk deviates from them in two ways, and this
+ * file bounds both, per (Gaussian, segment) triple, from the FP64 values:
+ *   - rounding mass r: to first order, the relative error of an FP32 weight
+ *     w = alpha T is at most eps_alpha + rho_T + 2^-24, where eps_alpha
+ *     bounds the relative error of alpha (alpha_eps below: the exponent is
+ *     a quadratic in the pixel offset, evaluated in FP32 from FP32-rounded
+ *     coefficients as an expansion about a point within 3.5 px of the pixel
+ *     in each axis; every rounding is counted with the magnitude of the
+ *     value it rounds; exp2 adds 2 ulp) and rho_T bounds the relative error
+ *     of the transmittance, which grows by eps_alpha alpha / (1 - alpha) +
+ *     2^-24 per blend (alpha clamped at 0.99 on both sides carries no error);
+ *   - decision mass U: a threshold decision (alpha against 1/255, T' against
+ *     1e-4) whose FP64 operand lies within that error bound of the threshold
+ *     may go the other way in FP32; U bounds how much W could move because
+ *     of it (see composite_pixel).  With U = 0 a triple must match exactly
+ *     in membership.
+ * Both bounds are derived from the operation sequence, not fitted to any
+ * observed error; a test re-walks the same per-pixel lists in FP32
+ * (orc_lift_view_f32) and checks that it stays inside them.
  */
 #include <math.h>
 #include <stdint.h>
@@ -75,9 +90,12 @@ typedef struct {
 #define D_TMIN 1e-4
 #define D_DIL 0.3
 #define D_CLAMP 1.3
-/* relative half-widths of the bands in which an FP32 decision may differ */
-#define EPS_ALPHA 1e-3
-#define EPS_T 1e-3
+#define D_L2E 1.4426950408889634074      /* log2(e) */
+#define D_LN2 0.69314718055994530942
+#define U32 0x1p-24                          /* unit roundoff of FP32 */
+/* FP32 thresholds differ from the FP64 ones by at most this relative amount
+ * ((float)(1/255) and 1e-4f are rounded) */
+#define CONST_REL 0x1p-23
 
 /* ========================================================================
  * FP32 mirror: camera depth, culling and the conservative pixel box.
@@ -176,6 +194,7 @@ typedef struct {
     double conic[3];    /* Sigma2^{-1}: xx, xy, yy */
     double zc;          /* camera-space depth */
     double o;
+    double lo2;         /* log2(o) */
 } proj64;
 
 static void project64(const float* mf, const float* sf, const float* qf, float opac,
@@ -248,15 +267,16 @@ static void project64(const float* mf, const float* sf, const float* qf, float o
     p->mu[1] = c->fy * tyz + c->cy;
     p->zc = Z;
     p->o = opac;
+    p->lo2 = log2((double)opac);
 }
 
 /* ========================================================================
  * growable arrays and a (g,s) -> (W,U) hash map
  * ====================================================================== */
-typedef struct { int32_t g, s; double w, u; } contrib;
+typedef struct { int32_t g, s; double w, u, r; } contrib;
 typedef struct { contrib* a; int64_t n, cap; } cbuf;
 
-static int cbuf_push(cbuf* b, int32_t g, int32_t s, double w, double u)
+static int cbuf_push(cbuf* b, int32_t g, int32_t s, double w, double u, double r)
 {
     if (b->n == b->cap) {
         int64_t nc = b->cap ? 2 * b->cap : 256;
@@ -265,11 +285,12 @@ static int cbuf_push(cbuf* b, int32_t g, int32_t s, double w, double u)
         b->a = na; b->cap = nc;
     }
     b->a[b->n].g = g; b->a[b->n].s = s; b->a[b->n].w = w; b->a[b->n].u = u;
+    b->a[b->n].r = r;
     b->n++;
     return 0;
 }
 
-typedef struct { uint64_t* key; double* w; double* u; int64_t cap, n; } hmap;
+typedef struct { uint64_t* key; double* w; double* u; double* r; int64_t cap, n; } hmap;
 #define HEMPTY 0xFFFFFFFFFFFFFFFFull
 
 static int hmap_init(hmap* h, int64_t cap)
@@ -279,13 +300,14 @@ static int hmap_init(hmap* h, int64_t cap)
     h->key = (uint64_t*)malloc((size_t)c * 8);
     h->w = (double*)calloc((size_t)c, 8);
     h->u = (double*)calloc((size_t)c, 8);
-    if (!h->key || !h->w || !h->u) return -1;
+    h->r = (double*)calloc((size_t)c, 8);
+    if (!h->key || !h->w || !h->u || !h->r) return -1;
     memset(h->key, 0xFF, (size_t)c * 8);
     h->cap = c; h->n = 0;
     return 0;
 }
 
-static void hmap_free(hmap* h) { free(h->key); free(h->w); free(h->u); }
+static void hmap_free(hmap* h) { free(h->key); free(h->w); free(h->u); free(h->r); }
 
 static int64_t hslot(const hmap* h, uint64_t k)
 {
@@ -295,7 +317,7 @@ static int64_t hslot(const hmap* h, uint64_t k)
     return i;
 }
 
-static int hmap_add(hmap* h, uint64_t k, double w, double u)
+static int hmap_add(hmap* h, uint64_t k, double w, double u, double r)
 {
     if (2 * (h->n + 1) > h->cap) {
         hmap nh;
@@ -303,7 +325,8 @@ static int hmap_add(hmap* h, uint64_t k, double w, double u)
         for (int64_t i = 0; i < h->cap; i++)
             if (h->key[i] != HEMPTY) {
                 int64_t j = hslot(&nh, h->key[i]);
-                nh.key[j] = h->key[i]; nh.w[j] = h->w[i]; nh.u[j] = h->u[i]; nh.n++;
+                nh.key[j] = h->key[i]; nh.w[j] = h->w[i]; nh.u[j] = h->u[i];
+                nh.r[j] = h->r[i]; nh.n++;
             }
         hmap_free(h);
         *h = nh;
@@ -312,6 +335,7 @@ static int hmap_add(hmap* h, uint64_t k, double w, double u)
     if (h->key[i] == HEMPTY) { h->key[i] = k; h->n++; }
     h->w[i] += w;
     h->u[i] += u;
+    h->r[i] += r;
     return 0;
 }
 
@@ -323,84 +347,193 @@ typedef struct {
     const mirror_out* Mi;
 } view_ctx;
 
-static inline double alpha_at(const proj64* p, double px, double py)
+/* alpha = min(0.99, o exp(-q/2)) with q = d^T Sigma2^{-1} d; also returns
+ * the unclamped value */
+static inline double alpha_at(const proj64* p, double px, double py, double* unclamped)
 {
     double dx = px - p->mu[0], dy = py - p->mu[1];
     double q = p->conic[0] * dx * dx + 2.0 * p->conic[1] * dx * dy + p->conic[2] * dy * dy;
     if (q < 0.0) q = 0.0;
     double a = p->o * exp(-0.5 * q);
+    if (unclamped) *unclamped = a;
     return a < D_AMAX ? a : D_AMAX;
 }
 
 /*
- * Walk the depth-ordered candidates of one pixel.  Emits (g, s, w, u) for
+ * Bound on the relative error of an FP32 alpha at pixel centre (px, py).
+ * The FP32 exponent is e = log2(o) + A dx^2 + B dx dy + C dy^2 with
+ * A = -log2(e) conic_xx / 2, B = -log2(e) conic_xy, C = -log2(e) conic_yy / 2
+ * and (dx, dy) the offset of the pixel from the mean, evaluated from FP32
+ * roundings of A, B, C, log2(o) and of the mean's offset from the box corner
+ * (x0, y0), as a quadratic expanded about a point within L = 3.5 px of the
+ * pixel in each axis:  c0 + lx (cx + A lx + B ly) + ly (cy + C ly), with c0,
+ * cx, cy the value and gradient at the expansion point (three FMA chains).
+ * Magnitudes (a, b, c = |A|, |B|, |C|; U, V bound the expansion point's
+ * offset from the mean; X, Y its gradient; M0 its value):
+ *   coefficient rounding         u (a dx^2 + b |dx dy| + c dy^2 + |log2 o|)
+ *   mean-offset rounding         u (2a|dx| + b|dy|)(|u - x0| + U) + (same in y)
+ *   value and gradient at the
+ *   expansion point (5 + 2 ops)  <= 7 u M0
+ *   per-pixel chains             <= 6 u L (X + Y) + 4 u L^2 (a + b + c)
+ * (each rounding bounded by u = 2^-24 times the magnitude it rounds,
+ * propagated through the multiplications by lx, ly, |lx|, |ly| <= L).
+ * alpha = 2^e then has relative error ln 2 |de| + 2^-22 (exp2: 2 ulp).
+ */
+static double alpha_eps(const proj64* p, const mirror_out* mo, double px, double py)
+{
+    const double a = 0.5 * D_L2E * fabs(p->conic[0]);
+    const double b = D_L2E * fabs(p->conic[1]);
+    const double c = 0.5 * D_L2E * fabs(p->conic[2]);
+    const double lo2 = fabs(p->lo2);
+    const double dx = fabs(px - p->mu[0]), dy = fabs(py - p->mu[1]);
+    const double L = 3.5, U = dx + L, V = dy + L;
+    const double Mpix = a * dx * dx + b * dx * dy + c * dy * dy + lo2;
+    const double M0 = a * U * U + b * U * V + c * V * V + lo2;
+    const double X = 2.0 * a * U + b * V, Y = b * U + 2.0 * c * V;
+    const double ur = fabs(p->mu[0] - (double)mo->x0), vr = fabs(p->mu[1] - (double)mo->y0);
+    const double G = (2.0 * a * dx + b * dy) * (ur + U) + (b * dx + 2.0 * c * dy) * (vr + V);
+    const double de = U32 * (Mpix + 7.0 * M0 + 6.0 * L * (X + Y) + 4.0 * L * L * (a + b + c) + G);
+    return D_LN2 * de * (1.0 + 1e-6) + 0x1p-22;
+}
+
+/*
+ * Walk the depth-ordered candidates of one pixel.  Emits (g, s, w, u, r) for
  * accepted blends when the pixel has a segment (s >= 0).
  *
- * u bounds how far an FP32 walk could move this contribution:
- *  - a blend with alpha within EPS_ALPHA of 1/255 may be skipped (u = w),
- *    and one just below may be taken (a zero-weight entry with u = alpha T);
- *    either flip scales the transmittance seen by everything behind it by
- *    about (1 - alpha), so later blends get u += w * delta, delta += alpha;
- *  - a stop decision with T' within (EPS_T + delta) of 1e-4 may go the
+ * rho is the bound on the FP32 transmittance's relative error (given the
+ * same decisions so far); eps that of alpha (alpha_eps, plus the rounding of
+ * the FP32 threshold constants).  r = w (eps + rho + 2^-24) bounds the
+ * rounding of the weight.  u bounds how far a flipped decision could move a
+ * contribution:
+ *  - alpha with alpha (1 - eps) < 1/255 <= alpha may be skipped (u = w), and
+ *    one with alpha < 1/255 <= alpha (1 + eps) may be taken (a zero-weight
+ *    entry with u = its possible weight); either flip scales the
+ *    transmittance seen by everything behind it by (1 - alpha), so later
+ *    blends get u += w delta with delta += alpha / (1 - alpha);
+ *  - a stop decision with |T' - 1e-4| within (rho' + delta) of T' may go the
  *    other way: if the walk continues here, this and every later blend may
  *    vanish (u = w, delta = 1); if it stops here, this Gaussian and the next
  *    acceptable one may still be blended (entries with u = their weights).
+ * Returns the final T, the sum of weights, the final rho, and whether any
+ * decision of the pixel lay inside its band.
  */
 static int composite_pixel(const view_ctx* vc, const int32_t* cand, int64_t nc,
                            int ix, int iy, int32_t seg, cbuf* out,
-                           double* T_out, double* wsum_out, int64_t* n_c, int64_t* n_q,
-                           int64_t* n_unc, int count_box_only)
+                           double* T_out, double* wsum_out, double* rho_out, int* near_out,
+                           int64_t* n_c, int64_t* n_q, int64_t* n_unc, int count_box_only)
 {
     const double px = ix + 0.5, py = iy + 0.5;
-    double T = 1.0, delta = 0.0, sumw = 0.0;
+    double T = 1.0, rho = 0.0, delta = 0.0, sumw = 0.0;
+    int any_near = 0;
     for (int64_t k = 0; k < nc; k++) {
         const int32_t g = cand[k];
         const proj64* p = &vc->P[g];
         const mirror_out* mo = &vc->Mi[g];
         if (!count_box_only || (mo->vis && ix >= mo->x0 && ix <= mo->x1 && iy >= mo->y0 && iy <= mo->y1))
             (*n_q)++;
-        double alpha = alpha_at(p, px, py);
-        /* upstream flips change T here by a relative amount of at most delta
-         * (to first order), so a flipped decision here moves at most
-         * alpha T (1 + delta) */
-        const double grow = 1.0 + (delta < 1.0 ? delta : 1.0);
+        double au;
+        const double alpha = alpha_at(p, px, py, &au);
+        const double eps = alpha_eps(p, mo, px, py) + CONST_REL;
+        /* both sides clamp at 0.99 when even the lower FP32 value exceeds it */
+        const double ea = (au * (1.0 - eps) >= D_AMAX) ? 0.0 : eps;
+        const double dl = delta < 1.0 ? delta : 1.0;
+        const double grow = 1.0 + dl;
         if (alpha < D_AMIN) {
-            if (alpha >= D_AMIN * (1.0 - EPS_ALPHA)) {
+            if (alpha * (1.0 + eps) >= D_AMIN) {
                 (*n_unc)++;
-                if (seg >= 0 && cbuf_push(out, g, seg, 0.0, alpha * T * grow)) return -1;
-                delta += alpha;
+                any_near = 1;
+                if (seg >= 0 && cbuf_push(out, g, seg, 0.0, alpha * T * grow * (1.0 + eps + rho), 0.0))
+                    return -1;
+                delta += alpha / (1.0 - alpha);
             }
             continue;
         }
-        int near_a = alpha < D_AMIN * (1.0 + EPS_ALPHA);
-        double Tn = T * (1.0 - alpha);
-        double band = (EPS_T + delta) * D_TMIN;
-        int near_t = fabs(Tn - D_TMIN) <= band;
-        if (near_a || near_t) (*n_unc)++;
+        const int near_a = alpha * (1.0 - eps) < D_AMIN;
+        const double Tn = T * (1.0 - alpha);
+        const double rho_n = rho + ea * alpha / (1.0 - alpha) + U32;
+        const double band = (rho_n + CONST_REL + dl) * (Tn > D_TMIN ? Tn : D_TMIN);
+        const int near_t = fabs(Tn - D_TMIN) <= band;
+        if (near_a || near_t) { (*n_unc)++; any_near = 1; }
         if (Tn < D_TMIN) {
             if (near_t && seg >= 0) {
-                if (cbuf_push(out, g, seg, 0.0, alpha * T * grow)) return -1;
+                if (cbuf_push(out, g, seg, 0.0, alpha * T * grow * (1.0 + ea + rho), 0.0)) return -1;
                 for (int64_t h = k + 1; h < nc; h++) {
-                    double ah = alpha_at(&vc->P[cand[h]], px, py);
-                    if (ah >= D_AMIN * (1.0 - EPS_ALPHA)) {
-                        if (cbuf_push(out, cand[h], seg, 0.0, ah * Tn * grow)) return -1;
+                    const proj64* ph = &vc->P[cand[h]];
+                    const double ah = alpha_at(ph, px, py, NULL);
+                    const double eh = alpha_eps(ph, &vc->Mi[cand[h]], px, py) + CONST_REL;
+                    if (ah * (1.0 + eh) >= D_AMIN) {
+                        if (cbuf_push(out, cand[h], seg, 0.0, ah * Tn * grow * (1.0 + eh + rho_n), 0.0))
+                            return -1;
                         break;
                     }
                 }
             }
             break;
         }
-        double w = alpha * T;
-        double u = w * (delta < 1.0 ? delta : 1.0);
+        const double w = alpha * T;
+        const double r = w * (ea + rho + U32);
+        double u = w * dl;
         if (near_a) u = w * grow;
         if (near_t) { u = w * grow; delta = 1.0; }
         (*n_c)++;
         sumw += w;
-        if (seg >= 0 && cbuf_push(out, g, seg, w, u)) return -1;
-        if (near_a) delta += alpha;
+        if (seg >= 0 && cbuf_push(out, g, seg, w, u, r)) return -1;
+        if (near_a) delta += alpha / (1.0 - alpha);
         T = Tn;
+        rho = rho_n;
     }
     *T_out = T;
+    *wsum_out = sumw;
+    *rho_out = rho;
+    *near_out = any_near;
+    return 0;
+}
+
+/*
+ * The same per-pixel walk in FP32, evaluated the way a tile rasterizer with
+ * 8x8-pixel wave blocks does it: the exponent is expanded about the centre of
+ * the pixel's aligned 8x8 block (lx, ly in -3.5 .. 3.5), from coefficients
+ * rounded to FP32 once per Gaussian (the mean as an offset from the box
+ * corner).  Test infrastructure for the error model above: its weights must
+ * stay within r + U of the FP64 walk's.  Decisions are taken in FP32.
+ */
+static int composite_pixel_f32(const view_ctx* vc, const int32_t* cand, int64_t nc,
+                               int ix, int iy, int32_t seg, cbuf* out, double* T_out,
+                               double* wsum_out)
+{
+    const float AMIN_F = 1.0f / 255.0f, AMAX_F = 0.99f, TMIN_F = 1e-4f;
+    const int bx0 = ix & ~7, by0 = iy & ~7;
+    const float lx = (float)(ix & 7) - 3.5f, ly = (float)(iy & 7) - 3.5f;
+    float T = 1.0f;
+    double sumw = 0.0;
+    for (int64_t k = 0; k < nc; k++) {
+        const int32_t g = cand[k];
+        const proj64* p = &vc->P[g];
+        const mirror_out* mo = &vc->Mi[g];
+        const float A = (float)(-0.5 * D_L2E * p->conic[0]);
+        const float B = (float)(-D_L2E * p->conic[1]);
+        const float C = (float)(-0.5 * D_L2E * p->conic[2]);
+        const float lo2 = (float)p->lo2;
+        const float urel = (float)(p->mu[0] - (double)mo->x0);
+        const float vrel = (float)(p->mu[1] - (double)mo->y0);
+        const float du = urel + (float)(mo->x0 - bx0 - 4);   /* mean minus block centre */
+        const float dv = vrel + (float)(mo->y0 - by0 - 4);
+        const float cx = -fmaf(2.0f * A, du, B * dv);
+        const float cy = -fmaf(B, du, 2.0f * C * dv);
+        const float c0 = fmaf(A * du, du, fmaf(B * du, dv, C * dv * dv)) + lo2;
+        const float tx = fmaf(B, ly, fmaf(A, lx, cx));
+        const float ty = fmaf(C, ly, cy);
+        const float e = fmaf(ty, ly, fmaf(tx, lx, c0));
+        const float alpha = fminf(AMAX_F, exp2f(e));
+        if (!(alpha >= AMIN_F)) continue;
+        const float Tn = fmaf(-alpha, T, T);
+        if (Tn < TMIN_F) break;
+        const float w = alpha * T;
+        sumw += (double)w;
+        if (seg >= 0 && cbuf_push(out, g, seg, (double)w, 0.0, 0.0)) return -1;
+        T = Tn;
+    }
+    *T_out = (double)T;
     *wsum_out = sumw;
     return 0;
 }
@@ -454,6 +587,7 @@ typedef struct {
     int32_t* s;
     double* w;
     double* u;
+    double* r;
 } view_result;
 
 static int cmp_u64(const void* a, const void* b)
@@ -463,16 +597,21 @@ static int cmp_u64(const void* a, const void* b)
 }
 
 /*
- * Lift one view.  mode 0 = brute (every Gaussian in front of the camera is a
- * candidate of every pixel), mode 1 = box (only Gaussians whose conservative
- * pixel box contains the pixel).  Both walk candidates in the same depth
- * order, so the two must agree bit for bit.
+ * Lift one view.  mode bit 0: 0 = brute (every Gaussian in front of the
+ * camera is a candidate of every pixel), 1 = box (only Gaussians whose
+ * conservative pixel box contains the pixel).  Both walk candidates in the
+ * same depth order, so the two must agree bit for bit.  Mode bit 1 selects the
+ * FP32 walk (composite_pixel_f32; box candidates only, no margins or counts).
+ * pix_rho (optional) receives the final T's relative error bound, or -1 at
+ * pixels where some decision lay inside its band.
  */
 void* orc_lift_view(int64_t n, const float* means, const float* scales, const float* quats,
                     const float* opacity, const orc_camera* cam, const int32_t* ids,
                     int32_t mode, int32_t nthreads, double* pix_T, double* pix_wsum,
-                    orc_counts* counts, int64_t* n_triples)
+                    double* pix_rho, orc_counts* counts, int64_t* n_triples)
 {
+    const int f32 = (mode & 2) != 0;
+    mode &= 1;
     const int W = cam->width, H = cam->height;
     proj64* P = (proj64*)malloc((size_t)(n ? n : 1) * sizeof(proj64));
     mirror_out* Mi = (mirror_out*)malloc((size_t)(n ? n : 1) * sizeof(mirror_out));
@@ -552,11 +691,14 @@ void* orc_lift_view(int64_t n, const float* means, const float* scales, const fl
                     sort_depth(cand + start[pi], ncand, z, tmp);
                     c = cand + start[pi];
                 }
-                double Tf = 1.0, ws = 0.0;
-                if (composite_pixel(&vc, c, ncand, x, y, seg, &rows[y], &Tf, &ws,
-                                    &nc_tot, &nq_tot, &nu_tot, mode == 0))
-                    failed = 1;
+                double Tf = 1.0, ws = 0.0, rf = 0.0;
+                int nr = 0;
+                const int bad = f32 ? composite_pixel_f32(&vc, c, ncand, x, y, seg, &rows[y], &Tf, &ws)
+                                    : composite_pixel(&vc, c, ncand, x, y, seg, &rows[y], &Tf, &ws,
+                                                      &rf, &nr, &nc_tot, &nq_tot, &nu_tot, mode == 0);
+                if (bad) failed = 1;
                 if (pix_T) pix_T[pi] = Tf;
+                if (pix_rho) pix_rho[pi] = nr ? -1.0 : rf;
                 if (pix_wsum) pix_wsum[pi] = ws;
             }
         }
@@ -571,7 +713,8 @@ void* orc_lift_view(int64_t n, const float* means, const float* scales, const fl
     for (int y = 0; y < H; y++) {
         for (int64_t i = 0; i < rows[y].n; i++) {
             const contrib* e = &rows[y].a[i];
-            if (hmap_add(&hm, ((uint64_t)(uint32_t)e->g << 32) | (uint32_t)e->s, e->w, e->u)) return NULL;
+            if (hmap_add(&hm, ((uint64_t)(uint32_t)e->g << 32) | (uint32_t)e->s, e->w, e->u, e->r))
+                return NULL;
         }
         free(rows[y].a);
     }
@@ -588,12 +731,14 @@ void* orc_lift_view(int64_t n, const float* means, const float* scales, const fl
     vr->s = (int32_t*)malloc((size_t)(k ? k : 1) * 4);
     vr->w = (double*)malloc((size_t)(k ? k : 1) * 8);
     vr->u = (double*)malloc((size_t)(k ? k : 1) * 8);
+    vr->r = (double*)malloc((size_t)(k ? k : 1) * 8);
     for (int64_t i = 0; i < k; i++) {
         int64_t sl = hslot(&hm, keys[i]);
         vr->g[i] = (int32_t)(keys[i] >> 32);
         vr->s[i] = (int32_t)(keys[i] & 0xFFFFFFFFu);
         vr->w[i] = hm.w[sl];
         vr->u[i] = hm.u[sl];
+        vr->r[i] = hm.r[sl];
     }
     free(keys);
     hmap_free(&hm);
@@ -608,7 +753,7 @@ void* orc_lift_view(int64_t n, const float* means, const float* scales, const fl
     return vr;
 }
 
-void orc_view_fetch(void* h, int32_t* g, int32_t* s, double* w, double* u)
+void orc_view_fetch(void* h, int32_t* g, int32_t* s, double* w, double* u, double* r)
 {
     view_result* vr = (view_result*)h;
     size_t k = (size_t)vr->n_triples;
@@ -616,13 +761,14 @@ void orc_view_fetch(void* h, int32_t* g, int32_t* s, double* w, double* u)
     if (s) memcpy(s, vr->s, k * 4);
     if (w) memcpy(w, vr->w, k * 8);
     if (u) memcpy(u, vr->u, k * 8);
+    if (r) memcpy(r, vr->r, k * 8);
 }
 
 void orc_view_free(void* h)
 {
     view_result* vr = (view_result*)h;
     if (!vr) return;
-    free(vr->g); free(vr->s); free(vr->w); free(vr->u);
+    free(vr->g); free(vr->s); free(vr->w); free(vr->u); free(vr->r);
     free(vr);
 }
 

@@ -25,6 +25,8 @@ SLAG_HOST, SLAG_DEVICE = 0, 1
 SLAG_F32, SLAG_BF16 = 0, 1
 SLAG_FLAG_PROFILE, SLAG_FLAG_COUNT, SLAG_FLAG_KEEP_DEBUG, SLAG_FLAG_GRAPH, SLAG_FLAG_AUTOTUNE = \
     1, 2, 4, 8, 16
+SLAG_DEBUG_KEYS, SLAG_DEBUG_TILE_RANGES, SLAG_DEBUG_W_VIEW, SLAG_DEBUG_PIXEL_T_FINAL, \
+    SLAG_DEBUG_PIXEL_WSUM, SLAG_DEBUG_PIXEL_COUNT, SLAG_DEBUG_COUNTERS = range(7)
 
 STATUS_NAMES = {0: "SLAG_OK", 1: "SLAG_E_INVALID_ARG", 2: "SLAG_E_OUT_OF_MEMORY",
                 3: "SLAG_E_DEVICE", 4: "SLAG_E_STATE", 5: "SLAG_E_CAPACITY",
@@ -49,7 +51,7 @@ class slag_stats(ctypes.Structure):
                 ("n_contrib", ctypes.c_int64), ("n_tests", ctypes.c_int64),
                 ("n_tile_tests", ctypes.c_int64), ("ms_total", ctypes.c_double),
                 ("ms_stage", ctypes.c_double * 16), ("n_stages", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("n_lost", ctypes.c_int64)]
 
 
 class slag_tuning(ctypes.Structure):
@@ -66,7 +68,7 @@ class slag_train_cfg(ctypes.Structure):
 EXPORTS = ["slag_create", "slag_destroy", "slag_last_error", "slag_set_gaussians",
            "slag_set_cameras", "slag_set_segments", "slag_set_features", "slag_lift",
            "slag_get_embeddings", "slag_get_stats", "slag_stage_name", "slag_debug_tile_lists",
-           "slag_debug_weights", "slag_get_tuning", "slag_variant_name",
+           "slag_debug_weights", "slag_get_tuning", "slag_variant_name", "slag_get_debug",
            # include/slag_codec.h
            "slag_codec_init", "slag_codec_get_params", "slag_codec_clear_pool",
            "slag_codec_set_pool", "slag_codec_add_lift_rows", "slag_codec_pool_size",
@@ -103,7 +105,8 @@ def lib():
     L.slag_set_segments.argtypes = [P, I32, P, I32, I32]
     L.slag_set_features.argtypes = [P, I32, I32, P, I32]
     L.slag_lift.argtypes = [P]
-    L.slag_get_embeddings.argtypes = [P, P, P, I32]
+    L.slag_get_embeddings.argtypes = [P, P, I32, P, I32]
+    L.slag_get_debug.argtypes = [P, I32, I32, P, I64, ctypes.POINTER(I64)]
     L.slag_get_stats.argtypes = [P, ctypes.POINTER(slag_stats)]
     L.slag_stage_name.argtypes = [I32]
     L.slag_stage_name.restype = ctypes.c_char_p
@@ -200,10 +203,43 @@ def slag_lift(ctx):
     _check(ctx, lib().slag_lift(ctx))
 
 
+def _dtype_of(a) -> int:
+    """SLAG_F32 for float32 arrays/tensors, SLAG_BF16 for torch.bfloat16 tensors
+    or uint16 arrays of bfloat16 bit patterns."""
+    name = str(getattr(a, "dtype", ""))
+    if name in ("float32", "torch.float32"):
+        return SLAG_F32
+    if name in ("uint16", "torch.bfloat16", "torch.uint16", "torch.int16"):
+        return SLAG_BF16
+    raise ValueError(f"unsupported output dtype {name}")
+
+
 def slag_get_embeddings(ctx, out, den=None):
     p, w = _ptr(out)
-    pd, _ = _ptr(den)
-    _check(ctx, lib().slag_get_embeddings(ctx, p, pd, w))
+    pd, wd = _ptr(den)
+    if out is not None and den is not None and w != wd:
+        raise ValueError("out and den must be in the same memory")
+    dt = _dtype_of(out) if out is not None else SLAG_F32
+    _check(ctx, lib().slag_get_embeddings(ctx, p, dt, pd, w if out is not None else wd))
+
+
+_DEBUG_DTYPE = {SLAG_DEBUG_KEYS: (np.uint32, 3), SLAG_DEBUG_TILE_RANGES: (np.uint32, 2),
+                SLAG_DEBUG_W_VIEW: (np.uint32, 3), SLAG_DEBUG_PIXEL_T_FINAL: (np.float32, 0),
+                SLAG_DEBUG_PIXEL_WSUM: (np.float32, 0), SLAG_DEBUG_PIXEL_COUNT: (np.uint32, 0),
+                SLAG_DEBUG_COUNTERS: (np.int64, 1)}
+
+
+def slag_get_debug(ctx, what: int, view: int = 0) -> np.ndarray:
+    """One debug export as a NumPy array (rows per the layout in slag.h;
+    per-pixel exports come back as [H, W])."""
+    n = ctypes.c_int64(0)
+    _check(ctx, lib().slag_get_debug(ctx, int(what), int(view), None, 0, ctypes.byref(n)))
+    buf = np.empty(max(n.value, 1), np.uint8)
+    _check(ctx, lib().slag_get_debug(ctx, int(what), int(view), _ptr(buf)[0], n.value,
+                                     ctypes.byref(n)))
+    dt, cols = _DEBUG_DTYPE[int(what)]
+    a = buf[:n.value].view(dt)
+    return a.reshape(-1, cols) if cols > 1 else a
 
 
 def slag_get_stats(ctx) -> dict:

@@ -22,6 +22,8 @@
 // Accumulation is FP32.  The weight sums (denominators) are FP32 sums in view
 // order; every chunk is filled in a fixed order, so results are
 // deterministic.
+#include <algorithm>
+
 #include "slag_internal.h"
 
 namespace slag {
@@ -407,7 +409,24 @@ void launch_nt(int64_t n, int nb, int d, bool bf16, const uint32_t* perm, const 
                            (int)last);
 }
 
+__global__ __launch_bounds__(256) void k_f32_to_bf16(uint64_t n, const float* __restrict__ in,
+                                                     uint16_t* __restrict__ out)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * 256) {
+        const uint32_t b = __float_as_uint(in[i]);
+        out[i] = (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+    }
+}
+
 }  // namespace
+
+void launch_f32_to_bf16(uint64_t n, const float* in, uint16_t* out, hipStream_t st)
+{
+    if (!n) return;
+    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3((unsigned)blocks), dim3(256), 0, st, n, in, out);
+}
 
 bool contract_supported(int d)
 {

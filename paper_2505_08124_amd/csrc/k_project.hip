@@ -106,6 +106,51 @@ __device__ __forceinline__ bool project(const ViewDev& V, float mx, float my, fl
     return true;
 }
 
+// Compositing form of a visible pair, in FP64 from the FP64 world covariance
+// (same operations as the FP32 path, so the conic is the exact inverse of the
+// projected covariance up to FP64 rounding): the prescaled conic
+// (A, B, C) = -log2(e) (conic_xx / 2, conic_xy, conic_yy / 2) and the screen
+// mean as an offset from the pixel box's corner (x0, y0), each rounded to FP32
+// once.  alpha = 2^(lo2 + A dx^2 + B dx dy + C dy^2).
+__device__ __forceinline__ void project_fine(const ViewDev& V, float mx, float my, float mz,
+                                             const double* S, int x0, int y0, float4& r0,
+                                             float& rc)
+{
+    const float* R = V.R;
+    const double X = (double)R[0] * mx + (double)R[1] * my + (double)R[2] * mz + (double)V.t[0];
+    const double Y = (double)R[3] * mx + (double)R[4] * my + (double)R[5] * mz + (double)V.t[1];
+    const double Z = (double)R[6] * mx + (double)R[7] * my + (double)R[8] * mz + (double)V.t[2];
+    const double limx = 1.3 * (0.5 * (double)V.W / (double)V.fx);
+    const double limy = 1.3 * (0.5 * (double)V.H / (double)V.fy);
+    const double txz = X / Z, tyz = Y / Z;
+    const double tx = fmin(limx, fmax(-limx, txz)), ty = fmin(limy, fmax(-limy, tyz));
+    const double j00 = (double)V.fx / Z, j02 = -j00 * tx;
+    const double j11 = (double)V.fy / Z, j12 = -j11 * ty;
+    double a[6];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        a[k] = j00 * R[k] + j02 * R[6 + k];
+        a[3 + k] = j11 * R[3 + k] + j12 * R[6 + k];
+    }
+    const double sxx = S[0], sxy = S[1], sxz = S[2], syy = S[3], syz = S[4], szz = S[5];
+    const double b0 = a[0] * sxx + a[1] * sxy + a[2] * sxz;
+    const double b1 = a[0] * sxy + a[1] * syy + a[2] * syz;
+    const double b2 = a[0] * sxz + a[1] * syz + a[2] * szz;
+    const double b3 = a[3] * sxx + a[4] * sxy + a[5] * sxz;
+    const double b4 = a[3] * sxy + a[4] * syy + a[5] * syz;
+    const double b5 = a[3] * sxz + a[4] * syz + a[5] * szz;
+    const double c00 = b0 * a[0] + b1 * a[1] + b2 * a[2] + 0.3;
+    const double c01 = b0 * a[3] + b1 * a[4] + b2 * a[5];
+    const double c11 = b3 * a[3] + b4 * a[4] + b5 * a[5] + 0.3;
+    const double idet = 1.0 / (c00 * c11 - c01 * c01);
+    const double L2E = 1.4426950408889634074;
+    const double u = (double)V.fx * txz + (double)V.cx;
+    const double v = (double)V.fy * tyz + (double)V.cy;
+    r0 = make_float4((float)(u - (double)x0), (float)(v - (double)y0),
+                     (float)(-0.5 * L2E * c11 * idet), (float)(L2E * c01 * idet));
+    rc = (float)(-0.5 * L2E * c00 * idet);
+}
+
 __device__ __forceinline__ uint32_t tiles_of(const Proj& P)
 {
     return (uint32_t)((P.x1 / TILE - P.x0 / TILE + 1) * (P.y1 / TILE - P.y0 / TILE + 1));
@@ -136,11 +181,17 @@ __device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* lds, uint
     return off + x - v;
 }
 
+// Upload: validation, the FP32 world covariance of the decision path, and
+// the FP64 world covariance and log2 of the opacity that the records of the
+// compositing are formed from (so that alpha carries only the rounding of the
+// stored coefficients, not that of an FP32 projection).
 __global__ __launch_bounds__(256) void k_prep_gauss(int64_t n, const float* __restrict__ means,
                                                     const float* __restrict__ scales,
                                                     const float* __restrict__ quats,
                                                     const float* __restrict__ opac,
-                                                    float* __restrict__ cov3, uint32_t* err)
+                                                    float* __restrict__ cov3,
+                                                    double* __restrict__ covd,
+                                                    float* __restrict__ lo2, uint32_t* err)
 {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
@@ -154,13 +205,33 @@ __global__ __launch_bounds__(256) void k_prep_gauss(int64_t n, const float* __re
     ok = ok && nq > 0.0f && isfinite(nq) && o > 0.0f && o <= 1.0f;
     if (!ok) {
         atomicOr(err, 1u);
-        for (int k = 0; k < 6; k++) cov3[k * n + g] = 0.0f;
+        for (int k = 0; k < 6; k++) {
+            cov3[k * n + g] = 0.0f;
+            covd[k * n + g] = 0.0;
+        }
+        lo2[g] = 0.0f;
         return;
     }
     float S[6];
     world_cov(s, q, S);
 #pragma unroll
     for (int k = 0; k < 6; k++) cov3[k * n + g] = S[k];
+    // FP64: Sigma3 = Rq diag(s^2) Rq^T from the normalised quaternion
+    const double qn = sqrt((double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] +
+                           (double)q[3] * q[3]);
+    const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+    const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                         2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                         2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+    const double s2[3] = {(double)s[0] * s[0], (double)s[1] * s[1], (double)s[2] * s[2]};
+    const int ij[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        const int i = ij[k][0], j = ij[k][1];
+        covd[k * n + g] = R[3 * i] * s2[0] * R[3 * j] + R[3 * i + 1] * s2[1] * R[3 * j + 1] +
+                          R[3 * i + 2] * s2[2] * R[3 * j + 2];
+    }
+    lo2[g] = (float)log2((double)o);
 }
 
 __global__ __launch_bounds__(256) void k_validate_ids(int64_t npix, const int32_t* __restrict__ ids,
@@ -256,7 +327,8 @@ __global__ __launch_bounds__(256) void k_count(int64_t n, const ViewDev* __restr
 // debug exports.  Same striped layout as pass 1.
 __global__ __launch_bounds__(256) void k_emit_pairs(
     int64_t n, const ViewDev* __restrict__ views, const float* __restrict__ means,
-    const float* __restrict__ cov3, const float* __restrict__ opac, uint32_t* __restrict__ tcnt,
+    const float* __restrict__ cov3, const double* __restrict__ covd,
+    const float* __restrict__ lo2, uint32_t* __restrict__ tcnt,
     const uint32_t* __restrict__ blk_off, float4* __restrict__ rec, uint32_t* __restrict__ pgauss,
     uint16_t* __restrict__ pview, uint64_t* __restrict__ dkey, uint32_t* __restrict__ dval,
     uint32_t* __restrict__ psz, uint32_t* __restrict__ pz, const uint32_t* __restrict__ sat,
@@ -296,7 +368,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
     // the next Gaussian's inputs are loaded (clamped, unconditionally) while
     // the current one is projected and written
     struct GIn {
-        float C[6], x, y, z, o;
+        float C[6], x, y, z, lo2;
         uint32_t pg;
     };
     auto load_in = [&](int i, GIn& a) {
@@ -306,7 +378,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         a.x = means[3 * gc];
         a.y = means[3 * gc + 1];
         a.z = means[3 * gc + 2];
-        a.o = opac[gc];
+        a.lo2 = lo2[gc];
         a.pg = perm[gc];
     };
     GIn nx;
@@ -328,11 +400,17 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         }
         Proj P;
         project(V, cur.x, cur.y, cur.z, cur.C, P);
-        // compositing form: prescaled conic, log2 of the opacity
-        rec[2 * (size_t)pidx] = make_float4(P.u, P.v, P.ca * NHALF_LOG2E, P.cb * NLOG2E);
+        // compositing form (FP64 projection): mean offset from the box corner,
+        // prescaled conic, log2 of the opacity, pixel box
+        double Sd[6];
+#pragma unroll
+        for (int k = 0; k < 6; k++) Sd[k] = covd[k * n + g];
+        float4 r0;
+        float rc;
+        project_fine(V, cur.x, cur.y, cur.z, Sd, P.x0, P.y0, r0, rc);
+        rec[2 * (size_t)pidx] = r0;
         rec[2 * (size_t)pidx + 1] =
-            make_float4(P.cc * NHALF_LOG2E, __builtin_amdgcn_logf(cur.o),
-                        __uint_as_float((uint32_t)P.x0 | ((uint32_t)P.y0 << 16)),
+            make_float4(rc, cur.lo2, __uint_as_float((uint32_t)P.x0 | ((uint32_t)P.y0 << 16)),
                         __uint_as_float((uint32_t)P.x1 | ((uint32_t)P.y1 << 16)));
         pgauss[pidx] = cur.pg;                       // the caller's index of the Gaussian
         pview[pidx] = (uint16_t)vl;
@@ -484,10 +562,12 @@ __global__ __launch_bounds__(256) void k_invert(int64_t n, const uint32_t* __res
 __global__ __launch_bounds__(256) void k_gather_gauss(int64_t n, const uint32_t* __restrict__ perm,
                                                       const float* __restrict__ means,
                                                       const float* __restrict__ cov3,
-                                                      const float* __restrict__ opac,
+                                                      const double* __restrict__ covd,
+                                                      const float* __restrict__ lo2,
                                                       float* __restrict__ means_o,
                                                       float* __restrict__ cov3_o,
-                                                      float* __restrict__ opac_o)
+                                                      double* __restrict__ covd_o,
+                                                      float* __restrict__ lo2_o)
 {
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (q >= n) return;
@@ -495,8 +575,11 @@ __global__ __launch_bounds__(256) void k_gather_gauss(int64_t n, const uint32_t*
 #pragma unroll
     for (int k = 0; k < 3; k++) means_o[3 * q + k] = means[3 * g + k];
 #pragma unroll
-    for (int k = 0; k < 6; k++) cov3_o[k * n + q] = cov3[k * n + g];
-    opac_o[q] = opac[g];
+    for (int k = 0; k < 6; k++) {
+        cov3_o[k * n + q] = cov3[k * n + g];
+        covd_o[k * n + q] = covd[k * n + g];
+    }
+    lo2_o[q] = lo2[g];
 }
 
 }  // namespace
@@ -504,11 +587,12 @@ __global__ __launch_bounds__(256) void k_gather_gauss(int64_t n, const uint32_t*
 int count_blocks_per_view(int64_t n) { return (int)((n + CPB - 1) / CPB); }
 
 void launch_prep_gauss(int64_t n, const float* means, const float* scales, const float* quats,
-                       const float* opac, float* cov3, uint32_t* err, hipStream_t st)
+                       const float* opac, float* cov3, double* covd, float* lo2, uint32_t* err,
+                       hipStream_t st)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_prep_gauss, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, means,
-                       scales, quats, opac, cov3, err);
+                       scales, quats, opac, cov3, covd, lo2, err);
 }
 
 void launch_validate_ids(int64_t npix, const int32_t* ids, int32_t nseg, uint32_t* err,
@@ -530,7 +614,8 @@ void launch_count(int nb, int64_t n, const ViewDev* views, const float* means, c
 }
 
 void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* means,
-                       const float* cov3, const float* opac, uint32_t* tcnt_pairof,
+                       const float* cov3, const double* covd, const float* lo2,
+                       uint32_t* tcnt_pairof,
                        const uint32_t* blk_off, float4* rec, uint32_t* pgauss, uint16_t* pview,
                        uint64_t* dkey, uint32_t* dval, uint32_t* psz, uint32_t* pz,
                        const uint32_t* sat, uint32_t zmin, int zbits, int pbits, uint32_t* blk_tot,
@@ -539,7 +624,7 @@ void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* mea
 {
     if (n <= 0 || nb <= 0) return;
     hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)nb, (unsigned)count_blocks_per_view(n)),
-                       dim3(256), 0, st, n, views, means, cov3, opac, tcnt_pairof, blk_off, rec,
+                       dim3(256), 0, st, n, views, means, cov3, covd, lo2, tcnt_pairof, blk_off, rec,
                        pgauss, pview, dkey, dval, psz, pz, sat, zmin, zbits, pbits, blk_tot, perm,
                        pair_of_m, prect, lbits);
 }
@@ -575,12 +660,12 @@ void launch_invert(int64_t n, const uint32_t* perm, uint32_t* rank, hipStream_t 
 }
 
 void launch_gather_gauss(int64_t n, const uint32_t* perm, const float* means, const float* cov3,
-                         const float* opac, float* means_o, float* cov3_o, float* opac_o,
-                         hipStream_t st)
+                         const double* covd, const float* lo2, float* means_o, float* cov3_o,
+                         double* covd_o, float* lo2_o, hipStream_t st)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_gather_gauss, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, perm,
-                       means, cov3, opac, means_o, cov3_o, opac_o);
+                       means, cov3, covd, lo2, means_o, cov3_o, covd_o, lo2_o);
 }
 
 }  // namespace slag

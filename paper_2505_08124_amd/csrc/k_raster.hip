@@ -208,7 +208,8 @@ __device__ __forceinline__ float wave_sum4(float v0, float v1, float v2, float v
 // Blend this wave's compacted entries of one batch into its 64 pixels, four
 // entries at a time; the four entries' per-segment weight sums over the
 // wave's pixels go to acc[batch entry][segment slot].
-// A lane's pixel inside its wave's 8x8 block (lx, ly in 0..7).
+// A lane's pixel inside its wave's 8x8 block, relative to the block centre (lx, ly in
+// -3.5 .. 3.5).
 struct LaneXY {
     float lx, ly;
 };
@@ -219,7 +220,7 @@ __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const
                                             int px, int py, int slot, int uslot, uint32_t slot_mask,
                                             float& T, bool& done, float (*acc)[NS_CAP], int lane,
                                             unsigned long long& n_acc, unsigned long long& n_box,
-                                            unsigned long long& n_tile)
+                                            unsigned long long& n_tile, float& wsum)
 {
     const bool slot_ok = slot >= 0;
     const int r = lane >> 4;
@@ -257,6 +258,7 @@ __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const
                               py >= (int)(a >> 16) && py <= (int)(b >> 16));
                 }
                 n_acc += take;
+                wsum += take ? alpha * T : 0.0f;
                 T = take ? Tn : T;
                 done = done || stop;
             } else {
@@ -299,7 +301,8 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
     const uint32_t* __restrict__ ival, uint2* __restrict__ pinfo,
     const float4* __restrict__ rec, const uint32_t* __restrict__ ns_tile,
     const uint16_t* __restrict__ segl, const int32_t* __restrict__ ids, uint2* __restrict__ part,
-    unsigned long long* __restrict__ counters)
+    unsigned long long* __restrict__ counters, float* __restrict__ pix_t,
+    float* __restrict__ pix_w, uint32_t* __restrict__ pix_n)
 {
     __shared__ float4 s_w0[4][BATCH];         // per wave: entries touching its block, exponent
     __shared__ float4 s_w1[4][BATCH];         //   coefficients (c0, cx, cy, cxx), (cxy, cyy, box, box)
@@ -335,10 +338,13 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
         }
         ls = lo;
     }
+    // lane offsets from the block centre (bx0 + 4, by0 + 4): the exponent is
+    // expanded there, so no lane is more than 3.5 px from the expansion point
     LaneXY Q;
-    Q.lx = (float)(lane & 7);
-    Q.ly = (float)(lane >> 3);
+    Q.lx = (float)(lane & 7) - 3.5f;
+    Q.ly = (float)(lane >> 3) - 3.5f;
     unsigned long long n_acc = 0, n_box = 0, n_tile = 0;
+    float wsum = 0.0f;   // counting pass: the pixel's accepted weight
     const uint32_t last = end - 1;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
@@ -398,13 +404,16 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
                        (int)(ba & 0xFFFFu) <= bx0 + ax1 && (int)(bb >> 16) >= by0 + ay0 &&
                        (int)(ba >> 16) <= by0 + ay1;
             // exponent log2(o) + A dx^2 + B dx dy + C dy^2 with dx = lx - du,
-            // dy = ly - dv (pixel centre relative to the entry's mean)
+            // dy = ly - dv (pixel centre relative to the entry's mean; du, dv:
+            // the mean relative to the block centre, from its offset to the box
+            // corner)
             const float A = q0.z, B = q0.w, C = q1.x;   // prescaled in the record
-            const float du = q0.x - ((float)bx0 + 0.5f), dv = q0.y - ((float)by0 + 0.5f);
+            const float du = q0.x + (float)((int)(ba & 0xFFFFu) - bx0 - 4);
+            const float dv = q0.y + (float)((int)(ba >> 16) - by0 - 4);
             const float lo2 = q1.y;                        // log2(o)
             if (!COUNT && hit)
-                hit = reaches_amin(A, B, C, lo2, (float)ax0 - du, (float)ax1 - du, (float)ay0 - dv,
-                                   (float)ay1 - dv);
+                hit = reaches_amin(A, B, C, lo2, (float)ax0 - 3.5f - du, (float)ax1 - 3.5f - du,
+                                   (float)ay0 - 3.5f - dv, (float)ay1 - 3.5f - dv);
             const uint64_t hm = __ballot(hit);
             const int cnt = __popcll(hm);
             if (hit) {
@@ -437,16 +446,16 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
             if (cnt && !__all(done)) {
                 if (counting) {
                     if (mode == MODE_UNIFORM)
-                        blend_batch<MODE_UNIFORM, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                        blend_batch<MODE_UNIFORM, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum);
                     else if (mode == MODE_MIXED)
-                        blend_batch<MODE_MIXED, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                        blend_batch<MODE_MIXED, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum);
                     else
-                        blend_batch<MODE_NONE, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                        blend_batch<MODE_NONE, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum);
                 } else {
                     if (mode == MODE_UNIFORM)
-                        blend_batch<MODE_UNIFORM, false, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                        blend_batch<MODE_UNIFORM, false, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum);
                     else
-                        blend_batch<MODE_MIXED, false, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile);
+                        blend_batch<MODE_MIXED, false, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum);
                 }
             }
             __syncthreads();
@@ -480,10 +489,21 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
                         for (int k = 0; k < NS_CAP; k++)
                             if (sv[k] != 0.0f)
                                 *dst++ = make_uint2(tk | (uint32_t)s_seg[g0 + k], __float_as_uint(sv[k]));
+                    } else {
+                        // a capacity error would lose weight: count it, the
+                        // fetch of the result reports it
+                        atomicAdd(&counters[3], (unsigned long long)nz);
                     }
                 }
             }
             if (__syncthreads_count(!done) == 0) break;
+        }
+        if (counting && pix_t && valid) {
+            // per-pixel debug outputs of the counting pass (every pixel walked)
+            const uint64_t pi = V.pix_off + (uint64_t)py * V.W + px;
+            pix_t[pi] = T;
+            pix_w[pi] = wsum;
+            pix_n[pi] = (uint32_t)n_acc;
         }
         __syncthreads();
     }
@@ -572,14 +592,15 @@ void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t
                       const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
                       uint2* pinfo, const float4* rec, const uint32_t* ns_tile,
                       const uint16_t* segl, const int32_t* ids, uint2* part,
-                      unsigned long long* counters, hipStream_t st)
+                      unsigned long long* counters, float* pix_t, float* pix_w, uint32_t* pix_n,
+                      hipStream_t st)
 {
     if (!nbuckets) return;
 #define SLAG_COMP(C, W, P)                                                                         \
     hipLaunchKernelGGL((k_composite<C, W, P>), dim3(nbuckets), dim3(256), 0, st, order, obase,     \
                        bucket_view, views, bstart, bend, ival, pinfo, rec,                        \
                        ns_tile, segl, ids,                                                         \
-                       part, counters)
+                       part, counters, pix_t, pix_w, pix_n)
     if (count) {
         SLAG_COMP(true, 8, false);
         return;

@@ -177,19 +177,23 @@ static slag_status morton_order(slag_ctx* c, int64_t n)
     const uint32_t* sorted = alt ? c->dval_alt.as<uint32_t>() : c->dval.as<uint32_t>();
     HC(c, hipMemcpyAsync(c->perm.p, sorted, (size_t)n * 4, hipMemcpyDeviceToDevice, c->st));
     launch_invert(n, c->perm.as<uint32_t>(), c->rank.as<uint32_t>(), c->st);
-    DevBuf m2, c2, o2;
+    DevBuf m2, c2, d2, l2;
     CK(ensure(c, m2, nn * 12));
     CK(ensure(c, c2, nn * 24));
-    CK(ensure(c, o2, nn * 4));
+    CK(ensure(c, d2, nn * 48));
+    CK(ensure(c, l2, nn * 4));
     launch_gather_gauss(n, c->perm.as<uint32_t>(), c->means.as<float>(), c->cov3.as<float>(),
-                        c->opac.as<float>(), m2.as<float>(), c2.as<float>(), o2.as<float>(), c->st);
+                        c->covd.as<double>(), c->lo2.as<float>(), m2.as<float>(), c2.as<float>(),
+                        d2.as<double>(), l2.as<float>(), c->st);
     HC(c, hipStreamSynchronize(c->st));
     std::swap(c->means, m2);
     std::swap(c->cov3, c2);
-    std::swap(c->opac, o2);
+    std::swap(c->covd, d2);
+    std::swap(c->lo2, l2);
     release(m2);
     release(c2);
-    release(o2);
+    release(d2);
+    release(l2);
     return SLAG_OK;
 }
 
@@ -384,7 +388,8 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
     CK(ensure(c, c->tcr, np * 4 + 16));
     CK(ensure(c, c->wlen, np * 4));
     CK(ensure(c, c->pair_of_m, npq * 4));
-    launch_emit_pairs(nb, n, views, c->means.as<float>(), c->cov3.as<float>(), c->opac.as<float>(),
+    launch_emit_pairs(nb, n, views, c->means.as<float>(), c->cov3.as<float>(),
+                      c->covd.as<double>(), c->lo2.as<float>(),
                       c->tcnt.as<uint32_t>(), c->blk_vis.as<uint32_t>(), c->rec.as<float4>(),
                       c->pgauss.as<uint32_t>(), c->pview.as<uint16_t>(),
                       c->dkey.as<uint64_t>(), c->dval.as<uint32_t>(), c->psz.as<uint32_t>(),
@@ -526,6 +531,22 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         launch_init_pinfo(npairs, c->psz.as<uint32_t>(), (uint32_t)nparts, c->pinfo.as<uint2>(), st);
         CK(stage_end(c, ST_PART_PREP, ev));
 
+        // per-pixel debug outputs (counting lifts with debug exports): pixels
+        // of tiles without list entries keep T = 1, no weight, no blend
+        float* pix_t = nullptr;
+        float* pix_w = nullptr;
+        uint32_t* pix_n = nullptr;
+        if (count && debug) {
+            const uint64_t P = c->pix_off[c->nviews];
+            const uint64_t p0 = c->pix_off[B.v0], p1 = c->pix_off[B.v0 + nb];
+            CK(ensure(c, c->pixdbg, P * 12 + 16));
+            pix_t = c->pixdbg.as<float>();
+            pix_w = pix_t + P;
+            pix_n = reinterpret_cast<uint32_t*>(pix_w + P);
+            launch_fill_u32(reinterpret_cast<uint32_t*>(pix_t) + p0, p1 - p0, 0x3F800000u, st);
+            launch_fill_u32(reinterpret_cast<uint32_t*>(pix_w) + p0, p1 - p0, 0u, st);
+            launch_fill_u32(pix_n + p0, p1 - p0, 0u, st);
+        }
         CK(stage_begin(c, ST_COMPOSITE, &ev));
         auto clear_lists = [&]() {
             launch_init_pinfo(npairs, c->psz.as<uint32_t>(), (uint32_t)nparts,
@@ -546,7 +567,8 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
                                  c->bend.as<uint32_t>(), sval, c->pinfo.as<uint2>(), c->rec.as<float4>(),
                                  c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
                                  c->ids.as<int32_t>(), c->part.as<uint2>(),
-                                 reinterpret_cast<unsigned long long*>(small + SM_COUNTERS), st);
+                                 reinterpret_cast<unsigned long long*>(small + SM_COUNTERS),
+                                 nullptr, nullptr, nullptr, st);
             };
             TuneEntry te;
             te.n_variants = std::min(composite_variants(), 8);
@@ -563,7 +585,8 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
                                  c->bend.as<uint32_t>(), sval, c->pinfo.as<uint2>(), c->rec.as<float4>(),
                                  c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
                                  c->ids.as<int32_t>(), c->part.as<uint2>(),
-                                 reinterpret_cast<unsigned long long*>(small + SM_COUNTERS), st);
+                                 reinterpret_cast<unsigned long long*>(small + SM_COUNTERS),
+                                 pix_t, pix_w, pix_n, st);
             };
             const uint64_t key = ((uint64_t)B.cls_w[k] << 32) | B.cls_h[k];
             auto it = c->tune.find(key);
@@ -591,6 +614,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
 
     c->last_v0 = B.v0;
     c->last_nb = nb;
+    c->last_pix = count && debug;
     c->last_npairs = npairs;
     c->last_ni = ni;
     c->last_ikey = skey;
@@ -642,7 +666,8 @@ void slag_destroy(slag_ctx* c)
     if (!c) return;
     hipSetDevice(c->device);
     if (c->st) hipStreamSynchronize(c->st);
-    DevBuf* bufs[] = {&c->means, &c->scales, &c->quats, &c->opac, &c->cov3, &c->ids, &c->feats,
+    DevBuf* bufs[] = {&c->means, &c->scales, &c->quats, &c->opac, &c->cov3, &c->covd, &c->lo2,
+                      &c->ids, &c->feats,
                       &c->num, &c->den, &c->ns_tile, &c->segl, &c->sat, &c->tcnt, &c->blk_vis,
                       &c->small, &c->scan_ws, &c->hist, &c->rec, &c->pgauss, &c->pview, &c->dkey,
                       &c->dkey_alt, &c->dval, &c->dval_alt, &c->psz, &c->pz, &c->tcr, &c->wlen,
@@ -650,7 +675,8 @@ void slag_destroy(slag_ctx* c)
                       &c->part, &c->wrow, &c->perm, &c->rank, &c->pair_of_m,
                       &c->pinfo, &c->prect, &c->prank, &c->blk_aux, &c->bkey,
                       &c->bkey_alt, &c->bord, &c->bord_alt, &c->tflag, &c->tpos, &c->tv,
-                      &c->tv_alt, &c->tg, &c->thead, &c->tk, &c->tk_alt};
+                      &c->tv_alt, &c->tg, &c->thead, &c->tk, &c->tk_alt, &c->pixdbg,
+                      &c->outbf};
     destroy_graph(c);
     for (DevBuf* b : bufs) release(*b);
     codec_release(c);
@@ -709,10 +735,13 @@ slag_status slag_set_gaussians(slag_ctx* c, int64_t n, const float* means, const
     CK(copy_in(c, c->quats, quats, (size_t)n * 16, where));
     CK(copy_in(c, c->opac, opacity, (size_t)n * 4, where));
     CK(ensure(c, c->cov3, (size_t)std::max<int64_t>(n, 1) * 24));
+    CK(ensure(c, c->covd, (size_t)std::max<int64_t>(n, 1) * 48));
+    CK(ensure(c, c->lo2, (size_t)std::max<int64_t>(n, 1) * 4));
     uint32_t* err = reinterpret_cast<uint32_t*>(c->small.as<uint64_t>() + SM_ERR);
     launch_fill_u32(err, 1, 0u, c->st);
     launch_prep_gauss(n, c->means.as<float>(), c->scales.as<float>(), c->quats.as<float>(),
-                      c->opac.as<float>(), c->cov3.as<float>(), err, c->st);
+                      c->opac.as<float>(), c->cov3.as<float>(), c->covd.as<double>(),
+                      c->lo2.as<float>(), err, c->st);
     CK(read_small(c, SM_ERR, 1));
     c->n = -1;
     c->have_out = false;
@@ -964,17 +993,37 @@ extern "C" {
 
 slag_status slag_lift(slag_ctx* c) { return run_lift(c, false); }
 
-slag_status slag_get_embeddings(slag_ctx* c, float* out, float* den, slag_mem where)
+slag_status slag_get_embeddings(slag_ctx* c, void* out, slag_dtype dtype, float* den,
+                                slag_mem where)
 {
     if (!c) return SLAG_E_INVALID_ARG;
     c->err.clear();
     if (!c->have_out) FAIL(c, SLAG_E_STATE, "no lift result");
+    if (dtype != SLAG_F32 && dtype != SLAG_BF16) FAIL(c, SLAG_E_INVALID_ARG, "bad output dtype");
+    if (where != SLAG_HOST && where != SLAG_DEVICE) FAIL(c, SLAG_E_INVALID_ARG, "bad memory kind");
     HC(c, hipSetDevice(c->device));
     const hipMemcpyKind k = where == SLAG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     const size_t n = (size_t)c->n;
-    if (out && n) HC(c, hipMemcpyAsync(out, c->num.p, n * c->d * 4, k, c->st));
+    if (out && n) {
+        if (dtype == SLAG_F32) {
+            HC(c, hipMemcpyAsync(out, c->num.p, n * c->d * 4, k, c->st));
+        } else if (where == SLAG_DEVICE) {
+            launch_f32_to_bf16((uint64_t)n * c->d, c->num.as<float>(), static_cast<uint16_t*>(out),
+                               c->st);
+        } else {
+            CK(ensure(c, c->outbf, n * c->d * 2));
+            launch_f32_to_bf16((uint64_t)n * c->d, c->num.as<float>(), c->outbf.as<uint16_t>(),
+                               c->st);
+            HC(c, hipMemcpyAsync(out, c->outbf.p, n * c->d * 2, k, c->st));
+        }
+    }
     if (den && n) HC(c, hipMemcpyAsync(den, c->den.p, n * 4, k, c->st));
-    HC(c, hipStreamSynchronize(c->st));
+    // part-list capacity errors of the last lift (none by construction)
+    CK(read_small(c, SM_COUNTERS + 3, 1));
+    if (c->host_small[SM_COUNTERS + 3])
+        FAIL(c, SLAG_E_CAPACITY, std::to_string(c->host_small[SM_COUNTERS + 3]) +
+                                     " part-list entries did not fit their capacity; the result "
+                                     "is incomplete");
     return SLAG_OK;
 }
 
@@ -985,6 +1034,7 @@ slag_status slag_get_stats(slag_ctx* c, slag_stats* s)
     HC(c, hipSetDevice(c->device));
     HC(c, hipStreamSynchronize(c->st));
     CK(read_small(c, SM_COUNTERS, 6));
+    c->stats.n_lost = (int64_t)c->host_small[SM_COUNTERS + 3];
     c->stats.n_contrib = (int64_t)c->host_small[SM_COUNTERS];
     c->stats.n_tests = (int64_t)c->host_small[SM_COUNTERS + 1];
     c->stats.n_tile_tests = (int64_t)c->host_small[SM_COUNTERS + 2];
@@ -1092,3 +1142,89 @@ slag_status slag_debug_weights(slag_ctx* c, int32_t view, uint32_t* gauss, uint3
 }
 
 }  // extern "C"
+
+extern "C" slag_status slag_get_debug(slag_ctx* c, slag_debug what, int32_t view, void* out,
+                                      int64_t cap, int64_t* len)
+{
+    if (!c || !len || cap < 0 || (cap > 0 && !out)) return SLAG_E_INVALID_ARG;
+    c->err.clear();
+    *len = 0;
+    if (what == SLAG_DEBUG_COUNTERS) {
+        HC(c, hipSetDevice(c->device));
+        HC(c, hipStreamSynchronize(c->st));
+        CK(read_small(c, SM_COUNTERS, 4));
+        *len = 32;
+        if (cap >= 32) std::memcpy(out, c->host_small + SM_COUNTERS, 32);
+        return SLAG_OK;
+    }
+    if (!(c->opt.flags & SLAG_FLAG_KEEP_DEBUG) || c->last_v0 < 0)
+        FAIL(c, SLAG_E_STATE, "debug exports need SLAG_FLAG_KEEP_DEBUG and a lift");
+    if (view < c->last_v0 || view >= c->last_v0 + c->last_nb)
+        FAIL(c, SLAG_E_STATE, "view not in the last launch");
+    HC(c, hipSetDevice(c->device));
+    const int W = c->cams[view].width, H = c->cams[view].height;
+    switch (what) {
+    case SLAG_DEBUG_KEYS:
+    case SLAG_DEBUG_TILE_RANGES: {
+        int64_t m = 0;
+        CK(slag_debug_tile_lists(c, view, nullptr, nullptr, nullptr, 0, &m));
+        std::vector<uint32_t> t(m), z(m), g(m);
+        if (m) CK(slag_debug_tile_lists(c, view, t.data(), z.data(), g.data(), m, &m));
+        if (what == SLAG_DEBUG_KEYS) {
+            *len = m * 12;
+            if (*len > cap) return SLAG_OK;
+            uint32_t* o = static_cast<uint32_t*>(out);
+            for (int64_t i = 0; i < m; i++) {
+                o[3 * i] = t[i];
+                o[3 * i + 1] = z[i];
+                o[3 * i + 2] = g[i];
+            }
+        } else {
+            const int64_t nt = (int64_t)((W + TILE - 1) / TILE) * ((H + TILE - 1) / TILE);
+            *len = nt * 8;
+            if (*len > cap) return SLAG_OK;
+            uint32_t* o = static_cast<uint32_t*>(out);
+            int64_t i = 0;
+            for (int64_t k = 0; k < nt; k++) {
+                o[2 * k] = (uint32_t)i;
+                while (i < m && t[i] == (uint32_t)k) i++;
+                o[2 * k + 1] = (uint32_t)i;
+            }
+        }
+        return SLAG_OK;
+    }
+    case SLAG_DEBUG_W_VIEW: {
+        int64_t m = 0;
+        CK(slag_debug_weights(c, view, nullptr, nullptr, nullptr, 0, &m));
+        *len = m * 12;
+        if (*len > cap || !m) return SLAG_OK;
+        std::vector<uint32_t> g(m), s(m);
+        std::vector<float> w(m);
+        CK(slag_debug_weights(c, view, g.data(), s.data(), w.data(), m, &m));
+        uint32_t* o = static_cast<uint32_t*>(out);
+        for (int64_t i = 0; i < m; i++) {
+            o[3 * i] = g[i];
+            o[3 * i + 1] = s[i];
+            std::memcpy(&o[3 * i + 2], &w[i], 4);
+        }
+        return SLAG_OK;
+    }
+    case SLAG_DEBUG_PIXEL_T_FINAL:
+    case SLAG_DEBUG_PIXEL_WSUM:
+    case SLAG_DEBUG_PIXEL_COUNT: {
+        if (!c->last_pix)
+            FAIL(c, SLAG_E_STATE, "per-pixel exports need a lift with SLAG_FLAG_COUNT");
+        const uint64_t P = c->pix_off[c->nviews];
+        const uint64_t npx = (uint64_t)W * (uint64_t)H;
+        *len = (int64_t)(npx * 4);
+        if (*len > cap) return SLAG_OK;
+        const int k = what == SLAG_DEBUG_PIXEL_T_FINAL ? 0 : what == SLAG_DEBUG_PIXEL_WSUM ? 1 : 2;
+        const uint32_t* src = c->pixdbg.as<uint32_t>() + (uint64_t)k * P + c->pix_off[view];
+        HC(c, hipStreamSynchronize(c->st));
+        HC(c, hipMemcpy(out, src, npx * 4, hipMemcpyDeviceToHost));
+        return SLAG_OK;
+    }
+    default:
+        FAIL(c, SLAG_E_INVALID_ARG, "unknown debug export");
+    }
+}

@@ -84,6 +84,7 @@ struct slag_ctx {
 
     int64_t n = -1;
     slag_host::DevBuf means, scales, quats, opac, cov3;
+    slag_host::DevBuf covd, lo2;    // FP64 world covariance [6][N], log2 opacity [N]
     slag_host::DevBuf perm, rank;   // Morton order of the Gaussians (rank -> input index, inverse)
 
     int nviews = -1;
@@ -113,6 +114,8 @@ struct slag_ctx {
     slag_host::DevBuf ikey, ikey_alt, ival, ival_alt, bstart, bend, part, wrow, pinfo;
     slag_host::DevBuf prect, prank, blk_aux, bkey, bkey_alt, bord, bord_alt;
     slag_host::DevBuf tflag, tpos, tv, tv_alt, tg, thead, tk, tk_alt;   // depth ties
+    slag_host::DevBuf pixdbg;         // per-pixel T_final, weight sum, blend count (debug)
+    slag_host::DevBuf outbf;          // BF16 copy of the output for host fetches
     uint64_t* host_small = nullptr;   // pinned read-back area
 
     slag_host::CodecState codec;
@@ -136,6 +139,7 @@ struct slag_ctx {
     std::vector<hipEvent_t> free_events;
     // last batch (debug exports, training rows)
     int last_v0 = -1, last_nb = 0;
+    bool last_pix = false;            // the last batch wrote the per-pixel outputs
     uint64_t last_npairs = 0, last_ni = 0;
     const uint32_t* last_ikey = nullptr;
     const uint32_t* last_ival = nullptr;

@@ -28,16 +28,20 @@ struct ViewDev {
 
 // Pair record (one visible (view, Gaussian) pair), two float4, with the
 // inverse covariance prescaled so that alpha = o exp(-q/2) = 2^(log2(o) +
-// A dx^2 + B dx dy + C dy^2):
-//   r0 = (u, v, A, B)   screen mean, A = -log2(e)/2 conic_xx, B = -log2(e) conic_xy
+// A dx^2 + B dx dy + C dy^2), formed in FP64 and rounded once:
+//   r0 = (u - x0, v - y0, A, B)   screen mean as an offset from the box corner,
+//        A = -log2(e)/2 conic_xx, B = -log2(e) conic_xy
 //   r1 = (C, log2(o), x0 | y0 << 16, x1 | y1 << 16)   C = -log2(e)/2 conic_yy;
 //        pixel box (inclusive)
 constexpr float NHALF_LOG2E = -0.72134752044448170368f;   // -log2(e) / 2
 constexpr float NLOG2E = -1.44269504088896340736f;        // -log2(e)
 
 // ---- launchers (each enqueues on `st`) ----
+// Validation, FP32 world covariance cov3 [6][n] (decision path), FP64 world
+// covariance covd [6][n] and lo2 = log2(opacity) (compositing records).
 void launch_prep_gauss(int64_t n, const float* means, const float* scales, const float* quats,
-                       const float* opac, float* cov3, uint32_t* err, hipStream_t st);
+                       const float* opac, float* cov3, double* covd, float* lo2, uint32_t* err,
+                       hipStream_t st);
 void launch_validate_ids(int64_t npix, const int32_t* ids, int32_t nseg, uint32_t* err,
                          hipStream_t st);
 void launch_count(int nb, int64_t n, const ViewDev* views, const float* means, const float* cov3,
@@ -50,7 +54,8 @@ int count_blocks_per_view(int64_t n);
 // Gaussian index pgauss[pair] = perm[g], the view pview, and the (view, rank)
 // -> pair map pair_of_m (NONE where not visible); pz only when non-null.
 void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* means,
-                       const float* cov3, const float* opac, uint32_t* tcnt_pairof,
+                       const float* cov3, const double* covd, const float* lo2,
+                       uint32_t* tcnt_pairof,
                        const uint32_t* blk_off, float4* rec, uint32_t* pgauss, uint16_t* pview,
                        uint64_t* dkey, uint32_t* dval, uint32_t* psz, uint32_t* pz,
                        const uint32_t* sat, uint32_t zmin, int zbits, int pbits, uint32_t* blk_tot,
@@ -67,10 +72,10 @@ void launch_morton(int64_t n, const float* means, const float* lo_scale, uint64_
                    uint32_t* vals, hipStream_t st);
 void launch_invert(int64_t n, const uint32_t* perm, uint32_t* rank, hipStream_t st);
 // Gaussians into Morton order: q-th output = input perm[q] (means [n][3],
-// covariances [6][n], opacities [n]).
+// covariances [6][n] FP32 and FP64, log2 opacities [n]).
 void launch_gather_gauss(int64_t n, const uint32_t* perm, const float* means, const float* cov3,
-                         const float* opac, float* means_o, float* cov3_o, float* opac_o,
-                         hipStream_t st);
+                         const double* covd, const float* lo2, float* means_o, float* cov3_o,
+                         double* covd_o, float* lo2_o, hipStream_t st);
 
 // scans: exclusive prefix sum in place; the 64-bit total goes to *total_dev
 size_t scan_workspace_bytes(uint64_t n);
@@ -138,12 +143,20 @@ const char* composite_variant_name(int v);
 // in the fill field (zeroed by launch_init_pinfo).
 void launch_init_pinfo(uint64_t npairs, const uint32_t* base, uint32_t total, uint2* pinfo,
                        hipStream_t st);
+// counters: [0] accepted blends, [1] in-box tests, [2] tile-list tests (count
+// mode), [3] part-list entries lost to a capacity error (always; 0 by
+// construction).  pix_t / pix_w / pix_n (count mode, may be null): final
+// transmittance, sum of accepted weights and accepted blends of every pixel
+// walked (indexed like the id maps).
 void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t* order,
                       uint32_t obase, const uint32_t* bucket_view, const ViewDev* views,
                       const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
                       uint2* pinfo, const float4* rec, const uint32_t* ns_tile,
                       const uint16_t* segl, const int32_t* ids, uint2* part,
-                      unsigned long long* counters, hipStream_t st);
+                      unsigned long long* counters, float* pix_t, float* pix_w, uint32_t* pix_n,
+                      hipStream_t st);
+// out[i] = bfloat16(in[i]) (round to nearest even), as bit patterns
+void launch_f32_to_bf16(uint64_t n, const float* in, uint16_t* out, hipStream_t st);
 void launch_merge(uint64_t npairs, const uint16_t* pview, const ViewDev* views, const uint2* pinfo,
                   const uint2* part, uint2* wrow, uint32_t* wlen, unsigned long long* nnz,
                   hipStream_t st);
