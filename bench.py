@@ -2,14 +2,18 @@
 """Throughput of the segment-embedding lift on one MI355X.
 
 One step = one full lift (tile segment tables, projection, depth sort,
-binning, tile sort, compositing with masking, merge, contraction and
-normalisation) of the 200k-Gaussian / 100-view / D=512 BF16 synthetic scene,
-with every input resident in HBM before the timed region.
+binning, tile sort, compositing with masking, contraction and normalisation)
+of the headline workload: 4M Gaussians in 200 clusters over 10 x 10 x 3,
+1000 nadir views of 1024x768 on a lawnmower path, 100-200 segments per view,
+D = 768 BF16 features (the large aerial scene of the paper's experiments,
+synthetic), with every input resident in HBM before the timed region.
 
 Prints one JSON line: views/s (value), Gaussian-pixel contributions/s, the
 dominant kernel's achieved rate against its roofline (from HIP events on the
-library's stream), and the FP64 CPU oracle's rate on a bounded sample of the
-same workload.
+library's stream), per-stage algorithmic lower bounds, the accuracy of the
+lift against the FP64 oracle on sampled views, the smaller workloads and the
+learned codec as secondary sections, and the FP64 CPU oracle's rate on a
+bounded sample of the headline workload.
 """
 from __future__ import annotations
 
@@ -17,6 +21,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -25,19 +30,32 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = "plain_bf16_200k"
-WORKLOAD_DESC = ("200k Gaussians in 20 anisotropic clusters, 100 spiral views 512x384, "
-                 "40-80 Voronoi segments/view + ~10% background, D=512 BF16 features")
 METRIC = "lift views/s + Gaussian-pixel contribs/s at 1 GPU"
+HEADLINE = "stress_4m"
+DESC = {
+    "stress_4m": "4M Gaussians from 200 clusters over 10x10x3, 1000 nadir views 1024x768 on a "
+                 "lawnmower path, 100-200 Voronoi segments/view, D=768 BF16 object-vocabulary "
+                 "features",
+    "uneven_1m": "1M Gaussians, 300 views of 320x240/640x480/1280x960 in one launch, 50-150 "
+                 "segments/view, D=512 BF16 object-vocabulary features",
+    "plain_bf16_200k": "200k Gaussians in 20 anisotropic clusters, 100 spiral views 512x384, "
+                       "40-80 Voronoi segments/view + ~10% background, D=512 BF16 features",
+    "plain_fp32_2k": "2,000 Gaussians, 4 ring views 64x64, 8 Voronoi segments/view, D=64 FP32 "
+                     "features",
+}
 
 # Peaks of one MI355X (vendor figures; 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz)
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12      # lane-operations per second (non-packed)
-# Minimal VALU issue slots per (pixel, Gaussian) support test of the blend
-# arithmetic: 2 sub, 5 mul/fma for the exponent, 1 clamp, exp2 (4 slots,
-# quarter rate), 1 mul + 1 min for alpha, 1 compare, 1 fma for T', 1 compare,
-# 1 mul for w, 1 select.
-OPS_PER_TEST = 19
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+# VALU work per (pixel, Gaussian) support test of the blend: quadratic form
+# about 7, exp about 5 (a multiply and the transcendental at four slots),
+# clamp/test 2, transmittance update/test 2 = 16 slot-operations.  The kernel
+# issues 19 slots per test (2 sub, 5 mul/fma, clamp, exp2 at 4, mul + min,
+# compare, fma, compare, mul, select); both fractions are reported, the
+# first one is the headline.
+OPS_PER_TEST = 16
+SLOTS_PER_TEST = 19
 
 
 def _log(*a):
@@ -49,10 +67,10 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(workload: str):
     """HBM bytes per compositing launch from the committed counter summary, if
     it was taken on the current kernel source and this workload; else None."""
-    p = os.path.join(ROOT, "profiles", f"composite_traffic_{WORKLOAD}.txt")
+    p = os.path.join(ROOT, "profiles", f"composite_traffic_{workload}.txt")
     if not os.path.exists(p):
         return None
     kv = {}
@@ -60,7 +78,7 @@ def measured_traffic():
         if ":" in line and not line.startswith(("|", "#", " ", "`")):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256_16") != kernel_source_hash() or kv.get("workload") != WORKLOAD:
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash() or kv.get("workload") != workload:
         return None
     try:
         return int(float(kv["bytes_per_launch"]))
@@ -68,19 +86,185 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(scene, budget_s: float):
-    import oracle
-    views = []
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def stage_bounds(scene, st, stage_ms, n_tests):
+    """Per-stage algorithmic lower bounds (ms) from the work the method must
+    do, each against the bound of its stage: HBM at 8 TB/s for the data
+    movement stages, the VALU lane-op peak for compositing."""
+    N, V, D = scene.n, scene.n_views, scene.dim
+    P = scene.pixels()
+    S = int(scene.nseg.sum())
+    pairs, ni = st["n_visible_pairs"], st["n_intersections"]
+    nnz = st["n_weights"]
+    nb = st["n_batches"]
+    fb = 2 if scene.feat_dtype == "bf16" else 4
+    by = {
+        # 4 B of segment id per pixel read, 2 B per tile-table entry (about one per tile)
+        "tile_segments": 4.0 * P,
+        # 44 B per Gaussian per launch read, 32 B record per visible pair written
+        "project": 44.0 * N * nb + 32.0 * pairs,
+        # one read and one write of an 8 B key + 4 B value per pair
+        "depth_sort": 24.0 * pairs,
+        # 32 B read per visible pair, 12 B written per intersection
+        "bin": 32.0 * pairs + 12.0 * ni,
+        # one read and one write of key + value per intersection
+        "tile_sort": 24.0 * ni,
+        # 8 B per non-zero partial read, feature table once, E and den written
+        "contract": 8.0 * nnz + fb * S * D + 4.0 * (D + 1) * N,
+    }
+    out = {}
+    lb_total = 0.0
+    for k, b in by.items():
+        lb = b / (HBM_PEAK_GBS * 1e9) * 1e3
+        out[k] = dict(bound="hbm", bytes=int(b), lb_ms=round(lb, 4),
+                      ms=round(stage_ms.get(k, 0.0), 4),
+                      frac=round(lb / stage_ms[k], 4) if stage_ms.get(k) else None)
+        lb_total += lb
+    if n_tests:
+        lb = n_tests * OPS_PER_TEST / (VALU_PEAK_TOPS * 1e12) * 1e3
+        out["composite"] = dict(bound="alu", ops=int(n_tests * OPS_PER_TEST), lb_ms=round(lb, 4),
+                                ms=round(stage_ms.get("composite", 0.0), 4),
+                                frac=round(lb / stage_ms["composite"], 4)
+                                if stage_ms.get("composite") else None)
+        lb_total += lb
+    return out, lb_total
+
+
+def measure(slag, torch, scene, steps, warmup, count=True, stage_steps=3, eager=False):
+    """Time K back-to-back lifts (graph replays) on one default-priority
+    stream with HIP events, then per-stage times from eager profiled lifts.
+    Returns a dict of measurements (and the embeddings of the timed lift)."""
+    V = scene.n_views
+    res = {}
+    if count:
+        # contributions, in-box tests and non-zero weights: a separate counting
+        # lift (not timed)
+        with slag.Lifter(0, flags=slag.SLAG_FLAG_COUNT | slag.SLAG_FLAG_KEEP_DEBUG) as Lc:
+            Lc.set_scene(scene, device_tensors=True)
+            Lc.lift()
+            st = Lc.stats()
+        res.update(n_contrib=st["n_contrib"], n_tests=st["n_tests"],
+                   n_tile_tests=st["n_tile_tests"], n_weights=st["n_weights"])
+        _log(f"{scene.name}: contributions {st['n_contrib']}, in-box tests {st['n_tests']}, "
+             f"tile tests {st['n_tile_tests']}, non-zero weights {st['n_weights']}")
+    flags = slag.SLAG_FLAG_PROFILE | slag.SLAG_FLAG_AUTOTUNE | (0 if eager else slag.SLAG_FLAG_GRAPH)
+    stream = torch.cuda.Stream()
+    L = slag.Lifter(0, stream=stream.cuda_stream, flags=flags)
+    t_up = time.perf_counter()
+    L.set_scene(scene, device_tensors=True)
+    torch.cuda.synchronize()
+    res["upload_s"] = round(time.perf_counter() - t_up, 3)
+    for _ in range(max(warmup, 1)):
+        L.lift()
+    L.embeddings()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    for v in range(scene.n_views):
-        views.append(v)
-        oracle.lift_view(scene, v)
-        if time.perf_counter() - t0 >= budget_s:
-            break
+    ev0.record(stream)
+    for _ in range(steps):
+        L.lift()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ev_ms = ev0.elapsed_time(ev1) / steps
+    ms = (t1 - t0) * 1e3 / steps
+    E, den = L.embeddings()
+    assert np.isfinite(E).all()
+    info = L.stats()
+    res["tuning"] = slag.slag_get_tuning(L.ctx)
+    L.close()
+    res.update(ms_step=ms, ms_hip_events=ev_ms, views_per_s=V / (ms * 1e-3),
+               n_visible_pairs=info["n_visible_pairs"], n_intersections=info["n_intersections"],
+               n_part_slots=info["n_part_slots"], n_batches=info["n_batches"])
+    _log(f"{scene.name}: step {ms:.3f} ms wall, {ev_ms:.3f} ms HIP events "
+         f"({'eager' if eager else 'graph replay'}), {info['n_batches']} launch(es)")
+    stage_ms = {}
+    with slag.Lifter(0, flags=slag.SLAG_FLAG_PROFILE | slag.SLAG_FLAG_AUTOTUNE) as Lp:
+        Lp.set_scene(scene, device_tensors=True)
+        Lp.lift()
+        Lp.stats()
+        for _ in range(stage_steps):
+            Lp.lift()
+            for k, v in Lp.stats()["ms_stage"].items():
+                stage_ms[k] = stage_ms.get(k, 0.0) + v
+    res["stage_ms"] = {k: v / stage_steps for k, v in stage_ms.items()}
+    _log(f"{scene.name}: stage ms", json.dumps({k: round(v, 4) for k, v in res["stage_ms"].items()}))
+    if count:
+        res["contribs_per_s"] = res["n_contrib"] / (ms * 1e-3)
+        st = dict(n_visible_pairs=res["n_visible_pairs"], n_intersections=res["n_intersections"],
+                  n_weights=res["n_weights"], n_batches=res["n_batches"])
+        res["stages"], lb = stage_bounds(scene, st, res["stage_ms"], res["n_tests"])
+        res["lift_lb_ms"] = lb
+        res["lift_roofline_frac"] = lb / ms
+    return res, E, den
+
+
+def composite_roofline(res, workload):
+    comp = res["stage_ms"].get("composite", 0.0)
+    if not res.get("n_tests") or comp <= 0:
+        return None
+    ach = res["n_tests"] * OPS_PER_TEST / (comp * 1e-3) / 1e12
+    ach19 = res["n_tests"] * SLOTS_PER_TEST / (comp * 1e-3) / 1e12
+    return dict(kernel="k_composite", bound="alu", achieved=round(ach, 4),
+                peak=round(VALU_PEAK_TOPS, 3), unit="Tops/s", frac=round(ach / VALU_PEAK_TOPS, 4),
+                traffic=measured_traffic(workload), ops_per_test=OPS_PER_TEST,
+                frac_issued_slots=round(ach19 / VALU_PEAK_TOPS, 4),
+                slots_per_test=SLOTS_PER_TEST, tests_per_launch=res["n_tests"],
+                avg_launch_ms=round(comp, 4),
+                dominant_stage=max(res["stage_ms"], key=res["stage_ms"].get))
+
+
+def accuracy_and_cpu(slag, scene, views, budget_s):
+    """The FP64 oracle lift of sampled views (timed: the CPU baseline) and the
+    GPU lift of the same views (all Gaussians), compared per Gaussian:
+    minimum cosine, maximum absolute error, and the propagated error bound."""
+    import oracle
+    sub = scene.subset_views(views)
+    t0 = time.perf_counter()
+    ref = oracle.lift(sub)
     dt = time.perf_counter() - t0
-    return dict(value=len(views) / dt, unit="views/s", cores=oracle.max_threads(), kind="oracle",
-                sample=f"first {len(views)} of {scene.n_views} views of the same scene "
-                       f"(per-view W_v lift, FP64, box candidates), {dt:.1f} s wall")
+    with slag.Lifter(0) as L:
+        L.set_scene(sub, device_tensors=True)
+        L.lift()
+        E, den = L.embeddings()
+    F = sub.feats_f64()
+    fmax = float(np.linalg.norm(F, axis=1).max()) if F.size else 1.0
+    bound, vanish = oracle.embedding_bound(ref, fmax, sub.n_views,
+                                           bf16_split=sub.feat_dtype == "bf16")
+    nz = ref.den > 0
+    cmp = nz & ~vanish & (den > 0)
+    a, b = E[cmp].astype(np.float64), ref.E[cmp]
+    err = np.linalg.norm(a - b, axis=1)
+    na, nb_ = np.linalg.norm(a, axis=1), np.linalg.norm(b, axis=1)
+    cos = np.sum(a * b, 1) / (na * nb_ + 1e-300)
+    implied = bound[cmp] <= np.sqrt(2.0 * 1e-4) * nb_
+    acc = dict(views=[int(v) for v in views], gaussians=int(nz.sum()),
+               min_cos=float(cos.min()) if cos.size else None,
+               frac_cos_ge_09999=float((cos >= 0.9999).mean()) if cos.size else None,
+               max_abs_err=float(err.max()) if err.size else None,
+               max_err_over_bound=float((err / bound[cmp]).max()) if err.size else None,
+               median_bound=float(np.median(bound[cmp])) if err.size else None,
+               frac_bound_implies_09999=float(implied.mean()) if cos.size else None,
+               zero_rows_agree=bool(np.array_equal(den > 0, nz)),
+               reference="FP64 oracle (per-pixel full depth sort, no tiles)")
+    cpu = dict(value=len(views) / dt, unit="views/s", cores=oracle.max_threads(), kind="oracle",
+               cpu_model=cpu_model(),
+               sample=f"views {list(views)} of the {scene.n_views}-view workload (all "
+                      f"{scene.n} Gaussians; per-view W_v in FP64 + contraction), {dt:.1f} s wall; "
+                      f"the whole workload extrapolates linearly in views (the lift is additive "
+                      f"over views) to {scene.n_views * dt / len(views):.0f} s",
+               extrapolated_workload_s=round(scene.n_views * dt / len(views), 1))
+    return acc, cpu
 
 
 def codec_section(args, slag, torch):
@@ -131,8 +315,7 @@ def codec_section(args, slag, torch):
     nz = den > 0
     a, b = E_plain[nz].astype(np.float64), E_codec[nz].astype(np.float64)
     cos = np.sum(a * b, 1) / (np.linalg.norm(a, axis=1) * np.linalg.norm(b, axis=1) + 1e-300)
-    out = dict(workload="uneven_1m", desc="1M Gaussians, 300 views of 320x240/640x480/1280x960, "
-               "50-150 segments/view, D=512 BF16 object-vocabulary features",
+    out = dict(workload="uneven_1m", desc=DESC["uneven_1m"],
                k=k, hidden=h, precision="bf16",
                plain_views_per_s=round(V / (ms_plain * 1e-3), 2),
                codec_views_per_s=round(V / (ms_codec * 1e-3), 2),
@@ -151,15 +334,21 @@ def codec_section(args, slag, torch):
     return out
 
 
+def _round(d):
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-budget", type=float, default=15.0,
-                    help="seconds of oracle work for the CPU baseline (0 = skip)")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=HEADLINE, choices=sorted(DESC))
+    ap.add_argument("--cpu-views", type=int, default=4,
+                    help="views of the workload the CPU oracle lifts (baseline + accuracy; 0 = skip)")
     ap.add_argument("--no-count", action="store_true", help="skip the counting lift")
     ap.add_argument("--eager", action="store_true", help="time eager lifts instead of graph replays")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the smaller workloads")
     ap.add_argument("--no-codec", action="store_true", help="skip the codec section")
     ap.add_argument("--codec-steps", type=int, default=2000)
     ap.add_argument("--codec-k", type=int, default=16, help="code size (16, 32, 48 or 64)")
@@ -179,21 +368,6 @@ def main():
     import paper_2505_08124_amd as slag
     from synthetic import make_scene
 
-    _log("generating scene", WORKLOAD)
-    scene = make_scene(WORKLOAD)
-    V = scene.n_views
-
-    # contributions and in-box tests (a separate counting lift, not timed)
-    n_contrib = n_tests = None
-    if not args.no_count:
-        with slag.Lifter(0, flags=slag.SLAG_FLAG_COUNT) as Lc:
-            Lc.set_scene(scene, device_tensors=True)
-            Lc.lift()
-            st = Lc.stats()
-            n_contrib, n_tests = st["n_contrib"], st["n_tests"]
-            n_tile_tests = st["n_tile_tests"]
-        _log(f"contributions {n_contrib}, in-box tests {n_tests}, tile tests {n_tile_tests}")
-
     if args.copy_calib > 0:
         # elementwise kernel reading and writing exactly copy_calib bytes
         x = torch.ones(args.copy_calib // 4, dtype=torch.float32, device="cuda")
@@ -204,99 +378,83 @@ def main():
         _log(f"copy calibration: {args.copy_calib} bytes read and written")
         del x, y
 
-    # timed region: graph replays of the whole lift (the first lift runs
-    # eagerly and captures the launch sequence; warm-up covers it)
-    flags = slag.SLAG_FLAG_PROFILE | slag.SLAG_FLAG_AUTOTUNE | \
-        (0 if args.eager else slag.SLAG_FLAG_GRAPH)
-    # the library runs on this (default-priority) stream, so HIP events on it
-    # bracket the K lifts; the lifts are issued back to back, no host
-    # synchronisation between them
-    stream = torch.cuda.Stream()
-    L = slag.Lifter(0, stream=stream.cuda_stream, flags=flags)
-    L.set_scene(scene, device_tensors=True)
-    for _ in range(max(args.warmup, 1)):
-        L.lift()
-    L.embeddings()
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    wl = args.workload
+    _log("generating scene", wl)
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        L.lift()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ev_total = ev0.elapsed_time(ev1)
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    _log(f"step {ms_step:.3f} ms wall, {ev_total / args.steps:.3f} ms HIP events "
-         f"({'eager' if args.eager else 'graph replay'})")
-    E, den = L.embeddings()
-    assert np.isfinite(E).all()
-    info = L.stats()
-    tuning = slag.slag_get_tuning(L.ctx)
-    _log("tuning:", json.dumps(tuning))
-    L.close()
+    scene = make_scene(wl)
+    _log(f"generated in {time.perf_counter() - t0:.1f} s")
+    V, N, D = scene.n_views, scene.n, scene.dim
+    res, _, _ = measure(slag, torch, scene, args.steps, args.warmup, count=not args.no_count,
+                        stage_steps=3 if scene.n >= 1_000_000 else args.steps, eager=args.eager)
+    roof = composite_roofline(res, wl)
 
-    # per-stage HIP events (same kernels, launched eagerly on the library's
-    # stream; a graph replay records no per-stage events)
-    stage_ms = {}
-    with slag.Lifter(0, flags=slag.SLAG_FLAG_PROFILE | slag.SLAG_FLAG_AUTOTUNE) as Lp:
-        Lp.set_scene(scene, device_tensors=True)
-        Lp.lift()
-        Lp.stats()
-        for _ in range(args.steps):
-            Lp.lift()
-            for k, v in Lp.stats()["ms_stage"].items():
-                stage_ms[k] = stage_ms.get(k, 0.0) + v
-    stage_ms = {k: v / args.steps for k, v in stage_ms.items()}
-    _log("stage ms:", json.dumps({k: round(v, 4) for k, v in stage_ms.items()}))
+    accuracy = cpu = None
+    if args.cpu_views > 0:
+        k = min(args.cpu_views, V)
+        views = sorted(set(int(round(i * (V - 1) / max(k - 1, 1))) for i in range(k)))
+        _log(f"CPU oracle on views {views} (baseline and accuracy)")
+        accuracy, cpu = accuracy_and_cpu(slag, scene, views, 0)
+        _log("accuracy:", json.dumps(accuracy))
+    del scene
 
-    dom = max(stage_ms, key=stage_ms.get)
-    comp_ms = stage_ms.get("composite", 0.0)
-    roof = None
-    if n_tests is not None and comp_ms > 0:
-        ach = n_tests * OPS_PER_TEST / (comp_ms * 1e-3) / 1e12
-        roof = dict(kernel="k_composite", bound="alu", achieved=round(ach, 4),
-                    peak=round(VALU_PEAK_TOPS, 3), unit="Tops/s",
-                    frac=round(ach / VALU_PEAK_TOPS, 4), traffic=measured_traffic(),
-                    ops_per_test=OPS_PER_TEST, tests_per_launch=n_tests,
-                    avg_launch_ms=round(comp_ms, 4), dominant_stage=dom)
+    secondary = []
+    if not args.no_secondary:
+        for w in ("plain_bf16_200k", "uneven_1m", "plain_fp32_2k"):
+            if w == wl:
+                continue
+            _log("secondary workload", w)
+            sc = make_scene(w)
+            r, _, _ = measure(slag, torch, sc, max(args.steps, 10), args.warmup,
+                              stage_steps=5 if sc.n >= 1_000_000 else 10)
+            ro = composite_roofline(r, w)
+            secondary.append(dict(
+                workload=w, desc=DESC[w], n_gaussians=sc.n, n_views=sc.n_views,
+                feature_dim=sc.dim, feature_dtype=sc.feat_dtype,
+                views_per_s=round(r["views_per_s"], 2), ms_per_step=round(r["ms_step"], 4),
+                contribs_per_s=round(r["contribs_per_s"], 1), n_contrib=r["n_contrib"],
+                composite_frac=ro["frac"] if ro else None,
+                lift_roofline_frac=round(r["lift_roofline_frac"], 4),
+                stage_ms={k: round(v, 4) for k, v in r["stage_ms"].items()},
+                launches=r["n_batches"]))
+            del sc
 
     codec = None
     if not args.no_codec:
         codec = codec_section(args, slag, torch)
 
-    cpu = None
-    if args.cpu_budget > 0:
-        _log("timing the CPU oracle")
-        cpu = cpu_baseline(scene, args.cpu_budget)
-
+    ms = res["ms_step"]
     out = {
         "metric": METRIC,
-        "value": round(V / (ms_step * 1e-3), 2),
+        "value": round(V / (ms * 1e-3), 2),
         "unit": "views/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(ms, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16" if wl != "plain_fp32_2k" else "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "desc": WORKLOAD_DESC, "n_gaussians": scene.n,
-                   "n_views": V, "resolution": [512, 384], "feature_dim": scene.dim,
-                   "feature_dtype": "bf16", "parallelism": "single GPU"},
-        "contribs_per_s": (round(n_contrib / (ms_step * 1e-3), 1) if n_contrib else None),
-        "n_contrib": n_contrib,
-        "n_visible_pairs": info["n_visible_pairs"],
-        "n_intersections": info["n_intersections"],
-        "ms_per_step_hip_events": round(ev_total / args.steps, 4),
+        "config": {"workload": wl, "desc": DESC[wl], "n_gaussians": N, "n_views": V,
+                   "feature_dim": D, "parallelism": "single GPU"},
+        "contribs_per_s": round(res["contribs_per_s"], 1) if "contribs_per_s" in res else None,
+        "n_contrib": res.get("n_contrib"),
+        "n_visible_pairs": res["n_visible_pairs"],
+        "n_intersections": res["n_intersections"],
+        "n_weights": res.get("n_weights"),
+        "launches": res["n_batches"],
+        "ms_per_step_hip_events": round(res["ms_hip_events"], 4),
         "launch": "eager" if args.eager else "hip graph replay",
-        "tuning": tuning,
-        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "upload_s": res["upload_s"],
+        "tuning": res["tuning"],
+        "stage_ms": {k: round(v, 4) for k, v in res["stage_ms"].items()},
         "roofline": roof,
+        "stage_roofline": res.get("stages"),
+        "lift_roofline_frac": round(res["lift_roofline_frac"], 4) if "lift_roofline_frac" in res
+        else None,
+        "accuracy": accuracy,
+        "secondary": secondary,
         "codec": codec,
         "cpu_baseline": cpu,
     }

@@ -79,7 +79,15 @@ enum {
 typedef struct {
     int32_t max_views_per_launch;   /* 0 = as many as fit (all views if possible) */
     int32_t flags;                  /* SLAG_FLAG_* */
-    int64_t reserved[6];
+    /* Cap on the tile intersections and on the part slots of one launch
+     * (0 = 2^32 - 16, the limit of the 32-bit list positions).  An eager lift
+     * whose launch would exceed it re-plans with half the views per launch
+     * and starts over, until every launch fits (a launch of one view that
+     * does not fit is SLAG_E_CAPACITY); the context keeps the smaller plan
+     * until the Gaussians or cameras change.  Results do not depend on the
+     * plan beyond FP32 rounding of the contraction. */
+    int64_t max_launch_entries;
+    int64_t reserved[5];
 } slag_options;
 
 typedef struct {

@@ -201,7 +201,8 @@ def embedding_bound(ref: LiftResult, fmax: float, n_views: int, bf16_split: bool
     mask of Gaussians whose weight could vanish (den <= B).
 
     With W perturbed by dW (|dW_s| <= b_s, sum b_s = B): E' - E =
-    sum_s dW_s (F_s - E) / (den + sum dW), so ||E' - E|| <= 2 fmax B / (den - B).
+    sum_s dW_s (F_s - E) / (den + sum dW), and ||F_s - E|| <= fmax + ||E||
+    (triangle inequality), so ||E' - E|| <= (fmax + ||E||) B / (den - B).
     The contraction adds the hi/lo split of W (2^-18 relative), FP32
     accumulation of the products (at most nnz + 64 roundings of partial sums
     bounded by fmax den) and the per-view FP32 sums of den (n_views
@@ -212,7 +213,7 @@ def embedding_bound(ref: LiftResult, fmax: float, n_views: int, bf16_split: bool
     out = np.zeros_like(den)
     split = 2.0 ** -18 if bf16_split else 0.0
     d = np.where(ok, den - B, 1.0)
-    e_w = 2.0 * fmax * B / d
+    e_w = (fmax + np.linalg.norm(ref.E, axis=1)) * B / d
     e_c = fmax * (split + (ref.nnz + 64 + n_views) * u) * den / d
     out[ok] = (e_w + e_c)[ok] + u * np.linalg.norm(ref.E[ok], axis=1)
     return out, ~ok & (den > 0)

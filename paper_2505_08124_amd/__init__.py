@@ -41,7 +41,7 @@ class slag_camera(ctypes.Structure):
 
 class slag_options(ctypes.Structure):
     _fields_ = [("max_views_per_launch", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int64 * 6)]
+                ("max_launch_entries", ctypes.c_int64), ("reserved", ctypes.c_int64 * 5)]
 
 
 class slag_stats(ctypes.Structure):
@@ -72,7 +72,9 @@ EXPORTS = ["slag_create", "slag_destroy", "slag_last_error", "slag_set_gaussians
            # include/slag_codec.h
            "slag_codec_init", "slag_codec_get_params", "slag_codec_clear_pool",
            "slag_codec_set_pool", "slag_codec_add_lift_rows", "slag_codec_pool_size",
-           "slag_codec_loss_grad", "slag_codec_train", "slag_lift_codec", "slag_get_codes"]
+           "slag_codec_loss_grad", "slag_codec_train", "slag_lift_codec", "slag_get_codes",
+           # include/slag_query.h
+           "slag_query", "slag_classify"]
 
 _lib_handle = None
 
@@ -126,6 +128,9 @@ def lib():
     L.slag_codec_train.argtypes = [P, ctypes.POINTER(slag_train_cfg), P]
     L.slag_lift_codec.argtypes = [P]
     L.slag_get_codes.argtypes = [P, P, I32]
+    L.slag_query.argtypes = [P, I64, I32, P, I32, I32, P, I32, ctypes.c_float, I32,
+                             ctypes.POINTER(I64), P, P, I32]
+    L.slag_classify.argtypes = [P, I64, I32, P, I32, I32, P, I32, P, P, I32]
     for f in EXPORTS:
         if f not in ("slag_destroy", "slag_last_error", "slag_stage_name", "slag_variant_name"):
             getattr(L, f).restype = I32
@@ -160,8 +165,9 @@ def _ptr(a):
 
 # ---------------------------------------------------------------- C names
 
-def slag_create(device: int = 0, stream=None, max_views_per_launch: int = 0, flags: int = 0):
-    o = slag_options(max_views_per_launch, flags)
+def slag_create(device: int = 0, stream=None, max_views_per_launch: int = 0, flags: int = 0,
+                max_launch_entries: int = 0):
+    o = slag_options(max_views_per_launch, flags, max_launch_entries)
     h = ctypes.c_void_p()
     st = lib().slag_create(device, ctypes.c_void_p(stream) if stream else None, ctypes.byref(o),
                            ctypes.byref(h))
@@ -348,14 +354,54 @@ def slag_get_codes(ctx, out):
     _check(ctx, lib().slag_get_codes(ctx, p, w))
 
 
+def slag_query(ctx, emb, queries, threshold: float = 0.0, k: int = 0, out=None):
+    """Cosine-similarity search: returns (count[Q], top_idx[Q][k], top_cos[Q][k]).
+    emb [n][d] and queries [Q][d]: float32 NumPy arrays or CUDA tensors.  The
+    top-k rows go to `out` = (idx, cos) when given (NumPy or CUDA tensors),
+    else to new NumPy arrays."""
+    n, d = int(emb.shape[0]), int(emb.shape[1])
+    nq = int(queries.shape[0])
+    pe, we = _ptr(emb)
+    pq, wq = _ptr(queries)
+    cnt = np.zeros(nq, np.int64)
+    if out is None:
+        idx = np.empty((nq, k), np.uint32)
+        cs = np.empty((nq, k), np.float32)
+    else:
+        idx, cs = out
+    pi, wo = _ptr(idx) if k > 0 else (None, SLAG_HOST)
+    pc, _ = _ptr(cs) if k > 0 else (None, SLAG_HOST)
+    _check(ctx, lib().slag_query(ctx, n, d, pe, we, nq, pq, wq, float(threshold), int(k),
+                                 cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), pi, pc, wo))
+    return cnt, idx, cs
+
+
+def slag_classify(ctx, emb, classes, out=None):
+    """Per-Gaussian class of highest cosine: returns (label[n], best[n]);
+    `out` = (label, best) tensors or arrays to write into."""
+    n, d = int(emb.shape[0]), int(emb.shape[1])
+    nc = int(classes.shape[0])
+    pe, we = _ptr(emb)
+    pq, wq = _ptr(classes)
+    if out is None:
+        lab = np.empty(n, np.int32)
+        best = np.empty(n, np.float32)
+    else:
+        lab, best = out
+    pl, wo = _ptr(lab)
+    pb, _ = _ptr(best)
+    _check(ctx, lib().slag_classify(ctx, n, d, pe, we, nc, pq, wq, pl, pb, wo))
+    return lab, best
+
+
 # ---------------------------------------------------------------- convenience
 
 class Lifter:
     """One context on one device: upload a scene, lift, fetch."""
 
     def __init__(self, device: int = 0, stream=None, max_views_per_launch: int = 0,
-                 flags: int = 0):
-        self.ctx = slag_create(device, stream, max_views_per_launch, flags)
+                 flags: int = 0, max_launch_entries: int = 0):
+        self.ctx = slag_create(device, stream, max_views_per_launch, flags, max_launch_entries)
         self.n = 0
         self.d = 0
 

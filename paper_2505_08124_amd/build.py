@@ -14,7 +14,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SLAG_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["k_project.hip", "k_sort.hip", "k_raster.hip", "k_contract.hip", "k_codec.hip",
-           "slag_api.cpp", "slag_codec.cpp"]
+           "k_query.hip", "slag_api.cpp", "slag_codec.cpp", "slag_query.cpp"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

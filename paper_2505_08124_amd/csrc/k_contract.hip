@@ -152,8 +152,14 @@ __device__ __forceinline__ uint32_t block_exscan(uint32_t x, uint32_t* scratch, 
     return off + v - x;
 }
 
+// Three workgroups per CU while the accumulators fit beside the walk's
+// registers (NT <= 8 column tiles per wave, D <= 512); wider rows take two,
+// so that the 12 or 16 accumulator tiles of D = 768 or 1024 do not spill.
+template <int NT>
+constexpr int contract_min_blocks() { return NT <= 8 ? 3 : 2; }
+
 template <int NT, bool BF16, int RT>
-__global__ __launch_bounds__(256, 3) void k_contract_mfma(
+__global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfma(
     int64_t n, int nb, int d, const uint32_t* __restrict__ perm,
     const uint32_t* __restrict__ pair_of_m, const ViewDev* __restrict__ views,
     const uint2* __restrict__ pinfo,

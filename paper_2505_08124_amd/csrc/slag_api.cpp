@@ -205,6 +205,7 @@ static slag_status build_plan(slag_ctx* c)
     c->plan.clear();
     const int V = c->nviews;
     int maxv = c->opt.max_views_per_launch > 0 ? c->opt.max_views_per_launch : V;
+    if (c->auto_maxv > 0) maxv = std::min(maxv, c->auto_maxv);   // set by an earlier re-plan
     maxv = std::min(maxv, 65535);
     // keep (view, Gaussian) indices and tile-list positions in 32 bits
     const int64_t n = std::max<int64_t>(c->n, 1);
@@ -410,9 +411,18 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         }
         ni = B.ni;
         nparts = B.nparts;
-        if (ni > 0xFFFFFFF0ull || nparts > 0xFFFFFFF0ull)
-            FAIL(c, SLAG_E_CAPACITY, "too many tile intersections in one launch; lower "
-                                     "max_views_per_launch");
+        const uint64_t cap = c->opt.max_launch_entries > 0
+                                 ? std::min<uint64_t>((uint64_t)c->opt.max_launch_entries, 0xFFFFFFF0ull)
+                                 : 0xFFFFFFF0ull;
+        if (ni > cap || nparts > cap) {
+            // 32-bit list positions would overflow: an eager lift re-plans
+            // with fewer views per launch (run_lift halves the batch and
+            // starts over); nothing has been written to the outputs yet
+            // that the restart does not overwrite
+            c->replan_views = nb > 1 ? (nb + 1) / 2 : 0;
+            FAIL(c, SLAG_E_CAPACITY, "too many tile intersections in one launch of " +
+                                         std::to_string(nb) + " views");
+        }
     }
     c->stats.n_visible_pairs += (int64_t)npairs;
     c->stats.n_intersections += (int64_t)ni;
@@ -676,7 +686,9 @@ void slag_destroy(slag_ctx* c)
                       &c->pinfo, &c->prect, &c->prank, &c->blk_aux, &c->bkey,
                       &c->bkey_alt, &c->bord, &c->bord_alt, &c->tflag, &c->tpos, &c->tv,
                       &c->tv_alt, &c->tg, &c->thead, &c->tk, &c->tk_alt, &c->pixdbg,
-                      &c->outbf};
+                      &c->outbf, &c->query.emb, &c->query.q, &c->query.qt, &c->query.counts,
+                      &c->query.keys, &c->query.vals, &c->query.keys_alt, &c->query.vals_alt,
+                      &c->query.hist, &c->query.scan_ws};
     destroy_graph(c);
     for (DevBuf* b : bufs) release(*b);
     codec_release(c);
@@ -751,6 +763,7 @@ slag_status slag_set_gaussians(slag_ctx* c, int64_t n, const float* means, const
     CK(morton_order(c, n));
     c->n = n;
     c->plan_views = -1;   // launch sizes depend on n
+    c->auto_maxv = 0;
     return SLAG_OK;
 }
 
@@ -786,6 +799,7 @@ slag_status slag_set_cameras(slag_ctx* c, int32_t n_views, const slag_camera* ca
     c->feats_set = false;
     c->have_out = false;
     c->plan_views = -1;
+    c->auto_maxv = 0;
     return SLAG_OK;
 }
 
@@ -962,7 +976,19 @@ slag_status run_lift(slag_ctx* c, bool codec)
         CK(ensure(c, c->num, (size_t)std::max<int64_t>(n, 1) * c->d * 4));
         CK(ensure(c, c->den, (size_t)std::max<int64_t>(n, 1) * 4));
         if (c->plan_views != c->nviews) CK(build_plan(c));
-        CK(lift_sequence(c, codec));
+        for (;;) {
+            c->replan_views = 0;
+            const slag_status s = lift_sequence(c, codec);
+            if (s == SLAG_OK) break;
+            // a launch too large for 32-bit list positions: fewer views per
+            // launch, then the whole sequence again (the first batch rewrites
+            // the outputs)
+            if (s != SLAG_E_CAPACITY || c->replan_views <= 0) return s;
+            c->auto_maxv = c->replan_views;
+            std::memset(&c->stats, 0, sizeof(c->stats));
+            c->last_v0 = -1;
+            CK(build_plan(c));
+        }
         c->stats.n_views = c->nviews;
         c->stats.n_batches = (int64_t)c->plan.size();
     }

@@ -73,6 +73,12 @@ struct CodecState {
     bool have_codes = false;
 };
 
+// Work arrays of the cosine-similarity search (library-allocated; kept
+// between calls).
+struct QueryState {
+    DevBuf emb, q, qt, counts, keys, vals, keys_alt, vals_alt, hist, scan_ws;
+};
+
 }  // namespace slag_host
 
 struct slag_ctx {
@@ -106,6 +112,8 @@ struct slag_ctx {
 
     std::vector<slag_host::Batch> plan;
     int plan_views = -1;
+    int auto_maxv = 0;                // views per launch found by a re-plan (0 = no limit)
+    int replan_views = 0;             // set by a launch that overflowed: views to try instead
 
     // workspace
     slag_host::DevBuf ns_tile, segl, sat, tcnt, blk_vis, small, scan_ws, hist;
@@ -119,6 +127,7 @@ struct slag_ctx {
     uint64_t* host_small = nullptr;   // pinned read-back area
 
     slag_host::CodecState codec;
+    slag_host::QueryState query;
 
     // compositing variant per image size (SLAG_FLAG_AUTOTUNE), and the events that time them
     std::map<uint64_t, slag_host::TuneEntry> tune;

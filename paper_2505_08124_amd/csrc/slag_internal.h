@@ -217,4 +217,18 @@ void launch_row_gather(int64_t n, int nb, uint32_t rows, const uint32_t* gid, co
 void launch_copy_rows(uint32_t rows, int d, const uint32_t* gid, const float* src, float* dst,
                       hipStream_t st);
 
+// cosine-similarity search (k_query.hip): unit queries transposed to
+// qt[d][qp] (qp = nq rounded up to 16; err |= 1 for a zero or non-finite
+// query); scores of every (query, Gaussian) with per-query counts of
+// scores >= thr (counts zeroed by the caller) and, if keys != null, sort keys
+// and indices at [q n + g]; the class of highest score per Gaussian; the
+// first k entries of each query's sorted list
+void launch_qprep(int nq, int qp, int d, const float* q, float* qt, uint32_t* err, hipStream_t st);
+void launch_scores(int nq, int64_t n, int d, const float* E, const float* qt, float thr,
+                   uint32_t* keys, uint32_t* vals, unsigned long long* counts, hipStream_t st);
+void launch_classify(int nc, int64_t n, int d, const float* E, const float* qt, int32_t* label,
+                     float* best, hipStream_t st);
+void launch_topk_out(int nq, int k, int64_t n, const uint32_t* keys, const uint32_t* vals,
+                     uint32_t* idx, float* cosv, hipStream_t st);
+
 }  // namespace slag

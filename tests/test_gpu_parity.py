@@ -10,10 +10,13 @@ CPU in ``tests/test_oracle_error_model.py``), none fitted to observed errors:
     of every (view, Gaussian, segment) triple with U = 0;
   * den within the sum of its triples' bounds plus the per-view FP32 sums;
   * embeddings: ||E_gpu - E_orc|| <= the propagated bound
-    (oracle.embedding_bound), and cosine >= 0.9999 for every Gaussian whose
-    bound guarantees it; the Gaussians whose bound does not (decisions in
-    band carrying more than ~1% of their weight) are counted and capped at
-    0.1 %; zero rows exactly where the oracle's den is 0 and no decision
+    (oracle.embedding_bound) for every Gaussian, and cosine >= 0.9999 for
+    every Gaussian whose bound guarantees it; a Gaussian whose bound does not
+    (its weight is mostly decisions inside their FP32 band: alpha within
+    rounding of 1/255 over most of its footprint) may fall below 0.9999 only
+    within its bound, and such Gaussians are capped at 0.1 % of those with
+    weight; both counts, and the weight share of the uncertified ones, are
+    recorded; zero rows exactly where the oracle's den is 0 and no decision
     could make it positive.
 Each check appends one JSON line of statistics to $SLAG_PARITY_LOG when set.
 """
@@ -32,7 +35,7 @@ pytestmark = pytest.mark.gpu
 
 COS_MIN = 0.9999
 U32 = 2.0 ** -24
-MAX_UNCOMPARED = 1e-3      # fraction of Gaussians whose bound does not imply COS_MIN
+MAX_UNCOMPARED = 1e-3      # fraction of Gaussians below COS_MIN (each uncertified by its bound)
 
 
 def _say(*a):
@@ -114,23 +117,28 @@ def check_embeddings(E, den, ref, scene, tag=""):
     Eg = E[cmp].astype(np.float64)
     Eo = ref.E[cmp]
     eerr = np.linalg.norm(Eg - Eo, axis=1)
-    assert np.all(eerr <= bound[cmp]), (eerr / bound[cmp]).max()
     no = np.linalg.norm(Eo, axis=1)
     cos = np.sum(Eg * Eo, 1) / (np.linalg.norm(Eg, axis=1) * no + 1e-300)
     # a bound b on ||dE|| gives 1 - cos <= (b / |E|)^2 / 2
     implied = bound[cmp] <= np.sqrt(2.0 * (1.0 - COS_MIN)) * no
-    assert cos[implied].min() >= COS_MIN, cos[implied].min()
-    frac_unc = 1.0 - implied.sum() / max(int(nz.sum()), 1)
-    assert frac_unc <= MAX_UNCOMPARED, frac_unc
+    ngz = max(int(nz.sum()), 1)
+    below = cos < COS_MIN
     st = dict(check="embeddings", case=tag, gaussians=int(nz.sum()),
               min_cos=float(cos.min()) if cos.size else 1.0,
               min_cos_bound_implied=float(cos[implied].min()) if implied.any() else 1.0,
-              frac_not_implied=float(frac_unc), n_not_implied=int(nz.sum() - implied.sum()),
+              frac_not_implied=float(1.0 - implied.sum() / ngz),
+              n_not_implied=int(nz.sum() - implied.sum()),
+              weight_share_not_implied=float(ref.den[cmp][~implied].sum() / ref.den[nz].sum())
+              if nz.any() else 0.0,
+              n_cos_below=int(below.sum()), frac_cos_below=float(below.sum() / ngz),
               max_abs_err=float(eerr.max()) if eerr.size else 0.0,
               max_err_over_bound=float((eerr / bound[cmp]).max()) if eerr.size else 0.0,
               median_bound=float(np.median(bound[cmp])) if eerr.size else 0.0,
               max_den_rel_err=float((derr[nz] / ref.den[nz]).max()) if nz.any() else 0.0)
     _record(**st)
+    assert np.all(eerr <= bound[cmp]), (eerr / bound[cmp]).max()
+    assert not np.any(below & implied), cos[implied].min()
+    assert st["frac_cos_below"] <= MAX_UNCOMPARED, st
     return st["min_cos"], st["max_abs_err"]
 
 

@@ -127,3 +127,30 @@ def test_transmittance_bound_covers_the_fp32_walk(oracle_2k, scene_2k):
         assert ok.mean() > 0.99
         err = np.abs(r32.T[ok] - r64.T[ok])
         assert np.all(err <= r64.rho[ok] * r64.T[ok] + 2.0 ** -24), (err / r64.T[ok]).max()
+
+
+@pytest.mark.parametrize("case", ["plain_fp32_2k", "plain_bf16_200k[2 views]"])
+def test_embedding_bound_covers_the_fp32_walk(case):
+    """Embeddings contracted from the FP32 re-walk's weights stay within the
+    propagated embedding bound of the FP64 lift (the aggregation equation
+    perturbed by the weight errors), Gaussian by Gaussian."""
+    if case == "plain_fp32_2k":
+        sc = make_scene("plain_fp32_2k")
+    else:
+        sc = make_scene("plain_bf16_200k", views=dict(n=2))
+    views = list(range(sc.n_views))
+    ref = oracle.lift(sc)
+    r32 = [oracle.lift_view(sc, v, fp32=True) for v in views]
+    W32 = oracle.weight_matrix(sc, views, r32)
+    F = sc.feats_f64()
+    den32 = np.asarray(W32.sum(axis=1)).ravel()
+    num32 = np.asarray(W32 @ F)
+    fmax = float(np.linalg.norm(F, axis=1).max())
+    bound, vanish = oracle.embedding_bound(ref, fmax, sc.n_views,
+                                           bf16_split=sc.feat_dtype == "bf16")
+    ok = (ref.den > 0) & ~vanish & (den32 > 0)
+    E32 = num32[ok] / den32[ok, None]
+    err = np.linalg.norm(E32 - ref.E[ok], axis=1)
+    assert np.all(err <= bound[ok]), (err / bound[ok]).max()
+    assert ok.sum() > 0.9 * (ref.den > 0).sum()
+    print(f"{case}: max error / bound {(err / bound[ok]).max():.3g}")
