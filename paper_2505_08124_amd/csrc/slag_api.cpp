@@ -1001,7 +1001,11 @@ slag_status run_lift(slag_ctx* c, bool codec)
     if (use_graph && !replay && c->n > 0) {
         c->graph_stats = c->stats;
         for (int i = 0; i < 16; i++) c->graph_stats.ms_stage[i] = 0.0;
+        // recording the launch sequence walks the batches again: keep the
+        // eager lift's counts
+        const slag_stats eager = c->stats;
         CK(capture_lift(c, codec));
+        c->stats = eager;
     }
     c->have_out = true;
     c->out_is_codec = codec;
