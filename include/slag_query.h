@@ -45,6 +45,25 @@ slag_status slag_query(slag_ctx* ctx, int64_t n, int32_t d, const float* emb, sl
                        int32_t k, int64_t* count, uint32_t* top_idx, float* top_cos,
                        slag_mem out_where);
 
+/* The same search for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid it): every
+ * work array lives in one static device buffer of SLAG_QUERY_SCRATCH_BYTES
+ * per GPU (reserved when the library's first context on that GPU is
+ * created, held until the process ends) instead of library-allocated
+ * workspace; no hipMalloc, hipFree or allocating library call.  emb must be
+ * device memory (SLAG_DEVICE); queries and outputs are as for slag_query.
+ * Sizes whose work arrays do not fit the buffer (about 16 n Q bytes for
+ * k > 0, plus the sort's histograms and 4 d Q + 4 d Q bytes for the queries)
+ * are rejected with SLAG_E_CAPACITY.  Results equal slag_query's bit for
+ * bit.  All calls on one GPU share the buffer, which keeps the last call's
+ * contents: calls that overlap in time on one GPU (two contexts or two host
+ * threads) race and must be serialised by the caller. */
+#define SLAG_QUERY_SCRATCH_BYTES (128u << 20)
+slag_status slag_query_static(slag_ctx* ctx, int64_t n, int32_t d, const float* emb,
+                              slag_mem emb_where, int32_t n_queries, const float* queries,
+                              slag_mem q_where, float threshold, int32_t k, int64_t* count,
+                              uint32_t* top_idx, float* top_cos, slag_mem out_where);
+
 /* Per-Gaussian class (the ScanNet-style semantic labelling of the paper's
  * evaluation): label[g] = the class c of highest cos(g, c) among
  * classes[C][d] (ties to the lower class), -1 where E_g = 0; best[g] (may be

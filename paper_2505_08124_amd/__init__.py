@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libslag.so")
 SLAG_OK, SLAG_E_INVALID_ARG, SLAG_E_OUT_OF_MEMORY, SLAG_E_DEVICE, SLAG_E_STATE, \
     SLAG_E_CAPACITY, SLAG_E_NOT_SUPPORTED = range(7)
 SLAG_HOST, SLAG_DEVICE = 0, 1
+SLAG_QUERY_SCRATCH_BYTES = 128 << 20      # include/slag_query.h
 SLAG_F32, SLAG_BF16 = 0, 1
 SLAG_FLAG_PROFILE, SLAG_FLAG_COUNT, SLAG_FLAG_KEEP_DEBUG, SLAG_FLAG_GRAPH, SLAG_FLAG_AUTOTUNE = \
     1, 2, 4, 8, 16
@@ -74,7 +75,7 @@ EXPORTS = ["slag_create", "slag_destroy", "slag_last_error", "slag_set_gaussians
            "slag_codec_set_pool", "slag_codec_add_lift_rows", "slag_codec_pool_size",
            "slag_codec_loss_grad", "slag_codec_train", "slag_lift_codec", "slag_get_codes",
            # include/slag_query.h
-           "slag_query", "slag_classify"]
+           "slag_query", "slag_classify", "slag_query_static"]
 
 _lib_handle = None
 
@@ -131,6 +132,7 @@ def lib():
     L.slag_query.argtypes = [P, I64, I32, P, I32, I32, P, I32, ctypes.c_float, I32,
                              ctypes.POINTER(I64), P, P, I32]
     L.slag_classify.argtypes = [P, I64, I32, P, I32, I32, P, I32, P, P, I32]
+    L.slag_query_static.argtypes = L.slag_query.argtypes
     for f in EXPORTS:
         if f not in ("slag_destroy", "slag_last_error", "slag_stage_name", "slag_variant_name"):
             getattr(L, f).restype = I32
@@ -354,11 +356,13 @@ def slag_get_codes(ctx, out):
     _check(ctx, lib().slag_get_codes(ctx, p, w))
 
 
-def slag_query(ctx, emb, queries, threshold: float = 0.0, k: int = 0, out=None):
+def slag_query(ctx, emb, queries, threshold: float = 0.0, k: int = 0, out=None,
+               static: bool = False):
     """Cosine-similarity search: returns (count[Q], top_idx[Q][k], top_cos[Q][k]).
     emb [n][d] and queries [Q][d]: float32 NumPy arrays or CUDA tensors.  The
     top-k rows go to `out` = (idx, cos) when given (NumPy or CUDA tensors),
-    else to new NumPy arrays."""
+    else to new NumPy arrays.  static=True calls slag_query_static (no
+    device allocation; emb must be a CUDA tensor)."""
     n, d = int(emb.shape[0]), int(emb.shape[1])
     nq = int(queries.shape[0])
     pe, we = _ptr(emb)
@@ -371,8 +375,9 @@ def slag_query(ctx, emb, queries, threshold: float = 0.0, k: int = 0, out=None):
         idx, cs = out
     pi, wo = _ptr(idx) if k > 0 else (None, SLAG_HOST)
     pc, _ = _ptr(cs) if k > 0 else (None, SLAG_HOST)
-    _check(ctx, lib().slag_query(ctx, n, d, pe, we, nq, pq, wq, float(threshold), int(k),
-                                 cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), pi, pc, wo))
+    fn = lib().slag_query_static if static else lib().slag_query
+    _check(ctx, fn(ctx, n, d, pe, we, nq, pq, wq, float(threshold), int(k),
+                   cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), pi, pc, wo))
     return cnt, idx, cs
 
 

@@ -14,10 +14,44 @@
 // in A and B) and the row's sum of squares.  Reading E once is the bound
 // (4 d bytes per Gaussian) while Qp stays below about 40.
 #include <cmath>
+#include <mutex>
 
+#include "../../include/slag_query.h"
 #include "slag_internal.h"
 
+// Work area of slag_query_static (callers that cannot allocate): one static
+// buffer per GPU, reserved with the code object and kept until the process
+// ends.  Host code never uses this name as an address (on the host it is a
+// stand-in, not device memory): it takes the per-device address returned by
+// hipGetSymbolAddress in query_scratch_init.
+static __device__ __align__(256) unsigned char scratch[SLAG_QUERY_SCRATCH_BYTES];
+
 namespace slag {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+hipError_t query_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return hipSuccess;
+    // the caller made `device` current
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_scratch[device] = p;
+    return e;
+}
+
+void* query_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[device];
+}
 
 namespace {
 

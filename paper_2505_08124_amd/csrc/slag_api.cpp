@@ -644,6 +644,8 @@ slag_status slag_create(int32_t device, void* hip_stream, const slag_options* op
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return SLAG_E_INVALID_ARG;
     if (hipSetDevice(device) != hipSuccess) return SLAG_E_DEVICE;
+    // the search's static work area on this device (slag_query_static)
+    if (slag::query_scratch_init(device) != hipSuccess) return SLAG_E_DEVICE;
     slag_ctx* c = new (std::nothrow) slag_ctx();
     if (!c) return SLAG_E_OUT_OF_MEMORY;
     c->device = device;

@@ -230,5 +230,10 @@ void launch_classify(int nc, int64_t n, int d, const float* E, const float* qt, 
                      float* best, hipStream_t st);
 void launch_topk_out(int nq, int k, int64_t n, const uint32_t* keys, const uint32_t* vals,
                      uint32_t* idx, float* cosv, hipStream_t st);
+// Device address of the search's static work area on `device` (current when
+// query_scratch_init is called, once per device, at context creation);
+// null before that.
+hipError_t query_scratch_init(int device);
+void* query_scratch(int device);
 
 }  // namespace slag

@@ -141,6 +141,67 @@ slag_status slag_query(slag_ctx* c, int64_t n, int32_t d, const float* emb, slag
     return run_query(c, w, n, d, nq, qdev, thr, k, count, top_idx, top_cos, ow);
 }
 
+slag_status slag_query_static(slag_ctx* c, int64_t n, int32_t d, const float* emb, slag_mem ew,
+                              int32_t nq, const float* q, slag_mem qw, float thr, int32_t k,
+                              int64_t* count, uint32_t* top_idx, float* top_cos, slag_mem ow)
+{
+    if (!c) return SLAG_E_INVALID_ARG;
+    c->err.clear();
+    CK(check_args(c, n, d, emb, ew, nq, q, qw, ow));
+    if (ew != SLAG_DEVICE && n > 0)
+        FAIL(c, SLAG_E_INVALID_ARG, "slag_query_static needs the embeddings in device memory");
+    if (k < 0 || k > n) FAIL(c, SLAG_E_INVALID_ARG, "k must be in [0, n]");
+    if (k > 0 && (!top_idx || !top_cos)) FAIL(c, SLAG_E_INVALID_ARG, "null top-k output");
+    HC(c, hipSetDevice(c->device));
+    // the static work area's address on this device (taken at context creation)
+    unsigned char* base = static_cast<unsigned char*>(query_scratch(c->device));
+    if (!base) FAIL(c, SLAG_E_STATE, "no static work area on this device");
+    const int qp = (nq + 15) & ~15;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    const size_t o_qt = carve((size_t)d * qp * 4);
+    const size_t o_cnt = carve((2 * QMAX + 2) * 8);
+    const size_t o_q = qw == SLAG_HOST ? carve((size_t)nq * d * 4) : 0;
+    size_t o_keys = 0, o_vals = 0, o_ka = 0, o_va = 0, o_hist = 0, o_ws = 0;
+    if (k > 0) {
+        const size_t m = (size_t)nq * (size_t)n * 4;
+        o_keys = carve(m);
+        o_vals = carve(m);
+        o_ka = carve(m);
+        o_va = carve(m);
+        o_hist = carve(radix_hist_bytes((uint64_t)n));
+        o_ws = carve(sort_scan_bytes(n));
+    }
+    if (off > (size_t)SLAG_QUERY_SCRATCH_BYTES)
+        FAIL(c, SLAG_E_CAPACITY, "slag_query_static: " + std::to_string(off) +
+                                     " bytes of work arrays exceed the static area of " +
+                                     std::to_string((size_t)SLAG_QUERY_SCRATCH_BYTES) +
+                                     " bytes (fewer queries, k = 0, or slag_query)");
+    QueryWork w;
+    w.emb = emb;
+    w.qt = reinterpret_cast<float*>(base + o_qt);
+    w.counts = reinterpret_cast<unsigned long long*>(base + o_cnt);
+    const float* qdev = q;
+    if (qw == SLAG_HOST) {
+        float* qs = reinterpret_cast<float*>(base + o_q);
+        HC(c, hipMemcpyAsync(qs, q, (size_t)nq * d * 4, hipMemcpyHostToDevice, c->st));
+        qdev = qs;
+    }
+    if (k > 0) {
+        w.keys = reinterpret_cast<uint32_t*>(base + o_keys);
+        w.vals = reinterpret_cast<uint32_t*>(base + o_vals);
+        w.keys_alt = reinterpret_cast<uint32_t*>(base + o_ka);
+        w.vals_alt = reinterpret_cast<uint32_t*>(base + o_va);
+        w.hist = reinterpret_cast<uint32_t*>(base + o_hist);
+        w.scan_ws = base + o_ws;
+    }
+    return run_query(c, w, n, d, nq, qdev, thr, k, count, top_idx, top_cos, ow);
+}
+
 slag_status slag_classify(slag_ctx* c, int64_t n, int32_t d, const float* emb, slag_mem ew,
                           int32_t nc, const float* cls, slag_mem cw, int32_t* label, float* best,
                           slag_mem ow)
