@@ -87,7 +87,27 @@ typedef struct {
      * until the Gaussians or cameras change.  Results do not depend on the
      * plan beyond FP32 rounding of the contraction. */
     int64_t max_launch_entries;
-    int64_t reserved[5];
+    /* Rasterizer constants, which the paper leaves to the rasterizer (0 =
+     * 3D Gaussian splatting's value, in brackets): alpha_max [0.99] caps
+     * alpha; blends with alpha < alpha_min [1/255] are skipped (and the
+     * conservative pixel box is sized for it: rho^2 = 2 ln(1 / alpha_min));
+     * a pixel stops before the blend that would take its transmittance below
+     * t_min [1e-4]; dilation [0.3 px^2] is added to the projected covariance's
+     * diagonal; Gaussians at camera depth <= near_z [0.01] are culled; guard
+     * [1.3] clamps x/z and y/z of the Jacobian at that many half-FOV
+     * tangents.  Need 0 < alpha_min < alpha_max <= 1, 0 < t_min < 1, else
+     * slag_create fails with SLAG_E_INVALID_ARG. */
+    float alpha_max, alpha_min, t_min, dilation, near_z, guard;
+    int32_t tile_size;              /* compositing tile edge: 0 (= 16) or 16; others are
+                                       SLAG_E_NOT_SUPPORTED */
+    int32_t deterministic;          /* 0 or 1: every lift is deterministic (bitwise-equal
+                                       results for equal inputs and options, whatever the
+                                       launch order or atomics' timing); 1 asks for it */
+    int32_t labels_per_pixel;       /* masks one pixel may lie in (overlapping masks): 0 or 1
+                                       (one id per pixel), up to 4; see
+                                       slag_set_segments_multi */
+    int32_t reserved32;
+    int64_t reserved[1];
 } slag_options;
 
 typedef struct {
@@ -139,6 +159,17 @@ slag_status slag_set_cameras(slag_ctx* ctx, int32_t n_views, const slag_camera* 
 slag_status slag_set_segments(slag_ctx* ctx, int32_t view, const int32_t* ids, int32_t n_seg,
                               slag_mem where);
 
+/* Overlapping masks (the paper's masks M_j are per-object binary masks, and
+ * one pixel may lie in several): ids[H][W][n_labels] row-major int32, the
+ * masks containing each pixel (distinct, in any order), -1 for unused
+ * entries; 1 <= n_labels <= the context's labels_per_pixel option.  Every
+ * label of a pixel receives the pixel's blend weights (parameter masking per
+ * mask), and the aggregation sums over every mask and its pixels.  Copied;
+ * ids out of range or repeated within a pixel are SLAG_E_INVALID_ARG.  With
+ * n_labels = 1 this is slag_set_segments. */
+slag_status slag_set_segments_multi(slag_ctx* ctx, int32_t view, const int32_t* ids,
+                                    int32_t n_labels, int32_t n_seg, slag_mem where);
+
 /* The segment embeddings E_ij: table[sum_v n_seg_v][d], view-major (all
  * segments of view 0, then view 1, ...), FP32 or BF16.  Copied. */
 slag_status slag_set_features(slag_ctx* ctx, int32_t d, slag_dtype dtype, const void* table,
@@ -159,6 +190,22 @@ slag_status slag_lift(slag_ctx* ctx);
  * not be used) if the last lift lost weights to a capacity error. */
 slag_status slag_get_embeddings(slag_ctx* ctx, void* out, slag_dtype dtype, float* den,
                                 slag_mem where);
+
+/* The lift with E_GAUSSIAN streamed to host memory in chunks of
+ * `chunk_rows` Gaussians (the paper runs the aggregation in several
+ * iterations when the embedding tensor does not fit on the GPU: Method,
+ * multi-GPU scaling; Experiments, the large aerial scene): the device holds
+ * one chunk of the output (chunk_rows (d + 1) floats) instead of N (d + 1).
+ * out[N][d] (FP32, or BF16 rounded nearest-even) and den[N] (FP32) are host
+ * memory in the caller's Gaussian order; either may be NULL.  chunk_rows is
+ * a positive multiple of 16.  With one view launch the compositing runs
+ * once and only the contraction repeats per chunk; with several launches
+ * each chunk repeats the whole lift.  Results equal slag_lift followed by
+ * slag_get_embeddings bit for bit.  Synchronous; afterwards the context holds
+ * no lift result (slag_get_embeddings fails with SLAG_E_STATE) and
+ * slag_get_stats reports the first chunk's lift. */
+slag_status slag_lift_chunked(slag_ctx* ctx, int64_t chunk_rows, void* out, slag_dtype dtype,
+                              float* den);
 
 slag_status slag_get_stats(slag_ctx* ctx, slag_stats* stats);
 const char* slag_stage_name(int32_t stage);

@@ -16,6 +16,7 @@ Split of work:
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import dataclasses
 import os
@@ -57,14 +58,38 @@ def _lib():
         P = ctypes.c_void_p
         L.orc_lift_view.restype = P
         L.orc_lift_view.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32,
-                                    P, P, P, ctypes.POINTER(_Counts), ctypes.POINTER(ctypes.c_int64)]
+                                    ctypes.c_int32, P, P, P, ctypes.POINTER(_Counts),
+                                    ctypes.POINTER(ctypes.c_int64)]
         L.orc_view_fetch.argtypes = [P, P, P, P, P, P]
         L.orc_view_free.argtypes = [P]
         L.orc_mirror_view.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, P, P]
         L.orc_project64_view.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, P, P]
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_set_constants.argtypes = [P]
+        L.orc_set_constants.restype = None
         _lib_handle = L
     return _lib_handle
+
+
+CONSTANT_NAMES = ("alpha_max", "alpha_min", "t_min", "dilation", "near_z", "guard")
+
+
+@contextlib.contextmanager
+def constants(**kw):
+    """Run the oracle with non-default rasterizer constants (the library's
+    options of the same names; each given as the float the library receives,
+    0 or absent = the 3D Gaussian splatting default), restoring the defaults
+    afterwards."""
+    bad = set(kw) - set(CONSTANT_NAMES)
+    if bad:
+        raise ValueError(f"unknown constants {sorted(bad)}")
+    c = np.array([kw.get(k, 0.0) for k in CONSTANT_NAMES], np.float32)
+    L = _lib()
+    L.orc_set_constants(_p(c))
+    try:
+        yield
+    finally:
+        L.orc_set_constants(_p(np.zeros(6, np.float32)))
 
 
 def _p(a: Optional[np.ndarray]):
@@ -105,7 +130,10 @@ def lift_view(scene, v: int, mode: str = "box", pixels: bool = False,
     L = _lib()
     cam = np.ascontiguousarray(scene.cams[v:v + 1])
     ids = _c(scene.ids[v], np.int32)
-    H, W = ids.shape
+    # one label per pixel ([H, W]) or several ([H, W, L]: overlapping masks,
+    # -1 where a pixel lies in fewer)
+    H, W = ids.shape[:2]
+    nlab = ids.shape[2] if ids.ndim == 3 else 1
     T = np.empty((H, W), np.float64) if pixels else None
     ws = np.empty((H, W), np.float64) if pixels else None
     rho = np.empty((H, W), np.float64) if pixels else None
@@ -115,7 +143,7 @@ def lift_view(scene, v: int, mode: str = "box", pixels: bool = False,
     quats, opac = _c(scene.quats, np.float32), _c(scene.opacity, np.float32)
     m = (0 if mode == "brute" else 1) | (2 if fp32 else 0)
     h = L.orc_lift_view(scene.n, _p(means), _p(scales), _p(quats), _p(opac), _p(cam), _p(ids),
-                        m, int(nthreads), _p(T), _p(ws), _p(rho), ctypes.byref(cnt),
+                        nlab, m, int(nthreads), _p(T), _p(ws), _p(rho), ctypes.byref(cnt),
                         ctypes.byref(nt))
     if not h:
         raise MemoryError("oracle view lift failed")

@@ -18,7 +18,9 @@
  * contraction with the feature table and the normalisation are done by the
  * Python half of the oracle.
  *
- * Conventions the paper leaves open (taken from 3D Gaussian splatting):
+ * Conventions the paper leaves open (taken from 3D Gaussian splatting; the
+ * defaults below, settable with orc_set_constants like the library's
+ * options):
  *   alpha = min(0.99, o * exp(-q/2)), q = d^T Sigma2^{-1} d, d = p - mu2,
  *   p = pixel centre (u+0.5, v+0.5); contributions with alpha < 1/255 are
  *   skipped; the walk stops *before* a Gaussian whose blend would take the
@@ -78,21 +80,44 @@ typedef struct {
     int64_t n_uncertain;        /* near-threshold decisions met */
 } orc_counts;
 
-/* ---- FP32 decision constants (float literals, exact bit patterns) ---- */
-#define F_NEAR  0.01f
-#define F_DIL   0.3f
-#define F_CLAMP 1.3f
-#define F_RHO2  0x1.62a41p+3f       /* float nearest to 2 ln 255 */
+/* ---- Rasterizer constants (3D Gaussian splatting's by default; settable,
+ * orc_set_constants, to mirror the library's options).  FP32 decision values
+ * (exact bit patterns) and the FP64 weighting values. ---- */
+static float F_NEAR = 0.01f;
+static float F_DIL = 0.3f;
+static float F_CLAMP = 1.3f;
+static float F_RHO2 = 0x1.62a41p+3f;       /* float nearest to 2 ln 255: q bound of alpha >= 1/255 */
+static float F_AMIN = 1.0f / 255.0f, F_AMAX = 0.99f, F_TMIN = 1e-4f;
+static double D_AMIN = 1.0 / 255.0;
+static double D_AMAX = 0.99;
+static double D_TMIN = 1e-4;
+static double D_DIL = 0.3;
+static double D_CLAMP = 1.3;
 
-/* ---- FP64 weighting constants ---- */
-#define D_AMIN (1.0 / 255.0)
-#define D_AMAX 0.99
-#define D_TMIN 1e-4
-#define D_DIL 0.3
-#define D_CLAMP 1.3
+/* Non-default constants, each given as the float the library receives:
+ * c = (alpha_max, alpha_min, t_min, dilation, near_z, guard), 0 = default.
+ * The FP64 values are those floats widened; rho^2 = 2 ln(1 / alpha_min) is
+ * rounded once to float (the default keeps the float nearest to 2 ln 255). */
+void orc_set_constants(const float* c)
+{
+    F_AMAX = c[0] > 0.0f ? c[0] : 0.99f;
+    D_AMAX = c[0] > 0.0f ? (double)c[0] : 0.99;
+    F_AMIN = c[1] > 0.0f ? c[1] : 1.0f / 255.0f;
+    D_AMIN = c[1] > 0.0f ? (double)c[1] : 1.0 / 255.0;
+    F_RHO2 = c[1] > 0.0f ? (float)(2.0 * log(1.0 / (double)c[1])) : 0x1.62a41p+3f;
+    F_TMIN = c[2] > 0.0f ? c[2] : 1e-4f;
+    D_TMIN = c[2] > 0.0f ? (double)c[2] : 1e-4;
+    F_DIL = c[3] > 0.0f ? c[3] : 0.3f;
+    D_DIL = c[3] > 0.0f ? (double)c[3] : 0.3;
+    F_NEAR = c[4] > 0.0f ? c[4] : 0.01f;
+    F_CLAMP = c[5] > 0.0f ? c[5] : 1.3f;
+    D_CLAMP = c[5] > 0.0f ? (double)c[5] : 1.3;
+}
+
 #define D_L2E 1.4426950408889634074      /* log2(e) */
 #define D_LN2 0.69314718055994530942
 #define U32 0x1p-24                          /* unit roundoff of FP32 */
+#define ORC_MAX_LABELS 8                     /* masks a pixel may lie in (overlapping masks) */
 /* FP32 thresholds differ from the FP64 ones by at most this relative amount
  * ((float)(1/255) and 1e-4f are rounded) */
 #define CONST_REL 0x1p-23
@@ -293,6 +318,16 @@ static int cbuf_push(cbuf* b, int32_t g, int32_t s, double w, double u, double r
 typedef struct { uint64_t* key; double* w; double* u; double* r; int64_t cap, n; } hmap;
 #define HEMPTY 0xFFFFFFFFFFFFFFFFull
 
+/* One contribution to every mask that contains the pixel (overlapping masks:
+ * the weight goes to each of the pixel's labels). */
+static int push_labels(cbuf* b, int32_t g, const int32_t* segs, int nl, double w, double u,
+                       double r)
+{
+    for (int i = 0; i < nl; i++)
+        if (cbuf_push(b, g, segs[i], w, u, r)) return 1;
+    return 0;
+}
+
 static int hmap_init(hmap* h, int64_t cap)
 {
     int64_t c = 1024;
@@ -418,7 +453,7 @@ static double alpha_eps(const proj64* p, const mirror_out* mo, double px, double
  * decision of the pixel lay inside its band.
  */
 static int composite_pixel(const view_ctx* vc, const int32_t* cand, int64_t nc,
-                           int ix, int iy, int32_t seg, cbuf* out,
+                           int ix, int iy, const int32_t* segs, int nl, cbuf* out,
                            double* T_out, double* wsum_out, double* rho_out, int* near_out,
                            int64_t* n_c, int64_t* n_q, int64_t* n_unc, int count_box_only)
 {
@@ -442,7 +477,7 @@ static int composite_pixel(const view_ctx* vc, const int32_t* cand, int64_t nc,
             if (alpha * (1.0 + eps) >= D_AMIN) {
                 (*n_unc)++;
                 any_near = 1;
-                if (seg >= 0 && cbuf_push(out, g, seg, 0.0, alpha * T * grow * (1.0 + eps + rho), 0.0))
+                if (push_labels(out, g, segs, nl, 0.0, alpha * T * grow * (1.0 + eps + rho), 0.0))
                     return -1;
                 delta += alpha / (1.0 - alpha);
             }
@@ -455,14 +490,16 @@ static int composite_pixel(const view_ctx* vc, const int32_t* cand, int64_t nc,
         const int near_t = fabs(Tn - D_TMIN) <= band;
         if (near_a || near_t) { (*n_unc)++; any_near = 1; }
         if (Tn < D_TMIN) {
-            if (near_t && seg >= 0) {
-                if (cbuf_push(out, g, seg, 0.0, alpha * T * grow * (1.0 + ea + rho), 0.0)) return -1;
+            if (near_t && nl > 0) {
+                if (push_labels(out, g, segs, nl, 0.0, alpha * T * grow * (1.0 + ea + rho), 0.0))
+                    return -1;
                 for (int64_t h = k + 1; h < nc; h++) {
                     const proj64* ph = &vc->P[cand[h]];
                     const double ah = alpha_at(ph, px, py, NULL);
                     const double eh = alpha_eps(ph, &vc->Mi[cand[h]], px, py) + CONST_REL;
                     if (ah * (1.0 + eh) >= D_AMIN) {
-                        if (cbuf_push(out, cand[h], seg, 0.0, ah * Tn * grow * (1.0 + eh + rho_n), 0.0))
+                        if (push_labels(out, cand[h], segs, nl, 0.0,
+                                        ah * Tn * grow * (1.0 + eh + rho_n), 0.0))
                             return -1;
                         break;
                     }
@@ -477,7 +514,7 @@ static int composite_pixel(const view_ctx* vc, const int32_t* cand, int64_t nc,
         if (near_t) { u = w * grow; delta = 1.0; }
         (*n_c)++;
         sumw += w;
-        if (seg >= 0 && cbuf_push(out, g, seg, w, u, r)) return -1;
+        if (push_labels(out, g, segs, nl, w, u, r)) return -1;
         if (near_a) delta += alpha / (1.0 - alpha);
         T = Tn;
         rho = rho_n;
@@ -498,10 +535,10 @@ static int composite_pixel(const view_ctx* vc, const int32_t* cand, int64_t nc,
  * stay within r + U of the FP64 walk's.  Decisions are taken in FP32.
  */
 static int composite_pixel_f32(const view_ctx* vc, const int32_t* cand, int64_t nc,
-                               int ix, int iy, int32_t seg, cbuf* out, double* T_out,
+                               int ix, int iy, const int32_t* segs, int nl, cbuf* out, double* T_out,
                                double* wsum_out)
 {
-    const float AMIN_F = 1.0f / 255.0f, AMAX_F = 0.99f, TMIN_F = 1e-4f;
+    const float AMIN_F = F_AMIN, AMAX_F = F_AMAX, TMIN_F = F_TMIN;
     const int bx0 = ix & ~7, by0 = iy & ~7;
     const float lx = (float)(ix & 7) - 3.5f, ly = (float)(iy & 7) - 3.5f;
     float T = 1.0f;
@@ -530,7 +567,7 @@ static int composite_pixel_f32(const view_ctx* vc, const int32_t* cand, int64_t 
         if (Tn < TMIN_F) break;
         const float w = alpha * T;
         sumw += (double)w;
-        if (seg >= 0 && cbuf_push(out, g, seg, (double)w, 0.0, 0.0)) return -1;
+        if (push_labels(out, g, segs, nl, (double)w, 0.0, 0.0)) return -1;
         T = Tn;
     }
     *T_out = (double)T;
@@ -606,12 +643,13 @@ static int cmp_u64(const void* a, const void* b)
  * pixels where some decision lay inside its band.
  */
 void* orc_lift_view(int64_t n, const float* means, const float* scales, const float* quats,
-                    const float* opacity, const orc_camera* cam, const int32_t* ids,
+                    const float* opacity, const orc_camera* cam, const int32_t* ids, int32_t L,
                     int32_t mode, int32_t nthreads, double* pix_T, double* pix_wsum,
                     double* pix_rho, orc_counts* counts, int64_t* n_triples)
 {
     const int f32 = (mode & 2) != 0;
     mode &= 1;
+    if (L < 1 || L > ORC_MAX_LABELS) return NULL;
     const int W = cam->width, H = cam->height;
     proj64* P = (proj64*)malloc((size_t)(n ? n : 1) * sizeof(proj64));
     mirror_out* Mi = (mirror_out*)malloc((size_t)(n ? n : 1) * sizeof(mirror_out));
@@ -680,7 +718,13 @@ void* orc_lift_view(int64_t n, const float* means, const float* scales, const fl
         for (int y = 0; y < H; y++) {
             for (int x = 0; x < W; x++) {
                 const int64_t pi = (int64_t)y * W + x;
-                const int32_t seg = ids[pi];
+                /* the pixel's labels (masks containing it), -1 entries skipped */
+                int32_t segs[ORC_MAX_LABELS];
+                int nl = 0;
+                for (int l = 0; l < L; l++) {
+                    const int32_t sl = ids[pi * L + l];
+                    if (sl >= 0) segs[nl++] = sl;
+                }
                 const int32_t* c;
                 int64_t ncand;
                 if (mode == 0) {
@@ -693,8 +737,8 @@ void* orc_lift_view(int64_t n, const float* means, const float* scales, const fl
                 }
                 double Tf = 1.0, ws = 0.0, rf = 0.0;
                 int nr = 0;
-                const int bad = f32 ? composite_pixel_f32(&vc, c, ncand, x, y, seg, &rows[y], &Tf, &ws)
-                                    : composite_pixel(&vc, c, ncand, x, y, seg, &rows[y], &Tf, &ws,
+                const int bad = f32 ? composite_pixel_f32(&vc, c, ncand, x, y, segs, nl, &rows[y], &Tf, &ws)
+                                    : composite_pixel(&vc, c, ncand, x, y, segs, nl, &rows[y], &Tf, &ws,
                                                       &rf, &nr, &nc_tot, &nq_tot, &nu_tot, mode == 0);
                 if (bad) failed = 1;
                 if (pix_T) pix_T[pi] = Tf;

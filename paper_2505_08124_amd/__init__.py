@@ -42,7 +42,13 @@ class slag_camera(ctypes.Structure):
 
 class slag_options(ctypes.Structure):
     _fields_ = [("max_views_per_launch", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("max_launch_entries", ctypes.c_int64), ("reserved", ctypes.c_int64 * 5)]
+                ("max_launch_entries", ctypes.c_int64),
+                ("alpha_max", ctypes.c_float), ("alpha_min", ctypes.c_float),
+                ("t_min", ctypes.c_float), ("dilation", ctypes.c_float),
+                ("near_z", ctypes.c_float), ("guard", ctypes.c_float),
+                ("tile_size", ctypes.c_int32), ("deterministic", ctypes.c_int32),
+                ("labels_per_pixel", ctypes.c_int32), ("reserved32", ctypes.c_int32),
+                ("reserved", ctypes.c_int64 * 1)]
 
 
 class slag_stats(ctypes.Structure):
@@ -75,7 +81,8 @@ EXPORTS = ["slag_create", "slag_destroy", "slag_last_error", "slag_set_gaussians
            "slag_codec_set_pool", "slag_codec_add_lift_rows", "slag_codec_pool_size",
            "slag_codec_loss_grad", "slag_codec_train", "slag_lift_codec", "slag_get_codes",
            # include/slag_query.h
-           "slag_query", "slag_classify", "slag_query_static"]
+           "slag_query", "slag_classify", "slag_query_static", "slag_lift_chunked",
+           "slag_set_segments_multi"]
 
 _lib_handle = None
 
@@ -106,8 +113,10 @@ def lib():
     L.slag_set_gaussians.argtypes = [P, I64, P, P, P, P, I32]
     L.slag_set_cameras.argtypes = [P, I32, P]
     L.slag_set_segments.argtypes = [P, I32, P, I32, I32]
+    L.slag_set_segments_multi.argtypes = [P, I32, P, I32, I32, I32]
     L.slag_set_features.argtypes = [P, I32, I32, P, I32]
     L.slag_lift.argtypes = [P]
+    L.slag_lift_chunked.argtypes = [P, I64, P, I32, P]
     L.slag_get_embeddings.argtypes = [P, P, I32, P, I32]
     L.slag_get_debug.argtypes = [P, I32, I32, P, I64, ctypes.POINTER(I64)]
     L.slag_get_stats.argtypes = [P, ctypes.POINTER(slag_stats)]
@@ -168,8 +177,15 @@ def _ptr(a):
 # ---------------------------------------------------------------- C names
 
 def slag_create(device: int = 0, stream=None, max_views_per_launch: int = 0, flags: int = 0,
-                max_launch_entries: int = 0):
+                max_launch_entries: int = 0, **constants):
+    """constants: alpha_max, alpha_min, t_min, dilation, near_z, guard (floats),
+    tile_size, deterministic (ints); absent = default."""
     o = slag_options(max_views_per_launch, flags, max_launch_entries)
+    for k, v in constants.items():
+        if k not in ("alpha_max", "alpha_min", "t_min", "dilation", "near_z", "guard",
+                     "tile_size", "deterministic", "labels_per_pixel"):
+            raise ValueError(f"unknown option {k}")
+        setattr(o, k, v)
     h = ctypes.c_void_p()
     st = lib().slag_create(device, ctypes.c_void_p(stream) if stream else None, ctypes.byref(o),
                            ctypes.byref(h))
@@ -202,9 +218,24 @@ def slag_set_segments(ctx, view: int, ids, n_seg: int):
     _check(ctx, lib().slag_set_segments(ctx, int(view), p, int(n_seg), w))
 
 
+def slag_set_segments_multi(ctx, view: int, ids, n_seg: int):
+    """ids [H][W][L]: the masks containing each pixel, -1 for unused entries."""
+    p, w = _ptr(ids)
+    _check(ctx, lib().slag_set_segments_multi(ctx, int(view), p, int(ids.shape[2]), int(n_seg), w))
+
+
 def slag_set_features(ctx, table, dtype: int):
     p, w = _ptr(table)
     _check(ctx, lib().slag_set_features(ctx, int(table.shape[1]), int(dtype), p, w))
+
+
+def slag_lift_chunked(ctx, chunk_rows: int, out, den=None):
+    """Lift with the output streamed to host arrays out [N][d] (float32, or
+    uint16 BF16 bits) and den [N] (float32), chunk_rows Gaussians at a time."""
+    po, _ = _ptr(out)
+    pd, _ = _ptr(den)
+    dt = SLAG_BF16 if (out is not None and out.dtype == np.uint16) else SLAG_F32
+    _check(ctx, lib().slag_lift_chunked(ctx, int(chunk_rows), po, dt, pd))
 
 
 def slag_lift(ctx):
@@ -405,8 +436,9 @@ class Lifter:
     """One context on one device: upload a scene, lift, fetch."""
 
     def __init__(self, device: int = 0, stream=None, max_views_per_launch: int = 0,
-                 flags: int = 0, max_launch_entries: int = 0):
-        self.ctx = slag_create(device, stream, max_views_per_launch, flags, max_launch_entries)
+                 flags: int = 0, max_launch_entries: int = 0, **constants):
+        self.ctx = slag_create(device, stream, max_views_per_launch, flags, max_launch_entries,
+                               **constants)
         self.n = 0
         self.d = 0
 
@@ -442,7 +474,11 @@ class Lifter:
         slag_set_gaussians(self.ctx, means, scales, quats, opac)
         slag_set_cameras(self.ctx, scene.cams)
         for v, ids in enumerate(scene.ids):
-            slag_set_segments(self.ctx, v, np.ascontiguousarray(ids, np.int32), int(scene.nseg[v]))
+            ids = np.ascontiguousarray(ids, np.int32)
+            if ids.ndim == 3:                 # several masks per pixel
+                slag_set_segments_multi(self.ctx, v, ids, int(scene.nseg[v]))
+            else:
+                slag_set_segments(self.ctx, v, ids, int(scene.nseg[v]))
         dt = SLAG_BF16 if scene.feat_dtype == "bf16" else SLAG_F32
         slag_set_features(self.ctx, np.ascontiguousarray(scene.feats), dt)
         self.n = scene.n

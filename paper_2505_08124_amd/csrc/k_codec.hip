@@ -365,19 +365,82 @@ __global__ __launch_bounds__(256) void k_mix(int R, int k, const uint32_t* __res
     code[i] = s;
 }
 
-// dC[col[j]][c] += w[j] dcode[r][c] (training only; float atomics).
-__global__ __launch_bounds__(256) void k_mix_bwd(int R, int k, const uint32_t* __restrict__ row_ptr,
-                                                 const uint32_t* __restrict__ col,
+// Transpose of the mixing for the gradient: dC[s][c] = sum over the pool
+// entries j of column s whose row lies in this batch of w[j] dcode[row][c].
+// The pool's entries grouped by column (csc_j: entry indices, ascending
+// within each column, so rows ascend too; column s owns [cbeg[s], cend[s]));
+// the batch's entries (rows row0 .. row0 + R - 1, row pointers rp = the
+// pool's from row0) are the index range [rp[0], rp[R]), found in each column by
+// binary search; each (s, c) is summed by one thread in entry order, so the
+// result is deterministic (no atomics).
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* a, uint32_t lo, uint32_t hi,
+                                                    uint32_t x)
+{
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_mix_bwd(int NS, int k, const uint32_t* __restrict__ rp, int R,
+                                                 int64_t row0,
+                                                 const uint32_t* __restrict__ cbeg,
+                                                 const uint32_t* __restrict__ cend,
+                                                 const uint32_t* __restrict__ csc_j,
+                                                 const uint32_t* __restrict__ csc_row,
                                                  const float* __restrict__ w,
                                                  const float* __restrict__ dcode,
                                                  float* __restrict__ dC)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= (int64_t)R * k) return;
-    const int r = (int)(i / k), c = (int)(i - (int64_t)r * k);
-    const float g = dcode[i];
-    for (uint32_t j = row_ptr[r]; j < row_ptr[r + 1]; j++)
-        atomicAdd(&dC[(int64_t)col[j] * k + c], w[j] * g);
+    if (i >= (int64_t)NS * k) return;
+    const int sidx = (int)(i / k), c = (int)(i - (int64_t)sidx * k);
+    const uint32_t j0 = rp[0], j1 = rp[R];            // the batch's entry range
+    const uint32_t b = cbeg[sidx], e = cend[sidx];
+    const uint32_t lo = lower_bound_u32(csc_j, b, e, j0);
+    const uint32_t hi = lower_bound_u32(csc_j, lo, e, j1);
+    float acc = 0.0f;
+    for (uint32_t q = lo; q < hi; q++) {
+        const uint32_t j = csc_j[q];
+        acc = fmaf(w[j], dcode[((int64_t)csc_row[q] - row0) * k + c], acc);
+    }
+    dC[i] = acc;
+}
+
+// Entries of the pool grouped by column: given the column-sorted entries
+// (key = column, ascending; stable, so entry indices ascend within a
+// column), the range [cbeg[s], cend[s]) of each column s (empty columns keep
+// the zero-filled range) and the row of each sorted entry.
+__global__ __launch_bounds__(256) void k_csc_ranges(uint32_t nnz, const uint32_t* __restrict__ key,
+                                                    const uint32_t* __restrict__ csc_j,
+                                                    const uint32_t* __restrict__ row_of,
+                                                    uint32_t* __restrict__ cbeg,
+                                                    uint32_t* __restrict__ cend,
+                                                    uint32_t* __restrict__ csc_row)
+{
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nnz) return;
+    const uint32_t s = key[i];
+    if (i == 0 || key[i - 1] != s) cbeg[s] = i;
+    if (i + 1 == nnz || key[i + 1] != s) cend[s] = i + 1;
+    csc_row[i] = row_of[csc_j[i]];
+}
+
+// Row of every pool entry from the row pointers (one thread per row).
+__global__ __launch_bounds__(256) void k_row_of(uint32_t R, const uint32_t* __restrict__ row_ptr,
+                                                uint32_t* __restrict__ row_of,
+                                                uint32_t* __restrict__ key,
+                                                uint32_t* __restrict__ ent,
+                                                const uint32_t* __restrict__ col)
+{
+    const uint32_t r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= R) return;
+    for (uint32_t j = row_ptr[r]; j < row_ptr[r + 1]; j++) {
+        row_of[j] = r;
+        key[j] = col[j];
+        ent[j] = j;
+    }
 }
 
 // Per row (one wave each): loss_r = 1 - cos(y_r, t_r) and
@@ -678,12 +741,29 @@ void launch_mix(int R, int k, const uint32_t* row_ptr, const uint32_t* col, cons
                        w, C, code);
 }
 
-void launch_mix_bwd(int R, int k, const uint32_t* row_ptr, const uint32_t* col, const float* w,
-                    const float* dcode, float* dC, hipStream_t st)
+void launch_mix_bwd(int NS, int k, const uint32_t* rp, int R, int64_t row0, const uint32_t* cbeg,
+                    const uint32_t* cend, const uint32_t* csc_j, const uint32_t* csc_row,
+                    const float* w, const float* dcode, float* dC, hipStream_t st)
 {
-    if (R <= 0) return;
-    hipLaunchKernelGGL(k_mix_bwd, dim3(blocks((int64_t)R * k)), dim3(256), 0, st, R, k, row_ptr,
-                       col, w, dcode, dC);
+    if (NS <= 0) return;
+    hipLaunchKernelGGL(k_mix_bwd, dim3(blocks((int64_t)NS * k)), dim3(256), 0, st, NS, k, rp, R,
+                       row0, cbeg, cend, csc_j, csc_row, w, dcode, dC);
+}
+
+void launch_row_of(uint32_t R, const uint32_t* row_ptr, const uint32_t* col, uint32_t* row_of,
+                   uint32_t* key, uint32_t* ent, hipStream_t st)
+{
+    if (!R) return;
+    hipLaunchKernelGGL(k_row_of, dim3(blocks(R)), dim3(256), 0, st, R, row_ptr, row_of, key, ent, col);
+}
+
+void launch_csc_ranges(uint32_t nnz, const uint32_t* key, const uint32_t* csc_j,
+                       const uint32_t* row_of, uint32_t* cbeg, uint32_t* cend, uint32_t* csc_row,
+                       hipStream_t st)
+{
+    if (!nnz) return;
+    hipLaunchKernelGGL(k_csc_ranges, dim3(blocks(nnz)), dim3(256), 0, st, nnz, key, csc_j, row_of,
+                       cbeg, cend, csc_row);
 }
 
 void launch_cos_loss(int R, int d, const float* y, const float* tg, float* dy, float* loss_part,

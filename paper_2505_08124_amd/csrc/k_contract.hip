@@ -162,19 +162,23 @@ template <int NT, bool BF16, int RT>
 __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfma(
     int64_t n, int nb, int d, const uint32_t* __restrict__ perm,
     const uint32_t* __restrict__ pair_of_m, const ViewDev* __restrict__ views,
+    const uint16_t* __restrict__ vlist, const uint32_t* __restrict__ vcnt,
     const uint2* __restrict__ pinfo,
     const uint2* __restrict__ part, const void* __restrict__ feats, float* __restrict__ num,
-    float* __restrict__ den, int first, int last)
+    float* __restrict__ den, int first, int last, int64_t q_begin, int64_t q_end, int local)
 {
     constexpr int G = BlockLds<RT>::G, GT = BlockLds<RT>::GT, GV = BlockLds<RT>::GV;
     __shared__ BlockLds<RT> L;
     const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
-    const int64_t q0 = (int64_t)blockIdx.x * G;           // first Morton rank of the block
+    // Morton ranks [q_begin, q_end) (q_begin a multiple of G); output row of
+    // rank q: its caller index perm[q], or q - q_begin (local rows of a chunk)
+    const int64_t q0 = q_begin + (int64_t)blockIdx.x * G;  // first Morton rank of the block
+    auto orow = [&](int64_t q) -> int64_t { return local ? q - q_begin : (int64_t)perm[q]; };
     const int c0 = wv * 16 * NT;                          // this wave's first feature column
     const bool wact = c0 < d;                             // (d < 64: waves past d only walk)
     const int m = lane & 15, kq = lane >> 4;
     const int row = t % G, vt = t / G;                    // walking role
-    const bool row_ok = q0 + row < n;
+    const bool row_ok = q0 + row < q_end;
     const int64_t qr = row_ok ? q0 + row : q0;
 
     floatx4 acc[RT][NT];
@@ -186,13 +190,13 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
             for (int i = 0; i < NT; i++) acc[r][i] = floatx4{0.f, 0.f, 0.f, 0.f};
     } else {
         // clamped (always valid) loads, all in flight before the first is used
-        uint32_t gq[RT][4];
+        int64_t gq[RT][4];
 #pragma unroll
         for (int r = 0; r < RT; r++)
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const int64_t q = q0 + 16 * r + 4 * kq + j;
-                gq[r][j] = perm[q < n ? q : n - 1];
+                gq[r][j] = orow(q < q_end ? q : q_end - 1);
             }
 #pragma unroll
         for (int r = 0; r < RT; r++)
@@ -202,22 +206,27 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
                 for (int j = 0; j < 4; j++) {
                     const int64_t q = q0 + 16 * r + 4 * kq + j;
                     const float x = num[(size_t)gq[r][j] * d + (wact ? c0 + 16 * i + m : 0)];
-                    acc[r][i][j] = (wact && q < n) ? x : 0.0f;
+                    acc[r][i][j] = (wact && q < q_end) ? x : 0.0f;
                 }
-        if (t < G && q0 + t < n) dsum = den[perm[q0 + t]];
+        if (t < G && q0 + t < q_end) dsum = den[orow(q0 + t)];
     }
 
-    auto pair_at = [&](int v) -> uint32_t {
-        const int vc = v < nb ? v : nb - 1;                 // clamped: always a valid address
-        const uint32_t p = pair_of_m[(int64_t)vc * n + qr];
-        return (row_ok && v < nb) ? p : NONE;
+    // only the views in which this block's Gaussian block has visible pairs
+    // (ascending): slot i of the walk is view vl[i]
+    const int64_t cb = q0 / GBLOCK;
+    const uint16_t* vl = vlist + (size_t)cb * (size_t)nb;
+    const int nvb = (int)vcnt[cb];
+    auto pair_at = [&](int i) -> uint32_t {
+        const int v = i < nvb ? (int)vl[i] : 0;            // clamped: always a valid address
+        const uint32_t p = pair_of_m[(int64_t)v * n + qr];
+        return (row_ok && i < nvb) ? p : NONE;
     };
     uint32_t pn[VPT];
 #pragma unroll
     for (int j = 0; j < VPT; j++) pn[j] = pair_at(vt + GT * j);
 
-    for (int v0 = 0; v0 < nb; v0 += GV) {
-        // this step's pairs (view v0 + vt + GT j); the next step's in flight
+    for (int v0 = 0; v0 < nvb; v0 += GV) {
+        // this step's pairs (slot v0 + vt + GT j); the next step's in flight
         uint32_t pb[VPT], cnt[VPT], nsv = 0;
         bool any = false;
 #pragma unroll
@@ -229,8 +238,8 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
             if (p != NONE) pi = pinfo[p];                 // (base, fill): one load
             pb[j] = pi.x;
             cnt[j] = pi.y;
-            const int v = v0 + vt + GT * j;
-            nsv = max(nsv, v < nb ? views[v].nseg : 0u);
+            const int i = v0 + vt + GT * j;
+            nsv = max(nsv, i < nvb ? views[vl[i]].nseg : 0u);
         }
         if (!__syncthreads_or(any)) continue;
         // stage the step's entries: thread t's lists go to [soff[t], ...) in
@@ -329,8 +338,8 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
                     const int i = VPT * t + j;
                     uint32_t bb = wb[j];
                     if (!bb) continue;
-                    const int vw = v0 + (i >> 3);
-                    const uint32_t so = vw < nb ? views[vw].seg_off : 0u;
+                    const int iw = v0 + (i >> 3);
+                    const uint32_t so = iw < nvb ? views[vl[iw]].seg_off : 0u;
                     uint32_t c = L.wbase[i];
                     while (bb) {
                         const uint32_t bit = (uint32_t)(__ffs((int)bb) - 1);
@@ -371,7 +380,7 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
         for (int j = 0; j < VPT; j++) L.dpart[vt + GT * j][row] = from_fx(dv[j]);
         __syncthreads();
         if (t < G) {
-            const int nv = min(GV, nb - v0);
+            const int nv = min(GV, nvb - v0);
             for (int i = 0; i < nv; i++) dsum += L.dpart[i][t];
         }
     }
@@ -385,8 +394,8 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
         for (int j = 0; j < 4; j++) {
             const int rr = 16 * r + 4 * kq + j;
             const int64_t q = q0 + rr;
-            if (q >= n || !wact) continue;
-            const uint32_t g = perm[q];
+            if (q >= q_end || !wact) continue;
+            const int64_t g = orow(q);
             const float dn = drow[rr];
 #pragma unroll
             for (int i = 0; i < NT; i++) {
@@ -394,25 +403,57 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
                 num[(size_t)g * d + c0 + 16 * i + m] = last ? (dn > 0.0f ? a / dn : 0.0f) : a;
             }
         }
-    if (t < G && q0 + t < n) den[perm[q0 + t]] = dsum;
+    if (t < G && q0 + t < q_end) den[orow(q0 + t)] = dsum;
 }
 
 template <int NT, int RT>
 void launch_nt(int64_t n, int nb, int d, bool bf16, const uint32_t* perm, const uint32_t* pair_of_m,
-               const ViewDev* views, const uint2* pinfo,
+               const ViewDev* views, const uint16_t* vlist, const uint32_t* vcnt, const uint2* pinfo,
                const uint2* part, const void* feats, float* num, float* den, bool first, bool last,
-               hipStream_t st)
+               int64_t q_begin, int64_t q_end, bool local, hipStream_t st)
 {
     constexpr int G = 16 * RT;
-    const dim3 grid((unsigned)((n + G - 1) / G));
+    static_assert(GBLOCK % G == 0, "contraction blocks lie inside one Gaussian block");
+    const dim3 grid((unsigned)((q_end - q_begin + G - 1) / G));
     if (bf16)
         hipLaunchKernelGGL((k_contract_mfma<NT, true, RT>), grid, dim3(256), 0, st, n, nb, d, perm,
-                           pair_of_m, views, pinfo, part, feats, num, den, (int)first,
-                           (int)last);
+                           pair_of_m, views, vlist, vcnt, pinfo, part, feats, num, den, (int)first,
+                           (int)last, q_begin, q_end, (int)local);
     else
         hipLaunchKernelGGL((k_contract_mfma<NT, false, RT>), grid, dim3(256), 0, st, n, nb, d, perm,
-                           pair_of_m, views, pinfo, part, feats, num, den, (int)first,
-                           (int)last);
+                           pair_of_m, views, vlist, vcnt, pinfo, part, feats, num, den, (int)first,
+                           (int)last, q_begin, q_end, (int)local);
+}
+
+// Views in which each Gaussian block has visible pairs, ascending:
+// vlist[blk nb + i], i < vcnt[blk]; blk_off = exclusive scan of the visible
+// pair counts per (view, block), nb nblk + 1 entries.
+__global__ __launch_bounds__(256) void k_view_lists(int nb, int nblk, const uint32_t* __restrict__ blk_off,
+                                                    uint16_t* __restrict__ vlist,
+                                                    uint32_t* __restrict__ vcnt)
+{
+    __shared__ uint32_t wc[4];
+    const int blk = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t base = 0;
+    for (int v0 = 0; v0 < nb; v0 += 256) {
+        const int v = v0 + (int)threadIdx.x;
+        bool vis = false;
+        if (v < nb) {
+            const int64_t bi = (int64_t)v * nblk + blk;
+            vis = blk_off[bi + 1] != blk_off[bi];
+        }
+        const uint64_t m = __ballot(vis);
+        if (lane == 0) wc[wv] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t off = 0;
+        for (int w = 0; w < wv; w++) off += wc[w];
+        const uint32_t tot = wc[0] + wc[1] + wc[2] + wc[3];
+        if (vis) vlist[(size_t)blk * nb + base + off + (uint32_t)__popcll(m & lt)] = (uint16_t)v;
+        base += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) vcnt[blk] = base;
 }
 
 __global__ __launch_bounds__(256) void k_f32_to_bf16(uint64_t n, const float* __restrict__ in,
@@ -441,14 +482,24 @@ bool contract_supported(int d)
 
 bool contract_supported_codes(int d) { return d == 16 || d == 32 || d == 48 || contract_supported(d); }
 
-void launch_contract(int64_t n, int nb, int d, bool bf16, const uint32_t* perm,
-                     const uint32_t* pair_of_m, const ViewDev* views, const uint2* pinfo,
-                     const uint2* part, const void* feats, float* num,
-                     float* den, bool first, bool last, hipStream_t st)
+void launch_view_lists(int nb, int nblk, const uint32_t* blk_off, uint16_t* vlist, uint32_t* vcnt,
+                       hipStream_t st)
 {
-    if (n <= 0) return;
-#define SLAG_NT(NTV) launch_nt<NTV, kContractRT>(n, nb, d, bf16, perm, pair_of_m, views, pinfo, part, \
-                                    feats, num, den, first, last, st)
+    if (nb <= 0 || nblk <= 0) return;
+    hipLaunchKernelGGL(k_view_lists, dim3((unsigned)nblk), dim3(256), 0, st, nb, nblk, blk_off, vlist,
+                       vcnt);
+}
+
+void launch_contract(int64_t n, int nb, int d, bool bf16, const uint32_t* perm,
+                     const uint32_t* pair_of_m, const ViewDev* views, const uint16_t* vlist,
+                     const uint32_t* vcnt, const uint2* pinfo, const uint2* part, const void* feats,
+                     float* num, float* den, bool first, bool last, int64_t q_begin, int64_t q_end,
+                     bool local, hipStream_t st)
+{
+    if (n <= 0 || q_end <= q_begin) return;
+#define SLAG_NT(NTV) launch_nt<NTV, kContractRT>(n, nb, d, bf16, perm, pair_of_m, views, vlist, vcnt, \
+                                    pinfo, part, feats, num, den, first, last, q_begin, q_end,     \
+                                    local, st)
     switch (d) {
     case 16:
     case 32:

@@ -8,17 +8,19 @@
 // sqrt, no other contraction (this file is built with -ffp-contract=off).
 // The same sequence written independently on the CPU reproduces the depth
 // keys and tile lists bit for bit.
+#include <algorithm>
+
 #include "slag_internal.h"
 
 namespace slag {
 
 namespace {
 
-constexpr float NEAR = 0.01f;
-constexpr float DIL = 0.3f;              // screen-space dilation (px^2)
-constexpr float RHO2 = 0x1.62a41p+3f;    // float nearest to 2 ln 255: q bound of alpha >= 1/255
+// The near plane, the screen-space dilation and the pixel box's q bound
+// (rho^2 = 2 ln(1 / alpha_min)) come with each view (the context's options).
 constexpr int PER_THREAD = 8;
 constexpr int CPB = 256 * PER_THREAD;    // Gaussians per block and view
+static_assert(CPB == GBLOCK, "projection blocks are the Gaussian blocks of the view lists");
 
 struct Proj {
     float u, v, ca, cb, cc, z;
@@ -61,7 +63,7 @@ __device__ __forceinline__ bool project(const ViewDev& V, float mx, float my, fl
     float Y = fmaf(R[3], mx, fmaf(R[4], my, fmaf(R[5], mz, V.t[1])));
     float Z = fmaf(R[6], mx, fmaf(R[7], my, fmaf(R[8], mz, V.t[2])));
     P.z = Z;
-    if (!(Z > NEAR)) return false;
+    if (!(Z > V.near_z)) return false;
     float iz = 1.0f / Z;
     float txr = X * iz, tyr = Y * iz;
     float tx = fminf(V.limx, fmaxf(-V.limx, txr));
@@ -80,9 +82,9 @@ __device__ __forceinline__ bool project(const ViewDev& V, float mx, float my, fl
     float b3 = fmaf(a3, sxx, fmaf(a4, sxy, a5 * sxz));
     float b4 = fmaf(a3, sxy, fmaf(a4, syy, a5 * syz));
     float b5 = fmaf(a3, sxz, fmaf(a4, syz, a5 * szz));
-    float c00 = fmaf(b0, a0, fmaf(b1, a1, b2 * a2)) + DIL;
+    float c00 = fmaf(b0, a0, fmaf(b1, a1, b2 * a2)) + V.dil;
     float c01 = fmaf(b0, a3, fmaf(b1, a4, b2 * a5));
-    float c11 = fmaf(b3, a3, fmaf(b4, a4, b5 * a5)) + DIL;
+    float c11 = fmaf(b3, a3, fmaf(b4, a4, b5 * a5)) + V.dil;
     float det = fmaf(c00, c11, -(c01 * c01));
     if (!(det > 0.0f)) return false;
     float idet = 1.0f / det;
@@ -93,8 +95,8 @@ __device__ __forceinline__ bool project(const ViewDev& V, float mx, float my, fl
     float v = fmaf(V.fy, tyr, V.cy);
     P.u = u;
     P.v = v;
-    float ex = sqrtf(RHO2 * c00);
-    float ey = sqrtf(RHO2 * c11);
+    float ex = sqrtf(V.rho2 * c00);
+    float ey = sqrtf(V.rho2 * c11);
     float x0 = ceilf(u - (ex + 1.5f)), x1 = floorf(u + (ex + 0.5f));
     float y0 = ceilf(v - (ey + 1.5f)), y1 = floorf(v + (ey + 0.5f));
     float wm1 = (float)(V.W - 1), hm1 = (float)(V.H - 1);
@@ -120,8 +122,8 @@ __device__ __forceinline__ void project_fine(const ViewDev& V, float mx, float m
     const double X = (double)R[0] * mx + (double)R[1] * my + (double)R[2] * mz + (double)V.t[0];
     const double Y = (double)R[3] * mx + (double)R[4] * my + (double)R[5] * mz + (double)V.t[1];
     const double Z = (double)R[6] * mx + (double)R[7] * my + (double)R[8] * mz + (double)V.t[2];
-    const double limx = 1.3 * (0.5 * (double)V.W / (double)V.fx);
-    const double limy = 1.3 * (0.5 * (double)V.H / (double)V.fy);
+    const double limx = V.guard_d * (0.5 * (double)V.W / (double)V.fx);
+    const double limy = V.guard_d * (0.5 * (double)V.H / (double)V.fy);
     const double txz = X / Z, tyz = Y / Z;
     const double tx = fmin(limx, fmax(-limx, txz)), ty = fmin(limy, fmax(-limy, tyz));
     const double j00 = (double)V.fx / Z, j02 = -j00 * tx;
@@ -139,9 +141,9 @@ __device__ __forceinline__ void project_fine(const ViewDev& V, float mx, float m
     const double b3 = a[3] * sxx + a[4] * sxy + a[5] * sxz;
     const double b4 = a[3] * sxy + a[4] * syy + a[5] * syz;
     const double b5 = a[3] * sxz + a[4] * syz + a[5] * szz;
-    const double c00 = b0 * a[0] + b1 * a[1] + b2 * a[2] + 0.3;
+    const double c00 = b0 * a[0] + b1 * a[1] + b2 * a[2] + V.dil_d;
     const double c01 = b0 * a[3] + b1 * a[4] + b2 * a[5];
-    const double c11 = b3 * a[3] + b4 * a[4] + b5 * a[5] + 0.3;
+    const double c11 = b3 * a[3] + b4 * a[4] + b5 * a[5] + V.dil_d;
     const double idet = 1.0 / (c00 * c11 - c01 * c01);
     const double L2E = 1.4426950408889634074;
     const double u = (double)V.fx * txz + (double)V.cx;
@@ -179,6 +181,87 @@ __device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* lds, uint
     total = lds[0] + lds[1] + lds[2] + lds[3];
     __syncthreads();
     return off + x - v;
+}
+
+// Per block of CPB consecutive (Morton-ordered) Gaussians: the bounding box
+// of the means and the largest trace of the world covariance (a bound of
+// the variance along any axis): geo[8 blk + (0..2: min xyz, 3..5: max xyz,
+// 6: max trace)].
+__global__ __launch_bounds__(256) void k_block_geo(int64_t n, const float* __restrict__ means,
+                                                   const float* __restrict__ cov3,
+                                                   float* __restrict__ geo)
+{
+    __shared__ float red[4][7];
+    const int64_t b0 = (int64_t)blockIdx.x * CPB;
+    float v[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0f};
+    for (int64_t g = b0 + threadIdx.x; g < n && g < b0 + CPB; g += 256) {
+        for (int k = 0; k < 3; k++) {
+            const float m = means[3 * g + k];
+            v[k] = fminf(v[k], m);
+            v[3 + k] = fmaxf(v[3 + k], m);
+        }
+        v[6] = fmaxf(v[6], cov3[g] + cov3[3 * n + g] + cov3[5 * n + g]);
+    }
+    for (int o = 32; o >= 1; o >>= 1)
+        for (int k = 0; k < 7; k++) {
+            const float w = __shfl_xor(v[k], o, 64);
+            v[k] = (k < 3) ? fminf(v[k], w) : fmaxf(v[k], w);
+        }
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 7; k++) red[threadIdx.x >> 6][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        const int k = threadIdx.x;
+        float r = red[0][k];
+        for (int w = 1; w < 4; w++) r = (k < 3) ? fminf(r, red[w][k]) : fmaxf(r, red[w][k]);
+        geo[8 * blockIdx.x + k] = r;
+    }
+}
+
+// Can no Gaussian of a block have a non-empty pixel box in view V?  A
+// conservative bound, with margins far beyond any FP32 rounding: the camera
+// depth and the screen coordinates x/z, y/z of the means are extreme at the
+// corners of the block's box (affine and linear-fractional maps of a box in
+// front of the camera), and a pixel box's half-extent is at most
+// sqrt(rho^2 ((f / z_min)^2 (1 + lim^2) trace + dilation)) (the Jacobian row
+// has squared norm (f / z)^2 (1 + t^2), t the clamped x/z).  Blocks that the
+// bound cannot rule out are projected Gaussian by Gaussian as before, so
+// every visibility decision is unchanged.
+__device__ __forceinline__ bool block_outside(const ViewDev& V, const float* __restrict__ g8)
+{
+    const float* R = V.R;
+    float zmin = INFINITY, zmax = -INFINITY, xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY,
+          ymx = -INFINITY, mag = fabsf(V.t[0]) + fabsf(V.t[1]) + fabsf(V.t[2]);
+    float X[8], Y[8], Z[8];
+#pragma unroll
+    for (int c = 0; c < 8; c++) {
+        const float mx = g8[(c & 1) ? 3 : 0], my = g8[(c & 2) ? 4 : 1], mz = g8[(c & 4) ? 5 : 2];
+        X[c] = fmaf(R[0], mx, fmaf(R[1], my, fmaf(R[2], mz, V.t[0])));
+        Y[c] = fmaf(R[3], mx, fmaf(R[4], my, fmaf(R[5], mz, V.t[1])));
+        Z[c] = fmaf(R[6], mx, fmaf(R[7], my, fmaf(R[8], mz, V.t[2])));
+        zmin = fminf(zmin, Z[c]);
+        zmax = fmaxf(zmax, Z[c]);
+        mag = fmaxf(mag, fabsf(mx) + fabsf(my) + fabsf(mz));
+    }
+    const float tol = 1e-4f * (1.0f + 2.0f * mag);
+    if (zmax < V.near_z - tol) return true;       // every mean behind the near plane
+    if (!(zmin > V.near_z + tol) || !(g8[6] >= 0.0f) || !isfinite(g8[6])) return false;
+#pragma unroll
+    for (int c = 0; c < 8; c++) {
+        xmn = fminf(xmn, X[c] / Z[c]);
+        xmx = fmaxf(xmx, X[c] / Z[c]);
+        ymn = fminf(ymn, Y[c] / Z[c]);
+        ymx = fmaxf(ymx, Y[c] / Z[c]);
+    }
+    const float iz = 1.0f / (zmin - tol);
+    const float ex = sqrtf(V.rho2 * (V.fx * V.fx * iz * iz * (1.0f + V.limx * V.limx) * g8[6] * 1.01f + V.dil)) + 2.0f;
+    const float ey = sqrtf(V.rho2 * (V.fy * V.fy * iz * iz * (1.0f + V.limy * V.limy) * g8[6] * 1.01f + V.dil)) + 2.0f;
+    const float umn = fmaf(V.fx, xmn, V.cx), umx = fmaf(V.fx, xmx, V.cx);
+    const float vmn = fmaf(V.fy, ymn, V.cy), vmx = fmaf(V.fy, ymx, V.cy);
+    const float su = 2.0f + 1e-3f * (fabsf(umn) + fabsf(umx));
+    const float sv = 2.0f + 1e-3f * (fabsf(vmn) + fabsf(vmx));
+    return (umn - ex - 1.5f > (float)(V.W - 1) + su) || (umx + ex + 0.5f < -su) ||
+           (vmn - ey - 1.5f > (float)(V.H - 1) + sv) || (vmx + ey + 0.5f < -sv);
 }
 
 // Upload: validation, the FP32 world covariance of the decision path, and
@@ -235,15 +318,31 @@ __global__ __launch_bounds__(256) void k_prep_gauss(int64_t n, const float* __re
 }
 
 __global__ __launch_bounds__(256) void k_validate_ids(int64_t npix, const int32_t* __restrict__ ids,
-                                                      int32_t nseg, uint32_t* err)
+                                                      int lpp, int32_t nseg, uint32_t* err)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool bad = false;
     for (; i < npix; i += (int64_t)gridDim.x * blockDim.x) {
-        int32_t s = ids[i];
-        bad |= (s < -1) || (s >= nseg);
+        int32_t lab[MAX_LABELS];
+        for (int l = 0; l < lpp; l++) {
+            const int32_t s = ids[i * lpp + l];
+            lab[l] = s;
+            bad |= (s < -1) || (s >= nseg);
+            for (int m = 0; m < l; m++) bad |= s >= 0 && lab[m] == s;   // one mask listed twice
+        }
     }
     if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(err, 2u);
+}
+
+__global__ __launch_bounds__(256) void k_expand_labels(int64_t npix, const int32_t* __restrict__ src,
+                                                       int lin, int32_t* __restrict__ dst, int lout)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix * lout;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = i / lout;
+        const int l = (int)(i - p * lout);
+        dst[i] = l < lin ? src[p * lin + l] : -1;
+    }
 }
 
 // Pass 1: tile count of every (view, Gaussian) pair (0 = not visible), the
@@ -253,6 +352,7 @@ __global__ __launch_bounds__(256) void k_validate_ids(int64_t npix, const int32_
 __global__ __launch_bounds__(256) void k_count(int64_t n, const ViewDev* __restrict__ views,
                                                const float* __restrict__ means,
                                                const float* __restrict__ cov3,
+                                               const float* __restrict__ geo,
                                                uint32_t* __restrict__ tcnt,
                                                uint32_t* __restrict__ blk_vis,
                                                uint32_t* __restrict__ zrange)
@@ -263,6 +363,17 @@ __global__ __launch_bounds__(256) void k_count(int64_t n, const ViewDev* __restr
     const int vl = blockIdx.x;
     const int blk = blockIdx.y, nblk = gridDim.y;
     const ViewDev V = views[vl];
+    if (block_outside(V, geo + 8 * blk)) {
+        // no Gaussian of the block is visible: no pair (the emission skips
+        // the block without reading its tile counts)
+        if (threadIdx.x == 0) {
+            const int64_t bi = (int64_t)vl * nblk + blk;
+            blk_vis[bi] = 0;
+            zrange[2 * bi] = 0xFFFFFFFFu;
+            zrange[2 * bi + 1] = 0;
+        }
+        return;
+    }
     const int64_t g0 = (int64_t)blk * CPB + threadIdx.x;
     uint32_t* out = tcnt + (int64_t)vl * n;
     uint32_t nvis = 0, zmin = 0xFFFFFFFFu, zmax = 0;
@@ -340,6 +451,19 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
     __shared__ uint64_t msk[4][PER_THREAD];
     const int vl = blockIdx.x;                       // grid (view, Gaussian block)
     const int blk = blockIdx.y, nblk = gridDim.y;
+    const int64_t bi0 = (int64_t)vl * nblk + blk;
+    if (blk_off[bi0 + 1] == blk_off[bi0]) {
+        // no visible pair in this (view, block): only the map entries
+        for (int i = 0; i < PER_THREAD; i++) {
+            const int64_t g = (int64_t)blk * CPB + (int64_t)i * 256 + threadIdx.x;
+            if (g < n) pair_of_m[(int64_t)vl * n + g] = NONE;
+        }
+        if (threadIdx.x == 0) {
+            blk_tot[2 * bi0] = 0;
+            blk_tot[2 * bi0 + 1] = 0;
+        }
+        return;
+    }
     const ViewDev V = views[vl];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -460,27 +584,50 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
 
 // Reduction of per-block results: out[0] = min over even entries (u32 min),
 // out[1] = max over odd entries; or (sum mode) 64-bit sums of even and odd
-// entries.  One block; fixed order per thread, so results are deterministic.
+// entries.  Grid-stride blocks, one integer atomic per block into out
+// (initialised by k_reduce_init): integer min, max and sums do not depend on
+// the order, so the results are deterministic.
+__global__ __launch_bounds__(256) void k_reduce_init(int sum_mode, unsigned long long* __restrict__ out)
+{
+    if (threadIdx.x == 0) {
+        out[0] = sum_mode ? 0ull : 0xFFFFFFFFull;
+        out[1] = 0ull;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_reduce_pairs(const uint32_t* __restrict__ in, uint64_t npairs,
                                                       int sum_mode, unsigned long long* __restrict__ out)
 {
-    __shared__ unsigned long long a_l[256], b_l[256];
+    __shared__ unsigned long long a_l[4], b_l[4];
     unsigned long long a = sum_mode ? 0ull : 0xFFFFFFFFull, b = 0ull;
-    for (uint64_t i = threadIdx.x; i < npairs; i += 256) {
-        const uint32_t x = in[2 * i], y = in[2 * i + 1];
-        if (sum_mode) { a += x; b += y; }
-        else { a = min(a, (unsigned long long)x); b = max(b, (unsigned long long)y); }
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < npairs;
+         i += (uint64_t)gridDim.x * 256) {
+        const uint2 xy = reinterpret_cast<const uint2*>(in)[i];
+        if (sum_mode) { a += xy.x; b += xy.y; }
+        else { a = min(a, (unsigned long long)xy.x); b = max(b, (unsigned long long)xy.y); }
     }
-    a_l[threadIdx.x] = a;
-    b_l[threadIdx.x] = b;
+    for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned long long ao = __shfl_xor(a, o, 64), bo = __shfl_xor(b, o, 64);
+        if (sum_mode) { a += ao; b += bo; }
+        else { a = min(a, ao); b = max(b, bo); }
+    }
+    if ((threadIdx.x & 63) == 0) {
+        a_l[threadIdx.x >> 6] = a;
+        b_l[threadIdx.x >> 6] = b;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int i = 1; i < 256; i++) {
-            if (sum_mode) { a += a_l[i]; b += b_l[i]; }
-            else { a = min(a, a_l[i]); b = max(b, b_l[i]); }
+        for (int w = 1; w < 4; w++) {
+            if (sum_mode) { a += a_l[w]; b += b_l[w]; }
+            else { a = min(a, a_l[w]); b = max(b, b_l[w]); }
         }
-        out[0] = a;
-        out[1] = b;
+        if (sum_mode) {
+            atomicAdd(&out[0], a);
+            atomicAdd(&out[1], b);
+        } else {
+            atomicMin(&out[0], a);
+            atomicMax(&out[1], b);
+        }
     }
 }
 
@@ -595,22 +742,39 @@ void launch_prep_gauss(int64_t n, const float* means, const float* scales, const
                        scales, quats, opac, cov3, covd, lo2, err);
 }
 
-void launch_validate_ids(int64_t npix, const int32_t* ids, int32_t nseg, uint32_t* err,
+void launch_expand_labels(int64_t npix, const int32_t* src, int lin, int32_t* dst, int lout,
+                          hipStream_t st)
+{
+    if (npix <= 0) return;
+    const int64_t blocks = std::min<int64_t>((npix * lout + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_expand_labels, dim3((unsigned)blocks), dim3(256), 0, st, npix, src, lin, dst,
+                       lout);
+}
+
+void launch_validate_ids(int64_t npix, const int32_t* ids, int lpp, int32_t nseg, uint32_t* err,
                          hipStream_t st)
 {
     if (npix <= 0) return;
     int64_t blocks = (npix + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_validate_ids, dim3((unsigned)blocks), dim3(256), 0, st, npix, ids, nseg,
-                       err);
+    hipLaunchKernelGGL(k_validate_ids, dim3((unsigned)blocks), dim3(256), 0, st, npix, ids,
+                       lpp < 1 ? 1 : lpp, nseg, err);
+}
+
+void launch_block_geo(int64_t n, const float* means, const float* cov3, float* geo, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_block_geo, dim3((unsigned)count_blocks_per_view(n)), dim3(256), 0, st, n,
+                       means, cov3, geo);
 }
 
 void launch_count(int nb, int64_t n, const ViewDev* views, const float* means, const float* cov3,
-                  uint32_t* tcnt, uint32_t* blk_vis, uint32_t* zrange, hipStream_t st)
+                  const float* geo, uint32_t* tcnt, uint32_t* blk_vis, uint32_t* zrange,
+                  hipStream_t st)
 {
     if (n <= 0 || nb <= 0) return;
     hipLaunchKernelGGL(k_count, dim3((unsigned)nb, (unsigned)count_blocks_per_view(n)), dim3(256),
-                       0, st, n, views, means, cov3, tcnt, blk_vis, zrange);
+                       0, st, n, views, means, cov3, geo, tcnt, blk_vis, zrange);
 }
 
 void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* means,
@@ -632,8 +796,11 @@ void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* mea
 void launch_reduce_pairs(const uint32_t* in, uint64_t npairs, bool sum_mode,
                          unsigned long long* out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(256), 0, st, in, npairs, sum_mode ? 1 : 0,
-                       out);
+    hipLaunchKernelGGL(k_reduce_init, dim3(1), dim3(64), 0, st, sum_mode ? 1 : 0, out);
+    if (!npairs) return;
+    const uint64_t blocks = std::min<uint64_t>((npairs + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_reduce_pairs, dim3((unsigned)blocks), dim3(256), 0, st, in, npairs,
+                       sum_mode ? 1 : 0, out);
 }
 
 void launch_bbox(int64_t n, const float* means, uint32_t* box6, hipStream_t st)

@@ -19,10 +19,9 @@ namespace slag {
 
 namespace {
 
-constexpr float AMIN = 1.0f / 255.0f;
-constexpr float AMAX = 0.99f;
-constexpr float TMIN = 1e-4f;
-constexpr float LOG2_AMIN = -7.99435343685885793770f;     // log2(1 / 255)
+// alpha_min, alpha_max, the transmittance stop t_min and log2(alpha_min)
+// come with each view (the context's options; 3D Gaussian splatting's
+// 1/255, 0.99 and 1e-4 by default).
 
 __device__ __forceinline__ void box_of(const float4& r1, int& x0, int& x1, int& y0, int& y1)
 {
@@ -56,20 +55,25 @@ __device__ __forceinline__ uint32_t sat_rect(const uint32_t* S, int sw, int xa, 
     return S[(yb + 1) * sw + xb + 1] - S[ya * sw + xb + 1] - S[(yb + 1) * sw + xa] + S[ya * sw + xa];
 }
 
-// Distinct segment ids of each tile, ascending.  Each wave extracts the
-// distinct ids among its 64 pixels with a ballot loop (one iteration per
-// distinct id); the up to 4 x 64 candidates are then merged: a candidate is
-// kept if no earlier candidate has its id, and goes to the position given by
-// the number of kept candidates with a smaller id.  Tiles hold few segments,
-// so both loops are short; 256 distinct ids cost 2 x 256 LDS reads per thread.
+// Distinct segment ids of each tile, ascending, over every label layer of
+// its pixels (a pixel lies in up to lpp masks; -1 = none).  Each wave
+// extracts the distinct ids among its 64 pixels with a ballot loop per layer
+// (one iteration per distinct id; an id already found in an earlier layer is
+// not repeated); the candidates of the four waves are then merged: a
+// candidate is kept if no candidate of an earlier wave has its id, and goes
+// to the position given by the number of kept candidates with a smaller id.
+// Tiles hold few segments, so both loops are short.  More than TILE_PIX
+// distinct ids in one tile (only possible with several layers) set bit 4 of
+// *err and keep the TILE_PIX smallest.
 __global__ __launch_bounds__(256) void k_tile_segs(const uint32_t* __restrict__ bucket_view,
                                                    const ViewDev* __restrict__ views,
-                                                   const int32_t* __restrict__ ids,
+                                                   const int32_t* __restrict__ ids, int lpp,
                                                    uint32_t* __restrict__ ns_tile,
-                                                   uint16_t* __restrict__ segl)
+                                                   uint16_t* __restrict__ segl,
+                                                   unsigned long long* __restrict__ err)
 {
-    __shared__ uint32_t cand[4][64];
-    __shared__ uint32_t keep[TILE_PIX];
+    __shared__ uint32_t cand[4][64 * MAX_LABELS];
+    __shared__ uint32_t keep[4 * 64 * MAX_LABELS];
     __shared__ uint32_t wn[4];
     const uint32_t b = blockIdx.x;
     const ViewDev& V = views[bucket_view[b]];
@@ -77,51 +81,64 @@ __global__ __launch_bounds__(256) void k_tile_segs(const uint32_t* __restrict__ 
     const int tx = (int)(tile % (uint32_t)V.ntx), ty = (int)(tile / (uint32_t)V.ntx);
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int px = tx * TILE + (t & (TILE - 1)), py = ty * TILE + t / TILE;
-    int32_t id = -1;
-    if (px < V.W && py < V.H) id = ids[V.pix_off + (uint64_t)py * V.W + px];
-    // 1. distinct ids of this wave's pixels
-    bool left = id >= 0;
+    const bool inside = px < V.W && py < V.H;
+    const uint64_t pb = (V.pix_off + (uint64_t)py * V.W + px) * (uint64_t)lpp;
+    // 1. distinct ids of this wave's pixels, layer by layer
     uint32_t nc = 0;
-    for (;;) {
-        const uint64_t act = __ballot(left);
-        if (!act) break;
-        const int v = __builtin_amdgcn_readlane(id, __ffsll((long long)act) - 1);
-        if (lane == 0) cand[w][nc] = (uint32_t)v;
-        nc++;
-        left = left && id != v;
+    for (int l = 0; l < lpp; l++) {
+        const int32_t id = inside ? ids[pb + l] : -1;
+        bool left = id >= 0;
+        const uint32_t nprev = nc;             // candidates of earlier layers
+        for (;;) {
+            const uint64_t act = __ballot(left);
+            if (!act) break;
+            const int v = __builtin_amdgcn_readlane(id, __ffsll((long long)act) - 1);
+            bool dup = false;
+            for (uint32_t i = 0; i < nprev; i++) dup = dup || cand[w][i] == (uint32_t)v;
+            if (!dup) {
+                if (lane == 0) cand[w][nc] = (uint32_t)v;
+                nc++;
+            }
+            left = left && id != v;
+        }
     }
     if (lane == 0) wn[w] = nc;
     __syncthreads();
     // 2. merge: candidate i of the flat list (waves in order)
     const uint32_t n0 = wn[0], n1 = wn[1], n2 = wn[2], n3 = wn[3];
     const uint32_t C = n0 + n1 + n2 + n3;
-    uint32_t c = 0xFFFFFFFFu;
-    bool kept = false;
-    if ((uint32_t)t < C) {
-        const uint32_t i = (uint32_t)t;
+    for (uint32_t i = (uint32_t)t; i < C; i += 256) {
         const int cw = i < n0 ? 0 : i < n0 + n1 ? 1 : i < n0 + n1 + n2 ? 2 : 3;
         const uint32_t ci = i - (cw > 0 ? n0 : 0) - (cw > 1 ? n1 : 0) - (cw > 2 ? n2 : 0);
-        c = cand[cw][ci];
+        const uint32_t c = cand[cw][ci];
         // earlier waves' candidates with the same id (a wave's own are distinct)
-        kept = true;
+        bool kept = true;
         for (int u = 0; u < cw && kept; u++) {
             const uint32_t nu = u == 0 ? n0 : u == 1 ? n1 : n2;
             for (uint32_t j = 0; j < nu; j++)
                 if (cand[u][j] == c) { kept = false; break; }
         }
+        keep[i] = kept ? c : 0xFFFFFFFFu;
     }
-    keep[t] = kept ? c : 0xFFFFFFFFu;
     __syncthreads();
-    if (kept) {
+    uint32_t nk = 0;
+    for (uint32_t i = (uint32_t)t; i < C; i += 256) {
+        const uint32_t c = keep[i];
+        if (c == 0xFFFFFFFFu) continue;
+        nk++;
         uint32_t pos = 0;
         for (uint32_t j = 0; j < C; j++) pos += keep[j] < c;
-        segl[(uint64_t)b * TILE_PIX + pos] = (uint16_t)c;
+        if (pos < (uint32_t)TILE_PIX) segl[(uint64_t)b * TILE_PIX + pos] = (uint16_t)c;
     }
-    const uint64_t km = __ballot(kept);
+    for (int o = 32; o >= 1; o >>= 1) nk += __shfl_xor(nk, o, 64);
     __syncthreads();
-    if (lane == 0) wn[w] = (uint32_t)__popcll(km);
+    if (lane == 0) wn[w] = nk;
     __syncthreads();
-    if (t == 0) ns_tile[b] = wn[0] + wn[1] + wn[2] + wn[3];
+    if (t == 0) {
+        const uint32_t K = wn[0] + wn[1] + wn[2] + wn[3];
+        ns_tile[b] = K < (uint32_t)TILE_PIX ? K : (uint32_t)TILE_PIX;
+        if (K > (uint32_t)TILE_PIX) atomicOr(err, 4ull);
+    }
 }
 
 // Per-view summed-area table of the tile segment counts: (nty+1) x (ntx+1).
@@ -177,7 +194,7 @@ __device__ __forceinline__ float qmax_edge(float a, float t0, float t1, float P,
 // blend sums) beyond any rounding of the blend's own evaluation: then every
 // pixel gets alpha < 1/255 and is left unchanged, so dropping it is exact.
 __device__ __forceinline__ bool reaches_amin(float A, float B, float C, float lo2, float x0,
-                                             float x1, float y0, float y1)
+                                             float x1, float y0, float y1, float l2amin)
 {
     float m = 0.0f;
     if (!(x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f))
@@ -185,7 +202,7 @@ __device__ __forceinline__ bool reaches_amin(float A, float B, float C, float lo
                   fmaxf(qmax_edge(y0, x0, x1, C, B, A), qmax_edge(y1, x0, x1, C, B, A)));
     const float d = fmaxf(fmaxf(fabsf(x0), fabsf(x1)), fmaxf(fabsf(y0), fabsf(y1))) + 8.0f;
     const float mag = 3.0f * (fabsf(A) + fabsf(B) + fabsf(C)) * d * d + fabsf(lo2);
-    return lo2 + m >= LOG2_AMIN - 0.01f - 1e-6f * mag;
+    return lo2 + m >= l2amin - 0.01f - 1e-6f * mag;
 }
 
 // Wave sums of four per-lane values: on return every lane of row r (lanes
@@ -217,12 +234,14 @@ struct LaneXY {
 template <int MODE, bool COUNTING, bool PAD>
 __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const float4* __restrict__ w1,
                                             const int* __restrict__ wj, int cnt, const LaneXY& Q,
-                                            int px, int py, int slot, int uslot, uint32_t slot_mask,
+                                            int px, int py, uint32_t sbits, int uslot,
+                                            uint32_t slot_mask,
                                             float& T, bool& done, float (*acc)[NS_CAP], int lane,
                                             unsigned long long& n_acc, unsigned long long& n_box,
-                                            unsigned long long& n_tile, float& wsum)
+                                            unsigned long long& n_tile, float& wsum, float amin,
+                                            float amax, float tmin)
 {
-    const bool slot_ok = slot >= 0;
+    const bool slot_ok = sbits != 0;   // the pixel lies in a segment of this pass
     const int r = lane >> 4;
     const bool writer = (lane & 15) == 0;
     for (int g = 0; g < cnt; g += 4) {
@@ -244,11 +263,11 @@ __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const
             const float tx = fmaf(p1.x, Q.ly, fmaf(p0.w, Q.lx, p0.y));   // cx + cxx lx + cxy ly
             const float ty = fmaf(p1.y, Q.ly, p0.z);                       // cy + cyy ly
             const float e = fmaf(ty, Q.ly, fmaf(tx, Q.lx, p0.x));
-            const float alpha = fminf(AMAX, __builtin_amdgcn_exp2f(e));
+            const float alpha = fminf(amax, __builtin_amdgcn_exp2f(e));
             const float Tn = fmaf(-alpha, T, T);
             if (COUNTING) {
-                const bool ok = !done && alpha >= AMIN;
-                const bool stop = ok && Tn < TMIN;
+                const bool ok = !done && alpha >= amin;
+                const bool stop = ok && Tn < tmin;
                 const bool take = ok && !stop;
                 w[u] = (take && slot_ok) ? alpha * T : 0.0f;
                 if (!done && jj < cnt) {
@@ -263,9 +282,9 @@ __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const
                 done = done || stop;
             } else {
                 // T = 0 marks a finished pixel (stopped, or nothing to add in
-                // this pass): then Tn = 0 < TMIN and w = 0 from here on
-                const bool ok = alpha >= AMIN;
-                const bool keep = Tn >= TMIN;
+                // this pass): then Tn = 0 < tmin and w = 0 from here on
+                const bool ok = alpha >= amin;
+                const bool keep = Tn >= tmin;
                 w[u] = (ok && keep) ? alpha * T : 0.0f;
                 T = ok ? (keep ? Tn : 0.0f) : T;
             }
@@ -280,7 +299,7 @@ __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const
             while (sm) {
                 const int sl = __builtin_ctz(sm);
                 sm &= sm - 1u;
-                const bool mine = slot == sl;
+                const bool mine = (sbits >> sl) & 1u;
                 const float s = wave_sum4(mine ? w[0] : 0.0f, mine ? w[1] : 0.0f,
                                           mine ? w[2] : 0.0f, mine ? w[3] : 0.0f);
                 if (writer && jr < cnt) acc[wj[jr]][sl] = s;
@@ -293,16 +312,16 @@ __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const
 // Variants (same arithmetic, bitwise-equal results): MINW = waves per SIMD
 // the register budget must allow; PAD = four-entry groups padded with null
 // entries (loads of a group can be issued together) or cut at the end.
-template <bool COUNT, int MINW, bool PAD>
+template <bool COUNT, int MINW, bool PAD, int LMAX>
 __global__ __launch_bounds__(256, MINW) void k_composite(
     const uint32_t* __restrict__ order, uint32_t obase,
     const uint32_t* __restrict__ bucket_view, const ViewDev* __restrict__ views,
     const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ bend,
     const uint32_t* __restrict__ ival, uint2* __restrict__ pinfo,
     const float4* __restrict__ rec, const uint32_t* __restrict__ ns_tile,
-    const uint16_t* __restrict__ segl, const int32_t* __restrict__ ids, uint2* __restrict__ part,
-    unsigned long long* __restrict__ counters, float* __restrict__ pix_t,
-    float* __restrict__ pix_w, uint32_t* __restrict__ pix_n)
+    const uint16_t* __restrict__ segl, const int32_t* __restrict__ ids, int lpp,
+    uint2* __restrict__ part, unsigned long long* __restrict__ counters,
+    float* __restrict__ pix_t, float* __restrict__ pix_w, uint32_t* __restrict__ pix_n)
 {
     __shared__ float4 s_w0[4][BATCH];         // per wave: entries touching its block, exponent
     __shared__ float4 s_w1[4][BATCH];         //   coefficients (c0, cx, cy, cxx), (cxy, cyy, box, box)
@@ -321,22 +340,31 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
     const uint32_t tile = b - V.tile_base;
     const int tx = (int)(tile % (uint32_t)V.ntx), ty = (int)(tile / (uint32_t)V.ntx);
     const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+    const float amin = V.amin, amax = V.amax, tmin = V.tmin, l2amin = V.l2amin;
     const int bx0 = tx * TILE + (wv & 1) * 8;    // this wave's 8x8 pixel block
     const int by0 = ty * TILE + (wv >> 1) * 8;
     const int px = bx0 + (lane & 7);
     const int py = by0 + (lane >> 3);
     const bool valid = px < V.W && py < V.H;
-    const int32_t seg = valid ? ids[V.pix_off + (uint64_t)py * V.W + px] : -1;
+    // the pixel's segments (masks containing it; LMAX = 1: one id per pixel)
+    int32_t seg[LMAX];
+#pragma unroll
+    for (int l = 0; l < LMAX; l++)
+        seg[l] = (valid && l < lpp) ? ids[(V.pix_off + (uint64_t)py * V.W + px) * (uint64_t)lpp + l] : -1;
     for (uint32_t i = t; i < ns; i += 256) s_seg[i] = segl[(uint64_t)b * TILE_PIX + i];
     __syncthreads();
-    int ls = -1;   // index of this pixel's segment among the tile's segments
-    if (seg >= 0) {
-        int lo = 0, hi = (int)ns - 1;
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if ((int)s_seg[mid] < seg) lo = mid + 1; else hi = mid;
+    int ls[LMAX];   // index of each of the pixel's segments among the tile's segments
+#pragma unroll
+    for (int l = 0; l < LMAX; l++) {
+        ls[l] = -1;
+        if (seg[l] >= 0) {
+            int lo = 0, hi = (int)ns - 1;
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if ((int)s_seg[mid] < seg[l]) lo = mid + 1; else hi = mid;
+            }
+            ls[l] = (int)s_seg[lo] == seg[l] ? lo : -1;   // not kept: a tile over capacity
         }
-        ls = lo;
     }
     // lane offsets from the block centre (bx0 + 4, by0 + 4): the exponent is
     // expanded there, so no lane is more than 3.5 px from the expansion point
@@ -353,24 +381,30 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
         const int g0 = pass * NS_CAP;
         const int nsc = min(NS_CAP, (int)ns - g0);
         const bool counting = COUNT && pass == 0;
-        const int slot = (ls >= g0 && ls < g0 + NS_CAP) ? ls - g0 : -1;
-        // wave-uniform slot when every accumulating lane shares one segment;
-        // else the set of slots present in the wave
+        // this pass's slots of the pixel's segments, as bits
+        uint32_t sbits = 0;
+#pragma unroll
+        for (int l = 0; l < LMAX; l++)
+            if (ls[l] >= g0 && ls[l] < g0 + NS_CAP) sbits |= 1u << (ls[l] - g0);
+        // wave-uniform slot when every accumulating lane has the same single
+        // segment; else the set of slots present in the wave
         int mode = MODE_NONE, uslot = -1;
         uint32_t slot_mask = 0;
         {
-            const uint64_t has = __ballot(slot >= 0);
+            const uint64_t has = __ballot(sbits != 0);
             if (has) {
-                const int first = __builtin_amdgcn_readlane(slot, __ffsll((long long)has) - 1);
-                const bool mixed = __ballot(slot >= 0 && slot != first) != 0;
+                const uint32_t first =
+                    (uint32_t)__builtin_amdgcn_readlane((int)sbits, __ffsll((long long)has) - 1);
+                const bool mixed = (first & (first - 1u)) != 0 ||
+                                   __ballot(sbits != 0 && sbits != first) != 0;
                 mode = mixed ? MODE_MIXED : MODE_UNIFORM;
-                uslot = first;
+                uslot = __builtin_ctz(first);
                 for (int k = 0; k < nsc; k++)
-                    if (__ballot(slot == k)) slot_mask |= 1u << k;
+                    if (__ballot((sbits >> k) & 1u)) slot_mask |= 1u << k;
             }
         }
-        bool done = counting ? !valid : (slot < 0);
-        float T = (counting || slot >= 0) ? 1.0f : 0.0f;
+        bool done = counting ? !valid : (sbits == 0);
+        float T = (counting || sbits != 0) ? 1.0f : 0.0f;
         for (int i = lane; i < BATCH * NS_CAP; i += 64) (&s_acc[wv][0][0])[i] = 0.0f;
         // lane l holds entry l of the batch.  Two-deep prefetch: records of the
         // next batch and list entries of the one after are in flight while a
@@ -413,7 +447,7 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
             const float lo2 = q1.y;                        // log2(o)
             if (!COUNT && hit)
                 hit = reaches_amin(A, B, C, lo2, (float)ax0 - 3.5f - du, (float)ax1 - 3.5f - du,
-                                   (float)ay0 - 3.5f - dv, (float)ay1 - 3.5f - dv);
+                                   (float)ay0 - 3.5f - dv, (float)ay1 - 3.5f - dv, l2amin);
             const uint64_t hm = __ballot(hit);
             const int cnt = __popcll(hm);
             if (hit) {
@@ -446,16 +480,16 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
             if (cnt && !__all(done)) {
                 if (counting) {
                     if (mode == MODE_UNIFORM)
-                        blend_batch<MODE_UNIFORM, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum);
+                        blend_batch<MODE_UNIFORM, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, sbits, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum, amin, amax, tmin);
                     else if (mode == MODE_MIXED)
-                        blend_batch<MODE_MIXED, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum);
+                        blend_batch<MODE_MIXED, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, sbits, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum, amin, amax, tmin);
                     else
-                        blend_batch<MODE_NONE, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum);
+                        blend_batch<MODE_NONE, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, sbits, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum, amin, amax, tmin);
                 } else {
                     if (mode == MODE_UNIFORM)
-                        blend_batch<MODE_UNIFORM, false, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum);
+                        blend_batch<MODE_UNIFORM, false, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, sbits, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum, amin, amax, tmin);
                     else
-                        blend_batch<MODE_MIXED, false, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, slot, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum);
+                        blend_batch<MODE_MIXED, false, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, sbits, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum, amin, amax, tmin);
                 }
             }
             __syncthreads();
@@ -564,11 +598,12 @@ __global__ __launch_bounds__(256) void k_merge(uint64_t npairs, const uint16_t* 
 }  // namespace
 
 void launch_tile_segs(uint32_t nbuckets, const uint32_t* bucket_view, const ViewDev* views,
-                      const int32_t* ids, uint32_t* ns_tile, uint16_t* segl, hipStream_t st)
+                      const int32_t* ids, int lpp, uint32_t* ns_tile, uint16_t* segl,
+                      unsigned long long* err, hipStream_t st)
 {
     if (!nbuckets) return;
-    hipLaunchKernelGGL(k_tile_segs, dim3(nbuckets), dim3(256), 0, st, bucket_view, views, ids,
-                       ns_tile, segl);
+    hipLaunchKernelGGL(k_tile_segs, dim3(nbuckets), dim3(256), 0, st, bucket_view, views, ids, lpp,
+                       ns_tile, segl, err);
 }
 
 void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t* sat,
@@ -591,26 +626,32 @@ void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t
                       uint32_t obase, const uint32_t* bucket_view, const ViewDev* views,
                       const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
                       uint2* pinfo, const float4* rec, const uint32_t* ns_tile,
-                      const uint16_t* segl, const int32_t* ids, uint2* part,
+                      const uint16_t* segl, const int32_t* ids, int lpp, uint2* part,
                       unsigned long long* counters, float* pix_t, float* pix_w, uint32_t* pix_n,
                       hipStream_t st)
 {
     if (!nbuckets) return;
-#define SLAG_COMP(C, W, P)                                                                         \
-    hipLaunchKernelGGL((k_composite<C, W, P>), dim3(nbuckets), dim3(256), 0, st, order, obase,     \
+#define SLAG_COMP(C, W, P, LM)                                                                     \
+    hipLaunchKernelGGL((k_composite<C, W, P, LM>), dim3(nbuckets), dim3(256), 0, st, order, obase, \
                        bucket_view, views, bstart, bend, ival, pinfo, rec,                        \
-                       ns_tile, segl, ids,                                                         \
+                       ns_tile, segl, ids, lpp,                                                    \
                        part, counters, pix_t, pix_w, pix_n)
-    if (count) {
-        SLAG_COMP(true, 8, false);
-        return;
-    }
-    switch (variant) {
-    case 1: SLAG_COMP(false, 6, true); break;
-    case 2: SLAG_COMP(false, 5, true); break;
-    case 3: SLAG_COMP(false, 8, false); break;
-    default: SLAG_COMP(false, 8, true); break;
-    }
+#define SLAG_COMP_V(LM)                                                                            \
+    do {                                                                                           \
+        if (count) {                                                                               \
+            SLAG_COMP(true, 8, false, LM);                                                         \
+            break;                                                                                 \
+        }                                                                                          \
+        switch (variant) {                                                                         \
+        case 1: SLAG_COMP(false, 6, true, LM); break;                                              \
+        case 2: SLAG_COMP(false, 5, true, LM); break;                                              \
+        case 3: SLAG_COMP(false, 8, false, LM); break;                                             \
+        default: SLAG_COMP(false, 8, true, LM); break;                                             \
+        }                                                                                          \
+    } while (0)
+    if (lpp <= 1) SLAG_COMP_V(1);
+    else SLAG_COMP_V(MAX_LABELS);
+#undef SLAG_COMP_V
 #undef SLAG_COMP
 }
 

@@ -194,6 +194,9 @@ static slag_status morton_order(slag_ctx* c, int64_t n)
     release(c2);
     release(d2);
     release(l2);
+    // per Gaussian block: bounding box and largest covariance trace
+    CK(ensure(c, c->bgeo, (size_t)count_blocks_per_view(n) * 32));
+    launch_block_geo(n, c->means.as<float>(), c->cov3.as<float>(), c->bgeo.as<float>(), c->st);
     return SLAG_OK;
 }
 
@@ -239,10 +242,20 @@ static slag_status build_plan(slag_ctx* c)
             std::memcpy(x.t, cam.t, sizeof(x.t));
             x.W = cam.width; x.H = cam.height;
             // guard clamp, same FP32 operations as the CPU decision path
+            const RasterConsts& K = c->rc;
             volatile float hw = 0.5f * (float)cam.width, hh = 0.5f * (float)cam.height;
             volatile float tanx = hw / cam.fx, tany = hh / cam.fy;
-            x.limx = 1.3f * tanx;
-            x.limy = 1.3f * tany;
+            x.limx = K.guard * tanx;
+            x.limy = K.guard * tany;
+            x.near_z = K.near_z;
+            x.dil = K.dil;
+            x.rho2 = K.rho2;
+            x.amin = K.amin;
+            x.amax = K.amax;
+            x.tmin = K.tmin;
+            x.l2amin = K.l2amin;
+            x.guard_d = K.guard_d;
+            x.dil_d = K.dil_d;
             x.ntx = (cam.width + TILE - 1) / TILE;
             x.nty = (cam.height + TILE - 1) / TILE;
             x.tile_base = tb;
@@ -321,8 +334,28 @@ struct ContractTarget {
     const void* table;   // [rows][d] FP32 or BF16
     int d;
     bool bf16;
-    float* out;          // [N][d]
+    float* out;          // [N][d], or [q_end - q_begin][d] rows in Morton order when local
+    float* den;          // [N], or [q_end - q_begin] when local
+    int64_t q_begin = 0, q_end = -1;   // Morton ranks contracted (q_end < 0: all)
+    bool local = false;
 };
+
+// The contraction of one view batch whose part lists are on the device.
+static slag_status contract_batch(slag_ctx* c, Batch& B, bool first, bool last,
+                                  const ContractTarget& ct)
+{
+    hipEvent_t ev;
+    const int cbv = count_blocks_per_view(c->n);
+    CK(stage_begin(c, ST_CONTRACT, &ev));
+    launch_view_lists(B.nb, cbv, c->blk_vis.as<uint32_t>(), c->vlist.as<uint16_t>(),
+                      c->vcnt.as<uint32_t>(), c->st);
+    launch_contract(c->n, B.nb, ct.d, ct.bf16, c->perm.as<uint32_t>(), c->pair_of_m.as<uint32_t>(),
+                    B.views.as<ViewDev>(), c->vlist.as<uint16_t>(), c->vcnt.as<uint32_t>(),
+                    c->pinfo.as<uint2>(), c->part.as<uint2>(), ct.table, ct.out, ct.den, first,
+                    last, ct.q_begin, ct.q_end < 0 ? c->n : ct.q_end, ct.local, c->st);
+    CK(stage_end(c, ST_CONTRACT, ev));
+    return SLAG_OK;
+}
 
 static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
                               const ContractTarget& ct)
@@ -341,8 +374,9 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
     CK(ensure(c, c->ns_tile, (size_t)B.nbuckets * 4));
     CK(ensure(c, c->segl, (size_t)B.nbuckets * TILE_PIX * 2));
     CK(ensure(c, c->sat, (size_t)B.nsat * 4));
-    launch_tile_segs(B.nbuckets, B.bucket_view.as<uint32_t>(), views, c->ids.as<int32_t>(),
-                     c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(), st);
+    launch_tile_segs(B.nbuckets, B.bucket_view.as<uint32_t>(), views, c->ids.as<int32_t>(), c->lpp,
+                     c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
+                     reinterpret_cast<unsigned long long*>(small + SM_LERR), st);
     launch_sat(nb, views, c->ns_tile.as<uint32_t>(), c->sat.as<uint32_t>(), st);
     CK(stage_end(c, ST_TILES, ev));
 
@@ -353,13 +387,18 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
     const uint64_t nblk = (uint64_t)cbv * nb;
     CK(ensure(c, c->tcnt, npq * 4));
     CK(ensure(c, c->blk_vis, nblk * 4 + 16));
+    CK(ensure(c, c->vlist, nblk * 2 + 16));
+    CK(ensure(c, c->vcnt, (size_t)cbv * 4 + 16));
     CK(ensure(c, c->blk_aux, nblk * 8 + 16));
-    CK(ensure_scan(c, nblk));
-    launch_count(nb, n, views, c->means.as<float>(), c->cov3.as<float>(), c->tcnt.as<uint32_t>(),
-                 c->blk_vis.as<uint32_t>(), c->blk_aux.as<uint32_t>(), st);
+    CK(ensure_scan(c, nblk + 1));
+    launch_count(nb, n, views, c->means.as<float>(), c->cov3.as<float>(), c->bgeo.as<float>(),
+                 c->tcnt.as<uint32_t>(), c->blk_vis.as<uint32_t>(), c->blk_aux.as<uint32_t>(), st);
     launch_reduce_pairs(c->blk_aux.as<uint32_t>(), nblk, false,
                         reinterpret_cast<unsigned long long*>(small + SM_ZRANGE), st);
-    scan_u32(c->blk_vis.as<uint32_t>(), nblk, small + SM_TOT, c->scan_ws.p, st);
+    // one extra zero entry: after the scan it holds the total, so every
+    // block's count is the difference of two neighbours
+    launch_fill_u32(c->blk_vis.as<uint32_t>() + nblk, 1, 0u, st);
+    scan_u32(c->blk_vis.as<uint32_t>(), nblk + 1, small + SM_TOT, c->scan_ws.p, st);
     if (!c->capturing) {
         CK(read_small(c, 0, 4));
         B.npairs = c->host_small[SM_TOT];
@@ -576,7 +615,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
                                  B.bucket_view.as<uint32_t>(), views, c->bstart.as<uint32_t>(),
                                  c->bend.as<uint32_t>(), sval, c->pinfo.as<uint2>(), c->rec.as<float4>(),
                                  c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
-                                 c->ids.as<int32_t>(), c->part.as<uint2>(),
+                                 c->ids.as<int32_t>(), c->lpp, c->part.as<uint2>(),
                                  reinterpret_cast<unsigned long long*>(small + SM_COUNTERS),
                                  nullptr, nullptr, nullptr, st);
             };
@@ -594,7 +633,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
                                  B.bucket_view.as<uint32_t>(), views, c->bstart.as<uint32_t>(),
                                  c->bend.as<uint32_t>(), sval, c->pinfo.as<uint2>(), c->rec.as<float4>(),
                                  c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
-                                 c->ids.as<int32_t>(), c->part.as<uint2>(),
+                                 c->ids.as<int32_t>(), c->lpp, c->part.as<uint2>(),
                                  reinterpret_cast<unsigned long long*>(small + SM_COUNTERS),
                                  pix_t, pix_w, pix_n, st);
             };
@@ -616,11 +655,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         }
     }
 
-    CK(stage_begin(c, ST_CONTRACT, &ev));
-    launch_contract(n, nb, ct.d, ct.bf16, c->perm.as<uint32_t>(), c->pair_of_m.as<uint32_t>(),
-                    views, c->pinfo.as<uint2>(), c->part.as<uint2>(),
-                    ct.table, ct.out, c->den.as<float>(), first, last, st);
-    CK(stage_end(c, ST_CONTRACT, ev));
+    CK(contract_batch(c, B, first, last, ct));
 
     c->last_v0 = B.v0;
     c->last_nb = nb;
@@ -650,6 +685,47 @@ slag_status slag_create(int32_t device, void* hip_stream, const slag_options* op
     if (!c) return SLAG_E_OUT_OF_MEMORY;
     c->device = device;
     if (opt) c->opt = *opt;
+    {
+        // rasterizer constants: 0 = 3D Gaussian splatting's default; the FP64
+        // values are the option floats widened, rho^2 = 2 ln(1 / alpha_min)
+        // rounded once (the defaults keep their exact literals)
+        const slag_options& o = c->opt;
+        const float amax = o.alpha_max > 0.0f ? o.alpha_max : 0.99f;
+        const float amin = o.alpha_min > 0.0f ? o.alpha_min : 1.0f / 255.0f;
+        const float tmin = o.t_min > 0.0f ? o.t_min : 1e-4f;
+        const bool ok = std::isfinite(o.alpha_max) && std::isfinite(o.alpha_min) &&
+                        std::isfinite(o.t_min) && std::isfinite(o.dilation) &&
+                        std::isfinite(o.near_z) && std::isfinite(o.guard) && o.alpha_max >= 0.0f &&
+                        o.alpha_min >= 0.0f && o.t_min >= 0.0f && o.dilation >= 0.0f &&
+                        o.near_z >= 0.0f && o.guard >= 0.0f && amin < amax && amax <= 1.0f &&
+                        tmin < 1.0f && (o.deterministic == 0 || o.deterministic == 1);
+        if (!ok) {
+            delete c;
+            return SLAG_E_INVALID_ARG;
+        }
+        if (o.tile_size != 0 && o.tile_size != TILE) {
+            delete c;
+            return SLAG_E_NOT_SUPPORTED;
+        }
+        if (o.labels_per_pixel < 0 || o.labels_per_pixel > MAX_LABELS) {
+            delete c;
+            return SLAG_E_INVALID_ARG;
+        }
+        c->lpp = o.labels_per_pixel > 0 ? o.labels_per_pixel : 1;
+        RasterConsts& K = c->rc;
+        K.amax = amax;
+        K.amin = amin;
+        K.tmin = tmin;
+        K.rho2 = o.alpha_min > 0.0f ? (float)(2.0 * std::log(1.0 / (double)o.alpha_min))
+                                    : 0x1.62a41p+3f;
+        K.l2amin = o.alpha_min > 0.0f ? (float)std::log2((double)o.alpha_min)
+                                      : -7.99435343685885793770f;
+        K.dil = o.dilation > 0.0f ? o.dilation : 0.3f;
+        K.dil_d = o.dilation > 0.0f ? (double)o.dilation : 0.3;
+        K.near_z = o.near_z > 0.0f ? o.near_z : 0.01f;
+        K.guard = o.guard > 0.0f ? o.guard : 1.3f;
+        K.guard_d = o.guard > 0.0f ? (double)o.guard : 1.3;
+    }
     if (hip_stream) {
         c->st = reinterpret_cast<hipStream_t>(hip_stream);
     } else {
@@ -688,7 +764,8 @@ void slag_destroy(slag_ctx* c)
                       &c->pinfo, &c->prect, &c->prank, &c->blk_aux, &c->bkey,
                       &c->bkey_alt, &c->bord, &c->bord_alt, &c->tflag, &c->tpos, &c->tv,
                       &c->tv_alt, &c->tg, &c->thead, &c->tk, &c->tk_alt, &c->pixdbg,
-                      &c->outbf, &c->query.emb, &c->query.q, &c->query.qt, &c->query.counts,
+                      &c->outbf, &c->idstage, &c->bgeo, &c->vlist, &c->vcnt, &c->cnum, &c->cden, &c->cbf,
+                      &c->query.emb, &c->query.q, &c->query.qt, &c->query.counts,
                       &c->query.keys, &c->query.vals, &c->query.keys_alt, &c->query.vals_alt,
                       &c->query.hist, &c->query.scan_ws};
     destroy_graph(c);
@@ -700,6 +777,7 @@ void slag_destroy(slag_ctx* c)
         if (e) hipEventDestroy(e);
     for (auto e : c->free_events) hipEventDestroy(e);
     if (c->host_small) hipHostFree(c->host_small);
+    if (c->chost) hipHostFree(c->chost);
     if (c->own_stream && c->st) hipStreamDestroy(c->st);
     delete c;
 }
@@ -792,7 +870,7 @@ slag_status slag_set_cameras(slag_ctx* c, int32_t n_views, const slag_camera* ca
     }
     off[n_views] = tot;
     HC(c, hipSetDevice(c->device));
-    CK(ensure(c, c->ids, std::max<uint64_t>(tot, 1) * 4));
+    CK(ensure(c, c->ids, std::max<uint64_t>(tot, 1) * 4 * (uint64_t)c->lpp));
     c->cams.assign(cams, cams + n_views);
     c->pix_off = off;
     c->nviews = n_views;
@@ -808,27 +886,50 @@ slag_status slag_set_cameras(slag_ctx* c, int32_t n_views, const slag_camera* ca
 slag_status slag_set_segments(slag_ctx* c, int32_t view, const int32_t* ids, int32_t n_seg,
                               slag_mem where)
 {
+    return slag_set_segments_multi(c, view, ids, 1, n_seg, where);
+}
+
+slag_status slag_set_segments_multi(slag_ctx* c, int32_t view, const int32_t* ids, int32_t nl,
+                                    int32_t n_seg, slag_mem where)
+{
     if (!c) return SLAG_E_INVALID_ARG;
     c->err.clear();
     invalidate_graph(c);
     if (c->nviews < 0) FAIL(c, SLAG_E_STATE, "set cameras before segments");
     if (view < 0 || view >= c->nviews) FAIL(c, SLAG_E_INVALID_ARG, "view index out of range");
     if (!ids || n_seg < 0) FAIL(c, SLAG_E_INVALID_ARG, "null ids or negative segment count");
+    if (nl < 1 || nl > c->lpp)
+        FAIL(c, SLAG_E_INVALID_ARG, "labels per pixel must be in [1, labels_per_pixel = " +
+                                        std::to_string(c->lpp) + "]");
+    if (where != SLAG_HOST && where != SLAG_DEVICE) FAIL(c, SLAG_E_INVALID_ARG, "bad memory kind");
     if (n_seg > 65535) FAIL(c, SLAG_E_NOT_SUPPORTED, "at most 65535 segments per view");
     HC(c, hipSetDevice(c->device));
     const uint64_t npix = c->pix_off[view + 1] - c->pix_off[view];
-    int32_t* dst = c->ids.as<int32_t>() + c->pix_off[view];
-    HC(c, hipMemcpyAsync(dst, ids, npix * 4,
-                         where == SLAG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                         c->st));
+    const int L = c->lpp;
+    int32_t* dst = c->ids.as<int32_t>() + c->pix_off[view] * (uint64_t)L;
+    if (nl == L) {
+        HC(c, hipMemcpyAsync(dst, ids, npix * 4 * (uint64_t)L,
+                             where == SLAG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                             c->st));
+    } else {
+        // fewer labels than the context's layout: widened with -1
+        const int32_t* src = ids;
+        if (where == SLAG_HOST) {
+            CK(ensure(c, c->idstage, npix * 4 * (uint64_t)nl));
+            HC(c, hipMemcpyAsync(c->idstage.p, ids, npix * 4 * (uint64_t)nl, hipMemcpyHostToDevice,
+                                 c->st));
+            src = c->idstage.as<int32_t>();
+        }
+        launch_expand_labels((int64_t)npix, src, nl, dst, L, c->st);
+    }
     uint32_t* err = reinterpret_cast<uint32_t*>(c->small.as<uint64_t>() + SM_ERR);
     launch_fill_u32(err, 1, 0u, c->st);
-    launch_validate_ids((int64_t)npix, dst, n_seg, err, c->st);
+    launch_validate_ids((int64_t)npix, dst, L, n_seg, err, c->st);
     CK(read_small(c, SM_ERR, 1));
     if (c->host_small[SM_ERR] & 2) {
         c->seg_set[view] = 0;
-        FAIL(c, SLAG_E_INVALID_ARG, "segment id out of range [-1, n_seg) in view " +
-                                        std::to_string(view));
+        FAIL(c, SLAG_E_INVALID_ARG, "segment id out of range [-1, n_seg), or a mask listed "
+                                    "twice for one pixel, in view " + std::to_string(view));
     }
     if (c->nseg[view] != n_seg) c->feats_set = false;
     c->nseg[view] = n_seg;
@@ -878,15 +979,16 @@ static slag_status lift_sequence(slag_ctx* c, bool codec)
     const int64_t n = c->n;
     uint64_t* small = c->small.as<uint64_t>();
     launch_fill_u32(reinterpret_cast<uint32_t*>(small + SM_COUNTERS), 12, 0u, c->st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(small + SM_LERR), 2, 0u, c->st);
     if (n == 0) return SLAG_OK;
-    ContractTarget ct{c->feats.p, c->d, c->fdt == SLAG_BF16, c->num.as<float>()};
+    ContractTarget ct{c->feats.p, c->d, c->fdt == SLAG_BF16, c->num.as<float>(), c->den.as<float>()};
     if (codec) {
         hipEvent_t ev;
         CK(stage_begin(c, ST_ENCODE, &ev));
         CK(codec_encode_table(c));
         CK(stage_end(c, ST_ENCODE, ev));
         CK(ensure(c, K.codes, (size_t)n * K.k * 4));
-        ct = ContractTarget{K.C.p, K.k, false, K.codes.as<float>()};
+        ct = ContractTarget{K.C.p, K.k, false, K.codes.as<float>(), c->den.as<float>()};
     }
     if (c->plan.empty()) {
         launch_fill_u32(reinterpret_cast<uint32_t*>(ct.out), (uint64_t)n * ct.d, 0u, c->st);
@@ -943,15 +1045,21 @@ static slag_status capture_lift(slag_ctx* c, bool codec)
     return SLAG_OK;
 }
 
-slag_status run_lift(slag_ctx* c, bool codec)
+static slag_status check_inputs(slag_ctx* c)
 {
-    if (!c) return SLAG_E_INVALID_ARG;
-    c->err.clear();
     if (c->n < 0) FAIL(c, SLAG_E_STATE, "Gaussians not set");
     if (c->nviews < 0) FAIL(c, SLAG_E_STATE, "cameras not set");
     for (int v = 0; v < c->nviews; v++)
         if (!c->seg_set[v]) FAIL(c, SLAG_E_STATE, "segments of view " + std::to_string(v) + " not set");
     if (!c->feats_set) FAIL(c, SLAG_E_STATE, "features not set (or segment counts changed)");
+    return SLAG_OK;
+}
+
+slag_status run_lift(slag_ctx* c, bool codec)
+{
+    if (!c) return SLAG_E_INVALID_ARG;
+    c->err.clear();
+    CK(check_inputs(c));
     CodecState& K = c->codec;
     if (codec && !K.ready) FAIL(c, SLAG_E_STATE, "codec not initialised");
     if (codec && K.d != c->d) FAIL(c, SLAG_E_STATE, "codec dimension differs from the features'");
@@ -1015,6 +1123,77 @@ slag_status run_lift(slag_ctx* c, bool codec)
     return SLAG_OK;
 }
 
+// The lift with the output streamed to host memory in chunks of Morton
+// ranks (slag_lift_chunked).
+static slag_status chunked_lift(slag_ctx* c, int64_t R, void* out, slag_dtype dtype, float* den)
+{
+    const int64_t n = c->n;
+    const int d = c->d;
+    hipStream_t st = c->st;
+    const size_t esz = dtype == SLAG_BF16 ? 2 : 4;
+    CK(ensure(c, c->cnum, (size_t)R * d * 4));
+    CK(ensure(c, c->cden, (size_t)R * 4));
+    if (dtype == SLAG_BF16) CK(ensure(c, c->cbf, (size_t)R * d * 2));
+    const size_t hbytes = (size_t)R * d * esz + (size_t)R * 4;
+    if (c->chost_cap < hbytes) {
+        if (c->chost) hipHostFree(c->chost);
+        c->chost = nullptr;
+        c->chost_cap = 0;
+        if (hipHostMalloc(&c->chost, hbytes, hipHostMallocDefault) != hipSuccess)
+            FAIL(c, SLAG_E_OUT_OF_MEMORY, "pinned staging for a chunked lift");
+        c->chost_cap = hbytes;
+    }
+    std::vector<uint32_t> perm((size_t)n);
+    HC(c, hipMemcpyAsync(perm.data(), c->perm.p, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+    HC(c, hipStreamSynchronize(st));
+    unsigned char* hrow = static_cast<unsigned char*>(c->chost);
+    float* hden = reinterpret_cast<float*>(hrow + (size_t)R * d * esz);
+    const bool single = c->plan.size() == 1;
+    slag_stats first_stats{};
+    for (int64_t r0 = 0; r0 < n; r0 += R) {
+        const int64_t r1 = std::min<int64_t>(n, r0 + R);
+        ContractTarget ct{c->feats.p, d, c->fdt == SLAG_BF16, c->cnum.as<float>(),
+                          c->cden.as<float>(), r0, r1, true};
+        for (size_t i = 0; i < c->plan.size(); i++) {
+            const bool first = i == 0, last = i + 1 == c->plan.size();
+            if (single && r0 > 0) CK(contract_batch(c, c->plan[i], first, last, ct));
+            else CK(lift_batch(c, c->plan[i], first, last, ct));
+        }
+        if (r0 == 0) first_stats = c->stats;
+        const int64_t rows = r1 - r0;
+        if (out) {
+            if (dtype == SLAG_BF16) {
+                launch_f32_to_bf16((uint64_t)rows * d, c->cnum.as<float>(), c->cbf.as<uint16_t>(), st);
+                HC(c, hipMemcpyAsync(hrow, c->cbf.p, (size_t)rows * d * 2, hipMemcpyDeviceToHost, st));
+            } else {
+                HC(c, hipMemcpyAsync(hrow, c->cnum.p, (size_t)rows * d * 4, hipMemcpyDeviceToHost, st));
+            }
+        }
+        if (den) HC(c, hipMemcpyAsync(hden, c->cden.p, (size_t)rows * 4, hipMemcpyDeviceToHost, st));
+        HC(c, hipStreamSynchronize(st));
+        // rows arrive in Morton order: each goes to its caller index
+        const size_t rb = (size_t)d * esz;
+        for (int64_t q = r0; q < r1; q++) {
+            const size_t g = perm[(size_t)q];
+            if (out) std::memcpy(static_cast<unsigned char*>(out) + g * rb, hrow + (size_t)(q - r0) * rb, rb);
+            if (den) den[g] = hden[q - r0];
+        }
+    }
+    c->stats = first_stats;
+    return SLAG_OK;
+}
+
+// Errors the last lift's kernels flagged (bit 4: a tile held more distinct
+// segments than its table).
+slag_status check_lift_errors(slag_ctx* c)
+{
+    CK(read_small(c, SM_LERR, 1));
+    if (c->host_small[SM_LERR] & 4)
+        FAIL(c, SLAG_E_CAPACITY, "a 16x16 tile lies in more than 256 distinct masks; the result "
+                                 "is incomplete");
+    return SLAG_OK;
+}
+
 void invalidate_graph(slag_ctx* c) { c->gen++; }
 
 void destroy_graph(slag_ctx* c) { drop_graph(c); }
@@ -1024,6 +1203,49 @@ void destroy_graph(slag_ctx* c) { drop_graph(c); }
 extern "C" {
 
 slag_status slag_lift(slag_ctx* c) { return run_lift(c, false); }
+
+slag_status slag_lift_chunked(slag_ctx* c, int64_t chunk_rows, void* out, slag_dtype dtype,
+                              float* den)
+{
+    if (!c) return SLAG_E_INVALID_ARG;
+    c->err.clear();
+    if (chunk_rows <= 0 || chunk_rows % 16) FAIL(c, SLAG_E_INVALID_ARG, "chunk_rows must be a positive multiple of 16");
+    if (dtype != SLAG_F32 && dtype != SLAG_BF16) FAIL(c, SLAG_E_INVALID_ARG, "bad output dtype");
+    CK(check_inputs(c));
+    HC(c, hipSetDevice(c->device));
+    c->have_out = false;
+    c->out_is_codec = false;
+    c->codec.have_codes = false;
+    for (auto& e : c->events) { c->free_events.push_back(e.a); c->free_events.push_back(e.b); }
+    c->events.clear();
+    std::memset(&c->stats, 0, sizeof(c->stats));
+    c->last_v0 = -1;
+    if (c->n == 0) return SLAG_OK;
+    const int64_t R = std::min<int64_t>(chunk_rows, (c->n + 15) & ~(int64_t)15);
+    if (c->plan_views != c->nviews) CK(build_plan(c));
+    uint64_t* small = c->small.as<uint64_t>();
+    for (;;) {
+        launch_fill_u32(reinterpret_cast<uint32_t*>(small + SM_COUNTERS), 12, 0u, c->st);
+        launch_fill_u32(reinterpret_cast<uint32_t*>(small + SM_LERR), 2, 0u, c->st);
+        c->replan_views = 0;
+        const slag_status s = chunked_lift(c, R, out, dtype, den);
+        if (s == SLAG_OK) break;
+        if (s != SLAG_E_CAPACITY || c->replan_views <= 0) return s;
+        c->auto_maxv = c->replan_views;
+        std::memset(&c->stats, 0, sizeof(c->stats));
+        c->last_v0 = -1;
+        CK(build_plan(c));
+    }
+    c->stats.n_views = c->nviews;
+    c->stats.n_batches = (int64_t)c->plan.size();
+    CK(check_lift_errors(c));
+    CK(read_small(c, SM_COUNTERS + 3, 1));
+    if (c->host_small[SM_COUNTERS + 3])
+        FAIL(c, SLAG_E_CAPACITY, std::to_string(c->host_small[SM_COUNTERS + 3]) +
+                                     " part-list entries did not fit their capacity; the result "
+                                     "is incomplete");
+    return SLAG_OK;
+}
 
 slag_status slag_get_embeddings(slag_ctx* c, void* out, slag_dtype dtype, float* den,
                                 slag_mem where)
@@ -1050,6 +1272,7 @@ slag_status slag_get_embeddings(slag_ctx* c, void* out, slag_dtype dtype, float*
         }
     }
     if (den && n) HC(c, hipMemcpyAsync(den, c->den.p, n * 4, k, c->st));
+    CK(check_lift_errors(c));
     // part-list capacity errors of the last lift (none by construction)
     CK(read_small(c, SM_COUNTERS + 3, 1));
     if (c->host_small[SM_COUNTERS + 3])

@@ -95,6 +95,47 @@ slag_status decode(slag_ctx* c, int rows, const float* code, float* a3, float* h
     return SLAG_OK;
 }
 
+// The pool's entries grouped by column: a stable radix sort of (column,
+// entry) pairs (entries stay in row order within a column), then each
+// column's range and each grouped entry's row.
+static slag_status build_csc(slag_ctx* c)
+{
+    CodecState& S = c->codec;
+    if (S.csc_valid) return SLAG_OK;
+    const uint64_t nnz = (uint64_t)S.pool_nnz, NS = (uint64_t)std::max<int64_t>(S.pool_seg, 1);
+    const size_t m = (size_t)std::max<uint64_t>(nnz, 1) * 4;
+    CK(ensure(c, S.csc_key, m));
+    CK(ensure(c, S.csc_j, m));
+    CK(ensure(c, S.csc_key_alt, m));
+    CK(ensure(c, S.csc_j_alt, m));
+    CK(ensure(c, S.csc_row, m));
+    CK(ensure(c, S.row_of, m));
+    CK(ensure(c, S.cbeg, NS * 4));
+    CK(ensure(c, S.cend, NS * 4));
+    CK(ensure(c, S.csc_hist, radix_hist_bytes(std::max<uint64_t>(nnz, 1))));
+    CK(ensure(c, S.csc_ws, scan_workspace_bytes(radix_hist_bytes(std::max<uint64_t>(nnz, 1)) / 4 + 1)));
+    hipStream_t st = c->st;
+    launch_fill_u32(S.cbeg.as<uint32_t>(), NS, 0u, st);
+    launch_fill_u32(S.cend.as<uint32_t>(), NS, 0u, st);
+    if (nnz) {
+        launch_row_of((uint32_t)S.pool_rows, S.prow.as<uint32_t>(), S.pcol.as<uint32_t>(),
+                      S.row_of.as<uint32_t>(), S.csc_key.as<uint32_t>(), S.csc_j.as<uint32_t>(), st);
+        const bool alt = radix_sort_u32(S.csc_key.as<uint32_t>(), S.csc_j.as<uint32_t>(),
+                                        S.csc_key_alt.as<uint32_t>(), S.csc_j_alt.as<uint32_t>(), nnz,
+                                        std::max(1, bit_length(NS - 1)), S.csc_hist.as<uint32_t>(),
+                                        S.csc_ws.p, nullptr, st);
+        if (alt) {
+            std::swap(S.csc_key, S.csc_key_alt);
+            std::swap(S.csc_j, S.csc_j_alt);
+        }
+        launch_csc_ranges((uint32_t)nnz, S.csc_key.as<uint32_t>(), S.csc_j.as<uint32_t>(),
+                          S.row_of.as<uint32_t>(), S.cbeg.as<uint32_t>(), S.cend.as<uint32_t>(),
+                          S.csc_row.as<uint32_t>(), st);
+    }
+    S.csc_valid = true;
+    return SLAG_OK;
+}
+
 // Loss over pool rows [row0, row0 + R) into *loss_dev; with grad, the full
 // gradient into codec.grad.
 slag_status forward_backward(slag_ctx* c, int64_t row0, int R, bool grad, float* loss_dev)
@@ -142,9 +183,10 @@ slag_status forward_backward(slag_ctx* c, int64_t row0, int R, bool grad, float*
     CK(gemm(c, h, k, R, da3, false, 1, h, S.code.as<float>(), k, 1, G + o.W3, k, none));
     CK(colsum(c, R, h, da3, G + o.b3));
     CK(gemm(c, R, k, h, da3, false, h, 1, P + o.W3, k, 1, S.dcode.as<float>(), k, none));
-    // mixing
-    launch_fill_u32(S.dC.as<uint32_t>(), (uint64_t)NS * k, 0u, st);
-    launch_mix_bwd(R, k, rp, S.pcol.as<uint32_t>(), S.pw.as<float>(), S.dcode.as<float>(),
+    // mixing (transposed through the column grouping: no atomics)
+    CK(build_csc(c));
+    launch_mix_bwd(NS, k, rp, R, row0, S.cbeg.as<uint32_t>(), S.cend.as<uint32_t>(), S.csc_j.as<uint32_t>(),
+                   S.csc_row.as<uint32_t>(), S.pw.as<float>(), S.dcode.as<float>(),
                    S.dC.as<float>(), st);
     // encoder
     CK(gemm(c, k, h, NS, S.dC.p, false, 1, k, S.h1.as<float>(), h, 1, G + o.W2, h, none));
@@ -205,8 +247,11 @@ void codec_release(slag_ctx* c)
     DevBuf* bufs[] = {&S.params, &S.grad, &S.adam_m, &S.adam_v, &S.pF, &S.prow, &S.pcol, &S.pw,
                       &S.ptgt, &S.a1, &S.h1, &S.C, &S.dC, &S.code, &S.dcode, &S.a3, &S.h2,
                       &S.y, &S.dy, &S.gpart, &S.cpart, &S.lpart, &S.loss, &S.rflag, &S.ridx,
-                      &S.rlen, &S.roff, &S.rgid, &S.codes, &S.hid};
+                      &S.rlen, &S.roff, &S.rgid, &S.codes, &S.hid, &S.csc_key, &S.csc_j,
+                      &S.csc_key_alt, &S.csc_j_alt, &S.csc_row, &S.row_of, &S.cbeg, &S.cend,
+                      &S.csc_hist, &S.csc_ws};
     for (DevBuf* b : bufs) release(*b);
+    S.csc_valid = false;
 }
 
 }  // namespace slag_host
@@ -239,6 +284,7 @@ slag_status slag_codec_init(slag_ctx* c, int32_t d, int32_t hidden, int32_t k,
     launch_fill_u32(S.adam_v.as<uint32_t>(), (uint64_t)o.total, 0u, c->st);
     if (S.d != d) {                    // the pool's rows have the old dimension
         S.pool_seg = S.pool_rows = S.pool_nnz = 0;
+        S.csc_valid = false;
     }
     S.d = d;
     S.h = hidden;
@@ -268,6 +314,7 @@ slag_status slag_codec_clear_pool(slag_ctx* c)
     if (!c) return SLAG_E_INVALID_ARG;
     c->err.clear();
     c->codec.pool_seg = c->codec.pool_rows = c->codec.pool_nnz = 0;
+    c->codec.csc_valid = false;
     return SLAG_OK;
 }
 
@@ -304,6 +351,7 @@ slag_status slag_codec_set_pool(slag_ctx* c, int64_t n_seg, const float* feats, 
     S.pool_seg = n_seg;
     S.pool_rows = n_rows;
     S.pool_nnz = (int64_t)nnz;
+    S.csc_valid = false;
     return SLAG_OK;
 }
 
@@ -375,6 +423,7 @@ slag_status slag_codec_add_lift_rows(slag_ctx* c, int64_t max_rows, uint64_t see
     HC(c, hipStreamSynchronize(st));
     S.pool_rows += rows;
     S.pool_nnz += (int64_t)nnz_new;
+    S.csc_valid = false;
     S.pool_seg += (int64_t)seg_new;
     if (added) *added = rows;
     return SLAG_OK;

@@ -68,9 +68,19 @@ struct CodecState {
     DevBuf a1, h1, C, dC, code, dcode, a3, h2, y, dy, gpart, cpart, lpart, loss;
     // training-row extraction
     DevBuf rflag, ridx, rlen, roff, rgid;
+    // the pool's entries grouped by column (gradient of the mixing without
+    // atomics), rebuilt when the pool changes
+    DevBuf csc_key, csc_j, csc_key_alt, csc_j_alt, csc_row, row_of, cbeg, cend, csc_hist, csc_ws;
+    bool csc_valid = false;
     // codec lift
     DevBuf codes, hid;
     bool have_codes = false;
+};
+
+// Rasterizer constants of a context (slag_options, defaults filled in).
+struct RasterConsts {
+    float amax, amin, tmin, rho2, l2amin, dil, near_z, guard;
+    double dil_d, guard_d;
 };
 
 // Work arrays of the cosine-similarity search (library-allocated; kept
@@ -86,19 +96,24 @@ struct slag_ctx {
     hipStream_t st = nullptr;
     bool own_stream = false;
     slag_options opt{};
+    slag_host::RasterConsts rc{};
     std::string err;
 
     int64_t n = -1;
     slag_host::DevBuf means, scales, quats, opac, cov3;
     slag_host::DevBuf covd, lo2;    // FP64 world covariance [6][N], log2 opacity [N]
     slag_host::DevBuf perm, rank;   // Morton order of the Gaussians (rank -> input index, inverse)
+    slag_host::DevBuf bgeo;         // per Gaussian block: bounding box, largest covariance trace
+    slag_host::DevBuf vlist, vcnt;  // per Gaussian block: views with visible pairs (this launch)
 
     int nviews = -1;
     std::vector<slag_camera> cams;
     std::vector<uint64_t> pix_off;
     std::vector<int32_t> nseg;
     std::vector<char> seg_set;
-    slag_host::DevBuf ids;
+    slag_host::DevBuf ids;            // [pixels][lpp] segment ids, -1 = none
+    slag_host::DevBuf idstage;        // host ids staged for widening to lpp labels
+    int lpp = 1;                      // labels per pixel (slag_options.labels_per_pixel)
 
     int d = 0;
     slag_dtype fdt = SLAG_F32;
@@ -124,6 +139,9 @@ struct slag_ctx {
     slag_host::DevBuf tflag, tpos, tv, tv_alt, tg, thead, tk, tk_alt;   // depth ties
     slag_host::DevBuf pixdbg;         // per-pixel T_final, weight sum, blend count (debug)
     slag_host::DevBuf outbf;          // BF16 copy of the output for host fetches
+    slag_host::DevBuf cnum, cden, cbf;  // one chunk of a streamed lift's output (Morton rows)
+    void* chost = nullptr;            // pinned staging of one chunk
+    size_t chost_cap = 0;
     uint64_t* host_small = nullptr;   // pinned read-back area
 
     slag_host::CodecState codec;
@@ -158,7 +176,7 @@ namespace slag_host {
 
 // small device area layout (uint64 words)
 enum { SM_TOT = 0, SM_ZRANGE = 2, SM_TOTALS = 4, SM_COUNTERS = 8, SM_NNZ = 12, SM_ERR = 14,
-       SM_TIES = 16, SM_WORDS = 18 };
+       SM_TIES = 16, SM_LERR = 18, SM_WORDS = 20 };
 
 #define FAIL(ctx, code, msg)                 \
     do {                                     \
@@ -196,6 +214,8 @@ int bit_length(uint64_t x);
 
 // The lift (plain or codec) on the context's inputs.
 slag_status run_lift(slag_ctx* c, bool codec);
+// SLAG_E_CAPACITY if the last lift's kernels flagged an error.
+slag_status check_lift_errors(slag_ctx* c);
 // Codec pieces used by the lift: codes of the context's feature table into
 // codec.C, and decoding of codec.codes into the context's output.
 slag_status codec_encode_table(slag_ctx* c);

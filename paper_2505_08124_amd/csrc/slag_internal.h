@@ -9,6 +9,7 @@ constexpr int TILE = 16;                 // tile edge in pixels (16 x 16 = 4 wav
 constexpr int TILE_PIX = TILE * TILE;
 constexpr int NS_CAP = 4;                // tile segments accumulated per compositing pass
 constexpr int BATCH = 64;                // tile-list entries staged in LDS per step
+constexpr int MAX_LABELS = 4;            // masks one pixel may lie in (overlapping masks)
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 
 // One view of the current launch, with everything its kernels need.
@@ -24,6 +25,11 @@ struct ViewDev {
     uint64_t pix_off;        // first pixel of this view in the id array
     uint32_t seg_off;        // first feature row of this view
     uint32_t nseg;           // segments of this view
+    // rasterizer constants of the context (FP32 decision values; the FP64
+    // values of the compositing records)
+    float near_z, dil, rho2;         // near plane, dilation (px^2), pixel-box q bound
+    float amin, amax, tmin, l2amin;  // alpha bounds, transmittance stop, log2(alpha_min)
+    double guard_d, dil_d;           // Jacobian clamp (half-FOV tangents), dilation
 };
 
 // Pair record (one visible (view, Gaussian) pair), two float4, with the
@@ -42,10 +48,25 @@ constexpr float NLOG2E = -1.44269504088896340736f;        // -log2(e)
 void launch_prep_gauss(int64_t n, const float* means, const float* scales, const float* quats,
                        const float* opac, float* cov3, double* covd, float* lo2, uint32_t* err,
                        hipStream_t st);
-void launch_validate_ids(int64_t npix, const int32_t* ids, int32_t nseg, uint32_t* err,
+// Segment ids of npix pixels, lpp labels each: every id in [-1, nseg) and a
+// pixel's non-negative labels distinct, else err |= 2.
+void launch_validate_ids(int64_t npix, const int32_t* ids, int lpp, int32_t nseg, uint32_t* err,
                          hipStream_t st);
+// dst[p][l] = l < lin ? src[p][l] : -1 for l < lout (label layers widened).
+void launch_expand_labels(int64_t npix, const int32_t* src, int lin, int32_t* dst, int lout,
+                          hipStream_t st);
+// Gaussian blocks of the projection grid: GBLOCK consecutive (Morton-order)
+// Gaussians.  Per block, the bounding box of the means and the largest
+// covariance trace (geo [nblk][8]), from which the counting pass rules out
+// whole blocks outside a view.
+constexpr int GBLOCK = 2048;
+void launch_block_geo(int64_t n, const float* means, const float* cov3, float* geo, hipStream_t st);
+// Pass 1 over a (view, Gaussian block) grid: tile count of each pair (0 = not
+// visible), visible pairs per block (blk_vis), depth range per block.  Blocks
+// ruled out by their geometry get blk_vis = 0 and leave tcnt unwritten.
 void launch_count(int nb, int64_t n, const ViewDev* views, const float* means, const float* cov3,
-                  uint32_t* tcnt, uint32_t* blk_vis, uint32_t* zrange, hipStream_t st);
+                  const float* geo, uint32_t* tcnt, uint32_t* blk_vis, uint32_t* zrange,
+                  hipStream_t st);
 int count_blocks_per_view(int64_t n);
 // Pass 2 over the same (view, Gaussian block) grid: visible pairs compacted
 // in (view, Morton rank) order with their records, depth keys (pair index in
@@ -53,6 +74,8 @@ int count_blocks_per_view(int64_t n);
 // psz, packed tile rectangles prect (entry key base for lbits), the caller's
 // Gaussian index pgauss[pair] = perm[g], the view pview, and the (view, rank)
 // -> pair map pair_of_m (NONE where not visible); pz only when non-null.
+// blk_off = exclusive scan of blk_vis over nb * nblk + 1 entries (a block
+// with no visible pair reads no tile count).
 void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* means,
                        const float* cov3, const double* covd, const float* lo2,
                        uint32_t* tcnt_pairof,
@@ -130,8 +153,12 @@ void launch_bucket_keys(uint32_t nb, const uint32_t* bucket_view, const uint8_t*
 void launch_bucket_ranges(uint64_t ni, const uint32_t* ikey, const ViewDev* views, int lbits,
                           uint32_t* bstart, uint32_t* bend, hipStream_t st);
 
+// Distinct segment ids of each tile over the lpp label layers of its pixels
+// (ids [pixels][lpp], -1 = none); more than TILE_PIX in one tile sets bit 4
+// of *err.
 void launch_tile_segs(uint32_t nbuckets, const uint32_t* bucket_view, const ViewDev* views,
-                      const int32_t* ids, uint32_t* ns_tile, uint16_t* segl, hipStream_t st);
+                      const int32_t* ids, int lpp, uint32_t* ns_tile, uint16_t* segl,
+                      unsigned long long* err, hipStream_t st);
 void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t* sat,
                 hipStream_t st);
 // Compositing variants (bitwise-equal results, different register budgets).
@@ -152,7 +179,7 @@ void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t
                       uint32_t obase, const uint32_t* bucket_view, const ViewDev* views,
                       const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
                       uint2* pinfo, const float4* rec, const uint32_t* ns_tile,
-                      const uint16_t* segl, const int32_t* ids, uint2* part,
+                      const uint16_t* segl, const int32_t* ids, int lpp, uint2* part,
                       unsigned long long* counters, float* pix_t, float* pix_w, uint32_t* pix_n,
                       hipStream_t st);
 // out[i] = bfloat16(in[i]) (round to nearest even), as bit patterns
@@ -164,10 +191,19 @@ void launch_merge(uint64_t npairs, const uint16_t* pview, const ViewDev* views, 
 bool contract_supported(int d);
 // code tables of the codec: d in {16, 32, 48} besides the feature sizes
 bool contract_supported_codes(int d);
+// Per Gaussian block, the views of the launch in which it has visible pairs
+// (ascending; vlist [nblk][nb], vcnt [nblk]) from the scanned visible counts;
+// the contraction walks only those views.
+void launch_view_lists(int nb, int nblk, const uint32_t* blk_off, uint16_t* vlist, uint32_t* vcnt,
+                       hipStream_t st);
+// Contraction of the Gaussians of Morton ranks [q_begin, q_end) (q_begin a
+// multiple of 16): output row of rank q is perm[q] (the caller's order), or
+// q - q_begin when `local` (one chunk of a streamed lift).
 void launch_contract(int64_t n, int nb, int d, bool bf16, const uint32_t* perm,
-                     const uint32_t* pair_of_m, const ViewDev* views, const uint2* pinfo,
-                     const uint2* part, const void* feats, float* num, float* den, bool first,
-                     bool last, hipStream_t st);
+                     const uint32_t* pair_of_m, const ViewDev* views, const uint16_t* vlist,
+                     const uint32_t* vcnt, const uint2* pinfo, const uint2* part, const void* feats,
+                     float* num, float* den, bool first, bool last, int64_t q_begin, int64_t q_end,
+                     bool local, hipStream_t st);
 
 // ---- codec ----
 enum { GEMM_NONE = 0, GEMM_GELU = 1, GEMM_GELU_BWD = 2 };
@@ -197,8 +233,21 @@ size_t colsum_part_floats(int R, int N);
 void launch_colsum(int R, int N, const float* X, float* out, float* part, hipStream_t st);
 void launch_mix(int R, int k, const uint32_t* row_ptr, const uint32_t* col, const float* w,
                 const float* C, float* code, hipStream_t st);
-void launch_mix_bwd(int R, int k, const uint32_t* row_ptr, const uint32_t* col, const float* w,
-                    const float* dcode, float* dC, hipStream_t st);
+// Gradient of the mixing through the pool's column grouping (no atomics):
+// the batch is rows row0 .. row0 + R - 1 (row pointers rp from row0, so its
+// entries are [rp[0], rp[R])); cbeg/cend
+// the column ranges of csc_j (entry indices, ascending per column), csc_row
+// the row of each grouped entry.  launch_row_of writes the row of every
+// entry plus (column, entry) sort pairs; launch_csc_ranges the column ranges
+// and rows from the column-sorted pairs (cbeg/cend zero-filled first).
+void launch_mix_bwd(int NS, int k, const uint32_t* rp, int R, int64_t row0, const uint32_t* cbeg,
+                    const uint32_t* cend, const uint32_t* csc_j, const uint32_t* csc_row,
+                    const float* w, const float* dcode, float* dC, hipStream_t st);
+void launch_row_of(uint32_t R, const uint32_t* row_ptr, const uint32_t* col, uint32_t* row_of,
+                   uint32_t* key, uint32_t* ent, hipStream_t st);
+void launch_csc_ranges(uint32_t nnz, const uint32_t* key, const uint32_t* csc_j,
+                       const uint32_t* row_of, uint32_t* cbeg, uint32_t* cend, uint32_t* csc_row,
+                       hipStream_t st);
 void launch_cos_loss(int R, int d, const float* y, const float* tg, float* dy, float* loss_part,
                      float* loss, hipStream_t st);
 void launch_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,

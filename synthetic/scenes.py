@@ -22,6 +22,8 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from typing import Dict, List, Optional
 
 import numpy as np
@@ -205,6 +207,7 @@ def _gaussians(rng, spec, n):
         lo, hi = spec["lo"], spec["hi"]
         means = rng.uniform(lo, hi, size=(n, 3))
         centres = None
+        sig = None
     elif kind == "clusters":
         k = spec["k"]
         lo = np.asarray(spec["centre_lo"], np.float64)
@@ -226,22 +229,113 @@ def _gaussians(rng, spec, n):
     op_mu, op_sd = spec["opacity_logit"]
     opacity = 1.0 / (1.0 + np.exp(-rng.normal(op_mu, op_sd, size=n)))
     return (means.astype(np.float32), scales.astype(np.float32), quats.astype(np.float32),
-            opacity.astype(np.float32), centres, labels)
+            opacity.astype(np.float32), centres, labels, sig)
 
 
 # ----------------------------------------------------------------------------
 # segments
 
-def _voronoi_ids(rng, w, h, n_seg, bg_frac):
+def _voronoi_seeds(rng, w, h, n_seg, bg_frac):
+    """Seed points of a view's Voronoi cells (the extra background cells last)."""
     n_bg = int(round(n_seg * bg_frac / max(1e-9, 1.0 - bg_frac))) if bg_frac > 0 else 0
-    seeds = np.column_stack([rng.uniform(0, w, n_seg + n_bg), rng.uniform(0, h, n_seg + n_bg)])
+    return np.column_stack([rng.uniform(0, w, n_seg + n_bg), rng.uniform(0, h, n_seg + n_bg)])
+
+
+def _voronoi_map(seeds, w, h, n_seg, workers=-1):
+    """Cell of every pixel centre (ties to the lower seed); background cells -1."""
     tree = cKDTree(seeds)
     uu, vv = np.meshgrid(np.arange(w) + 0.5, np.arange(h) + 0.5)
-    _, idx = tree.query(np.column_stack([uu.ravel(), vv.ravel()]), workers=-1)
+    _, idx = tree.query(np.column_stack([uu.ravel(), vv.ravel()]), workers=workers)
     idx = idx.astype(np.int32).reshape(h, w)
-    if n_bg:
+    if seeds.shape[0] > n_seg:
         idx[idx >= n_seg] = -1
-    return idx, seeds[:n_seg]
+    return idx
+
+
+def _voronoi_ids(rng, w, h, n_seg, bg_frac):
+    seeds = _voronoi_seeds(rng, w, h, n_seg, bg_frac)
+    return _voronoi_map(seeds, w, h, n_seg), seeds[:n_seg]
+
+
+def _pixel_rays(cam):
+    """Camera centre and unit world-space directions of every pixel centre's
+    ray ([H, W, 3]), from the pinhole model (OpenCV axes)."""
+    W, H = int(cam["width"]), int(cam["height"])
+    R = cam["R"].astype(np.float64).reshape(3, 3)
+    t = cam["t"].astype(np.float64)
+    C = -R.T @ t
+    u, v = np.meshgrid(np.arange(W) + 0.5, np.arange(H) + 0.5)
+    dc = np.stack([(u - float(cam["cx"])) / float(cam["fx"]), (v - float(cam["cy"])) / float(cam["fy"]),
+                   np.ones_like(u)], axis=-1)
+    d = dc @ R                      # R^T d_cam, row-wise
+    d /= np.linalg.norm(d, axis=-1, keepdims=True)
+    return C, d
+
+
+def _object_map_box(cam, centres, lo, hi):
+    """Object under each pixel of a solid box of Gaussians partitioned into
+    the Voronoi cells of `centres`: the cell of the point where the pixel's
+    ray enters the box; -1 where the ray misses it.  No compositing."""
+    C, d = _pixel_rays(cam)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t1 = (lo - C) / d
+        t2 = (hi - C) / d
+    tn = np.nanmax(np.minimum(t1, t2), axis=-1)
+    tf = np.nanmin(np.maximum(t1, t2), axis=-1)
+    hit = (tn <= tf) & (tf > 0)
+    tn = np.maximum(tn, 0.0)
+    obj = np.full(hit.shape, -1, np.int64)
+    if hit.any():
+        pts = C + tn[hit][:, None] * d[hit]
+        _, idx = cKDTree(centres).query(pts, workers=-1)
+        obj[hit] = idx
+    return obj
+
+
+def _object_map_spheres(cam, centres, radii):
+    """Object under each pixel of a scene of Gaussian clusters, each taken as
+    a sphere around its centre: the first sphere the pixel's ray enters; -1
+    where it enters none.  Each sphere is tested only inside the pixel box of
+    its projection.  No compositing."""
+    W, H = int(cam["width"]), int(cam["height"])
+    C, d = _pixel_rays(cam)
+    best = np.full((H, W), np.inf)
+    obj = np.full((H, W), -1, np.int64)
+    u, v, z = _project_points(cam, centres)
+    f = max(float(cam["fx"]), float(cam["fy"]))
+    for o in range(centres.shape[0]):
+        r = radii[o]
+        if z[o] + r <= 1e-3:
+            continue                                    # behind the camera
+        if z[o] - r > 1e-3:
+            rp = f * r / (z[o] - r) + 2.0
+            x0, x1 = int(max(0, np.floor(u[o] - rp))), int(min(W, np.ceil(u[o] + rp)))
+            y0, y1 = int(max(0, np.floor(v[o] - rp))), int(min(H, np.ceil(v[o] + rp)))
+            if x0 >= x1 or y0 >= y1:
+                continue
+        else:
+            x0, x1, y0, y1 = 0, W, 0, H
+        dd = d[y0:y1, x0:x1]
+        oc = C - centres[o]
+        b = dd @ oc
+        disc = b * b - (oc @ oc - r * r)
+        tt = -b - np.sqrt(np.maximum(disc, 0.0))
+        hit = (disc >= 0) & (tt > 0) & (tt < best[y0:y1, x0:x1])
+        best[y0:y1, x0:x1][hit] = tt[hit]
+        obj[y0:y1, x0:x1][hit] = o
+    return obj
+
+
+def _segments_on_objects(cells, obj):
+    """Segments = the (2D cell, object) parts of a view: each Voronoi cell
+    split along the object boundaries; pixels without an object are
+    background (-1).  Returns the id map and each segment's object."""
+    key = cells.astype(np.int64) * (1 << 20) + obj
+    valid = obj >= 0
+    uk, inv = np.unique(key[valid], return_inverse=True)
+    ids = np.full(cells.shape, -1, np.int32)
+    ids[valid] = inv.astype(np.int32)
+    return ids, (uk % (1 << 20)).astype(np.int64)
 
 
 # ----------------------------------------------------------------------------
@@ -260,6 +354,18 @@ def _project_points(cam, pts):
         u = cam["fx"] * pc[:, 0] / z + cam["cx"]
         v = cam["fy"] * pc[:, 1] / z + cam["cy"]
     return u, v, z
+
+
+def _features_of_objects(rng, spec, D, seg_obj, n_obj):
+    """Object vocabulary: every object takes one of the global words (seed
+    word_seed); a segment's feature is its object's word plus noise."""
+    words = _unit_rows(np.random.default_rng(spec.get("word_seed", 7)).standard_normal(
+        (spec.get("n_words", 64), D)))
+    obj_word = rng.integers(0, words.shape[0], size=n_obj) if n_obj > words.shape[0] else \
+        rng.permutation(words.shape[0])[:n_obj]
+    lab = np.concatenate(seg_obj) if seg_obj else np.zeros(0, np.int64)
+    noise = rng.standard_normal((lab.size, D)) / math.sqrt(D)
+    return _unit_rows(words[obj_word[lab]] + spec.get("noise", 0.25) * noise), lab
 
 
 def _features(rng, spec, D, nseg, seeds_per_view, cams, obj_centres):
@@ -317,7 +423,7 @@ CONFIGS: Dict[str, Dict] = {
         gauss=dict(kind="uniform", lo=-1.0, hi=1.0, log_scale=(-5.0, 0.6), opacity_logit=(0.5, 1.5)),
         views=dict(kind="fibonacci", n=300, radius=3.0,
                    res_list=[(320, 240), (640, 480), (1280, 960)], focal_ratio=0.8),
-        segments=dict(lo=50, hi=150, bg_frac=0.0),
+        segments=dict(lo=50, hi=150, bg_frac=0.0, kind="objects"),
         features=dict(D=512, dtype="bf16", model="vocab", n_objects=48)),
     # 4M Gaussians from 200 clusters over 10x10x3, 1000 nadir views 1024x768
     "stress_4m": dict(
@@ -326,7 +432,7 @@ CONFIGS: Dict[str, Dict] = {
                    sigma=(0.1, 0.5), aniso=False, log_scale=(-5.0, 0.7), opacity_logit=(0.5, 1.5)),
         views=dict(kind="lawnmower", rows=25, cols=40, extent=10.0, height=2.0,
                    res=(1024, 768), focal_ratio=0.8),
-        segments=dict(lo=100, hi=200, bg_frac=0.0),
+        segments=dict(lo=100, hi=200, bg_frac=0.0, kind="objects"),
         features=dict(D=768, dtype="bf16", model="vocab", objects="clusters")),
 }
 CONFIGS["codec_train"] = dict(CONFIGS["uneven_1m"], seed=1041)
@@ -352,7 +458,7 @@ def make_scene(name: str, seed: Optional[int] = None, **over) -> Scene:
     ss = np.random.SeedSequence(seed)
     r_gauss, r_view, r_seg, r_feat = [np.random.default_rng(s) for s in ss.spawn(4)]
     n = int(spec["n"])
-    means, scales, quats, opacity, centres, labels = _gaussians(r_gauss, spec["gauss"], n)
+    means, scales, quats, opacity, centres, labels, csig = _gaussians(r_gauss, spec["gauss"], n)
 
     vs = spec["views"]
     kind = vs["kind"]
@@ -376,25 +482,57 @@ def make_scene(name: str, seed: Optional[int] = None, **over) -> Scene:
     cams = np.array(cams, dtype=camera_dtype)
 
     sg = spec["segments"]
-    ids, seeds_pv = [], []
-    nseg = np.zeros(len(cams), dtype=np.int32)
-    for v, c in enumerate(cams):
-        k = int(r_seg.integers(sg["lo"], sg["hi"] + 1))
-        m, sd = _voronoi_ids(r_seg, int(c["width"]), int(c["height"]), k, sg.get("bg_frac", 0.0))
-        ids.append(m)
-        seeds_pv.append(sd)
-        nseg[v] = k
-
     fs = spec["features"]
     D = int(fs["D"])
+    obj = None
     if fs["model"] == "vocab":
         if fs.get("objects") == "clusters" and centres is not None:
             obj = centres
         else:
             obj = np.random.default_rng(seed + 7919).uniform(-1, 1, size=(fs.get("n_objects", 48), 3))
+    # objects of the scene geometry (vocabulary model with per-pixel object
+    # segments): cells of a solid box, or spheres of 2.2 sigma around the
+    # cluster centres (about where a ray through a cluster becomes opaque)
+    on_objects = fs["model"] == "vocab" and sg.get("kind", "voronoi") == "objects"
+    # all random draws first, in view order; the per-pixel maps are then
+    # built view by view on a thread pool (same bytes whatever the threads)
+    draws = []
+    for v, c in enumerate(cams):
+        k = int(r_seg.integers(sg["lo"], sg["hi"] + 1))
+        draws.append((k, _voronoi_seeds(r_seg, int(c["width"]), int(c["height"]), k,
+                                        sg.get("bg_frac", 0.0))))
+
+    def view_maps(v):
+        c = cams[v]
+        k, seeds = draws[v]
+        m = _voronoi_map(seeds, int(c["width"]), int(c["height"]), k, workers=1)
+        so = None
+        if on_objects:
+            if fs.get("objects") == "clusters" and centres is not None:
+                om = _object_map_spheres(c, obj, 2.2 * csig[:, 0])
+            else:
+                om = _object_map_box(c, obj, spec["gauss"]["lo"], spec["gauss"]["hi"])
+            m, so = _segments_on_objects(m, om)
+        return m, so
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        maps = list(ex.map(view_maps, range(len(cams))))
+    ids, seeds_pv, seg_obj = [], [], []
+    nseg = np.zeros(len(cams), dtype=np.int32)
+    for v in range(len(cams)):
+        m, so = maps[v]
+        ids.append(m)
+        seeds_pv.append(draws[v][1][: draws[v][0]])
+        if on_objects:
+            seg_obj.append(so)
+            nseg[v] = so.size
+        else:
+            nseg[v] = draws[v][0]
+
+    if on_objects:
+        F64, seg_labels = _features_of_objects(r_feat, fs, D, seg_obj, obj.shape[0])
     else:
-        obj = None
-    F64, seg_labels = _features(r_feat, fs, D, nseg, seeds_pv, cams, obj)
+        F64, seg_labels = _features(r_feat, fs, D, nseg, seeds_pv, cams, obj)
     F32 = F64.astype(np.float32)
     feats = f32_to_bf16_bits(F32) if fs["dtype"] == "bf16" else F32
     meta = dict(spec=spec, seg_labels=seg_labels, gauss_labels=labels)

@@ -170,3 +170,26 @@ def test_training_lowers_loss_and_beats_baselines():
     _say(f"mean cosine to the plain lift: trained {c_tr.mean():.4f} (p1 {np.percentile(c_tr, 1):.4f}, "
          f"min {c_tr.min():.4f}), PCA-{k} {c_pca.mean():.4f}, untrained {c_un.mean():.4f}")
     assert c_tr.mean() > c_pca.mean() > c_un.mean()
+
+
+def test_training_is_deterministic():
+    """Training twice from the same parameters on the same pool gives the same
+    parameters bit for bit (the mixing's gradient is summed per column in
+    entry order, and the weight gradients' K-split slices in a fixed order)."""
+    import paper_2505_08124_amd as slag
+    from synthetic.codec_inputs import random_pool
+    d, h, k = 128, 64, 16
+    F, rp, col, w, T = random_pool(5, 3000, 20000, d)
+    p0 = init_params(d, h, k, seed=7)
+    out = []
+    for _ in range(2):
+        L = slag.Lifter(0)
+        slag.slag_codec_init(L.ctx, d, h, k, slag.SLAG_BF16, p0)
+        slag.slag_codec_set_pool(L.ctx, F, rp, col, w, T)
+        slag.slag_codec_train(L.ctx, steps=40, batch_rows=4096, lr=1e-3)
+        p = np.zeros_like(p0)
+        slag.slag_codec_get_params(L.ctx, p)
+        out.append(p)
+        L.close()
+    assert np.array_equal(out[0], out[1])
+    assert not np.array_equal(out[0], p0)

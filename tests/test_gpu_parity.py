@@ -558,3 +558,140 @@ def test_full_size_uneven_1m_sampled_views():
     assert np.array_equal(den, den2)
     np.testing.assert_allclose(E2, E, rtol=1e-5, atol=1e-6)
     L2.close()
+
+
+CUSTOM = dict(alpha_max=0.9, alpha_min=0.02, t_min=0.01, dilation=0.5, near_z=0.5, guard=1.1)
+
+
+@pytest.mark.parametrize("case", ["plain_fp32_2k", "ragged"])
+def test_custom_constants_match_oracle(case):
+    """Non-default rasterizer constants (slag_options) against the oracle run
+    with the same constants: tile lists bit-exact, W_v within the bounds,
+    embeddings within the bound; the result differs from the default lift."""
+    import paper_2505_08124_amd as slag
+    sc = make_scene("plain_fp32_2k") if case == "plain_fp32_2k" else _ragged_scene()
+    K = {k: float(np.float32(v)) for k, v in CUSTOM.items()}
+    L = slag.Lifter(0, flags=slag.SLAG_FLAG_KEEP_DEBUG, **K)
+    L.set_scene(sc)
+    L.lift()
+    E, den = L.embeddings()
+    with oracle.constants(**{k: np.float32(v) for k, v in K.items()}):
+        ref = oracle.lift(sc)
+        for v in range(sc.n_views):
+            _say(f"custom constants {case}: view {v}")
+            check_tile_lists(L, sc, v)
+            check_view_weights(L, sc, v, ref.views[v], "custom_" + case)
+    check_embeddings(E, den, ref, sc, "custom_" + case)
+    L.close()
+    L0 = _lifter(sc)
+    L0.lift()
+    E0, den0 = L0.embeddings()
+    L0.close()
+    assert not np.array_equal(den0, den)
+
+
+def test_invalid_options_are_rejected():
+    import paper_2505_08124_amd as slag
+    for bad in (dict(alpha_min=0.5, alpha_max=0.4), dict(t_min=1.5), dict(dilation=-1.0),
+                dict(deterministic=2)):
+        with pytest.raises(slag.SlagError) as ei:
+            slag.Lifter(0, **bad)
+        assert ei.value.status == slag.SLAG_E_INVALID_ARG, bad
+    with pytest.raises(slag.SlagError) as ei:
+        slag.Lifter(0, tile_size=8)
+    assert ei.value.status == slag.SLAG_E_NOT_SUPPORTED
+    slag.Lifter(0, tile_size=16, deterministic=1).close()
+
+
+@pytest.mark.parametrize("max_views,chunk", [(0, 512), (0, 208), (2, 1024), (0, 4096)])
+def test_chunked_lift_equals_lift(scene_2k, lift_2k, max_views, chunk):
+    """The lift streamed to host memory in chunks of Gaussians (the paper's
+    iterated aggregation for outputs that do not fit on the GPU) equals the
+    one-piece lift bit for bit, in one or several view launches, FP32 and
+    BF16 output."""
+    import paper_2505_08124_amd as slag
+    from synthetic import f32_to_bf16_bits
+    L0 = _lifter(scene_2k, max_views=max_views)
+    L0.lift()
+    E0, den0 = L0.embeddings()
+    L0.close()
+    L = slag.Lifter(0, None, max_views)
+    L.set_scene(scene_2k)
+    E = np.full(E0.shape, np.nan, np.float32)
+    den = np.full(den0.shape, np.nan, np.float32)
+    slag.slag_lift_chunked(L.ctx, chunk, E, den)
+    assert np.array_equal(E, E0) and np.array_equal(den, den0)
+    Eb = np.zeros(E0.shape, np.uint16)
+    slag.slag_lift_chunked(L.ctx, chunk, Eb)
+    assert np.array_equal(Eb, f32_to_bf16_bits(E0))
+    if max_views:
+        assert L.stats()["n_batches"] == 2
+    with pytest.raises(slag.SlagError):
+        slag.slag_lift_chunked(L.ctx, 100, E)         # not a multiple of 16
+    L.close()
+
+
+def _overlap_scene(base, n_extra=9, frac=0.6, seed=11):
+    """base with a second mask layer: a 3x3 grid of masks over a random
+    ~60 % of each view's pixels, overlapping the first layer's segments."""
+    rng = np.random.default_rng(seed)
+    ids, nseg, rows = [], [], []
+    off = base.seg_offsets
+    F = base.feats
+    for v in range(base.n_views):
+        i0 = base.ids[v]
+        H, W = i0.shape
+        yy, xx = np.mgrid[0:H, 0:W]
+        grid = (3 * yy // H) * 3 + (3 * xx // W)
+        k0 = int(base.nseg[v])
+        l1 = np.where(rng.random((H, W)) < frac, k0 + grid, -1).astype(np.int32)
+        ids.append(np.stack([i0, l1], axis=-1))
+        nseg.append(k0 + n_extra)
+        extra = rng.standard_normal((n_extra, F.shape[1])).astype(np.float32)
+        extra /= np.linalg.norm(extra, axis=1, keepdims=True)
+        rows.append(np.concatenate([F[off[v]:off[v + 1]], extra.astype(F.dtype)]))
+    return dataclasses.replace(base, ids=ids, nseg=np.array(nseg, np.int32),
+                               feats=np.ascontiguousarray(np.concatenate(rows)))
+
+
+@pytest.mark.parametrize("case", ["plain_fp32_2k", "uneven_40k"])
+def test_overlapping_masks_match_oracle(case):
+    """Pixels in two masks give their weights to both (paper: masks M_j are
+    per-object binary masks, and the aggregation sums over every mask and its
+    pixels): tile lists, W_v and embeddings against the oracle."""
+    import paper_2505_08124_amd as slag
+    base = make_scene("plain_fp32_2k") if case == "plain_fp32_2k" else \
+        make_scene("uneven_1m", n=40000, views=dict(n=3))
+    sc = _overlap_scene(base)
+    L = slag.Lifter(0, flags=slag.SLAG_FLAG_KEEP_DEBUG, labels_per_pixel=2)
+    L.set_scene(sc)
+    L.lift()
+    E, den = L.embeddings()
+    ref = oracle.lift(sc)
+    for v in range(sc.n_views):
+        _say(f"overlapping masks {case}: view {v}")
+        check_tile_lists(L, sc, v)
+        check_view_weights(L, sc, v, ref.views[v], "overlap_" + case)
+    check_embeddings(E, den, ref, sc, "overlap_" + case)
+    L.close()
+
+
+def test_empty_second_label_layer_is_bitwise_neutral(scene_2k, lift_2k):
+    """labels_per_pixel = 2 with the second layer empty equals the one-label
+    lift bit for bit; a repeated label in one pixel is rejected."""
+    import paper_2505_08124_amd as slag
+    _, E0, den0 = lift_2k
+    ids2 = [np.stack([i, np.full_like(i, -1)], axis=-1) for i in scene_2k.ids]
+    sc = dataclasses.replace(scene_2k, ids=ids2)
+    L = slag.Lifter(0, labels_per_pixel=2)
+    L.set_scene(sc)
+    L.lift()
+    E, den = L.embeddings()
+    assert np.array_equal(E, E0) and np.array_equal(den, den0)
+    bad = np.stack([scene_2k.ids[0], scene_2k.ids[0]], axis=-1)
+    with pytest.raises(slag.SlagError):
+        slag.slag_set_segments_multi(L.ctx, 0, bad, int(scene_2k.nseg[0]))
+    with pytest.raises(slag.SlagError):
+        slag.slag_set_segments_multi(L.ctx, 0, np.stack([bad] * 2, -1).reshape(64, 64, 4),
+                                     int(scene_2k.nseg[0]))      # more layers than the option
+    L.close()

@@ -337,3 +337,128 @@ def test_sorted_keys_cover_boxes(scene_2k):
         b = mv.box[mv.vis == 1]
         exp = ((b[:, 1] // tw - b[:, 0] // tw + 1) * (b[:, 3] // th - b[:, 2] // th + 1)).sum()
         assert t.size == exp
+
+
+# --------------------------------------------------------------------------
+# rasterizer constants as options (the reading of the constants the paper
+# leaves to the rasterizer: they are the library's options, and the oracle
+# takes the same values)
+
+def test_custom_alpha_bounds_and_dilation_closed_form():
+    """With alpha_max = 0.6, alpha_min = 0.05 and 1.0 px^2 of dilation one
+    Gaussian weighs w(p) = min(0.6, o exp(-q/2)) where that reaches 0.05,
+    Sigma2 = diag(f^2 s^2 / z^2) + 1.0 I."""
+    amax, amin, dil = F32(0.6), F32(0.05), F32(1.0)
+    sc = _axis_scene([(3.0, [0.3, 0.15, 0.1], 0.8)])
+    with oracle.constants(alpha_max=amax, alpha_min=amin, dilation=dil):
+        r = oracle.lift_view(sc, 0, pixels=True)
+        mu, cov, _, _ = oracle.project64_view(sc, 0)
+    f, z = float(sc.cams[0]["fx"]), 3.0
+    s = sc.scales[0].astype(np.float64)
+    sxx, syy = f * f * s[0] ** 2 / z ** 2 + float(dil), f * f * s[1] ** 2 / z ** 2 + float(dil)
+    np.testing.assert_allclose(cov[0], [sxx, 0.0, syy], rtol=1e-12, atol=1e-15)
+    u, v = np.meshgrid(np.arange(32) + 0.5, np.arange(32) + 0.5)
+    o = float(sc.opacity[0])
+    a = np.minimum(float(amax), o * np.exp(-0.5 * ((u - 16.0) ** 2 / sxx + (v - 16.0) ** 2 / syy)))
+    exp = np.where(a >= float(amin), a, 0.0).ravel()
+    got = _dense_w(r, 0, 32 * 32)
+    np.testing.assert_allclose(got, exp, rtol=1e-12, atol=0)
+    assert (got == float(amax)).sum() > 4 and 20 < (got > 0).sum() < (exp.size - 50)
+    # the defaults are restored afterwards (alpha above 0.6 is kept again)
+    r0 = oracle.lift_view(sc, 0)
+    assert _dense_w(r0, 0, 1024).max() > float(amax)
+
+
+def test_custom_stop_is_exclusive():
+    """t_min = 0.01 and alpha = 0.95: after one blend T = 0.05; the second
+    would take T to 0.0025 < 0.01, so exactly one Gaussian blends."""
+    gs = [(2.0 + 0.1 * k, [0.05, 0.05, 0.05], 0.95) for k in range(4)]
+    sc = _axis_scene(gs, cx=16.5, cy=16.5)
+    p = 16 * 32 + 16
+    a = float(np.float32(0.95))
+    with oracle.constants(t_min=F32(0.01)):
+        r = oracle.lift_view(sc, 0, pixels=True)
+    assert _dense_w(r, 0, 1024)[p] == pytest.approx(a, rel=1e-13)
+    assert all(_dense_w(r, g, 1024)[p] == 0.0 for g in (1, 2, 3))
+    assert r.T.ravel()[p] == pytest.approx(1 - a, rel=1e-12)
+
+
+def test_custom_near_plane_and_guard():
+    """near_z = 0.5 culls a Gaussian at depth 0.3 and keeps one at 0.8; with
+    guard g a Gaussian beyond the clamp projects with the Jacobian at
+    x/z = g tan(half FOV): Sigma2_xx = (f / z)^2 (sx^2 + t^2 sz^2) + 0.3."""
+    cam = _cam(64, 48, 40.0)
+    sc = make_custom_scene([[0, 0, 0.3], [0, 0, 0.8]], [[0.01] * 3] * 2, [[1, 0, 0, 0]] * 2,
+                           [0.5, 0.5], [cam], [np.zeros((48, 64), np.int32)], _unit_feats(1, 4))
+    with oracle.constants(near_z=F32(0.5)):
+        mv = oracle.mirror_view(sc, 0)
+    assert mv.vis[0] == 0 and mv.vis[1] == 1
+    assert np.all(oracle.mirror_view(sc, 0).vis == 1)
+    z, x = 2.0, 3.0                     # x/z = 1.5, beyond 1.3 * 32/40 and 1.1 * 32/40
+    s = np.array([0.05, 0.04, 0.2], np.float32)
+    sc2 = make_custom_scene([[x, 0, z]], [s], [[1, 0, 0, 0]], [0.5], [cam],
+                            [np.zeros((48, 64), np.int32)], _unit_feats(1, 4))
+    for g in (1.1, 1.3):
+        with oracle.constants(guard=F32(g)):
+            _, cov, _, _ = oracle.project64_view(sc2, 0)
+        t = float(F32(g)) * 0.5 * 64 / 40.0
+        sd = s.astype(np.float64)
+        exp = (40.0 / z) ** 2 * (sd[0] ** 2 + t * t * sd[2] ** 2) + 0.3
+        assert cov[0, 0] == pytest.approx(exp, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# overlapping masks (a pixel may lie in several masks M_j: parameter masking
+# gives its weight to each of them, and the aggregation sums over every mask
+# and its pixels)
+
+def test_disjoint_masks_reproduce_single_labels(scene_2k, oracle_2k):
+    """A second label layer of -1 everywhere changes nothing, bit for bit."""
+    import dataclasses
+    ids2 = [np.stack([i, np.full_like(i, -1)], axis=-1) for i in scene_2k.ids]
+    sc2 = dataclasses.replace(scene_2k, ids=ids2)
+    for v in range(scene_2k.n_views):
+        r2 = oracle.lift_view(sc2, v)
+        r1 = oracle_2k.views[v]
+        assert np.array_equal(r1.g, r2.g) and np.array_equal(r1.s, r2.s)
+        assert np.array_equal(r1.w, r2.w) and np.array_equal(r1.u, r2.u)
+
+
+def test_pixel_in_two_masks_adds_weight_to_both():
+    """Per-pixel masks plus one large mask over the left half: every pixel's
+    own mask keeps its single-label weight, and the large mask receives the
+    sum of the weights of its pixels."""
+    sc = _axis_scene([(3.0, [0.3, 0.15, 0.1], 0.8)])
+    r1 = oracle.lift_view(sc, 0)
+    big = np.full((32, 32), -1, np.int32)
+    big[:, :16] = 32 * 32
+    ids2 = np.stack([sc.ids[0], big], axis=-1)
+    sc2 = make_custom_scene(sc.means, sc.scales, sc.quats, sc.opacity,
+                            [dict(fx=float(sc.cams[0]["fx"]), fy=float(sc.cams[0]["fy"]),
+                                  cx=float(sc.cams[0]["cx"]), cy=float(sc.cams[0]["cy"]),
+                                  width=32, height=32)],
+                            [ids2], _unit_feats(32 * 32 + 1, 4), nseg=[32 * 32 + 1])
+    r2 = oracle.lift_view(sc2, 0)
+    per_pixel = _dense_w(r1, 0, 32 * 32)
+    got = np.zeros(32 * 32 + 1)
+    got[r2.s[r2.g == 0]] = r2.w[r2.g == 0]
+    np.testing.assert_array_equal(got[:32 * 32], per_pixel)
+    left = (np.arange(32 * 32) % 32) < 16
+    assert got[32 * 32] == pytest.approx(per_pixel[left].sum(), rel=1e-13)
+    assert got[32 * 32] > 0
+
+
+def test_two_full_masks_average_their_features():
+    """Two masks that both cover the whole image: every Gaussian's weight goes
+    to both in equal amounts, so E = (f1 + f2) / 2 exactly."""
+    sc = _axis_scene([(3.0, [0.3, 0.15, 0.1], 0.8), (2.5, [0.1, 0.2, 0.1], 0.6)])
+    ids2 = np.stack([np.zeros((32, 32), np.int32), np.ones((32, 32), np.int32)], axis=-1)
+    f = _unit_feats(2, 8, seed=3)
+    c = sc.cams[0]
+    sc2 = make_custom_scene(sc.means, sc.scales, sc.quats, sc.opacity,
+                            [dict(fx=float(c["fx"]), fy=float(c["fy"]), cx=float(c["cx"]),
+                                  cy=float(c["cy"]), width=32, height=32)], [ids2], f, nseg=[2])
+    ref = oracle.lift(sc2)
+    want = (f[0].astype(np.float64) + f[1].astype(np.float64)) / 2
+    for g in range(2):
+        np.testing.assert_allclose(ref.E[g], want, rtol=0, atol=1e-15)
