@@ -267,32 +267,38 @@ def accuracy_and_cpu(slag, scene, views, budget_s):
     return acc, cpu
 
 
-def codec_section(args, slag, torch):
-    """The learned codec on the uneven 1M-Gaussian / 300-view workload: train
-    on the plain lifts of three seeded scenes of the same recipe (GPU
-    kernels), then time the plain and the codec lift of the workload scene
-    (graph replays) and compare the codec's embeddings with the plain ones."""
-    from synthetic import make_scene
+def codec_section(args, slag, torch, eval_scene, k, hidden, steps, train_recipe, train_over):
+    """The learned codec: train on the plain lifts of three seeded scenes of
+    the evaluation scene's recipe (GPU kernels), then time the plain and the
+    codec lift of the evaluation scene (graph replays) and compare the
+    codec's embeddings with the plain ones.  Besides the mean cosine, the
+    weight-weighted mean (each Gaussian weighted by its total weight den) and
+    the ceiling any k-dim code of this feature model faces: a segment's
+    feature is its object's word plus noise spread over all D dimensions, and
+    a code that carries words cannot carry that noise, so a Gaussian's best
+    cosine is about |P E| / |E|, P the projection onto the span of the
+    vocabulary (few segments: little averaging of the noise)."""
+    from synthetic import make_scene, vocabulary_words
     from synthetic.codec_inputs import init_params
-    d, h, k = 512, args.codec_hidden, args.codec_k
+    d = eval_scene.dim
     t0 = time.perf_counter()
     L = slag.Lifter(0, flags=slag.SLAG_FLAG_GRAPH | slag.SLAG_FLAG_PROFILE | slag.SLAG_FLAG_AUTOTUNE)
-    slag.slag_codec_init(L.ctx, d, h, k, slag.SLAG_BF16, init_params(d, h, k, seed=1040))
-    for s in (1041, 1042, 1043):
-        _log("codec: training scene", s)
-        sc = make_scene("codec_train", seed=s)
+    slag.slag_codec_init(L.ctx, d, hidden, k, slag.SLAG_BF16, init_params(d, hidden, k, seed=1040))
+    seeds = (1041, 1042, 1043) if train_recipe != "stress_4m" else (1051, 1052, 1053)
+    for sd in seeds:
+        _log("codec: training scene", train_recipe, sd)
+        sc = make_scene(train_recipe, seed=sd, **train_over)
         L.set_scene(sc, device_tensors=True)
         L.lift()
-        slag.slag_codec_add_lift_rows(L.ctx, 100_000, s)
+        slag.slag_codec_add_lift_rows(L.ctx, 100_000, sd)
         del sc
     nseg, nrows, nnz = slag.slag_codec_pool_size(L.ctx)
     t1 = time.perf_counter()
-    steps = args.codec_steps
     hist = slag.slag_codec_train(L.ctx, steps=steps, batch_rows=8192, lr=1e-3)
     t2 = time.perf_counter()
     _log(f"codec: trained {steps} steps on {nrows} rows in {t2 - t1:.1f} s, "
          f"loss {hist[:5].mean():.4f} -> {hist[-20:].mean():.4f}")
-    sc = make_scene("uneven_1m")
+    sc = eval_scene
     L.set_scene(sc, device_tensors=True)
     V = sc.n_views
 
@@ -312,22 +318,43 @@ def codec_section(args, slag, torch):
     ms_codec = timed(L.lift_codec, args.codec_reps)
     E_codec, _ = L.embeddings()
     L.close()
+    # the decode's share (eager, per-stage events): lift-to-codes = codec lift - decode
+    with slag.Lifter(0, flags=slag.SLAG_FLAG_PROFILE) as Lp:
+        slag.slag_codec_init(Lp.ctx, d, hidden, k, slag.SLAG_BF16, init_params(d, hidden, k, seed=1040))
+        Lp.set_scene(sc, device_tensors=True)
+        Lp.lift_codec()
+        Lp.stats()
+        Lp.lift_codec()
+        st = Lp.stats()["ms_stage"]
+    dec_ms = st.get("decode", 0.0)
     nz = den > 0
     a, b = E_plain[nz].astype(np.float64), E_codec[nz].astype(np.float64)
-    cos = np.sum(a * b, 1) / (np.linalg.norm(a, axis=1) * np.linalg.norm(b, axis=1) + 1e-300)
-    out = dict(workload="uneven_1m", desc=DESC["uneven_1m"],
-               k=k, hidden=h, precision="bf16",
+    na = np.linalg.norm(a, axis=1)
+    cos = np.sum(a * b, 1) / (na * np.linalg.norm(b, axis=1) + 1e-300)
+    Wd = vocabulary_words(d)
+    Q, _ = np.linalg.qr(Wd.T)                     # orthonormal basis of the vocabulary's span
+    ceil = np.linalg.norm(a @ Q, axis=1) / (na + 1e-300)
+    wts = den[nz].astype(np.float64)
+    out = dict(workload=sc.name, desc=DESC.get(sc.name, sc.name),
+               k=k, hidden=hidden, precision="bf16",
                plain_views_per_s=round(V / (ms_plain * 1e-3), 2),
                codec_views_per_s=round(V / (ms_codec * 1e-3), 2),
                plain_ms=round(ms_plain, 3), codec_ms=round(ms_codec, 3),
+               lift_to_codes_ms=round(ms_codec - dec_ms, 3), decode_ms=round(dec_ms, 3),
                speedup=round(ms_plain / ms_codec, 4),
+               speedup_to_codes=round(ms_plain / max(ms_codec - dec_ms, 1e-9), 4),
                cos_mean=round(float(cos.mean()), 5), cos_p1=round(float(np.percentile(cos, 1)), 5),
+               cos_median=round(float(np.median(cos)), 5),
+               cos_mean_weight_weighted=round(float(np.sum(cos * wts) / np.sum(wts)), 5),
                cos_min=round(float(cos.min()), 5),
                frac_cos_ge_099=round(float((cos >= 0.99).mean()), 5),
+               ceiling_mean=round(float(ceil.mean()), 5),
+               ceiling_weight_weighted=round(float(np.sum(ceil * wts) / np.sum(wts)), 5),
+               cos_over_ceiling_mean=round(float(np.mean(cos / np.maximum(ceil, 1e-12))), 5),
                tuning=tuning,
-               train=dict(scenes=[1041, 1042, 1043], rows=nrows, segments=nseg, weights=nnz,
-                          steps=steps, batch_rows=8192, seconds=round(t2 - t1, 2),
-                          loss_first=round(float(hist[:5].mean()), 5),
+               train=dict(recipe=train_recipe, overrides=train_over, scenes=list(seeds), rows=nrows,
+                          segments=nseg, weights=nnz, steps=steps, batch_rows=8192,
+                          seconds=round(t2 - t1, 2), loss_first=round(float(hist[:5].mean()), 5),
                           loss_last=round(float(hist[-20:].mean()), 5),
                           setup_seconds=round(t1 - t0, 1)))
     _log("codec:", json.dumps(out))
@@ -350,7 +377,7 @@ def main():
     ap.add_argument("--eager", action="store_true", help="time eager lifts instead of graph replays")
     ap.add_argument("--no-secondary", action="store_true", help="skip the smaller workloads")
     ap.add_argument("--no-codec", action="store_true", help="skip the codec section")
-    ap.add_argument("--codec-steps", type=int, default=2000)
+    ap.add_argument("--codec-steps", type=int, default=4000)
     ap.add_argument("--codec-k", type=int, default=16, help="code size (16, 32, 48 or 64)")
     ap.add_argument("--codec-hidden", type=int, default=256)
     ap.add_argument("--codec-reps", type=int, default=5)
@@ -395,15 +422,23 @@ def main():
         _log(f"CPU oracle on views {views} (baseline and accuracy)")
         accuracy, cpu = accuracy_and_cpu(slag, scene, views, 0)
         _log("accuracy:", json.dumps(accuracy))
+
+    codec_stress = None
+    if not args.no_codec and wl == "stress_4m":
+        codec_stress = codec_section(args, slag, torch, scene, 32, 256, args.codec_steps, "stress_4m",
+                                     dict(n=1_000_000, views=dict(n=200)))
     del scene
 
     secondary = []
+    uneven = None
     if not args.no_secondary:
         for w in ("plain_bf16_200k", "uneven_1m", "plain_fp32_2k"):
             if w == wl:
                 continue
             _log("secondary workload", w)
             sc = make_scene(w)
+            if w == "uneven_1m":
+                uneven = sc
             r, _, _ = measure(slag, torch, sc, max(args.steps, 10), args.warmup,
                               stage_steps=5 if sc.n >= 1_000_000 else 10)
             ro = composite_roofline(r, w)
@@ -420,7 +455,10 @@ def main():
 
     codec = None
     if not args.no_codec:
-        codec = codec_section(args, slag, torch)
+        if uneven is None:
+            uneven = make_scene("uneven_1m")
+        codec = codec_section(args, slag, torch, uneven, args.codec_k, args.codec_hidden,
+                              args.codec_steps, "codec_train", {})
 
     ms = res["ms_step"]
     out = {
@@ -456,6 +494,7 @@ def main():
         "accuracy": accuracy,
         "secondary": secondary,
         "codec": codec,
+        "codec_headline": codec_stress,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -356,11 +356,16 @@ def _project_points(cam, pts):
     return u, v, z
 
 
+def vocabulary_words(D: int, n_words: int = 64, seed: int = 7) -> np.ndarray:
+    """The global unit words of the object-vocabulary feature model [n_words][D]
+    (float64)."""
+    return _unit_rows(np.random.default_rng(seed).standard_normal((n_words, D)))
+
+
 def _features_of_objects(rng, spec, D, seg_obj, n_obj):
     """Object vocabulary: every object takes one of the global words (seed
     word_seed); a segment's feature is its object's word plus noise."""
-    words = _unit_rows(np.random.default_rng(spec.get("word_seed", 7)).standard_normal(
-        (spec.get("n_words", 64), D)))
+    words = vocabulary_words(D, spec.get("n_words", 64), spec.get("word_seed", 7))
     obj_word = rng.integers(0, words.shape[0], size=n_obj) if n_obj > words.shape[0] else \
         rng.permutation(words.shape[0])[:n_obj]
     lab = np.concatenate(seg_obj) if seg_obj else np.zeros(0, np.int64)
