@@ -106,7 +106,11 @@ typedef struct {
     int32_t labels_per_pixel;       /* masks one pixel may lie in (overlapping masks): 0 or 1
                                        (one id per pixel), up to 4; see
                                        slag_set_segments_multi */
-    int32_t reserved32;
+    int32_t weight_mode;            /* the weight w_kp a pixel gives each Gaussian the
+                                       front-to-back walk blends: 0 = the blend weight
+                                       alpha T (default), 1 = the Gaussian kernel
+                                       exp(-q/2) itself (the paper's weight equation,
+                                       with the contributing set of the walk) */
     int64_t reserved[1];
 } slag_options;
 
@@ -206,6 +210,26 @@ slag_status slag_get_embeddings(slag_ctx* ctx, void* out, slag_dtype dtype, floa
  * slag_get_stats reports the first chunk's lift. */
 slag_status slag_lift_chunked(slag_ctx* ctx, int64_t chunk_rows, void* out, slag_dtype dtype,
                               float* den);
+
+/* Render per-Gaussian attributes into one view with the weights of the
+ * lift (Method, the rendering equation: the Gaussians covering a pixel are
+ * alpha-composited front to back; with the lift's weight w = alpha T, or
+ * the kernel weight when weight_mode = 1; every pixel, no masking):
+ *   out[y][x][c] = sum_k w_k attr[g_k][c] / sum_k w_k   (0 where nothing blends)
+ *   wsum[y][x]   = sum_k w_k
+ * attr [N][C] FP32 in the caller's Gaussian order, C = 1 .. 1024 (for
+ * example E_GAUSSIAN rendered back into a view as a feature map, or a
+ * per-Gaussian query score), in host or device memory as attr_where says;
+ * out [H][W][C] and wsum [H][W] (may be NULL) FP32 where out_where says,
+ * H x W the view's camera.  Needs the Gaussians and cameras only (segments
+ * and features need not be set).  The view is projected, sorted and binned
+ * anew in the lift's buffers: the last lift's debug exports fail with
+ * SLAG_E_STATE afterwards; its embeddings and statistics stay.  Synchronous.
+ * Errors: SLAG_E_INVALID_ARG (view or C out of range, null pointers, bad
+ * memory kind), SLAG_E_STATE (no Gaussians or cameras), SLAG_E_CAPACITY
+ * (the view's tile intersections exceed max_launch_entries), device errors. */
+slag_status slag_render(slag_ctx* ctx, int32_t view, const float* attr, int32_t C,
+                        slag_mem attr_where, float* out, float* wsum, slag_mem out_where);
 
 slag_status slag_get_stats(slag_ctx* ctx, slag_stats* stats);
 const char* slag_stage_name(int32_t stage);

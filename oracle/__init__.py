@@ -67,18 +67,23 @@ def _lib():
         L.orc_max_threads.restype = ctypes.c_int
         L.orc_set_constants.argtypes = [P]
         L.orc_set_constants.restype = None
+        L.orc_render_view.restype = ctypes.c_int32
+        L.orc_render_view.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int32,
+                                      ctypes.c_int32, P, P, P, P]
         _lib_handle = L
     return _lib_handle
 
 
-CONSTANT_NAMES = ("alpha_max", "alpha_min", "t_min", "dilation", "near_z", "guard")
+CONSTANT_NAMES = ("alpha_max", "alpha_min", "t_min", "dilation", "near_z", "guard",
+                  "weight_mode")
 
 
 @contextlib.contextmanager
 def constants(**kw):
     """Run the oracle with non-default rasterizer constants (the library's
     options of the same names; each given as the float the library receives,
-    0 or absent = the 3D Gaussian splatting default), restoring the defaults
+    0 or absent = the 3D Gaussian splatting default; weight_mode = 1: kernel
+    weights exp(-q/2) instead of alpha T), restoring the defaults
     afterwards."""
     bad = set(kw) - set(CONSTANT_NAMES)
     if bad:
@@ -89,7 +94,7 @@ def constants(**kw):
     try:
         yield
     finally:
-        L.orc_set_constants(_p(np.zeros(6, np.float32)))
+        L.orc_set_constants(_p(np.zeros(len(CONSTANT_NAMES), np.float32)))
 
 
 def _p(a: Optional[np.ndarray]):
@@ -157,6 +162,57 @@ def lift_view(scene, v: int, mode: str = "box", pixels: bool = False,
     L.orc_view_free(h)
     return ViewResult(g, s, w, u, r, cnt.n_contrib, cnt.n_tests, cnt.n_visible, cnt.n_uncertain,
                       T, ws, rho)
+
+
+@dataclasses.dataclass
+class RenderResult:
+    out: np.ndarray        # [H, W, C] float64 sum w a / sum w (0 where nothing blends)
+    wsum: np.ndarray       # [H, W] float64 sum of the weights
+    bw: np.ndarray         # [H, W] float64 bound on the FP32 weights' total deviation
+    nb: np.ndarray         # [H, W] int32 contributions (taken or possibly taken)
+
+
+def render_view(scene, v: int, attr: np.ndarray, nthreads: int = 0) -> RenderResult:
+    """Render per-Gaussian attributes into view v with the lift's weights
+    (Method, the rendering equation: the attributes alpha-composited front to
+    back with the same alpha T (or kernel) weights the lift sums, normalised
+    by their sum; no masking)."""
+    L = _lib()
+    a = _c(attr, np.float32)
+    if a.ndim != 2 or a.shape[0] != scene.n:
+        raise ValueError("attr must be [N, C]")
+    C = a.shape[1]
+    cam = np.ascontiguousarray(scene.cams[v:v + 1])
+    H, W = int(cam["height"][0]), int(cam["width"][0])
+    out = np.empty((H, W, C), np.float64)
+    ws = np.empty((H, W), np.float64)
+    bw = np.empty((H, W), np.float64)
+    nb = np.empty((H, W), np.int32)
+    means, scales = _c(scene.means, np.float32), _c(scene.scales, np.float32)
+    quats, opac = _c(scene.quats, np.float32), _c(scene.opacity, np.float32)
+    if L.orc_render_view(scene.n, _p(means), _p(scales), _p(quats), _p(opac), _p(cam), _p(a), C,
+                         int(nthreads), _p(out), _p(ws), _p(bw), _p(nb)) != 0:
+        raise MemoryError("oracle render failed")
+    return RenderResult(out, ws, bw, nb)
+
+
+def render_bound(rr: RenderResult, amax: np.ndarray) -> np.ndarray:
+    """Bound on |out_fp32 - out| per pixel and channel for a front-to-back
+    FP32 accumulation of w a and w (one rounding per term) followed by one
+    reciprocal and one product.  amax [C]: max |attr| per channel.  With
+    eD = Bw + m u (D + Bw) and eN = amax (Bw + m u (D + Bw)), m = nb + 1:
+      |N'/D' - N/D| <= (eN + |out| eD) / (D - eD)   (+ 4 u of the result);
+    inf where D <= eD (nothing certain blends at the pixel)."""
+    u = 2.0 ** -24
+    D = rr.wsum[..., None]
+    Bw = rr.bw[..., None]
+    m = rr.nb[..., None].astype(np.float64) + 1.0
+    eD = Bw + m * u * (D + Bw)
+    eN = np.asarray(amax, np.float64)[None, None, :] * eD
+    o = np.abs(rr.out)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        b = np.where(D > eD, (eN + o * eD) / (D - eD), np.inf)
+    return b + 4.0 * u * (o + b)
 
 
 @dataclasses.dataclass

@@ -93,9 +93,14 @@ static double D_AMAX = 0.99;
 static double D_TMIN = 1e-4;
 static double D_DIL = 0.3;
 static double D_CLAMP = 1.3;
+/* Weight of a blended Gaussian: 0 = alpha T (the front-to-back blend weight,
+ * the default reading), 1 = the Gaussian kernel exp(-q/2) itself (the
+ * paper's weight equation) for each Gaussian the walk blends. */
+static int g_kernel_w = 0;
 
 /* Non-default constants, each given as the float the library receives:
- * c = (alpha_max, alpha_min, t_min, dilation, near_z, guard), 0 = default.
+ * c = (alpha_max, alpha_min, t_min, dilation, near_z, guard, weight mode),
+ * 0 = default (weight mode 1: kernel weights).
  * The FP64 values are those floats widened; rho^2 = 2 ln(1 / alpha_min) is
  * rounded once to float (the default keeps the float nearest to 2 ln 255). */
 void orc_set_constants(const float* c)
@@ -112,6 +117,7 @@ void orc_set_constants(const float* c)
     F_NEAR = c[4] > 0.0f ? c[4] : 0.01f;
     F_CLAMP = c[5] > 0.0f ? c[5] : 1.3f;
     D_CLAMP = c[5] > 0.0f ? (double)c[5] : 1.3;
+    g_kernel_w = c[6] > 0.0f;
 }
 
 #define D_L2E 1.4426950408889634074      /* log2(e) */
@@ -473,11 +479,16 @@ static int composite_pixel(const view_ctx* vc, const int32_t* cand, int64_t nc,
         const double ea = (au * (1.0 - eps) >= D_AMAX) ? 0.0 : eps;
         const double dl = delta < 1.0 ? delta : 1.0;
         const double grow = 1.0 + dl;
+        /* the weight this Gaussian would get: alpha T, or its kernel value
+         * (unclamped alpha / o); with kernel weights T carries no error */
+        const double kv = au / p->o;
+        const double wt = g_kernel_w ? kv : alpha * T;
+        const double rt = g_kernel_w ? 0.0 : rho;
         if (alpha < D_AMIN) {
             if (alpha * (1.0 + eps) >= D_AMIN) {
                 (*n_unc)++;
                 any_near = 1;
-                if (push_labels(out, g, segs, nl, 0.0, alpha * T * grow * (1.0 + eps + rho), 0.0))
+                if (push_labels(out, g, segs, nl, 0.0, wt * grow * (1.0 + eps + rt), 0.0))
                     return -1;
                 delta += alpha / (1.0 - alpha);
             }
@@ -491,15 +502,17 @@ static int composite_pixel(const view_ctx* vc, const int32_t* cand, int64_t nc,
         if (near_a || near_t) { (*n_unc)++; any_near = 1; }
         if (Tn < D_TMIN) {
             if (near_t && nl > 0) {
-                if (push_labels(out, g, segs, nl, 0.0, alpha * T * grow * (1.0 + ea + rho), 0.0))
+                if (push_labels(out, g, segs, nl, 0.0, wt * grow * (1.0 + ea + rt), 0.0))
                     return -1;
                 for (int64_t h = k + 1; h < nc; h++) {
                     const proj64* ph = &vc->P[cand[h]];
-                    const double ah = alpha_at(ph, px, py, NULL);
+                    double ahu;
+                    const double ah = alpha_at(ph, px, py, &ahu);
                     const double eh = alpha_eps(ph, &vc->Mi[cand[h]], px, py) + CONST_REL;
                     if (ah * (1.0 + eh) >= D_AMIN) {
+                        const double wh = g_kernel_w ? ahu / ph->o : ah * Tn;
                         if (push_labels(out, cand[h], segs, nl, 0.0,
-                                        ah * Tn * grow * (1.0 + eh + rho_n), 0.0))
+                                        wh * grow * (1.0 + eh + (g_kernel_w ? 0.0 : rho_n)), 0.0))
                             return -1;
                         break;
                     }
@@ -507,8 +520,11 @@ static int composite_pixel(const view_ctx* vc, const int32_t* cand, int64_t nc,
             }
             break;
         }
-        const double w = alpha * T;
-        const double r = w * (ea + rho + U32);
+        /* kernel weights: exp2 of the exponent less log2(o), one more
+         * subtraction and the exp2 of the FP32 path */
+        const double w = wt;
+        const double r = g_kernel_w ? w * (eps + U32 * (5.0 + D_LN2 * (fabs(p->lo2) - log2(kv))))
+                                    : w * (ea + rho + U32);
         double u = w * dl;
         if (near_a) u = w * grow;
         if (near_t) { u = w * grow; delta = 1.0; }
@@ -565,7 +581,7 @@ static int composite_pixel_f32(const view_ctx* vc, const int32_t* cand, int64_t 
         if (!(alpha >= AMIN_F)) continue;
         const float Tn = fmaf(-alpha, T, T);
         if (Tn < TMIN_F) break;
-        const float w = alpha * T;
+        const float w = g_kernel_w ? exp2f(e - lo2) : alpha * T;
         sumw += (double)w;
         if (push_labels(out, g, segs, nl, (double)w, 0.0, 0.0)) return -1;
         T = Tn;
@@ -634,6 +650,36 @@ static int cmp_u64(const void* a, const void* b)
 }
 
 /*
+ * Per-pixel candidate lists of the box mode: start[npix + 1] (zeroed by the
+ * caller) receives the offsets, the returned array the Gaussians whose
+ * conservative pixel box contains each pixel, in index order (NULL when out
+ * of memory).
+ */
+static int32_t* box_candidates(int64_t n, const mirror_out* Mi, int W, int H, int64_t* start)
+{
+    const int64_t npix = (int64_t)W * H;
+    for (int64_t g = 0; g < n; g++) {
+        const mirror_out* m = &Mi[g];
+        if (!m->vis) continue;
+        for (int y = m->y0; y <= m->y1; y++)
+            for (int x = m->x0; x <= m->x1; x++) start[(int64_t)y * W + x + 1]++;
+    }
+    for (int64_t i = 0; i < npix; i++) start[i + 1] += start[i];
+    int32_t* cand = (int32_t*)malloc((size_t)(start[npix] ? start[npix] : 1) * sizeof(int32_t));
+    int64_t* fill = (int64_t*)malloc((size_t)(npix ? npix : 1) * sizeof(int64_t));
+    if (!cand || !fill) { free(cand); free(fill); return NULL; }
+    memcpy(fill, start, (size_t)npix * sizeof(int64_t));
+    for (int64_t g = 0; g < n; g++) {
+        const mirror_out* m = &Mi[g];
+        if (!m->vis) continue;
+        for (int y = m->y0; y <= m->y1; y++)
+            for (int x = m->x0; x <= m->x1; x++) cand[fill[(int64_t)y * W + x]++] = (int32_t)g;
+    }
+    free(fill);
+    return cand;
+}
+
+/*
  * Lift one view.  mode bit 0: 0 = brute (every Gaussian in front of the
  * camera is a candidate of every pixel), 1 = box (only Gaussians whose
  * conservative pixel box contains the pixel).  Both walk candidates in the
@@ -682,24 +728,8 @@ void* orc_lift_view(int64_t n, const float* means, const float* scales, const fl
         g_sort_z = z;
         qsort(all, (size_t)nall, sizeof(int32_t), cmp_depth);
     } else {
-        for (int64_t g = 0; g < n; g++) {
-            const mirror_out* m = &Mi[g];
-            if (!m->vis) continue;
-            for (int y = m->y0; y <= m->y1; y++)
-                for (int x = m->x0; x <= m->x1; x++) start[(int64_t)y * W + x + 1]++;
-        }
-        for (int64_t i = 0; i < npix; i++) start[i + 1] += start[i];
-        cand = (int32_t*)malloc((size_t)(start[npix] ? start[npix] : 1) * sizeof(int32_t));
-        int64_t* fill = (int64_t*)malloc((size_t)(npix ? npix : 1) * sizeof(int64_t));
-        if (!cand || !fill) return NULL;
-        memcpy(fill, start, (size_t)npix * sizeof(int64_t));
-        for (int64_t g = 0; g < n; g++) {
-            const mirror_out* m = &Mi[g];
-            if (!m->vis) continue;
-            for (int y = m->y0; y <= m->y1; y++)
-                for (int x = m->x0; x <= m->x1; x++) cand[fill[(int64_t)y * W + x]++] = (int32_t)g;
-        }
-        free(fill);
+        cand = box_candidates(n, Mi, W, H, start);
+        if (!cand) return NULL;
     }
 
     /* walk every pixel; rows in parallel, contributions kept per row */
@@ -795,6 +825,89 @@ void* orc_lift_view(int64_t n, const float* means, const float* scales, const fl
     }
     if (n_triples) *n_triples = k;
     return vr;
+}
+
+/*
+ * Render per-Gaussian attributes attr [n][C] into one view with the weights
+ * of the lift (Method, the rendering equation with w = alpha T, or the
+ * kernel weights): every pixel walks its depth-ordered candidates exactly as
+ * the lift does (composite_pixel, one pseudo-label, no masking) and gets
+ *   out[p][c] = sum_k w_k attr[g_k][c] / sum_k w_k   (0 where the sum is 0),
+ * with wsum[p] = sum_k w_k, bw[p] = sum_k (u_k + r_k) (the bound on the
+ * FP32 weights' total deviation, decision flips included) and nb[p] = the
+ * number of contributions (blended or possibly blended).  Returns 0, or -1
+ * when out of memory.
+ */
+int32_t orc_render_view(int64_t n, const float* means, const float* scales, const float* quats,
+                        const float* opacity, const orc_camera* cam, const float* attr, int32_t C,
+                        int32_t nthreads, double* out, double* wsum, double* bw, int32_t* nb)
+{
+    const int W = cam->width, H = cam->height;
+    const int64_t npix = (int64_t)W * H;
+    proj64* P = (proj64*)malloc((size_t)(n ? n : 1) * sizeof(proj64));
+    mirror_out* Mi = (mirror_out*)malloc((size_t)(n ? n : 1) * sizeof(mirror_out));
+    float* z = (float*)malloc((size_t)(n ? n : 1) * sizeof(float));
+    int64_t* start = (int64_t*)calloc((size_t)npix + 1, sizeof(int64_t));
+    if (!P || !Mi || !z || !start) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(static)
+    for (int64_t g = 0; g < n; g++) {
+        mirror_project(means + 3 * g, scales + 3 * g, quats + 4 * g, cam, &Mi[g]);
+        z[g] = Mi[g].z32;
+        if (Mi[g].vis_depth) project64(means + 3 * g, scales + 3 * g, quats + 4 * g, opacity[g], cam, &P[g]);
+    }
+    int32_t* cand = box_candidates(n, Mi, W, H, start);
+    if (!cand) return -1;
+    int64_t maxc = 0;
+    for (int64_t i = 0; i < npix; i++)
+        if (start[i + 1] - start[i] > maxc) maxc = start[i + 1] - start[i];
+    view_ctx vc = {P, Mi};
+    int failed = 0;
+#pragma omp parallel
+    {
+        int32_t* tmp = (int32_t*)malloc((size_t)(maxc + 1) * sizeof(int32_t));
+        cbuf cb = {NULL, 0, 0};
+        const int32_t seg0 = 0;
+#pragma omp for schedule(dynamic, 1)
+        for (int y = 0; y < H; y++) {
+            for (int x = 0; x < W; x++) {
+                const int64_t pi = (int64_t)y * W + x;
+                const int64_t nc = start[pi + 1] - start[pi];
+                if (!tmp) { failed = 1; continue; }
+                sort_depth(cand + start[pi], nc, z, tmp);
+                double Tf, ws, rf;
+                int nr;
+                int64_t c0 = 0, c1 = 0, c2 = 0;
+                cb.n = 0;
+                if (composite_pixel(&vc, cand + start[pi], nc, x, y, &seg0, 1, &cb, &Tf, &ws,
+                                            &rf, &nr, &c0, &c1, &c2, 0)) {
+                    failed = 1;
+                    continue;
+                }
+                double* o = out + pi * C;
+                for (int c = 0; c < C; c++) o[c] = 0.0;
+                double sw = 0.0, sb = 0.0;
+                for (int64_t i = 0; i < cb.n; i++) {
+                    const contrib* e = &cb.a[i];
+                    const float* a = attr + (int64_t)e->g * C;
+                    for (int c = 0; c < C; c++) o[c] += e->w * (double)a[c];
+                    sw += e->w;
+                    sb += e->u + e->r;
+                }
+                if (sw > 0.0)
+                    for (int c = 0; c < C; c++) o[c] /= sw;
+                wsum[pi] = sw;
+                bw[pi] = sb;
+                nb[pi] = (int32_t)cb.n;
+            }
+        }
+        free(cb.a);
+        free(tmp);
+    }
+    free(start); free(cand); free(P); free(Mi); free(z);
+    return failed ? -1 : 0;
 }
 
 void orc_view_fetch(void* h, int32_t* g, int32_t* s, double* w, double* u, double* r)

@@ -47,7 +47,7 @@ class slag_options(ctypes.Structure):
                 ("t_min", ctypes.c_float), ("dilation", ctypes.c_float),
                 ("near_z", ctypes.c_float), ("guard", ctypes.c_float),
                 ("tile_size", ctypes.c_int32), ("deterministic", ctypes.c_int32),
-                ("labels_per_pixel", ctypes.c_int32), ("reserved32", ctypes.c_int32),
+                ("labels_per_pixel", ctypes.c_int32), ("weight_mode", ctypes.c_int32),
                 ("reserved", ctypes.c_int64 * 1)]
 
 
@@ -82,7 +82,7 @@ EXPORTS = ["slag_create", "slag_destroy", "slag_last_error", "slag_set_gaussians
            "slag_codec_loss_grad", "slag_codec_train", "slag_lift_codec", "slag_get_codes",
            # include/slag_query.h
            "slag_query", "slag_classify", "slag_query_static", "slag_lift_chunked",
-           "slag_set_segments_multi"]
+           "slag_set_segments_multi", "slag_render"]
 
 _lib_handle = None
 
@@ -117,6 +117,7 @@ def lib():
     L.slag_set_features.argtypes = [P, I32, I32, P, I32]
     L.slag_lift.argtypes = [P]
     L.slag_lift_chunked.argtypes = [P, I64, P, I32, P]
+    L.slag_render.argtypes = [P, I32, P, I32, I32, P, P, I32]
     L.slag_get_embeddings.argtypes = [P, P, I32, P, I32]
     L.slag_get_debug.argtypes = [P, I32, I32, P, I64, ctypes.POINTER(I64)]
     L.slag_get_stats.argtypes = [P, ctypes.POINTER(slag_stats)]
@@ -183,7 +184,7 @@ def slag_create(device: int = 0, stream=None, max_views_per_launch: int = 0, fla
     o = slag_options(max_views_per_launch, flags, max_launch_entries)
     for k, v in constants.items():
         if k not in ("alpha_max", "alpha_min", "t_min", "dilation", "near_z", "guard",
-                     "tile_size", "deterministic", "labels_per_pixel"):
+                     "tile_size", "deterministic", "labels_per_pixel", "weight_mode"):
             raise ValueError(f"unknown option {k}")
         setattr(o, k, v)
     h = ctypes.c_void_p()
@@ -240,6 +241,21 @@ def slag_lift_chunked(ctx, chunk_rows: int, out, den=None):
 
 def slag_lift(ctx):
     _check(ctx, lib().slag_lift(ctx))
+
+
+def slag_render(ctx, view: int, attr, out, wsum=None):
+    """Render attr [N][C] (float32 array or tensor) into view `view`:
+    out [H][W][C] and wsum [H][W] (float32, both host arrays or both GPU
+    tensors; wsum may be None)."""
+    pa, wa = _ptr(attr)
+    po, wo = _ptr(out)
+    pw, ww = _ptr(wsum)
+    if wsum is not None and ww != wo:
+        raise ValueError("out and wsum must be in the same memory")
+    C = int(attr.shape[1]) if attr is not None and len(attr.shape) == 2 else 0
+    if out is None or tuple(out.shape[2:]) != (C,):
+        raise ValueError("out must be [H][W][C] with C = attr.shape[1]")
+    _check(ctx, lib().slag_render(ctx, int(view), pa, C, wa, po, pw, wo))
 
 
 def _dtype_of(a) -> int:
@@ -486,6 +502,16 @@ class Lifter:
 
     def lift(self):
         slag_lift(self.ctx)
+
+    def render(self, view: int, attr, cams):
+        """attr [N][C] rendered into view `view` of cams (the scene's cameras):
+        (out [H, W, C], wsum [H, W]) as host arrays."""
+        H, W = int(cams[view]["height"]), int(cams[view]["width"])
+        attr = np.ascontiguousarray(attr, np.float32)
+        out = np.empty((H, W, attr.shape[1]), np.float32)
+        ws = np.empty((H, W), np.float32)
+        slag_render(self.ctx, view, attr, out, ws)
+        return out, ws
 
     def embeddings(self):
         E = np.empty((self.n, self.d), np.float32)

@@ -231,8 +231,9 @@ struct LaneXY {
     float lx, ly;
 };
 
-template <int MODE, bool COUNTING, bool PAD>
+template <int MODE, bool COUNTING, bool PAD, bool KW>
 __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const float4* __restrict__ w1,
+                                            const float* __restrict__ wlo,
                                             const int* __restrict__ wj, int cnt, const LaneXY& Q,
                                             int px, int py, uint32_t sbits, int uslot,
                                             uint32_t slot_mask,
@@ -265,11 +266,15 @@ __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const
             const float e = fmaf(ty, Q.ly, fmaf(tx, Q.lx, p0.x));
             const float alpha = fminf(amax, __builtin_amdgcn_exp2f(e));
             const float Tn = fmaf(-alpha, T, T);
+            // the weight: alpha T, or (KW) the Gaussian kernel exp(-q/2) =
+            // 2^(e - log2 o) of each blended Gaussian (the paper's weight
+            // equation)
+            const float wv = KW ? __builtin_amdgcn_exp2f(e - wlo[jj]) : alpha * T;
             if (COUNTING) {
                 const bool ok = !done && alpha >= amin;
                 const bool stop = ok && Tn < tmin;
                 const bool take = ok && !stop;
-                w[u] = (take && slot_ok) ? alpha * T : 0.0f;
+                w[u] = (take && slot_ok) ? wv : 0.0f;
                 if (!done && jj < cnt) {
                     n_tile++;
                     const uint32_t a = __float_as_uint(p1.z), b = __float_as_uint(p1.w);
@@ -277,7 +282,7 @@ __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const
                               py >= (int)(a >> 16) && py <= (int)(b >> 16));
                 }
                 n_acc += take;
-                wsum += take ? alpha * T : 0.0f;
+                wsum += take ? wv : 0.0f;
                 T = take ? Tn : T;
                 done = done || stop;
             } else {
@@ -285,7 +290,7 @@ __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const
                 // this pass): then Tn = 0 < tmin and w = 0 from here on
                 const bool ok = alpha >= amin;
                 const bool keep = Tn >= tmin;
-                w[u] = (ok && keep) ? alpha * T : 0.0f;
+                w[u] = (ok && keep) ? wv : 0.0f;
                 T = ok ? (keep ? Tn : 0.0f) : T;
             }
         }
@@ -312,7 +317,7 @@ __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const
 // Variants (same arithmetic, bitwise-equal results): MINW = waves per SIMD
 // the register budget must allow; PAD = four-entry groups padded with null
 // entries (loads of a group can be issued together) or cut at the end.
-template <bool COUNT, int MINW, bool PAD, int LMAX>
+template <bool COUNT, int MINW, bool PAD, int LMAX, bool KW>
 __global__ __launch_bounds__(256, MINW) void k_composite(
     const uint32_t* __restrict__ order, uint32_t obase,
     const uint32_t* __restrict__ bucket_view, const ViewDev* __restrict__ views,
@@ -326,6 +331,7 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
     __shared__ float4 s_w0[4][BATCH];         // per wave: entries touching its block, exponent
     __shared__ float4 s_w1[4][BATCH];         //   coefficients (c0, cx, cy, cxx), (cxy, cyy, box, box)
     __shared__ int s_wj[4][BATCH];            //   their index in the batch
+    __shared__ float s_lo[4][BATCH];          //   log2(opacity) (kernel weights)
     __shared__ float s_acc[4][BATCH][NS_CAP]; // per wave weight sums [entry][segment]
     __shared__ uint32_t s_pair[BATCH];        // pair of each batch entry
     __shared__ uint32_t s_tir[BATCH];         // index of this tile in the pair's tile rectangle
@@ -460,10 +466,12 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
                 s_w0[wv][k] = make_float4(c0, cx, cy, A);
                 s_w1[wv][k] = make_float4(B, C, q1.z, q1.w);
                 s_wj[wv][k] = lane;
+                if (KW) s_lo[wv][k] = lo2;
             }
             if (PAD && lane >= cnt && lane < ((cnt + 3) & ~3)) {   // null entries up to a multiple of 4
                 s_w0[wv][lane] = make_float4(-1e30f, 0.0f, 0.0f, 0.0f);   // 2^e = 0
                 s_w1[wv][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (KW) s_lo[wv][lane] = 0.0f;
             }
             if (wv == 0 && lane < nb) {
                 const int rtx0 = (int)(ba & 0xFFFFu) / TILE, rty0 = (int)(ba >> 16) / TILE;
@@ -480,16 +488,16 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
             if (cnt && !__all(done)) {
                 if (counting) {
                     if (mode == MODE_UNIFORM)
-                        blend_batch<MODE_UNIFORM, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, sbits, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum, amin, amax, tmin);
+                        blend_batch<MODE_UNIFORM, true, PAD, KW>(s_w0[wv], s_w1[wv], s_lo[wv], s_wj[wv], cnt, Q, px, py, sbits, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum, amin, amax, tmin);
                     else if (mode == MODE_MIXED)
-                        blend_batch<MODE_MIXED, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, sbits, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum, amin, amax, tmin);
+                        blend_batch<MODE_MIXED, true, PAD, KW>(s_w0[wv], s_w1[wv], s_lo[wv], s_wj[wv], cnt, Q, px, py, sbits, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum, amin, amax, tmin);
                     else
-                        blend_batch<MODE_NONE, true, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, sbits, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum, amin, amax, tmin);
+                        blend_batch<MODE_NONE, true, PAD, KW>(s_w0[wv], s_w1[wv], s_lo[wv], s_wj[wv], cnt, Q, px, py, sbits, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum, amin, amax, tmin);
                 } else {
                     if (mode == MODE_UNIFORM)
-                        blend_batch<MODE_UNIFORM, false, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, sbits, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum, amin, amax, tmin);
+                        blend_batch<MODE_UNIFORM, false, PAD, KW>(s_w0[wv], s_w1[wv], s_lo[wv], s_wj[wv], cnt, Q, px, py, sbits, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum, amin, amax, tmin);
                     else
-                        blend_batch<MODE_MIXED, false, PAD>(s_w0[wv], s_w1[wv], s_wj[wv], cnt, Q, px, py, sbits, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum, amin, amax, tmin);
+                        blend_batch<MODE_MIXED, false, PAD, KW>(s_w0[wv], s_w1[wv], s_lo[wv], s_wj[wv], cnt, Q, px, py, sbits, uslot, slot_mask, T, done, s_acc[wv], lane, n_acc, n_box, n_tile, wsum, amin, amax, tmin);
                 }
             }
             __syncthreads();
@@ -556,6 +564,88 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
     }
 }
 
+// Render-back of per-Gaussian attributes into one view (the paper's
+// rendering equation with the lift's weights: C_p = sum_k w_kp a_k /
+// sum_k w_kp over the Gaussians the front-to-back walk blends at p, every
+// pixel, no masking).  One workgroup per 16x16 tile of the view, four waves
+// of 8x8 pixels; the tile's list is staged BATCH entries at a time with the
+// entries' attribute channels [c0, c0 + 16); every lane evaluates every
+// entry with the compositing's own exponent expansion (about its wave's
+// block centre), so its weights and decisions are the lift's, bit for bit.
+template <bool KW>
+__global__ __launch_bounds__(256) void k_render(const ViewDev* __restrict__ views, int vi,
+                                                const uint32_t* __restrict__ bstart,
+                                                const uint32_t* __restrict__ bend,
+                                                const uint32_t* __restrict__ ival,
+                                                const float4* __restrict__ rec,
+                                                const uint32_t* __restrict__ pgauss,
+                                                const float* __restrict__ attr, int C, int c0,
+                                                float* __restrict__ out,
+                                                float* __restrict__ wsum_out)
+{
+    __shared__ float4 s_r0[BATCH], s_r1[BATCH];
+    __shared__ float s_a[BATCH][16];
+    const ViewDev& V = views[vi];
+    const uint32_t tile = blockIdx.x;
+    const uint32_t b = V.tile_base + tile;
+    const int tx = (int)(tile % (uint32_t)V.ntx), ty = (int)(tile / (uint32_t)V.ntx);
+    const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+    const int bx0 = tx * TILE + (wv & 1) * 8, by0 = ty * TILE + (wv >> 1) * 8;
+    const int px = bx0 + (lane & 7), py = by0 + (lane >> 3);
+    const bool valid = px < V.W && py < V.H;
+    const float lx = (float)(lane & 7) - 3.5f, ly = (float)(lane >> 3) - 3.5f;
+    const float amin = V.amin, amax = V.amax, tmin = V.tmin;
+    const int cn = min(16, C - c0);
+    float T = 1.0f, ws = 0.0f, acc[16];
+#pragma unroll
+    for (int c = 0; c < 16; c++) acc[c] = 0.0f;
+    bool done = !valid;
+    const uint32_t start = bstart[b], end = bend[b];
+    for (uint32_t base = start; base < end; base += BATCH) {
+        const int nb = (int)min((uint32_t)BATCH, end - base);
+        if (t < nb) {
+            const uint32_t p = ival[base + t];
+            s_r0[t] = rec[2 * (size_t)p];
+            s_r1[t] = rec[2 * (size_t)p + 1];
+            const float* ar = attr + (size_t)pgauss[p] * C + c0;
+            for (int c = 0; c < cn; c++) s_a[t][c] = ar[c];
+        }
+        __syncthreads();
+        for (int j = 0; j < nb && !__all(done); j++) {
+            const float4 q0 = s_r0[j], q1 = s_r1[j];
+            const uint32_t ba = __float_as_uint(q1.z);
+            const float A = q0.z, B = q0.w, Cq = q1.x, lo2 = q1.y;
+            const float du = q0.x + (float)((int)(ba & 0xFFFFu) - bx0 - 4);
+            const float dv = q0.y + (float)((int)(ba >> 16) - by0 - 4);
+            const float cx = -fmaf(2.0f * A, du, B * dv);
+            const float cy = -fmaf(B, du, 2.0f * Cq * dv);
+            const float e0 = fmaf(A * du, du, fmaf(B * du, dv, Cq * dv * dv)) + lo2;
+            const float tq = fmaf(B, ly, fmaf(A, lx, cx));
+            const float tw = fmaf(Cq, ly, cy);
+            const float e = fmaf(tw, ly, fmaf(tq, lx, e0));
+            const float alpha = fminf(amax, __builtin_amdgcn_exp2f(e));
+            const float Tn = fmaf(-alpha, T, T);
+            const bool ok = !done && alpha >= amin;
+            const bool stop = ok && Tn < tmin;
+            const bool take = ok && !stop;
+            const float w = take ? (KW ? __builtin_amdgcn_exp2f(e - lo2) : alpha * T) : 0.0f;
+            ws += w;
+#pragma unroll
+            for (int c = 0; c < 16; c++)
+                if (c < cn) acc[c] = fmaf(w, s_a[j][c], acc[c]);
+            T = take ? Tn : T;
+            done = done || stop;
+        }
+        if (__syncthreads_count(!done) == 0) break;
+    }
+    if (valid) {
+        const size_t pi = (size_t)py * V.W + px;
+        const float inv = ws > 0.0f ? 1.0f / ws : 0.0f;
+        for (int c = 0; c < cn; c++) out[pi * C + c0 + c] = acc[c] * inv;
+        if (wsum_out && c0 == 0) wsum_out[pi] = ws;
+    }
+}
+
 // Part-list records: pinfo[p] = (base, 0) from the scanned capacities, and
 // the sentinel pinfo[npairs] = (total, 0), so a list's capacity is the next
 // record's base minus its own.
@@ -597,6 +687,22 @@ __global__ __launch_bounds__(256) void k_merge(uint64_t npairs, const uint16_t* 
 
 }  // namespace
 
+void launch_render(bool kernel_w, int ntiles, const ViewDev* views, int vi, const uint32_t* bstart,
+                   const uint32_t* bend, const uint32_t* ival, const float4* rec,
+                   const uint32_t* pgauss, const float* attr, int C, float* out, float* wsum,
+                   hipStream_t st)
+{
+    if (ntiles <= 0) return;
+    for (int c0 = 0; c0 < C; c0 += 16) {
+        if (kernel_w)
+            hipLaunchKernelGGL((k_render<true>), dim3((unsigned)ntiles), dim3(256), 0, st, views, vi,
+                               bstart, bend, ival, rec, pgauss, attr, C, c0, out, wsum);
+        else
+            hipLaunchKernelGGL((k_render<false>), dim3((unsigned)ntiles), dim3(256), 0, st, views, vi,
+                               bstart, bend, ival, rec, pgauss, attr, C, c0, out, wsum);
+    }
+}
+
 void launch_tile_segs(uint32_t nbuckets, const uint32_t* bucket_view, const ViewDev* views,
                       const int32_t* ids, int lpp, uint32_t* ns_tile, uint16_t* segl,
                       unsigned long long* err, hipStream_t st)
@@ -626,13 +732,14 @@ void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t
                       uint32_t obase, const uint32_t* bucket_view, const ViewDev* views,
                       const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
                       uint2* pinfo, const float4* rec, const uint32_t* ns_tile,
-                      const uint16_t* segl, const int32_t* ids, int lpp, uint2* part,
-                      unsigned long long* counters, float* pix_t, float* pix_w, uint32_t* pix_n,
-                      hipStream_t st)
+                      const uint16_t* segl, const int32_t* ids, int lpp, bool kernel_w,
+                      uint2* part, unsigned long long* counters, float* pix_t, float* pix_w,
+                      uint32_t* pix_n, hipStream_t st)
 {
     if (!nbuckets) return;
 #define SLAG_COMP(C, W, P, LM)                                                                     \
-    hipLaunchKernelGGL((k_composite<C, W, P, LM>), dim3(nbuckets), dim3(256), 0, st, order, obase, \
+    hipLaunchKernelGGL((k_composite<C, W, P, LM, false>), dim3(nbuckets), dim3(256), 0, st, order,  \
+                       obase,                                                                      \
                        bucket_view, views, bstart, bend, ival, pinfo, rec,                        \
                        ns_tile, segl, ids, lpp,                                                    \
                        part, counters, pix_t, pix_w, pix_n)
@@ -649,8 +756,23 @@ void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t
         default: SLAG_COMP(false, 8, true, LM); break;                                             \
         }                                                                                          \
     } while (0)
-    if (lpp <= 1) SLAG_COMP_V(1);
-    else SLAG_COMP_V(MAX_LABELS);
+    if (kernel_w) {
+        // kernel weights: the occupancy-8, cut-groups shape only (no tuning)
+#define SLAG_COMP_K(C, LM)                                                                         \
+    hipLaunchKernelGGL((k_composite<C, 8, false, LM, true>), dim3(nbuckets), dim3(256), 0, st,     \
+                       order, obase, bucket_view, views, bstart, bend, ival, pinfo, rec, ns_tile,  \
+                       segl, ids, lpp, part, counters, pix_t, pix_w, pix_n)
+        if (count) {
+            if (lpp <= 1) SLAG_COMP_K(true, 1); else SLAG_COMP_K(true, MAX_LABELS);
+        } else {
+            if (lpp <= 1) SLAG_COMP_K(false, 1); else SLAG_COMP_K(false, MAX_LABELS);
+        }
+#undef SLAG_COMP_K
+    } else if (lpp <= 1) {
+        SLAG_COMP_V(1);
+    } else {
+        SLAG_COMP_V(MAX_LABELS);
+    }
 #undef SLAG_COMP_V
 #undef SLAG_COMP
 }

@@ -30,6 +30,7 @@ slag_status ensure(slag_ctx* c, DevBuf& b, size_t bytes)
         hipFree(b.p);
         b.p = nullptr;
         b.cap = 0;
+        c->gen++;   // a recorded graph may hold the old address
     }
     size_t want = bytes + bytes / 8 + 256;
     hipError_t e = hipMalloc(&b.p, want);
@@ -202,6 +203,85 @@ static slag_status morton_order(slag_ctx* c, int64_t n)
 
 // ---------------------------------------------------------------- view plan
 
+// One launch of views [v0, v0 + nb): per-view constants, tile buckets and
+// resolution classes, uploaded.  seg_off[v] = the first segment of view v.
+static slag_status make_batch(slag_ctx* c, int v0, int nb, int lbits,
+                              const std::vector<uint64_t>& seg_off, Batch& b)
+{
+    b.v0 = v0;
+    b.nb = nb;
+    b.lbits = lbits;
+    std::vector<ViewDev> vd(b.nb);
+    std::vector<uint32_t> bv;
+    uint32_t tb = 0, so = 0;
+    for (int i = 0; i < b.nb; i++) {
+        const slag_camera& cam = c->cams[v0 + i];
+        ViewDev& x = vd[i];
+        x.fx = cam.fx; x.fy = cam.fy; x.cx = cam.cx; x.cy = cam.cy;
+        std::memcpy(x.R, cam.R, sizeof(x.R));
+        std::memcpy(x.t, cam.t, sizeof(x.t));
+        x.W = cam.width; x.H = cam.height;
+        // guard clamp, same FP32 operations as the CPU decision path
+        const RasterConsts& K = c->rc;
+        volatile float hw = 0.5f * (float)cam.width, hh = 0.5f * (float)cam.height;
+        volatile float tanx = hw / cam.fx, tany = hh / cam.fy;
+        x.limx = K.guard * tanx;
+        x.limy = K.guard * tany;
+        x.near_z = K.near_z;
+        x.dil = K.dil;
+        x.rho2 = K.rho2;
+        x.amin = K.amin;
+        x.amax = K.amax;
+        x.tmin = K.tmin;
+        x.l2amin = K.l2amin;
+        x.guard_d = K.guard_d;
+        x.dil_d = K.dil_d;
+        x.ntx = (cam.width + TILE - 1) / TILE;
+        x.nty = (cam.height + TILE - 1) / TILE;
+        x.tile_base = tb;
+        x.sat_off = so;
+        x.pix_off = c->pix_off[v0 + i];
+        x.seg_off = (uint32_t)seg_off[v0 + i];
+        x.nseg = (uint32_t)c->nseg[v0 + i];
+        const uint32_t nt = (uint32_t)(x.ntx * x.nty);
+        bv.insert(bv.end(), nt, (uint32_t)i);
+        tb += nt;
+        so += (uint32_t)((x.ntx + 1) * (x.nty + 1));
+    }
+    b.nbuckets = tb;
+    b.nsat = so;
+    // resolution classes
+    std::vector<uint8_t> vcls(b.nb);
+    for (int i = 0; i < b.nb; i++) {
+        const uint32_t W = (uint32_t)vd[i].W, H = (uint32_t)vd[i].H;
+        int k = 0;
+        while (k < b.ncls && !(b.cls_w[k] == W && b.cls_h[k] == H)) k++;
+        if (k == b.ncls) {
+            if (b.ncls < 256) {
+                b.cls_w.push_back(W);
+                b.cls_h.push_back(H);
+                b.cls_nb.push_back(0);
+                b.ncls++;
+            } else {
+                k = 255;   // beyond 256 sizes: share the last class
+            }
+        }
+        vcls[i] = (uint8_t)k;
+        b.cls_nb[k] += (uint32_t)(vd[i].ntx * vd[i].nty);
+    }
+    b.cls_off.assign(b.ncls + 1, 0);
+    for (int k = 0; k < b.ncls; k++) b.cls_off[k + 1] = b.cls_off[k] + b.cls_nb[k];
+    CK(ensure(c, b.view_cls, vcls.size() + 16));
+    HC(c, hipMemcpy(b.view_cls.p, vcls.data(), vcls.size(), hipMemcpyHostToDevice));
+    CK(ensure(c, b.views, vd.size() * sizeof(ViewDev)));
+    CK(ensure(c, b.bucket_view, bv.size() * sizeof(uint32_t)));
+    HC(c, hipMemcpy(b.views.p, vd.data(), vd.size() * sizeof(ViewDev), hipMemcpyHostToDevice));
+    if (!bv.empty())
+        HC(c, hipMemcpy(b.bucket_view.p, bv.data(), bv.size() * sizeof(uint32_t),
+                        hipMemcpyHostToDevice));
+    return SLAG_OK;
+}
+
 static slag_status build_plan(slag_ctx* c)
 {
     for (auto& b : c->plan) { release(b.views); release(b.bucket_view); release(b.view_cls); }
@@ -228,77 +308,7 @@ static slag_status build_plan(slag_ctx* c)
     for (int v = 0; v < V; v++) seg_off[v + 1] = seg_off[v] + (uint64_t)c->nseg[v];
     for (int v0 = 0; v0 < V; v0 += maxv) {
         Batch b;
-        b.v0 = v0;
-        b.nb = std::min(maxv, V - v0);
-        b.lbits = lbits;
-        std::vector<ViewDev> vd(b.nb);
-        std::vector<uint32_t> bv;
-        uint32_t tb = 0, so = 0;
-        for (int i = 0; i < b.nb; i++) {
-            const slag_camera& cam = c->cams[v0 + i];
-            ViewDev& x = vd[i];
-            x.fx = cam.fx; x.fy = cam.fy; x.cx = cam.cx; x.cy = cam.cy;
-            std::memcpy(x.R, cam.R, sizeof(x.R));
-            std::memcpy(x.t, cam.t, sizeof(x.t));
-            x.W = cam.width; x.H = cam.height;
-            // guard clamp, same FP32 operations as the CPU decision path
-            const RasterConsts& K = c->rc;
-            volatile float hw = 0.5f * (float)cam.width, hh = 0.5f * (float)cam.height;
-            volatile float tanx = hw / cam.fx, tany = hh / cam.fy;
-            x.limx = K.guard * tanx;
-            x.limy = K.guard * tany;
-            x.near_z = K.near_z;
-            x.dil = K.dil;
-            x.rho2 = K.rho2;
-            x.amin = K.amin;
-            x.amax = K.amax;
-            x.tmin = K.tmin;
-            x.l2amin = K.l2amin;
-            x.guard_d = K.guard_d;
-            x.dil_d = K.dil_d;
-            x.ntx = (cam.width + TILE - 1) / TILE;
-            x.nty = (cam.height + TILE - 1) / TILE;
-            x.tile_base = tb;
-            x.sat_off = so;
-            x.pix_off = c->pix_off[v0 + i];
-            x.seg_off = (uint32_t)seg_off[v0 + i];
-            x.nseg = (uint32_t)c->nseg[v0 + i];
-            const uint32_t nt = (uint32_t)(x.ntx * x.nty);
-            bv.insert(bv.end(), nt, (uint32_t)i);
-            tb += nt;
-            so += (uint32_t)((x.ntx + 1) * (x.nty + 1));
-        }
-        b.nbuckets = tb;
-        b.nsat = so;
-        // resolution classes
-        std::vector<uint8_t> vcls(b.nb);
-        for (int i = 0; i < b.nb; i++) {
-            const uint32_t W = (uint32_t)vd[i].W, H = (uint32_t)vd[i].H;
-            int k = 0;
-            while (k < b.ncls && !(b.cls_w[k] == W && b.cls_h[k] == H)) k++;
-            if (k == b.ncls) {
-                if (b.ncls < 256) {
-                    b.cls_w.push_back(W);
-                    b.cls_h.push_back(H);
-                    b.cls_nb.push_back(0);
-                    b.ncls++;
-                } else {
-                    k = 255;   // beyond 256 sizes: share the last class
-                }
-            }
-            vcls[i] = (uint8_t)k;
-            b.cls_nb[k] += (uint32_t)(vd[i].ntx * vd[i].nty);
-        }
-        b.cls_off.assign(b.ncls + 1, 0);
-        for (int k = 0; k < b.ncls; k++) b.cls_off[k + 1] = b.cls_off[k] + b.cls_nb[k];
-        CK(ensure(c, b.view_cls, vcls.size() + 16));
-        HC(c, hipMemcpy(b.view_cls.p, vcls.data(), vcls.size(), hipMemcpyHostToDevice));
-        CK(ensure(c, b.views, vd.size() * sizeof(ViewDev)));
-        CK(ensure(c, b.bucket_view, bv.size() * sizeof(uint32_t)));
-        HC(c, hipMemcpy(b.views.p, vd.data(), vd.size() * sizeof(ViewDev), hipMemcpyHostToDevice));
-        if (!bv.empty())
-            HC(c, hipMemcpy(b.bucket_view.p, bv.data(), bv.size() * sizeof(uint32_t),
-                            hipMemcpyHostToDevice));
+        CK(make_batch(c, v0, std::min(maxv, V - v0), lbits, seg_off, b));
         c->plan.push_back(b);
     }
     c->plan_views = V;
@@ -374,10 +384,15 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
     CK(ensure(c, c->ns_tile, (size_t)B.nbuckets * 4));
     CK(ensure(c, c->segl, (size_t)B.nbuckets * TILE_PIX * 2));
     CK(ensure(c, c->sat, (size_t)B.nsat * 4));
-    launch_tile_segs(B.nbuckets, B.bucket_view.as<uint32_t>(), views, c->ids.as<int32_t>(), c->lpp,
-                     c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
-                     reinterpret_cast<unsigned long long*>(small + SM_LERR), st);
-    launch_sat(nb, views, c->ns_tile.as<uint32_t>(), c->sat.as<uint32_t>(), st);
+    if (c->front_only) {
+        // render-back: no segments, so no part slots
+        launch_fill_u32(c->sat.as<uint32_t>(), B.nsat, 0u, st);
+    } else {
+        launch_tile_segs(B.nbuckets, B.bucket_view.as<uint32_t>(), views, c->ids.as<int32_t>(),
+                         c->lpp, c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
+                         reinterpret_cast<unsigned long long*>(small + SM_LERR), st);
+        launch_sat(nb, views, c->ns_tile.as<uint32_t>(), c->sat.as<uint32_t>(), st);
+    }
     CK(stage_end(c, ST_TILES, ev));
 
     // projection: count, compact, records
@@ -469,6 +484,10 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
 
     const uint32_t* skey = nullptr;
     const uint32_t* sval = nullptr;
+    if (c->front_only && !npairs) {
+        c->front_ival = nullptr;   // nothing visible: no lists
+        return SLAG_OK;
+    }
     if (npairs) {
         // depth order of pairs within each view
         CK(stage_begin(c, ST_DEPTH_SORT, &ev));
@@ -556,6 +575,11 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         launch_fill_u32(c->bend.as<uint32_t>(), B.nbuckets, 0u, st);
         launch_bucket_ranges(ni, skey, views, B.lbits, c->bstart.as<uint32_t>(),
                              c->bend.as<uint32_t>(), st);
+        if (c->front_only) {
+            CK(stage_end(c, ST_TILE_SORT, ev));
+            c->front_ival = sval;
+            return SLAG_OK;
+        }
         // dispatch order of the compositing workgroups: longest lists first
         CK(ensure(c, c->bkey, (size_t)B.nbuckets * 4 + 4));
         CK(ensure(c, c->bkey_alt, (size_t)B.nbuckets * 4 + 4));
@@ -604,7 +628,8 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         // tuning: time every variant of each untuned size (each run starts
         // from empty part lists), then composite every size once for real
         bool tuned_now = false;
-        for (int k = 0; k < B.ncls && (c->opt.flags & SLAG_FLAG_AUTOTUNE) && !c->capturing && !count;
+        for (int k = 0; k < B.ncls && (c->opt.flags & SLAG_FLAG_AUTOTUNE) && !c->capturing && !count &&
+                        !c->kernel_w;
              k++) {
             if (!B.cls_nb[k]) continue;
             const uint64_t key = ((uint64_t)B.cls_w[k] << 32) | B.cls_h[k];
@@ -615,7 +640,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
                                  B.bucket_view.as<uint32_t>(), views, c->bstart.as<uint32_t>(),
                                  c->bend.as<uint32_t>(), sval, c->pinfo.as<uint2>(), c->rec.as<float4>(),
                                  c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
-                                 c->ids.as<int32_t>(), c->lpp, c->part.as<uint2>(),
+                                 c->ids.as<int32_t>(), c->lpp, c->kernel_w, c->part.as<uint2>(),
                                  reinterpret_cast<unsigned long long*>(small + SM_COUNTERS),
                                  nullptr, nullptr, nullptr, st);
             };
@@ -633,7 +658,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
                                  B.bucket_view.as<uint32_t>(), views, c->bstart.as<uint32_t>(),
                                  c->bend.as<uint32_t>(), sval, c->pinfo.as<uint2>(), c->rec.as<float4>(),
                                  c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
-                                 c->ids.as<int32_t>(), c->lpp, c->part.as<uint2>(),
+                                 c->ids.as<int32_t>(), c->lpp, c->kernel_w, c->part.as<uint2>(),
                                  reinterpret_cast<unsigned long long*>(small + SM_COUNTERS),
                                  pix_t, pix_w, pix_n, st);
             };
@@ -712,6 +737,11 @@ slag_status slag_create(int32_t device, void* hip_stream, const slag_options* op
             return SLAG_E_INVALID_ARG;
         }
         c->lpp = o.labels_per_pixel > 0 ? o.labels_per_pixel : 1;
+        if (o.weight_mode != 0 && o.weight_mode != 1) {
+            delete c;
+            return SLAG_E_INVALID_ARG;
+        }
+        c->kernel_w = o.weight_mode == 1;
         RasterConsts& K = c->rc;
         K.amax = amax;
         K.amin = amin;
@@ -767,7 +797,8 @@ void slag_destroy(slag_ctx* c)
                       &c->outbf, &c->idstage, &c->bgeo, &c->vlist, &c->vcnt, &c->cnum, &c->cden, &c->cbf,
                       &c->query.emb, &c->query.q, &c->query.qt, &c->query.counts,
                       &c->query.keys, &c->query.vals, &c->query.keys_alt, &c->query.vals_alt,
-                      &c->query.hist, &c->query.scan_ws};
+                      &c->query.hist, &c->query.scan_ws, &c->rattr, &c->rout,
+                      &c->rbatch.views, &c->rbatch.bucket_view, &c->rbatch.view_cls};
     destroy_graph(c);
     for (DevBuf* b : bufs) release(*b);
     codec_release(c);
@@ -1482,4 +1513,76 @@ extern "C" slag_status slag_get_debug(slag_ctx* c, slag_debug what, int32_t view
     default:
         FAIL(c, SLAG_E_INVALID_ARG, "unknown debug export");
     }
+}
+
+// Render-back: one launch of the single view through projection, depth sort,
+// binning and tile ranges (no segments), then the attribute walk.
+extern "C" slag_status slag_render(slag_ctx* c, int32_t view, const float* attr, int32_t C,
+                                   slag_mem attr_where, float* out, float* wsum,
+                                   slag_mem out_where)
+{
+    if (!c) return SLAG_E_INVALID_ARG;
+    c->err.clear();
+    if (c->n < 0) FAIL(c, SLAG_E_STATE, "Gaussians not set");
+    if (c->nviews < 0) FAIL(c, SLAG_E_STATE, "cameras not set");
+    if (view < 0 || view >= c->nviews) FAIL(c, SLAG_E_INVALID_ARG, "view out of range");
+    if (C < 1 || C > 1024) FAIL(c, SLAG_E_INVALID_ARG, "1 to 1024 attribute channels");
+    if ((c->n > 0 && !attr) || !out) FAIL(c, SLAG_E_INVALID_ARG, "null attribute or output pointer");
+    if ((attr_where != SLAG_HOST && attr_where != SLAG_DEVICE) ||
+        (out_where != SLAG_HOST && out_where != SLAG_DEVICE))
+        FAIL(c, SLAG_E_INVALID_ARG, "bad memory kind");
+    HC(c, hipSetDevice(c->device));
+    hipStream_t st = c->st;
+    const slag_camera& cam = c->cams[view];
+    const int64_t npix = (int64_t)cam.width * cam.height;
+    const int64_t ntiles = (int64_t)((cam.width + TILE - 1) / TILE) * ((cam.height + TILE - 1) / TILE);
+    const int lbits = std::max(1, bit_length((uint64_t)std::max<int64_t>(ntiles - 1, 0)));
+    if (lbits > 31) FAIL(c, SLAG_E_CAPACITY, "image too large for 32-bit tile keys");
+    float* dout = out;
+    float* dws = wsum;
+    if (out_where == SLAG_HOST) {
+        CK(ensure(c, c->rout, (size_t)npix * (size_t)(C + 1) * 4 + 16));
+        dout = c->rout.as<float>();
+        dws = dout + (size_t)npix * C;
+    }
+    const float* dattr = attr;
+    if (attr_where == SLAG_HOST && c->n > 0) {
+        CK(ensure(c, c->rattr, (size_t)c->n * C * 4));
+        HC(c, hipMemcpyAsync(c->rattr.p, attr, (size_t)c->n * C * 4, hipMemcpyHostToDevice, st));
+        dattr = c->rattr.as<float>();
+    }
+    release(c->rbatch.views);
+    release(c->rbatch.bucket_view);
+    release(c->rbatch.view_cls);
+    c->rbatch = Batch();
+    const std::vector<uint64_t> seg_off((size_t)c->nviews + 1, 0);   // no segments
+    CK(make_batch(c, view, 1, lbits, seg_off, c->rbatch));
+    // the shared list buffers are rewritten: the last lift's debug exports go
+    const slag_stats keep = c->stats;
+    const int32_t flags = c->opt.flags;
+    c->opt.flags &= ~SLAG_FLAG_PROFILE;
+    c->front_only = true;
+    c->front_ival = nullptr;
+    c->last_v0 = -1;
+    ContractTarget ct{};
+    const slag_status s = c->n > 0 ? lift_batch(c, c->rbatch, true, true, ct) : SLAG_OK;
+    c->front_only = false;
+    c->opt.flags = flags;
+    c->stats = keep;
+    if (s != SLAG_OK) return s;
+    if (c->front_ival) {
+        launch_render(c->kernel_w, (int)ntiles, c->rbatch.views.as<ViewDev>(), 0,
+                      c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(), c->front_ival,
+                      c->rec.as<float4>(), c->pgauss.as<uint32_t>(), dattr, C, dout, dws, st);
+    } else {
+        launch_fill_u32(reinterpret_cast<uint32_t*>(dout), (uint64_t)npix * C, 0u, st);
+        if (dws) launch_fill_u32(reinterpret_cast<uint32_t*>(dws), (uint64_t)npix, 0u, st);
+    }
+    HC(c, hipGetLastError());
+    if (out_where == SLAG_HOST) {
+        HC(c, hipMemcpyAsync(out, dout, (size_t)npix * C * 4, hipMemcpyDeviceToHost, st));
+        if (wsum) HC(c, hipMemcpyAsync(wsum, dws, (size_t)npix * 4, hipMemcpyDeviceToHost, st));
+    }
+    HC(c, hipStreamSynchronize(st));
+    return SLAG_OK;
 }

@@ -114,6 +114,7 @@ struct slag_ctx {
     slag_host::DevBuf ids;            // [pixels][lpp] segment ids, -1 = none
     slag_host::DevBuf idstage;        // host ids staged for widening to lpp labels
     int lpp = 1;                      // labels per pixel (slag_options.labels_per_pixel)
+    bool kernel_w = false;            // weights are Gaussian kernel values (slag_options.weight_mode)
 
     int d = 0;
     slag_dtype fdt = SLAG_F32;
@@ -156,6 +157,11 @@ struct slag_ctx {
     uint64_t graph_gen = 0;           // generation the graph was captured for
     int graph_mode = -1;              // 0 plain, 1 codec
     bool capturing = false;
+    // render-back: the launch runs projection through the tile ranges only
+    bool front_only = false;
+    const uint32_t* front_ival = nullptr;   // its sorted list entries (pairs)
+    slag_host::Batch rbatch;                 // its one-view launch
+    slag_host::DevBuf rattr, rout;           // staged host attributes / outputs
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     slag_stats graph_stats{};

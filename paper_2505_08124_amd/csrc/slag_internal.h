@@ -179,9 +179,16 @@ void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t
                       uint32_t obase, const uint32_t* bucket_view, const ViewDev* views,
                       const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
                       uint2* pinfo, const float4* rec, const uint32_t* ns_tile,
-                      const uint16_t* segl, const int32_t* ids, int lpp, uint2* part,
-                      unsigned long long* counters, float* pix_t, float* pix_w, uint32_t* pix_n,
-                      hipStream_t st);
+                      const uint16_t* segl, const int32_t* ids, int lpp, bool kernel_w,
+                      uint2* part, unsigned long long* counters, float* pix_t, float* pix_w,
+                      uint32_t* pix_n, hipStream_t st);
+// Render-back of attr [N][C] (caller's Gaussian order) into view vi of the
+// last launch: out [H][W][C] = sum w a / sum w per pixel (0 where no weight),
+// wsum [H][W] (may be null); ntiles = the view's tile count.
+void launch_render(bool kernel_w, int ntiles, const ViewDev* views, int vi, const uint32_t* bstart,
+                   const uint32_t* bend, const uint32_t* ival, const float4* rec,
+                   const uint32_t* pgauss, const float* attr, int C, float* out, float* wsum,
+                   hipStream_t st);
 // out[i] = bfloat16(in[i]) (round to nearest even), as bit patterns
 void launch_f32_to_bf16(uint64_t n, const float* in, uint16_t* out, hipStream_t st);
 void launch_merge(uint64_t npairs, const uint16_t* pview, const ViewDev* views, const uint2* pinfo,

@@ -462,3 +462,124 @@ def test_two_full_masks_average_their_features():
     want = (f[0].astype(np.float64) + f[1].astype(np.float64)) / 2
     for g in range(2):
         np.testing.assert_allclose(ref.E[g], want, rtol=0, atol=1e-15)
+
+
+def test_kernel_weights_closed_form():
+    """weight_mode = 1 (the paper's weight equation): every Gaussian the walk
+    blends gets w = exp(-q/2), its kernel value, independent of opacity and of
+    the Gaussians in front; the contributing set is the walk's (alpha >= 1/255,
+    before the stop)."""
+    sc = _axis_scene([(4.0, [0.5, 0.4, 0.1], 0.8), (2.0, [0.15, 0.25, 0.1], 0.9)])
+    with oracle.constants(weight_mode=1.0):
+        r = oracle.lift_view(sc, 0)
+    u, v = np.meshgrid(np.arange(32) + 0.5, np.arange(32) + 0.5)
+    for g in (0, 1):
+        sxx, syy = _screen_diag(sc, g)
+        kv = np.exp(-0.5 * ((u - 16.0) ** 2 / sxx + (v - 16.0) ** 2 / syy)).ravel()
+        a = float(sc.opacity[g]) * kv
+        exp = np.where(np.minimum(0.99, a) >= 1 / 255, kv, 0.0)
+        np.testing.assert_allclose(_dense_w(r, g, 1024), exp, rtol=1e-12, atol=0)
+    # the back Gaussian's kernel weight is not reduced by the front one
+    assert _dense_w(r, 0, 1024).max() > 0.9
+
+
+def test_kernel_weights_fp32_rewalk_within_bound():
+    """The FP32 re-walk with kernel weights stays within the oracle's
+    rounding and decision masses."""
+    sc = make_scene_small()
+    with oracle.constants(weight_mode=1.0):
+        r64 = oracle.lift_view(sc, 0)
+        r32 = oracle.lift_view(sc, 0, fp32=True)
+    k64 = r64.g.astype(np.int64) << 32 | r64.s.astype(np.int64)
+    k32 = r32.g.astype(np.int64) << 32 | r32.s.astype(np.int64)
+    allk = np.union1d(k64, k32)
+    W64, W32, B = np.zeros(allk.size), np.zeros(allk.size), np.full(allk.size, oracle.SUM_ABS)
+    i64 = np.searchsorted(allk, k64)
+    W64[i64] = r64.w
+    B[i64] = oracle.weight_bound(r64.w, r64.u, r64.r)
+    W32[np.searchsorted(allk, k32)] = r32.w
+    assert np.all(np.abs(W32 - W64) <= B), (np.abs(W32 - W64) / B).max()
+
+
+# --------------------------------------------------------------------------
+# render-back (Method, the rendering equation with the lift's weights)
+
+def test_render_two_gaussian_closed_form():
+    """Two Gaussians on the optical axis: out = (w_f a_f + w_b a_b) /
+    (w_f + w_b) with w_f = alpha_f, w_b = alpha_b (1 - alpha_f) (each where it
+    reaches 1/255), 0 where neither blends."""
+    sc = _axis_scene([(4.0, [0.5, 0.4, 0.1], 0.8), (2.0, [0.15, 0.25, 0.1], 0.9)])
+    attr = np.array([[1.0, -2.0, 0.5], [3.0, 0.25, -1.0]], np.float32)
+    rr = oracle.render_view(sc, 0, attr)
+    u, v = np.meshgrid(np.arange(32) + 0.5, np.arange(32) + 0.5)
+    ab = _alpha(float(sc.opacity[0]), u - 16.0, v - 16.0, *_screen_diag(sc, 0))
+    af = _alpha(float(sc.opacity[1]), u - 16.0, v - 16.0, *_screen_diag(sc, 1))
+    af = np.where(af >= 1 / 255, af, 0.0)
+    wb = np.where(ab >= 1 / 255, ab * (1 - af), 0.0)
+    ws = af + wb
+    a = attr.astype(np.float64)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        want = np.where(ws[..., None] > 0,
+                        (af[..., None] * a[1] + wb[..., None] * a[0]) / ws[..., None], 0.0)
+    np.testing.assert_allclose(rr.wsum, ws, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(rr.out, want, rtol=1e-12, atol=1e-15)
+    assert (ws == 0).any() and (af > 0.5).any() and (wb > 0).sum() > 100
+
+
+def _random_small_scene(seed, n=300, w=48, h=40):
+    rng = np.random.default_rng(seed)
+    means = np.c_[rng.uniform(-1.2, 1.2, n), rng.uniform(-1.0, 1.0, n), rng.uniform(2.0, 5.0, n)]
+    scales = rng.uniform(0.03, 0.25, (n, 3))
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    ops = rng.uniform(0.05, 0.99, n)
+    ids = _pixel_ids(w, h)
+    return make_custom_scene(means, scales, q, ops, [_cam(w, h, 40.0)], [ids],
+                             _unit_feats(w * h, 4, seed))
+
+
+@pytest.mark.parametrize("kernel", [False, True])
+def test_render_is_the_lift_weights_per_pixel(kernel):
+    """With one segment per pixel the lift's W_v[g, p] is the weight of
+    Gaussian g at pixel p, so the render must equal sum_g W[g, p] a_g /
+    sum_g W[g, p] at every pixel, with wsum = sum_g W[g, p] (alpha T weights
+    and kernel weights); constant attributes render as that constant wherever
+    something blends."""
+    sc = _random_small_scene(11)
+    n, npix = sc.n, 48 * 40
+    attr = np.random.default_rng(5).standard_normal((n, 5)).astype(np.float32)
+    attr[:, 4] = 0.625
+    with oracle.constants(weight_mode=1.0 if kernel else 0.0):
+        r = oracle.lift_view(sc, 0)
+        rr = oracle.render_view(sc, 0, attr)
+    Wd = np.zeros((npix, n))
+    Wd[r.s, r.g] = r.w
+    ws = Wd.sum(axis=1)
+    num = Wd @ attr.astype(np.float64)
+    want = np.where(ws[:, None] > 0, num / np.where(ws > 0, ws, 1.0)[:, None], 0.0)
+    np.testing.assert_allclose(rr.wsum.ravel(), ws, rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(rr.out.reshape(npix, 5), want, rtol=1e-10, atol=1e-12)
+    lit = ws > 0
+    assert lit.mean() > 0.5 and (~lit).any()
+    np.testing.assert_allclose(rr.out.reshape(npix, 5)[lit, 4], 0.625, rtol=1e-13)
+    assert np.all(rr.nb.ravel()[lit] >= 1) and np.all(rr.bw >= 0)
+
+
+def test_render_bound_shape():
+    """The render bound is finite where a pixel's certain weight dominates,
+    infinite where nothing blends, and grows with the weights' deviation."""
+    sc = _random_small_scene(12)
+    attr = np.random.default_rng(6).standard_normal((sc.n, 3)).astype(np.float32)
+    rr = oracle.render_view(sc, 0, attr)
+    amax = np.abs(attr).max(axis=0)
+    b = oracle.render_bound(rr, amax)
+    assert np.all(np.isinf(b[rr.wsum == 0]))
+    lit = rr.wsum > 1e-3
+    assert np.all(np.isfinite(b[lit])) and np.median(b[lit] / amax) < 1e-4
+    rr2 = oracle.RenderResult(rr.out, rr.wsum, rr.bw * 10 + 1e-9, rr.nb)
+    assert np.all(oracle.render_bound(rr2, amax)[lit] > b[lit])
+
+
+def make_scene_small():
+    from synthetic import make_scene
+    return make_scene("plain_bf16_200k", n=20000, views=dict(n=1))
