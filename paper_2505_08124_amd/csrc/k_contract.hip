@@ -32,6 +32,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int KC = 32;          // K columns per chunk
 
@@ -45,6 +46,8 @@ constexpr float kFx = 1099511627776.0f;          // 2^40
 constexpr float kFxInv = 1.0f / 1099511627776.0f;
 __device__ __forceinline__ int64_t to_fx(float w) { return (int64_t)(w * kFx); }
 __device__ __forceinline__ float from_fx(int64_t x) { return (float)x * kFxInv; }
+// Blocks per XCD chunk of the contraction's launch order (0: plain order).
+constexpr int kXcdChunk = 16;
 constexpr int kContractRT = 1;  // row tiles per block (G = 16 Gaussians; 2 and 4 measured slower)
 
 // G = 16 RT rows per block; thread t walks row t % G and views
@@ -52,7 +55,7 @@ constexpr int kContractRT = 1;  // row tiles per block (G = 16 Gaussians; 2 and 
 constexpr int VPT = 2;
 // Part-list entries of one step staged in LDS (a step with more reads them
 // from global memory in both passes); SU loads per thread in flight.
-constexpr int STAGE = 3072;
+constexpr int STAGE = 2048;
 constexpr int SU = 4;
 template <int RT>
 struct BlockLds {
@@ -62,13 +65,28 @@ struct BlockLds {
     uint32_t ks[KMAX];          // feature row of each column of the round
     int64_t A[G][KMAX + 1];     // weights of the round's columns, fixed point
     float dpart[GV][G];         // per-view row weight sums of the step
+    uint64_t dfx[GV][G];        //   the same, fixed point
     uint32_t scan[8];
-    // the step's part-list entries, staged once (both passes read them)
+    // the step's part-list entries, staged once (both passes read them),
+    // with their owner (view slot G + row)
     uint2 stage[STAGE];
+    uint16_t sown[STAGE];
     uint32_t soff[256];         // first staged entry of each thread
     uint32_t spb[256][VPT];     // list base and length of each thread's pairs
     uint32_t scnt[256][VPT];
 };
+
+// Output column of lane m (of 16) in column tile i of a wave whose first
+// column is c0.  BF16 features, NT = 12 or 16 (D = 768, 1024): lane m holds the
+// four consecutive columns c0 + 64 (i / 4) + 4 m + (0 .. 3) of tiles
+// 4 (i / 4) .. + 3, so that one 8-byte load of a feature row feeds four
+// tiles; else tile i is columns c0 + 16 i + (0 .. 15).
+template <int NT, bool BF16>
+__device__ __forceinline__ int tile_col(int c0, int i, int m)
+{
+    if constexpr (BF16 && NT >= 12 && NT % 4 == 0) return c0 + 64 * (i >> 2) + 4 * m + (i & 3);
+    else return c0 + 16 * i + m;
+}
 
 // Multiply columns [k0, k0 + kn) of the staged round into the accumulators
 // acc[r][t] (row tile r, column tile t).
@@ -77,7 +95,60 @@ __device__ __forceinline__ void mfma_chunk(const BlockLds<RT>& L, int k0, int kn
                                            int d, int c0, floatx4 (*acc)[NT], int lane)
 {
     const int m = lane & 15, kq = lane >> 4;
-    if constexpr (BF16) {
+    if constexpr (BF16 && NT >= 12 && NT % 4 == 0) {
+        // the chunk's feature loads in batches of GF groups of four columns
+        // (8 K rows x 8 bytes per group), each batch in flight at once (rows
+        // past kn are not read); GF keeps the batch within the registers
+        // the occupancy leaves
+        constexpr int NG = NT / 4;
+        constexpr int GF = NT == 12 ? 3 : 1;
+        bf16x8 ahi[RT], alo[RT];
+        const uint2* rp[8];
+        const uint16_t* F = reinterpret_cast<const uint16_t*>(feats) + c0 + 4 * m;
+        uint32_t live = 0;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const int k = 8 * kq + j;
+            live |= (k < kn ? 1u : 0u) << j;
+            rp[j] = reinterpret_cast<const uint2*>(F + (size_t)(k < kn ? L.ks[k0 + k] : 0u) * d);
+#pragma unroll
+            for (int r = 0; r < RT; r++) {
+                const float a = k < kn ? from_fx(L.A[16 * r + m][k0 + k]) : 0.0f;
+                const __bf16 h = (__bf16)a;
+                ahi[r][j] = h;
+                alo[r][j] = (__bf16)(a - (float)h);
+            }
+        }
+#pragma unroll
+        for (int g0 = 0; g0 < NG; g0 += GF) {
+            uint2 raw[8][GF];
+#pragma unroll
+            for (int j = 0; j < 8; j++)
+#pragma unroll
+                for (int gg = 0; gg < GF; gg++)
+                    raw[j][gg] = ((live >> j) & 1u) ? rp[j][16 * (g0 + gg)] : make_uint2(0u, 0u);
+#pragma unroll
+            for (int gg = 0; gg < GF; gg++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    u32x4 w;
+#pragma unroll
+                    for (int jj = 0; jj < 4; jj++) {
+                        const uint32_t x0 = (e < 2) ? raw[2 * jj][gg].x : raw[2 * jj][gg].y;
+                        const uint32_t x1 = (e < 2) ? raw[2 * jj + 1][gg].x : raw[2 * jj + 1][gg].y;
+                        w[jj] = (e & 1) ? ((x0 >> 16) | (x1 & 0xFFFF0000u)) : ((x0 & 0xFFFFu) | (x1 << 16));
+                    }
+                    const bf16x8 b = __builtin_bit_cast(bf16x8, w);
+                    const int ti = 4 * (g0 + gg) + e;
+#pragma unroll
+                    for (int r = 0; r < RT; r++) {
+                        acc[r][ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[r], b, acc[r][ti], 0, 0, 0);
+                        acc[r][ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[r], b, acc[r][ti], 0, 0, 0);
+                    }
+                }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else if constexpr (BF16) {
         bf16x8 ahi[RT], alo[RT];
         const uint16_t* rowp[8];   // this lane's column in each K row (row 0 stands in for
         uint32_t live = 0;         // unused K slots; their values are replaced by zero)
@@ -165,14 +236,32 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
     const uint16_t* __restrict__ vlist, const uint32_t* __restrict__ vcnt,
     const uint2* __restrict__ pinfo,
     const uint2* __restrict__ part, const void* __restrict__ feats, float* __restrict__ num,
-    float* __restrict__ den, int first, int last, int64_t q_begin, int64_t q_end, int local)
+    float* __restrict__ den, int first, int last, int64_t q_begin, int64_t q_end, int local,
+    const uint32_t* __restrict__ gorder)
 {
     constexpr int G = BlockLds<RT>::G, GT = BlockLds<RT>::GT, GV = BlockLds<RT>::GV;
     __shared__ BlockLds<RT> L;
     const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
     // Morton ranks [q_begin, q_end) (q_begin a multiple of G); output row of
     // rank q: its caller index perm[q], or q - q_begin (local rows of a chunk)
-    const int64_t q0 = q_begin + (int64_t)blockIdx.x * G;  // first Morton rank of the block
+    // Dispatch order: the Gaussian blocks (GBLOCK ranks) of the range,
+    // heaviest first (gorder: by descending visible pair count), so the
+    // blocks with the most views do not form the kernel's tail; inside one,
+    // its GBLOCK / G workgroups in Morton order.  XCD-aware: workgroups are
+    // dealt to the 8 XCDs round-robin; each group of 8 C workgroups gives
+    // XCD x the C consecutive blocks x C .. x C + C - 1 of the group, so
+    // neighbouring blocks (which touch the same segments) share one L2
+    // (the grid is whole groups).
+    constexpr int BPG = GBLOCK / G;
+    int64_t lb = blockIdx.x;
+    if (kXcdChunk > 0) {
+        const int64_t gs = 8 * kXcdChunk, w = lb % gs;
+        lb = lb - w + (w % 8) * kXcdChunk + w / 8;
+    }
+    const int64_t ng = (q_end + GBLOCK - 1) / GBLOCK - q_begin / GBLOCK;
+    if (lb >= ng * BPG) return;
+    const int64_t q0 = (int64_t)gorder[lb / BPG] * GBLOCK + (lb % BPG) * G;  // first Morton rank
+    if (q0 < q_begin || q0 >= q_end) return;
     auto orow = [&](int64_t q) -> int64_t { return local ? q - q_begin : (int64_t)perm[q]; };
     const int c0 = wv * 16 * NT;                          // this wave's first feature column
     const bool wact = c0 < d;                             // (d < 64: waves past d only walk)
@@ -205,7 +294,7 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
 #pragma unroll
                 for (int j = 0; j < 4; j++) {
                     const int64_t q = q0 + 16 * r + 4 * kq + j;
-                    const float x = num[(size_t)gq[r][j] * d + (wact ? c0 + 16 * i + m : 0)];
+                    const float x = num[(size_t)gq[r][j] * d + (wact ? tile_col<NT, BF16>(c0, i, m) : 0)];
                     acc[r][i][j] = (wact && q < q_end) ? x : 0.0f;
                 }
         if (t < G && q0 + t < q_end) dsum = den[orow(q0 + t)];
@@ -245,27 +334,26 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
         // stage the step's entries: thread t's lists go to [soff[t], ...) in
         // pair order; all threads load, SU clamped (always valid) loads each
         // in flight, the owner of entry i found by binary search over soff
-        uint32_t sb[VPT];
         bool staged;
+        uint32_t tot_st = 0;   // entries staged (block-uniform)
         {
             uint32_t ct = 0;
 #pragma unroll
             for (int j = 0; j < VPT; j++) {
-                sb[j] = ct;
                 ct += cnt[j];
                 L.spb[t][j] = pb[j];
                 L.scnt[t][j] = cnt[j];
             }
             uint32_t tot;
             const uint32_t off = block_exscan(ct, L.scan, tot);
-#pragma unroll
-            for (int j = 0; j < VPT; j++) sb[j] += off;
             L.soff[t] = off;
             staged = tot <= (uint32_t)STAGE;
+            tot_st = staged ? tot : 0u;
             __syncthreads();
             if (staged && tot) {
                 for (uint32_t i0 = 0; i0 < tot; i0 += 256 * SU) {
                     uint2 xv[SU];
+                    uint16_t ow[SU];
 #pragma unroll
                     for (int u = 0; u < SU; u++) {
                         const uint32_t i = min(i0 + (uint32_t)(u * 256 + t), tot - 1u);
@@ -280,35 +368,53 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
                         for (int j = 0; j + 1 < VPT; j++)
                             if (jj == j && k >= L.scnt[lo][j]) { k -= L.scnt[lo][j]; jj = j + 1; }
                         xv[u] = part[L.spb[lo][jj] + k];
+                        ow[u] = (uint16_t)((lo / G + GT * jj) * G + lo % G);
                     }
 #pragma unroll
                     for (int u = 0; u < SU; u++) {
                         const uint32_t i = i0 + (uint32_t)(u * 256 + t);
-                        if (i < tot) L.stage[i] = xv[u];
+                        if (i < tot) {
+                            L.stage[i] = xv[u];
+                            L.sown[i] = ow[u];
+                        }
                     }
                 }
                 __syncthreads();
             }
         }
-        // bitmap words: word i covers view v0 + (i >> 3), ids w0 + 32 (i & 7) + [0, 32)
-        int64_t dv[VPT];
-#pragma unroll
-        for (int j = 0; j < VPT; j++) dv[j] = 0;
+        // bitmap words: word i covers view v0 + (i >> 3), ids w0 + 32 (i & 7) + [0, 32).
+        // Staged steps are walked entry by entry (every thread the same
+        // count; same-slot sums by integer LDS atomics, exact in any order),
+        // others list by list.
+        for (int i = t; i < GV * G; i += 256) (&L.dfx[0][0])[i] = 0ull;
         for (uint32_t w0 = 0; __syncthreads_or(w0 < nsv); w0 += 256) {
             for (int i = t; i < GV * 8; i += 256) L.bits[i] = 0;
             __syncthreads();
-            // 1. mark the segments the rows touch (slot order: dv does not
-            //    depend on how columns are cut)
-#pragma unroll
-            for (int j = 0; j < VPT; j++) {
-                const int vw = (vt + GT * j) * 8;
-                for (uint32_t k = 0; k < cnt[j]; k++) {
-                    const uint2 x = staged ? L.stage[sb[j] + k] : part[pb[j] + k];
+            // 1. mark the segments the rows touch, and add the weights into
+            //    the per-view row sums
+            if (staged) {
+                for (uint32_t i = t; i < tot_st; i += 256) {
+                    const uint2 x = L.stage[i];
                     const uint32_t s = (x.x & 0xFFFFu) - w0;
                     const float w = __uint_as_float(x.y);
                     if (s < 256u && w > 0.0f) {
-                        atomicOr(&L.bits[vw + (s >> 5)], 1u << (s & 31));
-                        dv[j] += to_fx(w);
+                        const uint32_t ow = L.sown[i], sl = ow / G;
+                        atomicOr(&L.bits[sl * 8 + (s >> 5)], 1u << (s & 31));
+                        atomicAdd(&L.dfx[sl][ow % G], (unsigned long long)to_fx(w));
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < VPT; j++) {
+                    const int vw = (vt + GT * j) * 8;
+                    for (uint32_t k = 0; k < cnt[j]; k++) {
+                        const uint2 x = part[pb[j] + k];
+                        const uint32_t s = (x.x & 0xFFFFu) - w0;
+                        const float w = __uint_as_float(x.y);
+                        if (s < 256u && w > 0.0f) {
+                            atomicOr(&L.bits[vw + (s >> 5)], 1u << (s & 31));
+                            atomicAdd(&L.dfx[vt + GT * j][row], (unsigned long long)to_fx(w));
+                        }
                     }
                 }
             }
@@ -351,19 +457,37 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
                 }
                 for (int i = t; i < G * (KMAX + 1); i += 256) (&L.A[0][0])[i] = 0;
                 __syncthreads();
-                // 3. weights: each thread adds its pairs' slots into its row
-#pragma unroll
-                for (int j = 0; j < VPT; j++) {
-                    const int vw = (vt + GT * j) * 8;
-                    for (uint32_t k = 0; k < cnt[j]; k++) {
-                        const uint2 x = staged ? L.stage[sb[j] + k] : part[pb[j] + k];
+                // 3. weights into A (entry by entry with integer atomics, or
+                //    each thread its own pairs' lists, which no other
+                //    thread's entries share a (row, column) with)
+                if (staged) {
+                    for (uint32_t i = t; i < tot_st; i += 256) {
+                        const uint2 x = L.stage[i];
                         const uint32_t s = (x.x & 0xFFFFu) - w0;
                         const float w = __uint_as_float(x.y);
                         if (s >= 256u || !(w > 0.0f)) continue;
-                        const int wi = vw + (int)(s >> 5);
+                        const uint32_t ow = L.sown[i];
+                        const int wi = (int)(ow / G) * 8 + (int)(s >> 5);
                         const uint32_t bit = 1u << (s & 31);
                         const uint32_t col = L.wbase[wi] + (uint32_t)__popc(L.bits[wi] & (bit - 1u));
-                        if (col >= kr && col < kr + KMAX) L.A[row][col - kr] += to_fx(w);
+                        if (col >= kr && col < kr + KMAX)
+                            atomicAdd(reinterpret_cast<unsigned long long*>(&L.A[ow % G][col - kr]),
+                                      (unsigned long long)to_fx(w));
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < VPT; j++) {
+                        const int vw = (vt + GT * j) * 8;
+                        for (uint32_t k = 0; k < cnt[j]; k++) {
+                            const uint2 x = part[pb[j] + k];
+                            const uint32_t s = (x.x & 0xFFFFu) - w0;
+                            const float w = __uint_as_float(x.y);
+                            if (s >= 256u || !(w > 0.0f)) continue;
+                            const int wi = vw + (int)(s >> 5);
+                            const uint32_t bit = 1u << (s & 31);
+                            const uint32_t col = L.wbase[wi] + (uint32_t)__popc(L.bits[wi] & (bit - 1u));
+                            if (col >= kr && col < kr + KMAX) L.A[row][col - kr] += to_fx(w);
+                        }
                     }
                 }
                 __syncthreads();
@@ -376,8 +500,8 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
             }
         }
         // row weight sums, views in order
-#pragma unroll
-        for (int j = 0; j < VPT; j++) L.dpart[vt + GT * j][row] = from_fx(dv[j]);
+        for (int i = t; i < GV * G; i += 256)
+            (&L.dpart[0][0])[i] = from_fx((int64_t)(&L.dfx[0][0])[i]);
         __syncthreads();
         if (t < G) {
             const int nv = min(GV, nvb - v0);
@@ -400,7 +524,7 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
 #pragma unroll
             for (int i = 0; i < NT; i++) {
                 const float a = acc[r][i][j];
-                num[(size_t)g * d + c0 + 16 * i + m] = last ? (dn > 0.0f ? a / dn : 0.0f) : a;
+                num[(size_t)g * d + tile_col<NT, BF16>(c0, i, m)] = last ? (dn > 0.0f ? a / dn : 0.0f) : a;
             }
         }
     if (t < G && q0 + t < q_end) den[orow(q0 + t)] = dsum;
@@ -410,50 +534,69 @@ template <int NT, int RT>
 void launch_nt(int64_t n, int nb, int d, bool bf16, const uint32_t* perm, const uint32_t* pair_of_m,
                const ViewDev* views, const uint16_t* vlist, const uint32_t* vcnt, const uint2* pinfo,
                const uint2* part, const void* feats, float* num, float* den, bool first, bool last,
-               int64_t q_begin, int64_t q_end, bool local, hipStream_t st)
+               int64_t q_begin, int64_t q_end, bool local, const uint32_t* gorder, hipStream_t st)
 {
     constexpr int G = 16 * RT;
     static_assert(GBLOCK % G == 0, "contraction blocks lie inside one Gaussian block");
-    const dim3 grid((unsigned)((q_end - q_begin + G - 1) / G));
+    const int64_t gs = kXcdChunk > 0 ? 8 * kXcdChunk : 1;
+    const int64_t ng = (q_end + GBLOCK - 1) / GBLOCK - q_begin / GBLOCK;   // Gaussian blocks met
+    const dim3 grid((unsigned)((ng * (GBLOCK / G) + gs - 1) / gs * gs));
     if (bf16)
         hipLaunchKernelGGL((k_contract_mfma<NT, true, RT>), grid, dim3(256), 0, st, n, nb, d, perm,
                            pair_of_m, views, vlist, vcnt, pinfo, part, feats, num, den, (int)first,
-                           (int)last, q_begin, q_end, (int)local);
+                           (int)last, q_begin, q_end, (int)local, gorder);
     else
         hipLaunchKernelGGL((k_contract_mfma<NT, false, RT>), grid, dim3(256), 0, st, n, nb, d, perm,
                            pair_of_m, views, vlist, vcnt, pinfo, part, feats, num, den, (int)first,
-                           (int)last, q_begin, q_end, (int)local);
+                           (int)last, q_begin, q_end, (int)local, gorder);
 }
 
 // Views in which each Gaussian block has visible pairs, ascending:
 // vlist[blk nb + i], i < vcnt[blk]; blk_off = exclusive scan of the visible
-// pair counts per (view, block), nb nblk + 1 entries.
+// pair counts per (view, block), nb nblk + 1 entries.  Also the dispatch key
+// of the block for the contraction over Gaussian blocks [gb0, gb1): blocks
+// in range by descending pair count (the block's work), the rest after them
+// (wkey = 2^27 - 1 - pairs, or 2^27), with gidx = the block.
 __global__ __launch_bounds__(256) void k_view_lists(int nb, int nblk, const uint32_t* __restrict__ blk_off,
                                                     uint16_t* __restrict__ vlist,
-                                                    uint32_t* __restrict__ vcnt)
+                                                    uint32_t* __restrict__ vcnt, int64_t gb0,
+                                                    int64_t gb1, uint32_t* __restrict__ wkey,
+                                                    uint32_t* __restrict__ gidx)
 {
-    __shared__ uint32_t wc[4];
+    __shared__ uint32_t wc[4], wp[4];
     const int blk = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t base = 0;
+    uint32_t base = 0, pairs = 0;
     for (int v0 = 0; v0 < nb; v0 += 256) {
         const int v = v0 + (int)threadIdx.x;
-        bool vis = false;
+        uint32_t np = 0;
         if (v < nb) {
             const int64_t bi = (int64_t)v * nblk + blk;
-            vis = blk_off[bi + 1] != blk_off[bi];
+            np = blk_off[bi + 1] - blk_off[bi];
         }
+        const bool vis = np != 0;
         const uint64_t m = __ballot(vis);
-        if (lane == 0) wc[wv] = (uint32_t)__popcll(m);
+        uint32_t ps = np;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) ps += __shfl_xor(ps, o, 64);
+        if (lane == 0) { wc[wv] = (uint32_t)__popcll(m); wp[wv] = ps; }
         __syncthreads();
         uint32_t off = 0;
         for (int w = 0; w < wv; w++) off += wc[w];
         const uint32_t tot = wc[0] + wc[1] + wc[2] + wc[3];
+        pairs += wp[0] + wp[1] + wp[2] + wp[3];
         if (vis) vlist[(size_t)blk * nb + base + off + (uint32_t)__popcll(m & lt)] = (uint16_t)v;
         base += tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) vcnt[blk] = base;
+    if (threadIdx.x == 0) {
+        vcnt[blk] = base;
+        if (wkey) {
+            const bool in = blk >= gb0 && blk < gb1;
+            wkey[blk] = in ? (1u << 27) - 1u - min(pairs, (1u << 27) - 1u) : (1u << 27);
+            gidx[blk] = (uint32_t)blk;
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_f32_to_bf16(uint64_t n, const float* __restrict__ in,
@@ -483,23 +626,23 @@ bool contract_supported(int d)
 bool contract_supported_codes(int d) { return d == 16 || d == 32 || d == 48 || contract_supported(d); }
 
 void launch_view_lists(int nb, int nblk, const uint32_t* blk_off, uint16_t* vlist, uint32_t* vcnt,
-                       hipStream_t st)
+                       int64_t gb0, int64_t gb1, uint32_t* wkey, uint32_t* gidx, hipStream_t st)
 {
     if (nb <= 0 || nblk <= 0) return;
     hipLaunchKernelGGL(k_view_lists, dim3((unsigned)nblk), dim3(256), 0, st, nb, nblk, blk_off, vlist,
-                       vcnt);
+                       vcnt, gb0, gb1, wkey, gidx);
 }
 
 void launch_contract(int64_t n, int nb, int d, bool bf16, const uint32_t* perm,
                      const uint32_t* pair_of_m, const ViewDev* views, const uint16_t* vlist,
                      const uint32_t* vcnt, const uint2* pinfo, const uint2* part, const void* feats,
                      float* num, float* den, bool first, bool last, int64_t q_begin, int64_t q_end,
-                     bool local, hipStream_t st)
+                     bool local, const uint32_t* gorder, hipStream_t st)
 {
     if (n <= 0 || q_end <= q_begin) return;
 #define SLAG_NT(NTV) launch_nt<NTV, kContractRT>(n, nb, d, bf16, perm, pair_of_m, views, vlist, vcnt, \
                                     pinfo, part, feats, num, den, first, last, q_begin, q_end,     \
-                                    local, st)
+                                    local, gorder, st)
     switch (d) {
     case 16:
     case 32:

@@ -356,13 +356,28 @@ static slag_status contract_batch(slag_ctx* c, Batch& B, bool first, bool last,
 {
     hipEvent_t ev;
     const int cbv = count_blocks_per_view(c->n);
+    const int64_t q_end = ct.q_end < 0 ? c->n : ct.q_end;
     CK(stage_begin(c, ST_CONTRACT, &ev));
+    // view lists, and the Gaussian blocks of the range heaviest first
+    const size_t gb = (size_t)cbv * 4 + 16;
+    CK(ensure(c, c->gkey, gb));
+    CK(ensure(c, c->gkey_alt, gb));
+    CK(ensure(c, c->gval, gb));
+    CK(ensure(c, c->gval_alt, gb));
+    CK(ensure(c, c->hist, radix_hist_bytes((uint64_t)cbv)));
+    CK(ensure_scan(c, (uint64_t)cbv));
     launch_view_lists(B.nb, cbv, c->blk_vis.as<uint32_t>(), c->vlist.as<uint16_t>(),
-                      c->vcnt.as<uint32_t>(), c->st);
+                      c->vcnt.as<uint32_t>(), ct.q_begin / GBLOCK, (q_end + GBLOCK - 1) / GBLOCK,
+                      c->gkey.as<uint32_t>(), c->gval.as<uint32_t>(), c->st);
+    const bool alt = radix_sort_u32(c->gkey.as<uint32_t>(), c->gval.as<uint32_t>(),
+                                    c->gkey_alt.as<uint32_t>(), c->gval_alt.as<uint32_t>(),
+                                    (uint64_t)cbv, 28, c->hist.as<uint32_t>(), c->scan_ws.p,
+                                    nullptr, c->st);
+    const uint32_t* gorder = alt ? c->gval_alt.as<uint32_t>() : c->gval.as<uint32_t>();
     launch_contract(c->n, B.nb, ct.d, ct.bf16, c->perm.as<uint32_t>(), c->pair_of_m.as<uint32_t>(),
                     B.views.as<ViewDev>(), c->vlist.as<uint16_t>(), c->vcnt.as<uint32_t>(),
                     c->pinfo.as<uint2>(), c->part.as<uint2>(), ct.table, ct.out, ct.den, first,
-                    last, ct.q_begin, ct.q_end < 0 ? c->n : ct.q_end, ct.local, c->st);
+                    last, ct.q_begin, q_end, ct.local, gorder, c->st);
     CK(stage_end(c, ST_CONTRACT, ev));
     return SLAG_OK;
 }
@@ -797,7 +812,8 @@ void slag_destroy(slag_ctx* c)
                       &c->outbf, &c->idstage, &c->bgeo, &c->vlist, &c->vcnt, &c->cnum, &c->cden, &c->cbf,
                       &c->query.emb, &c->query.q, &c->query.qt, &c->query.counts,
                       &c->query.keys, &c->query.vals, &c->query.keys_alt, &c->query.vals_alt,
-                      &c->query.hist, &c->query.scan_ws, &c->rattr, &c->rout,
+                      &c->query.hist, &c->query.scan_ws, &c->rattr, &c->rout, &c->gkey,
+                      &c->gkey_alt, &c->gval, &c->gval_alt,
                       &c->rbatch.views, &c->rbatch.bucket_view, &c->rbatch.view_cls};
     destroy_graph(c);
     for (DevBuf* b : bufs) release(*b);

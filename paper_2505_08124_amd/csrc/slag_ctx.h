@@ -162,6 +162,8 @@ struct slag_ctx {
     const uint32_t* front_ival = nullptr;   // its sorted list entries (pairs)
     slag_host::Batch rbatch;                 // its one-view launch
     slag_host::DevBuf rattr, rout;           // staged host attributes / outputs
+    // contraction dispatch order: per Gaussian block a work key and its index
+    slag_host::DevBuf gkey, gkey_alt, gval, gval_alt;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     slag_stats graph_stats{};

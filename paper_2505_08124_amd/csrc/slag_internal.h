@@ -200,17 +200,21 @@ bool contract_supported(int d);
 bool contract_supported_codes(int d);
 // Per Gaussian block, the views of the launch in which it has visible pairs
 // (ascending; vlist [nblk][nb], vcnt [nblk]) from the scanned visible counts;
-// the contraction walks only those views.
+// the contraction walks only those views.  With wkey/gidx (nblk entries
+// each): the dispatch keys of the blocks for a contraction over Gaussian
+// blocks [gb0, gb1) (sorting them over 28 bits gives the blocks in range,
+// heaviest first, then the others).
 void launch_view_lists(int nb, int nblk, const uint32_t* blk_off, uint16_t* vlist, uint32_t* vcnt,
-                       hipStream_t st);
+                       int64_t gb0, int64_t gb1, uint32_t* wkey, uint32_t* gidx, hipStream_t st);
 // Contraction of the Gaussians of Morton ranks [q_begin, q_end) (q_begin a
 // multiple of 16): output row of rank q is perm[q] (the caller's order), or
-// q - q_begin when `local` (one chunk of a streamed lift).
+// q - q_begin when `local` (one chunk of a streamed lift).  gorder: the
+// Gaussian blocks met by the range in dispatch order (its first entries).
 void launch_contract(int64_t n, int nb, int d, bool bf16, const uint32_t* perm,
                      const uint32_t* pair_of_m, const ViewDev* views, const uint16_t* vlist,
                      const uint32_t* vcnt, const uint2* pinfo, const uint2* part, const void* feats,
                      float* num, float* den, bool first, bool last, int64_t q_begin, int64_t q_end,
-                     bool local, hipStream_t st);
+                     bool local, const uint32_t* gorder, hipStream_t st);
 
 // ---- codec ----
 enum { GEMM_NONE = 0, GEMM_GELU = 1, GEMM_GELU_BWD = 2 };
