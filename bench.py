@@ -62,15 +62,20 @@ def _log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_2505_08124_amd", "csrc", "k_raster.hip")
+KERNEL_SOURCES = {"k_composite": "k_raster.hip", "k_contract_mfma": "k_contract.hip"}
+TRAFFIC_FILES = {"k_composite": "composite_traffic_{}.txt", "k_contract_mfma": "contract_traffic_{}.txt"}
+
+
+def kernel_source_hash(kernel: str = "k_composite") -> str:
+    p = os.path.join(ROOT, "paper_2505_08124_amd", "csrc", KERNEL_SOURCES[kernel])
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per compositing launch from the committed counter summary, if
-    it was taken on the current kernel source and this workload; else None."""
-    p = os.path.join(ROOT, "profiles", f"composite_traffic_{workload}.txt")
+def measured_traffic(workload: str, kernel: str = "k_composite"):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if it was taken on the current kernel source and this workload; else
+    None."""
+    p = os.path.join(ROOT, "profiles", TRAFFIC_FILES[kernel].format(workload))
     if not os.path.exists(p):
         return None
     kv = {}
@@ -78,7 +83,7 @@ def measured_traffic(workload: str):
         if ":" in line and not line.startswith(("|", "#", " ", "`")):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256_16") != kernel_source_hash() or kv.get("workload") != workload:
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash(kernel) or kv.get("workload") != workload:
         return None
     try:
         return int(float(kv["bytes_per_launch"]))
@@ -188,16 +193,24 @@ def measure(slag, torch, scene, steps, warmup, count=True, stage_steps=3, eager=
                n_part_slots=info["n_part_slots"], n_batches=info["n_batches"])
     _log(f"{scene.name}: step {ms:.3f} ms wall, {ev_ms:.3f} ms HIP events "
          f"({'eager' if eager else 'graph replay'}), {info['n_batches']} launch(es)")
+    # per-stage times: HIP events the library records on its stream around
+    # each stage of eager lifts of the same scene, right after the timed
+    # replays (events recorded by graph nodes cannot be timed on this
+    # runtime); their sum is checked against the replayed step
     stage_ms = {}
+    tot = 0.0
     with slag.Lifter(0, flags=slag.SLAG_FLAG_PROFILE | slag.SLAG_FLAG_AUTOTUNE) as Lp:
         Lp.set_scene(scene, device_tensors=True)
         Lp.lift()
         Lp.stats()
         for _ in range(stage_steps):
             Lp.lift()
-            for k, v in Lp.stats()["ms_stage"].items():
+            stp = Lp.stats()
+            tot += stp["ms_total"]
+            for k, v in stp["ms_stage"].items():
                 stage_ms[k] = stage_ms.get(k, 0.0) + v
     res["stage_ms"] = {k: v / stage_steps for k, v in stage_ms.items()}
+    res["stage_ms_eager_total"] = tot / stage_steps
     _log(f"{scene.name}: stage ms", json.dumps({k: round(v, 4) for k, v in res["stage_ms"].items()}))
     if count:
         res["contribs_per_s"] = res["n_contrib"] / (ms * 1e-3)
@@ -209,19 +222,40 @@ def measure(slag, torch, scene, steps, warmup, count=True, stage_steps=3, eager=
     return res, E, den
 
 
-def composite_roofline(res, workload):
+def kernel_rooflines(res, workload):
+    """Roofline of the two heaviest kernels per launch: k_composite (VALU:
+    in-box tests x 16 operations, and the 19 issue slots the kernel spends per
+    test) and k_contract_mfma (HBM: 8 B per non-zero partial, the feature
+    table once, E and den written), each from its stage time over the
+    launches of one step, and which of them dominates."""
+    out = {}
+    nl = int(res.get("n_batches") or 1)
     comp = res["stage_ms"].get("composite", 0.0)
-    if not res.get("n_tests") or comp <= 0:
-        return None
-    ach = res["n_tests"] * OPS_PER_TEST / (comp * 1e-3) / 1e12
-    ach19 = res["n_tests"] * SLOTS_PER_TEST / (comp * 1e-3) / 1e12
-    return dict(kernel="k_composite", bound="alu", achieved=round(ach, 4),
-                peak=round(VALU_PEAK_TOPS, 3), unit="Tops/s", frac=round(ach / VALU_PEAK_TOPS, 4),
-                traffic=measured_traffic(workload), ops_per_test=OPS_PER_TEST,
-                frac_issued_slots=round(ach19 / VALU_PEAK_TOPS, 4),
-                slots_per_test=SLOTS_PER_TEST, tests_per_launch=res["n_tests"],
-                avg_launch_ms=round(comp, 4),
-                dominant_stage=max(res["stage_ms"], key=res["stage_ms"].get))
+    ncomp = nl * max(1, len(res.get("tuning") or []))   # one launch per (view launch, image size)
+    if res.get("n_tests") and comp > 0:
+        ach = res["n_tests"] * OPS_PER_TEST / (comp * 1e-3) / 1e12
+        ach19 = res["n_tests"] * SLOTS_PER_TEST / (comp * 1e-3) / 1e12
+        out["k_composite"] = dict(
+            kernel="k_composite", bound="alu", achieved=round(ach, 4), peak=round(VALU_PEAK_TOPS, 3),
+            unit="Tops/s", frac=round(ach / VALU_PEAK_TOPS, 4),
+            traffic=measured_traffic(workload, "k_composite"), ops_per_test=OPS_PER_TEST,
+            frac_issued_slots=round(ach19 / VALU_PEAK_TOPS, 4), slots_per_test=SLOTS_PER_TEST,
+            launches_per_step=ncomp, tests_per_launch=int(res["n_tests"] / ncomp),
+            avg_launch_ms=round(comp / ncomp, 4))
+    con = res["stage_ms"].get("contract", 0.0)
+    st = res.get("stages") or {}
+    if "contract" in st and con > 0:
+        b = st["contract"]["bytes"]
+        ach = b / (con * 1e-3) / 1e9
+        out["k_contract_mfma"] = dict(
+            kernel="k_contract_mfma", bound="hbm", achieved=round(ach, 2), peak=HBM_PEAK_GBS,
+            unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
+            traffic=measured_traffic(workload, "k_contract_mfma"), launches_per_step=nl,
+            bytes_per_launch=int(b / nl), avg_launch_ms=round(con / nl, 4))
+    if not out:
+        return None, out
+    dom = max(out, key=lambda k: res["stage_ms"]["composite" if k == "k_composite" else "contract"])
+    return dict(out[dom], dominant_stage=max(res["stage_ms"], key=res["stage_ms"].get)), out
 
 
 def accuracy_and_cpu(slag, scene, views, budget_s):
@@ -413,7 +447,7 @@ def main():
     V, N, D = scene.n_views, scene.n, scene.dim
     res, _, _ = measure(slag, torch, scene, args.steps, args.warmup, count=not args.no_count,
                         stage_steps=3 if scene.n >= 1_000_000 else args.steps, eager=args.eager)
-    roof = composite_roofline(res, wl)
+    roof, kernels = kernel_rooflines(res, wl)
 
     accuracy = cpu = None
     if args.cpu_views > 0:
@@ -441,13 +475,14 @@ def main():
                 uneven = sc
             r, _, _ = measure(slag, torch, sc, max(args.steps, 10), args.warmup,
                               stage_steps=5 if sc.n >= 1_000_000 else 10)
-            ro = composite_roofline(r, w)
+            ro, rk = kernel_rooflines(r, w)
             secondary.append(dict(
                 workload=w, desc=DESC[w], n_gaussians=sc.n, n_views=sc.n_views,
                 feature_dim=sc.dim, feature_dtype=sc.feat_dtype,
                 views_per_s=round(r["views_per_s"], 2), ms_per_step=round(r["ms_step"], 4),
                 contribs_per_s=round(r["contribs_per_s"], 1), n_contrib=r["n_contrib"],
-                composite_frac=ro["frac"] if ro else None,
+                composite_frac=rk["k_composite"]["frac"] if "k_composite" in rk else None,
+                contract_frac=rk["k_contract_mfma"]["frac"] if "k_contract_mfma" in rk else None,
                 lift_roofline_frac=round(r["lift_roofline_frac"], 4),
                 stage_ms={k: round(v, 4) for k, v in r["stage_ms"].items()},
                 launches=r["n_batches"]))
@@ -488,6 +523,7 @@ def main():
         "tuning": res["tuning"],
         "stage_ms": {k: round(v, 4) for k, v in res["stage_ms"].items()},
         "roofline": roof,
+        "kernel_roofline": kernels,
         "stage_roofline": res.get("stages"),
         "lift_roofline_frac": round(res["lift_roofline_frac"], 4) if "lift_roofline_frac" in res
         else None,

@@ -63,7 +63,8 @@ typedef struct {
 } slag_camera;
 
 enum {
-    SLAG_FLAG_PROFILE = 1,      /* record per-stage HIP events (slag_get_stats) */
+    SLAG_FLAG_PROFILE = 1,      /* record per-stage HIP events (slag_get_stats; eager
+                                   lifts only: a graph replay reports ms_total alone) */
     SLAG_FLAG_COUNT = 2,        /* count blends and tests (slag_get_stats) */
     SLAG_FLAG_KEEP_DEBUG = 4,   /* keep the last view batch's tile lists and W rows */
     SLAG_FLAG_GRAPH = 8,        /* replay the lift as one HIP graph while the inputs are
@@ -175,7 +176,9 @@ slag_status slag_set_segments_multi(slag_ctx* ctx, int32_t view, const int32_t* 
                                     int32_t n_labels, int32_t n_seg, slag_mem where);
 
 /* The segment embeddings E_ij: table[sum_v n_seg_v][d], view-major (all
- * segments of view 0, then view 1, ...), FP32 or BF16.  Copied. */
+ * segments of view 0, then view 1, ...), FP32 or BF16.  Copied.  d is 64,
+ * 128, 256, 512, 768 or 1024 (else SLAG_E_NOT_SUPPORTED); a BF16 table is at
+ * most 4 GiB (else SLAG_E_CAPACITY). */
 slag_status slag_set_features(slag_ctx* ctx, int32_t d, slag_dtype dtype, const void* table,
                               slag_mem where);
 

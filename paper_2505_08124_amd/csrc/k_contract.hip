@@ -52,7 +52,8 @@ constexpr int kContractRT = 1;  // row tiles per block (G = 16 Gaussians; 2 and 
 
 // G = 16 RT rows per block; thread t walks row t % G and views
 // v0 + t / G + (256 / G) j, j < VPT: GV = VPT 256 / G views per step.
-constexpr int VPT = 2;
+constexpr int VPT = 2;   // (a thread numbers the bitmap words 2 t, 2 t + 1: view slot t / 4)
+static_assert(VPT == 2, "the walk reads one view offset per thread per step");
 // Part-list entries of one step staged in LDS (a step with more reads them
 // from global memory in both passes); SU loads per thread in flight.
 constexpr int STAGE = 2048;
@@ -103,14 +104,14 @@ __device__ __forceinline__ void mfma_chunk(const BlockLds<RT>& L, int k0, int kn
         constexpr int NG = NT / 4;
         constexpr int GF = NT == 12 ? 3 : 1;
         bf16x8 ahi[RT], alo[RT];
-        const uint2* rp[8];
-        const uint16_t* F = reinterpret_cast<const uint16_t*>(feats) + c0 + 4 * m;
+        uint32_t roff[8];   // byte offset of this lane's four columns in each K row
+        const char* Fb = reinterpret_cast<const char*>(feats);
         uint32_t live = 0;
 #pragma unroll
         for (int j = 0; j < 8; j++) {
             const int k = 8 * kq + j;
             live |= (k < kn ? 1u : 0u) << j;
-            rp[j] = reinterpret_cast<const uint2*>(F + (size_t)(k < kn ? L.ks[k0 + k] : 0u) * d);
+            roff[j] = ((k < kn ? L.ks[k0 + k] : 0u) * (uint32_t)d + (uint32_t)(c0 + 4 * m)) * 2u;
 #pragma unroll
             for (int r = 0; r < RT; r++) {
                 const float a = k < kn ? from_fx(L.A[16 * r + m][k0 + k]) : 0.0f;
@@ -126,7 +127,9 @@ __device__ __forceinline__ void mfma_chunk(const BlockLds<RT>& L, int k0, int kn
             for (int j = 0; j < 8; j++)
 #pragma unroll
                 for (int gg = 0; gg < GF; gg++)
-                    raw[j][gg] = ((live >> j) & 1u) ? rp[j][16 * (g0 + gg)] : make_uint2(0u, 0u);
+                    raw[j][gg] = ((live >> j) & 1u)
+                                     ? *reinterpret_cast<const uint2*>(Fb + (roff[j] + 128u * (uint32_t)(g0 + gg)))
+                                     : make_uint2(0u, 0u);
 #pragma unroll
             for (int gg = 0; gg < GF; gg++)
 #pragma unroll
@@ -150,9 +153,9 @@ __device__ __forceinline__ void mfma_chunk(const BlockLds<RT>& L, int k0, int kn
         }
     } else if constexpr (BF16) {
         bf16x8 ahi[RT], alo[RT];
-        const uint16_t* rowp[8];   // this lane's column in each K row (row 0 stands in for
-        uint32_t live = 0;         // unused K slots; their values are replaced by zero)
-        const uint16_t* F = reinterpret_cast<const uint16_t*>(feats) + c0 + m;
+        uint32_t roff[8];          // byte offset of this lane's column in each K row (row 0
+        uint32_t live = 0;         // stands in for unused K slots; their values become zero)
+        const char* Fb = reinterpret_cast<const char*>(feats);
 #pragma unroll
         for (int j = 0; j < 8; j++) {
             const int k = 8 * kq + j;
@@ -165,14 +168,14 @@ __device__ __forceinline__ void mfma_chunk(const BlockLds<RT>& L, int k0, int kn
             }
             const uint32_t kr = k < kn ? L.ks[k0 + k] : 0u;
             live |= (k < kn ? 1u : 0u) << j;
-            rowp[j] = F + (size_t)kr * d;
+            roff[j] = (kr * (uint32_t)d + (uint32_t)(c0 + m)) * 2u;
         }
 #pragma unroll
         for (int t = 0; t < NT; t++) {
             bf16x8 b;
 #pragma unroll
             for (int j = 0; j < 8; j++) {
-                const uint16_t v = rowp[j][16 * t];
+                const uint16_t v = *reinterpret_cast<const uint16_t*>(Fb + (roff[j] + 32u * (uint32_t)t));
                 b[j] = __builtin_bit_cast(__bf16, ((live >> j) & 1u) ? v : (uint16_t)0);
             }
 #pragma unroll
@@ -204,7 +207,9 @@ __device__ __forceinline__ void mfma_chunk(const BlockLds<RT>& L, int k0, int kn
     }
 }
 
-// Exclusive scan of one value per thread over the 256-thread block.
+// Exclusive scan of one value per thread over the 256-thread block.  The
+// caller must pass a block barrier before scratch is written again (every
+// caller does, right after the scan).
 __device__ __forceinline__ uint32_t block_exscan(uint32_t x, uint32_t* scratch, uint32_t& total)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -219,7 +224,6 @@ __device__ __forceinline__ uint32_t block_exscan(uint32_t x, uint32_t* scratch, 
     uint32_t off = 0;
     for (int i = 0; i < w; i++) off += scratch[i];
     total = scratch[0] + scratch[1] + scratch[2] + scratch[3];
-    __syncthreads();
     return off + v - x;
 }
 
@@ -310,25 +314,47 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
         const uint32_t p = pair_of_m[(int64_t)v * n + qr];
         return (row_ok && i < nvb) ? p : NONE;
     };
-    uint32_t pn[VPT];
+    // Everything a step needs from global memory before its entries is
+    // loaded one step ahead (the pairs two steps ahead): the pairs' (base,
+    // fill) records, the views' segment counts and the segment offset of
+    // the view whose bitmap words this thread numbers (slot t / 4)
+    auto view_at = [&](int i) -> const ViewDev* { return &views[i < nvb ? (int)vl[i] : (int)vl[0]]; };
+    uint32_t pc[VPT], pn[VPT], nsc[VPT], soc;
+    uint2 pin[VPT];
 #pragma unroll
-    for (int j = 0; j < VPT; j++) pn[j] = pair_at(vt + GT * j);
+    for (int j = 0; j < VPT; j++) pc[j] = pair_at(vt + GT * j);
+#pragma unroll
+    for (int j = 0; j < VPT; j++) {
+        pin[j] = pc[j] != NONE ? pinfo[pc[j]] : make_uint2(0u, 0u);
+        nsc[j] = vt + GT * j < nvb ? view_at(vt + GT * j)->nseg : 0u;
+        pn[j] = pair_at(GV + vt + GT * j);
+    }
+    soc = (t >> 2) < nvb ? view_at(t >> 2)->seg_off : 0u;
 
+    for (int i = t; i < GV * 8; i += 256) L.bits[i] = 0;
     for (int v0 = 0; v0 < nvb; v0 += GV) {
-        // this step's pairs (slot v0 + vt + GT j); the next step's in flight
+        // this step's pairs (slot v0 + vt + GT j)
         uint32_t pb[VPT], cnt[VPT], nsv = 0;
         bool any = false;
+        const uint32_t so_step = soc;
 #pragma unroll
         for (int j = 0; j < VPT; j++) {
-            const uint32_t p = pn[j];
-            pn[j] = pair_at(v0 + GV + vt + GT * j);
+            const uint32_t p = pc[j];
+            const uint2 pi = pin[j];
             any = any || p != NONE;
-            uint2 pi = make_uint2(0u, 0u);
-            if (p != NONE) pi = pinfo[p];                 // (base, fill): one load
-            pb[j] = pi.x;
-            cnt[j] = pi.y;
-            const int i = v0 + vt + GT * j;
-            nsv = max(nsv, i < nvb ? views[vl[i]].nseg : 0u);
+            pb[j] = p != NONE ? pi.x : 0u;
+            cnt[j] = p != NONE ? pi.y : 0u;
+            nsv = max(nsv, nsc[j]);
+            // the next step's
+            const int in = v0 + GV + vt + GT * j;
+            pc[j] = pn[j];
+            pin[j] = pn[j] != NONE ? pinfo[pn[j]] : make_uint2(0u, 0u);
+            nsc[j] = in < nvb ? view_at(in)->nseg : 0u;
+            pn[j] = pair_at(v0 + 2 * GV + vt + GT * j);
+        }
+        {
+            const int in = v0 + GV + (t >> 2);
+            soc = in < nvb ? view_at(in)->seg_off : 0u;
         }
         if (!__syncthreads_or(any)) continue;
         // stage the step's entries: thread t's lists go to [soff[t], ...) in
@@ -388,8 +414,8 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
         // others list by list.
         for (int i = t; i < GV * G; i += 256) (&L.dfx[0][0])[i] = 0ull;
         for (uint32_t w0 = 0; __syncthreads_or(w0 < nsv); w0 += 256) {
-            for (int i = t; i < GV * 8; i += 256) L.bits[i] = 0;
-            __syncthreads();
+            // (the bitmaps are zero here: cleared before the walk and after
+            // each window's last reader)
             // 1. mark the segments the rows touch, and add the weights into
             //    the per-view row sums
             if (staged) {
@@ -421,15 +447,15 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
             __syncthreads();
             // 2. columns: marked segments in (view, id) order; thread t owns
             //    words VPT t .. VPT t + VPT - 1
-            uint32_t wb[VPT], pc = 0;
+            uint32_t wb[VPT], npop = 0;
 #pragma unroll
             for (int j = 0; j < VPT; j++) {
                 const int i = VPT * t + j;
                 wb[j] = i < GV * 8 ? L.bits[i] : 0u;
-                pc += (uint32_t)__popc(wb[j]);
+                npop += (uint32_t)__popc(wb[j]);
             }
             uint32_t ktot;
-            uint32_t base = block_exscan(pc, L.scan, ktot);
+            uint32_t base = block_exscan(npop, L.scan, ktot);
 #pragma unroll
             for (int j = 0; j < VPT; j++) {
                 const int i = VPT * t + j;
@@ -444,8 +470,7 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
                     const int i = VPT * t + j;
                     uint32_t bb = wb[j];
                     if (!bb) continue;
-                    const int iw = v0 + (i >> 3);
-                    const uint32_t so = iw < nvb ? views[vl[iw]].seg_off : 0u;
+                    const uint32_t so = so_step;   // view slot i >> 3 = t >> 2
                     uint32_t c = L.wbase[i];
                     while (bb) {
                         const uint32_t bit = (uint32_t)(__ffs((int)bb) - 1);
@@ -498,6 +523,9 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
                         mfma_chunk<NT, BF16, RT>(L, k0, min(KC, kc - k0), feats, d, c0, acc, lane);
                 __syncthreads();
             }
+            // the bitmaps' last reader is behind a barrier: clear them for the
+            // next window or step
+            for (int i = t; i < GV * 8; i += 256) L.bits[i] = 0;
         }
         // row weight sums, views in order
         for (int i = t; i < GV * G; i += 256)

@@ -1002,6 +1002,9 @@ slag_status slag_set_features(slag_ctx* c, int32_t d, slag_dtype dtype, const vo
     uint64_t rows = 0;
     for (int v = 0; v < c->nviews; v++) rows += (uint64_t)c->nseg[v];
     if (rows > 0 && !table) FAIL(c, SLAG_E_INVALID_ARG, "null feature table");
+    // the contraction addresses BF16 rows with 32-bit byte offsets
+    if (dtype == SLAG_BF16 && rows * (uint64_t)d * 2u > 0xFFFFFFFFull)
+        FAIL(c, SLAG_E_CAPACITY, "BF16 feature table over 4 GiB");
     HC(c, hipSetDevice(c->device));
     const size_t es = dtype == SLAG_BF16 ? 2 : 4;
     CK(copy_in(c, c->feats, table, rows * (size_t)d * es, where));
