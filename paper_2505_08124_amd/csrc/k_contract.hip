@@ -68,6 +68,7 @@ struct BlockLds {
     float dpart[GV][G];         // per-view row weight sums of the step
     uint64_t dfx[GV][G];        //   the same, fixed point
     uint32_t scan[8];
+    uint32_t chead, clast, cbase;   // chunk list of the block (walk-only launch)
     // the step's part-list entries, staged once (both passes read them),
     // with their owner (view slot G + row)
     uint2 stage[STAGE];
@@ -89,6 +90,48 @@ __device__ __forceinline__ int tile_col(int c0, int i, int m)
     else return c0 + 16 * i + m;
 }
 
+// One 32-column chunk on the matrix cores for D >= 768 BF16 features (one
+// row tile): this lane's K rows k = 8 kq + j at byte offsets roff[j] (bit j
+// of live: a real column; others are read as zero), weights split hi + lo.
+// The feature loads go in batches of GF groups of four columns (8 rows x 8
+// bytes per group), each batch in flight at once; GF keeps a batch within
+// the registers the occupancy leaves.
+template <int NT>
+__device__ __forceinline__ void wide_mfma(const char* __restrict__ Fb, const uint32_t (&roff)[8],
+                                          uint32_t live, bf16x8 ahi, bf16x8 alo, floatx4* acc)
+{
+    constexpr int NG = NT / 4;
+    constexpr int GF = NT == 12 ? 3 : 1;
+#pragma unroll
+    for (int g0 = 0; g0 < NG; g0 += GF) {
+        uint2 raw[8][GF];
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+#pragma unroll
+            for (int gg = 0; gg < GF; gg++)
+                raw[j][gg] = ((live >> j) & 1u)
+                                 ? *reinterpret_cast<const uint2*>(Fb + (roff[j] + 128u * (uint32_t)(g0 + gg)))
+                                 : make_uint2(0u, 0u);
+#pragma unroll
+        for (int gg = 0; gg < GF; gg++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                u32x4 w;
+#pragma unroll
+                for (int jj = 0; jj < 4; jj++) {
+                    const uint32_t x0 = (e < 2) ? raw[2 * jj][gg].x : raw[2 * jj][gg].y;
+                    const uint32_t x1 = (e < 2) ? raw[2 * jj + 1][gg].x : raw[2 * jj + 1][gg].y;
+                    w[jj] = (e & 1) ? ((x0 >> 16) | (x1 & 0xFFFF0000u)) : ((x0 & 0xFFFFu) | (x1 << 16));
+                }
+                const bf16x8 b = __builtin_bit_cast(bf16x8, w);
+                const int ti = 4 * (g0 + gg) + e;
+                acc[ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, b, acc[ti], 0, 0, 0);
+                acc[ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, b, acc[ti], 0, 0, 0);
+            }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // Multiply columns [k0, k0 + kn) of the staged round into the accumulators
 // acc[r][t] (row tile r, column tile t).
 template <int NT, bool BF16, int RT>
@@ -97,60 +140,21 @@ __device__ __forceinline__ void mfma_chunk(const BlockLds<RT>& L, int k0, int kn
 {
     const int m = lane & 15, kq = lane >> 4;
     if constexpr (BF16 && NT >= 12 && NT % 4 == 0) {
-        // the chunk's feature loads in batches of GF groups of four columns
-        // (8 K rows x 8 bytes per group), each batch in flight at once (rows
-        // past kn are not read); GF keeps the batch within the registers
-        // the occupancy leaves
-        constexpr int NG = NT / 4;
-        constexpr int GF = NT == 12 ? 3 : 1;
-        bf16x8 ahi[RT], alo[RT];
+        static_assert(RT == 1, "the wide-load path multiplies one row tile");
+        bf16x8 ahi, alo;
         uint32_t roff[8];   // byte offset of this lane's four columns in each K row
-        const char* Fb = reinterpret_cast<const char*>(feats);
         uint32_t live = 0;
 #pragma unroll
         for (int j = 0; j < 8; j++) {
             const int k = 8 * kq + j;
             live |= (k < kn ? 1u : 0u) << j;
             roff[j] = ((k < kn ? L.ks[k0 + k] : 0u) * (uint32_t)d + (uint32_t)(c0 + 4 * m)) * 2u;
-#pragma unroll
-            for (int r = 0; r < RT; r++) {
-                const float a = k < kn ? from_fx(L.A[16 * r + m][k0 + k]) : 0.0f;
-                const __bf16 h = (__bf16)a;
-                ahi[r][j] = h;
-                alo[r][j] = (__bf16)(a - (float)h);
-            }
+            const float a = k < kn ? from_fx(L.A[m][k0 + k]) : 0.0f;
+            const __bf16 h = (__bf16)a;
+            ahi[j] = h;
+            alo[j] = (__bf16)(a - (float)h);
         }
-#pragma unroll
-        for (int g0 = 0; g0 < NG; g0 += GF) {
-            uint2 raw[8][GF];
-#pragma unroll
-            for (int j = 0; j < 8; j++)
-#pragma unroll
-                for (int gg = 0; gg < GF; gg++)
-                    raw[j][gg] = ((live >> j) & 1u)
-                                     ? *reinterpret_cast<const uint2*>(Fb + (roff[j] + 128u * (uint32_t)(g0 + gg)))
-                                     : make_uint2(0u, 0u);
-#pragma unroll
-            for (int gg = 0; gg < GF; gg++)
-#pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    u32x4 w;
-#pragma unroll
-                    for (int jj = 0; jj < 4; jj++) {
-                        const uint32_t x0 = (e < 2) ? raw[2 * jj][gg].x : raw[2 * jj][gg].y;
-                        const uint32_t x1 = (e < 2) ? raw[2 * jj + 1][gg].x : raw[2 * jj + 1][gg].y;
-                        w[jj] = (e & 1) ? ((x0 >> 16) | (x1 & 0xFFFF0000u)) : ((x0 & 0xFFFFu) | (x1 << 16));
-                    }
-                    const bf16x8 b = __builtin_bit_cast(bf16x8, w);
-                    const int ti = 4 * (g0 + gg) + e;
-#pragma unroll
-                    for (int r = 0; r < RT; r++) {
-                        acc[r][ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[r], b, acc[r][ti], 0, 0, 0);
-                        acc[r][ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[r], b, acc[r][ti], 0, 0, 0);
-                    }
-                }
-            __builtin_amdgcn_sched_barrier(0);
-        }
+        wide_mfma<NT>(reinterpret_cast<const char*>(feats), roff, live, ahi, alo, acc[0]);
     } else if constexpr (BF16) {
         bf16x8 ahi[RT], alo[RT];
         uint32_t roff[8];          // byte offset of this lane's column in each K row (row 0
@@ -233,15 +237,18 @@ __device__ __forceinline__ uint32_t block_exscan(uint32_t x, uint32_t* scratch, 
 template <int NT>
 constexpr int contract_min_blocks() { return NT <= 8 ? 3 : 2; }
 
-template <int NT, bool BF16, int RT>
-__global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfma(
+// SPLIT: the walk alone (no accumulators, so three workgroups per CU at any
+// D): each round's columns and weights go to a chunk list of the block and
+// the rows' weight sums to co.rowden; k_contract_chunks multiplies them.
+template <int NT, bool BF16, int RT, bool SPLIT>
+__global__ __launch_bounds__(256, contract_min_blocks<SPLIT ? 1 : NT>()) void k_contract_mfma(
     int64_t n, int nb, int d, const uint32_t* __restrict__ perm,
     const uint32_t* __restrict__ pair_of_m, const ViewDev* __restrict__ views,
     const uint16_t* __restrict__ vlist, const uint32_t* __restrict__ vcnt,
     const uint2* __restrict__ pinfo,
     const uint2* __restrict__ part, const void* __restrict__ feats, float* __restrict__ num,
     float* __restrict__ den, int first, int last, int64_t q_begin, int64_t q_end, int local,
-    const uint32_t* __restrict__ gorder)
+    const uint32_t* __restrict__ gorder, ChunkOut co)
 {
     constexpr int G = BlockLds<RT>::G, GT = BlockLds<RT>::GT, GV = BlockLds<RT>::GV;
     __shared__ BlockLds<RT> L;
@@ -276,7 +283,10 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
 
     floatx4 acc[RT][NT];
     float dsum = 0.0f;   // running weight sum of row t (threads t < G)
-    if (first) {
+    if (SPLIT) {
+        if (t == 0) { L.chead = NONE; L.clast = NONE; }
+        if (!first && t < G && q0 + t < q_end) dsum = den[orow(q0 + t)];
+    } else if (first) {
 #pragma unroll
         for (int r = 0; r < RT; r++)
 #pragma unroll
@@ -516,11 +526,38 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
                     }
                 }
                 __syncthreads();
-                // 4. matrix cores, 32 columns at a time
                 const int kc = (int)min((uint32_t)KMAX, ktot - kr);
-                if (wact)
-                    for (int k0 = 0; k0 < kc; k0 += KC)
-                        mfma_chunk<NT, BF16, RT>(L, k0, min(KC, kc - k0), feats, d, c0, acc, lane);
+                if constexpr (SPLIT) {
+                    // 4. the round's columns, 32 to a chunk (feature row, or
+                    //    NONE past kc; the 16 rows' weights), appended to the
+                    //    block's chunk list; nothing is written past co.cap
+                    //    (the counter still counts: the host then re-runs)
+                    const int nchk = (kc + KC - 1) / KC;
+                    if (t == 0) L.cbase = atomicAdd(co.counter, (uint32_t)nchk);
+                    __syncthreads();
+                    const uint32_t cb0 = L.cbase;
+                    if ((uint64_t)cb0 + (uint64_t)nchk <= (uint64_t)co.cap) {
+                        for (int i = t; i < nchk * KC; i += 256)
+                            co.cks[(size_t)cb0 * KC + i] = i < kc ? L.ks[i] : NONE;
+                        for (int i = t; i < nchk * KC * G; i += 256) {
+                            const int c = i / (KC * G), r = (i / KC) % G, k = i % KC, col = c * KC + k;
+                            co.cA[((size_t)cb0 + c) * (KC * G) + r * KC + k] =
+                                col < kc ? from_fx(L.A[r][col]) : 0.0f;
+                        }
+                        if (t == 0) {
+                            for (int c = 0; c < nchk; c++)
+                                co.cnext[cb0 + c] = c + 1 < nchk ? cb0 + c + 1 : NONE;
+                            if (L.clast != NONE) co.cnext[L.clast] = cb0;
+                            else L.chead = cb0;
+                            L.clast = cb0 + (uint32_t)nchk - 1u;
+                        }
+                    }
+                } else {
+                    // 4. matrix cores, 32 columns at a time
+                    if (wact)
+                        for (int k0 = 0; k0 < kc; k0 += KC)
+                            mfma_chunk<NT, BF16, RT>(L, k0, min(KC, kc - k0), feats, d, c0, acc, lane);
+                }
                 __syncthreads();
             }
             // the bitmaps' last reader is behind a barrier: clear them for the
@@ -535,6 +572,12 @@ __global__ __launch_bounds__(256, contract_min_blocks<NT>()) void k_contract_mfm
             const int nv = min(GV, nvb - v0);
             for (int i = 0; i < nv; i++) dsum += L.dpart[i][t];
         }
+    }
+    if constexpr (SPLIT) {
+        const int64_t bl = (q0 - q_begin) / G;   // the block's index in the range
+        if (t < G) co.rowden[bl * G + t] = dsum;
+        if (t == 0) co.head[bl] = L.chead;
+        return;
     }
     __syncthreads();
     float* drow = &L.dpart[0][0];
@@ -569,14 +612,106 @@ void launch_nt(int64_t n, int nb, int d, bool bf16, const uint32_t* perm, const 
     const int64_t gs = kXcdChunk > 0 ? 8 * kXcdChunk : 1;
     const int64_t ng = (q_end + GBLOCK - 1) / GBLOCK - q_begin / GBLOCK;   // Gaussian blocks met
     const dim3 grid((unsigned)((ng * (GBLOCK / G) + gs - 1) / gs * gs));
+    const ChunkOut none{};
     if (bf16)
-        hipLaunchKernelGGL((k_contract_mfma<NT, true, RT>), grid, dim3(256), 0, st, n, nb, d, perm,
-                           pair_of_m, views, vlist, vcnt, pinfo, part, feats, num, den, (int)first,
-                           (int)last, q_begin, q_end, (int)local, gorder);
+        hipLaunchKernelGGL((k_contract_mfma<NT, true, RT, false>), grid, dim3(256), 0, st, n, nb, d,
+                           perm, pair_of_m, views, vlist, vcnt, pinfo, part, feats, num, den,
+                           (int)first, (int)last, q_begin, q_end, (int)local, gorder, none);
     else
-        hipLaunchKernelGGL((k_contract_mfma<NT, false, RT>), grid, dim3(256), 0, st, n, nb, d, perm,
-                           pair_of_m, views, vlist, vcnt, pinfo, part, feats, num, den, (int)first,
-                           (int)last, q_begin, q_end, (int)local, gorder);
+        hipLaunchKernelGGL((k_contract_mfma<NT, false, RT, false>), grid, dim3(256), 0, st, n, nb, d,
+                           perm, pair_of_m, views, vlist, vcnt, pinfo, part, feats, num, den,
+                           (int)first, (int)last, q_begin, q_end, (int)local, gorder, none);
+}
+
+// Grid of a contraction launch over [q_begin, q_end): the Gaussian blocks met,
+// GBLOCK / 16 workgroups each, in whole XCD groups.
+dim3 contract_grid(int64_t q_begin, int64_t q_end)
+{
+    const int64_t gs = kXcdChunk > 0 ? 8 * kXcdChunk : 1;
+    const int64_t ng = (q_end + GBLOCK - 1) / GBLOCK - q_begin / GBLOCK;
+    return dim3((unsigned)((ng * (GBLOCK / 16) + gs - 1) / gs * gs));
+}
+
+// The chunk multiply: one workgroup per block of 16 Gaussians (the walk's
+// dispatch order), four independent waves of NT column tiles; each follows
+// the block's chunk list and multiplies every chunk with the same operations
+// as the fused kernel (bitwise-equal results), then writes E (or the running
+// sums) and den.
+template <int NT>
+__global__ __launch_bounds__(256, 2) void k_contract_chunks(
+    int64_t n, int d, const uint32_t* __restrict__ perm, const uint32_t* __restrict__ head,
+    const uint32_t* __restrict__ cnext, const uint32_t* __restrict__ cks, const float* __restrict__ cA,
+    const float* __restrict__ rowden, const void* __restrict__ feats, float* __restrict__ num,
+    float* __restrict__ den, int first, int last, int64_t q_begin, int64_t q_end, int local,
+    const uint32_t* __restrict__ gorder)
+{
+    constexpr int G = 16, BPG = GBLOCK / G;
+    int64_t lb = blockIdx.x;
+    if (kXcdChunk > 0) {
+        const int64_t gs = 8 * kXcdChunk, w = lb % gs;
+        lb = lb - w + (w % 8) * kXcdChunk + w / 8;
+    }
+    const int64_t ng = (q_end + GBLOCK - 1) / GBLOCK - q_begin / GBLOCK;
+    if (lb >= ng * BPG) return;
+    const int64_t q0 = (int64_t)gorder[lb / BPG] * GBLOCK + (lb % BPG) * G;
+    if (q0 < q_begin || q0 >= q_end) return;
+    const int64_t bl = (q0 - q_begin) / G;
+    auto orow = [&](int64_t q) -> int64_t { return local ? q - q_begin : (int64_t)perm[q]; };
+    const int t = threadIdx.x, wv = t >> 6, lane = t & 63, m = lane & 15, kq = lane >> 4;
+    const int c0 = wv * 16 * NT;   // d = 64 NT: every wave has columns
+    floatx4 acc[NT];
+    if (first) {
+#pragma unroll
+        for (int i = 0; i < NT; i++) acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
+    } else {
+        int64_t gq[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int64_t q = q0 + 4 * kq + j;
+            gq[j] = orow(q < q_end ? q : q_end - 1);
+        }
+#pragma unroll
+        for (int i = 0; i < NT; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const float x = num[(size_t)gq[j] * d + tile_col<NT, true>(c0, i, m)];
+                acc[i][j] = (q0 + 4 * kq + j < q_end) ? x : 0.0f;
+            }
+    }
+    const char* Fb = reinterpret_cast<const char*>(feats);
+    for (uint32_t ch = head[bl]; ch != NONE;) {
+        const uint32_t nx = cnext[ch];
+        const float* ap = cA + (size_t)ch * (KC * G) + m * KC + 8 * kq;
+        const uint32_t* kp = cks + (size_t)ch * KC + 8 * kq;
+        bf16x8 ahi, alo;
+        uint32_t roff[8], live = 0;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const uint32_t kr = kp[j];
+            live |= (kr != NONE ? 1u : 0u) << j;
+            roff[j] = ((kr != NONE ? kr : 0u) * (uint32_t)d + (uint32_t)(c0 + 4 * m)) * 2u;
+            const float a = ap[j];
+            const __bf16 h = (__bf16)a;
+            ahi[j] = h;
+            alo[j] = (__bf16)(a - (float)h);
+        }
+        wide_mfma<NT>(Fb, roff, live, ahi, alo, acc);
+        ch = nx;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int rr = 4 * kq + j;
+        const int64_t q = q0 + rr;
+        if (q >= q_end) continue;
+        const int64_t g = orow(q);
+        const float dn = rowden[bl * G + rr];
+#pragma unroll
+        for (int i = 0; i < NT; i++) {
+            const float a = acc[i][j];
+            num[(size_t)g * d + tile_col<NT, true>(c0, i, m)] = last ? (dn > 0.0f ? a / dn : 0.0f) : a;
+        }
+    }
+    if (t < G && q0 + t < q_end) den[orow(q0 + t)] = rowden[bl * G + t];
 }
 
 // Views in which each Gaussian block has visible pairs, ascending:
@@ -684,6 +819,45 @@ void launch_contract(int64_t n, int nb, int d, bool bf16, const uint32_t* perm,
     default: break;
     }
 #undef SLAG_NT
+}
+
+bool contract_split(int d, bool bf16) { return bf16 && (d == 768 || d == 1024); }
+
+void launch_contract_walk(int64_t n, int nb, int d, const uint32_t* perm, const uint32_t* pair_of_m,
+                          const ViewDev* views, const uint16_t* vlist, const uint32_t* vcnt,
+                          const uint2* pinfo, const uint2* part, const float* den, bool first,
+                          int64_t q_begin, int64_t q_end, bool local, const uint32_t* gorder,
+                          const ChunkOut& co, hipStream_t st)
+{
+    if (n <= 0 || q_end <= q_begin || !contract_split(d, true)) return;
+    static_assert(kContractRT == 1, "the chunk multiply takes blocks of 16 Gaussians");
+    const dim3 grid = contract_grid(q_begin, q_end);
+    float* dn = const_cast<float*>(den);   // read only (when not first)
+    if (d == 768)
+        hipLaunchKernelGGL((k_contract_mfma<12, true, 1, true>), grid, dim3(256), 0, st, n, nb, d,
+                           perm, pair_of_m, views, vlist, vcnt, pinfo, part, nullptr, nullptr, dn,
+                           (int)first, 0, q_begin, q_end, (int)local, gorder, co);
+    else
+        hipLaunchKernelGGL((k_contract_mfma<16, true, 1, true>), grid, dim3(256), 0, st, n, nb, d,
+                           perm, pair_of_m, views, vlist, vcnt, pinfo, part, nullptr, nullptr, dn,
+                           (int)first, 0, q_begin, q_end, (int)local, gorder, co);
+}
+
+void launch_contract_chunks(int64_t n, int d, const uint32_t* perm, const ChunkOut& co,
+                            const void* feats, float* num, float* den, bool first, bool last,
+                            int64_t q_begin, int64_t q_end, bool local, const uint32_t* gorder,
+                            hipStream_t st)
+{
+    if (n <= 0 || q_end <= q_begin || !contract_split(d, true)) return;
+    const dim3 grid = contract_grid(q_begin, q_end);
+    if (d == 768)
+        hipLaunchKernelGGL(k_contract_chunks<12>, grid, dim3(256), 0, st, n, d, perm, co.head,
+                           co.cnext, co.cks, co.cA, co.rowden, feats, num, den, (int)first,
+                           (int)last, q_begin, q_end, (int)local, gorder);
+    else
+        hipLaunchKernelGGL(k_contract_chunks<16>, grid, dim3(256), 0, st, n, d, perm, co.head,
+                           co.cnext, co.cks, co.cA, co.rowden, feats, num, den, (int)first,
+                           (int)last, q_begin, q_end, (int)local, gorder);
 }
 
 }  // namespace slag

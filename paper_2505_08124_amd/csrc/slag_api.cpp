@@ -374,10 +374,50 @@ static slag_status contract_batch(slag_ctx* c, Batch& B, bool first, bool last,
                                     (uint64_t)cbv, 28, c->hist.as<uint32_t>(), c->scan_ws.p,
                                     nullptr, c->st);
     const uint32_t* gorder = alt ? c->gval_alt.as<uint32_t>() : c->gval.as<uint32_t>();
-    launch_contract(c->n, B.nb, ct.d, ct.bf16, c->perm.as<uint32_t>(), c->pair_of_m.as<uint32_t>(),
-                    B.views.as<ViewDev>(), c->vlist.as<uint16_t>(), c->vcnt.as<uint32_t>(),
-                    c->pinfo.as<uint2>(), c->part.as<uint2>(), ct.table, ct.out, ct.den, first,
-                    last, ct.q_begin, q_end, ct.local, gorder, c->st);
+    if (!contract_split(ct.d, ct.bf16)) {
+        launch_contract(c->n, B.nb, ct.d, ct.bf16, c->perm.as<uint32_t>(),
+                        c->pair_of_m.as<uint32_t>(), B.views.as<ViewDev>(), c->vlist.as<uint16_t>(),
+                        c->vcnt.as<uint32_t>(), c->pinfo.as<uint2>(), c->part.as<uint2>(), ct.table,
+                        ct.out, ct.den, first, last, ct.q_begin, q_end, ct.local, gorder, c->st);
+    } else if (q_end > ct.q_begin && c->n > 0) {
+        // the walk writes each block's chunk list; the chunk count is read
+        // back after an eager walk (a walk that ran out of room is re-run
+        // with room for all), and a recorded graph reuses it
+        const bool whole = ct.q_begin == 0 && q_end == c->n;
+        const uint64_t nblocks = (uint64_t)((q_end - ct.q_begin + 15) / 16);
+        uint64_t cap = (whole && B.nchunks) ? B.nchunks : nblocks * 12 + 1024;   // a guess first
+        cap = std::min<uint64_t>(cap, 0xFFFFFFF0ull);
+        CK(ensure(c, c->chead, nblocks * 4 + 16));
+        CK(ensure(c, c->rowden, nblocks * 64 + 16));
+        uint64_t* small = c->small.as<uint64_t>();
+        for (;;) {
+            CK(ensure(c, c->cks, cap * 128 + 16));
+            CK(ensure(c, c->cA, cap * 2048 + 16));
+            CK(ensure(c, c->cnext, cap * 4 + 16));
+            ChunkOut co{c->cks.as<uint32_t>(), c->cA.as<float>(), c->cnext.as<uint32_t>(),
+                        c->chead.as<uint32_t>(), c->rowden.as<float>(),
+                        reinterpret_cast<uint32_t*>(small + SM_CHUNKS), (uint32_t)cap};
+            launch_fill_u32(co.counter, 2, 0u, c->st);
+            launch_contract_walk(c->n, B.nb, ct.d, c->perm.as<uint32_t>(),
+                                 c->pair_of_m.as<uint32_t>(), B.views.as<ViewDev>(),
+                                 c->vlist.as<uint16_t>(), c->vcnt.as<uint32_t>(),
+                                 c->pinfo.as<uint2>(), c->part.as<uint2>(), ct.den, first,
+                                 ct.q_begin, q_end, ct.local, gorder, co, c->st);
+            if (!c->capturing) {
+                CK(read_small(c, SM_CHUNKS, 1));
+                const uint64_t used = c->host_small[SM_CHUNKS] & 0xFFFFFFFFull;
+                if (used > cap) {
+                    if (used > 0xFFFFFFF0ull) FAIL(c, SLAG_E_CAPACITY, "too many contraction chunks");
+                    cap = used;
+                    continue;
+                }
+                if (whole) B.nchunks = used;
+            }
+            launch_contract_chunks(c->n, ct.d, c->perm.as<uint32_t>(), co, ct.table, ct.out, ct.den,
+                                   first, last, ct.q_begin, q_end, ct.local, gorder, c->st);
+            break;
+        }
+    }
     CK(stage_end(c, ST_CONTRACT, ev));
     return SLAG_OK;
 }
@@ -813,7 +853,8 @@ void slag_destroy(slag_ctx* c)
                       &c->query.emb, &c->query.q, &c->query.qt, &c->query.counts,
                       &c->query.keys, &c->query.vals, &c->query.keys_alt, &c->query.vals_alt,
                       &c->query.hist, &c->query.scan_ws, &c->rattr, &c->rout, &c->gkey,
-                      &c->gkey_alt, &c->gval, &c->gval_alt,
+                      &c->gkey_alt, &c->gval, &c->gval_alt, &c->cks, &c->cA, &c->cnext,
+                      &c->chead, &c->rowden,
                       &c->rbatch.views, &c->rbatch.bucket_view, &c->rbatch.view_cls};
     destroy_graph(c);
     for (DevBuf* b : bufs) release(*b);

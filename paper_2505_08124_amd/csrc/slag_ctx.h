@@ -32,6 +32,7 @@ struct Batch {
     DevBuf views, bucket_view;
     // sizes read back by the last eager lift (reused while capturing a graph)
     uint64_t npairs = 0, ni = 0, nparts = 0, ntie = 0;
+    uint64_t nchunks = 0;   // chunks the contraction's walk took (whole range)
     uint32_t zmin = 0, zmax = 0;
     // resolution classes (distinct image sizes, first appearance order): the
     // compositing runs one launch per class, with the class's tuned variant
@@ -164,6 +165,8 @@ struct slag_ctx {
     slag_host::DevBuf rattr, rout;           // staged host attributes / outputs
     // contraction dispatch order: per Gaussian block a work key and its index
     slag_host::DevBuf gkey, gkey_alt, gval, gval_alt;
+    // walk + chunk multiply (D >= 768 BF16): chunk lists of the blocks
+    slag_host::DevBuf cks, cA, cnext, chead, rowden;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     slag_stats graph_stats{};
@@ -184,7 +187,7 @@ namespace slag_host {
 
 // small device area layout (uint64 words)
 enum { SM_TOT = 0, SM_ZRANGE = 2, SM_TOTALS = 4, SM_COUNTERS = 8, SM_NNZ = 12, SM_ERR = 14,
-       SM_TIES = 16, SM_LERR = 18, SM_WORDS = 20 };
+       SM_TIES = 16, SM_LERR = 18, SM_CHUNKS = 20, SM_WORDS = 22 };
 
 #define FAIL(ctx, code, msg)                 \
     do {                                     \

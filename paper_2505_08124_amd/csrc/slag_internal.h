@@ -206,6 +206,19 @@ bool contract_supported_codes(int d);
 // heaviest first, then the others).
 void launch_view_lists(int nb, int nblk, const uint32_t* blk_off, uint16_t* vlist, uint32_t* vcnt,
                        int64_t gb0, int64_t gb1, uint32_t* wkey, uint32_t* gidx, hipStream_t st);
+// The walk-only contraction's output (BF16 features, D >= 768): per block
+// of 16 Gaussians of the range, a list of chunks of 32 columns.
+struct ChunkOut {
+    uint32_t* cks;       // [cap][32] feature row of each column, NONE past a round's end
+    float* cA;           // [cap][16][32] the 16 rows' weights of each column
+    uint32_t* cnext;     // [cap] next chunk of the block, NONE after its last
+    uint32_t* head;      // [blocks] first chunk of each block, NONE if it has none
+    float* rowden;       // [blocks][16] the rows' weight sums (den after this launch)
+    uint32_t* counter;   // chunks taken (zeroed by the caller); may exceed cap,
+    uint32_t cap;        //   and then nothing past cap is written
+};
+// Whether a contraction of width d runs as walk + chunk multiply.
+bool contract_split(int d, bool bf16);
 // Contraction of the Gaussians of Morton ranks [q_begin, q_end) (q_begin a
 // multiple of 16): output row of rank q is perm[q] (the caller's order), or
 // q - q_begin when `local` (one chunk of a streamed lift).  gorder: the
@@ -215,6 +228,18 @@ void launch_contract(int64_t n, int nb, int d, bool bf16, const uint32_t* perm,
                      const uint32_t* vcnt, const uint2* pinfo, const uint2* part, const void* feats,
                      float* num, float* den, bool first, bool last, int64_t q_begin, int64_t q_end,
                      bool local, const uint32_t* gorder, hipStream_t st);
+// The same split in two (contract_split(d, bf16)): the walk writes co; after
+// it (and after the caller has checked co.counter <= co.cap), the chunk
+// multiply writes num and den.
+void launch_contract_walk(int64_t n, int nb, int d, const uint32_t* perm, const uint32_t* pair_of_m,
+                          const ViewDev* views, const uint16_t* vlist, const uint32_t* vcnt,
+                          const uint2* pinfo, const uint2* part, const float* den, bool first,
+                          int64_t q_begin, int64_t q_end, bool local, const uint32_t* gorder,
+                          const ChunkOut& co, hipStream_t st);
+void launch_contract_chunks(int64_t n, int d, const uint32_t* perm, const ChunkOut& co,
+                            const void* feats, float* num, float* den, bool first, bool last,
+                            int64_t q_begin, int64_t q_end, bool local, const uint32_t* gorder,
+                            hipStream_t st);
 
 // ---- codec ----
 enum { GEMM_NONE = 0, GEMM_GELU = 1, GEMM_GELU_BWD = 2 };
