@@ -62,8 +62,8 @@ def _log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = {"k_composite": "k_raster.hip", "k_contract_mfma": "k_contract.hip"}
-TRAFFIC_FILES = {"k_composite": "composite_traffic_{}.txt", "k_contract_mfma": "contract_traffic_{}.txt"}
+KERNEL_SOURCES = {"k_composite": "k_raster.hip", "contraction": "k_contract.hip"}
+TRAFFIC_FILES = {"k_composite": "composite_traffic_{}.txt", "contraction": "contract_traffic_{}.txt"}
 
 
 def kernel_source_hash(kernel: str = "k_composite") -> str:
@@ -149,7 +149,7 @@ def measure(slag, torch, scene, steps, warmup, count=True, stage_steps=3, eager=
     stream with HIP events, then per-stage times from eager profiled lifts.
     Returns a dict of measurements (and the embeddings of the timed lift)."""
     V = scene.n_views
-    res = {}
+    res = {"feature_dim": scene.dim, "feat_bf16": scene.feat_dtype == "bf16"}
     if count:
         # contributions, in-box tests and non-zero weights: a separate counting
         # lift (not timed)
@@ -223,11 +223,12 @@ def measure(slag, torch, scene, steps, warmup, count=True, stage_steps=3, eager=
 
 
 def kernel_rooflines(res, workload):
-    """Roofline of the two heaviest kernels per launch: k_composite (VALU:
+    """Roofline of the two heaviest stages per launch: k_composite (VALU:
     in-box tests x 16 operations, and the 19 issue slots the kernel spends per
-    test) and k_contract_mfma (HBM: 8 B per non-zero partial, the feature
-    table once, E and den written), each from its stage time over the
-    launches of one step, and which of them dominates."""
+    test) and the contraction (HBM: 8 B per non-zero partial, the feature
+    table once, E and den written; k_contract_mfma, which at D >= 768 BF16
+    walks only and hands chunks to k_contract_chunks), each from its stage
+    time over the launches of one step, and which of them dominates."""
     out = {}
     nl = int(res.get("n_batches") or 1)
     comp = res["stage_ms"].get("composite", 0.0)
@@ -247,10 +248,12 @@ def kernel_rooflines(res, workload):
     if "contract" in st and con > 0:
         b = st["contract"]["bytes"]
         ach = b / (con * 1e-3) / 1e9
-        out["k_contract_mfma"] = dict(
-            kernel="k_contract_mfma", bound="hbm", achieved=round(ach, 2), peak=HBM_PEAK_GBS,
+        split = res.get("feature_dim", 0) >= 768 and res.get("feat_bf16", False)
+        out["contraction"] = dict(
+            kernel="k_contract_mfma + k_contract_chunks" if split else "k_contract_mfma",
+            bound="hbm", achieved=round(ach, 2), peak=HBM_PEAK_GBS,
             unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
-            traffic=measured_traffic(workload, "k_contract_mfma"), launches_per_step=nl,
+            traffic=measured_traffic(workload, "contraction"), launches_per_step=nl,
             bytes_per_launch=int(b / nl), avg_launch_ms=round(con / nl, 4))
     if not out:
         return None, out
@@ -482,7 +485,7 @@ def main():
                 views_per_s=round(r["views_per_s"], 2), ms_per_step=round(r["ms_step"], 4),
                 contribs_per_s=round(r["contribs_per_s"], 1), n_contrib=r["n_contrib"],
                 composite_frac=rk["k_composite"]["frac"] if "k_composite" in rk else None,
-                contract_frac=rk["k_contract_mfma"]["frac"] if "k_contract_mfma" in rk else None,
+                contract_frac=rk["contraction"]["frac"] if "contraction" in rk else None,
                 lift_roofline_frac=round(r["lift_roofline_frac"], 4),
                 stage_ms={k: round(v, 4) for k, v in r["stage_ms"].items()},
                 launches=r["n_batches"]))

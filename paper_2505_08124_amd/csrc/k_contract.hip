@@ -94,14 +94,13 @@ __device__ __forceinline__ int tile_col(int c0, int i, int m)
 // row tile): this lane's K rows k = 8 kq + j at byte offsets roff[j] (bit j
 // of live: a real column; others are read as zero), weights split hi + lo.
 // The feature loads go in batches of GF groups of four columns (8 rows x 8
-// bytes per group), each batch in flight at once; GF keeps a batch within
-// the registers the occupancy leaves.
-template <int NT>
+// bytes per group, the last batch possibly short), each batch in flight at
+// once; GF keeps a batch within the registers the occupancy leaves.
+template <int NT, int GF>
 __device__ __forceinline__ void wide_mfma(const char* __restrict__ Fb, const uint32_t (&roff)[8],
                                           uint32_t live, bf16x8 ahi, bf16x8 alo, floatx4* acc)
 {
     constexpr int NG = NT / 4;
-    constexpr int GF = NT == 12 ? 3 : 1;
 #pragma unroll
     for (int g0 = 0; g0 < NG; g0 += GF) {
         uint2 raw[8][GF];
@@ -109,13 +108,14 @@ __device__ __forceinline__ void wide_mfma(const char* __restrict__ Fb, const uin
         for (int j = 0; j < 8; j++)
 #pragma unroll
             for (int gg = 0; gg < GF; gg++)
-                raw[j][gg] = ((live >> j) & 1u)
+                raw[j][gg] = ((live >> j) & 1u) && g0 + gg < NG
                                  ? *reinterpret_cast<const uint2*>(Fb + (roff[j] + 128u * (uint32_t)(g0 + gg)))
                                  : make_uint2(0u, 0u);
 #pragma unroll
         for (int gg = 0; gg < GF; gg++)
 #pragma unroll
             for (int e = 0; e < 4; e++) {
+                if (g0 + gg >= NG) continue;
                 u32x4 w;
 #pragma unroll
                 for (int jj = 0; jj < 4; jj++) {
@@ -154,7 +154,7 @@ __device__ __forceinline__ void mfma_chunk(const BlockLds<RT>& L, int k0, int kn
             ahi[j] = h;
             alo[j] = (__bf16)(a - (float)h);
         }
-        wide_mfma<NT>(reinterpret_cast<const char*>(feats), roff, live, ahi, alo, acc[0]);
+        wide_mfma<NT, NT == 12 ? 3 : 1>(reinterpret_cast<const char*>(feats), roff, live, ahi, alo, acc[0]);
     } else if constexpr (BF16) {
         bf16x8 ahi[RT], alo[RT];
         uint32_t roff[8];          // byte offset of this lane's column in each K row (row 0
@@ -638,7 +638,7 @@ dim3 contract_grid(int64_t q_begin, int64_t q_end)
 // as the fused kernel (bitwise-equal results), then writes E (or the running
 // sums) and den.
 template <int NT>
-__global__ __launch_bounds__(256, 2) void k_contract_chunks(
+__global__ __launch_bounds__(256, 3) void k_contract_chunks(
     int64_t n, int d, const uint32_t* __restrict__ perm, const uint32_t* __restrict__ head,
     const uint32_t* __restrict__ cnext, const uint32_t* __restrict__ cks, const float* __restrict__ cA,
     const float* __restrict__ rowden, const void* __restrict__ feats, float* __restrict__ num,
@@ -695,7 +695,7 @@ __global__ __launch_bounds__(256, 2) void k_contract_chunks(
             ahi[j] = h;
             alo[j] = (__bf16)(a - (float)h);
         }
-        wide_mfma<NT>(Fb, roff, live, ahi, alo, acc);
+        wide_mfma<NT, NT == 12 ? 2 : 1>(Fb, roff, live, ahi, alo, acc);
         ch = nx;
     }
 #pragma unroll
