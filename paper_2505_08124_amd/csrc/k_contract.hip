@@ -69,10 +69,10 @@ struct BlockLds {
     uint64_t dfx[GV][G];        //   the same, fixed point
     uint32_t scan[8];
     uint32_t chead, clast, cbase;   // chunk list of the block (walk-only launch)
-    // the step's part-list entries, staged once (both passes read them),
-    // with their owner (view slot G + row)
+    // the step's part-list entries, staged once (both passes read them);
+    // the high half of .x (the entry's tile in its pair's rectangle, unused
+    // here) is replaced by the entry's owner, view slot G + row
     uint2 stage[STAGE];
-    uint16_t sown[STAGE];
     uint32_t soff[256];         // first staged entry of each thread
     uint32_t spb[256][VPT];     // list base and length of each thread's pairs
     uint32_t scnt[256][VPT];
@@ -284,8 +284,10 @@ __global__ __launch_bounds__(256, contract_min_blocks<SPLIT ? 1 : NT>()) void k_
     floatx4 acc[RT][NT];
     float dsum = 0.0f;   // running weight sum of row t (threads t < G)
     if (SPLIT) {
+        // the rows' sums so far: the earlier view launches' walks left them
+        // in co.rowden_in (a walk run again reads the same)
         if (t == 0) { L.chead = NONE; L.clast = NONE; }
-        if (!first && t < G && q0 + t < q_end) dsum = den[orow(q0 + t)];
+        if (!first && t < G) dsum = co.rowden_in[((q0 - q_begin) / G) * G + t];
     } else if (first) {
 #pragma unroll
         for (int r = 0; r < RT; r++)
@@ -410,8 +412,7 @@ __global__ __launch_bounds__(256, contract_min_blocks<SPLIT ? 1 : NT>()) void k_
                     for (int u = 0; u < SU; u++) {
                         const uint32_t i = i0 + (uint32_t)(u * 256 + t);
                         if (i < tot) {
-                            L.stage[i] = xv[u];
-                            L.sown[i] = ow[u];
+                            L.stage[i] = make_uint2((xv[u].x & 0xFFFFu) | ((uint32_t)ow[u] << 16), xv[u].y);
                         }
                     }
                 }
@@ -434,7 +435,7 @@ __global__ __launch_bounds__(256, contract_min_blocks<SPLIT ? 1 : NT>()) void k_
                     const uint32_t s = (x.x & 0xFFFFu) - w0;
                     const float w = __uint_as_float(x.y);
                     if (s < 256u && w > 0.0f) {
-                        const uint32_t ow = L.sown[i], sl = ow / G;
+                        const uint32_t ow = x.x >> 16, sl = ow / G;
                         atomicOr(&L.bits[sl * 8 + (s >> 5)], 1u << (s & 31));
                         atomicAdd(&L.dfx[sl][ow % G], (unsigned long long)to_fx(w));
                     }
@@ -501,7 +502,7 @@ __global__ __launch_bounds__(256, contract_min_blocks<SPLIT ? 1 : NT>()) void k_
                         const uint32_t s = (x.x & 0xFFFFu) - w0;
                         const float w = __uint_as_float(x.y);
                         if (s >= 256u || !(w > 0.0f)) continue;
-                        const uint32_t ow = L.sown[i];
+                        const uint32_t ow = x.x >> 16;
                         const int wi = (int)(ow / G) * 8 + (int)(s >> 5);
                         const uint32_t bit = 1u << (s & 31);
                         const uint32_t col = L.wbase[wi] + (uint32_t)__popc(L.bits[wi] & (bit - 1u));
@@ -632,17 +633,19 @@ dim3 contract_grid(int64_t q_begin, int64_t q_end)
     return dim3((unsigned)((ng * (GBLOCK / 16) + gs - 1) / gs * gs));
 }
 
-// The chunk multiply: one workgroup per block of 16 Gaussians (the walk's
-// dispatch order), four independent waves of NT column tiles; each follows
-// the block's chunk list and multiplies every chunk with the same operations
-// as the fused kernel (bitwise-equal results), then writes E (or the running
-// sums) and den.
+// The chunk multiply, once per lift: one workgroup per block of 16
+// Gaussians (the walk's dispatch order), four independent waves of NT column
+// tiles; each follows the block's chunk lists of every view launch in order
+// (nlists lists of nblocks heads) and multiplies every chunk with the same
+// operations as the fused kernel (FP32 accumulation in the same order, so
+// the results equal a fused contraction per launch carried over in num),
+// then writes E and den.
 template <int NT>
 __global__ __launch_bounds__(256, 3) void k_contract_chunks(
     int64_t n, int d, const uint32_t* __restrict__ perm, const uint32_t* __restrict__ head,
-    const uint32_t* __restrict__ cnext, const uint32_t* __restrict__ cks, const float* __restrict__ cA,
-    const float* __restrict__ rowden, const void* __restrict__ feats, float* __restrict__ num,
-    float* __restrict__ den, int first, int last, int64_t q_begin, int64_t q_end, int local,
+    int nlists, const uint32_t* __restrict__ cnext, const uint32_t* __restrict__ cks,
+    const float* __restrict__ cA, const float* __restrict__ rowden, const void* __restrict__ feats,
+    float* __restrict__ num, float* __restrict__ den, int64_t q_begin, int64_t q_end, int local,
     const uint32_t* __restrict__ gorder)
 {
     constexpr int G = 16, BPG = GBLOCK / G;
@@ -659,27 +662,13 @@ __global__ __launch_bounds__(256, 3) void k_contract_chunks(
     auto orow = [&](int64_t q) -> int64_t { return local ? q - q_begin : (int64_t)perm[q]; };
     const int t = threadIdx.x, wv = t >> 6, lane = t & 63, m = lane & 15, kq = lane >> 4;
     const int c0 = wv * 16 * NT;   // d = 64 NT: every wave has columns
+    const int64_t nblocks = (q_end - q_begin + G - 1) / G;
     floatx4 acc[NT];
-    if (first) {
 #pragma unroll
-        for (int i = 0; i < NT; i++) acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
-    } else {
-        int64_t gq[4];
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int64_t q = q0 + 4 * kq + j;
-            gq[j] = orow(q < q_end ? q : q_end - 1);
-        }
-#pragma unroll
-        for (int i = 0; i < NT; i++)
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const float x = num[(size_t)gq[j] * d + tile_col<NT, true>(c0, i, m)];
-                acc[i][j] = (q0 + 4 * kq + j < q_end) ? x : 0.0f;
-            }
-    }
+    for (int i = 0; i < NT; i++) acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
     const char* Fb = reinterpret_cast<const char*>(feats);
-    for (uint32_t ch = head[bl]; ch != NONE;) {
+    for (int li = 0; li < nlists; li++)
+    for (uint32_t ch = head[(int64_t)li * nblocks + bl]; ch != NONE;) {
         const uint32_t nx = cnext[ch];
         const float* ap = cA + (size_t)ch * (KC * G) + m * KC + 8 * kq;
         const uint32_t* kp = cks + (size_t)ch * KC + 8 * kq;
@@ -708,7 +697,7 @@ __global__ __launch_bounds__(256, 3) void k_contract_chunks(
 #pragma unroll
         for (int i = 0; i < NT; i++) {
             const float a = acc[i][j];
-            num[(size_t)g * d + tile_col<NT, true>(c0, i, m)] = last ? (dn > 0.0f ? a / dn : 0.0f) : a;
+            num[(size_t)g * d + tile_col<NT, true>(c0, i, m)] = dn > 0.0f ? a / dn : 0.0f;
         }
     }
     if (t < G && q0 + t < q_end) den[orow(q0 + t)] = rowden[bl * G + t];
@@ -843,21 +832,20 @@ void launch_contract_walk(int64_t n, int nb, int d, const uint32_t* perm, const 
                            (int)first, 0, q_begin, q_end, (int)local, gorder, co);
 }
 
-void launch_contract_chunks(int64_t n, int d, const uint32_t* perm, const ChunkOut& co,
-                            const void* feats, float* num, float* den, bool first, bool last,
-                            int64_t q_begin, int64_t q_end, bool local, const uint32_t* gorder,
-                            hipStream_t st)
+void launch_contract_chunks(int64_t n, int d, const uint32_t* perm, const ChunkOut& co, int nlists,
+                            const void* feats, float* num, float* den, int64_t q_begin,
+                            int64_t q_end, bool local, const uint32_t* gorder, hipStream_t st)
 {
     if (n <= 0 || q_end <= q_begin || !contract_split(d, true)) return;
     const dim3 grid = contract_grid(q_begin, q_end);
     if (d == 768)
-        hipLaunchKernelGGL(k_contract_chunks<12>, grid, dim3(256), 0, st, n, d, perm, co.head,
-                           co.cnext, co.cks, co.cA, co.rowden, feats, num, den, (int)first,
-                           (int)last, q_begin, q_end, (int)local, gorder);
+        hipLaunchKernelGGL(k_contract_chunks<12>, grid, dim3(256), 0, st, n, d, perm, co.head, nlists,
+                           co.cnext, co.cks, co.cA, co.rowden, feats, num, den, q_begin, q_end,
+                           (int)local, gorder);
     else
-        hipLaunchKernelGGL(k_contract_chunks<16>, grid, dim3(256), 0, st, n, d, perm, co.head,
-                           co.cnext, co.cks, co.cA, co.rowden, feats, num, den, (int)first,
-                           (int)last, q_begin, q_end, (int)local, gorder);
+        hipLaunchKernelGGL(k_contract_chunks<16>, grid, dim3(256), 0, st, n, d, perm, co.head, nlists,
+                           co.cnext, co.cks, co.cA, co.rowden, feats, num, den, q_begin, q_end,
+                           (int)local, gorder);
 }
 
 }  // namespace slag

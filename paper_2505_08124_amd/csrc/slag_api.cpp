@@ -351,6 +351,20 @@ struct ContractTarget {
 };
 
 // The contraction of one view batch whose part lists are on the device.
+// Room for `want` contraction chunks, keeping the first chunk_used chunks
+// (the lists of the lift's earlier view launches).
+static slag_status grow_chunks(slag_ctx* c, uint64_t want)
+{
+    if (want <= c->chunk_cap && c->cks.p) return SLAG_OK;
+    const uint64_t cap = std::max<uint64_t>(want + want / 8, 1024);
+    CK(grow_keep(c, c->cks, cap * 128 + 16, c->chunk_used * 128));
+    CK(grow_keep(c, c->cA, cap * 2048 + 16, c->chunk_used * 2048));
+    CK(grow_keep(c, c->cnext, cap * 4 + 16, c->chunk_used * 4));
+    c->chunk_cap = cap;
+    c->gen++;   // a recorded graph may hold the old addresses
+    return SLAG_OK;
+}
+
 static slag_status contract_batch(slag_ctx* c, Batch& B, bool first, bool last,
                                   const ContractTarget& ct)
 {
@@ -380,42 +394,64 @@ static slag_status contract_batch(slag_ctx* c, Batch& B, bool first, bool last,
                         c->vcnt.as<uint32_t>(), c->pinfo.as<uint2>(), c->part.as<uint2>(), ct.table,
                         ct.out, ct.den, first, last, ct.q_begin, q_end, ct.local, gorder, c->st);
     } else if (q_end > ct.q_begin && c->n > 0) {
-        // the walk writes each block's chunk list; the chunk count is read
-        // back after an eager walk (a walk that ran out of room is re-run
-        // with room for all), and a recorded graph reuses it
+        // Each view launch's walk appends its blocks' chunk lists to one
+        // buffer (and carries the rows' weight sums in rowden); after the
+        // last launch one multiply takes every launch's lists.  An eager
+        // walk reads the chunk count back: one that ran out of room is run
+        // again after the buffer has grown (the earlier launches' chunks
+        // copied over); a recorded graph reuses the sizes.
         const bool whole = ct.q_begin == 0 && q_end == c->n;
         const uint64_t nblocks = (uint64_t)((q_end - ct.q_begin + 15) / 16);
-        uint64_t cap = (whole && B.nchunks) ? B.nchunks : nblocks * 12 + 1024;   // a guess first
-        cap = std::min<uint64_t>(cap, 0xFFFFFFF0ull);
-        CK(ensure(c, c->chead, nblocks * 4 + 16));
-        CK(ensure(c, c->rowden, nblocks * 64 + 16));
+        const int nbat = (int)c->plan.size();
+        const int bi = (int)(&B - c->plan.data());
+        if (bi < 0 || bi >= nbat) FAIL(c, SLAG_E_STATE, "contraction of a launch outside the plan");
+        CK(ensure(c, c->chead, (uint64_t)nbat * nblocks * 4 + 16));
+        CK(ensure(c, c->rowden, 2 * nblocks * 64 + 16));   // two halves: in, out by launch parity
         uint64_t* small = c->small.as<uint64_t>();
+        uint32_t* counter = reinterpret_cast<uint32_t*>(small + SM_CHUNKS);
+        if (first) {
+            c->chunk_used = 0;
+            launch_fill_u32(counter, 2, 0u, c->st);
+        }
+        if (!c->capturing) {
+            // first guess one chunk per block: most first lifts outgrow it
+            // once (so the re-run path is the common one, not a rare one)
+            const uint64_t want = c->chunk_used + ((whole && B.nchunks) ? B.nchunks : nblocks + 1024);
+            CK(grow_chunks(c, want));
+        }
         for (;;) {
-            CK(ensure(c, c->cks, cap * 128 + 16));
-            CK(ensure(c, c->cA, cap * 2048 + 16));
-            CK(ensure(c, c->cnext, cap * 4 + 16));
+            float* rd = c->rowden.as<float>();
             ChunkOut co{c->cks.as<uint32_t>(), c->cA.as<float>(), c->cnext.as<uint32_t>(),
-                        c->chead.as<uint32_t>(), c->rowden.as<float>(),
-                        reinterpret_cast<uint32_t*>(small + SM_CHUNKS), (uint32_t)cap};
-            launch_fill_u32(co.counter, 2, 0u, c->st);
+                        c->chead.as<uint32_t>() + (uint64_t)bi * nblocks,
+                        rd + (uint64_t)((bi + 1) & 1) * nblocks * 16, rd + (uint64_t)(bi & 1) * nblocks * 16,
+                        counter, (uint32_t)std::min<uint64_t>(c->chunk_cap, 0xFFFFFFF0ull)};
             launch_contract_walk(c->n, B.nb, ct.d, c->perm.as<uint32_t>(),
                                  c->pair_of_m.as<uint32_t>(), B.views.as<ViewDev>(),
                                  c->vlist.as<uint16_t>(), c->vcnt.as<uint32_t>(),
                                  c->pinfo.as<uint2>(), c->part.as<uint2>(), ct.den, first,
                                  ct.q_begin, q_end, ct.local, gorder, co, c->st);
-            if (!c->capturing) {
-                CK(read_small(c, SM_CHUNKS, 1));
-                const uint64_t used = c->host_small[SM_CHUNKS] & 0xFFFFFFFFull;
-                if (used > cap) {
-                    if (used > 0xFFFFFFF0ull) FAIL(c, SLAG_E_CAPACITY, "too many contraction chunks");
-                    cap = used;
-                    continue;
-                }
-                if (whole) B.nchunks = used;
+            if (c->capturing) break;
+            CK(read_small(c, SM_CHUNKS, 1));
+            const uint64_t used = c->host_small[SM_CHUNKS] & 0xFFFFFFFFull;
+            if (used > c->chunk_cap) {
+                // nothing past the buffer was written, and the walk reads
+                // only its inputs: grow, rewind the count, walk again
+                if (used > 0xFFFFFFF0ull) FAIL(c, SLAG_E_CAPACITY, "too many contraction chunks");
+                CK(grow_chunks(c, used));
+                launch_fill_u32(counter, 1, (uint32_t)c->chunk_used, c->st);
+                continue;
             }
-            launch_contract_chunks(c->n, ct.d, c->perm.as<uint32_t>(), co, ct.table, ct.out, ct.den,
-                                   first, last, ct.q_begin, q_end, ct.local, gorder, c->st);
+            if (whole) B.nchunks = used - c->chunk_used;
+            c->chunk_used = used;
             break;
+        }
+        if (last) {
+            float* rd = c->rowden.as<float>();
+            ChunkOut co{c->cks.as<uint32_t>(), c->cA.as<float>(), c->cnext.as<uint32_t>(),
+                        c->chead.as<uint32_t>(), rd, rd + (uint64_t)(bi & 1) * nblocks * 16, counter,
+                        (uint32_t)std::min<uint64_t>(c->chunk_cap, 0xFFFFFFF0ull)};
+            launch_contract_chunks(c->n, ct.d, c->perm.as<uint32_t>(), co, bi + 1, ct.table, ct.out,
+                                   ct.den, ct.q_begin, q_end, ct.local, gorder, c->st);
         }
     }
     CK(stage_end(c, ST_CONTRACT, ev));

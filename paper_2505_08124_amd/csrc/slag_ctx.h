@@ -167,6 +167,8 @@ struct slag_ctx {
     slag_host::DevBuf gkey, gkey_alt, gval, gval_alt;
     // walk + chunk multiply (D >= 768 BF16): chunk lists of the blocks
     slag_host::DevBuf cks, cA, cnext, chead, rowden;
+    uint64_t chunk_cap = 0;    // chunks the buffers hold
+    uint64_t chunk_used = 0;   // chunks of the lift's earlier view launches (eager)
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     slag_stats graph_stats{};

@@ -213,7 +213,8 @@ struct ChunkOut {
     float* cA;           // [cap][16][32] the 16 rows' weights of each column
     uint32_t* cnext;     // [cap] next chunk of the block, NONE after its last
     uint32_t* head;      // [blocks] first chunk of each block, NONE if it has none
-    float* rowden;       // [blocks][16] the rows' weight sums (den after this launch)
+    const float* rowden_in;   // [blocks][16] the rows' weight sums of the earlier launches
+    float* rowden;       // [blocks][16] the same after this launch (den after the last)
     uint32_t* counter;   // chunks taken (zeroed by the caller); may exceed cap,
     uint32_t cap;        //   and then nothing past cap is written
 };
@@ -228,18 +229,19 @@ void launch_contract(int64_t n, int nb, int d, bool bf16, const uint32_t* perm,
                      const uint32_t* vcnt, const uint2* pinfo, const uint2* part, const void* feats,
                      float* num, float* den, bool first, bool last, int64_t q_begin, int64_t q_end,
                      bool local, const uint32_t* gorder, hipStream_t st);
-// The same split in two (contract_split(d, bf16)): the walk writes co; after
-// it (and after the caller has checked co.counter <= co.cap), the chunk
-// multiply writes num and den.
+// The same split in two (contract_split(d, bf16)): each view launch's walk
+// appends to co (heads at co.head, its rows' running sums in co.rowden,
+// starting from zero when `first`); after the last one (and after the caller
+// has checked co.counter <= co.cap), one chunk multiply over the nlists
+// launches' lists (heads co.head[l][block]) writes E and den.
 void launch_contract_walk(int64_t n, int nb, int d, const uint32_t* perm, const uint32_t* pair_of_m,
                           const ViewDev* views, const uint16_t* vlist, const uint32_t* vcnt,
                           const uint2* pinfo, const uint2* part, const float* den, bool first,
                           int64_t q_begin, int64_t q_end, bool local, const uint32_t* gorder,
                           const ChunkOut& co, hipStream_t st);
-void launch_contract_chunks(int64_t n, int d, const uint32_t* perm, const ChunkOut& co,
-                            const void* feats, float* num, float* den, bool first, bool last,
-                            int64_t q_begin, int64_t q_end, bool local, const uint32_t* gorder,
-                            hipStream_t st);
+void launch_contract_chunks(int64_t n, int d, const uint32_t* perm, const ChunkOut& co, int nlists,
+                            const void* feats, float* num, float* den, int64_t q_begin,
+                            int64_t q_end, bool local, const uint32_t* gorder, hipStream_t st);
 
 // ---- codec ----
 enum { GEMM_NONE = 0, GEMM_GELU = 1, GEMM_GELU_BWD = 2 };

@@ -51,6 +51,49 @@ def test_d768_small_scene_full_parity():
     L.close()
 
 
+@pytest.mark.parametrize("max_views,chunk", [(0, 0), (2, 0), (2, 4096), (0, 1024)])
+def test_d768_split_contraction_across_launches(max_views, chunk):
+    """At D = 768 the contraction runs as a walk per view launch (chunk
+    lists appended to one buffer, grown and the walk re-run when the first
+    guess is too small) and one chunk multiply after the last launch. With
+    the same view plan, the graph replay and the chunked output give the
+    eager lift's bits; across plans (one launch against three) den is
+    bitwise equal (per-view sums in view order) and E equal to FP32
+    rounding (the chunks group the columns differently)."""
+    import paper_2505_08124_amd as slag
+    sc = make_scene("stress_4m", n=40000, views=dict(n=6))
+
+    def plain(mv):
+        L0 = slag.Lifter(0, max_views_per_launch=mv)
+        L0.set_scene(sc)
+        L0.lift()
+        out = L0.embeddings()
+        nb = L0.stats()["n_batches"]
+        L0.close()
+        return out, nb
+
+    (E0, den0), nb = plain(max_views)
+    assert nb == (3 if max_views else 1)
+    L = slag.Lifter(0, max_views_per_launch=max_views, flags=slag.SLAG_FLAG_GRAPH)
+    L.set_scene(sc)
+    if chunk:
+        E = np.full(E0.shape, np.nan, np.float32)
+        den = np.full(den0.shape, np.nan, np.float32)
+        slag.slag_lift_chunked(L.ctx, chunk, E, den)
+    else:
+        L.lift()
+        E, den = L.embeddings()
+        L.lift()                               # graph replay
+        E2, den2 = L.embeddings()
+        assert np.array_equal(E2, E) and np.array_equal(den2, den)
+    L.close()
+    assert np.array_equal(den, den0) and np.array_equal(E, E0)
+    if max_views:
+        (E1, den1), _ = plain(0)
+        assert np.array_equal(den1, den0)
+        np.testing.assert_allclose(E0, E1, rtol=1e-5, atol=1e-6)
+
+
 def test_replan_when_a_launch_would_overflow():
     """A launch whose tile intersections or part slots exceed the cap is
     re-planned with fewer views per launch; the result equals the one-launch
