@@ -553,14 +553,19 @@ __global__ __launch_bounds__(256) void k_row_len(int64_t n, int nb, const uint32
                                                  uint32_t max_rows,
                                                  const uint32_t* __restrict__ rank,
                                                  const uint32_t* __restrict__ pair_of_m,
+                                                 const uint32_t* __restrict__ blk_off, int nblk,
                                                  const uint32_t* __restrict__ wlen,
                                                  uint32_t* __restrict__ len, uint32_t* __restrict__ gid)
 {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= n || !flag[g] || ridx[g] >= max_rows) return;
     const uint32_t q = rank[g];
+    const int cb = (int)(q / GBLOCK);
     uint32_t l = 0;
     for (int v = 0; v < nb; v++) {
+        // (view, block) without visible pairs: the pair map is not written there
+        const int64_t bi = (int64_t)v * nblk + cb;
+        if (blk_off[bi + 1] == blk_off[bi]) continue;
         const uint32_t p = pair_of_m[(int64_t)v * n + q];
         if (p != NONE) l += wlen[p];
     }
@@ -575,6 +580,7 @@ __global__ __launch_bounds__(256) void k_row_gather(int64_t n, int nb, uint32_t 
                                                     uint32_t nnz0, uint32_t seg0,
                                                     const uint32_t* __restrict__ rank,
                                                     const uint32_t* __restrict__ pair_of_m,
+                                                    const uint32_t* __restrict__ blk_off, int nblk,
                                                     const uint32_t* __restrict__ wlen,
                                                     const uint32_t* __restrict__ part_base,
                                                     const uint2* __restrict__ wrow,
@@ -588,7 +594,10 @@ __global__ __launch_bounds__(256) void k_row_gather(int64_t n, int nb, uint32_t 
     const float inv = 1.0f / den[g];
     uint32_t o = nnz0 + off[r];
     row_ptr[r] = o;
+    const int cb = (int)(q / GBLOCK);
     for (int v = 0; v < nb; v++) {
+        const int64_t bi = (int64_t)v * nblk + cb;
+        if (blk_off[bi + 1] == blk_off[bi]) continue;
         const uint32_t p = pair_of_m[(int64_t)v * n + q];
         if (p == NONE) continue;
         const uint32_t b = part_base[p];
@@ -625,22 +634,25 @@ void launch_pick_rows(int64_t n, const float* den, uint64_t seed, uint32_t thres
 
 void launch_row_len(int64_t n, int nb, const uint32_t* flag, const uint32_t* ridx,
                     uint32_t max_rows, const uint32_t* rank, const uint32_t* pair_of_m,
-                    const uint32_t* wlen, uint32_t* len, uint32_t* gid, hipStream_t st)
+                    const uint32_t* blk_off, int nblk, const uint32_t* wlen, uint32_t* len,
+                    uint32_t* gid, hipStream_t st)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_row_len, dim3(blocks(n)), dim3(256), 0, st, n, nb, flag, ridx, max_rows,
-                       rank, pair_of_m, wlen, len, gid);
+                       rank, pair_of_m, blk_off, nblk, wlen, len, gid);
 }
 
 void launch_row_gather(int64_t n, int nb, uint32_t rows, const uint32_t* gid, const uint32_t* off,
                        uint32_t nnz0, uint32_t seg0, const uint32_t* rank,
-                       const uint32_t* pair_of_m, const uint32_t* wlen, const uint32_t* part_base,
-                       const uint2* wrow, const float* den, uint32_t* row_ptr, uint32_t* col,
-                       float* w, hipStream_t st)
+                       const uint32_t* pair_of_m, const uint32_t* blk_off, int nblk,
+                       const uint32_t* wlen, const uint32_t* part_base, const uint2* wrow,
+                       const float* den, uint32_t* row_ptr, uint32_t* col, float* w,
+                       hipStream_t st)
 {
     if (!rows) return;
     hipLaunchKernelGGL(k_row_gather, dim3(blocks(rows)), dim3(256), 0, st, n, nb, rows, gid, off,
-                       nnz0, seg0, rank, pair_of_m, wlen, part_base, wrow, den, row_ptr, col, w);
+                       nnz0, seg0, rank, pair_of_m, blk_off, nblk, wlen, part_base, wrow, den,
+                       row_ptr, col, w);
 }
 
 void launch_copy_rows(uint32_t rows, int d, const uint32_t* gid, const float* src, float* dst,

@@ -453,11 +453,9 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
     const int blk = blockIdx.y, nblk = gridDim.y;
     const int64_t bi0 = (int64_t)vl * nblk + blk;
     if (blk_off[bi0 + 1] == blk_off[bi0]) {
-        // no visible pair in this (view, block): only the map entries
-        for (int i = 0; i < PER_THREAD; i++) {
-            const int64_t g = (int64_t)blk * CPB + (int64_t)i * 256 + threadIdx.x;
-            if (g < n) pair_of_m[(int64_t)vl * n + g] = NONE;
-        }
+        // no visible pair in this (view, block): nothing to emit, and the pair
+        // map is not written (its readers skip such (view, block)s by the
+        // scanned counts)
         if (threadIdx.x == 0) {
             blk_tot[2 * bi0] = 0;
             blk_tot[2 * bi0 + 1] = 0;

@@ -1246,6 +1246,7 @@ slag_status run_lift(slag_ctx* c, bool codec)
     }
     c->have_out = true;
     c->out_is_codec = codec;
+    c->lists_valid = true;
     K.have_codes = codec;
     return SLAG_OK;
 }
@@ -1660,6 +1661,7 @@ extern "C" slag_status slag_render(slag_ctx* c, int32_t view, const float* attr,
     c->front_only = true;
     c->front_ival = nullptr;
     c->last_v0 = -1;
+    c->lists_valid = false;
     ContractTarget ct{};
     const slag_status s = c->n > 0 ? lift_batch(c, c->rbatch, true, true, ct) : SLAG_OK;
     c->front_only = false;

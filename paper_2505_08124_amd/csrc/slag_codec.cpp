@@ -361,7 +361,8 @@ slag_status slag_codec_add_lift_rows(slag_ctx* c, int64_t max_rows, uint64_t see
     CodecState& S = c->codec;
     if (added) *added = 0;
     if (max_rows < 0) FAIL(c, SLAG_E_INVALID_ARG, "negative row count");
-    if (!c->have_out || c->out_is_codec) FAIL(c, SLAG_E_STATE, "needs a plain lift first");
+    if (!c->have_out || c->out_is_codec || !c->lists_valid)
+        FAIL(c, SLAG_E_STATE, "needs a plain lift first (and no render since)");
     if (c->plan.size() != 1) FAIL(c, SLAG_E_STATE, "training rows need all views in one launch");
     if (S.d != c->d) FAIL(c, SLAG_E_STATE, "codec dimension differs from the features'");
     const int64_t n = c->n;
@@ -392,8 +393,9 @@ slag_status slag_codec_add_lift_rows(slag_ctx* c, int64_t max_rows, uint64_t see
     CK(ensure(c, S.roff, (size_t)rows * 4 + 16));
     CK(ensure(c, S.rgid, (size_t)rows * 4 + 16));
     launch_row_len(n, B.nb, S.rflag.as<uint32_t>(), S.ridx.as<uint32_t>(), rows,
-                   c->rank.as<uint32_t>(), c->pair_of_m.as<uint32_t>(), c->wlen.as<uint32_t>(),
-                   S.rlen.as<uint32_t>(), S.rgid.as<uint32_t>(), st);
+                   c->rank.as<uint32_t>(), c->pair_of_m.as<uint32_t>(), c->blk_vis.as<uint32_t>(),
+                   count_blocks_per_view(n), c->wlen.as<uint32_t>(), S.rlen.as<uint32_t>(),
+                   S.rgid.as<uint32_t>(), st);
     HC(c, hipMemcpyAsync(S.roff.p, S.rlen.p, (size_t)rows * 4, hipMemcpyDeviceToDevice, st));
     CK(ensure_scan(c, rows));
     scan_u32(S.roff.as<uint32_t>(), rows, small + SM_TOTALS, c->scan_ws.p, st);
@@ -410,7 +412,8 @@ slag_status slag_codec_add_lift_rows(slag_ctx* c, int64_t max_rows, uint64_t see
     CK(grow_keep(c, S.pF, ((size_t)S.pool_seg + seg_new) * d * 4 + 16, (size_t)S.pool_seg * d * 4));
     launch_row_gather(n, B.nb, rows, S.rgid.as<uint32_t>(), S.roff.as<uint32_t>(),
                       (uint32_t)S.pool_nnz, (uint32_t)S.pool_seg, c->rank.as<uint32_t>(),
-                      c->pair_of_m.as<uint32_t>(), c->wlen.as<uint32_t>(), c->psz.as<uint32_t>(),
+                      c->pair_of_m.as<uint32_t>(), c->blk_vis.as<uint32_t>(), count_blocks_per_view(n),
+                      c->wlen.as<uint32_t>(), c->psz.as<uint32_t>(),
                       c->wrow.as<uint2>(), c->den.as<float>(),
                       S.prow.as<uint32_t>() + S.pool_rows, S.pcol.as<uint32_t>(),
                       S.pw.as<float>(), st);

@@ -160,6 +160,7 @@ struct slag_ctx {
     bool capturing = false;
     // render-back: the launch runs projection through the tile ranges only
     bool front_only = false;
+    bool lists_valid = false;                // the last lift's pair lists are still in the buffers
     const uint32_t* front_ival = nullptr;   // its sorted list entries (pairs)
     slag_host::Batch rbatch;                 // its one-view launch
     slag_host::DevBuf rattr, rout;           // staged host attributes / outputs

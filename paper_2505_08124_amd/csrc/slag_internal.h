@@ -293,14 +293,18 @@ void launch_adam(int64_t n, float* p, const float* g, float* m, float* v, float 
 void launch_to_f32(int64_t n, const void* src, bool bf16, float* dst, hipStream_t st);
 void launch_pick_rows(int64_t n, const float* den, uint64_t seed, uint32_t thresh, uint32_t* flag,
                       hipStream_t st);
+// (the pair map is read only in (view, block)s with visible pairs, by blk_off,
+// the scanned per-(view, block) counts, nblk blocks per view)
 void launch_row_len(int64_t n, int nb, const uint32_t* flag, const uint32_t* ridx,
                     uint32_t max_rows, const uint32_t* rank, const uint32_t* pair_of_m,
-                    const uint32_t* wlen, uint32_t* len, uint32_t* gid, hipStream_t st);
+                    const uint32_t* blk_off, int nblk, const uint32_t* wlen, uint32_t* len,
+                    uint32_t* gid, hipStream_t st);
 void launch_row_gather(int64_t n, int nb, uint32_t rows, const uint32_t* gid, const uint32_t* off,
                        uint32_t nnz0, uint32_t seg0, const uint32_t* rank,
-                       const uint32_t* pair_of_m, const uint32_t* wlen, const uint32_t* part_base,
-                       const uint2* wrow, const float* den, uint32_t* row_ptr, uint32_t* col,
-                       float* w, hipStream_t st);
+                       const uint32_t* pair_of_m, const uint32_t* blk_off, int nblk,
+                       const uint32_t* wlen, const uint32_t* part_base, const uint2* wrow,
+                       const float* den, uint32_t* row_ptr, uint32_t* col, float* w,
+                       hipStream_t st);
 void launch_copy_rows(uint32_t rows, int d, const uint32_t* gid, const float* src, float* dst,
                       hipStream_t st);
 
