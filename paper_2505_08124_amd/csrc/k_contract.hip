@@ -46,8 +46,10 @@ constexpr float kFx = 1099511627776.0f;          // 2^40
 constexpr float kFxInv = 1.0f / 1099511627776.0f;
 __device__ __forceinline__ int64_t to_fx(float w) { return (int64_t)(w * kFx); }
 __device__ __forceinline__ float from_fx(int64_t x) { return (float)x * kFxInv; }
-// Blocks per XCD chunk of the contraction's launch order (0: plain order).
+// Blocks per XCD chunk of the contraction's launch order (0: plain order):
+// the fused kernel and the walk, and the chunk multiply.
 constexpr int kXcdChunk = 16;
+constexpr int kXcdChunkMul = 16;
 constexpr int kContractRT = 1;  // row tiles per block (G = 16 Gaussians; 2 and 4 measured slower)
 
 // G = 16 RT rows per block; thread t walks row t % G and views
@@ -626,9 +628,9 @@ void launch_nt(int64_t n, int nb, int d, bool bf16, const uint32_t* perm, const 
 
 // Grid of a contraction launch over [q_begin, q_end): the Gaussian blocks met,
 // GBLOCK / 16 workgroups each, in whole XCD groups.
-dim3 contract_grid(int64_t q_begin, int64_t q_end)
+dim3 contract_grid(int64_t q_begin, int64_t q_end, int chunk = kXcdChunk)
 {
-    const int64_t gs = kXcdChunk > 0 ? 8 * kXcdChunk : 1;
+    const int64_t gs = chunk > 0 ? 8 * chunk : 1;
     const int64_t ng = (q_end + GBLOCK - 1) / GBLOCK - q_begin / GBLOCK;
     return dim3((unsigned)((ng * (GBLOCK / 16) + gs - 1) / gs * gs));
 }
@@ -650,9 +652,9 @@ __global__ __launch_bounds__(256, 3) void k_contract_chunks(
 {
     constexpr int G = 16, BPG = GBLOCK / G;
     int64_t lb = blockIdx.x;
-    if (kXcdChunk > 0) {
-        const int64_t gs = 8 * kXcdChunk, w = lb % gs;
-        lb = lb - w + (w % 8) * kXcdChunk + w / 8;
+    if (kXcdChunkMul > 0) {
+        const int64_t gs = 8 * kXcdChunkMul, w = lb % gs;
+        lb = lb - w + (w % 8) * kXcdChunkMul + w / 8;
     }
     const int64_t ng = (q_end + GBLOCK - 1) / GBLOCK - q_begin / GBLOCK;
     if (lb >= ng * BPG) return;
@@ -837,7 +839,7 @@ void launch_contract_chunks(int64_t n, int d, const uint32_t* perm, const ChunkO
                             int64_t q_end, bool local, const uint32_t* gorder, hipStream_t st)
 {
     if (n <= 0 || q_end <= q_begin || !contract_split(d, true)) return;
-    const dim3 grid = contract_grid(q_begin, q_end);
+    const dim3 grid = contract_grid(q_begin, q_end, kXcdChunkMul);
     if (d == 768)
         hipLaunchKernelGGL(k_contract_chunks<12>, grid, dim3(256), 0, st, n, d, perm, co.head, nlists,
                            co.cnext, co.cks, co.cA, co.rowden, feats, num, den, q_begin, q_end,

@@ -26,8 +26,8 @@ slag_status ensure(slag_ctx* c, DevBuf& b, size_t bytes)
 {
     if (bytes <= b.cap && b.p) return SLAG_OK;
     if (b.p) {
-        hipStreamSynchronize(c->st);
-        hipFree(b.p);
+        (void)hipStreamSynchronize(c->st);
+        (void)hipFree(b.p);
         b.p = nullptr;
         b.cap = 0;
         c->gen++;   // a recorded graph may hold the old address
@@ -46,7 +46,7 @@ slag_status ensure(slag_ctx* c, DevBuf& b, size_t bytes)
 
 void release(DevBuf& b)
 {
-    if (b.p) hipFree(b.p);
+    if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
     b.cap = 0;
 }
@@ -64,7 +64,7 @@ slag_status grow_keep(slag_ctx* c, DevBuf& b, size_t bytes, size_t keep)
             c->err = std::string("grow_keep copy: ") + hipGetErrorString(e);
             return SLAG_E_DEVICE;
         }
-        hipStreamSynchronize(c->st);
+        (void)hipStreamSynchronize(c->st);
     }
     release(b);
     b = nb;
@@ -873,8 +873,8 @@ slag_status slag_create(int32_t device, void* hip_stream, const slag_options* op
 void slag_destroy(slag_ctx* c)
 {
     if (!c) return;
-    hipSetDevice(c->device);
-    if (c->st) hipStreamSynchronize(c->st);
+    (void)hipSetDevice(c->device);
+    if (c->st) (void)hipStreamSynchronize(c->st);
     DevBuf* bufs[] = {&c->means, &c->scales, &c->quats, &c->opac, &c->cov3, &c->covd, &c->lo2,
                       &c->ids, &c->feats,
                       &c->num, &c->den, &c->ns_tile, &c->segl, &c->sat, &c->tcnt, &c->blk_vis,
@@ -896,13 +896,13 @@ void slag_destroy(slag_ctx* c)
     for (DevBuf* b : bufs) release(*b);
     codec_release(c);
     for (auto& b : c->plan) { release(b.views); release(b.bucket_view); release(b.view_cls); }
-    for (auto& e : c->events) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
+    for (auto& e : c->events) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     for (auto e : c->tune_ev)
-        if (e) hipEventDestroy(e);
-    for (auto e : c->free_events) hipEventDestroy(e);
-    if (c->host_small) hipHostFree(c->host_small);
-    if (c->chost) hipHostFree(c->chost);
-    if (c->own_stream && c->st) hipStreamDestroy(c->st);
+        if (e) (void)hipEventDestroy(e);
+    for (auto e : c->free_events) (void)hipEventDestroy(e);
+    if (c->host_small) (void)hipHostFree(c->host_small);
+    if (c->chost) (void)hipHostFree(c->chost);
+    if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
     delete c;
 }
 
@@ -1134,8 +1134,8 @@ static slag_status lift_sequence(slag_ctx* c, bool codec)
 
 static void drop_graph(slag_ctx* c)
 {
-    if (c->gexec) hipGraphExecDestroy(c->gexec);
-    if (c->graph) hipGraphDestroy(c->graph);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
     c->gexec = nullptr;
     c->graph = nullptr;
     c->graph_mode = -1;
@@ -1152,11 +1152,11 @@ static slag_status capture_lift(slag_ctx* c, bool codec)
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(c->st, &g);
     if (s != SLAG_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return s;
     }
     if (e != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         c->err = std::string("graph capture: ") + hipGetErrorString(e);
         return SLAG_E_DEVICE;
     }
@@ -1264,7 +1264,7 @@ static slag_status chunked_lift(slag_ctx* c, int64_t R, void* out, slag_dtype dt
     if (dtype == SLAG_BF16) CK(ensure(c, c->cbf, (size_t)R * d * 2));
     const size_t hbytes = (size_t)R * d * esz + (size_t)R * 4;
     if (c->chost_cap < hbytes) {
-        if (c->chost) hipHostFree(c->chost);
+        if (c->chost) (void)hipHostFree(c->chost);
         c->chost = nullptr;
         c->chost_cap = 0;
         if (hipHostMalloc(&c->chost, hbytes, hipHostMallocDefault) != hipSuccess)
