@@ -232,7 +232,7 @@ def kernel_rooflines(res, workload):
     out = {}
     nl = int(res.get("n_batches") or 1)
     comp = res["stage_ms"].get("composite", 0.0)
-    ncomp = nl * max(1, len(res.get("tuning") or []))   # one launch per (view launch, image size)
+    ncomp = nl   # one compositing launch per view launch, all image sizes together
     if res.get("n_tests") and comp > 0:
         ach = res["n_tests"] * OPS_PER_TEST / (comp * 1e-3) / 1e12
         ach19 = res["n_tests"] * SLOTS_PER_TEST / (comp * 1e-3) / 1e12

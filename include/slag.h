@@ -73,8 +73,15 @@ enum {
                                    sequence; later lifts launch the graph.  Replays record
                                    ms_total but no per-stage times. */
     SLAG_FLAG_AUTOTUNE = 16     /* eager lifts time every compositing variant once per image
-                                   size (all give bitwise-equal results) and keep the
-                                   fastest for later lifts of this context */
+                                   size (all give bitwise-equal results); a launch then
+                                   composites all its views in one kernel with the variant of
+                                   least summed time over its image sizes.  Tuned sizes are
+                                   kept for later lifts of this context and, if the
+                                   environment variable SLAG_TUNE_CACHE names a file, read
+                                   from it at slag_create and written back after tuning
+                                   (text, one line per device kind and image size; lines of
+                                   other devices or variant sets are kept, unreadable lines
+                                   ignored) */
 };
 
 typedef struct {
@@ -112,7 +119,11 @@ typedef struct {
                                        alpha T (default), 1 = the Gaussian kernel
                                        exp(-q/2) itself (the paper's weight equation,
                                        with the contributing set of the walk) */
-    int64_t reserved[1];
+    int32_t composite_variant;      /* 0: the tuned variant (SLAG_FLAG_AUTOTUNE) or variant
+                                       0; v + 1 forces compositing variant v (0 <= v <
+                                       slag_variant_count(), names from slag_variant_name);
+                                       every variant gives bitwise-equal results */
+    int32_t reserved;
 } slag_options;
 
 typedef struct {
@@ -238,7 +249,8 @@ slag_status slag_get_stats(slag_ctx* ctx, slag_stats* stats);
 const char* slag_stage_name(int32_t stage);
 
 /* Compositing variant chosen per image size (SLAG_FLAG_AUTOTUNE), with the
- * time of each variant on the lift that tuned it. */
+ * time of each variant on the lift that tuned it (or as read from the tuning
+ * cache). */
 typedef struct {
     int32_t width, height;
     int32_t variant;                /* index of the fastest, see slag_variant_name() */
@@ -248,6 +260,8 @@ typedef struct {
 /* Copies up to `cap` entries to out; *n receives the number of tuned sizes. */
 slag_status slag_get_tuning(slag_ctx* ctx, slag_tuning* out, int32_t cap, int32_t* n);
 const char* slag_variant_name(int32_t variant);
+/* Number of compositing variants (at most 8). */
+int32_t slag_variant_count(void);
 
 /* Debug exports for the last view batch (needs SLAG_FLAG_KEEP_DEBUG).
  * Tile lists of view `view`: entries ordered by (tile, depth, Gaussian) with

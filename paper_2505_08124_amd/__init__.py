@@ -48,7 +48,7 @@ class slag_options(ctypes.Structure):
                 ("near_z", ctypes.c_float), ("guard", ctypes.c_float),
                 ("tile_size", ctypes.c_int32), ("deterministic", ctypes.c_int32),
                 ("labels_per_pixel", ctypes.c_int32), ("weight_mode", ctypes.c_int32),
-                ("reserved", ctypes.c_int64 * 1)]
+                ("composite_variant", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class slag_stats(ctypes.Structure):
@@ -76,6 +76,7 @@ EXPORTS = ["slag_create", "slag_destroy", "slag_last_error", "slag_set_gaussians
            "slag_set_cameras", "slag_set_segments", "slag_set_features", "slag_lift",
            "slag_get_embeddings", "slag_get_stats", "slag_stage_name", "slag_debug_tile_lists",
            "slag_debug_weights", "slag_get_tuning", "slag_variant_name", "slag_get_debug",
+           "slag_variant_count",
            # include/slag_codec.h
            "slag_codec_init", "slag_codec_get_params", "slag_codec_clear_pool",
            "slag_codec_set_pool", "slag_codec_add_lift_rows", "slag_codec_pool_size",
@@ -127,6 +128,7 @@ def lib():
     L.slag_debug_weights.argtypes = [P, I32, P, P, P, I64, ctypes.POINTER(I64)]
     L.slag_get_tuning.argtypes = [P, ctypes.POINTER(slag_tuning), I32, ctypes.POINTER(I32)]
     L.slag_variant_name.argtypes = [I32]
+    L.slag_variant_count.argtypes = []
     L.slag_variant_name.restype = ctypes.c_char_p
     L.slag_codec_init.argtypes = [P, I32, I32, I32, I32, P, I32]
     L.slag_codec_get_params.argtypes = [P, P, I32]
@@ -180,11 +182,13 @@ def _ptr(a):
 def slag_create(device: int = 0, stream=None, max_views_per_launch: int = 0, flags: int = 0,
                 max_launch_entries: int = 0, **constants):
     """constants: alpha_max, alpha_min, t_min, dilation, near_z, guard (floats),
-    tile_size, deterministic (ints); absent = default."""
+    tile_size, deterministic, labels_per_pixel, weight_mode, composite_variant (ints);
+    absent = default."""
     o = slag_options(max_views_per_launch, flags, max_launch_entries)
     for k, v in constants.items():
         if k not in ("alpha_max", "alpha_min", "t_min", "dilation", "near_z", "guard",
-                     "tile_size", "deterministic", "labels_per_pixel", "weight_mode"):
+                     "tile_size", "deterministic", "labels_per_pixel", "weight_mode",
+                     "composite_variant"):
             raise ValueError(f"unknown option {k}")
         setattr(o, k, v)
     h = ctypes.c_void_p()
@@ -316,6 +320,10 @@ def slag_get_tuning(ctx) -> list:
                         name=lib().slag_variant_name(t.variant).decode(),
                         ms=[round(t.ms[i], 4) for i in range(t.n_variants)]))
     return out
+
+
+def slag_variant_count() -> int:
+    return int(lib().slag_variant_count())
 
 
 def slag_debug_tile_lists(ctx, view: int):

@@ -13,6 +13,8 @@
 // the entry's part slots: one (tile-local segment id, weight) slot per (pair,
 // tile, tile segment), laid out pair-major so each pair's slots are
 // contiguous for the contraction.
+#include <algorithm>
+
 #include "slag_internal.h"
 
 namespace slag {
@@ -314,12 +316,14 @@ __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const
     }
 }
 
-// Variants (same arithmetic, bitwise-equal results): MINW = waves per SIMD
-// the register budget must allow; PAD = four-entry groups padded with null
-// entries (loads of a group can be issued together) or cut at the end.
-template <bool COUNT, int MINW, bool PAD, int LMAX, bool KW>
-__global__ __launch_bounds__(256, MINW) void k_composite(
-    const uint32_t* __restrict__ order, uint32_t obase,
+// One tile (bucket b: a (view, tile) with a non-empty list) composited by the
+// workgroup.  Variants (same arithmetic, bitwise-equal results): MINW (of the
+// kernel) = waves per SIMD the register budget must allow; PAD = four-entry
+// groups padded with null entries (loads of a group can be issued together)
+// or cut at the end.
+template <bool COUNT, bool PAD, int LMAX, bool KW>
+__device__ __forceinline__ void composite_tile(
+    const uint32_t b, const int t,
     const uint32_t* __restrict__ bucket_view, const ViewDev* __restrict__ views,
     const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ bend,
     const uint32_t* __restrict__ ival, uint2* __restrict__ pinfo,
@@ -337,7 +341,6 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
     __shared__ uint32_t s_tir[BATCH];         // index of this tile in the pair's tile rectangle
     __shared__ uint16_t s_seg[TILE_PIX];
 
-    const uint32_t b = order[obase + blockIdx.x];   // tiles with the longest lists first
     const uint32_t start = bstart[b], end = bend[b];
     if (start >= end) return;
     const uint32_t ns = ns_tile[b];
@@ -345,7 +348,7 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
     const ViewDev& V = views[bucket_view[b]];
     const uint32_t tile = b - V.tile_base;
     const int tx = (int)(tile % (uint32_t)V.ntx), ty = (int)(tile / (uint32_t)V.ntx);
-    const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+    const int wv = t >> 6, lane = t & 63;
     const float amin = V.amin, amax = V.amax, tmin = V.tmin, l2amin = V.l2amin;
     const int bx0 = tx * TILE + (wv & 1) * 8;    // this wave's 8x8 pixel block
     const int by0 = ty * TILE + (wv >> 1) * 8;
@@ -564,6 +567,50 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
     }
 }
 
+// The compositing kernel.  Buckets are taken in the given order (longest
+// lists first, over all views of the launch): either one workgroup per
+// bucket (the hardware hands out workgroups in index order), or PERSIST: a
+// grid of resident workgroups that each take the next bucket from a queue
+// counter (*queue = 0 at launch) until all nbk are taken.
+template <bool COUNT, int MINW, bool PAD, int LMAX, bool KW, bool PERSIST>
+__global__ __launch_bounds__(256, MINW) void k_composite(
+    const uint32_t* __restrict__ order, uint32_t obase, uint32_t nbk,
+    uint32_t* __restrict__ queue,
+    const uint32_t* __restrict__ bucket_view, const ViewDev* __restrict__ views,
+    const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ bend,
+    const uint32_t* __restrict__ ival, uint2* __restrict__ pinfo,
+    const float4* __restrict__ rec, const uint32_t* __restrict__ ns_tile,
+    const uint16_t* __restrict__ segl, const int32_t* __restrict__ ids, int lpp,
+    uint2* __restrict__ part, unsigned long long* __restrict__ counters,
+    float* __restrict__ pix_t, float* __restrict__ pix_w, uint32_t* __restrict__ pix_n)
+{
+    if (!PERSIST) {
+        composite_tile<COUNT, PAD, LMAX, KW>(order[obase + blockIdx.x], (int)threadIdx.x,
+                                             bucket_view, views,
+                                             bstart, bend, ival, pinfo, rec, ns_tile, segl, ids,
+                                             lpp, part, counters, pix_t, pix_w, pix_n);
+        return;
+    }
+    __shared__ uint32_t s_q;
+    for (;;) {
+        // the two barriers: every thread has left the previous tile before
+        // the next index is published, and has read it before it changes
+        if (threadIdx.x == 0) s_q = atomicAdd(queue, 1u);
+        __syncthreads();
+        const uint32_t i = s_q;
+        __syncthreads();
+        if (i >= nbk) break;   // the counter only grows: every workgroup gets here
+        // the thread index passed as a value the compiler cannot carry across
+        // tiles: what the tile derives from it is formed per tile, not held
+        // in registers over the loop
+        int t = (int)threadIdx.x;
+        asm volatile("" : "+v"(t));
+        composite_tile<COUNT, PAD, LMAX, KW>(order[obase + i], t, bucket_view, views, bstart, bend,
+                                             ival, pinfo, rec, ns_tile, segl, ids, lpp, part,
+                                             counters, pix_t, pix_w, pix_n);
+    }
+}
+
 // Render-back of per-Gaussian attributes into one view (the paper's
 // rendering equation with the lift's weights: C_p = sum_k w_kp a_k /
 // sum_k w_kp over the Gaussians the front-to-back walk blends at p, every
@@ -719,13 +766,15 @@ void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t*
     hipLaunchKernelGGL(k_sat, dim3(nb), dim3(256), 0, st, views, ns_tile, sat);
 }
 
-int composite_variants() { return 4; }
+int composite_variants() { return 6; }
 
 const char* composite_variant_name(int v)
 {
-    static const char* names[4] = {"occupancy 8, padded groups", "occupancy 6, padded groups",
-                                   "occupancy 5, padded groups", "occupancy 8, cut groups"};
-    return (v >= 0 && v < 4) ? names[v] : "";
+    static const char* names[6] = {"occupancy 8, padded groups", "occupancy 6, padded groups",
+                                   "occupancy 5, padded groups", "occupancy 8, cut groups",
+                                   "occupancy 8, cut groups, persistent queue",
+                                   "occupancy 8, padded groups, persistent queue"};
+    return (v >= 0 && v < 6) ? names[v] : "";
 }
 
 void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t* order,
@@ -734,40 +783,43 @@ void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t
                       uint2* pinfo, const float4* rec, const uint32_t* ns_tile,
                       const uint16_t* segl, const int32_t* ids, int lpp, bool kernel_w,
                       uint2* part, unsigned long long* counters, float* pix_t, float* pix_w,
-                      uint32_t* pix_n, hipStream_t st)
+                      uint32_t* pix_n, uint32_t* queue, uint32_t pgrid, hipStream_t st)
 {
     if (!nbuckets) return;
-#define SLAG_COMP(C, W, P, LM)                                                                     \
-    hipLaunchKernelGGL((k_composite<C, W, P, LM, false>), dim3(nbuckets), dim3(256), 0, st, order,  \
-                       obase,                                                                      \
-                       bucket_view, views, bstart, bend, ival, pinfo, rec,                        \
-                       ns_tile, segl, ids, lpp,                                                    \
-                       part, counters, pix_t, pix_w, pix_n)
+    const bool persist = !count && !kernel_w && (variant == 4 || variant == 5);
+    uint32_t grid = nbuckets;
+    if (persist) {
+        launch_fill_u32(queue, 1, 0u, st);
+        grid = std::min(nbuckets, std::max(pgrid, 1u));
+    }
+#define SLAG_COMP(C, W, P, LM, K, Q)                                                               \
+    hipLaunchKernelGGL((k_composite<C, W, P, LM, K, Q>), dim3(grid), dim3(256), 0, st, order,     \
+                       obase, nbuckets, queue, bucket_view, views, bstart, bend, ival, pinfo, rec, \
+                       ns_tile, segl, ids, lpp, part, counters, pix_t, pix_w, pix_n)
 #define SLAG_COMP_V(LM)                                                                            \
     do {                                                                                           \
         if (count) {                                                                               \
-            SLAG_COMP(true, 8, false, LM);                                                         \
+            SLAG_COMP(true, 8, false, LM, false, false);                                           \
             break;                                                                                 \
         }                                                                                          \
         switch (variant) {                                                                         \
-        case 1: SLAG_COMP(false, 6, true, LM); break;                                              \
-        case 2: SLAG_COMP(false, 5, true, LM); break;                                              \
-        case 3: SLAG_COMP(false, 8, false, LM); break;                                             \
-        default: SLAG_COMP(false, 8, true, LM); break;                                             \
+        case 1: SLAG_COMP(false, 6, true, LM, false, false); break;                                \
+        case 2: SLAG_COMP(false, 5, true, LM, false, false); break;                                \
+        case 3: SLAG_COMP(false, 8, false, LM, false, false); break;                               \
+        case 4: SLAG_COMP(false, 8, false, LM, false, true); break;                                \
+        case 5: SLAG_COMP(false, 8, true, LM, false, true); break;                                 \
+        default: SLAG_COMP(false, 8, true, LM, false, false); break;                               \
         }                                                                                          \
     } while (0)
     if (kernel_w) {
         // kernel weights: the occupancy-8, cut-groups shape only (no tuning)
-#define SLAG_COMP_K(C, LM)                                                                         \
-    hipLaunchKernelGGL((k_composite<C, 8, false, LM, true>), dim3(nbuckets), dim3(256), 0, st,     \
-                       order, obase, bucket_view, views, bstart, bend, ival, pinfo, rec, ns_tile,  \
-                       segl, ids, lpp, part, counters, pix_t, pix_w, pix_n)
         if (count) {
-            if (lpp <= 1) SLAG_COMP_K(true, 1); else SLAG_COMP_K(true, MAX_LABELS);
+            if (lpp <= 1) SLAG_COMP(true, 8, false, 1, true, false);
+            else SLAG_COMP(true, 8, false, MAX_LABELS, true, false);
         } else {
-            if (lpp <= 1) SLAG_COMP_K(false, 1); else SLAG_COMP_K(false, MAX_LABELS);
+            if (lpp <= 1) SLAG_COMP(false, 8, false, 1, true, false);
+            else SLAG_COMP(false, 8, false, MAX_LABELS, true, false);
         }
-#undef SLAG_COMP_K
     } else if (lpp <= 1) {
         SLAG_COMP_V(1);
     } else {

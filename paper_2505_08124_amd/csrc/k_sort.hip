@@ -552,7 +552,8 @@ __global__ __launch_bounds__(256) void k_bucket_keys(uint32_t nb,
     const uint32_t b = blockIdx.x * 256 + threadIdx.x;
     if (b >= nb) return;
     const uint32_t len = bend[b] - bstart[b];
-    key[b] = ((uint32_t)view_cls[bucket_view[b]] << 16) | (0xFFFFu - min(len, 0xFFFFu));
+    const uint32_t cls = view_cls ? (uint32_t)view_cls[bucket_view[b]] : 0u;
+    key[b] = (cls << 16) | (0xFFFFu - min(len, 0xFFFFu));
     val[b] = b;
 }
 

@@ -3,8 +3,13 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cctype>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
+#include <unistd.h>
 #include <vector>
 
 #include "slag_ctx.h"
@@ -316,6 +321,80 @@ static slag_status build_plan(slag_ctx* c)
 }
 
 // ------------------------------------------------------------------ the lift
+
+// Tuning cache (SLAG_TUNE_CACHE): one text line per device kind and image
+// size, "slag-tune <device kind> <variants> <width> <height> <variant> <ms>...".
+// Lines of other device kinds or variant sets are kept when the file is
+// rewritten; lines that do not parse are ignored (and dropped on rewrite).
+static const char* kTuneTag = "slag-tune";
+
+static bool parse_tune_line(const std::string& line, std::string& kind, int& nvar, uint32_t& w,
+                            uint32_t& h, TuneEntry& te)
+{
+    std::istringstream is(line);
+    std::string tag;
+    long long W = 0, H = 0;
+    if (!(is >> tag >> kind >> nvar >> W >> H >> te.variant) || tag != kTuneTag) return false;
+    if (nvar < 1 || nvar > 8 || W < 1 || H < 1 || W > 0xFFFFFFFFll || H > 0xFFFFFFFFll ||
+        te.variant < 0 || te.variant >= nvar)
+        return false;
+    for (int v = 0; v < nvar; v++)
+        if (!(is >> te.ms[v]) || !std::isfinite(te.ms[v])) return false;
+    te.n_variants = nvar;
+    w = (uint32_t)W;
+    h = (uint32_t)H;
+    return true;
+}
+
+static void load_tune_cache(slag_ctx* c)
+{
+    if (c->tune_cache.empty()) return;
+    std::ifstream f(c->tune_cache);
+    std::string line, kind;
+    while (std::getline(f, line)) {
+        TuneEntry te;
+        int nvar = 0;
+        uint32_t w = 0, h = 0;
+        if (parse_tune_line(line, kind, nvar, w, h, te) && kind == c->dev_kind &&
+            nvar == composite_variants())
+            c->tune[((uint64_t)w << 32) | h] = te;
+    }
+}
+
+// Best effort: a cache that cannot be written leaves the lift unaffected.
+static void save_tune_cache(slag_ctx* c)
+{
+    if (c->tune_cache.empty()) return;
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(c->tune_cache);
+        std::string line, kind;
+        while (std::getline(f, line)) {
+            TuneEntry te;
+            int nvar = 0;
+            uint32_t w = 0, h = 0;
+            if (!parse_tune_line(line, kind, nvar, w, h, te)) continue;
+            if (kind == c->dev_kind && nvar == composite_variants() &&
+                c->tune.count(((uint64_t)w << 32) | h))
+                continue;   // replaced by this context's entry
+            keep.push_back(line);
+        }
+    }
+    const std::string tmp = c->tune_cache + ".tmp" + std::to_string((long long)getpid());
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (const auto& l : keep) std::fprintf(f, "%s\n", l.c_str());
+    for (const auto& kv : c->tune) {
+        const TuneEntry& te = kv.second;
+        if (te.n_variants != composite_variants()) continue;
+        std::fprintf(f, "%s %s %d %u %u %d", kTuneTag, c->dev_kind.c_str(), te.n_variants,
+                     (unsigned)(kv.first >> 32), (unsigned)(kv.first & 0xFFFFFFFFu), te.variant);
+        for (int v = 0; v < te.n_variants; v++) std::fprintf(f, " %.9g", (double)te.ms[v]);
+        std::fprintf(f, "\n");
+    }
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), c->tune_cache.c_str()) != 0) std::remove(tmp.c_str());
+}
 
 // Time every compositing variant on one resolution class (second of two
 // runs each, so caches are warm) and keep the fastest.
@@ -672,20 +751,27 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
             return SLAG_OK;
         }
         // dispatch order of the compositing workgroups: longest lists first
+        // over all views of the launch (by_class: image size first, for the
+        // tuner, which times each size alone)
         CK(ensure(c, c->bkey, (size_t)B.nbuckets * 4 + 4));
         CK(ensure(c, c->bkey_alt, (size_t)B.nbuckets * 4 + 4));
         CK(ensure(c, c->bord, (size_t)B.nbuckets * 4 + 4));
         CK(ensure(c, c->bord_alt, (size_t)B.nbuckets * 4 + 4));
         CK(ensure(c, c->hist, radix_hist_bytes(B.nbuckets)));
         CK(ensure_scan(c, B.nbuckets));
-        launch_bucket_keys(B.nbuckets, B.bucket_view.as<uint32_t>(), B.view_cls.as<uint8_t>(),
-                           c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(),
-                           c->bkey.as<uint32_t>(), c->bord.as<uint32_t>(), st);
-        const bool alt3 = radix_sort_u32(c->bkey.as<uint32_t>(), c->bord.as<uint32_t>(),
-                                         c->bkey_alt.as<uint32_t>(), c->bord_alt.as<uint32_t>(),
-                                         B.nbuckets, 16 + bit_length((uint64_t)(B.ncls - 1)),
-                                         c->hist.as<uint32_t>(), c->scan_ws.p, nullptr, st);
-        const uint32_t* border = alt3 ? c->bord_alt.as<uint32_t>() : c->bord.as<uint32_t>();
+        auto sort_buckets = [&](bool by_class) -> const uint32_t* {
+            launch_bucket_keys(B.nbuckets, B.bucket_view.as<uint32_t>(),
+                               by_class ? B.view_cls.as<uint8_t>() : nullptr,
+                               c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(),
+                               c->bkey.as<uint32_t>(), c->bord.as<uint32_t>(), st);
+            const int kbits = 16 + (by_class ? bit_length((uint64_t)(B.ncls - 1)) : 0);
+            const bool alt = radix_sort_u32(c->bkey.as<uint32_t>(), c->bord.as<uint32_t>(),
+                                            c->bkey_alt.as<uint32_t>(), c->bord_alt.as<uint32_t>(),
+                                            B.nbuckets, kbits, c->hist.as<uint32_t>(),
+                                            c->scan_ws.p, nullptr, st);
+            return alt ? c->bord_alt.as<uint32_t>() : c->bord.as<uint32_t>();
+        };
+        const uint32_t* border = sort_buckets(false);
         CK(stage_end(c, ST_TILE_SORT, ev));
 
         // part lists: pinfo[p] = (base psz[p] (scanned), fill 0), sentinel (total, 0)
@@ -716,47 +802,66 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
             launch_init_pinfo(npairs, c->psz.as<uint32_t>(), (uint32_t)nparts,
                               c->pinfo.as<uint2>(), st);
         };
-        // tuning: time every variant of each untuned size (each run starts
-        // from empty part lists), then composite every size once for real
-        bool tuned_now = false;
-        for (int k = 0; k < B.ncls && (c->opt.flags & SLAG_FLAG_AUTOTUNE) && !c->capturing && !count &&
-                        !c->kernel_w;
-             k++) {
-            if (!B.cls_nb[k]) continue;
-            const uint64_t key = ((uint64_t)B.cls_w[k] << 32) | B.cls_h[k];
-            if (c->tune.count(key)) continue;
-            auto launch = [&](int var) {
-                clear_lists();
-                launch_composite(false, var, B.cls_nb[k], border, B.cls_off[k],
-                                 B.bucket_view.as<uint32_t>(), views, c->bstart.as<uint32_t>(),
-                                 c->bend.as<uint32_t>(), sval, c->pinfo.as<uint2>(), c->rec.as<float4>(),
-                                 c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
-                                 c->ids.as<int32_t>(), c->lpp, c->kernel_w, c->part.as<uint2>(),
-                                 reinterpret_cast<unsigned long long*>(small + SM_COUNTERS),
-                                 nullptr, nullptr, nullptr, st);
-            };
-            TuneEntry te;
-            te.n_variants = std::min(composite_variants(), 8);
-            CK(tune_class(c, te, launch));
-            c->tune.emplace(key, te);
-            tuned_now = true;
+        // tuning: time every variant of each untuned size alone (each run
+        // starts from empty part lists), then composite the launch for real
+        uint32_t* queue = reinterpret_cast<uint32_t*>(small + SM_QUEUE);
+        const bool tuning = (c->opt.flags & SLAG_FLAG_AUTOTUNE) && !c->capturing && !count &&
+                            !c->kernel_w && c->opt.composite_variant == 0;
+        bool untuned = false;
+        for (int k = 0; k < B.ncls; k++)
+            untuned = untuned ||
+                      (B.cls_nb[k] && !c->tune.count(((uint64_t)B.cls_w[k] << 32) | B.cls_h[k]));
+        if (tuning && untuned) {
+            const uint32_t* corder = sort_buckets(true);
+            for (int k = 0; k < B.ncls; k++) {
+                if (!B.cls_nb[k]) continue;
+                const uint64_t key = ((uint64_t)B.cls_w[k] << 32) | B.cls_h[k];
+                if (c->tune.count(key)) continue;
+                auto launch = [&](int var) {
+                    clear_lists();
+                    launch_composite(false, var, B.cls_nb[k], corder, B.cls_off[k],
+                                     B.bucket_view.as<uint32_t>(), views, c->bstart.as<uint32_t>(),
+                                     c->bend.as<uint32_t>(), sval, c->pinfo.as<uint2>(),
+                                     c->rec.as<float4>(), c->ns_tile.as<uint32_t>(),
+                                     c->segl.as<uint16_t>(), c->ids.as<int32_t>(), c->lpp,
+                                     c->kernel_w, c->part.as<uint2>(),
+                                     reinterpret_cast<unsigned long long*>(small + SM_COUNTERS),
+                                     nullptr, nullptr, nullptr, queue, c->pgrid, st);
+                };
+                TuneEntry te;
+                te.n_variants = std::min(composite_variants(), 8);
+                CK(tune_class(c, te, launch));
+                c->tune.emplace(key, te);
+            }
+            clear_lists();
+            border = sort_buckets(false);
+            save_tune_cache(c);
         }
-        if (tuned_now) clear_lists();
-        for (int k = 0; k < B.ncls; k++) {
-            if (!B.cls_nb[k]) continue;
-            auto launch = [&](int var) {
-                launch_composite(count, var, B.cls_nb[k], border, B.cls_off[k],
-                                 B.bucket_view.as<uint32_t>(), views, c->bstart.as<uint32_t>(),
-                                 c->bend.as<uint32_t>(), sval, c->pinfo.as<uint2>(), c->rec.as<float4>(),
-                                 c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
-                                 c->ids.as<int32_t>(), c->lpp, c->kernel_w, c->part.as<uint2>(),
-                                 reinterpret_cast<unsigned long long*>(small + SM_COUNTERS),
-                                 pix_t, pix_w, pix_n, st);
-            };
-            const uint64_t key = ((uint64_t)B.cls_w[k] << 32) | B.cls_h[k];
-            auto it = c->tune.find(key);
-            launch(it == c->tune.end() ? 0 : it->second.variant);
+        int var = 0;
+        if (c->opt.composite_variant > 0) {
+            var = c->opt.composite_variant - 1;
+        } else {
+            // the variant of least summed time over the launch's image sizes
+            // (variant 0 while a size is untuned)
+            double tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            bool all = true;
+            for (int k = 0; k < B.ncls && all; k++) {
+                if (!B.cls_nb[k]) continue;
+                auto it = c->tune.find(((uint64_t)B.cls_w[k] << 32) | B.cls_h[k]);
+                all = it != c->tune.end() && it->second.n_variants == composite_variants();
+                for (int v = 0; all && v < it->second.n_variants; v++) tot[v] += it->second.ms[v];
+            }
+            if (all)
+                for (int v = 1; v < std::min(composite_variants(), 8); v++)
+                    if (tot[v] < tot[var]) var = v;
         }
+        launch_composite(count, var, B.nbuckets, border, 0, B.bucket_view.as<uint32_t>(), views,
+                         c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(), sval,
+                         c->pinfo.as<uint2>(), c->rec.as<float4>(), c->ns_tile.as<uint32_t>(),
+                         c->segl.as<uint16_t>(), c->ids.as<int32_t>(), c->lpp, c->kernel_w,
+                         c->part.as<uint2>(),
+                         reinterpret_cast<unsigned long long*>(small + SM_COUNTERS), pix_t, pix_w,
+                         pix_n, queue, c->pgrid, st);
         CK(stage_end(c, ST_COMPOSITE, ev));
 
         if (c->opt.flags & SLAG_FLAG_KEEP_DEBUG) {
@@ -833,6 +938,10 @@ slag_status slag_create(int32_t device, void* hip_stream, const slag_options* op
             return SLAG_E_INVALID_ARG;
         }
         c->kernel_w = o.weight_mode == 1;
+        if (o.composite_variant < 0 || o.composite_variant > composite_variants()) {
+            delete c;
+            return SLAG_E_INVALID_ARG;
+        }
         RasterConsts& K = c->rc;
         K.amax = amax;
         K.amin = amin;
@@ -865,6 +974,23 @@ slag_status slag_create(int32_t device, void* hip_stream, const slag_options* op
     if (hipMemset(c->small.p, 0, SM_WORDS * 8) != hipSuccess) {
         slag_destroy(c);
         return SLAG_E_DEVICE;
+    }
+    {
+        // persistent compositing: eight resident workgroups per compute unit;
+        // the tuning cache is keyed by the device kind
+        hipDeviceProp_t pr;
+        if (hipGetDeviceProperties(&pr, device) != hipSuccess) {
+            slag_destroy(c);
+            return SLAG_E_DEVICE;
+        }
+        c->pgrid = (uint32_t)std::max(pr.multiProcessorCount, 1) * 8u;
+        std::string arch(pr.gcnArchName);
+        for (auto& ch : arch)
+            if (std::isspace((unsigned char)ch)) ch = '_';
+        c->dev_kind = arch + "/" + std::to_string(pr.multiProcessorCount);
+        const char* path = std::getenv("SLAG_TUNE_CACHE");
+        c->tune_cache = path ? path : "";
+        load_tune_cache(c);
     }
     *out = c;
     return SLAG_OK;
@@ -927,6 +1053,8 @@ slag_status slag_get_tuning(slag_ctx* c, slag_tuning* out, int32_t cap, int32_t*
 }
 
 const char* slag_variant_name(int32_t v) { return composite_variant_name(v); }
+
+int32_t slag_variant_count(void) { return composite_variants(); }
 
 const char* slag_stage_name(int32_t s)
 {

@@ -35,7 +35,7 @@ struct Batch {
     uint64_t nchunks = 0;   // chunks the contraction's walk took (whole range)
     uint32_t zmin = 0, zmax = 0;
     // resolution classes (distinct image sizes, first appearance order): the
-    // compositing runs one launch per class, with the class's tuned variant
+    // tuner times each class alone; the compositing runs one launch over all
     int ncls = 0;
     int lbits = 0;     // bits of the largest view's tile count (tile-sort key width)
     std::vector<uint32_t> cls_w, cls_h, cls_nb, cls_off;
@@ -152,6 +152,9 @@ struct slag_ctx {
     // compositing variant per image size (SLAG_FLAG_AUTOTUNE), and the events that time them
     std::map<uint64_t, slag_host::TuneEntry> tune;
     hipEvent_t tune_ev[2] = {nullptr, nullptr};
+    std::string tune_cache;   // file named by SLAG_TUNE_CACHE ("" = none)
+    std::string dev_kind;     // architecture name and compute-unit count
+    uint32_t pgrid = 0;       // workgroups of a persistent compositing launch
 
     // graph replay of the lift (SLAG_FLAG_GRAPH)
     uint64_t gen = 1;                 // bumped by every input change
@@ -190,7 +193,7 @@ namespace slag_host {
 
 // small device area layout (uint64 words)
 enum { SM_TOT = 0, SM_ZRANGE = 2, SM_TOTALS = 4, SM_COUNTERS = 8, SM_NNZ = 12, SM_ERR = 14,
-       SM_TIES = 16, SM_LERR = 18, SM_CHUNKS = 20, SM_WORDS = 22 };
+       SM_TIES = 16, SM_LERR = 18, SM_CHUNKS = 20, SM_QUEUE = 22, SM_WORDS = 24 };
 
 #define FAIL(ctx, code, msg)                 \
     do {                                     \

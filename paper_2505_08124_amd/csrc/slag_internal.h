@@ -146,7 +146,8 @@ void launch_emit_isect(uint64_t npairs, const uint32_t* order, const uint64_t* o
                        const uint32_t* ioff, int lbits, uint32_t* ikey, uint32_t* ival,
                        hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
-// Dispatch keys: (resolution class << 16) | (0xFFFF - min(list length, 0xFFFF)).
+// Dispatch keys: (resolution class << 16) | (0xFFFF - min(list length, 0xFFFF)),
+// class 0 for every view when view_cls is null.
 void launch_bucket_keys(uint32_t nb, const uint32_t* bucket_view, const uint8_t* view_cls,
                         const uint32_t* bstart, const uint32_t* bend, uint32_t* key,
                         uint32_t* val, hipStream_t st);
@@ -161,7 +162,8 @@ void launch_tile_segs(uint32_t nbuckets, const uint32_t* bucket_view, const View
                       unsigned long long* err, hipStream_t st);
 void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t* sat,
                 hipStream_t st);
-// Compositing variants (bitwise-equal results, different register budgets).
+// Compositing variants (bitwise-equal results; register budgets, group
+// padding, one workgroup per bucket or a persistent queue).
 int composite_variants();
 const char* composite_variant_name(int v);
 // Part lists: pinfo[p] = (base, fill), pinfo[npairs] = (total, 0); pair p
@@ -174,14 +176,16 @@ void launch_init_pinfo(uint64_t npairs, const uint32_t* base, uint32_t total, ui
 // mode), [3] part-list entries lost to a capacity error (always; 0 by
 // construction).  pix_t / pix_w / pix_n (count mode, may be null): final
 // transmittance, sum of accepted weights and accepted blends of every pixel
-// walked (indexed like the id maps).
+// walked (indexed like the id maps).  The persistent variants (4, 5) run
+// min(nbuckets, pgrid) workgroups that take buckets from *queue (zeroed here
+// by a fill kernel); the others ignore queue and pgrid.
 void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t* order,
                       uint32_t obase, const uint32_t* bucket_view, const ViewDev* views,
                       const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
                       uint2* pinfo, const float4* rec, const uint32_t* ns_tile,
                       const uint16_t* segl, const int32_t* ids, int lpp, bool kernel_w,
                       uint2* part, unsigned long long* counters, float* pix_t, float* pix_w,
-                      uint32_t* pix_n, hipStream_t st);
+                      uint32_t* pix_n, uint32_t* queue, uint32_t pgrid, hipStream_t st);
 // Render-back of attr [N][C] (caller's Gaussian order) into view vi of the
 // last launch: out [H][W][C] = sum w a / sum w per pixel (0 where no weight),
 // wsum [H][W] (may be null); ntiles = the view's tile count.

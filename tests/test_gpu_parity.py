@@ -382,9 +382,79 @@ def test_autotune_is_bitwise_neutral():
     E2, den2 = L.embeddings()
     tun = slag.slag_get_tuning(L.ctx)
     _say("tuning", tun)
-    assert len(tun) == 3 and all(len(t["ms"]) == 4 for t in tun)
+    assert len(tun) == 3 and all(len(t["ms"]) == slag.slag_variant_count() for t in tun)
     assert np.array_equal(E0, E1) and np.array_equal(E0, E2)
     assert np.array_equal(den0, den1) and np.array_equal(den0, den2)
+
+
+@pytest.mark.parametrize("lpp", [1, 2])
+def test_every_compositing_variant_is_bitwise_equal(lpp):
+    """Every compositing variant (register budget, group padding, one
+    workgroup per tile or a persistent grid taking tiles from a queue),
+    forced through the composite_variant option, gives the default lift's
+    bits, eagerly and on graph replays (the queue counter is reset inside the
+    graph).  Three image sizes composited in one launch, 12,600 tiles: far
+    more than the persistent grid, so its workgroups take many tiles each."""
+    import paper_2505_08124_amd as slag
+    sc = make_scene("uneven_1m", n=40000, views=dict(n=6))
+    if lpp == 2:
+        sc = _overlap_scene(sc)
+    L0 = slag.Lifter(0, labels_per_pixel=lpp)
+    L0.set_scene(sc)
+    L0.lift()
+    E0, den0 = L0.embeddings()
+    L0.close()
+    assert den0.max() > 0
+    for v in range(slag.slag_variant_count()):
+        _say(f"variant {v} ({slag.lib().slag_variant_name(v).decode()}), labels {lpp}")
+        L = slag.Lifter(0, flags=slag.SLAG_FLAG_GRAPH, labels_per_pixel=lpp,
+                        composite_variant=v + 1)
+        L.set_scene(sc)
+        for rep in range(3):
+            L.lift()
+            E, den = L.embeddings()
+            assert np.array_equal(E, E0) and np.array_equal(den, den0), (v, rep)
+            _other_gpu_work()
+        L.close()
+    with pytest.raises(slag.SlagError):
+        slag.Lifter(0, composite_variant=slag.slag_variant_count() + 1)
+    with pytest.raises(slag.SlagError):
+        slag.Lifter(0, composite_variant=-1)
+
+
+def test_tuning_cache_file(tmp_path, monkeypatch):
+    """SLAG_TUNE_CACHE: the tuned sizes are written after tuning and read by
+    the next context (which then tunes nothing and lifts the same bits);
+    lines of another device kind are kept, unreadable lines dropped."""
+    import paper_2505_08124_amd as slag
+    sc = _ragged_scene()
+    path = tmp_path / "tune.txt"
+    foreign = "slag-tune other/1 6 10 10 0 1 2 3 4 5 6"
+    path.write_text("not a tuning line\n" + foreign + "\n")
+    monkeypatch.setenv("SLAG_TUNE_CACHE", str(path))
+    L = _lifter(sc, flags=slag.SLAG_FLAG_AUTOTUNE)
+    assert slag.slag_get_tuning(L.ctx) == []
+    L.lift()
+    E1, den1 = L.embeddings()
+    t1 = slag.slag_get_tuning(L.ctx)
+    L.close()
+    assert len(t1) == 3
+    lines = path.read_text().splitlines()
+    _say("tuning cache", lines)
+    assert foreign in lines and "not a tuning line" not in lines
+    assert len(lines) == 4 and all(ln.startswith("slag-tune ") for ln in lines)
+    L2 = _lifter(sc, flags=slag.SLAG_FLAG_AUTOTUNE)
+    assert slag.slag_get_tuning(L2.ctx) == t1          # read from the file
+    L2.lift()
+    E2, den2 = L2.embeddings()
+    assert slag.slag_get_tuning(L2.ctx) == t1          # nothing tuned again
+    assert np.array_equal(E1, E2) and np.array_equal(den1, den2)
+    L2.close()
+    assert path.read_text().splitlines() == lines
+    monkeypatch.delenv("SLAG_TUNE_CACHE")
+    L3 = _lifter(sc, flags=slag.SLAG_FLAG_AUTOTUNE)
+    assert slag.slag_get_tuning(L3.ctx) == []
+    L3.close()
 
 
 def test_uneven_resolutions_one_launch():
