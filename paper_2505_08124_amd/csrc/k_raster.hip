@@ -58,88 +58,75 @@ __device__ __forceinline__ uint32_t sat_rect(const uint32_t* S, int sw, int xa, 
 }
 
 // Distinct segment ids of each tile, ascending, over every label layer of
-// its pixels (a pixel lies in up to lpp masks; -1 = none).  Each wave
-// extracts the distinct ids among its 64 pixels with a ballot loop per layer
-// (one iteration per distinct id; an id already found in an earlier layer is
-// not repeated); the candidates of the four waves are then merged: a
-// candidate is kept if no candidate of an earlier wave has its id, and goes
-// to the position given by the number of kept candidates with a smaller id.
-// Tiles hold few segments, so both loops are short.  More than TILE_PIX
-// distinct ids in one tile (only possible with several layers) set bit 4 of
-// *err and keep the TILE_PIX smallest.
-__global__ __launch_bounds__(256) void k_tile_segs(const uint32_t* __restrict__ bucket_view,
+// its pixels (a pixel lies in up to lpp masks; -1 = none).  One wave per
+// tile, four tiles per workgroup: each lane holds four pixels of the 16 x 16
+// tile (column lane % 16, rows lane / 16 + 4 r) with their NL = 1 or
+// MAX_LABELS layers.  A ballot loop finds one distinct id per iteration (the
+// first remaining value of the first lane that has one), clears it in every
+// lane and appends it to the wave's list in LDS; each id of the list then
+// goes to the position given by the number of smaller ids.  Tiles hold few
+// segments, so both loops are short.  More than TILE_PIX distinct ids in one
+// tile (only possible with several layers) set bit 4 of *err and keep the
+// TILE_PIX smallest.
+template <int NL>
+__global__ __launch_bounds__(256) void k_tile_segs(uint32_t nbuckets,
+                                                   const uint32_t* __restrict__ bucket_view,
                                                    const ViewDev* __restrict__ views,
                                                    const int32_t* __restrict__ ids, int lpp,
                                                    uint32_t* __restrict__ ns_tile,
                                                    uint16_t* __restrict__ segl,
                                                    unsigned long long* __restrict__ err)
 {
-    __shared__ uint32_t cand[4][64 * MAX_LABELS];
-    __shared__ uint32_t keep[4 * 64 * MAX_LABELS];
-    __shared__ uint32_t wn[4];
-    const uint32_t b = blockIdx.x;
+    constexpr int NV = 4 * NL;   // values per lane
+    __shared__ uint32_t cand[4][64 * NV];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t b = blockIdx.x * 4u + (uint32_t)w;
+    if (b >= nbuckets) return;   // whole waves; nothing below waits for other waves
     const ViewDev& V = views[bucket_view[b]];
     const uint32_t tile = b - V.tile_base;
     const int tx = (int)(tile % (uint32_t)V.ntx), ty = (int)(tile / (uint32_t)V.ntx);
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int px = tx * TILE + (t & (TILE - 1)), py = ty * TILE + t / TILE;
-    const bool inside = px < V.W && py < V.H;
-    const uint64_t pb = (V.pix_off + (uint64_t)py * V.W + px) * (uint64_t)lpp;
-    // 1. distinct ids of this wave's pixels, layer by layer
-    uint32_t nc = 0;
-    for (int l = 0; l < lpp; l++) {
-        const int32_t id = inside ? ids[pb + l] : -1;
-        bool left = id >= 0;
-        const uint32_t nprev = nc;             // candidates of earlier layers
-        for (;;) {
-            const uint64_t act = __ballot(left);
-            if (!act) break;
-            const int v = __builtin_amdgcn_readlane(id, __ffsll((long long)act) - 1);
-            bool dup = false;
-            for (uint32_t i = 0; i < nprev; i++) dup = dup || cand[w][i] == (uint32_t)v;
-            if (!dup) {
-                if (lane == 0) cand[w][nc] = (uint32_t)v;
-                nc++;
-            }
-            left = left && id != v;
+    const int px = tx * TILE + (lane & 15);
+    int32_t idv[NV];
+    uint32_t left = 0;   // bit k: value k is an id not yet taken
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const int py = ty * TILE + (lane >> 4) + 4 * r;
+        const bool inside = px < V.W && py < V.H;
+        const uint64_t pb = (V.pix_off + (uint64_t)py * V.W + px) * (uint64_t)lpp;
+#pragma unroll
+        for (int l = 0; l < NL; l++) {
+            const int32_t id = (inside && l < lpp) ? ids[pb + l] : -1;
+            idv[r * NL + l] = id;
+            if (id >= 0) left |= 1u << (r * NL + l);
         }
     }
-    if (lane == 0) wn[w] = nc;
-    __syncthreads();
-    // 2. merge: candidate i of the flat list (waves in order)
-    const uint32_t n0 = wn[0], n1 = wn[1], n2 = wn[2], n3 = wn[3];
-    const uint32_t C = n0 + n1 + n2 + n3;
-    for (uint32_t i = (uint32_t)t; i < C; i += 256) {
-        const int cw = i < n0 ? 0 : i < n0 + n1 ? 1 : i < n0 + n1 + n2 ? 2 : 3;
-        const uint32_t ci = i - (cw > 0 ? n0 : 0) - (cw > 1 ? n1 : 0) - (cw > 2 ? n2 : 0);
-        const uint32_t c = cand[cw][ci];
-        // earlier waves' candidates with the same id (a wave's own are distinct)
-        bool kept = true;
-        for (int u = 0; u < cw && kept; u++) {
-            const uint32_t nu = u == 0 ? n0 : u == 1 ? n1 : n2;
-            for (uint32_t j = 0; j < nu; j++)
-                if (cand[u][j] == c) { kept = false; break; }
-        }
-        keep[i] = kept ? c : 0xFFFFFFFFu;
+    uint32_t nc = 0;   // wave-uniform
+    for (;;) {
+        const uint64_t act = __ballot(left != 0);
+        if (!act) break;
+        int mine = 0;
+#pragma unroll
+        for (int k = NV - 1; k >= 0; k--)
+            if ((left >> k) & 1u) mine = idv[k];
+        const int v = __builtin_amdgcn_readlane(mine, __ffsll((long long)act) - 1);
+#pragma unroll
+        for (int k = 0; k < NV; k++)
+            if (idv[k] == v) left &= ~(1u << k);
+        if (lane == 0) cand[w][nc] = (uint32_t)v;
+        nc++;
     }
-    __syncthreads();
-    uint32_t nk = 0;
-    for (uint32_t i = (uint32_t)t; i < C; i += 256) {
-        const uint32_t c = keep[i];
-        if (c == 0xFFFFFFFFu) continue;
-        nk++;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t i = (uint32_t)lane; i < nc; i += 64) {
+        const uint32_t c = cand[w][i];
         uint32_t pos = 0;
-        for (uint32_t j = 0; j < C; j++) pos += keep[j] < c;
+        for (uint32_t j = 0; j < nc; j++) pos += cand[w][j] < c;
         if (pos < (uint32_t)TILE_PIX) segl[(uint64_t)b * TILE_PIX + pos] = (uint16_t)c;
     }
-    for (int o = 32; o >= 1; o >>= 1) nk += __shfl_xor(nk, o, 64);
-    __syncthreads();
-    if (lane == 0) wn[w] = nk;
-    __syncthreads();
-    if (t == 0) {
-        const uint32_t K = wn[0] + wn[1] + wn[2] + wn[3];
-        ns_tile[b] = K < (uint32_t)TILE_PIX ? K : (uint32_t)TILE_PIX;
-        if (K > (uint32_t)TILE_PIX) atomicOr(err, 4ull);
+    if (lane == 0) {
+        ns_tile[b] = nc < (uint32_t)TILE_PIX ? nc : (uint32_t)TILE_PIX;
+        if (nc > (uint32_t)TILE_PIX) atomicOr(err, 4ull);
     }
 }
 
@@ -755,8 +742,13 @@ void launch_tile_segs(uint32_t nbuckets, const uint32_t* bucket_view, const View
                       unsigned long long* err, hipStream_t st)
 {
     if (!nbuckets) return;
-    hipLaunchKernelGGL(k_tile_segs, dim3(nbuckets), dim3(256), 0, st, bucket_view, views, ids, lpp,
-                       ns_tile, segl, err);
+    const dim3 grid((nbuckets + 3) / 4);
+    if (lpp <= 1)
+        hipLaunchKernelGGL(k_tile_segs<1>, grid, dim3(256), 0, st, nbuckets, bucket_view, views, ids,
+                           lpp, ns_tile, segl, err);
+    else
+        hipLaunchKernelGGL(k_tile_segs<MAX_LABELS>, grid, dim3(256), 0, st, nbuckets, bucket_view,
+                           views, ids, lpp, ns_tile, segl, err);
 }
 
 void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t* sat,
