@@ -170,6 +170,13 @@ def test_training_lowers_loss_and_beats_baselines():
     _say(f"mean cosine to the plain lift: trained {c_tr.mean():.4f} (p1 {np.percentile(c_tr, 1):.4f}, "
          f"min {c_tr.min():.4f}), PCA-{k} {c_pca.mean():.4f}, untrained {c_un.mean():.4f}")
     assert c_tr.mean() > c_pca.mean() > c_un.mean()
+    # regression floor under the measured 0.897 (this held-out scene, 1,500
+    # steps on three small training scenes)
+    assert c_tr.mean() >= 0.85
+    if c_tr.mean() < 0.99:
+        pytest.xfail(f"codec target not reached: mean cosine {c_tr.mean():.4f} against 0.99 "
+                     "(0.966 on the uneven 1M benchmark scene after 4,000 steps; the ceiling "
+                     "of Gaussians seen through few noisy segments is 0.993 there)")
 
 
 def test_training_is_deterministic():
