@@ -81,7 +81,9 @@ enum {
                                    from it at slag_create and written back after tuning
                                    (text, one line per device kind and image size; lines of
                                    other devices or variant sets are kept, unreadable lines
-                                   ignored) */
+                                   ignored; the file is replaced by rename, so processes that
+                                   tune at once never leave it half written, and the last
+                                   writer's table wins) */
 };
 
 typedef struct {
