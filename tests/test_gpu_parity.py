@@ -385,6 +385,15 @@ def test_autotune_is_bitwise_neutral():
     assert len(tun) == 3 and all(len(t["ms"]) == slag.slag_variant_count() for t in tun)
     assert np.array_equal(E0, E1) and np.array_equal(E0, E2)
     assert np.array_equal(den0, den1) and np.array_equal(den0, den2)
+    # tuned inside a lift that records a graph, then replayed
+    L = _lifter(sc, flags=slag.SLAG_FLAG_AUTOTUNE | slag.SLAG_FLAG_GRAPH)
+    for _ in range(3):
+        L.lift()
+        E3, den3 = L.embeddings()
+        assert np.array_equal(E0, E3) and np.array_equal(den0, den3)
+        _other_gpu_work()
+    assert len(slag.slag_get_tuning(L.ctx)) == 3
+    L.close()
 
 
 @pytest.mark.parametrize("lpp", [1, 2])
