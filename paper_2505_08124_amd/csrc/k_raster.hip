@@ -308,7 +308,7 @@ __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const
 // kernel) = waves per SIMD the register budget must allow; PAD = four-entry
 // groups padded with null entries (loads of a group can be issued together)
 // or cut at the end.
-template <bool COUNT, bool PAD, int LMAX, bool KW>
+template <bool COUNT, bool PAD, int LMAX, bool KW, int BT>
 __device__ __forceinline__ void composite_tile(
     const uint32_t b, const int t,
     const uint32_t* __restrict__ bucket_view, const ViewDev* __restrict__ views,
@@ -319,13 +319,14 @@ __device__ __forceinline__ void composite_tile(
     uint2* __restrict__ part, unsigned long long* __restrict__ counters,
     float* __restrict__ pix_t, float* __restrict__ pix_w, uint32_t* __restrict__ pix_n)
 {
-    __shared__ float4 s_w0[4][BATCH];         // per wave: entries touching its block, exponent
-    __shared__ float4 s_w1[4][BATCH];         //   coefficients (c0, cx, cy, cxx), (cxy, cyy, box, box)
-    __shared__ int s_wj[4][BATCH];            //   their index in the batch
-    __shared__ float s_lo[4][BATCH];          //   log2(opacity) (kernel weights)
-    __shared__ float s_acc[4][BATCH][NS_CAP]; // per wave weight sums [entry][segment]
-    __shared__ uint32_t s_pair[BATCH];        // pair of each batch entry
-    __shared__ uint32_t s_tir[BATCH];         // index of this tile in the pair's tile rectangle
+    static_assert(BT % 4 == 0 && BT <= 64, "one batch entry per lane, groups of four");
+    __shared__ float4 s_w0[4][BT];            // per wave: entries touching its block, exponent
+    __shared__ float4 s_w1[4][BT];            //   coefficients (c0, cx, cy, cxx), (cxy, cyy, box, box)
+    __shared__ int s_wj[4][BT];               //   their index in the batch
+    __shared__ float s_lo[4][BT];             //   log2(opacity) (kernel weights)
+    __shared__ float s_acc[4][BT][NS_CAP];    // per wave weight sums [entry][segment]
+    __shared__ uint32_t s_pair[BT];           // pair of each batch entry
+    __shared__ uint32_t s_tir[BT];            // index of this tile in the pair's tile rectangle
     __shared__ uint16_t s_seg[TILE_PIX];
 
     const uint32_t start = bstart[b], end = bend[b];
@@ -401,18 +402,20 @@ __device__ __forceinline__ void composite_tile(
         }
         bool done = counting ? !valid : (sbits == 0);
         float T = (counting || sbits != 0) ? 1.0f : 0.0f;
-        for (int i = lane; i < BATCH * NS_CAP; i += 64) (&s_acc[wv][0][0])[i] = 0.0f;
-        // lane l holds entry l of the batch.  Two-deep prefetch: records of the
-        // next batch and list entries of the one after are in flight while a
-        // batch blends (unconditional clamped loads: every address is inside
-        // the list; nothing waits on them until they are used).
-        uint32_t e = min(start + (uint32_t)lane, last);
+        for (int i = lane; i < BT * NS_CAP; i += 64) (&s_acc[wv][0][0])[i] = 0.0f;
+        // lane l holds entry l of the batch (lanes past BT repeat the last
+        // one).  Two-deep prefetch: records of the next batch and list
+        // entries of the one after are in flight while a batch blends
+        // (unconditional clamped loads: every address is inside the list;
+        // nothing waits on them until they are used).
+        const uint32_t le = (uint32_t)min(lane, BT - 1);
+        uint32_t e = min(start + le, last);
         uint32_t pcur = ival[e];
         float4 q0 = rec[2 * (size_t)pcur], q1 = rec[2 * (size_t)pcur + 1];
-        e = min(start + BATCH + (uint32_t)lane, last);
+        e = min(start + BT + le, last);
         uint32_t pn = ival[e];
-        for (uint32_t base = start; base < end; base += BATCH) {
-            const int nb = (int)min((uint32_t)BATCH, end - base);
+        for (uint32_t base = start; base < end; base += BT) {
+            const int nb = (int)min((uint32_t)BT, end - base);
             // the bounding box of this wave's pixels that can still take
             // weight (lane = 8 y + x), from the active-lane mask
             const uint64_t am = __ballot(!done);
@@ -472,7 +475,7 @@ __device__ __forceinline__ void composite_tile(
             q0 = rec[2 * (size_t)pn];
             q1 = rec[2 * (size_t)pn + 1];
             pcur = pn;
-            e = min(base + 2 * BATCH + (uint32_t)lane, last);
+            e = min(base + 2 * BT + le, last);
             pn = ival[e];
             __builtin_amdgcn_wave_barrier();
             if (cnt && !__all(done)) {
@@ -559,7 +562,7 @@ __device__ __forceinline__ void composite_tile(
 // bucket (the hardware hands out workgroups in index order), or PERSIST: a
 // grid of resident workgroups that each take the next bucket from a queue
 // counter (*queue = 0 at launch) until all nbk are taken.
-template <bool COUNT, int MINW, bool PAD, int LMAX, bool KW, bool PERSIST>
+template <bool COUNT, int MINW, bool PAD, int LMAX, bool KW, bool PERSIST, int BT>
 __global__ __launch_bounds__(256, MINW) void k_composite(
     const uint32_t* __restrict__ order, uint32_t obase, uint32_t nbk,
     uint32_t* __restrict__ queue,
@@ -572,7 +575,7 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
     float* __restrict__ pix_t, float* __restrict__ pix_w, uint32_t* __restrict__ pix_n)
 {
     if (!PERSIST) {
-        composite_tile<COUNT, PAD, LMAX, KW>(order[obase + blockIdx.x], (int)threadIdx.x,
+        composite_tile<COUNT, PAD, LMAX, KW, BT>(order[obase + blockIdx.x], (int)threadIdx.x,
                                              bucket_view, views,
                                              bstart, bend, ival, pinfo, rec, ns_tile, segl, ids,
                                              lpp, part, counters, pix_t, pix_w, pix_n);
@@ -592,7 +595,7 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
         // in registers over the loop
         int t = (int)threadIdx.x;
         asm volatile("" : "+v"(t));
-        composite_tile<COUNT, PAD, LMAX, KW>(order[obase + i], t, bucket_view, views, bstart, bend,
+        composite_tile<COUNT, PAD, LMAX, KW, BT>(order[obase + i], t, bucket_view, views, bstart, bend,
                                              ival, pinfo, rec, ns_tile, segl, ids, lpp, part,
                                              counters, pix_t, pix_w, pix_n);
     }
@@ -758,15 +761,16 @@ void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t*
     hipLaunchKernelGGL(k_sat, dim3(nb), dim3(256), 0, st, views, ns_tile, sat);
 }
 
-int composite_variants() { return 6; }
+int composite_variants() { return 7; }
 
 const char* composite_variant_name(int v)
 {
-    static const char* names[6] = {"occupancy 8, padded groups", "occupancy 6, padded groups",
+    static const char* names[7] = {"occupancy 8, padded groups", "occupancy 6, padded groups",
                                    "occupancy 5, padded groups", "occupancy 8, cut groups",
                                    "occupancy 8, cut groups, persistent queue",
-                                   "occupancy 8, padded groups, persistent queue"};
-    return (v >= 0 && v < 6) ? names[v] : "";
+                                   "occupancy 8, padded groups, persistent queue",
+                                   "occupancy 8, cut groups, batches of 32"};
+    return (v >= 0 && v < 7) ? names[v] : "";
 }
 
 void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t* order,
@@ -784,33 +788,34 @@ void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t
         launch_fill_u32(queue, 1, 0u, st);
         grid = std::min(nbuckets, std::max(pgrid, 1u));
     }
-#define SLAG_COMP(C, W, P, LM, K, Q)                                                               \
-    hipLaunchKernelGGL((k_composite<C, W, P, LM, K, Q>), dim3(grid), dim3(256), 0, st, order,     \
+#define SLAG_COMP(C, W, P, LM, K, Q, BT)                                                           \
+    hipLaunchKernelGGL((k_composite<C, W, P, LM, K, Q, BT>), dim3(grid), dim3(256), 0, st, order, \
                        obase, nbuckets, queue, bucket_view, views, bstart, bend, ival, pinfo, rec, \
                        ns_tile, segl, ids, lpp, part, counters, pix_t, pix_w, pix_n)
 #define SLAG_COMP_V(LM)                                                                            \
     do {                                                                                           \
         if (count) {                                                                               \
-            SLAG_COMP(true, 8, false, LM, false, false);                                           \
+            SLAG_COMP(true, 8, false, LM, false, false, 64);                                       \
             break;                                                                                 \
         }                                                                                          \
         switch (variant) {                                                                         \
-        case 1: SLAG_COMP(false, 6, true, LM, false, false); break;                                \
-        case 2: SLAG_COMP(false, 5, true, LM, false, false); break;                                \
-        case 3: SLAG_COMP(false, 8, false, LM, false, false); break;                               \
-        case 4: SLAG_COMP(false, 8, false, LM, false, true); break;                                \
-        case 5: SLAG_COMP(false, 8, true, LM, false, true); break;                                 \
-        default: SLAG_COMP(false, 8, true, LM, false, false); break;                               \
+        case 1: SLAG_COMP(false, 6, true, LM, false, false, 64); break;                            \
+        case 2: SLAG_COMP(false, 5, true, LM, false, false, 64); break;                            \
+        case 3: SLAG_COMP(false, 8, false, LM, false, false, 64); break;                           \
+        case 4: SLAG_COMP(false, 8, false, LM, false, true, 64); break;                            \
+        case 5: SLAG_COMP(false, 8, true, LM, false, true, 64); break;                             \
+        case 6: SLAG_COMP(false, 8, false, LM, false, false, 32); break;                           \
+        default: SLAG_COMP(false, 8, true, LM, false, false, 64); break;                           \
         }                                                                                          \
     } while (0)
     if (kernel_w) {
         // kernel weights: the occupancy-8, cut-groups shape only (no tuning)
         if (count) {
-            if (lpp <= 1) SLAG_COMP(true, 8, false, 1, true, false);
-            else SLAG_COMP(true, 8, false, MAX_LABELS, true, false);
+            if (lpp <= 1) SLAG_COMP(true, 8, false, 1, true, false, 64);
+            else SLAG_COMP(true, 8, false, MAX_LABELS, true, false, 64);
         } else {
-            if (lpp <= 1) SLAG_COMP(false, 8, false, 1, true, false);
-            else SLAG_COMP(false, 8, false, MAX_LABELS, true, false);
+            if (lpp <= 1) SLAG_COMP(false, 8, false, 1, true, false, 64);
+            else SLAG_COMP(false, 8, false, MAX_LABELS, true, false, 64);
         }
     } else if (lpp <= 1) {
         SLAG_COMP_V(1);
