@@ -301,6 +301,14 @@ def accuracy_and_cpu(slag, scene, views, budget_s):
                       f"the whole workload extrapolates linearly in views (the lift is additive "
                       f"over views) to {scene.n_views * dt / len(views):.0f} s",
                extrapolated_workload_s=round(scene.n_views * dt / len(views), 1))
+    # the same oracle on one thread, whole 2,000-Gaussian workload (4 views of 64x64)
+    from synthetic import make_scene
+    small = make_scene("plain_fp32_2k")
+    t0 = time.perf_counter()
+    oracle.lift(small, nthreads=1)
+    dt1 = time.perf_counter() - t0
+    cpu["single_thread_plain_fp32_2k"] = dict(value=round(small.n_views / dt1, 3), unit="views/s",
+                                              threads=1, seconds=round(dt1, 3))
     return acc, cpu
 
 
