@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "lift views/s + Gaussian-pixel contribs/s at 1 GPU"
 HEADLINE = "stress_4m"
+TILE_SIZE = 16   # tile edge of the measured lifts (--tile-size)
 DESC = {
     "stress_4m": "4M Gaussians from 200 clusters over 10x10x3, 1000 nadir views 1024x768 on a "
                  "lawnmower path, 100-200 Voronoi segments/view, D=768 BF16 object-vocabulary "
@@ -153,7 +154,8 @@ def measure(slag, torch, scene, steps, warmup, count=True, stage_steps=3, eager=
     if count:
         # contributions, in-box tests and non-zero weights: a separate counting
         # lift (not timed)
-        with slag.Lifter(0, flags=slag.SLAG_FLAG_COUNT | slag.SLAG_FLAG_KEEP_DEBUG) as Lc:
+        with slag.Lifter(0, flags=slag.SLAG_FLAG_COUNT | slag.SLAG_FLAG_KEEP_DEBUG,
+                         tile_size=TILE_SIZE) as Lc:
             Lc.set_scene(scene, device_tensors=True)
             Lc.lift()
             st = Lc.stats()
@@ -163,7 +165,7 @@ def measure(slag, torch, scene, steps, warmup, count=True, stage_steps=3, eager=
              f"tile tests {st['n_tile_tests']}, non-zero weights {st['n_weights']}")
     flags = slag.SLAG_FLAG_PROFILE | slag.SLAG_FLAG_AUTOTUNE | (0 if eager else slag.SLAG_FLAG_GRAPH)
     stream = torch.cuda.Stream()
-    L = slag.Lifter(0, stream=stream.cuda_stream, flags=flags)
+    L = slag.Lifter(0, stream=stream.cuda_stream, flags=flags, tile_size=TILE_SIZE)
     t_up = time.perf_counter()
     L.set_scene(scene, device_tensors=True)
     torch.cuda.synchronize()
@@ -199,7 +201,8 @@ def measure(slag, torch, scene, steps, warmup, count=True, stage_steps=3, eager=
     # runtime); their sum is checked against the replayed step
     stage_ms = {}
     tot = 0.0
-    with slag.Lifter(0, flags=slag.SLAG_FLAG_PROFILE | slag.SLAG_FLAG_AUTOTUNE) as Lp:
+    with slag.Lifter(0, flags=slag.SLAG_FLAG_PROFILE | slag.SLAG_FLAG_AUTOTUNE,
+                     tile_size=TILE_SIZE) as Lp:
         Lp.set_scene(scene, device_tensors=True)
         Lp.lift()
         Lp.stats()
@@ -422,6 +425,8 @@ def main():
     ap.add_argument("--eager", action="store_true", help="time eager lifts instead of graph replays")
     ap.add_argument("--no-secondary", action="store_true", help="skip the smaller workloads")
     ap.add_argument("--no-codec", action="store_true", help="skip the codec section")
+    ap.add_argument("--tile-size", type=int, default=16, choices=[8, 16],
+                    help="binning and compositing tile edge of the timed lifts")
     ap.add_argument("--codec-steps", type=int, default=4000)
     ap.add_argument("--codec-k", type=int, default=16, help="code size (16, 32, 48 or 64)")
     ap.add_argument("--codec-hidden", type=int, default=256)
@@ -430,6 +435,8 @@ def main():
                     help="also run one plain device copy of BYTES (read) + BYTES (write), "
                          "to scale hardware traffic counters")
     args = ap.parse_args()
+    global TILE_SIZE
+    TILE_SIZE = args.tile_size
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library lifts on a "
               "single GPU and does not shard across GPUs", file=sys.stderr)
@@ -521,7 +528,7 @@ def main():
         "dtype": "bf16" if wl != "plain_fp32_2k" else "f32",
         "data": "synthetic",
         "config": {"workload": wl, "desc": DESC[wl], "n_gaussians": N, "n_views": V,
-                   "feature_dim": D, "parallelism": "single GPU"},
+                   "feature_dim": D, "tile_size": TILE_SIZE, "parallelism": "single GPU"},
         "contribs_per_s": round(res["contribs_per_s"], 1) if "contribs_per_s" in res else None,
         "n_contrib": res.get("n_contrib"),
         "n_visible_pairs": res["n_visible_pairs"],

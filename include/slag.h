@@ -108,8 +108,11 @@ typedef struct {
      * tangents.  Need 0 < alpha_min < alpha_max <= 1, 0 < t_min < 1, else
      * slag_create fails with SLAG_E_INVALID_ARG. */
     float alpha_max, alpha_min, t_min, dilation, near_z, guard;
-    int32_t tile_size;              /* compositing tile edge: 0 (= 16) or 16; others are
-                                       SLAG_E_NOT_SUPPORTED */
+    int32_t tile_size;              /* binning and compositing tile edge in pixels: 0 (=
+                                       16), 16 (four waves of 8 x 8 per tile) or 8 (one
+                                       wave); others are SLAG_E_NOT_SUPPORTED.  Contributing
+                                       sets and per-pixel weights do not depend on it; W,
+                                       den and E only through the order of FP32 sums */
     int32_t deterministic;          /* 0 or 1: every lift is deterministic (bitwise-equal
                                        results for equal inputs and options, whatever the
                                        launch order or atomics' timing); 1 asks for it */
@@ -131,7 +134,7 @@ typedef struct {
 typedef struct {
     int64_t n_views, n_batches;
     int64_t n_visible_pairs;        /* (view, Gaussian) pairs with a non-empty box */
-    int64_t n_intersections;        /* (pair, 16x16 tile) entries */
+    int64_t n_intersections;        /* (pair, tile) entries */
     int64_t n_part_slots;           /* per-(intersection, tile segment) partial sums */
     int64_t n_weights;              /* non-zero (pair, tile, segment) weights */
     int64_t n_contrib;              /* accepted blends, all pixels (SLAG_FLAG_COUNT) */
@@ -267,7 +270,7 @@ int32_t slag_variant_count(void);
 
 /* Debug exports for the last view batch (needs SLAG_FLAG_KEEP_DEBUG).
  * Tile lists of view `view`: entries ordered by (tile, depth, Gaussian) with
- * tile = ty * ceil(W/16) + tx; three host arrays of capacity `cap`.  *len
+ * tile = ty * ceil(W/T) + tx for tiles of T x T pixels; three host arrays of capacity `cap`.  *len
  * receives the count (also when it exceeds cap, then nothing is written). */
 slag_status slag_debug_tile_lists(slag_ctx* ctx, int32_t view, uint32_t* tile,
                                   uint32_t* depth_bits, uint32_t* gauss, int64_t cap,

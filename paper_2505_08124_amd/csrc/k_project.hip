@@ -153,9 +153,11 @@ __device__ __forceinline__ void project_fine(const ViewDev& V, float mx, float m
     rc = (float)(-0.5 * L2E * c00 * idet);
 }
 
-__device__ __forceinline__ uint32_t tiles_of(const Proj& P)
+// Tiles of the pixel box (tsh = log2 of the tile edge; the box is clamped to
+// the image, so its corners are not negative).
+__device__ __forceinline__ uint32_t tiles_of(const Proj& P, int tsh)
 {
-    return (uint32_t)((P.x1 / TILE - P.x0 / TILE + 1) * (P.y1 / TILE - P.y0 / TILE + 1));
+    return (uint32_t)(((P.x1 >> tsh) - (P.x0 >> tsh) + 1) * ((P.y1 >> tsh) - (P.y0 >> tsh) + 1));
 }
 
 __device__ __forceinline__ void load_cov(const float* cov3, int64_t n, int64_t g, float* S)
@@ -401,7 +403,7 @@ __global__ __launch_bounds__(256) void k_count(int64_t n, const ViewDev* __restr
         Proj P;
         uint32_t tc = 0;
         if (project(V, mx, my, mz, S, P)) {
-            tc = tiles_of(P);
+            tc = tiles_of(P, V.tsh);
             nvis++;
             const uint32_t zb = __float_as_uint(P.z);
             zmin = min(zmin, zb);
@@ -545,7 +547,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         }
         if (pz) pz[pidx] = __float_as_uint(P.z);      // debug exports only
         // part slots of this pair: sum of the tile segment counts over its tile rect
-        const int tx0 = P.x0 / TILE, tx1 = P.x1 / TILE, ty0 = P.y0 / TILE, ty1 = P.y1 / TILE;
+        const int tx0 = P.x0 >> V.tsh, tx1 = P.x1 >> V.tsh, ty0 = P.y0 >> V.tsh, ty1 = P.y1 >> V.tsh;
         const uint32_t ps = S[(ty1 + 1) * sw + tx1 + 1] - S[ty0 * sw + tx1 + 1] -
                             S[(ty1 + 1) * sw + tx0] + S[ty0 * sw + tx0];
         psz[pidx] = ps;

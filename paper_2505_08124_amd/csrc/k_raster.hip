@@ -4,7 +4,7 @@
 // and the per-view part of the aggregation sums over p in M_j).
 //
 // A 16x16 tile is one 256-thread workgroup: four wave64s, each owning an 8x8
-// pixel block.  The tile's depth-ordered list is staged through LDS BATCH
+// pixel block (an 8x8 tile, the other tile size, is one wave).  The tile's depth-ordered list is staged through LDS BATCH
 // entries at a time.  For every entry each lane blends its pixel
 // (alpha = min(0.99, o exp(-q/2)), skip below 1/255, stop before T < 1e-4,
 // w = alpha T) and each 16-lane row reduces w over the lanes of each segment
@@ -59,16 +59,16 @@ __device__ __forceinline__ uint32_t sat_rect(const uint32_t* S, int sw, int xa, 
 
 // Distinct segment ids of each tile, ascending, over every label layer of
 // its pixels (a pixel lies in up to lpp masks; -1 = none).  One wave per
-// tile, four tiles per workgroup: each lane holds four pixels of the 16 x 16
-// tile (column lane % 16, rows lane / 16 + 4 r) with their NL = 1 or
-// MAX_LABELS layers.  A ballot loop finds one distinct id per iteration (the
+// tile, four tiles per workgroup: each lane holds TS^2 / 64 pixels of the
+// TS x TS tile (column lane % TS, rows lane / TS + (64 / TS) r) with their
+// NL = 1 or MAX_LABELS layers.  A ballot loop finds one distinct id per iteration (the
 // first remaining value of the first lane that has one), clears it in every
 // lane and appends it to the wave's list in LDS; each id of the list then
 // goes to the position given by the number of smaller ids.  Tiles hold few
-// segments, so both loops are short.  More than TILE_PIX distinct ids in one
+// segments, so both loops are short.  More than TS^2 distinct ids in one
 // tile (only possible with several layers) set bit 4 of *err and keep the
-// TILE_PIX smallest.
-template <int NL>
+// TS^2 smallest.
+template <int NL, int TS>
 __global__ __launch_bounds__(256) void k_tile_segs(uint32_t nbuckets,
                                                    const uint32_t* __restrict__ bucket_view,
                                                    const ViewDev* __restrict__ views,
@@ -77,7 +77,8 @@ __global__ __launch_bounds__(256) void k_tile_segs(uint32_t nbuckets,
                                                    uint16_t* __restrict__ segl,
                                                    unsigned long long* __restrict__ err)
 {
-    constexpr int NV = 4 * NL;   // values per lane
+    constexpr int TPX = TS * TS, NR = TPX / 64, RPP = 64 / TS;
+    constexpr int NV = NR * NL;   // values per lane
     __shared__ uint32_t cand[4][64 * NV];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t b = blockIdx.x * 4u + (uint32_t)w;
@@ -85,12 +86,12 @@ __global__ __launch_bounds__(256) void k_tile_segs(uint32_t nbuckets,
     const ViewDev& V = views[bucket_view[b]];
     const uint32_t tile = b - V.tile_base;
     const int tx = (int)(tile % (uint32_t)V.ntx), ty = (int)(tile / (uint32_t)V.ntx);
-    const int px = tx * TILE + (lane & 15);
+    const int px = tx * TS + lane % TS;
     int32_t idv[NV];
     uint32_t left = 0;   // bit k: value k is an id not yet taken
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-        const int py = ty * TILE + (lane >> 4) + 4 * r;
+    for (int r = 0; r < NR; r++) {
+        const int py = ty * TS + lane / TS + RPP * r;
         const bool inside = px < V.W && py < V.H;
         const uint64_t pb = (V.pix_off + (uint64_t)py * V.W + px) * (uint64_t)lpp;
 #pragma unroll
@@ -122,11 +123,11 @@ __global__ __launch_bounds__(256) void k_tile_segs(uint32_t nbuckets,
         const uint32_t c = cand[w][i];
         uint32_t pos = 0;
         for (uint32_t j = 0; j < nc; j++) pos += cand[w][j] < c;
-        if (pos < (uint32_t)TILE_PIX) segl[(uint64_t)b * TILE_PIX + pos] = (uint16_t)c;
+        if (pos < (uint32_t)TPX) segl[(uint64_t)b * TPX + pos] = (uint16_t)c;
     }
     if (lane == 0) {
-        ns_tile[b] = nc < (uint32_t)TILE_PIX ? nc : (uint32_t)TILE_PIX;
-        if (nc > (uint32_t)TILE_PIX) atomicOr(err, 4ull);
+        ns_tile[b] = nc < (uint32_t)TPX ? nc : (uint32_t)TPX;
+        if (nc > (uint32_t)TPX) atomicOr(err, 4ull);
     }
 }
 
@@ -304,11 +305,11 @@ __device__ __forceinline__ void blend_batch(const float4* __restrict__ w0, const
 }
 
 // One tile (bucket b: a (view, tile) with a non-empty list) composited by the
-// workgroup.  Variants (same arithmetic, bitwise-equal results): MINW (of the
+// workgroup: TS x TS pixels, one wave per 8x8 block (four waves, or one).  Variants (same arithmetic, bitwise-equal results): MINW (of the
 // kernel) = waves per SIMD the register budget must allow; PAD = four-entry
 // groups padded with null entries (loads of a group can be issued together)
 // or cut at the end.
-template <bool COUNT, bool PAD, int LMAX, bool KW, int BT>
+template <bool COUNT, bool PAD, int LMAX, bool KW, int BT, int TS>
 __device__ __forceinline__ void composite_tile(
     const uint32_t b, const int t,
     const uint32_t* __restrict__ bucket_view, const ViewDev* __restrict__ views,
@@ -320,14 +321,16 @@ __device__ __forceinline__ void composite_tile(
     float* __restrict__ pix_t, float* __restrict__ pix_w, uint32_t* __restrict__ pix_n)
 {
     static_assert(BT % 4 == 0 && BT <= 64, "one batch entry per lane, groups of four");
-    __shared__ float4 s_w0[4][BT];            // per wave: entries touching its block, exponent
-    __shared__ float4 s_w1[4][BT];            //   coefficients (c0, cx, cy, cxx), (cxy, cyy, box, box)
-    __shared__ int s_wj[4][BT];               //   their index in the batch
-    __shared__ float s_lo[4][BT];             //   log2(opacity) (kernel weights)
-    __shared__ float s_acc[4][BT][NS_CAP];    // per wave weight sums [entry][segment]
+    static_assert(TS == 16 || TS == 8, "tiles of 16 x 16 or 8 x 8 pixels");
+    constexpr int NW = TS * TS / 64, NTH = 64 * NW, TPX = TS * TS;
+    __shared__ float4 s_w0[NW][BT];           // per wave: entries touching its block, exponent
+    __shared__ float4 s_w1[NW][BT];           //   coefficients (c0, cx, cy, cxx), (cxy, cyy, box, box)
+    __shared__ int s_wj[NW][BT];              //   their index in the batch
+    __shared__ float s_lo[NW][BT];            //   log2(opacity) (kernel weights)
+    __shared__ float s_acc[NW][BT][NS_CAP];   // per wave weight sums [entry][segment]
     __shared__ uint32_t s_pair[BT];           // pair of each batch entry
     __shared__ uint32_t s_tir[BT];            // index of this tile in the pair's tile rectangle
-    __shared__ uint16_t s_seg[TILE_PIX];
+    __shared__ uint16_t s_seg[TPX];
 
     const uint32_t start = bstart[b], end = bend[b];
     if (start >= end) return;
@@ -338,8 +341,8 @@ __device__ __forceinline__ void composite_tile(
     const int tx = (int)(tile % (uint32_t)V.ntx), ty = (int)(tile / (uint32_t)V.ntx);
     const int wv = t >> 6, lane = t & 63;
     const float amin = V.amin, amax = V.amax, tmin = V.tmin, l2amin = V.l2amin;
-    const int bx0 = tx * TILE + (wv & 1) * 8;    // this wave's 8x8 pixel block
-    const int by0 = ty * TILE + (wv >> 1) * 8;
+    const int bx0 = tx * TS + (wv & 1) * 8;    // this wave's 8x8 pixel block
+    const int by0 = ty * TS + (wv >> 1) * 8;
     const int px = bx0 + (lane & 7);
     const int py = by0 + (lane >> 3);
     const bool valid = px < V.W && py < V.H;
@@ -348,7 +351,7 @@ __device__ __forceinline__ void composite_tile(
 #pragma unroll
     for (int l = 0; l < LMAX; l++)
         seg[l] = (valid && l < lpp) ? ids[(V.pix_off + (uint64_t)py * V.W + px) * (uint64_t)lpp + l] : -1;
-    for (uint32_t i = t; i < ns; i += 256) s_seg[i] = segl[(uint64_t)b * TILE_PIX + i];
+    for (uint32_t i = t; i < ns; i += NTH) s_seg[i] = segl[(uint64_t)b * TPX + i];
     __syncthreads();
     int ls[LMAX];   // index of each of the pixel's segments among the tile's segments
 #pragma unroll
@@ -467,8 +470,8 @@ __device__ __forceinline__ void composite_tile(
                 if (KW) s_lo[wv][lane] = 0.0f;
             }
             if (wv == 0 && lane < nb) {
-                const int rtx0 = (int)(ba & 0xFFFFu) / TILE, rty0 = (int)(ba >> 16) / TILE;
-                const int rw = (int)(bb & 0xFFFFu) / TILE - rtx0 + 1;
+                const int rtx0 = (int)(ba & 0xFFFFu) / TS, rty0 = (int)(ba >> 16) / TS;
+                const int rw = (int)(bb & 0xFFFFu) / TS - rtx0 + 1;
                 s_pair[lane] = pcur;
                 s_tir[lane] = (uint32_t)((ty - rty0) * rw + (tx - rtx0));
             }
@@ -494,8 +497,8 @@ __device__ __forceinline__ void composite_tile(
                 }
             }
             __syncthreads();
-            // one thread per batch entry: the four waves' sums per segment, in
-            // a fixed order; the non-zero ones are appended to the pair's part
+            // one thread per batch entry: the waves' sums per segment, in a
+            // fixed order; the non-zero ones are appended to the pair's part
             // list (one atomic per (pair, tile) with output; the lists'
             // order is arbitrary, so readers visit entries by key)
             if (t < nb) {
@@ -505,9 +508,14 @@ __device__ __forceinline__ void composite_tile(
                 for (int k = 0; k < NS_CAP; k++) {
                     sv[k] = 0.0f;
                     if (k < nsc) {
-                        sv[k] = ((s_acc[0][t][k] + s_acc[1][t][k]) + s_acc[2][t][k]) + s_acc[3][t][k];
-                        s_acc[0][t][k] = 0.0f; s_acc[1][t][k] = 0.0f;
-                        s_acc[2][t][k] = 0.0f; s_acc[3][t][k] = 0.0f;
+                        if constexpr (NW == 4) {
+                            sv[k] = ((s_acc[0][t][k] + s_acc[1][t][k]) + s_acc[2][t][k]) + s_acc[3][t][k];
+                            s_acc[0][t][k] = 0.0f; s_acc[1][t][k] = 0.0f;
+                            s_acc[2][t][k] = 0.0f; s_acc[3][t][k] = 0.0f;
+                        } else {
+                            sv[k] = s_acc[0][t][k];
+                            s_acc[0][t][k] = 0.0f;
+                        }
                         nz += sv[k] != 0.0f;
                     }
                 }
@@ -562,8 +570,8 @@ __device__ __forceinline__ void composite_tile(
 // bucket (the hardware hands out workgroups in index order), or PERSIST: a
 // grid of resident workgroups that each take the next bucket from a queue
 // counter (*queue = 0 at launch) until all nbk are taken.
-template <bool COUNT, int MINW, bool PAD, int LMAX, bool KW, bool PERSIST, int BT>
-__global__ __launch_bounds__(256, MINW) void k_composite(
+template <bool COUNT, int MINW, bool PAD, int LMAX, bool KW, bool PERSIST, int BT, int TS>
+__global__ __launch_bounds__(TS * TS, TS == 16 ? MINW : 4 * MINW) void k_composite(
     const uint32_t* __restrict__ order, uint32_t obase, uint32_t nbk,
     uint32_t* __restrict__ queue,
     const uint32_t* __restrict__ bucket_view, const ViewDev* __restrict__ views,
@@ -575,7 +583,7 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
     float* __restrict__ pix_t, float* __restrict__ pix_w, uint32_t* __restrict__ pix_n)
 {
     if (!PERSIST) {
-        composite_tile<COUNT, PAD, LMAX, KW, BT>(order[obase + blockIdx.x], (int)threadIdx.x,
+        composite_tile<COUNT, PAD, LMAX, KW, BT, TS>(order[obase + blockIdx.x], (int)threadIdx.x,
                                              bucket_view, views,
                                              bstart, bend, ival, pinfo, rec, ns_tile, segl, ids,
                                              lpp, part, counters, pix_t, pix_w, pix_n);
@@ -595,7 +603,7 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
         // in registers over the loop
         int t = (int)threadIdx.x;
         asm volatile("" : "+v"(t));
-        composite_tile<COUNT, PAD, LMAX, KW, BT>(order[obase + i], t, bucket_view, views, bstart, bend,
+        composite_tile<COUNT, PAD, LMAX, KW, BT, TS>(order[obase + i], t, bucket_view, views, bstart, bend,
                                              ival, pinfo, rec, ns_tile, segl, ids, lpp, part,
                                              counters, pix_t, pix_w, pix_n);
     }
@@ -604,13 +612,13 @@ __global__ __launch_bounds__(256, MINW) void k_composite(
 // Render-back of per-Gaussian attributes into one view (the paper's
 // rendering equation with the lift's weights: C_p = sum_k w_kp a_k /
 // sum_k w_kp over the Gaussians the front-to-back walk blends at p, every
-// pixel, no masking).  One workgroup per 16x16 tile of the view, four waves
-// of 8x8 pixels; the tile's list is staged BATCH entries at a time with the
+// pixel, no masking).  One workgroup per TS x TS tile of the view, one wave
+// per 8x8 pixels; the tile's list is staged BATCH entries at a time with the
 // entries' attribute channels [c0, c0 + 16); every lane evaluates every
 // entry with the compositing's own exponent expansion (about its wave's
 // block centre), so its weights and decisions are the lift's, bit for bit.
-template <bool KW>
-__global__ __launch_bounds__(256) void k_render(const ViewDev* __restrict__ views, int vi,
+template <bool KW, int TS>
+__global__ __launch_bounds__(TS * TS) void k_render(const ViewDev* __restrict__ views, int vi,
                                                 const uint32_t* __restrict__ bstart,
                                                 const uint32_t* __restrict__ bend,
                                                 const uint32_t* __restrict__ ival,
@@ -627,7 +635,7 @@ __global__ __launch_bounds__(256) void k_render(const ViewDev* __restrict__ view
     const uint32_t b = V.tile_base + tile;
     const int tx = (int)(tile % (uint32_t)V.ntx), ty = (int)(tile / (uint32_t)V.ntx);
     const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
-    const int bx0 = tx * TILE + (wv & 1) * 8, by0 = ty * TILE + (wv >> 1) * 8;
+    const int bx0 = tx * TS + (wv & 1) * 8, by0 = ty * TS + (wv >> 1) * 8;
     const int px = bx0 + (lane & 7), py = by0 + (lane >> 3);
     const bool valid = px < V.W && py < V.H;
     const float lx = (float)(lane & 7) - 3.5f, ly = (float)(lane >> 3) - 3.5f;
@@ -724,34 +732,40 @@ __global__ __launch_bounds__(256) void k_merge(uint64_t npairs, const uint16_t* 
 
 }  // namespace
 
-void launch_render(bool kernel_w, int ntiles, const ViewDev* views, int vi, const uint32_t* bstart,
-                   const uint32_t* bend, const uint32_t* ival, const float4* rec,
-                   const uint32_t* pgauss, const float* attr, int C, float* out, float* wsum,
-                   hipStream_t st)
+void launch_render(bool kernel_w, int ts, int ntiles, const ViewDev* views, int vi,
+                   const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
+                   const float4* rec, const uint32_t* pgauss, const float* attr, int C, float* out,
+                   float* wsum, hipStream_t st)
 {
     if (ntiles <= 0) return;
+#define SLAG_RENDER(K, T)                                                                         \
+    hipLaunchKernelGGL((k_render<K, T>), dim3((unsigned)ntiles), dim3(T * T), 0, st, views, vi,   \
+                       bstart, bend, ival, rec, pgauss, attr, C, c0, out, wsum)
     for (int c0 = 0; c0 < C; c0 += 16) {
-        if (kernel_w)
-            hipLaunchKernelGGL((k_render<true>), dim3((unsigned)ntiles), dim3(256), 0, st, views, vi,
-                               bstart, bend, ival, rec, pgauss, attr, C, c0, out, wsum);
-        else
-            hipLaunchKernelGGL((k_render<false>), dim3((unsigned)ntiles), dim3(256), 0, st, views, vi,
-                               bstart, bend, ival, rec, pgauss, attr, C, c0, out, wsum);
+        if (ts == 8) {
+            if (kernel_w) SLAG_RENDER(true, 8); else SLAG_RENDER(false, 8);
+        } else {
+            if (kernel_w) SLAG_RENDER(true, 16); else SLAG_RENDER(false, 16);
+        }
     }
+#undef SLAG_RENDER
 }
 
-void launch_tile_segs(uint32_t nbuckets, const uint32_t* bucket_view, const ViewDev* views,
+void launch_tile_segs(int ts, uint32_t nbuckets, const uint32_t* bucket_view, const ViewDev* views,
                       const int32_t* ids, int lpp, uint32_t* ns_tile, uint16_t* segl,
                       unsigned long long* err, hipStream_t st)
 {
     if (!nbuckets) return;
     const dim3 grid((nbuckets + 3) / 4);
-    if (lpp <= 1)
-        hipLaunchKernelGGL(k_tile_segs<1>, grid, dim3(256), 0, st, nbuckets, bucket_view, views, ids,
-                           lpp, ns_tile, segl, err);
-    else
-        hipLaunchKernelGGL(k_tile_segs<MAX_LABELS>, grid, dim3(256), 0, st, nbuckets, bucket_view,
-                           views, ids, lpp, ns_tile, segl, err);
+#define SLAG_SEGS(L, T)                                                                           \
+    hipLaunchKernelGGL((k_tile_segs<L, T>), grid, dim3(256), 0, st, nbuckets, bucket_view, views, \
+                       ids, lpp, ns_tile, segl, err)
+    if (ts == 8) {
+        if (lpp <= 1) SLAG_SEGS(1, 8); else SLAG_SEGS(MAX_LABELS, 8);
+    } else {
+        if (lpp <= 1) SLAG_SEGS(1, 16); else SLAG_SEGS(MAX_LABELS, 16);
+    }
+#undef SLAG_SEGS
 }
 
 void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t* sat,
@@ -773,25 +787,19 @@ const char* composite_variant_name(int v)
     return (v >= 0 && v < 7) ? names[v] : "";
 }
 
-void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t* order,
-                      uint32_t obase, const uint32_t* bucket_view, const ViewDev* views,
-                      const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
-                      uint2* pinfo, const float4* rec, const uint32_t* ns_tile,
-                      const uint16_t* segl, const int32_t* ids, int lpp, bool kernel_w,
-                      uint2* part, unsigned long long* counters, float* pix_t, float* pix_w,
-                      uint32_t* pix_n, uint32_t* queue, uint32_t pgrid, hipStream_t st)
+template <int TS>
+static void composite_ts(bool count, int variant, uint32_t grid, uint32_t nbuckets,
+                         const uint32_t* order, uint32_t obase, const uint32_t* bucket_view,
+                         const ViewDev* views, const uint32_t* bstart, const uint32_t* bend,
+                         const uint32_t* ival, uint2* pinfo, const float4* rec,
+                         const uint32_t* ns_tile, const uint16_t* segl, const int32_t* ids, int lpp,
+                         bool kernel_w, uint2* part, unsigned long long* counters, float* pix_t,
+                         float* pix_w, uint32_t* pix_n, uint32_t* queue, hipStream_t st)
 {
-    if (!nbuckets) return;
-    const bool persist = !count && !kernel_w && (variant == 4 || variant == 5);
-    uint32_t grid = nbuckets;
-    if (persist) {
-        launch_fill_u32(queue, 1, 0u, st);
-        grid = std::min(nbuckets, std::max(pgrid, 1u));
-    }
 #define SLAG_COMP(C, W, P, LM, K, Q, BT)                                                           \
-    hipLaunchKernelGGL((k_composite<C, W, P, LM, K, Q, BT>), dim3(grid), dim3(256), 0, st, order, \
-                       obase, nbuckets, queue, bucket_view, views, bstart, bend, ival, pinfo, rec, \
-                       ns_tile, segl, ids, lpp, part, counters, pix_t, pix_w, pix_n)
+    hipLaunchKernelGGL((k_composite<C, W, P, LM, K, Q, BT, TS>), dim3(grid), dim3(TS * TS), 0, st, \
+                       order, obase, nbuckets, queue, bucket_view, views, bstart, bend, ival,      \
+                       pinfo, rec, ns_tile, segl, ids, lpp, part, counters, pix_t, pix_w, pix_n)
 #define SLAG_COMP_V(LM)                                                                            \
     do {                                                                                           \
         if (count) {                                                                               \
@@ -824,6 +832,32 @@ void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t
     }
 #undef SLAG_COMP_V
 #undef SLAG_COMP
+}
+
+void launch_composite(bool count, int variant, int ts, uint32_t nbuckets, const uint32_t* order,
+                      uint32_t obase, const uint32_t* bucket_view, const ViewDev* views,
+                      const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
+                      uint2* pinfo, const float4* rec, const uint32_t* ns_tile,
+                      const uint16_t* segl, const int32_t* ids, int lpp, bool kernel_w,
+                      uint2* part, unsigned long long* counters, float* pix_t, float* pix_w,
+                      uint32_t* pix_n, uint32_t* queue, uint32_t pgrid, hipStream_t st)
+{
+    if (!nbuckets) return;
+    const bool persist = !count && !kernel_w && (variant == 4 || variant == 5);
+    uint32_t grid = nbuckets;
+    if (persist) {
+        // pgrid: eight 4-wave workgroups per CU; 8 x 8 tiles are 1-wave workgroups
+        launch_fill_u32(queue, 1, 0u, st);
+        grid = std::min(nbuckets, std::max(pgrid * (ts == 8 ? 4u : 1u), 1u));
+    }
+    if (ts == 8)
+        composite_ts<8>(count, variant, grid, nbuckets, order, obase, bucket_view, views, bstart,
+                        bend, ival, pinfo, rec, ns_tile, segl, ids, lpp, kernel_w, part, counters,
+                        pix_t, pix_w, pix_n, queue, st);
+    else
+        composite_ts<16>(count, variant, grid, nbuckets, order, obase, bucket_view, views, bstart,
+                         bend, ival, pinfo, rec, ns_tile, segl, ids, lpp, kernel_w, part, counters,
+                         pix_t, pix_w, pix_n, queue, st);
 }
 
 void launch_init_pinfo(uint64_t npairs, const uint32_t* base, uint32_t total, uint2* pinfo,

@@ -241,8 +241,9 @@ static slag_status make_batch(slag_ctx* c, int v0, int nb, int lbits,
         x.l2amin = K.l2amin;
         x.guard_d = K.guard_d;
         x.dil_d = K.dil_d;
-        x.ntx = (cam.width + TILE - 1) / TILE;
-        x.nty = (cam.height + TILE - 1) / TILE;
+        x.ntx = (cam.width + c->ts - 1) / c->ts;
+        x.nty = (cam.height + c->ts - 1) / c->ts;
+        x.tsh = c->tsh;
         x.tile_base = tb;
         x.sat_off = so;
         x.pix_off = c->pix_off[v0 + i];
@@ -302,8 +303,8 @@ static slag_status build_plan(slag_ctx* c)
     // tile-sort keys are (view in launch << lbits) | tile in view, 32 bits
     int lbits = 0;
     for (int v = 0; v < V; v++) {
-        const int64_t nt = (int64_t)((c->cams[v].width + TILE - 1) / TILE) *
-                           ((c->cams[v].height + TILE - 1) / TILE);
+        const int64_t nt = (int64_t)((c->cams[v].width + c->ts - 1) / c->ts) *
+                           ((c->cams[v].height + c->ts - 1) / c->ts);
         lbits = std::max(lbits, bit_length((uint64_t)std::max<int64_t>(nt - 1, 0)));
     }
     lbits = std::max(lbits, 1);
@@ -552,13 +553,13 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
     // tile segment tables and their summed-area tables
     CK(stage_begin(c, ST_TILES, &ev));
     CK(ensure(c, c->ns_tile, (size_t)B.nbuckets * 4));
-    CK(ensure(c, c->segl, (size_t)B.nbuckets * TILE_PIX * 2));
+    CK(ensure(c, c->segl, (size_t)B.nbuckets * (size_t)(c->ts * c->ts) * 2));
     CK(ensure(c, c->sat, (size_t)B.nsat * 4));
     if (c->front_only) {
         // render-back: no segments, so no part slots
         launch_fill_u32(c->sat.as<uint32_t>(), B.nsat, 0u, st);
     } else {
-        launch_tile_segs(B.nbuckets, B.bucket_view.as<uint32_t>(), views, c->ids.as<int32_t>(),
+        launch_tile_segs(c->ts, B.nbuckets, B.bucket_view.as<uint32_t>(), views, c->ids.as<int32_t>(),
                          c->lpp, c->ns_tile.as<uint32_t>(), c->segl.as<uint16_t>(),
                          reinterpret_cast<unsigned long long*>(small + SM_LERR), st);
         launch_sat(nb, views, c->ns_tile.as<uint32_t>(), c->sat.as<uint32_t>(), st);
@@ -819,7 +820,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
                 if (c->tune.count(key)) continue;
                 auto launch = [&](int var) {
                     clear_lists();
-                    launch_composite(false, var, B.cls_nb[k], corder, B.cls_off[k],
+                    launch_composite(false, var, c->ts, B.cls_nb[k], corder, B.cls_off[k],
                                      B.bucket_view.as<uint32_t>(), views, c->bstart.as<uint32_t>(),
                                      c->bend.as<uint32_t>(), sval, c->pinfo.as<uint2>(),
                                      c->rec.as<float4>(), c->ns_tile.as<uint32_t>(),
@@ -855,7 +856,7 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
                 for (int v = 1; v < std::min(composite_variants(), 8); v++)
                     if (tot[v] < tot[var]) var = v;
         }
-        launch_composite(count, var, B.nbuckets, border, 0, B.bucket_view.as<uint32_t>(), views,
+        launch_composite(count, var, c->ts, B.nbuckets, border, 0, B.bucket_view.as<uint32_t>(), views,
                          c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(), sval,
                          c->pinfo.as<uint2>(), c->rec.as<float4>(), c->ns_tile.as<uint32_t>(),
                          c->segl.as<uint16_t>(), c->ids.as<int32_t>(), c->lpp, c->kernel_w,
@@ -924,10 +925,12 @@ slag_status slag_create(int32_t device, void* hip_stream, const slag_options* op
             delete c;
             return SLAG_E_INVALID_ARG;
         }
-        if (o.tile_size != 0 && o.tile_size != TILE) {
+        if (o.tile_size != 0 && o.tile_size != 16 && o.tile_size != 8) {
             delete c;
             return SLAG_E_NOT_SUPPORTED;
         }
+        c->ts = o.tile_size == 8 ? 8 : TILE;
+        c->tsh = c->ts == 8 ? 3 : 4;
         if (o.labels_per_pixel < 0 || o.labels_per_pixel > MAX_LABELS) {
             delete c;
             return SLAG_E_INVALID_ARG;
@@ -987,7 +990,8 @@ slag_status slag_create(int32_t device, void* hip_stream, const slag_options* op
         std::string arch(pr.gcnArchName);
         for (auto& ch : arch)
             if (std::isspace((unsigned char)ch)) ch = '_';
-        c->dev_kind = arch + "/" + std::to_string(pr.multiProcessorCount);
+        c->dev_kind = arch + "/" + std::to_string(pr.multiProcessorCount) + "/tile" +
+                      std::to_string(c->ts);
         const char* path = std::getenv("SLAG_TUNE_CACHE");
         c->tune_cache = path ? path : "";
         load_tune_cache(c);
@@ -1691,7 +1695,7 @@ extern "C" slag_status slag_get_debug(slag_ctx* c, slag_debug what, int32_t view
                 o[3 * i + 2] = g[i];
             }
         } else {
-            const int64_t nt = (int64_t)((W + TILE - 1) / TILE) * ((H + TILE - 1) / TILE);
+            const int64_t nt = (int64_t)((W + c->ts - 1) / c->ts) * ((H + c->ts - 1) / c->ts);
             *len = nt * 8;
             if (*len > cap) return SLAG_OK;
             uint32_t* o = static_cast<uint32_t*>(out);
@@ -1760,7 +1764,7 @@ extern "C" slag_status slag_render(slag_ctx* c, int32_t view, const float* attr,
     hipStream_t st = c->st;
     const slag_camera& cam = c->cams[view];
     const int64_t npix = (int64_t)cam.width * cam.height;
-    const int64_t ntiles = (int64_t)((cam.width + TILE - 1) / TILE) * ((cam.height + TILE - 1) / TILE);
+    const int64_t ntiles = (int64_t)((cam.width + c->ts - 1) / c->ts) * ((cam.height + c->ts - 1) / c->ts);
     const int lbits = std::max(1, bit_length((uint64_t)std::max<int64_t>(ntiles - 1, 0)));
     if (lbits > 31) FAIL(c, SLAG_E_CAPACITY, "image too large for 32-bit tile keys");
     float* dout = out;
@@ -1797,7 +1801,7 @@ extern "C" slag_status slag_render(slag_ctx* c, int32_t view, const float* attr,
     c->stats = keep;
     if (s != SLAG_OK) return s;
     if (c->front_ival) {
-        launch_render(c->kernel_w, (int)ntiles, c->rbatch.views.as<ViewDev>(), 0,
+        launch_render(c->kernel_w, c->ts, (int)ntiles, c->rbatch.views.as<ViewDev>(), 0,
                       c->bstart.as<uint32_t>(), c->bend.as<uint32_t>(), c->front_ival,
                       c->rec.as<float4>(), c->pgauss.as<uint32_t>(), dattr, C, dout, dws, st);
     } else {

@@ -155,6 +155,7 @@ struct slag_ctx {
     std::string tune_cache;   // file named by SLAG_TUNE_CACHE ("" = none)
     std::string dev_kind;     // architecture name and compute-unit count
     uint32_t pgrid = 0;       // workgroups of a persistent compositing launch
+    int ts = 16, tsh = 4;     // tile edge in pixels (16 or 8) and its log2
 
     // graph replay of the lift (SLAG_FLAG_GRAPH)
     uint64_t gen = 1;                 // bumped by every input change

@@ -5,8 +5,9 @@
 
 namespace slag {
 
-constexpr int TILE = 16;                 // tile edge in pixels (16 x 16 = 4 waves of 8 x 8)
-constexpr int TILE_PIX = TILE * TILE;
+constexpr int TILE = 16;                 // default tile edge in pixels (16 x 16 = 4 waves of 8 x 8;
+                                         // 8 x 8 tiles, one wave, are the other choice)
+constexpr int TILE_PIX = TILE * TILE;    // the most pixels (and tile segments) of a tile
 constexpr int NS_CAP = 4;                // tile segments accumulated per compositing pass
 constexpr int BATCH = 64;                // tile-list entries staged in LDS per step
 constexpr int MAX_LABELS = 4;            // masks one pixel may lie in (overlapping masks)
@@ -20,6 +21,7 @@ struct ViewDev {
     int32_t W, H;
     float limx, limy;        // guard clamp of x/z, y/z (1.3 x half-FOV tangent, FP32)
     int32_t ntx, nty;        // tiles per row / column
+    int32_t tsh;             // log2 of the tile edge (3 or 4)
     uint32_t tile_base;      // first bucket (tile) of this view in the launch
     uint32_t sat_off;        // first entry of this view's summed-area table
     uint64_t pix_off;        // first pixel of this view in the id array
@@ -154,10 +156,10 @@ void launch_bucket_keys(uint32_t nb, const uint32_t* bucket_view, const uint8_t*
 void launch_bucket_ranges(uint64_t ni, const uint32_t* ikey, const ViewDev* views, int lbits,
                           uint32_t* bstart, uint32_t* bend, hipStream_t st);
 
-// Distinct segment ids of each tile over the lpp label layers of its pixels
-// (ids [pixels][lpp], -1 = none); more than TILE_PIX in one tile sets bit 4
-// of *err.
-void launch_tile_segs(uint32_t nbuckets, const uint32_t* bucket_view, const ViewDev* views,
+// Distinct segment ids of each ts x ts tile over the lpp label layers of its
+// pixels (ids [pixels][lpp], -1 = none), ascending in segl[bucket][ts^2];
+// more than ts^2 in one tile sets bit 4 of *err.
+void launch_tile_segs(int ts, uint32_t nbuckets, const uint32_t* bucket_view, const ViewDev* views,
                       const int32_t* ids, int lpp, uint32_t* ns_tile, uint16_t* segl,
                       unsigned long long* err, hipStream_t st);
 void launch_sat(int nb, const ViewDev* views, const uint32_t* ns_tile, uint32_t* sat,
@@ -179,7 +181,7 @@ void launch_init_pinfo(uint64_t npairs, const uint32_t* base, uint32_t total, ui
 // walked (indexed like the id maps).  The persistent variants (4, 5) run
 // min(nbuckets, pgrid) workgroups that take buckets from *queue (zeroed here
 // by a fill kernel); the others ignore queue and pgrid.
-void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t* order,
+void launch_composite(bool count, int variant, int ts, uint32_t nbuckets, const uint32_t* order,
                       uint32_t obase, const uint32_t* bucket_view, const ViewDev* views,
                       const uint32_t* bstart, const uint32_t* bend, const uint32_t* ival,
                       uint2* pinfo, const float4* rec, const uint32_t* ns_tile,
@@ -189,7 +191,7 @@ void launch_composite(bool count, int variant, uint32_t nbuckets, const uint32_t
 // Render-back of attr [N][C] (caller's Gaussian order) into view vi of the
 // last launch: out [H][W][C] = sum w a / sum w per pixel (0 where no weight),
 // wsum [H][W] (may be null); ntiles = the view's tile count.
-void launch_render(bool kernel_w, int ntiles, const ViewDev* views, int vi, const uint32_t* bstart,
+void launch_render(bool kernel_w, int ts, int ntiles, const ViewDev* views, int vi, const uint32_t* bstart,
                    const uint32_t* bend, const uint32_t* ival, const float4* rec,
                    const uint32_t* pgauss, const float* attr, int C, float* out, float* wsum,
                    hipStream_t st);

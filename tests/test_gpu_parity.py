@@ -142,9 +142,9 @@ def check_embeddings(E, den, ref, scene, tag=""):
     return st["min_cos"], st["max_abs_err"]
 
 
-def check_tile_lists(L, scene, v):
+def check_tile_lists(L, scene, v, tile=16):
     t, z, g = L.tile_lists(v)
-    rt, rz, rg = oracle.sorted_keys(scene, v, 16, 16)
+    rt, rz, rg = oracle.sorted_keys(scene, v, tile, tile)
     assert t.size == rt.size, (t.size, rt.size)
     assert np.array_equal(t.astype(np.int64), rt)
     assert np.array_equal(z, rz)
@@ -396,8 +396,8 @@ def test_autotune_is_bitwise_neutral():
     L.close()
 
 
-@pytest.mark.parametrize("lpp", [1, 2])
-def test_every_compositing_variant_is_bitwise_equal(lpp):
+@pytest.mark.parametrize("lpp,tile", [(1, 16), (2, 16), (1, 8)])
+def test_every_compositing_variant_is_bitwise_equal(lpp, tile):
     """Every compositing variant (register budget, group padding, one
     workgroup per tile or a persistent grid taking tiles from a queue),
     forced through the composite_variant option, gives the default lift's
@@ -408,16 +408,16 @@ def test_every_compositing_variant_is_bitwise_equal(lpp):
     sc = make_scene("uneven_1m", n=40000, views=dict(n=6))
     if lpp == 2:
         sc = _overlap_scene(sc)
-    L0 = slag.Lifter(0, labels_per_pixel=lpp)
+    L0 = slag.Lifter(0, labels_per_pixel=lpp, tile_size=tile)
     L0.set_scene(sc)
     L0.lift()
     E0, den0 = L0.embeddings()
     L0.close()
     assert den0.max() > 0
     for v in range(slag.slag_variant_count()):
-        _say(f"variant {v} ({slag.lib().slag_variant_name(v).decode()}), labels {lpp}")
+        _say(f"variant {v} ({slag.lib().slag_variant_name(v).decode()}), labels {lpp}, tile {tile}")
         L = slag.Lifter(0, flags=slag.SLAG_FLAG_GRAPH, labels_per_pixel=lpp,
-                        composite_variant=v + 1)
+                        composite_variant=v + 1, tile_size=tile)
         L.set_scene(sc)
         for rep in range(3):
             L.lift()
@@ -464,6 +464,50 @@ def test_tuning_cache_file(tmp_path, monkeypatch):
     L3 = _lifter(sc, flags=slag.SLAG_FLAG_AUTOTUNE)
     assert slag.slag_get_tuning(L3.ctx) == []
     L3.close()
+
+
+@pytest.mark.parametrize("case", ["plain_fp32_2k", "ragged", "overlap"])
+def test_tile_size_8_and_independence(case):
+    """8 x 8 tiles (one wave per tile): tile lists bit-exact with the oracle's
+    key mirror at 8 x 8, W_v of every view and E against the oracle; and the
+    result does not depend on the tile size (the oracle has no tiles, and a
+    wave blends the same 8 x 8 pixel block with the same exponent expansion
+    at either size): the same (Gaussian, segment) sets, weights, den and E
+    equal to the 16 x 16 lift's up to the order of the FP32 sums."""
+    import paper_2505_08124_amd as slag
+    lpp = 1
+    if case == "plain_fp32_2k":
+        sc = make_scene("plain_fp32_2k")
+    elif case == "ragged":
+        sc = _ragged_scene()
+    else:
+        sc = _overlap_scene(make_scene("plain_fp32_2k"))
+        lpp = 2
+    ref = oracle.lift(sc)
+    out = {}
+    for tile in (8, 16):
+        L = slag.Lifter(0, flags=slag.SLAG_FLAG_KEEP_DEBUG, labels_per_pixel=lpp, tile_size=tile)
+        L.set_scene(sc)
+        L.lift()
+        E, den = L.embeddings()
+        trip = []
+        for v in range(sc.n_views):
+            check_tile_lists(L, sc, v, tile)
+            check_view_weights(L, sc, v, ref.views[v], f"tile{tile}_{case}")
+            trip.append(_gpu_triples(L, v))
+        check_embeddings(E, den, ref, sc, f"tile{tile}_{case}")
+        out[tile] = (E, den, trip)
+        L.close()
+    (E8, d8, t8), (E16, d16, t16) = out[8], out[16]
+    for v in range(sc.n_views):
+        (k8, w8), (k16, w16) = t8[v], t16[v]
+        assert np.array_equal(k8, k16), v                  # same contributing sets
+        np.testing.assert_allclose(w8, w16, rtol=1e-5, atol=1e-12)
+    assert np.array_equal(d8 > 0, d16 > 0)
+    np.testing.assert_allclose(d8, d16, rtol=1e-5, atol=1e-12)
+    np.testing.assert_allclose(E8, E16, rtol=1e-5, atol=1e-6)
+    _say(f"tile 8 vs 16 ({case}): max |dE| {np.abs(E8 - E16).max():.3g}, "
+         f"max rel d(den) {(np.abs(d8 - d16) / np.maximum(d16, 1e-30)).max():.3g}")
 
 
 def test_uneven_resolutions_one_launch():
@@ -676,10 +720,12 @@ def test_invalid_options_are_rejected():
         with pytest.raises(slag.SlagError) as ei:
             slag.Lifter(0, **bad)
         assert ei.value.status == slag.SLAG_E_INVALID_ARG, bad
-    with pytest.raises(slag.SlagError) as ei:
-        slag.Lifter(0, tile_size=8)
-    assert ei.value.status == slag.SLAG_E_NOT_SUPPORTED
+    for bad_tile in (4, 12, 32):
+        with pytest.raises(slag.SlagError) as ei:
+            slag.Lifter(0, tile_size=bad_tile)
+        assert ei.value.status == slag.SLAG_E_NOT_SUPPORTED
     slag.Lifter(0, tile_size=16, deterministic=1).close()
+    slag.Lifter(0, tile_size=8).close()
 
 
 @pytest.mark.parametrize("max_views,chunk", [(0, 512), (0, 208), (2, 1024), (0, 4096)])

@@ -73,6 +73,22 @@ def test_render_matches_oracle(case, C):
     L.close()
 
 
+def test_render_tile_size_8_is_bitwise_equal():
+    """8 x 8 tiles: a pixel meets the same Gaussians in the same order with
+    the same weights, so the render-back equals the 16 x 16 one bit for bit."""
+    import paper_2505_08124_amd as slag
+    sc = _ragged_scene()
+    attr = np.random.default_rng(5).standard_normal((sc.n, 5)).astype(np.float32)
+    res = {}
+    for tile in (8, 16):
+        L = slag.Lifter(0, tile_size=tile)
+        L.set_scene(sc)
+        res[tile] = [L.render(v, attr, sc.cams) for v in range(sc.n_views)]
+        L.close()
+    for (o8, w8), (o16, w16) in zip(res[8], res[16]):
+        assert np.array_equal(o8, o16) and np.array_equal(w8, w16)
+
+
 def test_render_kernel_weights_matches_oracle():
     """weight_mode = 1: the kernel weights of the blended Gaussians."""
     import paper_2505_08124_amd as slag
