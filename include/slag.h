@@ -127,7 +127,8 @@ typedef struct {
     int32_t composite_variant;      /* 0: the tuned variant (SLAG_FLAG_AUTOTUNE) or variant
                                        0; v + 1 forces compositing variant v (0 <= v <
                                        slag_variant_count(), names from slag_variant_name);
-                                       every variant gives bitwise-equal results */
+                                       every variant gives bitwise-equal results.  Kernel
+                                       weights (weight_mode 1) have one shape and ignore it */
     int32_t reserved;
 } slag_options;
 
