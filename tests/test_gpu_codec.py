@@ -63,8 +63,9 @@ def test_gradients_match_oracle(prec, tol):
         assert rel <= tol, (name, rel)
 
 
-@pytest.mark.parametrize("prec,cos_min", [("f32", 0.9999), ("bf16", 0.99)])
-def test_codec_lift_matches_oracle(scene_2k, oracle_2k, prec, cos_min):
+@pytest.mark.parametrize("prec,cos_min,tile", [("f32", 0.9999, 16), ("bf16", 0.99, 16),
+                                               ("f32", 0.9999, 8)])
+def test_codec_lift_matches_oracle(scene_2k, oracle_2k, prec, cos_min, tile):
     import paper_2505_08124_amd as slag
     sc = scene_2k
     dims = cd.Dims(d=sc.dim, h=64, k=16)
@@ -76,7 +77,7 @@ def test_codec_lift_matches_oracle(scene_2k, oracle_2k, prec, cos_min):
     Wn = sp.diags(inv) @ W
     E_ref, code_ref = cd.codec_lift(p.astype(np.float64), dims, Wn, sc.feats_f64())
     P = slag.SLAG_F32 if prec == "f32" else slag.SLAG_BF16
-    with slag.Lifter(0) as L:
+    with slag.Lifter(0, tile_size=tile) as L:
         L.set_scene(sc)
         slag.slag_codec_init(L.ctx, dims.d, dims.h, dims.k, P, p)
         L.lift_codec()
