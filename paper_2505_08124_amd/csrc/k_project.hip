@@ -445,7 +445,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
     const uint32_t* __restrict__ blk_off, float4* __restrict__ rec, uint32_t* __restrict__ pgauss,
     uint16_t* __restrict__ pview, uint64_t* __restrict__ dkey, uint32_t* __restrict__ dval,
     uint32_t* __restrict__ psz, uint32_t* __restrict__ pz, const uint32_t* __restrict__ sat,
-    uint32_t zmin, int zbits, int pbits, uint32_t* __restrict__ blk_tot,
+    uint32_t zmin, int zbits, int pbits, int plocal, uint32_t* __restrict__ blk_tot,
     const uint32_t* __restrict__ perm, uint32_t* __restrict__ pair_of_m, uint2* __restrict__ prect,
     int lbits)
 {
@@ -486,6 +486,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
     }
     __syncthreads();
     uint32_t run = blk_off[(int64_t)vl * nblk + blk];
+    const uint32_t vbase = blk_off[(int64_t)vl * nblk];   // the view's first pair
     const int sw = V.ntx + 1;
     const uint32_t* S = sat + V.sat_off;
     unsigned long long n_isect = 0, n_part = 0;
@@ -540,7 +541,9 @@ __global__ __launch_bounds__(256) void k_emit_pairs(
         pview[pidx] = (uint16_t)vl;
         const uint64_t dk = ((uint64_t)vl << zbits) | (uint64_t)(__float_as_uint(P.z) - zmin);
         if (pbits) {
-            dkey[pidx] = (dk << pbits) | pidx;       // the pair index rides in the low bits
+            // the pair index (or, plocal, its index within the view) rides in
+            // the low bits
+            dkey[pidx] = (dk << pbits) | (plocal ? pidx - vbase : pidx);
         } else {
             dkey[pidx] = dk;
             dval[pidx] = pidx;
@@ -782,15 +785,15 @@ void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* mea
                        uint32_t* tcnt_pairof,
                        const uint32_t* blk_off, float4* rec, uint32_t* pgauss, uint16_t* pview,
                        uint64_t* dkey, uint32_t* dval, uint32_t* psz, uint32_t* pz,
-                       const uint32_t* sat, uint32_t zmin, int zbits, int pbits, uint32_t* blk_tot,
-                       const uint32_t* perm, uint32_t* pair_of_m, uint2* prect, int lbits,
-                       hipStream_t st)
+                       const uint32_t* sat, uint32_t zmin, int zbits, int pbits, int plocal,
+                       uint32_t* blk_tot, const uint32_t* perm, uint32_t* pair_of_m, uint2* prect,
+                       int lbits, hipStream_t st)
 {
     if (n <= 0 || nb <= 0) return;
     hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)nb, (unsigned)count_blocks_per_view(n)),
                        dim3(256), 0, st, n, views, means, cov3, covd, lo2, tcnt_pairof, blk_off, rec,
-                       pgauss, pview, dkey, dval, psz, pz, sat, zmin, zbits, pbits, blk_tot, perm,
-                       pair_of_m, prect, lbits);
+                       pgauss, pview, dkey, dval, psz, pz, sat, zmin, zbits, pbits, plocal, blk_tot,
+                       perm, pair_of_m, prect, lbits);
 }
 
 void launch_reduce_pairs(const uint32_t* in, uint64_t npairs, bool sum_mode,

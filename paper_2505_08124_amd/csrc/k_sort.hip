@@ -557,6 +557,21 @@ __global__ __launch_bounds__(256) void k_bucket_keys(uint32_t nb,
     val[b] = b;
 }
 
+// Depth order from keys that carry each pair's index within its view.
+__global__ __launch_bounds__(256) void k_pairs_from_keys(uint64_t npairs,
+                                                         const uint64_t* __restrict__ keys,
+                                                         int vshift, uint64_t pmask,
+                                                         const uint32_t* __restrict__ blk_off,
+                                                         int cbv, uint32_t* __restrict__ order)
+{
+    for (uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x; r < npairs;
+         r += (uint64_t)gridDim.x * 256) {
+        const uint64_t k = keys[r];
+        const uint64_t v = k >> vshift;
+        order[r] = blk_off[v * (uint64_t)cbv] + (uint32_t)(k & pmask);
+    }
+}
+
 // ----------------------------------------------------------- depth ties
 //
 // After the depth sort, pairs of one view with bitwise-equal depth keep the
@@ -898,6 +913,14 @@ void launch_emit_isect(uint64_t npairs, const uint32_t* order, const uint64_t* o
     if (!npairs) return;
     hipLaunchKernelGGL(k_emit_isect, dim3(grid_for(npairs)), dim3(256), 0, st, npairs, order, okey,
                        pmask, prank, views, ioff, lbits, ikey, ival);
+}
+
+void launch_pairs_from_keys(uint64_t npairs, const uint64_t* keys, int vshift, uint64_t pmask,
+                            const uint32_t* blk_off, int cbv, uint32_t* order, hipStream_t st)
+{
+    if (!npairs) return;
+    hipLaunchKernelGGL(k_pairs_from_keys, dim3(grid_for(npairs)), dim3(256), 0, st, npairs, keys,
+                       vshift, pmask, blk_off, cbv, order);
 }
 
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st)

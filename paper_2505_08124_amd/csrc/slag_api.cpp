@@ -597,9 +597,14 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
     const int zbits = (npairs && zmax >= zmin) ? bit_length((uint64_t)(zmax - zmin)) : 0;
     const int vbits = bit_length((uint64_t)(nb > 0 ? nb - 1 : 0));
     // depth keys carry the pair index in their low bits when everything fits
-    // in 64 bits (one 8-byte array to sort instead of 8 + 4 bytes)
+    // in 64 bits (one 8-byte array to sort instead of 8 + 4 bytes); else the
+    // pair's index within its view (a view has at most n pairs), turned back
+    // into pair indices after the sort
     const int pneed = std::max(1, bit_length(npairs > 0 ? npairs - 1 : 0));
-    const int pbits = (vbits + zbits + pneed <= 64) ? pneed : 0;
+    const int lneed = std::max(1, bit_length((uint64_t)std::max<int64_t>(n - 1, 0)));
+    const bool pglobal = vbits + zbits + pneed <= 64;
+    const bool plocal = !pglobal && vbits + zbits + lneed <= 64;
+    const int pbits = pglobal ? pneed : plocal ? lneed : 0;
     const uint64_t np = std::max<uint64_t>(npairs, 1);
     CK(ensure(c, c->rec, np * 32));
     CK(ensure(c, c->pgauss, np * 4));
@@ -620,7 +625,8 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
                       c->pgauss.as<uint32_t>(), c->pview.as<uint16_t>(),
                       c->dkey.as<uint64_t>(), c->dval.as<uint32_t>(), c->psz.as<uint32_t>(),
                       debug ? c->pz.as<uint32_t>() : nullptr,
-                      c->sat.as<uint32_t>(), zmin, zbits, pbits, c->blk_aux.as<uint32_t>(),
+                      c->sat.as<uint32_t>(), zmin, zbits, pbits, plocal ? 1 : 0,
+                      c->blk_aux.as<uint32_t>(),
                       c->perm.as<uint32_t>(), c->pair_of_m.as<uint32_t>(), c->prect.as<uint2>(), B.lbits,
                       st);
     launch_reduce_pairs(c->blk_aux.as<uint32_t>(), nblk, true,
@@ -666,25 +672,33 @@ static slag_status lift_batch(slag_ctx* c, Batch& B, bool first, bool last,
         CK(ensure_scan(c, std::max<uint64_t>(npairs, ni / 2 + 4096)));
         const uint32_t* order = nullptr;
         const uint64_t* okey = nullptr;
+        uint64_t* skeys = nullptr;   // the sorted depth keys
         const uint64_t pmask = pbits ? ((1ull << pbits) - 1ull) : 0ull;
         if (pbits) {
             const bool alt = radix_sort_u64_keys(c->dkey.as<uint64_t>(), c->dkey_alt.as<uint64_t>(),
                                                  npairs, pbits, zbits + vbits,
                                                  c->hist.as<uint32_t>(), c->scan_ws.p, st);
-            okey = alt ? c->dkey_alt.as<uint64_t>() : c->dkey.as<uint64_t>();
+            skeys = alt ? c->dkey_alt.as<uint64_t>() : c->dkey.as<uint64_t>();
+            if (plocal) {
+                // view-local indices: the depth order as pair indices
+                launch_pairs_from_keys(npairs, skeys, pbits + zbits, pmask,
+                                       c->blk_vis.as<uint32_t>(), cbv, c->dval.as<uint32_t>(), st);
+                order = c->dval.as<uint32_t>();
+            } else {
+                okey = skeys;
+            }
         } else {
             const bool alt = radix_sort_u64(c->dkey.as<uint64_t>(), c->dval.as<uint32_t>(),
                                             c->dkey_alt.as<uint64_t>(), c->dval_alt.as<uint32_t>(),
                                             npairs, zbits + vbits, c->hist.as<uint32_t>(),
                                             c->scan_ws.p, nullptr, st);
             order = alt ? c->dval_alt.as<uint32_t>() : c->dval.as<uint32_t>();
+            skeys = alt ? c->dkey_alt.as<uint64_t>() : c->dkey.as<uint64_t>();
         }
         // equal depths: the caller's Gaussian index decides (pairs follow the
         // storage order, the Morton order, until here)
         {
-            uint64_t* tkeys = const_cast<uint64_t*>(okey);
-            if (!tkeys) tkeys = order == c->dval_alt.as<uint32_t>() ? c->dkey_alt.as<uint64_t>()
-                                                                  : c->dkey.as<uint64_t>();
+            uint64_t* tkeys = skeys;
             launch_fill_u32(reinterpret_cast<uint32_t*>(small + SM_TIES), 2, 0u, st);
             launch_tie_short(npairs, tkeys, pbits, const_cast<uint32_t*>(order), pmask,
                              c->pgauss.as<uint32_t>(),

@@ -71,8 +71,9 @@ void launch_count(int nb, int64_t n, const ViewDev* views, const float* means, c
                   hipStream_t st);
 int count_blocks_per_view(int64_t n);
 // Pass 2 over the same (view, Gaussian block) grid: visible pairs compacted
-// in (view, Morton rank) order with their records, depth keys (pair index in
-// the low pbits bits when pbits > 0, else in dval), part-list capacities
+// in (view, Morton rank) order with their records, depth keys (the pair
+// index -- or, plocal, its index within its view -- in the low pbits bits
+// when pbits > 0, else the pair index in dval), part-list capacities
 // psz, packed tile rectangles prect (entry key base for lbits), the caller's
 // Gaussian index pgauss[pair] = perm[g], the view pview, and the (view, rank)
 // -> pair map pair_of_m (NONE where not visible); pz only when non-null.
@@ -83,9 +84,9 @@ void launch_emit_pairs(int nb, int64_t n, const ViewDev* views, const float* mea
                        uint32_t* tcnt_pairof,
                        const uint32_t* blk_off, float4* rec, uint32_t* pgauss, uint16_t* pview,
                        uint64_t* dkey, uint32_t* dval, uint32_t* psz, uint32_t* pz,
-                       const uint32_t* sat, uint32_t zmin, int zbits, int pbits, uint32_t* blk_tot,
-                       const uint32_t* perm, uint32_t* pair_of_m, uint2* prect, int lbits,
-                       hipStream_t st);
+                       const uint32_t* sat, uint32_t zmin, int zbits, int pbits, int plocal,
+                       uint32_t* blk_tot, const uint32_t* perm, uint32_t* pair_of_m, uint2* prect,
+                       int lbits, hipStream_t st);
 // out[0..1] = (min of even, max of odd) entries of in[2 * npairs], or their
 // 64-bit sums in sum mode; one block
 void launch_reduce_pairs(const uint32_t* in, uint64_t npairs, bool sum_mode,
@@ -148,6 +149,12 @@ void launch_emit_isect(uint64_t npairs, const uint32_t* order, const uint64_t* o
                        const uint32_t* ioff, int lbits, uint32_t* ikey, uint32_t* ival,
                        hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
+// Depth order of pairs from sorted depth keys that carry each pair's index
+// within its view in the low bits (pmask): order[r] = the view's first pair
+// blk_off[view * cbv] + key & pmask, with view = key >> vshift (cbv Gaussian
+// blocks per view).
+void launch_pairs_from_keys(uint64_t npairs, const uint64_t* keys, int vshift, uint64_t pmask,
+                            const uint32_t* blk_off, int cbv, uint32_t* order, hipStream_t st);
 // Dispatch keys: (resolution class << 16) | (0xFFFF - min(list length, 0xFFFF)),
 // class 0 for every view when view_cls is null.
 void launch_bucket_keys(uint32_t nb, const uint32_t* bucket_view, const uint8_t* view_cls,
