@@ -688,7 +688,9 @@ __global__ __launch_bounds__(256) void k_tie_short(uint64_t n, uint64_t* __restr
 #pragma unroll
         for (int a = 0; a < TIE_SHORT; a++) {
             const bool in = eq[TIE_SHORT + a];
-            pv[a] = order ? order[in ? i + a : i] : (uint32_t)(sk[li + a] & pmask);
+            // positions past the run take the head's pair: their Gaussian
+            // index is not used, and the head's is already being loaded
+            pv[a] = order ? order[in ? i + a : i] : (uint32_t)(sk[li + (in ? a : 0)] & pmask);
         }
 #pragma unroll
         for (int a = 0; a < TIE_SHORT; a++) {
