@@ -510,6 +510,23 @@ def test_tile_size_8_and_independence(case):
          f"max rel d(den) {(np.abs(d8 - d16) / np.maximum(d16, 1e-30)).max():.3g}")
 
 
+@pytest.mark.parametrize("D,dtype", [(128, "f32"), (256, "bf16"), (1024, "bf16"), (1024, "f32")])
+def test_feature_sizes_match_oracle(D, dtype):
+    """Feature sizes beyond those of the benchmark workloads (64 to 1024 are
+    taken; BF16 768 and 1024 run the walk and the chunk multiply as two
+    kernels) against the FP64 oracle, with the ragged tiles of the 2,000-
+    Gaussian scene: E within the propagated bound, den within its bar."""
+    sc = make_scene("plain_fp32_2k", features=dict(D=D, dtype=dtype))
+    ref = oracle.lift(sc)
+    L = _lifter(sc)
+    L.lift()
+    E, den = L.embeddings()
+    assert E.shape == (sc.n, D)
+    cmin, emax = check_embeddings(E, den, ref, sc, f"d{D}_{dtype}")
+    _say(f"D = {D} {dtype}: min cosine {cmin:.9f}, max abs err {emax:.3g}")
+    L.close()
+
+
 def test_uneven_resolutions_one_launch():
     sc = make_scene("uneven_1m", n=40000, views=dict(n=6))
     _say("uneven: oracle")
