@@ -839,24 +839,26 @@ def test_empty_second_label_layer_is_bitwise_neutral(scene_2k, lift_2k):
     L.close()
 
 
-@pytest.mark.parametrize("case", ["plain_fp32_2k", "ragged"])
-def test_kernel_weights_match_oracle(case):
+@pytest.mark.parametrize("case,tile", [("plain_fp32_2k", 16), ("ragged", 16), ("ragged", 8)])
+def test_kernel_weights_match_oracle(case, tile):
     """weight_mode = 1, the paper's weight equation (the Gaussian kernel
     exp(-q/2) of each Gaussian the front-to-back walk blends): W_v and the
     embeddings against the oracle run in the same mode; differs from the
     blend-weight lift."""
     import paper_2505_08124_amd as slag
     sc = make_scene("plain_fp32_2k") if case == "plain_fp32_2k" else _ragged_scene()
-    L = slag.Lifter(0, flags=slag.SLAG_FLAG_KEEP_DEBUG | slag.SLAG_FLAG_AUTOTUNE, weight_mode=1)
+    L = slag.Lifter(0, flags=slag.SLAG_FLAG_KEEP_DEBUG | slag.SLAG_FLAG_AUTOTUNE, weight_mode=1,
+                    tile_size=tile)
     L.set_scene(sc)
     L.lift()
     E, den = L.embeddings()
     with oracle.constants(weight_mode=1.0):
         ref = oracle.lift(sc)
+    tag = f"kernel_{case}" + ("" if tile == 16 else f"_tile{tile}")
     for v in range(sc.n_views):
-        check_tile_lists(L, sc, v)
-        check_view_weights(L, sc, v, ref.views[v], "kernel_" + case)
-    check_embeddings(E, den, ref, sc, "kernel_" + case)
+        check_tile_lists(L, sc, v, tile)
+        check_view_weights(L, sc, v, ref.views[v], tag)
+    check_embeddings(E, den, ref, sc, tag)
     L.close()
     L0 = _lifter(sc)
     L0.lift()
