@@ -225,6 +225,56 @@ def measure(slag, torch, scene, steps, warmup, count=True, stage_steps=3, eager=
     return res, E, den
 
 
+def search_and_render(slag, torch, scene, E, reps=3):
+    """The search over the lifted embeddings (device-resident, the query
+    side of the paper) and the render-back of one view, timed on the GPU.
+    A count-only search reads the embedding table once (HBM-bound: its GB/s
+    against 8 TB/s); a top-k search adds a per-query sort of the n scores."""
+    dev = torch.from_numpy(E).cuda()
+    rng = np.random.default_rng(7)
+    F = scene.feats_f64()
+    gb = E.shape[0] * E.shape[1] * 4 / 1e9
+    search = []
+    with slag.Lifter(0) as L:
+        for q, k in ((1, 0), (16, 0), (1, 10), (16, 10)):
+            rows = F[rng.choice(F.shape[0], q, replace=False)].astype(np.float32)
+            Q = torch.from_numpy(np.ascontiguousarray(rows)).cuda()
+            torch.cuda.synchronize()
+            slag.slag_query(L.ctx, dev, Q, 0.28, k)      # first call sizes the workspace
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                cnt, _, _ = slag.slag_query(L.ctx, dev, Q, 0.28, k)
+            ms = (time.perf_counter() - t0) / reps * 1e3
+            row = dict(queries=q, k=k, threshold=0.28, ms=round(ms, 3),
+                       count_first=int(cnt[0]))
+            if k == 0:
+                row.update(emb_gb=round(gb, 3), gbs=round(gb / (ms * 1e-3), 1),
+                           frac=round(gb / (ms * 1e-3) / HBM_PEAK_GBS, 4))
+            search.append(row)
+        _log("search:", json.dumps(search))
+    del dev
+    # render-back of 16 channels into view 0 (projection, sorts and the
+    # compositing of one view, then one pass of k_render)
+    render = None
+    with slag.Lifter(0) as L:
+        L.set_scene(scene, device_tensors=True)
+        C = 16
+        attr = torch.from_numpy(np.ascontiguousarray(E[:, :C])).cuda()
+        H, W = int(scene.cams[0]["height"]), int(scene.cams[0]["width"])
+        out = torch.empty((H, W, C), dtype=torch.float32, device="cuda")
+        ws = torch.empty((H, W), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        slag.slag_render(L.ctx, 0, attr, out, ws)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            slag.slag_render(L.ctx, 0, attr, out, ws)
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        render = dict(view=0, width=W, height=H, channels=C, ms=round(ms, 3),
+                      lit_fraction=round(float((ws > 0).float().mean().item()), 4))
+        _log("render:", json.dumps(render))
+    return search, render
+
+
 def kernel_rooflines(res, workload):
     """Roofline of the two heaviest stages per launch: k_composite (VALU:
     in-box tests x 16 operations, and the 19 issue slots the kernel spends per
@@ -425,6 +475,8 @@ def main():
     ap.add_argument("--eager", action="store_true", help="time eager lifts instead of graph replays")
     ap.add_argument("--no-secondary", action="store_true", help="skip the smaller workloads")
     ap.add_argument("--no-codec", action="store_true", help="skip the codec section")
+    ap.add_argument("--no-search", action="store_true",
+                    help="skip the search and render-back timings")
     ap.add_argument("--tile-size", type=int, default=16, choices=[8, 16],
                     help="binning and compositing tile edge of the timed lifts")
     ap.add_argument("--codec-steps", type=int, default=4000)
@@ -463,7 +515,7 @@ def main():
     scene = make_scene(wl)
     _log(f"generated in {time.perf_counter() - t0:.1f} s")
     V, N, D = scene.n_views, scene.n, scene.dim
-    res, _, _ = measure(slag, torch, scene, args.steps, args.warmup, count=not args.no_count,
+    res, E_head, _ = measure(slag, torch, scene, args.steps, args.warmup, count=not args.no_count,
                         stage_steps=3 if scene.n >= 1_000_000 else args.steps, eager=args.eager)
     roof, kernels = kernel_rooflines(res, wl)
 
@@ -474,6 +526,11 @@ def main():
         _log(f"CPU oracle on views {views} (baseline and accuracy)")
         accuracy, cpu = accuracy_and_cpu(slag, scene, views, 0)
         _log("accuracy:", json.dumps(accuracy))
+
+    search = render = None
+    if not args.no_search:
+        search, render = search_and_render(slag, torch, scene, E_head)
+    del E_head
 
     codec_stress = None
     if not args.no_codec and wl == "stress_4m":
@@ -549,6 +606,8 @@ def main():
         "secondary": secondary,
         "codec": codec,
         "codec_headline": codec_stress,
+        "search": search,
+        "render": render,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
